@@ -1,0 +1,128 @@
+"""One Hessian-free frequency step and synthetic data (oracle; test infrastructure only).
+
+Section 3 and Section 6.3.2(a): for the current squared slowness m = c^-2, trace rays on the
+(smoothed) wavenumber map, form the Green's functions, predict the data at the receivers,
+take the residual g_res = g - data (Eq. residual), back-project it with Lambda
+(Eqs. sound_speed_update, sound_speed_update2) summed over the frequencies of the set, and
+update m <- m + tau dm, c = m^-1/2 (end of Section 3.4). Outside the mask c = c0 (Section 6.3).
+
+Readings:
+  * rays are traced and integrated on the smoothed map n_s; the part of the model the smoothing
+    removed, m - m_s with m_s = (n_s/c0)^2, enters the predicted data to first order through
+    the Born forward operator with w = omega^2 h^2 ("ray_born"); "ray_only" drops that term.
+    With a window of 1 both are the same;
+  * emitter-receiver pairs with e = r or without a bracketing ray are masked to zero.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import binning, born, green
+from .medium import C0, Grid, Ring, box_smooth, refractive_index
+from .trace import trace
+
+
+@dataclasses.dataclass
+class StepSetup:
+    grid: Grid
+    ring: Ring
+    n_rays: int
+    ds: float
+    max_steps: int
+    c0: float = C0
+
+
+def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None):
+    """Trace on box_window(c0/c) and bin; returns (Tables, n_s)."""
+    ns = box_smooth(refractive_index(c, st.c0), window)
+    s = trace(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps, emitters=emitters,
+              c0=st.c0)
+    tb = binning.tables(s, st.grid, st.ring, st.ds, st.max_steps, emitters=emitters, c0=st.c0)
+    return tb, ns
+
+
+def predicted(tb, c, ns, st: StepSetup, omega: float, mode: str = "ray_born"):
+    """Predicted data g(m; omega, r, e) and the G operands used for it."""
+    G, H, Hx, Hy = green.build_green(tb, omega, st.c0)
+    g = green.direct_data(tb, omega, st.c0)
+    if mode == "ray_born":
+        q = st.grid.mask_index()
+        m = 1.0 / c.ravel()[q] ** 2
+        ms = (ns.ravel()[q] / st.c0) ** 2
+        w = np.full(q.size, omega ** 2 * st.grid.dx ** 2)
+        g = g + born.forward(G, w, m - ms)
+    elif mode != "ray_only":
+        raise ValueError(mode)
+    return g, (G, H, Hx, Hy)
+
+
+def residual(g, data, rx_valid):
+    """g_res = g - data on valid pairs with e != r, zero elsewhere (Eq. residual)."""
+    N = g.shape[0]
+    keep = rx_valid & ~np.eye(N, dtype=bool)
+    return np.where(keep, g - data, 0.0)
+
+
+def update(c: np.ndarray, dm_mask: np.ndarray, tau: float, grid: Grid):
+    """m <- m + tau dm on the mask (FP64), c = m^-1/2; unchanged outside."""
+    q = grid.mask_index()
+    m = 1.0 / c.ravel()[q] ** 2
+    m_new = m + tau * dm_mask
+    out = c.copy().ravel()
+    out[q] = 1.0 / np.sqrt(m_new)
+    return out.reshape(c.shape)
+
+
+def frequency_step(c, st: StepSetup, omegas, d_omegas, data, tau, window=1,
+                   mode="ray_born", isochron_sign=1.0, return_parts=False):
+    """One Hessian-free update of the sound speed c (ny, nx) from the data of the frequency
+    set omegas (data shape (n_omega, N_e, N_r))."""
+    tb, ns = tables_for(c, st, window)
+    q = st.grid.mask_index()
+    cq = c.ravel()[q]
+    dm = np.zeros(q.size)
+    parts = []
+    for k, (om, dom) in enumerate(zip(omegas, d_omegas)):
+        g, (G, H, Hx, Hy) = predicted(tb, c, ns, st, om, mode)
+        R = residual(g, data[k], tb.rx_valid)
+        S = born.backproject_weight(om, dom, cq)
+        dmk = born.backproject(R, H, Hx, Hy, S, isochron_sign)
+        dm += dmk
+        parts.append(dict(g=g, R=R, G=G, H=H, Hx=Hx, Hy=Hy, dm=dmk))
+    c_new = update(c, dm, tau, st.grid)
+    if return_parts:
+        return c_new, dict(tables=tb, ns=ns, dm=dm, freqs=parts)
+    return c_new
+
+
+def synthesize(c_true, st: StepSetup, omegas, noise, background="water", window=1,
+               noise_level=0.01):
+    """Synthetic measured data: ray-Born prediction about a background plus noise.
+
+    background="water": g(water) + F[water](m_true - m_water) (first-order data about water);
+    background="smooth": the ray_born prediction of c_true with the given window.
+    noise: unit complex Gaussian samples of shape (n_omega, N, N); sigma = noise_level times
+    the rms of the clean data over valid pairs with e != r."""
+    N = st.ring.n
+    if background == "water":
+        cw = np.full_like(c_true, st.c0)
+        tb, ns = tables_for(cw, st, 1)
+        q = st.grid.mask_index()
+        dm = 1.0 / c_true.ravel()[q] ** 2 - 1.0 / st.c0 ** 2
+    else:
+        tb, ns = tables_for(c_true, st, window)
+    out = np.zeros((len(omegas), N, N), dtype=np.complex128)
+    keep = tb.rx_valid & ~np.eye(N, dtype=bool)
+    for k, om in enumerate(omegas):
+        if background == "water":
+            G, _, _, _ = green.build_green(tb, om, st.c0)
+            w = np.full(dm.size, om ** 2 * st.grid.dx ** 2)
+            clean = green.direct_data(tb, om, st.c0) + born.forward(G, w, dm)
+        else:
+            clean, _ = predicted(tb, c_true, ns, st, om, "ray_born")
+        rms = math.sqrt(np.mean(np.abs(clean[keep]) ** 2))
+        out[k] = clean + noise_level * rms * noise[k]
+    return out

@@ -1,0 +1,81 @@
+"""Pins of the oracle's frequency step (Section 3.4 update, Eq. residual, Section 6.3.2)."""
+import math
+
+import numpy as np
+
+import phantoms as ph
+from oracle import step
+from oracle.medium import box_smooth
+from tests.oracle_fixtures import C0, small_setup
+
+
+def test_consistent_data_give_zero_update():
+    # Data equal to the prediction of the current model: g_res = 0, so dm = 0 and c is
+    # returned unchanged (up to the rounding of c -> m -> c).
+    st = small_setup(N=16, n_rays=90)
+    c = ph.gaussian_inclusion(st.grid.nx, st.grid.ny, st.grid.dx, st.grid.x0, st.grid.y0,
+                              seed=3, amp=20.0, sigma=4e-3, centre_radius=4e-3,
+                              mask_radius=st.grid.mask_radius)
+    om = [2 * math.pi * 200e3]
+    tb, ns = step.tables_for(c, st, 1)
+    g, _ = step.predicted(tb, c, ns, st, om[0])
+    c1, parts = step.frequency_step(c, st, om, om, g[None], 0.12, return_parts=True)
+    assert np.all(parts["freqs"][0]["R"] == 0)
+    assert np.all(parts["dm"] == 0)
+    assert np.max(np.abs(c1 - c) / c) < 4e-16
+
+
+def test_ray_born_and_ray_only_agree_without_smoothing():
+    st = small_setup(N=16, n_rays=90)
+    c = ph.gaussian_inclusion(st.grid.nx, st.grid.ny, st.grid.dx, st.grid.x0, st.grid.y0,
+                              seed=4, amp=30.0, sigma=4e-3, centre_radius=4e-3,
+                              mask_radius=st.grid.mask_radius)
+    tb, ns = step.tables_for(c, st, 1)
+    a, _ = step.predicted(tb, c, ns, st, 2 * math.pi * 300e3, "ray_born")
+    b, _ = step.predicted(tb, c, ns, st, 2 * math.pi * 300e3, "ray_only")
+    assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(b))
+
+
+def test_rough_part_enters_through_born_term():
+    # With smoothing, g(m) = g_ray(m_s) + F[m_s](m - m_s) with m_s = (n_s / c0)^2.
+    st = small_setup(N=16, n_rays=90)
+    c = ph.gaussian_inclusion(st.grid.nx, st.grid.ny, st.grid.dx, st.grid.x0, st.grid.y0,
+                              seed=4, amp=30.0, sigma=2e-3, centre_radius=4e-3,
+                              mask_radius=st.grid.mask_radius)
+    tb, ns = step.tables_for(c, st, 5)
+    assert np.allclose(ns, box_smooth(C0 / c, 5))
+    a, _ = step.predicted(tb, c, ns, st, 2 * math.pi * 300e3, "ray_born")
+    b, _ = step.predicted(tb, c, ns, st, 2 * math.pi * 300e3, "ray_only")
+    assert np.max(np.abs(a - b)) > 1e-5 * np.max(np.abs(b))
+
+
+def test_update_is_linear_in_step_length_and_frequency_spacing():
+    st = small_setup(N=16, n_rays=90)
+    c_true = ph.gaussian_inclusion(st.grid.nx, st.grid.ny, st.grid.dx, st.grid.x0,
+                                   st.grid.y0, seed=6, amp=30.0, sigma=3e-3,
+                                   centre_radius=4e-3, mask_radius=st.grid.mask_radius)
+    om = [2 * math.pi * 250e3]
+    noise = np.zeros((1, 16, 16), dtype=complex)
+    data = step.synthesize(c_true, st, om, noise)
+    c = np.full_like(c_true, C0)
+    q = st.grid.mask_index()
+    _, p1 = step.frequency_step(c, st, om, om, data, 0.12, return_parts=True)
+    _, p2 = step.frequency_step(c, st, om, [2 * om[0]], data, 0.12, return_parts=True)
+    assert np.allclose(p2["dm"], 2 * p1["dm"], rtol=1e-12, atol=0)
+    c1 = step.update(c, p1["dm"], 0.12, st.grid)
+    m1 = 1.0 / c1.ravel()[q] ** 2
+    assert np.allclose(m1, 1 / C0 ** 2 + 0.12 * p1["dm"], rtol=1e-14, atol=0)
+    outside = np.setdiff1d(np.arange(c.size), q)
+    assert np.all(c1.ravel()[outside] == C0)
+    # the step moves the model towards the (faster) inclusion: dc correlates positively
+    dc = (c1 - C0).ravel()[q]
+    assert np.corrcoef(dc, (c_true - C0).ravel()[q])[0, 1] > 0
+
+
+def test_residual_masks_diagonal_and_invalid_pairs():
+    g = np.ones((4, 4), dtype=complex)
+    data = np.zeros((4, 4), dtype=complex)
+    valid = np.ones((4, 4), dtype=bool)
+    valid[1, 2] = False
+    R = step.residual(g, data, valid)
+    assert np.all(np.diag(R) == 0) and R[1, 2] == 0 and R[2, 1] == 1
