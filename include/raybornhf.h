@@ -1,0 +1,186 @@
+/*
+ * raybornhf: one Hessian-free ray-Born frequency step on an AMD MI355X (gfx950).
+ *
+ * Method: A. Javaherian, "Hessian-free ray-Born inversion for quantitative ultrasound
+ * tomography of weakly heterogeneous media" (arXiv 2211.00316).
+ *   - problem setting: Section 2.1 (ring of point emitters/receivers, sound speed c(x),
+ *     c0 outside the imaging region); unknown m = c^-2 (Section 3);
+ *   - ray tracing: Section 4 (Hamiltonian and paraxial ray equations, Algorithm 1);
+ *   - ray-to-grid interpolation: Section 4.5; receivers: Section 6.3;
+ *   - ray Green's function: Eqs. 2D_greens, phase-discretised, amplitude-geom-discretised;
+ *   - Born operator: Eqs. perturb1, derivative, scattering-potential;
+ *   - Q=1 gradient: Eq. functional-gradient; Hessian-free direction: Eqs.
+ *     sound_speed_update, sound_speed_update2; update m <- m + tau dm (Section 3.4).
+ *
+ * Conventions (every entry point):
+ *   - Lengths in metres, times in seconds, angular frequencies in rad/s.
+ *   - Grid node (j, i) sits at (x0 + i dx, y0 + j dx); flat index p = j nx + i (x fastest).
+ *     The imaging mask keeps nodes with x^2 + y^2 <= mask_radius^2; "mask nodes" are listed
+ *     in ascending flat index, P_m of them (rb_mask_count).
+ *   - Transducer e sits at R (cos psi_e, sin psi_e), psi_e = psi0 + 2 pi e / N.
+ *   - Every array argument is a DEVICE pointer allocated and owned by the caller; the
+ *     library never frees it. Complex numbers are interleaved (re, im) float pairs.
+ *   - Calls are asynchronous on the context's stream; outputs are ready when that stream is.
+ *   - Every entry point validates its arguments before launching anything and returns an
+ *     rb_status; on error nothing was launched (outputs unchanged) and rb_last_error()
+ *     describes the problem. RB_EDEVICE reports a failed HIP call.
+ *   - A context may be used from one host thread at a time.
+ */
+#ifndef RAYBORNHF_H
+#define RAYBORNHF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RB_OK = 0,
+    RB_EINVAL = -1,       /* invalid argument (null pointer, size, geometry) */
+    RB_ENOMEM = -2,       /* device workspace allocation failed */
+    RB_EDEVICE = -3,      /* a HIP runtime call failed */
+    RB_ENONFINITE = -4,   /* a ray exceeded max_steps, or a non-finite update was rejected */
+    RB_EUNSUPPORTED = -5  /* requested mode / precision not available */
+} rb_status;
+
+typedef enum { RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3 } rb_prec;
+
+/* Predicted data of the frequency step: ray Green's function at the receivers plus, in
+ * RB_RAY_BORN mode, the first-order Born term of the part of the model removed by the
+ * smoothing window (m - m_s); RB_RAY_ONLY omits that term. */
+typedef enum { RB_RAY_BORN = 0, RB_RAY_ONLY = 1 } rb_mode;
+
+/* Ring of n point transducers of radius `radius` (Section 2.1); each emits and receives. */
+typedef struct {
+    int32_t n;
+    double radius;
+    double psi0;
+} rb_ring;
+
+/* Square-spaced Cartesian grid and circular imaging mask (Section 6.3: 90 % of the ring). */
+typedef struct {
+    int32_t nx, ny;
+    double dx, x0, y0;
+    double mask_radius;
+} rb_grid;
+
+/* Fan of n_rays launch angles per transducer over the inward half-plane,
+ * gamma0_j = psi_e + pi + (j + 1/2 - n_rays/2) pi / n_rays; Heun step ds (Algorithm 1);
+ * a ray still inside the ring after max_steps steps makes the call fail (RB_ENONFINITE). */
+typedef struct {
+    int32_t n_rays;
+    int32_t max_steps;
+    double ds;
+    double c0;
+} rb_trace_params;
+
+/* Per-transducer tables (outputs of rb_trace_rays, inputs of rb_build_green).
+ * Grid tables over the mask nodes, row e = transducer, shape [n][n_mask]:
+ *   T  travel time from transducer e (s);
+ *   A  geometric amplitude times sqrt(k0): A_geom = A / sqrt(omega / c0);
+ *   ux, uy unit direction of the ray from e at the node;
+ *   flags bit 7 = valid, bits 0-1 = caustic count mod 4.
+ * Receiver tables, row = emitter, column = receiver, shape [n][n]: rx_T, rx_A, rx_flags. */
+typedef struct {
+    int32_t n;
+    int32_t n_mask;
+    double *T;
+    float *A;
+    float *ux;
+    float *uy;
+    uint8_t *flags;
+    double *rx_T;
+    float *rx_A;
+    uint8_t *rx_flags;
+} rb_tables;
+
+/* Green's-function operands of one frequency (output of rb_build_green), complex64:
+ *   G  [n][n_mask]     g(omega, x, e) = A exp(i (phi + pi/4))  (Eq. 2D_greens);
+ *   H  [3][n][n_mask]  back-projection operands a_e g_dagger, a_e g_dagger u_x,
+ *                      a_e g_dagger u_y (Eq. greens-time-reversed times the angular
+ *                      weight |d gamma_e / d e| De of Eq. sound_speed_update2).
+ * Only RB_F32 operands are produced by this version. */
+typedef struct {
+    int32_t n;
+    int32_t n_mask;
+    rb_prec prec;
+    void *G;
+    void *H;
+} rb_green;
+
+typedef struct rb_ctx rb_ctx;
+
+/* Create a context on HIP device `device` that launches on `hip_stream` (a hipStream_t,
+ * borrowed, may be NULL for the null stream). Returns RB_EDEVICE if the device is absent. */
+rb_status rb_create(rb_ctx **ctx, int device, void *hip_stream);
+/* Release the context's workspace. The caller's buffers are untouched. */
+void rb_destroy(rb_ctx *ctx);
+/* Message of the last error of this context (static storage inside the context). */
+const char *rb_last_error(const rb_ctx *ctx);
+/* Number of mask nodes of a grid (host arithmetic only; -1 if the grid is invalid). */
+int64_t rb_mask_count(const rb_grid *grid);
+
+/* Box-smoothed refractive index n_s = box_w(c0 / c) (Section 6.3.2: odd averaging window,
+ * edges replicated) as float [ny][nx], from c (double [ny][nx]). w must be odd and >= 1. */
+rb_status rb_refractive_index(rb_ctx *ctx, const rb_grid *grid, const double *c, double c0,
+                              int32_t w, float *n_s);
+
+/* Trace the fan of every transducer through the refractive-index map n_s (float [ny][nx],
+ * the uniform cubic B-spline of these samples is the medium; Section 4.5) with the paraxial
+ * Heun scheme of Algorithm 1, bin the rays onto the mask nodes by linear interpolation over
+ * the triangulated ray samples (Section 4.5), and fill the receiver tables from the rays'
+ * exit points (Section 6.3). Writes every field of `out` (sizes must match). */
+rb_status rb_trace_rays(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                        const rb_trace_params *tp, const float *n_s, const rb_tables *out);
+
+/* Assemble G and the back-projection operands H of angular frequency omega from the tables
+ * (Eqs. 2D_greens, phase-discretised, greens-time-reversed). The phase omega T + pi/4 -
+ * K pi/2 is reduced modulo 2 pi in FP64. Invalid table entries give zeros. */
+rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                         const rb_green *out);
+
+/* Born forward operator (Eqs. perturb1, derivative): d[e][r] = sum_q G[e][q] w[q] delta[q]
+ * G[r][q] for all (e, r) including e = r. w: complex64 [n_mask] (Upsilon h^2, e.g.
+ * omega^2 dx^2 for dm = delta m); delta: float [n_mask]; d: complex64 [n][n]. */
+rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
+                          float *d);
+
+/* Adjoint of rb_born_forward for real delta (Eq. functional-gradient with Q = 1):
+ * grad[q] = Re{ conj(w[q]) sum_e conj(G[e][q]) sum_r R[e][r] conj(G[r][q]) }.
+ * R: complex64 [n][n]; grad: float [n_mask]. */
+rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const float *R,
+                          float *grad);
+
+/* Residual of one frequency (Eq. residual): R[e][r] = g(omega, r, e) + d_born[e][r] - data[e][r]
+ * on valid pairs with e != r, zero elsewhere, where g(omega, r, e) = rx_A / sqrt(k0)
+ * exp(i (omega rx_T + pi/4 - K pi/2)) is the ray Green's function at the receivers.
+ * d_born: complex64 [n][n] or NULL; data, R: complex64 [n][n]. */
+rb_status rb_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                      const float *d_born, const float *data, float *R);
+
+/* Hessian-free search direction of one frequency (Eqs. sound_speed_update,
+ * sound_speed_update2): dm[q] = -S[q] Re sum_{e,r} R[e][r] [H_e H_r + H^x_e H^x_r +
+ * H^y_e H^y_r](q), with S[q] = 2 d_omega / ((2 pi)^3 omega c[q]^2) (lossless, two-way
+ * isochron gradient k (u_e + u_r)). c: double [n_mask] sound speed at the mask nodes;
+ * dm: float [n_mask], overwritten unless `accumulate` != 0 (then added). */
+rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
+                         double omega, double d_omega, float *dm, int32_t accumulate);
+
+/* One frequency step (the unit of the benchmark). c: double [ny][nx] sound speed, updated
+ * in place on the mask nodes (m <- m + tau sum_omega dm_omega, c = m^-1/2, FP64); omega and
+ * d_omega: HOST arrays of n_omega values; data: complex64 [n_omega][n][n] measured Green's
+ * functions (row = emitter). smooth_w: odd window of the tracing map. If any updated value
+ * is not finite the model is left unchanged and RB_ENONFINITE is returned.
+ * residual_norm (device double, may be NULL) receives sum |g_res|^2 over all frequencies. */
+rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            int32_t n_omega, const double *omega, const double *d_omega,
+                            const float *data, double tau, rb_mode mode,
+                            double *residual_norm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAYBORNHF_H */

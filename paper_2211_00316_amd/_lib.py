@@ -1,0 +1,273 @@
+"""ctypes binding of the raybornhf C ABI (include/raybornhf.h).
+
+Argument marshalling only: tensors are allocated with torch on the GPU and their device
+pointers are handed to the library; every step of the computation runs in the HIP kernels.
+There is no fallback: without the built library or a GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libraybornhf.so")
+
+RB_OK, RB_EINVAL, RB_ENOMEM, RB_EDEVICE, RB_ENONFINITE, RB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RB_F32, RB_BF16, RB_F16 = 1, 2, 3
+RB_RAY_BORN, RB_RAY_ONLY = 0, 1
+
+SYMBOLS = (
+    "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
+    "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
+    "rb_backproject", "rb_frequency_step",
+)
+
+
+class Ring(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("radius", ctypes.c_double), ("psi0", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("mask_radius", ctypes.c_double)]
+
+
+class TraceParams(ctypes.Structure):
+    _fields_ = [("n_rays", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("ds", ctypes.c_double), ("c0", ctypes.c_double)]
+
+
+class _Tables(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32),
+                ("T", ctypes.c_void_p), ("A", ctypes.c_void_p), ("ux", ctypes.c_void_p),
+                ("uy", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("rx_T", ctypes.c_void_p),
+                ("rx_A", ctypes.c_void_p), ("rx_flags", ctypes.c_void_p)]
+
+
+class _Green(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32), ("prec", ctypes.c_int),
+                ("G", ctypes.c_void_p), ("H", ctypes.c_void_p)]
+
+
+class RayBornError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"raybornhf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2211_00316_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "rb_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),
+        "rb_destroy": ([P], None),
+        "rb_last_error": ([P], ctypes.c_char_p),
+        "rb_mask_count": ([ctypes.POINTER(Grid)], ctypes.c_int64),
+        "rb_refractive_index": ([P, ctypes.POINTER(Grid), P, D, I32, P], ctypes.c_int),
+        "rb_trace_rays": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                           ctypes.POINTER(TraceParams), P, ctypes.POINTER(_Tables)], ctypes.c_int),
+        "rb_build_green": ([P, ctypes.POINTER(_Tables), D, D, ctypes.POINTER(_Green)],
+                           ctypes.c_int),
+        "rb_born_forward": ([P, ctypes.POINTER(_Green), P, P, P], ctypes.c_int),
+        "rb_born_adjoint": ([P, ctypes.POINTER(_Green), P, P, P], ctypes.c_int),
+        "rb_residual": ([P, ctypes.POINTER(_Tables), D, D, P, P, P], ctypes.c_int),
+        "rb_backproject": ([P, ctypes.POINTER(_Green), P, P, D, D, P, I32], ctypes.c_int),
+        "rb_frequency_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                               ctypes.POINTER(TraceParams), P, I32, I32,
+                               ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int, P],
+                              ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def mask_count(grid: Grid) -> int:
+    return int(load().rb_mask_count(ctypes.byref(grid)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, dtype):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} GPU tensor, got {t.dtype} on {t.device}")
+    return t
+
+
+@dataclasses.dataclass
+class Tables:
+    """Device tensors of rb_tables (grid tables [n][n_mask], receiver tables [n][n])."""
+
+    T: torch.Tensor
+    A: torch.Tensor
+    ux: torch.Tensor
+    uy: torch.Tensor
+    flags: torch.Tensor
+    rx_T: torch.Tensor
+    rx_A: torch.Tensor
+    rx_flags: torch.Tensor
+
+    @classmethod
+    def empty(cls, n, n_mask, device):
+        f = dict(device=device)
+        return cls(torch.empty(n, n_mask, dtype=torch.float64, **f),
+                   torch.empty(n, n_mask, dtype=torch.float32, **f),
+                   torch.empty(n, n_mask, dtype=torch.float32, **f),
+                   torch.empty(n, n_mask, dtype=torch.float32, **f),
+                   torch.empty(n, n_mask, dtype=torch.uint8, **f),
+                   torch.empty(n, n, dtype=torch.float64, **f),
+                   torch.empty(n, n, dtype=torch.float32, **f),
+                   torch.empty(n, n, dtype=torch.uint8, **f))
+
+    def struct(self):
+        n, nm = self.T.shape
+        return _Tables(n, nm, *(t.data_ptr() for t in (self.T, self.A, self.ux, self.uy,
+                                                       self.flags, self.rx_T, self.rx_A,
+                                                       self.rx_flags)))
+
+
+@dataclasses.dataclass
+class Green:
+    """Device tensors of rb_green: G [n][n_mask], H [3][n][n_mask] (complex64)."""
+
+    G: torch.Tensor
+    H: torch.Tensor
+
+    @classmethod
+    def empty(cls, n, n_mask, device):
+        return cls(torch.empty(n, n_mask, dtype=torch.complex64, device=device),
+                   torch.empty(3, n, n_mask, dtype=torch.complex64, device=device))
+
+    def struct(self):
+        n, nm = self.G.shape
+        return _Green(n, nm, RB_F32, self.G.data_ptr(), self.H.data_ptr())
+
+
+class Context:
+    """One rb_ctx bound to a torch device and its current stream."""
+
+    def __init__(self, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("raybornhf needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        idx = self.device.index or 0
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.rb_create(ctypes.byref(h), idx, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != RB_OK:
+            raise RayBornError(st, "rb_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.rb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != RB_OK:
+            raise RayBornError(st, self.lib.rb_last_error(self._h).decode())
+
+    # entry points (same names as the C ABI) ---------------------------------------------
+    def refractive_index(self, grid: Grid, c: torch.Tensor, c0: float, w: int) -> torch.Tensor:
+        _dev(c, torch.float64)
+        out = torch.empty(grid.ny, grid.nx, dtype=torch.float32, device=self.device)
+        self._check(self.lib.rb_refractive_index(self._h, ctypes.byref(grid), _ptr(c), c0, w,
+                                                 _ptr(out)))
+        return out
+
+    def trace_rays(self, grid: Grid, ring: Ring, tp: TraceParams, n_s: torch.Tensor) -> Tables:
+        _dev(n_s, torch.float32)
+        tb = Tables.empty(ring.n, mask_count(grid), self.device)
+        s = tb.struct()
+        self._check(self.lib.rb_trace_rays(self._h, ctypes.byref(grid), ctypes.byref(ring),
+                                           ctypes.byref(tp), _ptr(n_s), ctypes.byref(s)))
+        return tb
+
+    def build_green(self, tb: Tables, omega: float, c0: float, out: Green | None = None) -> Green:
+        n, nm = tb.T.shape
+        gr = out if out is not None else Green.empty(n, nm, self.device)
+        s, g = tb.struct(), gr.struct()
+        self._check(self.lib.rb_build_green(self._h, ctypes.byref(s), omega, c0, ctypes.byref(g)))
+        return gr
+
+    def born_forward(self, gr: Green, w: torch.Tensor, delta: torch.Tensor,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        _dev(w, torch.complex64)
+        _dev(delta, torch.float32)
+        n = gr.G.shape[0]
+        d = out if out is not None else torch.empty(n, n, dtype=torch.complex64, device=self.device)
+        g = gr.struct()
+        self._check(self.lib.rb_born_forward(self._h, ctypes.byref(g), _ptr(w), _ptr(delta),
+                                             _ptr(d)))
+        return d
+
+    def born_adjoint(self, gr: Green, w: torch.Tensor, R: torch.Tensor) -> torch.Tensor:
+        _dev(w, torch.complex64)
+        _dev(R, torch.complex64)
+        out = torch.empty(gr.G.shape[1], dtype=torch.float32, device=self.device)
+        g = gr.struct()
+        self._check(self.lib.rb_born_adjoint(self._h, ctypes.byref(g), _ptr(w), _ptr(R),
+                                             _ptr(out)))
+        return out
+
+    def residual(self, tb: Tables, omega: float, c0: float, data: torch.Tensor,
+                 d_born: torch.Tensor | None = None) -> torch.Tensor:
+        _dev(data, torch.complex64)
+        if d_born is not None:
+            _dev(d_born, torch.complex64)
+        R = torch.empty_like(data)
+        s = tb.struct()
+        self._check(self.lib.rb_residual(self._h, ctypes.byref(s), omega, c0, _ptr(d_born),
+                                         _ptr(data), _ptr(R)))
+        return R
+
+    def backproject(self, gr: Green, R: torch.Tensor, c_mask: torch.Tensor, omega: float,
+                    d_omega: float, out: torch.Tensor | None = None,
+                    accumulate: bool = False) -> torch.Tensor:
+        _dev(R, torch.complex64)
+        _dev(c_mask, torch.float64)
+        dm = out if out is not None else torch.empty(gr.G.shape[1], dtype=torch.float32,
+                                                     device=self.device)
+        g = gr.struct()
+        self._check(self.lib.rb_backproject(self._h, ctypes.byref(g), _ptr(R), _ptr(c_mask),
+                                            omega, d_omega, _ptr(dm), int(accumulate)))
+        return dm
+
+    def frequency_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
+                       smooth_w: int, omegas, d_omegas, data: torch.Tensor, tau: float,
+                       mode: int = RB_RAY_BORN, residual_norm: torch.Tensor | None = None):
+        """Updates c (float64 [ny][nx], on the GPU) in place."""
+        _dev(c, torch.float64)
+        _dev(data, torch.complex64)
+        k = len(omegas)
+        om = (ctypes.c_double * k)(*omegas)
+        dom = (ctypes.c_double * k)(*d_omegas)
+        self._check(self.lib.rb_frequency_step(
+            self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
+            int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), _ptr(residual_norm)))
+        return c

@@ -1,0 +1,390 @@
+// C-ABI entry points of raybornhf: argument validation, geometry cache, workspace, and the
+// orchestration of one frequency step (Section 3 and Section 6.3.2(a) of the paper).
+#include "rb_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq);
+rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0, float w,
+                               float *wv, float *delta);
+rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float *parts,
+                                           const double *c_mask, double omega, double d_omega,
+                                           double *dm_acc);
+rb_status rb_launch_zero_f64(rb_ctx *ctx, double *x, int n);
+rb_status rb_launch_update(rb_ctx *ctx, const double *cq, const double *dm, double tau,
+                           double *c_new);
+rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c);
+
+rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return st;
+}
+
+rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes) {
+    if (bytes <= a->cap) return RB_OK;
+    if (a->base) {
+        // kernels queued on the stream may still read the old block
+        RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        RB_HIP(ctx, hipFree(a->base));
+        a->base = nullptr;
+        a->cap = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return rb_fail(ctx, RB_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+    }
+    a->base = static_cast<char *>(p);
+    a->cap = bytes;
+    return RB_OK;
+}
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+rb_status rb_check_grid(rb_ctx *ctx, const rb_grid *g) {
+    if (!g) return rb_fail(ctx, RB_EINVAL, "grid is NULL");
+    if (g->nx < 4 || g->ny < 4) return rb_fail(ctx, RB_EINVAL, "grid must be at least 4x4");
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 30)
+        return rb_fail(ctx, RB_EINVAL, "grid too large");
+    if (!finite_pos(g->dx) || !std::isfinite(g->x0) || !std::isfinite(g->y0) ||
+        !finite_pos(g->mask_radius))
+        return rb_fail(ctx, RB_EINVAL, "grid spacing, origin and mask radius must be finite");
+    return RB_OK;
+}
+
+rb_status rb_check_ring(rb_ctx *ctx, const rb_grid *g, const rb_ring *r) {
+    if (!r) return rb_fail(ctx, RB_EINVAL, "ring is NULL");
+    if (r->n < 3 || r->n > 65536) return rb_fail(ctx, RB_EINVAL, "ring needs 3..65536 elements");
+    if (!finite_pos(r->radius) || !std::isfinite(r->psi0))
+        return rb_fail(ctx, RB_EINVAL, "ring radius must be positive");
+    if (g->mask_radius >= r->radius)
+        return rb_fail(ctx, RB_EINVAL, "imaging mask must lie inside the ring");
+    double xmax = g->x0 + (g->nx - 1) * g->dx, ymax = g->y0 + (g->ny - 1) * g->dx;
+    if (g->x0 > -r->radius || g->y0 > -r->radius || xmax < r->radius || ymax < r->radius)
+        return rb_fail(ctx, RB_EINVAL, "the grid must cover the ring");
+    return RB_OK;
+}
+
+rb_status rb_check_trace(rb_ctx *ctx, const rb_trace_params *tp) {
+    if (!tp) return rb_fail(ctx, RB_EINVAL, "trace parameters are NULL");
+    if (tp->n_rays < 2 || tp->n_rays > 2048)
+        return rb_fail(ctx, RB_EINVAL, "n_rays must be in 2..2048");
+    if (tp->max_steps < 1 || tp->max_steps > 100000)
+        return rb_fail(ctx, RB_EINVAL, "max_steps must be in 1..100000");
+    if ((uint64_t)tp->n_rays * (uint64_t)(tp->max_steps + 1) * 2 >= ((uint64_t)1 << 32))
+        return rb_fail(ctx, RB_EINVAL, "n_rays * (max_steps + 1) too large for triangle ids");
+    if (!finite_pos(tp->ds) || !finite_pos(tp->c0))
+        return rb_fail(ctx, RB_EINVAL, "ds and c0 must be positive");
+    return RB_OK;
+}
+
+static int64_t mask_list(const rb_grid *g, std::vector<int32_t> *idx, std::vector<int32_t> *map) {
+    int64_t n = 0;
+    double r2 = g->mask_radius * g->mask_radius;
+    if (map) map->assign((size_t)g->nx * g->ny, -1);
+    for (int j = 0; j < g->ny; ++j) {
+        double y = g->y0 + j * g->dx;
+        for (int i = 0; i < g->nx; ++i) {
+            double x = g->x0 + i * g->dx;
+            if (x * x + y * y <= r2) {
+                if (idx) idx->push_back(j * g->nx + i);
+                if (map) (*map)[(size_t)j * g->nx + i] = (int32_t)n;
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
+rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
+    if (ctx->have_grid && std::memcmp(&ctx->grid, g, sizeof(rb_grid)) == 0) return RB_OK;
+    std::vector<int32_t> idx, map;
+    int64_t n = mask_list(g, &idx, &map);
+    if (n < 1) return rb_fail(ctx, RB_EINVAL, "the imaging mask holds no grid node");
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->d_mask_index) RB_HIP(ctx, hipFree(ctx->d_mask_index));
+    if (ctx->d_qmap) RB_HIP(ctx, hipFree(ctx->d_qmap));
+    ctx->d_mask_index = nullptr;
+    ctx->d_qmap = nullptr;
+    ctx->have_grid = false;
+    RB_HIP(ctx, hipMalloc(&ctx->d_mask_index, n * sizeof(int32_t)));
+    RB_HIP(ctx, hipMalloc(&ctx->d_qmap, map.size() * sizeof(int32_t)));
+    RB_HIP(ctx, hipMemcpy(ctx->d_mask_index, idx.data(), n * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    RB_HIP(ctx, hipMemcpy(ctx->d_qmap, map.data(), map.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    ctx->grid = *g;
+    ctx->n_mask = n;
+    ctx->have_grid = true;
+    return RB_OK;
+}
+
+static rb_status check_tables(rb_ctx *ctx, const rb_tables *tb, int n, int64_t n_mask) {
+    if (!tb) return rb_fail(ctx, RB_EINVAL, "tables are NULL");
+    if (tb->n != n || tb->n_mask != n_mask)
+        return rb_fail(ctx, RB_EINVAL, "tables sized [%d][%d], expected [%d][%lld]", tb->n,
+                       tb->n_mask, n, (long long)n_mask);
+    if (!tb->T || !tb->A || !tb->ux || !tb->uy || !tb->flags || !tb->rx_T || !tb->rx_A ||
+        !tb->rx_flags)
+        return rb_fail(ctx, RB_EINVAL, "a table pointer is NULL");
+    return RB_OK;
+}
+
+static rb_status check_green(rb_ctx *ctx, const rb_green *gr) {
+    if (!gr) return rb_fail(ctx, RB_EINVAL, "green operands are NULL");
+    if (gr->n < 1 || gr->n_mask < 1 || !gr->G || !gr->H)
+        return rb_fail(ctx, RB_EINVAL, "green operands incomplete");
+    if (gr->prec != RB_F32)
+        return rb_fail(ctx, RB_EUNSUPPORTED, "only RB_F32 operands are available");
+    return RB_OK;
+}
+
+#define RB_TRY(x)                       \
+    do {                                \
+        rb_status s_ = (x);             \
+        if (s_ != RB_OK) return s_;     \
+    } while (0)
+
+extern "C" {
+
+rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
+    if (!out) return RB_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return RB_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return RB_EDEVICE;
+    rb_ctx *ctx = new rb_ctx();
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipMalloc(&ctx->d_flag, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        rb_destroy(ctx);
+        return RB_EDEVICE;
+    }
+    *out = ctx;
+    return RB_OK;
+}
+
+void rb_destroy(rb_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws.base) (void)hipFree(ctx->ws.base);
+    if (ctx->step.base) (void)hipFree(ctx->step.base);
+    if (ctx->d_mask_index) (void)hipFree(ctx->d_mask_index);
+    if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
+    if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
+    delete ctx;
+}
+
+const char *rb_last_error(const rb_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int64_t rb_mask_count(const rb_grid *grid) {
+    if (!grid || grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0)) return -1;
+    return mask_list(grid, nullptr, nullptr);
+}
+
+rb_status rb_refractive_index(rb_ctx *ctx, const rb_grid *grid, const double *c, double c0,
+                              int32_t w, float *n_s) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    if (!c || !n_s) return rb_fail(ctx, RB_EINVAL, "c and n_s must be device pointers");
+    if (w < 1 || (w & 1) == 0) return rb_fail(ctx, RB_EINVAL, "window must be odd and >= 1");
+    if (!finite_pos(c0)) return rb_fail(ctx, RB_EINVAL, "c0 must be positive");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    return rb_launch_refractive_index(ctx, grid, c, c0, w, n_s);
+}
+
+rb_status rb_trace_rays(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                        const rb_trace_params *tp, const float *n_s, const rb_tables *out) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    RB_TRY(rb_check_trace(ctx, tp));
+    if (!n_s) return rb_fail(ctx, RB_EINVAL, "n_s is NULL");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    RB_TRY(check_tables(ctx, out, ring->n, ctx->n_mask));
+    return rb_launch_trace(ctx, grid, ring, tp, n_s, out);
+}
+
+rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                         const rb_green *out) {
+    if (!ctx) return RB_EINVAL;
+    if (!tb) return rb_fail(ctx, RB_EINVAL, "tables are NULL");
+    RB_TRY(check_tables(ctx, tb, tb->n, tb->n_mask));
+    RB_TRY(check_green(ctx, out));
+    if (out->n != tb->n || out->n_mask != tb->n_mask)
+        return rb_fail(ctx, RB_EINVAL, "green operands and tables differ in size");
+    if (tb->n < 3 || tb->n_mask < 1) return rb_fail(ctx, RB_EINVAL, "empty tables");
+    if (!finite_pos(omega) || !finite_pos(c0))
+        return rb_fail(ctx, RB_EINVAL, "omega and c0 must be positive");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    return rb_launch_green(ctx, tb, omega, c0, out);
+}
+
+rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
+                          float *d) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_green(ctx, gr));
+    if (!w || !delta || !d) return rb_fail(ctx, RB_EINVAL, "w, delta and d must be non-NULL");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    return rb_launch_forward(ctx, gr, w, delta, d);
+}
+
+rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const float *R,
+                          float *grad) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_green(ctx, gr));
+    if (!w || !R || !grad) return rb_fail(ctx, RB_EINVAL, "w, R and grad must be non-NULL");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    int mb = rb_rowred_mblocks(gr->n);
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float))));
+    float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
+    RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->G, 1, 1, parts, &mb));
+    return rb_launch_adjoint_finish(ctx, gr->n_mask, mb, parts, w, grad);
+}
+
+rb_status rb_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                      const float *d_born, const float *data, float *R) {
+    if (!ctx) return RB_EINVAL;
+    if (!tb) return rb_fail(ctx, RB_EINVAL, "tables are NULL");
+    RB_TRY(check_tables(ctx, tb, tb->n, tb->n_mask));
+    if (!data || !R) return rb_fail(ctx, RB_EINVAL, "data and R must be non-NULL");
+    if (!finite_pos(omega) || !finite_pos(c0))
+        return rb_fail(ctx, RB_EINVAL, "omega and c0 must be positive");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    return rb_launch_residual(ctx, tb, omega, c0, d_born, data, R, nullptr);
+}
+
+rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
+                         double omega, double d_omega, float *dm, int32_t accumulate) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_green(ctx, gr));
+    if (!R || !c_mask || !dm) return rb_fail(ctx, RB_EINVAL, "R, c_mask and dm must be non-NULL");
+    if (!finite_pos(omega) || !finite_pos(d_omega))
+        return rb_fail(ctx, RB_EINVAL, "omega and d_omega must be positive");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    int mb = rb_rowred_mblocks(gr->n);
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float))));
+    float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
+    RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, parts, &mb));
+    return rb_launch_backproject_finish(ctx, gr->n_mask, mb, parts, c_mask, omega, d_omega, dm,
+                                        accumulate);
+}
+
+rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            int32_t n_omega, const double *omega, const double *d_omega,
+                            const float *data, double tau, rb_mode mode,
+                            double *residual_norm) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    RB_TRY(rb_check_trace(ctx, tp));
+    if (!c || !data) return rb_fail(ctx, RB_EINVAL, "c and data must be device pointers");
+    if (n_omega < 1 || !omega || !d_omega)
+        return rb_fail(ctx, RB_EINVAL, "need at least one frequency (host arrays)");
+    for (int k = 0; k < n_omega; ++k)
+        if (!finite_pos(omega[k]) || !finite_pos(d_omega[k]))
+            return rb_fail(ctx, RB_EINVAL, "frequencies and spacings must be positive");
+    if (smooth_w < 1 || (smooth_w & 1) == 0)
+        return rb_fail(ctx, RB_EINVAL, "smoothing window must be odd and >= 1");
+    if (!std::isfinite(tau)) return rb_fail(ctx, RB_EINVAL, "tau must be finite");
+    if (mode != RB_RAY_BORN && mode != RB_RAY_ONLY)
+        return rb_fail(ctx, RB_EINVAL, "unknown mode");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_TRY(rb_prepare_grid(ctx, grid));
+
+    const int N = ring->n;
+    const int nm = (int)ctx->n_mask;
+    const size_t P = (size_t)grid->nx * grid->ny;
+    const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
+    const int mb = rb_rowred_mblocks(N);
+    size_t bytes = rb_align(P * 4) + rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP) +
+                   rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * 8) +
+                   rb_align(3 * NP * 8) + 2 * rb_align(NN * 8) + rb_align((size_t)nm * 8) +
+                   rb_align((size_t)nm * 4) + 3 * rb_align((size_t)nm * 8) +
+                   rb_align((size_t)2 * mb * nm * 4) + rb_align(8);
+    ctx->step.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->step, bytes));
+    rb_arena *a = &ctx->step;
+    float *n_s = rb_carve<float>(a, P);
+    rb_tables tb;
+    tb.n = N;
+    tb.n_mask = nm;
+    tb.T = rb_carve<double>(a, NP);
+    tb.A = rb_carve<float>(a, NP);
+    tb.ux = rb_carve<float>(a, NP);
+    tb.uy = rb_carve<float>(a, NP);
+    tb.flags = rb_carve<uint8_t>(a, NP);
+    tb.rx_T = rb_carve<double>(a, NN);
+    tb.rx_A = rb_carve<float>(a, NN);
+    tb.rx_flags = rb_carve<uint8_t>(a, NN);
+    rb_green gr;
+    gr.n = N;
+    gr.n_mask = nm;
+    gr.prec = RB_F32;
+    gr.G = rb_carve<float2>(a, NP);
+    gr.H = rb_carve<float2>(a, 3 * NP);
+    float *d_born = rb_carve<float>(a, 2 * NN);
+    float *R = rb_carve<float>(a, 2 * NN);
+    float *wv = rb_carve<float>(a, 2 * (size_t)nm);
+    float *delta = rb_carve<float>(a, nm);
+    double *cq = rb_carve<double>(a, nm);
+    double *dm = rb_carve<double>(a, nm);
+    double *c_new = rb_carve<double>(a, nm);
+    float *parts = rb_carve<float>(a, (size_t)2 * mb * nm);
+
+    // a1: tracing map; a2-a3: rays and tables (independent of omega when lossless)
+    RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, n_s));
+    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, n_s, &tb));
+    RB_TRY(rb_launch_gather_mask(ctx, c, cq));
+    RB_TRY(rb_launch_zero_f64(ctx, dm, nm));
+    if (residual_norm) RB_HIP(ctx, hipMemsetAsync(residual_norm, 0, sizeof(double), ctx->stream));
+    for (int k = 0; k < n_omega; ++k) {
+        const double om = omega[k];
+        // a4: Green's functions and back-projection operands
+        RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr));
+        // a5-a6: predicted data (ray part + Born term of the rough part) and residual
+        const float *born = nullptr;
+        if (mode == RB_RAY_BORN) {
+            RB_TRY(rb_launch_rough_part(ctx, cq, n_s, tp->c0, (float)(om * om * grid->dx * grid->dx),
+                                        wv, delta));
+            RB_TRY(rb_launch_forward(ctx, &gr, wv, delta, d_born));
+            born = d_born;
+        }
+        RB_TRY(rb_launch_residual(ctx, &tb, om, tp->c0, born, data + 2 * NN * (size_t)k, R,
+                                  residual_norm));
+        // a8: Hessian-free back-projection, accumulated over the set in FP64
+        int mbo = mb;
+        RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, parts, &mbo));
+        RB_TRY(rb_launch_backproject_finish_acc(ctx, mbo, parts, cq, om, d_omega[k], dm));
+    }
+    // a9: model update, committed only if every value is finite
+    RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
+    RB_TRY(rb_launch_update(ctx, cq, dm, tau, c_new));
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*ctx->h_flag & 2)
+        return rb_fail(ctx, RB_ENONFINITE, "non-finite model update rejected; c unchanged");
+    RB_TRY(rb_launch_commit(ctx, c_new, c));
+    return RB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Green's-function assembly, residual, back-projection scaling and model update (gfx950).
+//
+// Eq. 2D_greens: g = A exp(i [phi + pi/4]) with A_geom = A_tab / sqrt(k0);
+// Eq. phase-discretised: phi = omega T - (pi/2) K (lossless);
+// Eq. greens-time-reversed: g_dagger = A^-1 exp(-i [phi + pi/4]);
+// Eq. sound_speed_update2: angular weights |d gamma_e / d e| De (central difference over
+// neighbouring transducers), pair weight |kbar| |d|kbar|/d omega| = (2k/c)(1 + u_e . u_r)
+// split into the three operands H, H u_x, H u_y; scale S = (Domega/(2 pi)^3)(2k/c)/omega^2.
+// Eq. residual: g_res = g - data; Section 3.4: m <- m + tau dm, c = m^-1/2 (FP64).
+//
+// These kernels are elementwise and bound by HBM bandwidth: each reads its table entries
+// once and writes the operands with coalesced 8-byte stores; only the phase is in FP64.
+#include "rb_internal.h"
+
+namespace {
+
+__device__ __forceinline__ double reduce_phase(double ph) {
+    return ph - RB_TWO_PI * floor(ph / RB_TWO_PI);
+}
+
+// One thread per (transducer e, mask node q); grid.y = e.
+__global__ void __launch_bounds__(256) green_kernel(rb_tables tb, int N, int n_mask,
+                                                    double omega, double c0,
+                                                    float2 *__restrict__ G,
+                                                    float2 *__restrict__ H) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int e = blockIdx.y;
+    if (q >= n_mask) return;
+    size_t o = (size_t)e * n_mask + q;
+    size_t plane = (size_t)N * n_mask;
+    uint8_t f = tb.flags[o];
+    if (!(f & 0x80)) {
+        G[o] = make_float2(0.f, 0.f);
+        H[o] = make_float2(0.f, 0.f);
+        H[plane + o] = make_float2(0.f, 0.f);
+        H[2 * plane + o] = make_float2(0.f, 0.f);
+        return;
+    }
+    double k0 = omega / c0;
+    double ph = reduce_phase(omega * tb.T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI);
+    float s, c;
+    sincosf((float)ph, &s, &c);
+    float A = tb.A[o];
+    float sk = (float)sqrt(k0);
+    float ga = A / sk;
+    G[o] = make_float2(ga * c, ga * s);
+
+    // angular weight: angle between the ray directions of the neighbouring transducers
+    int em = (e + N - 1) % N, ep = (e + 1) % N;
+    size_t om = (size_t)em * n_mask + q, op = (size_t)ep * n_mask + q;
+    bool vm = tb.flags[om] & 0x80, vp = tb.flags[op] & 0x80;
+    float ux = tb.ux[o], uy = tb.uy[o];
+    float a = 0.f;
+    if (vm && vp) {
+        float ax = tb.ux[om], ay = tb.uy[om], bx = tb.ux[op], by = tb.uy[op];
+        a = 0.5f * fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
+    } else if (vp) {
+        float bx = tb.ux[op], by = tb.uy[op];
+        a = fabsf(atan2f(ux * by - uy * bx, ux * bx + uy * by));
+    } else if (vm) {
+        float ax = tb.ux[om], ay = tb.uy[om];
+        a = fabsf(atan2f(ax * uy - ay * ux, ax * ux + ay * uy));
+    }
+    float ha = a * sk / A;
+    float hr = ha * c, hi = -ha * s;
+    H[o] = make_float2(hr, hi);
+    H[plane + o] = make_float2(hr * ux, hi * ux);
+    H[2 * plane + o] = make_float2(hr * uy, hi * uy);
+}
+
+// R[e][r] = g_rx + d_born - data on valid pairs with e != r; sum |R|^2 into *norm.
+__global__ void __launch_bounds__(256) residual_kernel(const double *__restrict__ rx_T,
+                                                       const float *__restrict__ rx_A,
+                                                       const uint8_t *__restrict__ rx_flags,
+                                                       int N, double omega, double c0,
+                                                       const float2 *__restrict__ d_born,
+                                                       const float2 *__restrict__ data,
+                                                       float2 *__restrict__ R, double *norm) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
+    bool in = r < N;
+    size_t o = (size_t)e * N + (in ? r : 0);
+    uint8_t f = in ? rx_flags[o] : 0;
+    float2 out = make_float2(0.f, 0.f);
+    if ((f & 0x80) && r != e) {
+        double k0 = omega / c0;
+        double ph = reduce_phase(omega * rx_T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI);
+        double s, c;
+        sincos(ph, &s, &c);
+        double a = (double)rx_A[o] / sqrt(k0);
+        double gr = a * c, gi = a * s;
+        if (d_born) {
+            gr += d_born[o].x;
+            gi += d_born[o].y;
+        }
+        float2 dd = data[o];
+        out = make_float2((float)(gr - dd.x), (float)(gi - dd.y));
+    }
+    if (in) R[o] = out;
+    if (norm) {
+        double v = (double)out.x * out.x + (double)out.y * out.y;
+        // wavefront sum, then one atomic per wavefront
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if ((threadIdx.x & 63) == 0) atomicAdd(norm, v);
+    }
+}
+
+__global__ void adjoint_finish_kernel(int n_mask, int mblocks, const float *__restrict__ parts,
+                                      const float2 *__restrict__ w, float *__restrict__ grad) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    float sr = 0.f, si = 0.f;
+    for (int b = 0; b < mblocks; ++b) {
+        sr += parts[(size_t)b * n_mask + q];
+        si += parts[(size_t)(mblocks + b) * n_mask + q];
+    }
+    float2 ww = w[q];
+    grad[q] = ww.x * sr + ww.y * si;  // Re{ conj(w) (sr + i si) }
+}
+
+template <typename OutT>
+__global__ void backproject_finish_kernel(int n_mask, int mblocks, const float *__restrict__ parts,
+                                          const double *__restrict__ c_mask, double omega,
+                                          double d_omega, OutT *__restrict__ dm, int accumulate) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    double sr = 0.0;
+    for (int b = 0; b < mblocks; ++b) sr += (double)parts[(size_t)b * n_mask + q];
+    double c = c_mask[q];
+    double S = 2.0 * d_omega / (RB_TWO_PI * RB_TWO_PI * RB_TWO_PI * omega * c * c);
+    double v = -S * sr;
+    if (accumulate) v += (double)dm[q];
+    dm[q] = (OutT)v;
+}
+
+// c at the mask nodes (double) gathered from the full map.
+__global__ void gather_mask(const double *__restrict__ c, const int32_t *__restrict__ mask_index,
+                            int n_mask, double *__restrict__ cq) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n_mask) cq[q] = c[mask_index[q]];
+}
+
+// w = omega^2 h^2 (complex, imaginary part 0) and delta = m - m_s at the mask nodes, where
+// m_s = (n_s / c0)^2 is the squared slowness of the smoothed map the rays were traced on.
+__global__ void rough_part(const double *__restrict__ cq, const float *__restrict__ n_s,
+                           const int32_t *__restrict__ mask_index, int n_mask, double c0,
+                           float w, float2 *__restrict__ wv, float *__restrict__ delta) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    double c = cq[q];
+    double ns = (double)n_s[mask_index[q]];
+    delta[q] = (float)(1.0 / (c * c) - ns * ns / (c0 * c0));
+    wv[q] = make_float2(w, 0.f);
+}
+
+// m <- m + tau dm (FP64); the candidate c is kept aside until every value is finite.
+__global__ void update_kernel(const double *__restrict__ cq, const double *__restrict__ dm,
+                              int n_mask, double tau, double *__restrict__ c_new, int *flag) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    double c = cq[q];
+    double m = 1.0 / (c * c) + tau * dm[q];
+    double cn = 1.0 / sqrt(m);
+    if (!(m > 0.0) || !isfinite(cn)) atomicOr(flag, 2);
+    c_new[q] = cn;
+}
+
+__global__ void commit_kernel(const double *__restrict__ c_new,
+                              const int32_t *__restrict__ mask_index, int n_mask,
+                              double *__restrict__ c) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n_mask) c[mask_index[q]] = c_new[q];
+}
+
+__global__ void zero_f64(double *x, int n) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) x[q] = 0.0;
+}
+
+inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                          const rb_green *out) {
+    dim3 grd(blocks(tb->n_mask), tb->n);
+    hipLaunchKernelGGL(green_kernel, grd, dim3(256), 0, ctx->stream, *tb, tb->n, tb->n_mask, omega,
+                       c0, (float2 *)out->G, (float2 *)out->H);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                             const float *d_born, const float *data, float *R,
+                             double *residual_norm) {
+    dim3 grd(blocks(tb->n), tb->n);
+    hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, ctx->stream, tb->rx_T, tb->rx_A,
+                       tb->rx_flags, tb->n, omega, c0, (const float2 *)d_born,
+                       (const float2 *)data, (float2 *)R, residual_norm);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_adjoint_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
+                                   const float *w, float *grad) {
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(blocks(n_mask)), dim3(256), 0, ctx->stream,
+                       n_mask, mblocks, parts, (const float2 *)w, grad);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
+                                       const double *c_mask, double omega, double d_omega,
+                                       float *dm, int accumulate) {
+    hipLaunchKernelGGL(backproject_finish_kernel<float>, dim3(blocks(n_mask)), dim3(256), 0,
+                       ctx->stream, n_mask, mblocks, parts, c_mask, omega, d_omega, dm,
+                       accumulate);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+// Internal helpers of rb_frequency_step --------------------------------------------------
+rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(gather_mask, dim3(blocks(n)), dim3(256), 0, ctx->stream, c,
+                       ctx->d_mask_index, n, cq);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0, float w,
+                               float *wv, float *delta) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(rough_part, dim3(blocks(n)), dim3(256), 0, ctx->stream, cq, n_s,
+                       ctx->d_mask_index, n, c0, w, (float2 *)wv, delta);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float *parts,
+                                           const double *c_mask, double omega, double d_omega,
+                                           double *dm_acc) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(backproject_finish_kernel<double>, dim3(blocks(n)), dim3(256), 0,
+                       ctx->stream, n, mblocks, parts, c_mask, omega, d_omega, dm_acc, 1);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_zero_f64(rb_ctx *ctx, double *x, int n) {
+    hipLaunchKernelGGL(zero_f64, dim3(blocks(n)), dim3(256), 0, ctx->stream, x, n);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_update(rb_ctx *ctx, const double *cq, const double *dm, double tau,
+                           double *c_new) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(update_kernel, dim3(blocks(n)), dim3(256), 0, ctx->stream, cq, dm, n, tau,
+                       c_new, ctx->d_flag);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(commit_kernel, dim3(blocks(n)), dim3(256), 0, ctx->stream, c_new,
+                       ctx->d_mask_index, n, c);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}

@@ -1,0 +1,91 @@
+// Internal declarations shared by the raybornhf HIP sources (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "raybornhf.h"
+
+#define RB_PI 3.14159265358979323846
+#define RB_TWO_PI 6.28318530717958647692
+
+// Device workspace owned by a context: one growing allocation, carved into aligned parts.
+struct rb_arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
+struct rb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char err[512] = {0};
+
+    // geometry cache: mask node list and node -> mask index map of the last grid seen
+    rb_grid grid{};
+    bool have_grid = false;
+    int64_t n_mask = 0;
+    int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
+    int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
+
+    rb_arena ws;                      // scratch of the current call
+    rb_arena step;                    // persistent buffers of rb_frequency_step
+    int32_t *d_flag = nullptr;        // device error flags (ray overflow, non-finite update)
+    int32_t *h_flag = nullptr;        // pinned host mirror
+};
+
+// Error reporting -------------------------------------------------------------------------
+rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...);
+
+#define RB_HIP(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return rb_fail((ctx), RB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RB_CHECK_LAUNCH(ctx) RB_HIP(ctx, hipGetLastError())
+
+// Workspace -------------------------------------------------------------------------------
+// Ensure the arena holds at least `bytes` (reallocates, dropping old contents).
+rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes);
+inline size_t rb_align(size_t x) { return (x + 255) & ~size_t(255); }
+template <typename T> T *rb_carve(rb_arena *a, size_t count) {
+    T *p = reinterpret_cast<T *>(a->base + a->used);
+    a->used += rb_align(count * sizeof(T));
+    return p;
+}
+
+// Geometry --------------------------------------------------------------------------------
+rb_status rb_check_grid(rb_ctx *ctx, const rb_grid *g);
+rb_status rb_check_ring(rb_ctx *ctx, const rb_grid *g, const rb_ring *r);
+rb_status rb_check_trace(rb_ctx *ctx, const rb_trace_params *tp);
+// Upload the mask list for this grid if it differs from the cached one.
+rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g);
+
+// Stage launchers (each validates nothing; callers have validated) -------------------------
+rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
+                                     int w, float *n_s);
+rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
+                          const rb_trace_params *tp, const float *n_s, const rb_tables *out);
+rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                          const rb_green *out);
+rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                             const float *d_born, const float *data, float *R,
+                             double *residual_norm);
+rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
+                            float *d);
+// Row-reduced complex GEMM: parts[2][mblocks][n_mask] (re, im) of
+// sum_e E_c[e][q] (R B_c)[e][q] summed over the n_comp components c.
+rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const float *B,
+                           int n_comp, int conj_b, float *parts, int *mblocks);
+rb_status rb_launch_adjoint_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
+                                   const float *w, float *grad);
+rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
+                                       const double *c_mask, double omega, double d_omega,
+                                       float *dm, int accumulate);
+int rb_rowred_mblocks(int n);

@@ -1,0 +1,580 @@
+// Ray tracing and ray-to-grid binning on gfx950.
+//
+// Section 4 of the paper: Hamiltonian ray equations (Eq. ray-equation-reference) and the
+// paraxial system (Eq. ray-equation-paraxial) integrated together by Heun's method with the
+// wave-vector normalisations of Algorithm 1; initial conditions of Section 4.4; ray
+// sampling of Definition 1 (last step lands on the ring); travel time by the trapezoid rule
+// (Eq. phase-discretised / omega), caustic count from sign changes of the Jacobian, and the
+// geometric amplitude of Eq. amplitude-geom-discretised referenced to the first sample by
+// Eq. attenuation_geom_reference. Section 4.5: the map is the uniform cubic B-spline of the
+// grid samples; ray-to-grid by linear interpolation over the triangulated ray samples.
+//
+// GPU design: one lane per ray, the 64 lanes of a wavefront are 64 neighbouring rays of one
+// transducer, so the per-step sample stores are coalesced ([emitter][step][ray] planes).
+// Positions and the travel time are kept in FP64 (one FMA each per step); the rest of the
+// ray and paraxial state is FP32. The spline at the new point is reused as the first
+// evaluation of the next step. Binning: one lane per quad of neighbouring samples; each
+// covered mask node keeps the smallest (travel-time, triangle-id) 64-bit key by atomicMin
+// (order independent, hence deterministic); a resolve pass per node re-interpolates the
+// winning triangle and writes the tables with coalesced stores.
+#include "rb_internal.h"
+
+#include <cmath>
+
+namespace {
+
+struct GridP {
+    int nx, ny;
+    double dx, x0, y0;
+};
+
+struct Spline {
+    float v, gx, gy, hxx, hxy, hyy;
+};
+
+// Uniform cubic B-spline weights of control points iu-1 .. iu+2 at offset t in [0, 1).
+__device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], float dd[4]) {
+    float t2 = t * t, t3 = t2 * t, s = 1.0f - t;
+    b[0] = s * s * s * (1.0f / 6.0f);
+    b[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+    b[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+    b[3] = t3 * (1.0f / 6.0f);
+    d[0] = -0.5f * s * s;
+    d[1] = 0.5f * (3.0f * t2 - 4.0f * t);
+    d[2] = 0.5f * (-3.0f * t2 + 2.0f * t + 1.0f);
+    d[3] = 0.5f * t2;
+    dd[0] = s;
+    dd[1] = 3.0f * t - 2.0f;
+    dd[2] = 1.0f - 3.0f * t;
+    dd[3] = t;
+}
+
+// Value, gradient and Hessian (per metre) of the spline of f at (x, y).
+__device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const GridP &g,
+                                              double x, double y) {
+    double u = (x - g.x0) / g.dx, v = (y - g.y0) / g.dx;
+    double fu = floor(u), fv = floor(v);
+    int iu = (int)fu, iv = (int)fv;
+    float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
+    bspline_basis((float)(u - fu), bu, du, ddu);
+    bspline_basis((float)(v - fv), bv, dv, ddv);
+    int ii[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ii[a] = min(max(iu - 1 + a, 0), g.nx - 1);
+    float s_v = 0, s_gx = 0, s_gy = 0, s_xx = 0, s_xy = 0, s_yy = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        int jj = min(max(iv - 1 + b, 0), g.ny - 1);
+        const float *row = f + (size_t)jj * g.nx;
+        float r0 = 0, r1 = 0, r2 = 0;  // row sums with B, B', B''
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            float fab = __ldg(row + ii[a]);
+            r0 = fmaf(bu[a], fab, r0);
+            r1 = fmaf(du[a], fab, r1);
+            r2 = fmaf(ddu[a], fab, r2);
+        }
+        s_v = fmaf(bv[b], r0, s_v);
+        s_gx = fmaf(bv[b], r1, s_gx);
+        s_gy = fmaf(dv[b], r0, s_gy);
+        s_xx = fmaf(bv[b], r2, s_xx);
+        s_xy = fmaf(dv[b], r1, s_xy);
+        s_yy = fmaf(ddv[b], r0, s_yy);
+    }
+    float ih = (float)(1.0 / g.dx), ih2 = ih * ih;
+    return Spline{s_v, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
+}
+
+struct Ray {
+    double x, y;
+    float kx, ky, dxx, dxy, dkx, dky;
+};
+
+// Paraxial right-hand side (Eq. ray-equation-paraxial with k -> n).
+__device__ __forceinline__ void paraxial_rhs(const Spline &s, float kx, float ky, float dxx,
+                                             float dxy, float dkx, float dky, float q[4]) {
+    float n = s.v, in = 1.0f / n, in2 = in * in;
+    float gdx = s.gx * dxx + s.gy * dxy;
+    float kdk = kx * dkx + ky * dky;
+    q[0] = -gdx * in2 * kx + dkx * in;
+    q[1] = -gdx * in2 * ky + dky * in;
+    q[2] = s.hxx * dxx + s.hxy * dxy - gdx * in * s.gx + kdk * in2 * s.gx;
+    q[3] = s.hxy * dxx + s.hyy * dxy - gdx * in * s.gy + kdk * in2 * s.gy;
+}
+
+// One step of Algorithm 1 of length h, given the spline at the current point.
+__device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const GridP &g,
+                                         const Spline &s1, const Ray &r, double h) {
+    float hf = (float)h;
+    float n = s1.v;
+    float kn = sqrtf(r.kx * r.kx + r.ky * r.ky);
+    float kx = n * r.kx / kn, ky = n * r.ky / kn;          // normalise the ray direction
+    float qxx = kx / n, qxy = ky / n;
+    float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
+    double xp = r.x + h * (double)qxx, yp = r.y + h * (double)qxy;
+    Spline s2 = spline_eval(ns, g, xp, yp);                 // auxiliary wavenumber
+    float n2 = s2.v;
+    float kpn = sqrtf(kpx * kpx + kpy * kpy);
+    kpx = n2 * kpx / kpn;
+    kpy = n2 * kpy / kpn;
+    float qxx2 = kpx / n2, qxy2 = kpy / n2;
+    float sx = qxx + qxx2, sy = qxy + qxy2;
+    float sn = sqrtf(sx * sx + sy * sy);
+    Ray o;
+    o.x = r.x + h * (double)(sx / sn);                      // position along mean direction
+    o.y = r.y + h * (double)(sy / sn);
+    o.kx = kx + hf * (s1.gx + s2.gx) * 0.5f;
+    o.ky = ky + hf * (s1.gy + s2.gy) * 0.5f;
+    float a[4], b[4];
+    paraxial_rhs(s1, kx, ky, r.dxx, r.dxy, r.dkx, r.dky, a);
+    float dkpx = r.dkx + hf * a[2], dkpy = r.dky + hf * a[3];
+    float dxpx = r.dxx + hf * a[0], dxpy = r.dxy + hf * a[1];
+    paraxial_rhs(s2, kpx, kpy, dxpx, dxpy, dkpx, dkpy, b);
+    o.dxx = r.dxx + hf * (a[0] + b[0]) * 0.5f;
+    o.dxy = r.dxy + hf * (a[1] + b[1]) * 0.5f;
+    o.dkx = r.dkx + hf * (a[2] + b[2]) * 0.5f;
+    o.dky = r.dky + hf * (a[3] + b[3]) * 0.5f;
+    return o;
+}
+
+struct SampleBufs {
+    float *u, *v, *dT, *L, *tx, *ty;  // [E][S][n_rays]
+    uint8_t *K;
+    int32_t *M;                        // [E][n_rays] last sample index, -1 if invalid
+    double *ex_beta;                   // [E][n_rays] exit angle from psi_e in [0, 2 pi)
+    float *ex_dT, *ex_L;
+    uint8_t *ex_K;
+};
+
+__global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns, GridP g,
+                                                    double R, double psi0, int N, int n_rays,
+                                                    int max_steps, double ds, double c0, int e0,
+                                                    int E, SampleBufs sb, int *flag) {
+    int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= E * n_rays) return;
+    int el = tid / n_rays, j = tid - el * n_rays;
+    int e = e0 + el;
+    const int S = max_steps + 1;
+    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    double xe = R * cos(psi), ye = R * sin(psi);
+    double gam = psi + RB_PI + ((double)j + 0.5 - 0.5 * (double)n_rays) * RB_PI / (double)n_rays;
+    double cg = cos(gam), sg = sin(gam);
+
+    Ray r;
+    r.x = xe;
+    r.y = ye;
+    Spline sc = spline_eval(ns, g, r.x, r.y);
+    float n_cur = sc.v;
+    r.kx = n_cur * (float)cg;
+    r.ky = n_cur * (float)sg;
+    r.dxx = 0.0f;
+    r.dxy = 0.0f;
+    r.dkx = -n_cur * (float)sg;
+    r.dky = n_cur * (float)cg;
+    double T = 0.0;
+
+    size_t base = (size_t)el * S * n_rays + j;
+    const float idx = (float)(1.0 / g.dx);
+    sb.u[base] = (float)((r.x - g.x0) / g.dx);
+    sb.v[base] = (float)((r.y - g.y0) / g.dx);
+    sb.dT[base] = 0.0f;
+    sb.L[base] = 0.0f;
+    sb.tx[base] = (float)cg;
+    sb.ty[base] = (float)sg;
+    sb.K[base] = 0;
+    (void)idx;
+
+    float J_prev = 0.0f, J1 = 0.0f, n1 = 1.0f;
+    float inv_sqrt_8pi_s1 = 0.0f;
+    int K = 0;
+    int M = -1;
+    const double R2 = R * R;
+    for (int i = 0; i < max_steps; ++i) {
+        Ray nr = heun_step(ns, g, sc, r, ds);
+        double h = ds;
+        bool last = nr.x * nr.x + nr.y * nr.y >= R2;
+        if (last) {
+            // Definition 1: redo the step with ds' = distance along the unit direction to
+            // the ring.
+            double kn = sqrt((double)r.kx * r.kx + (double)r.ky * r.ky);
+            double tx = r.kx / kn, ty = r.ky / kn;
+            double b = r.x * tx + r.y * ty;
+            double disc = b * b + R2 - (r.x * r.x + r.y * r.y);
+            h = -b + sqrt(fmax(disc, 0.0));
+            h = fmin(fmax(h, 0.0), ds);
+            nr = heun_step(ns, g, sc, r, h);
+        }
+        r = nr;
+        sc = spline_eval(ns, g, r.x, r.y);
+        float n_new = sc.v;
+        T += h * ((double)n_cur + (double)n_new) / (2.0 * c0);
+        float kn = sqrtf(r.kx * r.kx + r.ky * r.ky);
+        float tx = r.kx / kn, ty = r.ky / kn;
+        float J = r.dxx * (-ty) + r.dxy * tx;
+        if (i >= 1 && J * J_prev < 0.0f) ++K;
+        double d = sqrt((r.x - xe) * (r.x - xe) + (r.y - ye) * (r.y - ye));
+        if (i == 0) {
+            J1 = J;
+            n1 = n_new;
+            inv_sqrt_8pi_s1 = (float)(1.0 / sqrt(8.0 * RB_PI * d));
+        }
+        float A = sqrtf(n1 / n_new * J1 / fabsf(J)) * inv_sqrt_8pi_s1;
+        float dT = (float)(T - d / c0);
+        float L = logf(A) + 0.5f * (float)log(d);
+        size_t o = base + (size_t)(i + 1) * n_rays;
+        sb.u[o] = (float)((r.x - g.x0) / g.dx);
+        sb.v[o] = (float)((r.y - g.y0) / g.dx);
+        sb.dT[o] = dT;
+        sb.L[o] = L;
+        sb.tx[o] = tx;
+        sb.ty[o] = ty;
+        sb.K[o] = (uint8_t)min(K, 255);
+        J_prev = J;
+        n_cur = n_new;
+        if (last) {
+            M = i + 1;
+            double beta = atan2(r.y, r.x) - psi;
+            beta = beta - RB_TWO_PI * floor(beta / RB_TWO_PI);
+            size_t x = (size_t)el * n_rays + j;
+            sb.ex_beta[x] = beta;
+            sb.ex_dT[x] = dT;
+            sb.ex_L[x] = L;
+            sb.ex_K[x] = (uint8_t)min(K, 255);
+            break;
+        }
+    }
+    sb.M[(size_t)el * n_rays + j] = M;
+    if (M < 0) atomicOr(flag, 1);
+}
+
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Barycentric coordinates of node (pu, pv) in triangle (a, b, c), node-index units.
+__device__ __forceinline__ bool barycentric(float au, float av, float bu, float bv, float cu,
+                                            float cv, float pu, float pv, float &la, float &lb,
+                                            float &lc) {
+    float area = (bu - au) * (cv - av) - (bv - av) * (cu - au);
+    if (!(fabsf(area) > 1e-30f)) return false;
+    float ia = 1.0f / area;
+    la = ((bu - pu) * (cv - pv) - (bv - pv) * (cu - pu)) * ia;
+    lb = ((cu - pu) * (av - pv) - (cv - pv) * (au - pu)) * ia;
+    lc = ((au - pu) * (bv - pv) - (av - pv) * (bu - pu)) * ia;
+    return true;
+}
+
+// Coverage tolerance of the barycentric test in FP32: nodes on a shared edge are claimed by
+// both triangles (the smallest-key rule picks one), so no node falls between triangles.
+#define RB_BARY_EPS 1e-5f
+
+__device__ __forceinline__ void raster_tri(const float *tu, const float *tv, const float *tdT,
+                                           int nx, int ny, const int32_t *__restrict__ qmap,
+                                           unsigned long long *__restrict__ keys, uint32_t tid) {
+    float umin = fminf(fminf(tu[0], tu[1]), tu[2]), umax = fmaxf(fmaxf(tu[0], tu[1]), tu[2]);
+    float vmin = fminf(fminf(tv[0], tv[1]), tv[2]), vmax = fmaxf(fmaxf(tv[0], tv[1]), tv[2]);
+    int i0 = max((int)ceilf(umin - 1e-4f), 0), i1 = min((int)floorf(umax + 1e-4f), nx - 1);
+    int j0 = max((int)ceilf(vmin - 1e-4f), 0), j1 = min((int)floorf(vmax + 1e-4f), ny - 1);
+    for (int jj = j0; jj <= j1; ++jj) {
+        for (int ii = i0; ii <= i1; ++ii) {
+            int q = qmap[(size_t)jj * nx + ii];
+            if (q < 0) continue;
+            float la, lb, lc;
+            if (!barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la,
+                             lb, lc))
+                return;
+            if (la < -RB_BARY_EPS || lb < -RB_BARY_EPS || lc < -RB_BARY_EPS) continue;
+            float dT = la * tdT[0] + lb * tdT[1] + lc * tdT[2];
+            unsigned long long key = ((unsigned long long)ordered_bits(dT) << 32) | tid;
+            atomicMin(keys + q, key);
+        }
+    }
+}
+
+// One lane per quad (ray j, j+1; samples i, i+1), i >= 1, i + 1 <= min(M_j, M_j+1).
+__global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                     int nx, int ny, int n_mask,
+                                                     const int32_t *__restrict__ qmap,
+                                                     unsigned long long *__restrict__ keys) {
+    size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int nq = n_rays - 1;
+    size_t total = (size_t)E * S * nq;
+    if (tid >= total) return;
+    int j = (int)(tid % nq);
+    size_t rest = tid / nq;
+    int i = (int)(rest % S);
+    int el = (int)(rest / S);
+    if (i < 1) return;
+    int Mj = sb.M[(size_t)el * n_rays + j], Mj1 = sb.M[(size_t)el * n_rays + j + 1];
+    if (Mj < 0 || Mj1 < 0 || i + 1 > min(Mj, Mj1)) return;
+    size_t b00 = ((size_t)el * S + i) * n_rays + j;
+    size_t b01 = b00 + n_rays;  // (j, i+1)
+    float u00 = sb.u[b00], u10 = sb.u[b00 + 1], u11 = sb.u[b01 + 1], u01 = sb.u[b01];
+    float v00 = sb.v[b00], v10 = sb.v[b00 + 1], v11 = sb.v[b01 + 1], v01 = sb.v[b01];
+    float d00 = sb.dT[b00], d10 = sb.dT[b00 + 1], d11 = sb.dT[b01 + 1], d01 = sb.dT[b01];
+    unsigned long long *ek = keys + (size_t)el * n_mask;
+    uint32_t id0 = (uint32_t)(((size_t)j * S + i) * 2);
+    {
+        float tu[3] = {u00, u10, u11}, tv[3] = {v00, v10, v11}, td[3] = {d00, d10, d11};
+        raster_tri(tu, tv, td, nx, ny, qmap, ek, id0);
+    }
+    {
+        float tu[3] = {u00, u11, u01}, tv[3] = {v00, v11, v01}, td[3] = {d00, d11, d01};
+        raster_tri(tu, tv, td, nx, ny, qmap, ek, id0 + 1);
+    }
+}
+
+__global__ void fill_keys(unsigned long long *keys, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = ~0ull;
+}
+
+// Per (emitter, mask node): interpolate the winning triangle and write the tables.
+__global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                      int e0, GridP g, double R, double psi0,
+                                                      int N, double ds, double c0, int n_mask,
+                                                      const int32_t *__restrict__ mask_index,
+                                                      const unsigned long long *__restrict__ keys,
+                                                      rb_tables tb) {
+    size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (size_t)E * n_mask) return;
+    int el = (int)(tid / n_mask), q = (int)(tid - (size_t)el * n_mask);
+    int e = e0 + el;
+    size_t out = (size_t)e * n_mask + q;
+    unsigned long long key = keys[tid];
+    int p = mask_index[q];
+    int ii = p % g.nx, jj = p / g.nx;
+    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    double xe = R * cos(psi), ye = R * sin(psi);
+    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
+    double d = sqrt((px - xe) * (px - xe) + (py - ye) * (py - ye));
+    if (key == ~0ull || d < 2.0 * ds) {
+        tb.T[out] = 0.0;
+        tb.A[out] = 0.0f;
+        tb.ux[out] = 0.0f;
+        tb.uy[out] = 0.0f;
+        tb.flags[out] = 0;
+        return;
+    }
+    uint32_t tri = (uint32_t)(key & 0xffffffffu);
+    int half = tri & 1;
+    uint32_t rest = tri >> 1;
+    int j = (int)(rest / S), i = (int)(rest % S);
+    size_t b00 = ((size_t)el * S + i) * n_rays + j;
+    size_t b01 = b00 + n_rays;
+    size_t vb[3];
+    vb[0] = b00;
+    vb[1] = half ? b01 + 1 : b00 + 1;
+    vb[2] = half ? b01 : b01 + 1;
+    float tu[3], tv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        tu[k] = sb.u[vb[k]];
+        tv[k] = sb.v[vb[k]];
+    }
+    float la, lb, lc;
+    barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
+    float lam[3] = {la, lb, lc};
+    float dT = 0, L = 0, tx = 0, ty = 0;
+    int K = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dT += lam[k] * sb.dT[vb[k]];
+        L += lam[k] * sb.L[vb[k]];
+        tx += lam[k] * sb.tx[vb[k]];
+        ty += lam[k] * sb.ty[vb[k]];
+        K = max(K, (int)sb.K[vb[k]]);
+    }
+    float tn = sqrtf(tx * tx + ty * ty);
+    tb.T[out] = (double)dT + d / c0;
+    tb.A[out] = expf(L) / (float)sqrt(d);
+    tb.ux[out] = tx / tn;
+    tb.uy[out] = ty / tn;
+    tb.flags[out] = (uint8_t)(0x80 | (K & 3));
+}
+
+// Receiver tables: per emitter, bracket each receiver's angle between neighbouring exit
+// angles and interpolate dT and L linearly; the smallest travel time wins (lowest ray on a
+// tie); unbracketed pairs are invalid.
+__global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays, int e0, double R,
+                                                       double psi0, int N, double c0,
+                                                       rb_tables tb) {
+    extern __shared__ char smem[];
+    double *beta = reinterpret_cast<double *>(smem);
+    float *dTs = reinterpret_cast<float *>(beta + n_rays);
+    float *Ls = dTs + n_rays;
+    int *ok = reinterpret_cast<int *>(Ls + n_rays);
+    uint8_t *Ks = reinterpret_cast<uint8_t *>(ok + n_rays);
+    int el = blockIdx.x, e = e0 + el;
+    for (int j = threadIdx.x; j < n_rays; j += blockDim.x) {
+        size_t x = (size_t)el * n_rays + j;
+        int good = sb.M[x] >= 0;
+        ok[j] = good;
+        beta[j] = good ? sb.ex_beta[x] : 0.0;
+        dTs[j] = good ? sb.ex_dT[x] : 0.0f;
+        Ls[j] = good ? sb.ex_L[x] : 0.0f;
+        Ks[j] = good ? sb.ex_K[x] : 0;
+    }
+    __syncthreads();
+    double psi_e = psi0 + RB_TWO_PI * (double)e / (double)N;
+    double xe = R * cos(psi_e), ye = R * sin(psi_e);
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        size_t out = (size_t)e * N + r;
+        int rel = ((r - e) % N + N) % N;
+        double br = RB_TWO_PI * (double)rel / (double)N;
+        bool found = false;
+        double best = 0.0, bestL = 0.0;
+        int bestK = 0;
+        if (r != e) {
+            for (int j = 0; j + 1 < n_rays; ++j) {
+                if (!(ok[j] && ok[j + 1])) continue;
+                double b0 = beta[j], b1 = beta[j + 1];
+                if (b0 == b1 || br < fmin(b0, b1) || br > fmax(b0, b1)) continue;
+                double lam = (br - b0) / (b1 - b0);
+                double dT = (1.0 - lam) * (double)dTs[j] + lam * (double)dTs[j + 1];
+                if (!found || dT < best) {
+                    found = true;
+                    best = dT;
+                    bestL = (1.0 - lam) * (double)Ls[j] + lam * (double)Ls[j + 1];
+                    bestK = max((int)Ks[j], (int)Ks[j + 1]);
+                }
+            }
+        }
+        if (found) {
+            double psi_r = psi0 + RB_TWO_PI * (double)r / (double)N;
+            double xr = R * cos(psi_r), yr = R * sin(psi_r);
+            double dist = sqrt((xr - xe) * (xr - xe) + (yr - ye) * (yr - ye));
+            tb.rx_T[out] = best + dist / c0;
+            tb.rx_A[out] = (float)(exp(bestL) / sqrt(dist));
+            tb.rx_flags[out] = (uint8_t)(0x80 | (bestK & 3));
+        } else {
+            tb.rx_T[out] = 0.0;
+            tb.rx_A[out] = 0.0f;
+            tb.rx_flags[out] = 0;
+        }
+    }
+}
+
+// n = c0 / c followed by a separable odd box window with replicated edges (FP64 sums).
+__global__ void box_rows(const double *__restrict__ c, double c0, int nx, int ny, int w,
+                         double *__restrict__ tmp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    int h = w / 2;
+    double acc = 0.0;
+    for (int s = -h; s <= h; ++s) {
+        int k = min(max(i + s, 0), nx - 1);
+        acc += c0 / c[(size_t)j * nx + k];
+    }
+    tmp[(size_t)j * nx + i] = acc / w;
+}
+
+__global__ void box_cols(const double *__restrict__ tmp, int nx, int ny, int w,
+                         float *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    int h = w / 2;
+    double acc = 0.0;
+    for (int s = -h; s <= h; ++s) {
+        int k = min(max(j + s, 0), ny - 1);
+        acc += tmp[(size_t)k * nx + i];
+    }
+    out[(size_t)j * nx + i] = (float)(acc / w);
+}
+
+}  // namespace
+
+rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
+                                     int w, float *n_s) {
+    ctx->ws.used = 0;
+    size_t P = (size_t)g->nx * g->ny;
+    rb_status st = rb_arena_reserve(ctx, &ctx->ws, rb_align(P * sizeof(double)));
+    if (st != RB_OK) return st;
+    double *tmp = rb_carve<double>(&ctx->ws, P);
+    dim3 blk(256), grd((g->nx + 255) / 256, g->ny);
+    hipLaunchKernelGGL(box_rows, grd, blk, 0, ctx->stream, c, c0, g->nx, g->ny, w, tmp);
+    RB_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(box_cols, grd, blk, 0, ctx->stream, tmp, g->nx, g->ny, w, n_s);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+// Emitters per chunk so that the ray samples of one chunk stay below ~6 GiB.
+static int trace_chunk(const rb_ring *r, const rb_trace_params *tp, int64_t n_mask) {
+    size_t S = (size_t)tp->max_steps + 1;
+    size_t per = S * tp->n_rays * (6 * sizeof(float) + 1) + (size_t)n_mask * 8 +
+                 (size_t)tp->n_rays * 32;
+    size_t budget = (size_t)6 << 30;
+    size_t c = budget / per;
+    if (c < 1) c = 1;
+    if (c > (size_t)r->n) c = r->n;
+    return (int)c;
+}
+
+rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
+                          const rb_trace_params *tp, const float *n_s, const rb_tables *out) {
+    const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
+    const int n_mask = (int)ctx->n_mask;
+    const int C = trace_chunk(r, tp, n_mask);
+    size_t plane = (size_t)C * S * nr;
+    size_t bytes = 6 * rb_align(plane * sizeof(float)) + rb_align(plane) +
+                   rb_align((size_t)C * nr * sizeof(int32_t)) +
+                   rb_align((size_t)C * nr * sizeof(double)) +
+                   2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
+                   rb_align((size_t)C * n_mask * sizeof(unsigned long long));
+    ctx->ws.used = 0;
+    rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
+    if (st != RB_OK) return st;
+    SampleBufs sb;
+    sb.u = rb_carve<float>(&ctx->ws, plane);
+    sb.v = rb_carve<float>(&ctx->ws, plane);
+    sb.dT = rb_carve<float>(&ctx->ws, plane);
+    sb.L = rb_carve<float>(&ctx->ws, plane);
+    sb.tx = rb_carve<float>(&ctx->ws, plane);
+    sb.ty = rb_carve<float>(&ctx->ws, plane);
+    sb.K = rb_carve<uint8_t>(&ctx->ws, plane);
+    sb.M = rb_carve<int32_t>(&ctx->ws, (size_t)C * nr);
+    sb.ex_beta = rb_carve<double>(&ctx->ws, (size_t)C * nr);
+    sb.ex_dT = rb_carve<float>(&ctx->ws, (size_t)C * nr);
+    sb.ex_L = rb_carve<float>(&ctx->ws, (size_t)C * nr);
+    sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
+    unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
+
+    GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0};
+    RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
+    for (int e0 = 0; e0 < N; e0 += C) {
+        int E = std::min(C, N - e0);
+        int nthreads = E * nr;
+        hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
+                           n_s, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0, e0,
+                           E, sb, ctx->d_flag);
+        RB_CHECK_LAUNCH(ctx);
+        size_t nk = (size_t)E * n_mask;
+        hipLaunchKernelGGL(fill_keys, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
+                           ctx->stream, keys, nk);
+        RB_CHECK_LAUNCH(ctx);
+        size_t nquad = (size_t)E * S * (nr - 1);
+        if (nr > 1) {
+            hipLaunchKernelGGL(raster_kernel, dim3((unsigned)((nquad + 255) / 256)), dim3(256), 0,
+                               ctx->stream, sb, nr, S, E, g->nx, g->ny, n_mask, ctx->d_qmap,
+                               keys);
+            RB_CHECK_LAUNCH(ctx);
+        }
+        hipLaunchKernelGGL(resolve_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
+                           ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
+                           tp->c0, n_mask, ctx->d_mask_index, keys, *out);
+        RB_CHECK_LAUNCH(ctx);
+        size_t smem = (size_t)nr * (sizeof(double) + 2 * sizeof(float) + sizeof(int) + 1);
+        hipLaunchKernelGGL(receiver_kernel, dim3(E), dim3(256), smem, ctx->stream, sb, nr, e0,
+                           r->radius, r->psi0, N, tp->c0, *out);
+        RB_CHECK_LAUNCH(ctx);
+    }
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*ctx->h_flag & 1)
+        return rb_fail(ctx, RB_ENONFINITE, "a ray did not reach the ring within max_steps=%d",
+                       tp->max_steps);
+    return RB_OK;
+}

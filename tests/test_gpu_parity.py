@@ -1,0 +1,270 @@
+"""GPU-vs-oracle parity of every C-ABI entry point (HIP path on cuda:0, FP64 oracle on the
+host, same seeded inputs). Tolerances (relative L2 over valid entries) follow the FP32 form:
+travel time <= 1e-5, Green's functions, data and gradients <= 1e-4."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import born, green, step as ostep
+from tests.gpu_cases import (C0, abi_structs, case, ns_of, oracle_tables, rel_l2,
+                             tables_to_gpu, to_np)
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["small", "ragged", "ring64"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2211_00316_amd import _lib
+
+    return _lib.Context("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("window", [1, 5])
+def test_refractive_index(ctx, name, window):
+    import torch
+
+    st, c = case(name)
+    grid, ring, tp = abi_structs(st)
+    _say(f"refractive_index {name} w={window}")
+    ns = ctx.refractive_index(grid, torch.as_tensor(c, device="cuda:0"), C0, window)
+    ref = ns_of(c, window)
+    assert np.max(np.abs(to_np(ns) - ref)) < 2e-7
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_trace_rays_tables(ctx, name):
+    import torch
+
+    st, c = case(name)
+    grid, ring, tp = abi_structs(st)
+    tb_o, ns = oracle_tables(name)
+    _say(f"trace_rays {name} N={st.ring.n} rays={st.n_rays} grid={st.grid.nx}")
+    ns_g = torch.as_tensor(ns.astype(np.float32), device="cuda:0")
+    tb = ctx.trace_rays(grid, ring, tp, ns_g)
+    torch.cuda.synchronize()
+    flags = to_np(tb.flags)
+    valid = (flags & 0x80) != 0
+    # the valid set is decided by geometry (coverage, 2 ds exclusion) on both sides
+    mism = np.count_nonzero(valid != tb_o.valid)
+    assert mism <= 1e-4 * valid.size, mism
+    both = valid & tb_o.valid
+    assert rel_l2(to_np(tb.T)[both], tb_o.T[both]) <= 1e-5
+    assert rel_l2(to_np(tb.A)[both], tb_o.A[both]) <= 1e-4
+    assert np.max(np.abs(to_np(tb.ux)[both] - tb_o.ux[both])) < 1e-4
+    assert np.max(np.abs(to_np(tb.uy)[both] - tb_o.uy[both])) < 1e-4
+    assert np.array_equal(flags[both] & 3, tb_o.K[both] & 3)
+    rv = (to_np(tb.rx_flags) & 0x80) != 0
+    assert np.array_equal(rv, tb_o.rx_valid)
+    assert rel_l2(to_np(tb.rx_T)[rv], tb_o.rx_T[rv]) <= 1e-5
+    assert rel_l2(to_np(tb.rx_A)[rv], tb_o.rx_A[rv]) <= 1e-4
+
+
+def test_trace_rays_is_deterministic(ctx):
+    import torch
+
+    st, c = case("small")
+    grid, ring, tp = abi_structs(st)
+    ns = torch.as_tensor(oracle_tables("small")[1].astype(np.float32), device="cuda:0")
+    a = ctx.trace_rays(grid, ring, tp, ns)
+    b = ctx.trace_rays(grid, ring, tp, ns)
+    torch.cuda.synchronize()
+    for x, y in zip((a.T, a.A, a.ux, a.flags, a.rx_T), (b.T, b.A, b.ux, b.flags, b.rx_T)):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("f", [150e3, 800e3])
+def test_build_green(ctx, name, f):
+    st, c = case(name)
+    tb_o, _ = oracle_tables(name)
+    om = 2 * math.pi * f
+    _say(f"build_green {name} f={f}")
+    gr = ctx.build_green(tables_to_gpu(tb_o), om, C0)
+    G, H, Hx, Hy = green.build_green(tb_o, om)
+    assert rel_l2(to_np(gr.G), G) <= 1e-4
+    assert rel_l2(to_np(gr.H[0]), H) <= 1e-4
+    assert rel_l2(to_np(gr.H[1]), Hx) <= 1e-4
+    assert rel_l2(to_np(gr.H[2]), Hy) <= 1e-4
+    assert np.all(to_np(gr.G)[~tb_o.valid] == 0)
+
+
+def _green_gpu(ctx, name, om):
+    tb_o, _ = oracle_tables(name)
+    G, H, Hx, Hy = green.build_green(tb_o, om)
+    import torch
+    from paper_2211_00316_amd import _lib
+
+    gr = _lib.Green(torch.as_tensor(G.astype(np.complex64), device="cuda:0"),
+                    torch.as_tensor(np.stack([H, Hx, Hy]).astype(np.complex64), device="cuda:0"))
+    return tb_o, (G, H, Hx, Hy), gr
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_born_forward(ctx, name):
+    import torch
+
+    st, c = case(name)
+    om = 2 * math.pi * 300e3
+    tb_o, (G, H, Hx, Hy), gr = _green_gpu(ctx, name, om)
+    q = st.grid.mask_index()
+    w = np.full(q.size, om ** 2 * st.grid.dx ** 2)
+    delta = (1.0 / c.ravel()[q] ** 2 - 1.0 / C0 ** 2)
+    _say(f"born_forward {name} N={st.ring.n} P_m={q.size}")
+    d = ctx.born_forward(gr, torch.as_tensor(w.astype(np.complex64), device="cuda:0"),
+                         torch.as_tensor(delta.astype(np.float32), device="cuda:0"))
+    ref = born.forward(G, w, delta)
+    assert rel_l2(to_np(d), ref) <= 1e-4
+    dd = to_np(d)
+    assert np.array_equal(dd, dd.T)  # reciprocity, exact by construction
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_born_adjoint_and_dot_product(ctx, name):
+    import torch
+
+    st, c = case(name)
+    om = 2 * math.pi * 400e3
+    tb_o, (G, H, Hx, Hy), gr = _green_gpu(ctx, name, om)
+    N, P = G.shape
+    rng = np.random.default_rng(5)
+    R = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).astype(np.complex64)
+    w = (om ** 2 * st.grid.dx ** 2) * np.exp(1j * rng.uniform(0, 0.3, P))
+    _say(f"born_adjoint {name}")
+    w_g = torch.as_tensor(w.astype(np.complex64), device="cuda:0")
+    g = to_np(ctx.born_adjoint(gr, w_g, torch.as_tensor(R, device="cuda:0")))
+    ref = born.adjoint(G, w.astype(np.complex64).astype(np.complex128), R.astype(np.complex128))
+    assert rel_l2(g, ref) <= 1e-4
+    # dot-product test on the GPU operators: <F delta, R> = <delta, F^H R>
+    delta = rng.standard_normal(P).astype(np.float32)
+    d = to_np(ctx.born_forward(gr, w_g, torch.as_tensor(delta, device="cuda:0")))
+    lhs = np.real(np.vdot(d.astype(np.complex128), R.astype(np.complex128)))
+    rhs = float(np.dot(delta.astype(np.float64), g.astype(np.float64)))
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_backproject(ctx, name):
+    import torch
+
+    st, c = case(name)
+    om = 2 * math.pi * 350e3
+    tb_o, (G, H, Hx, Hy), gr = _green_gpu(ctx, name, om)
+    N, P = G.shape
+    rng = np.random.default_rng(9)
+    R = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).astype(np.complex64)
+    cq = c.ravel()[st.grid.mask_index()]
+    _say(f"backproject {name}")
+    dm = to_np(ctx.backproject(gr, torch.as_tensor(R, device="cuda:0"),
+                               torch.as_tensor(cq, device="cuda:0"), om, 0.5 * om))
+    S = born.backproject_weight(om, 0.5 * om, cq)
+    ref = born.backproject(R.astype(np.complex128), H, Hx, Hy, S)
+    assert rel_l2(dm, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_residual(ctx, name):
+    import torch
+
+    st, c = case(name)
+    tb_o, _ = oracle_tables(name)
+    N = st.ring.n
+    om = 2 * math.pi * 600e3
+    rng = np.random.default_rng(3)
+    data = (1e-2 * (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))))
+    dborn = (1e-3 * (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))))
+    data = data.astype(np.complex64)
+    dborn = dborn.astype(np.complex64)
+    _say(f"residual {name}")
+    R = to_np(ctx.residual(tables_to_gpu(tb_o), om, C0, torch.as_tensor(data, device="cuda:0"),
+                           torch.as_tensor(dborn, device="cuda:0")))
+    g = green.direct_data(tb_o, om)
+    ref = ostep.residual(g + dborn, data, tb_o.rx_valid)
+    assert rel_l2(R, ref) <= 1e-5
+    assert np.all(R[~(tb_o.rx_valid & ~np.eye(N, dtype=bool))] == 0)
+
+
+@pytest.mark.parametrize("name,window,mode", [("small", 1, 0), ("ring64", 1, 0),
+                                              ("ragged", 5, 0), ("ragged", 5, 1)])
+def test_frequency_step(ctx, name, window, mode):
+    import torch
+    import phantoms as ph
+
+    st, c_true = case(name)
+    N = st.ring.n
+    freqs = [250e3] if name != "ragged" else [200e3, 260e3]
+    om = [2 * math.pi * f for f in freqs]
+    dom = [om[0]] if len(om) == 1 else [om[1] - om[0]] * len(om)
+    noise = ph.complex_noise((len(om), N, N), 2)
+    data = ostep.synthesize(c_true, st, om, noise, background="water")
+    c0 = np.full_like(c_true, C0)
+    oracle_mode = "ray_born" if mode == 0 else "ray_only"
+    c_ref, parts = ostep.frequency_step(c0, st, om, dom, data, 0.12, window=window,
+                                        mode=oracle_mode, return_parts=True)
+    grid, ring, tp = abi_structs(st)
+    _say(f"frequency_step {name} w={window} mode={mode}")
+    c_g = torch.as_tensor(c0.copy(), device="cuda:0")
+    rn = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ctx.frequency_step(grid, ring, tp, c_g, window, om, dom,
+                       torch.as_tensor(data.astype(np.complex64), device="cuda:0"), 0.12,
+                       mode=mode, residual_norm=rn)
+    c_new = to_np(c_g)
+    q = st.grid.mask_index()
+    dc_ref = (c_ref - c0).ravel()[q]
+    dc = (c_new - c0).ravel()[q]
+    assert rel_l2(dc, dc_ref) <= 1e-4, rel_l2(dc, dc_ref)
+    outside = np.setdiff1d(np.arange(c0.size), q)
+    assert np.all(c_new.ravel()[outside] == C0)
+    rn_ref = sum(float(np.sum(np.abs(p["R"]) ** 2)) for p in parts["freqs"])
+    assert abs(float(to_np(rn)[0]) - rn_ref) <= 1e-4 * rn_ref
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    import torch
+    from paper_2211_00316_amd import _lib
+
+    st, c = case("small")
+    grid, ring, tp = abi_structs(st)
+    ns = torch.ones(st.grid.ny, st.grid.nx, dtype=torch.float32, device="cuda:0")
+    bad = _lib.TraceParams(1, tp.max_steps, tp.ds, tp.c0)
+    with pytest.raises(_lib.RayBornError) as e:
+        ctx.trace_rays(grid, ring, bad, ns)
+    assert e.value.status == _lib.RB_EINVAL
+    big_ring = _lib.Ring(ring.n, 1.0, 0.0)
+    with pytest.raises(_lib.RayBornError):
+        ctx.trace_rays(grid, big_ring, tp, ns)
+    with pytest.raises(_lib.RayBornError):
+        ctx.refractive_index(grid, torch.as_tensor(c, device="cuda:0"), C0, 4)
+    short = _lib.TraceParams(tp.n_rays, 10, tp.ds, tp.c0)
+    with pytest.raises(_lib.RayBornError) as e:
+        ctx.trace_rays(grid, ring, short, ns)
+    assert e.value.status == _lib.RB_ENONFINITE
+
+
+def test_nonfinite_update_leaves_model_unchanged(ctx):
+    import torch
+
+    st, c = case("small")
+    N = st.ring.n
+    grid, ring, tp = abi_structs(st)
+    data = np.full((1, N, N), np.nan, dtype=np.complex64)
+    c_g = torch.as_tensor(c.copy(), device="cuda:0")
+    from paper_2211_00316_amd import _lib
+
+    with pytest.raises(_lib.RayBornError) as e:
+        ctx.frequency_step(grid, ring, tp, c_g, 1, [2 * math.pi * 2e5], [2 * math.pi * 2e5],
+                           torch.as_tensor(data, device="cuda:0"), 0.12)
+    assert e.value.status == _lib.RB_ENONFINITE
+    assert np.array_equal(to_np(c_g), c)
