@@ -22,8 +22,10 @@
  *     library never frees it. Complex numbers are interleaved (re, im) float pairs.
  *   - Calls are asynchronous on the context's stream; outputs are ready when that stream is.
  *   - Every entry point validates its arguments before launching anything and returns an
- *     rb_status; on error nothing was launched (outputs unchanged) and rb_last_error()
- *     describes the problem. RB_EDEVICE reports a failed HIP call.
+ *     rb_status; on RB_EINVAL / RB_EUNSUPPORTED nothing was launched (outputs unchanged).
+ *     RB_ENONFINITE is reported after the kernels ran (outputs unspecified, except that
+ *     rb_frequency_step then leaves the model unchanged); RB_EDEVICE reports a failed HIP
+ *     call. rb_last_error() describes the problem.
  *   - A context may be used from one host thread at a time.
  */
 #ifndef RAYBORNHF_H
@@ -179,6 +181,16 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             int32_t n_omega, const double *omega, const double *d_omega,
                             const float *data, double tau, rb_mode mode,
                             double *residual_norm);
+
+/* Measurement: per-stage GPU time from HIP events recorded around every kernel launch on
+ * the context's stream while profiling is on (small overhead; off by default). Stages are
+ * numbered 0 .. RB_N_STAGES-1 (rb_stage_name). rb_profile_read synchronizes the stream,
+ * writes for each stage the summed kernel time in milliseconds and the launch count, and
+ * clears the record. */
+#define RB_N_STAGES 12
+rb_status rb_profile_enable(rb_ctx *ctx, int32_t on);
+rb_status rb_profile_read(rb_ctx *ctx, double *total_ms, int64_t *launches);
+const char *rb_stage_name(int32_t stage);
 
 #ifdef __cplusplus
 }

@@ -22,8 +22,10 @@ RB_RAY_BORN, RB_RAY_ONLY = 0, 1
 SYMBOLS = (
     "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
-    "rb_backproject", "rb_frequency_step",
+    "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
+    "rb_stage_name",
 )
+N_STAGES = 12
 
 
 class Ring(ctypes.Structure):
@@ -89,6 +91,9 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(TraceParams), P, I32, I32,
                                ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int, P],
                               ctypes.c_int),
+        "rb_profile_enable": ([P, I32], ctypes.c_int),
+        "rb_profile_read": ([P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "rb_stage_name": ([I32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -191,6 +196,17 @@ class Context:
     def _check(self, st):
         if st != RB_OK:
             raise RayBornError(st, self.lib.rb_last_error(self._h).decode())
+
+    # measurement ------------------------------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._check(self.lib.rb_profile_enable(self._h, int(on)))
+
+    def profile_read(self):
+        """{stage name: (total ms, launches)} since the last read (synchronizes)."""
+        ms = (ctypes.c_double * N_STAGES)()
+        cnt = (ctypes.c_int64 * N_STAGES)()
+        self._check(self.lib.rb_profile_read(self._h, ms, cnt))
+        return {self.lib.rb_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(N_STAGES)}
 
     # entry points (same names as the C ABI) ---------------------------------------------
     def refractive_index(self, grid: Grid, c: torch.Tensor, c0: float, w: int) -> torch.Tensor:

@@ -28,6 +28,27 @@ rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...) {
     return st;
 }
 
+void rb_prof_begin(rb_ctx *ctx, int stage) {
+    if (!ctx->prof || ctx->n_ev >= rb_ctx::kMaxEv) return;
+    int i = ctx->n_ev;
+    if (i >= ctx->n_ev_created) {
+        if (hipEventCreate(&ctx->ev[i][0]) != hipSuccess ||
+            hipEventCreate(&ctx->ev[i][1]) != hipSuccess) {
+            ctx->prof = false;
+            return;
+        }
+        ctx->n_ev_created = i + 1;
+    }
+    ctx->ev_stage[i] = stage;
+    (void)hipEventRecord(ctx->ev[i][0], ctx->stream);
+}
+
+void rb_prof_end(rb_ctx *ctx) {
+    if (!ctx->prof || ctx->n_ev >= rb_ctx::kMaxEv) return;
+    (void)hipEventRecord(ctx->ev[ctx->n_ev][1], ctx->stream);
+    ctx->n_ev++;
+}
+
 rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes) {
     if (bytes <= a->cap) return RB_OK;
     if (a->base) {
@@ -186,10 +207,46 @@ void rb_destroy(rb_ctx *ctx) {
     if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
+    for (int i = 0; i < ctx->n_ev_created; ++i) {
+        (void)hipEventDestroy(ctx->ev[i][0]);
+        (void)hipEventDestroy(ctx->ev[i][1]);
+    }
     delete ctx;
 }
 
 const char *rb_last_error(const rb_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+rb_status rb_profile_enable(rb_ctx *ctx, int32_t on) {
+    if (!ctx) return RB_EINVAL;
+    ctx->prof = on != 0;
+    ctx->n_ev = 0;
+    return RB_OK;
+}
+
+rb_status rb_profile_read(rb_ctx *ctx, double *total_ms, int64_t *launches) {
+    if (!ctx || !total_ms || !launches) return RB_EINVAL;
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < RB_N_STAGES; ++s) {
+        total_ms[s] = 0.0;
+        launches[s] = 0;
+    }
+    for (int i = 0; i < ctx->n_ev; ++i) {
+        float ms = 0.f;
+        RB_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[i][0], ctx->ev[i][1]));
+        total_ms[ctx->ev_stage[i]] += ms;
+        launches[ctx->ev_stage[i]] += 1;
+    }
+    ctx->n_ev = 0;
+    return RB_OK;
+}
+
+const char *rb_stage_name(int32_t stage) {
+    static const char *names[RB_N_STAGES] = {
+        "smooth", "trace", "raster", "resolve", "receivers", "build_green", "forward_gemm",
+        "forward_reduce", "residual", "backproject_gemm", "finish", "update"};
+    return (stage >= 0 && stage < RB_N_STAGES) ? names[stage] : "unknown";
+}
 
 int64_t rb_mask_count(const rb_grid *grid) {
     if (!grid || grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0)) return -1;

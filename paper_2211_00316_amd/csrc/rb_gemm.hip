@@ -282,12 +282,13 @@ __global__ void __launch_bounds__(256) forward_kernel(const float2 *__restrict__
         }
 }
 
-// d[e][r] = sum over splits of the partial at (e, r) if tile(e) <= tile(r), else at (r, e).
+// d[e][r] = d[r][e] = sum over splits of the partial at (min(e,r), max(e,r)), which lies in
+// a computed upper tile; both entries come from the same sums, so d is exactly symmetric.
 __global__ void forward_reduce(const float2 *__restrict__ dpart, int n, int splitk,
                                float2 *__restrict__ d) {
     int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
     if (r >= n) return;
-    size_t src = (e / FW_B <= r / FW_B) ? (size_t)e * n + r : (size_t)r * n + e;
+    size_t src = (e <= r) ? (size_t)e * n + r : (size_t)r * n + e;
     float sr = 0.f, si = 0.f;
     for (int s = 0; s < splitk; ++s) {
         float2 v = dpart[(size_t)s * n * n + src];
@@ -307,10 +308,12 @@ rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const
     int nblocks = (n_mask + RR_BN - 1) / RR_BN;
     int total = mblocks * nblocks;
     int grid = ((total + 7) / 8) * 8;
+    rb_prof_begin(ctx, ST_BACKPROJECT);
     hipLaunchKernelGGL(rowred_kernel, dim3(grid), dim3(256), 0, ctx->stream,
                        (const float2 *)R, (const float2 *)B, n, n_mask, n_comp, conj_b, mblocks,
                        nblocks, parts);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     if (mblocks_out) *mblocks_out = mblocks;
     return RB_OK;
 }
@@ -330,11 +333,15 @@ rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, con
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
     if (st != RB_OK) return st;
     float2 *dpart = rb_carve<float2>(&ctx->ws, (size_t)splitk * n * n);
+    rb_prof_begin(ctx, ST_FORWARD);
     hipLaunchKernelGGL(forward_kernel, dim3(tiles, splitk), dim3(256), 0, ctx->stream,
                        (const float2 *)gr->G, (const float2 *)w, delta, n, K, T, kchunk, dpart);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    rb_prof_begin(ctx, ST_FORWARD_REDUCE);
     hipLaunchKernelGGL(forward_reduce, dim3((n + 255) / 256, n), dim3(256), 0, ctx->stream, dpart,
                        n, splitk, (float2 *)d);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }

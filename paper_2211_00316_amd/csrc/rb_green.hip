@@ -183,9 +183,11 @@ inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                           const rb_green *out) {
     dim3 grd(blocks(tb->n_mask), tb->n);
+    rb_prof_begin(ctx, ST_GREEN);
     hipLaunchKernelGGL(green_kernel, grd, dim3(256), 0, ctx->stream, *tb, tb->n, tb->n_mask, omega,
                        c0, (float2 *)out->G, (float2 *)out->H);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
@@ -193,28 +195,34 @@ rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, dou
                              const float *d_born, const float *data, float *R,
                              double *residual_norm) {
     dim3 grd(blocks(tb->n), tb->n);
+    rb_prof_begin(ctx, ST_RESIDUAL);
     hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, ctx->stream, tb->rx_T, tb->rx_A,
                        tb->rx_flags, tb->n, omega, c0, (const float2 *)d_born,
                        (const float2 *)data, (float2 *)R, residual_norm);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
 rb_status rb_launch_adjoint_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
                                    const float *w, float *grad) {
+    rb_prof_begin(ctx, ST_FINISH);
     hipLaunchKernelGGL(adjoint_finish_kernel, dim3(blocks(n_mask)), dim3(256), 0, ctx->stream,
                        n_mask, mblocks, parts, (const float2 *)w, grad);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
 rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
                                        const double *c_mask, double omega, double d_omega,
                                        float *dm, int accumulate) {
+    rb_prof_begin(ctx, ST_FINISH);
     hipLaunchKernelGGL(backproject_finish_kernel<float>, dim3(blocks(n_mask)), dim3(256), 0,
                        ctx->stream, n_mask, mblocks, parts, c_mask, omega, d_omega, dm,
                        accumulate);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
@@ -240,9 +248,11 @@ rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float
                                            const double *c_mask, double omega, double d_omega,
                                            double *dm_acc) {
     int n = (int)ctx->n_mask;
+    rb_prof_begin(ctx, ST_FINISH);
     hipLaunchKernelGGL(backproject_finish_kernel<double>, dim3(blocks(n)), dim3(256), 0,
                        ctx->stream, n, mblocks, parts, c_mask, omega, d_omega, dm_acc, 1);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
@@ -255,9 +265,11 @@ rb_status rb_launch_zero_f64(rb_ctx *ctx, double *x, int n) {
 rb_status rb_launch_update(rb_ctx *ctx, const double *cq, const double *dm, double tau,
                            double *c_new) {
     int n = (int)ctx->n_mask;
+    rb_prof_begin(ctx, ST_UPDATE);
     hipLaunchKernelGGL(update_kernel, dim3(blocks(n)), dim3(256), 0, ctx->stream, cq, dm, n, tau,
                        c_new, ctx->d_flag);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 

@@ -32,11 +32,27 @@ struct rb_ctx {
     int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
     int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
 
+    // per-stage event timing (rb_profile_enable / rb_profile_read)
+    bool prof = false;
+    static constexpr int kMaxEv = 8192;
+    hipEvent_t ev[kMaxEv][2] = {};
+    int ev_stage[kMaxEv] = {0};
+    int n_ev = 0, n_ev_created = 0;
+
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
     int32_t *d_flag = nullptr;        // device error flags (ray overflow, non-finite update)
     int32_t *h_flag = nullptr;        // pinned host mirror
 };
+
+// Stages timed by the profiler (order = rb_stage_name).
+enum rb_stage {
+    ST_SMOOTH = 0, ST_TRACE, ST_RASTER, ST_RESOLVE, ST_RECEIVERS, ST_GREEN, ST_FORWARD,
+    ST_FORWARD_REDUCE, ST_RESIDUAL, ST_BACKPROJECT, ST_FINISH, ST_UPDATE
+};
+// Record the start / end event of a launch of `stage` (no-ops unless profiling is on).
+void rb_prof_begin(rb_ctx *ctx, int stage);
+void rb_prof_end(rb_ctx *ctx);
 
 // Error reporting -------------------------------------------------------------------------
 rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...);

@@ -493,10 +493,12 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
     if (st != RB_OK) return st;
     double *tmp = rb_carve<double>(&ctx->ws, P);
     dim3 blk(256), grd((g->nx + 255) / 256, g->ny);
+    rb_prof_begin(ctx, ST_SMOOTH);
     hipLaunchKernelGGL(box_rows, grd, blk, 0, ctx->stream, c, c0, g->nx, g->ny, w, tmp);
     RB_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(box_cols, grd, blk, 0, ctx->stream, tmp, g->nx, g->ny, w, n_s);
     RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
@@ -546,10 +548,13 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
         int nthreads = E * nr;
+        rb_prof_begin(ctx, ST_TRACE);
         hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
                            n_s, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0, e0,
                            E, sb, ctx->d_flag);
         RB_CHECK_LAUNCH(ctx);
+        rb_prof_end(ctx);
+        rb_prof_begin(ctx, ST_RASTER);
         size_t nk = (size_t)E * n_mask;
         hipLaunchKernelGGL(fill_keys, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
                            ctx->stream, keys, nk);
@@ -561,14 +566,19 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                                keys);
             RB_CHECK_LAUNCH(ctx);
         }
+        rb_prof_end(ctx);
+        rb_prof_begin(ctx, ST_RESOLVE);
         hipLaunchKernelGGL(resolve_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
                            tp->c0, n_mask, ctx->d_mask_index, keys, *out);
         RB_CHECK_LAUNCH(ctx);
+        rb_prof_end(ctx);
+        rb_prof_begin(ctx, ST_RECEIVERS);
         size_t smem = (size_t)nr * (sizeof(double) + 2 * sizeof(float) + sizeof(int) + 1);
         hipLaunchKernelGGL(receiver_kernel, dim3(E), dim3(256), smem, ctx->stream, sb, nr, e0,
                            r->radius, r->psi0, N, tp->c0, *out);
         RB_CHECK_LAUNCH(ctx);
+        rb_prof_end(ctx);
     }
     RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
