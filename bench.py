@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark: Hessian-free ray-Born frequency-step updates per second on one MI355X.
+
+Workload (default): ring of 1024 transducers (R = 110 mm), 1024^2 grid at 0.22 mm, breast-like
+phantom with 10 lesions, 1024 rays per transducer, frequencies 0.1-1.2 MHz (32, one per
+step, low to high). A step is one pass of the whole hot path for one frequency: smoothing,
+ray tracing + binning, Green's-function assembly, Born forward term, residual, Hessian-free
+back-projection and model update (rb_frequency_step). Inputs are resident on the GPU before
+the timed region; the synthetic data are made once, untimed, by the same library (ray-Born
+prediction of the phantom plus 1 % complex Gaussian noise).
+
+Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix
+HBM_PEAK_GBS = 8000.0
+
+
+def synthesize_data(ctx, w, grid, ring, tp, c_true, freq_idx):
+    """Measured data of the listed frequencies, made on the GPU by the library itself:
+    ray-Born prediction of the phantom (window of that frequency) plus 1 % noise."""
+    import numpy as np
+    import torch
+
+    import phantoms as ph
+    from paper_2211_00316_amd import _lib
+
+    N = w.n_trans
+    c_t = torch.as_tensor(c_true, device="cuda:0")
+    out = torch.empty(len(freq_idx), N, N, dtype=torch.complex64, device="cuda:0")
+    zero = torch.zeros(N, N, dtype=torch.complex64, device="cuda:0")
+    mask = _mask_index(w)
+    for s, k in enumerate(freq_idx):
+        om = 2 * math.pi * w.freqs[k]
+        ns = ctx.refractive_index(grid, c_t, 1500.0, w.smooth_window(k))
+        tb = ctx.trace_rays(grid, ring, tp, ns)
+        gr = ctx.build_green(tb, om, 1500.0)
+        cm = c_t.reshape(-1)[mask]
+        delta = (1.0 / cm ** 2 - (ns.reshape(-1)[mask].double() / 1500.0) ** 2).float()
+        wv = torch.full((mask.numel(),), om * om * w.dx * w.dx, dtype=torch.complex64,
+                        device="cuda:0")
+        d = ctx.born_forward(gr, wv, delta)
+        clean = ctx.residual(tb, om, 1500.0, zero, d)     # g_ray + Born term - 0
+        keep = (clean != 0)
+        rms = torch.sqrt(torch.mean(torch.abs(clean[keep]) ** 2)).item()
+        noise = torch.as_tensor(ph.complex_noise((N, N), w.noise_seed + k).astype(np.complex64),
+                                device="cuda:0")
+        out[s] = clean + 0.01 * rms * noise
+        del tb, gr, d, ns
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _mask_index(w):
+    import numpy as np
+    import torch
+
+    xs = w.x0 + w.dx * np.arange(w.nx)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    idx = np.flatnonzero((X * X + Y * Y <= w.mask_radius ** 2).ravel())
+    return torch.as_tensor(idx, device="cuda:0")
+
+
+def cpu_baseline(w):
+    """The FP64 oracle timed on the host on a bounded sample of the same workload: the full
+    trace + binning + receiver tables of one transducer (scaled by N), its Green's
+    functions, and the Born forward / back-projection products on a block of mask columns
+    (scaled by P_m / block); extrapolated to one frequency step."""
+    import numpy as np
+
+    import phantoms as ph
+    from oracle import born, green, step as ostep
+    from oracle.medium import Grid, Ring
+
+    grid = Grid(w.nx, w.ny, w.dx, w.x0, w.y0, w.mask_radius)
+    st = ostep.StepSetup(grid, Ring(w.n_trans, w.radius), w.n_rays, w.ds, w.max_steps())
+    c = ph.phantom_for(w)
+    N = w.n_trans
+    Pm = grid.mask_index().size
+    om = 2 * math.pi * w.freqs[0]
+    t0 = time.perf_counter()
+    sample = [k * N // 8 for k in range(8)]
+    tb, ns = ostep.tables_for(c, st, w.smooth_window(0), emitters=sample)
+    t_tab = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    green.build_green(tb, om)
+    t_green = time.perf_counter() - t0
+    block = 32768
+    rng = np.random.default_rng(0)
+    G = rng.standard_normal((N, block)) + 1j * rng.standard_normal((N, block))
+    H = [rng.standard_normal((N, block)) + 1j * rng.standard_normal((N, block)) for _ in range(3)]
+    R = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    t0 = time.perf_counter()
+    born.forward(G, np.ones(block), rng.standard_normal(block))
+    born.backproject(R, H[0], H[1], H[2], np.ones(block))
+    t_gemm = time.perf_counter() - t0
+    t_step = (t_tab + t_green) * N / len(sample) + t_gemm * Pm / block
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    return {
+        "value": 1.0 / t_step,
+        "unit": "frequency-step updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: trace+bin+receivers and Green's functions of "
+                   f"{len(sample)} of {N} transducers ({t_tab + t_green:.1f} s, "
+                   f"x{N / len(sample):.0f}) plus Born forward and "
+                   f"back-projection on {block} of {Pm} mask columns ({t_gemm:.1f} s, "
+                   f"x{Pm / block:.1f}); extrapolated step {t_step:.0f} s; trace/bin "
+                   f"single-threaded NumPy, products on {threads} BLAS threads"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ring1024_grid1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the frequency step on a single "
+              "MI355X (see the sharding design); --gpus above 1 is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import phantoms as ph
+    from paper_2211_00316_amd import _lib, setup_for
+
+    w = ph.WORKLOADS[args.workload]
+    grid, ring, tp = setup_for(w)
+    ctx = _lib.Context("cuda:0")
+    c_true = ph.phantom_for(w)
+    n_total = args.warmup + args.steps
+    if n_total > len(w.freqs):
+        raise SystemExit(f"at most {len(w.freqs)} steps (one per frequency)")
+    print(f"[bench] {w.name}: synthesizing data for {n_total} frequencies", file=sys.stderr,
+          flush=True)
+    data = synthesize_data(ctx, w, grid, ring, tp, c_true, list(range(n_total)))
+    d_om = 2 * math.pi * (w.freqs[1] - w.freqs[0]) if len(w.freqs) > 1 else None
+    c = torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
+    rn = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+
+    def one_step(k):
+        om = 2 * math.pi * w.freqs[k]
+        ctx.frequency_step(grid, ring, tp, c, w.smooth_window(k), [om], [d_om or om],
+                           data[k], w.tau, residual_norm=rn)
+
+    for k in range(args.warmup):
+        one_step(k)
+        print(f"[bench] warmup step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.warmup, n_total):
+        one_step(k)
+        print(f"[bench] step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = ctx.profile_read()
+    ctx.profile_enable(False)
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    N = w.n_trans
+    Pm = _mask_index(w).numel()
+    bp_ms, bp_n = stages["backproject_gemm"]
+    avg_bp = bp_ms / max(bp_n, 1)
+    flops_bp = 24.0 * N * N * Pm            # 3 complex GEMMs of N x N x P_m per launch
+    achieved = flops_bp / (avg_bp * 1e-3) / 1e12
+    roofline = {
+        "kernel": "rowred_kernel (Hessian-free back-projection, 3 complex GEMMs)",
+        "bound": "mfma",
+        "achieved": round(achieved, 2),
+        "peak": FP32_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_bp, 3),
+        "flops_per_launch": flops_bp,
+    }
+    line = {
+        "metric": "frequency-step updates/s at 1024 elems, 1024^2 grid (FP32 form)",
+        "value": round(1000.0 / ms_per_step, 4),
+        "unit": "frequency-step updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded breast-like phantom, ray-Born data + 1% noise)",
+        "config": {"workload": w.name, "transducers": N, "grid": f"{w.nx}x{w.ny}",
+                   "dx_mm": w.dx * 1e3, "rays_per_transducer": w.n_rays,
+                   "mask_nodes": int(Pm), "freqs_hz": [w.freqs[k] for k in
+                                                        range(args.warmup, n_total)],
+                   "parallelism": "single GPU"},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
