@@ -128,12 +128,50 @@ def cpu_baseline(w):
     }
 
 
+PEAKS = {"f32": (FP32_MFMA_PEAK_TFLOPS, "fp32 MFMA"), "bf16": (2500.0, "bf16 MFMA dense"),
+         "f16": (2500.0, "fp16 MFMA dense")}
+
+
+def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag):
+    """Time `steps` frequency steps of one form from the water model (after `warmup`)."""
+    import torch
+
+    from paper_2211_00316_amd import _lib
+
+    d_om = 2 * math.pi * (w.freqs[1] - w.freqs[0]) if len(w.freqs) > 1 else None
+    c = torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
+    rn = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+
+    def one_step(k):
+        om = 2 * math.pi * w.freqs[k]
+        ctx.frequency_step(grid, ring, tp, c, w.smooth_window(k), [om], [d_om or om],
+                           data[k], w.tau, residual_norm=rn, prec=prec)
+
+    for k in range(warmup):
+        one_step(k)
+        print(f"[bench] {tag} warmup step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        one_step(k)
+        print(f"[bench] {tag} step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = ctx.profile_read()
+    ctx.profile_enable(False)
+    return 1000.0 * elapsed / steps, stages, c
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ring1024_grid1024")
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "f16", "f32"],
+                    help="operand type of the headline (reduced-precision) form")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -158,59 +196,50 @@ def main():
     print(f"[bench] {w.name}: synthesizing data for {n_total} frequencies", file=sys.stderr,
           flush=True)
     data = synthesize_data(ctx, w, grid, ring, tp, c_true, list(range(n_total)))
-    d_om = 2 * math.pi * (w.freqs[1] - w.freqs[0]) if len(w.freqs) > 1 else None
-    c = torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
-    rn = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    prec_code = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
 
-    def one_step(k):
-        om = 2 * math.pi * w.freqs[k]
-        ctx.frequency_step(grid, ring, tp, c, w.smooth_window(k), [om], [d_om or om],
-                           data[k], w.tau, residual_norm=rn)
-
-    for k in range(args.warmup):
-        one_step(k)
-        print(f"[bench] warmup step {k} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(args.warmup, n_total):
-        one_step(k)
-        print(f"[bench] step {k} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = ctx.profile_read()
-    ctx.profile_enable(False)
-    ms_per_step = 1000.0 * elapsed / args.steps
+    forms = {}
+    if not args.no_fp32 and args.prec != "f32":
+        ms32, st32, c32 = run_form(ctx, w, grid, ring, tp, data, _lib.RB_F32, args.steps,
+                                   args.warmup, "f32")
+        forms["f32"] = (ms32, st32, c32)
+    ms, stages, c_lp = run_form(ctx, w, grid, ring, tp, data, prec_code, args.steps,
+                                args.warmup, args.prec)
+    forms[args.prec] = (ms, stages, c_lp)
 
     N = w.n_trans
-    Pm = _mask_index(w).numel()
+    mask = _mask_index(w)
+    Pm = mask.numel()
     bp_ms, bp_n = stages["backproject_gemm"]
     avg_bp = bp_ms / max(bp_n, 1)
     flops_bp = 24.0 * N * N * Pm            # 3 complex GEMMs of N x N x P_m per launch
     achieved = flops_bp / (avg_bp * 1e-3) / 1e12
+    peak, peak_name = PEAKS[args.prec]
     roofline = {
-        "kernel": "rowred_kernel (Hessian-free back-projection, 3 complex GEMMs)",
+        "kernel": "rowred (Hessian-free back-projection, 3 complex GEMMs N x N x P_m)",
         "bound": "mfma",
         "achieved": round(achieved, 2),
-        "peak": FP32_MFMA_PEAK_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+        "frac": round(achieved / peak, 4),
         "traffic": None,
+        "peak_is": peak_name,
         "avg_launch_ms": round(avg_bp, 3),
         "flops_per_launch": flops_bp,
     }
     line = {
-        "metric": "frequency-step updates/s at 1024 elems, 1024^2 grid (FP32 form)",
-        "value": round(1000.0 / ms_per_step, 4),
+        "metric": "frequency-step updates/s at 1024 elems, 1024^2 grid (reduced-precision form; "
+                  "FP32 form alongside)",
+        "value": round(1000.0 / ms, 4),
         "unit": "frequency-step updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
+        "ms_per_step": round(ms, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.prec,
         "data": "synthetic (seeded breast-like phantom, ray-Born data + 1% noise)",
         "config": {"workload": w.name, "transducers": N, "grid": f"{w.nx}x{w.ny}",
                    "dx_mm": w.dx * 1e3, "rays_per_transducer": w.n_rays,
@@ -220,6 +249,18 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
     }
+    if "f32" in forms and args.prec != "f32":
+        ms32, st32, c32 = forms["f32"]
+        line["fp32_form"] = {
+            "value": round(1000.0 / ms32, 4), "ms_per_step": round(ms32, 2),
+            "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st32.items()}}
+        line["speedup_vs_fp32"] = round(ms32 / ms, 3)
+        # same frequencies, same start: image difference between the two forms on the mask
+        a = c_lp.reshape(-1)[mask]
+        b = c32.reshape(-1)[mask]
+        line["image_rel_diff_vs_fp32"] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        da, db = a - 1500.0, b - 1500.0
+        line["update_rel_diff_vs_fp32"] = float(torch.linalg.norm(da - db) / torch.linalg.norm(db))
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

@@ -98,12 +98,16 @@ typedef struct {
     uint8_t *rx_flags;
 } rb_tables;
 
-/* Green's-function operands of one frequency (output of rb_build_green), complex64:
- *   G  [n][n_mask]     g(omega, x, e) = A exp(i (phi + pi/4))  (Eq. 2D_greens);
- *   H  [3][n][n_mask]  back-projection operands a_e g_dagger, a_e g_dagger u_x,
- *                      a_e g_dagger u_y (Eq. greens-time-reversed times the angular
- *                      weight |d gamma_e / d e| De of Eq. sound_speed_update2).
- * Only RB_F32 operands are produced by this version. */
+/* Green's-function operands of one frequency (output of rb_build_green):
+ *   G  g(omega, x, e) = A exp(i (phi + pi/4))  (Eq. 2D_greens);
+ *   H  back-projection operands a_e g_dagger, a_e g_dagger u_x, a_e g_dagger u_y
+ *      (Eq. greens-time-reversed times the angular weight |d gamma_e / d e| De of
+ *      Eq. sound_speed_update2).
+ * Layout by precision:
+ *   RB_F32:  G complex64 [n][n_mask];  H complex64 [3][n][n_mask].
+ *   RB_BF16, RB_F16 (16-bit operands, FP32 accumulation in every contraction):
+ *            G planar [2 (re, im)][n][n_mask];  H planar, node-major
+ *            [3][2 (re, im)][n_mask][n] (transducer index contiguous). */
 typedef struct {
     int32_t n;
     int32_t n_mask;
@@ -151,7 +155,7 @@ rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const
 
 /* Adjoint of rb_born_forward for real delta (Eq. functional-gradient with Q = 1):
  * grad[q] = Re{ conj(w[q]) sum_e conj(G[e][q]) sum_r R[e][r] conj(G[r][q]) }.
- * R: complex64 [n][n]; grad: float [n_mask]. */
+ * R: complex64 [n][n]; grad: float [n_mask]. RB_F32 operands only. */
 rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const float *R,
                           float *grad);
 
@@ -175,11 +179,13 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
  * d_omega: HOST arrays of n_omega values; data: complex64 [n_omega][n][n] measured Green's
  * functions (row = emitter). smooth_w: odd window of the tracing map. If any updated value
  * is not finite the model is left unchanged and RB_ENONFINITE is returned.
- * residual_norm (device double, may be NULL) receives sum |g_res|^2 over all frequencies. */
+ * residual_norm (device double, may be NULL) receives sum |g_res|^2 over all frequencies.
+ * prec selects the operand type of the Born contractions (RB_F32 plain form; RB_BF16 /
+ * RB_F16 reduced form); tracing, phases and the model update are the same in all forms. */
 rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
                             int32_t n_omega, const double *omega, const double *d_omega,
-                            const float *data, double tau, rb_mode mode,
+                            const float *data, double tau, rb_mode mode, rb_prec prec,
                             double *residual_norm);
 
 /* Measurement: per-stage GPU time from HIP events recorded around every kernel launch on

@@ -89,8 +89,8 @@ def load(path: str = LIB_PATH):
         "rb_backproject": ([P, ctypes.POINTER(_Green), P, P, D, D, P, I32], ctypes.c_int),
         "rb_frequency_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                                ctypes.POINTER(TraceParams), P, I32, I32,
-                               ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int, P],
-                              ctypes.c_int),
+                               ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int,
+                               ctypes.c_int, P], ctypes.c_int),
         "rb_profile_enable": ([P, I32], ctypes.c_int),
         "rb_profile_read": ([P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "rb_stage_name": ([I32], ctypes.c_char_p),
@@ -149,21 +149,51 @@ class Tables:
                                                        self.rx_flags)))
 
 
+_LP_DTYPE = {RB_BF16: torch.bfloat16, RB_F16: torch.float16}
+
+
 @dataclasses.dataclass
 class Green:
-    """Device tensors of rb_green: G [n][n_mask], H [3][n][n_mask] (complex64)."""
+    """Device tensors of rb_green.
+
+    RB_F32: G complex64 [n][n_mask], H complex64 [3][n][n_mask].
+    RB_BF16 / RB_F16: G planar [2][n][n_mask], H planar node-major [3][2][n_mask][n]."""
 
     G: torch.Tensor
     H: torch.Tensor
+    prec: int = RB_F32
 
     @classmethod
-    def empty(cls, n, n_mask, device):
-        return cls(torch.empty(n, n_mask, dtype=torch.complex64, device=device),
-                   torch.empty(3, n, n_mask, dtype=torch.complex64, device=device))
+    def empty(cls, n, n_mask, device, prec=RB_F32):
+        if prec == RB_F32:
+            return cls(torch.empty(n, n_mask, dtype=torch.complex64, device=device),
+                       torch.empty(3, n, n_mask, dtype=torch.complex64, device=device), prec)
+        dt = _LP_DTYPE[prec]
+        return cls(torch.empty(2, n, n_mask, dtype=dt, device=device),
+                   torch.empty(3, 2, n_mask, n, dtype=dt, device=device), prec)
+
+    @property
+    def n(self):
+        return self.G.shape[-2]
+
+    @property
+    def n_mask(self):
+        return self.G.shape[-1]
+
+    def complex_G(self):
+        """G as complex [n][n_mask] (float32 parts), for checks."""
+        if self.prec == RB_F32:
+            return self.G
+        return torch.complex(self.G[0].float(), self.G[1].float())
+
+    def complex_H(self):
+        """H, H u_x, H u_y as complex [3][n][n_mask], for checks."""
+        if self.prec == RB_F32:
+            return self.H
+        return torch.complex(self.H[:, 0].float(), self.H[:, 1].float()).transpose(1, 2)
 
     def struct(self):
-        n, nm = self.G.shape
-        return _Green(n, nm, RB_F32, self.G.data_ptr(), self.H.data_ptr())
+        return _Green(self.n, self.n_mask, self.prec, self.G.data_ptr(), self.H.data_ptr())
 
 
 class Context:
@@ -224,9 +254,10 @@ class Context:
                                            ctypes.byref(tp), _ptr(n_s), ctypes.byref(s)))
         return tb
 
-    def build_green(self, tb: Tables, omega: float, c0: float, out: Green | None = None) -> Green:
+    def build_green(self, tb: Tables, omega: float, c0: float, out: Green | None = None,
+                    prec: int = RB_F32) -> Green:
         n, nm = tb.T.shape
-        gr = out if out is not None else Green.empty(n, nm, self.device)
+        gr = out if out is not None else Green.empty(n, nm, self.device, prec)
         s, g = tb.struct(), gr.struct()
         self._check(self.lib.rb_build_green(self._h, ctypes.byref(s), omega, c0, ctypes.byref(g)))
         return gr
@@ -235,7 +266,7 @@ class Context:
                      out: torch.Tensor | None = None) -> torch.Tensor:
         _dev(w, torch.complex64)
         _dev(delta, torch.float32)
-        n = gr.G.shape[0]
+        n = gr.n
         d = out if out is not None else torch.empty(n, n, dtype=torch.complex64, device=self.device)
         g = gr.struct()
         self._check(self.lib.rb_born_forward(self._h, ctypes.byref(g), _ptr(w), _ptr(delta),
@@ -245,7 +276,7 @@ class Context:
     def born_adjoint(self, gr: Green, w: torch.Tensor, R: torch.Tensor) -> torch.Tensor:
         _dev(w, torch.complex64)
         _dev(R, torch.complex64)
-        out = torch.empty(gr.G.shape[1], dtype=torch.float32, device=self.device)
+        out = torch.empty(gr.n_mask, dtype=torch.float32, device=self.device)
         g = gr.struct()
         self._check(self.lib.rb_born_adjoint(self._h, ctypes.byref(g), _ptr(w), _ptr(R),
                                              _ptr(out)))
@@ -267,7 +298,7 @@ class Context:
                     accumulate: bool = False) -> torch.Tensor:
         _dev(R, torch.complex64)
         _dev(c_mask, torch.float64)
-        dm = out if out is not None else torch.empty(gr.G.shape[1], dtype=torch.float32,
+        dm = out if out is not None else torch.empty(gr.n_mask, dtype=torch.float32,
                                                      device=self.device)
         g = gr.struct()
         self._check(self.lib.rb_backproject(self._h, ctypes.byref(g), _ptr(R), _ptr(c_mask),
@@ -276,7 +307,8 @@ class Context:
 
     def frequency_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
                        smooth_w: int, omegas, d_omegas, data: torch.Tensor, tau: float,
-                       mode: int = RB_RAY_BORN, residual_norm: torch.Tensor | None = None):
+                       mode: int = RB_RAY_BORN, residual_norm: torch.Tensor | None = None,
+                       prec: int = RB_F32):
         """Updates c (float64 [ny][nx], on the GPU) in place."""
         _dev(c, torch.float64)
         _dev(data, torch.complex64)
@@ -285,5 +317,6 @@ class Context:
         dom = (ctypes.c_double * k)(*d_omegas)
         self._check(self.lib.rb_frequency_step(
             self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
-            int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), _ptr(residual_norm)))
+            int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), int(prec),
+            _ptr(residual_norm)))
         return c

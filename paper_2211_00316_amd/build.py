@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["rb_api.hip", "rb_trace.hip", "rb_green.hip", "rb_gemm.hip"]
+SOURCES = ["rb_api.hip", "rb_trace.hip", "rb_green.hip", "rb_gemm.hip", "rb_lowp.hip"]
 LIB = os.path.join(HERE, "libraybornhf.so")
 
 FLAGS = [

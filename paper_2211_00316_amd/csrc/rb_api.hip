@@ -163,8 +163,8 @@ static rb_status check_green(rb_ctx *ctx, const rb_green *gr) {
     if (!gr) return rb_fail(ctx, RB_EINVAL, "green operands are NULL");
     if (gr->n < 1 || gr->n_mask < 1 || !gr->G || !gr->H)
         return rb_fail(ctx, RB_EINVAL, "green operands incomplete");
-    if (gr->prec != RB_F32)
-        return rb_fail(ctx, RB_EUNSUPPORTED, "only RB_F32 operands are available");
+    if (gr->prec != RB_F32 && gr->prec != RB_BF16 && gr->prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "unknown operand precision %d", (int)gr->prec);
     return RB_OK;
 }
 
@@ -289,6 +289,7 @@ rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double 
     if (!finite_pos(omega) || !finite_pos(c0))
         return rb_fail(ctx, RB_EINVAL, "omega and c0 must be positive");
     RB_HIP(ctx, hipSetDevice(ctx->device));
+    if (out->prec != RB_F32) return rb_launch_green_lp(ctx, tb, omega, c0, out);
     return rb_launch_green(ctx, tb, omega, c0, out);
 }
 
@@ -298,6 +299,7 @@ rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const
     RB_TRY(check_green(ctx, gr));
     if (!w || !delta || !d) return rb_fail(ctx, RB_EINVAL, "w, delta and d must be non-NULL");
     RB_HIP(ctx, hipSetDevice(ctx->device));
+    if (gr->prec != RB_F32) return rb_launch_forward_lp(ctx, gr, w, delta, d);
     return rb_launch_forward(ctx, gr, w, delta, d);
 }
 
@@ -306,6 +308,8 @@ rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const
     if (!ctx) return RB_EINVAL;
     RB_TRY(check_green(ctx, gr));
     if (!w || !R || !grad) return rb_fail(ctx, RB_EINVAL, "w, R and grad must be non-NULL");
+    if (gr->prec != RB_F32)
+        return rb_fail(ctx, RB_EUNSUPPORTED, "the Q=1 adjoint takes RB_F32 operands only");
     RB_HIP(ctx, hipSetDevice(ctx->device));
     int mb = rb_rowred_mblocks(gr->n);
     ctx->ws.used = 0;
@@ -335,11 +339,23 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
     if (!finite_pos(omega) || !finite_pos(d_omega))
         return rb_fail(ctx, RB_EINVAL, "omega and d_omega must be positive");
     RB_HIP(ctx, hipSetDevice(ctx->device));
-    int mb = rb_rowred_mblocks(gr->n);
+    const bool lp = gr->prec != RB_F32;
+    int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
+    size_t nn = (size_t)gr->n * gr->n;
     ctx->ws.used = 0;
-    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float))));
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
+                                               rb_align(2 * nn * sizeof(uint16_t)) + rb_align(8)));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
-    RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, parts, &mb));
+    if (lp) {
+        uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nn);
+        float *rscale = rb_carve<float>(&ctx->ws, 2);
+        RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
+        RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb));
+        RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
+    } else {
+        RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, parts,
+                                &mb));
+    }
     return rb_launch_backproject_finish(ctx, gr->n_mask, mb, parts, c_mask, omega, d_omega, dm,
                                         accumulate);
 }
@@ -347,7 +363,7 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
 rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
                             int32_t n_omega, const double *omega, const double *d_omega,
-                            const float *data, double tau, rb_mode mode,
+                            const float *data, double tau, rb_mode mode, rb_prec prec,
                             double *residual_norm) {
     if (!ctx) return RB_EINVAL;
     RB_TRY(rb_check_grid(ctx, grid));
@@ -364,6 +380,8 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     if (!std::isfinite(tau)) return rb_fail(ctx, RB_EINVAL, "tau must be finite");
     if (mode != RB_RAY_BORN && mode != RB_RAY_ONLY)
         return rb_fail(ctx, RB_EINVAL, "unknown mode");
+    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
     RB_HIP(ctx, hipSetDevice(ctx->device));
     RB_TRY(rb_prepare_grid(ctx, grid));
 
@@ -371,12 +389,15 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     const int nm = (int)ctx->n_mask;
     const size_t P = (size_t)grid->nx * grid->ny;
     const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
-    const int mb = rb_rowred_mblocks(N);
+    const bool lp = prec != RB_F32;
+    const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
+    const size_t opb = lp ? 4 : 8;  // bytes per complex operand
     size_t bytes = rb_align(P * 4) + rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP) +
-                   rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * 8) +
-                   rb_align(3 * NP * 8) + 2 * rb_align(NN * 8) + rb_align((size_t)nm * 8) +
-                   rb_align((size_t)nm * 4) + 3 * rb_align((size_t)nm * 8) +
-                   rb_align((size_t)2 * mb * nm * 4) + rb_align(8);
+                   rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
+                   rb_align(3 * NP * opb) + 2 * rb_align(NN * 8) + rb_align(NN * 4) +
+                   rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
+                   3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
+                   rb_align(8);
     ctx->step.used = 0;
     RB_TRY(rb_arena_reserve(ctx, &ctx->step, bytes));
     rb_arena *a = &ctx->step;
@@ -395,11 +416,13 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     rb_green gr;
     gr.n = N;
     gr.n_mask = nm;
-    gr.prec = RB_F32;
-    gr.G = rb_carve<float2>(a, NP);
-    gr.H = rb_carve<float2>(a, 3 * NP);
+    gr.prec = prec;
+    gr.G = rb_carve<char>(a, NP * opb);
+    gr.H = rb_carve<char>(a, 3 * NP * opb);
     float *d_born = rb_carve<float>(a, 2 * NN);
     float *R = rb_carve<float>(a, 2 * NN);
+    uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NN);
+    float *rscale = rb_carve<float>(a, 2);
     float *wv = rb_carve<float>(a, 2 * (size_t)nm);
     float *delta = rb_carve<float>(a, nm);
     double *cq = rb_carve<double>(a, nm);
@@ -416,20 +439,32 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     for (int k = 0; k < n_omega; ++k) {
         const double om = omega[k];
         // a4: Green's functions and back-projection operands
-        RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr));
+        if (lp)
+            RB_TRY(rb_launch_green_lp(ctx, &tb, om, tp->c0, &gr));
+        else
+            RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr));
         // a5-a6: predicted data (ray part + Born term of the rough part) and residual
         const float *born = nullptr;
         if (mode == RB_RAY_BORN) {
             RB_TRY(rb_launch_rough_part(ctx, cq, n_s, tp->c0, (float)(om * om * grid->dx * grid->dx),
                                         wv, delta));
-            RB_TRY(rb_launch_forward(ctx, &gr, wv, delta, d_born));
+            if (lp)
+                RB_TRY(rb_launch_forward_lp(ctx, &gr, wv, delta, d_born));
+            else
+                RB_TRY(rb_launch_forward(ctx, &gr, wv, delta, d_born));
             born = d_born;
         }
         RB_TRY(rb_launch_residual(ctx, &tb, om, tp->c0, born, data + 2 * NN * (size_t)k, R,
                                   residual_norm));
         // a8: Hessian-free back-projection, accumulated over the set in FP64
         int mbo = mb;
-        RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, parts, &mbo));
+        if (lp) {
+            RB_TRY(rb_launch_to_planar(ctx, prec, R, N, Rp, rscale));
+            RB_TRY(rb_launch_rowred_lp(ctx, prec, N, nm, Rp, gr.H, 3, parts, &mbo));
+            RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mbo * nm, rscale));
+        } else {
+            RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, parts, &mbo));
+        }
         RB_TRY(rb_launch_backproject_finish_acc(ctx, mbo, parts, cq, om, d_omega[k], dm));
     }
     // a9: model update, committed only if every value is finite

@@ -105,3 +105,16 @@ rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, con
                                        const double *c_mask, double omega, double d_omega,
                                        float *dm, int accumulate);
 int rb_rowred_mblocks(int n);
+
+// Reduced-precision (BF16 / FP16 operand) form: layouts in rb_lowp.hip.
+rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                             const rb_green *out);
+// R -> planar 16-bit, scaled by a power of two kept in scale[0..1] (device, 2 floats).
+rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
+                              float *scale);
+rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);
+rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
+                              const void *Ht, int n_comp, float *parts, int *mblocks);
+rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
+                               const float *delta, float *d);
+int rb_rowred_lp_mblocks(int n);

@@ -1,0 +1,647 @@
+// Reduced-precision form of the Born operator (BF16 / FP16 operands, FP32 accumulation).
+//
+// The same mathematics as rb_green.hip / rb_gemm.hip (Eqs. 2D_greens, greens-time-reversed,
+// perturb1, derivative, sound_speed_update2), with the Green's-function operands stored in a
+// 16-bit type and the complex contractions on the 16-bit matrix cores
+// (v_mfma_f32_32x32x16_bf16 / _f16: K = 16 per instruction, 8 consecutive K per lane).
+// The phase omega T + pi/4 - K pi/2 is still reduced in FP64 and the sincos is FP32; only
+// the stored operands are rounded.
+//
+// Layouts (planar re / im, so that one 16-byte load gives 8 consecutive K of one part):
+//   Gp  [2][N][P_m]      G rows (transducer-major, node-contiguous): the forward operator
+//                        d = G diag(v) G^T contracts over nodes, K-contiguous for both sides;
+//   Ht  [3][2][P_m][N]   H, H u_x, H u_y transposed (node-major, transducer-contiguous): the
+//                        back-projection Y_c = R H_c contracts over transducers;
+//   Rp  [2][N][N]        residual rows.
+// The green kernel transposes H through LDS so that both layouts are written coalesced.
+#include "rb_internal.h"
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Lp;
+template <> struct Lp<__bf16> {
+    typedef bf16x8 vec;
+    static __device__ __forceinline__ floatx16 mfma(vec a, vec b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Lp<_Float16> {
+    typedef halfx8 vec;
+    static __device__ __forceinline__ floatx16 mfma(vec a, vec b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename T> __device__ __forceinline__ T to_lp(float x) { return (T)x; }
+template <typename T> __device__ __forceinline__ float from_lp(T x) { return (float)x; }
+
+// Negate eight packed 16-bit values (both types keep the sign in bit 15).
+__device__ __forceinline__ uint4 neg8(uint4 v) {
+    return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u,
+                      v.w ^ 0x80008000u);
+}
+
+template <typename T> __device__ __forceinline__ typename Lp<T>::vec as_vec(uint4 v) {
+    return __builtin_bit_cast(typename Lp<T>::vec, v);
+}
+
+__device__ __forceinline__ int mfma_row(int lane, int i) {
+    return (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+}
+
+__device__ __forceinline__ double reduce_phase(double ph) {
+    return ph - RB_TWO_PI * floor(ph / RB_TWO_PI);
+}
+
+// Green's functions --------------------------------------------------------------------
+constexpr int GT = 64;  // tile: 64 transducers x 64 mask nodes
+
+template <typename T>
+__global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
+                                                       double omega, double c0, T *__restrict__ Gp,
+                                                       T *__restrict__ Ht) {
+    __shared__ float s_ux[GT + 2][GT], s_uy[GT + 2][GT];
+    __shared__ uint8_t s_f[GT + 2][GT];
+    __shared__ T s_h[3][2][GT][GT + 8];
+    const int q0 = blockIdx.x * GT, e0 = blockIdx.y * GT;
+    const int tid = threadIdx.x, tq = tid & 63, tr = tid >> 6;
+    const int q = q0 + tq;
+    // halo rows e0-1 .. e0+64 (mod N) of directions and flags
+    for (int r = tr; r < GT + 2; r += 4) {
+        int e = (e0 - 1 + r + N) % N;
+        float ux = 0.f, uy = 0.f;
+        uint8_t f = 0;
+        if (q < n_mask) {
+            size_t o = (size_t)e * n_mask + q;
+            f = tb.flags[o];
+            ux = tb.ux[o];
+            uy = tb.uy[o];
+        }
+        s_ux[r][tq] = ux;
+        s_uy[r][tq] = uy;
+        s_f[r][tq] = f;
+    }
+    __syncthreads();
+    const double k0 = omega / c0;
+    const float sk = (float)sqrt(k0);
+    const size_t gplane = (size_t)N * n_mask;
+    for (int r = tr; r < GT; r += 4) {
+        int e = e0 + r;
+        float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, ux = 0.f, uy = 0.f;
+        if (e < N && q < n_mask) {
+            size_t o = (size_t)e * n_mask + q;
+            uint8_t f = s_f[r + 1][tq];
+            if (f & 0x80) {
+                double ph = reduce_phase(omega * tb.T[o] + 0.25 * RB_PI -
+                                         (double)(f & 3) * 0.5 * RB_PI);
+                float s, c;
+                sincosf((float)ph, &s, &c);
+                float A = tb.A[o];
+                float ga = A / sk;
+                gr = ga * c;
+                gi = ga * s;
+                ux = s_ux[r + 1][tq];
+                uy = s_uy[r + 1][tq];
+                bool vm = s_f[r][tq] & 0x80, vp = s_f[r + 2][tq] & 0x80;
+                float a = 0.f;
+                if (vm && vp) {
+                    float ax = s_ux[r][tq], ay = s_uy[r][tq];
+                    float bx = s_ux[r + 2][tq], by = s_uy[r + 2][tq];
+                    a = 0.5f * fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
+                } else if (vp) {
+                    float bx = s_ux[r + 2][tq], by = s_uy[r + 2][tq];
+                    a = fabsf(atan2f(ux * by - uy * bx, ux * bx + uy * by));
+                } else if (vm) {
+                    float ax = s_ux[r][tq], ay = s_uy[r][tq];
+                    a = fabsf(atan2f(ax * uy - ay * ux, ax * ux + ay * uy));
+                }
+                float ha = a * sk / A;
+                hr = ha * c;
+                hi = -ha * s;
+            }
+            Gp[o] = to_lp<T>(gr);
+            Gp[gplane + o] = to_lp<T>(gi);
+        }
+        s_h[0][0][tq][r] = to_lp<T>(hr);
+        s_h[0][1][tq][r] = to_lp<T>(hi);
+        s_h[1][0][tq][r] = to_lp<T>(hr * ux);
+        s_h[1][1][tq][r] = to_lp<T>(hi * ux);
+        s_h[2][0][tq][r] = to_lp<T>(hr * uy);
+        s_h[2][1][tq][r] = to_lp<T>(hi * uy);
+    }
+    __syncthreads();
+    // transposed store: rows (c, part, q), 64 transducers each, 8 bytes per thread
+    const size_t hplane = (size_t)n_mask * N;
+    for (int idx = tid; idx < 3 * 2 * GT * (GT / 4); idx += 256) {
+        int chunk = idx % (GT / 4), row = idx / (GT / 4);
+        int qq = row % GT, cp = row / GT;
+        int c = cp >> 1, part = cp & 1;
+        int gq = q0 + qq, ge = e0 + chunk * 4;
+        if (gq >= n_mask) continue;
+        T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * N + ge;
+        const T *src = &s_h[c][part][qq][chunk * 4];
+        if (ge + 3 < N && ((N & 3) == 0)) {
+            *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+        } else {
+            for (int u = 0; u < 4; ++u)
+                if (ge + u < N) dst[u] = src[u];
+        }
+    }
+}
+
+// Power-of-two range scale of an operand: scale[0] = 2^(14 - e) and scale[1] = 1/scale[0]
+// with 2^(e-1) <= max |x| < 2^e, so the largest scaled magnitude lies in [2^13, 2^14)
+// (inside the FP16 range, far from its subnormals). One block; exact (powers of two).
+__global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restrict__ x,
+                                                           size_t count, const float *__restrict__ y,
+                                                           float *__restrict__ scale) {
+    __shared__ float red[16];
+    float m = 0.f;
+    for (size_t i = threadIdx.x; i < count; i += blockDim.x) {
+        float2 v = x[i];
+        float a = fmaxf(fabsf(v.x), fabsf(v.y));
+        if (y) a *= fabsf(y[i]);
+        m = fmaxf(m, a);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mm = 0.f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mm = fmaxf(mm, red[i]);
+        int e = 0;
+        if (mm > 0.f && isfinite(mm)) frexpf(mm, &e);
+        float s = ldexpf(1.f, 14 - e);
+        scale[0] = s;
+        scale[1] = 1.f / s;
+    }
+}
+
+// complex64 [n][n] -> planar T [2][n][n], multiplied by scale[0]
+template <typename T>
+__global__ void to_planar_kernel(const float2 *__restrict__ src, int n,
+                                 const float *__restrict__ scale, T *__restrict__ dst) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t nn = (size_t)n * n;
+    if (i >= nn) return;
+    float s = scale[0];
+    float2 v = src[i];
+    dst[i] = to_lp<T>(v.x * s);
+    dst[nn + i] = to_lp<T>(v.y * s);
+}
+
+// parts *= scale[1] (undo the residual's range scale before the final sum)
+__global__ void unscale_kernel(float *__restrict__ parts, size_t count,
+                               const float *__restrict__ scale) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) parts[i] *= scale[1];
+}
+
+// Back-projection: Y_c = R H_c, epilogue sums over the tile's rows of H_c[e][q] Y_c[e][q] --
+constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_PAD = 8, LR_LD = LR_BK + LR_PAD;
+
+template <typename T>
+__global__ void __launch_bounds__(512) rowred_lp_kernel(const T *__restrict__ Rp,
+                                                        const T *__restrict__ Ht, int n,
+                                                        int n_cols, int n_comp, int mblocks,
+                                                        int nblocks, float *__restrict__ parts) {
+    __shared__ __attribute__((aligned(16))) T a_s[2][LR_BM][LR_LD];
+    __shared__ __attribute__((aligned(16))) T b_s[2][LR_BN][LR_LD];
+    __shared__ float red[2][4][LR_BN];
+
+    const int total = mblocks * nblocks;
+    const int per_xcd = (total + 7) / 8;
+    const int gid = blockIdx.x;
+    const int t = (gid & 7) * per_xcd + (gid >> 3);
+    if (t >= total) return;
+    const int nb = t / mblocks, mb = t - nb * mblocks;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves, 64 x 64 each
+    const int row0 = mb * LR_BM, col0 = nb * LR_BN;
+    const size_t rplane = (size_t)n * n;
+    const size_t hplane = (size_t)n_cols * n;
+    const bool kvec = (n % 8) == 0;
+
+    float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
+
+    // loader assignment: A tile 256 rows x 2 parts x 4 chunks of 8 -> 2048 chunks, 4 each;
+    // B tile 128 rows x 2 parts x 4 chunks -> 1024 chunks, 2 each.
+    for (int c = 0; c < n_comp; ++c) {
+        const T *Hc = Ht + (size_t)(2 * c) * hplane;
+        floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    acc_re[mt][nt][i] = 0.f;
+                    acc_im[mt][nt][i] = 0.f;
+                }
+        uint4 ra[4], rb[2];
+        auto load = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int idx = tid + u * 512;
+                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
+                int gr = row0 + row, gk = k0 + ch * 8;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (gr < n) {
+                    const T *src = Rp + part * rplane + (size_t)gr * n + gk;
+                    if (kvec && gk + 7 < n) {
+                        v = *reinterpret_cast<const uint4 *>(src);
+                    } else {
+                        T tmp[8];
+#pragma unroll
+                        for (int z = 0; z < 8; ++z) tmp[z] = (gk + z < n) ? src[z] : to_lp<T>(0.f);
+                        v = __builtin_bit_cast(uint4, tmp);
+                    }
+                }
+                ra[u] = v;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int idx = tid + u * 512;
+                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
+                int gq = col0 + row, gk = k0 + ch * 8;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (gq < n_cols) {
+                    const T *src = Hc + part * hplane + (size_t)gq * n + gk;
+                    if (kvec && gk + 7 < n) {
+                        v = *reinterpret_cast<const uint4 *>(src);
+                    } else {
+                        T tmp[8];
+#pragma unroll
+                        for (int z = 0; z < 8; ++z) tmp[z] = (gk + z < n) ? src[z] : to_lp<T>(0.f);
+                        v = __builtin_bit_cast(uint4, tmp);
+                    }
+                }
+                rb[u] = v;
+            }
+        };
+        load(0);
+        for (int k0 = 0; k0 < n; k0 += LR_BK) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int idx = tid + u * 512;
+                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
+                *reinterpret_cast<uint4 *>(&a_s[part][row][ch * 8]) = ra[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int idx = tid + u * 512;
+                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
+                *reinterpret_cast<uint4 *>(&b_s[part][row][ch * 8]) = rb[u];
+            }
+            __syncthreads();
+            if (k0 + LR_BK < n) load(k0 + LR_BK);
+#pragma unroll
+            for (int ks = 0; ks < LR_BK; ks += 16) {
+                int kk = ks + (lane >> 5) * 8;
+                uint4 ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    int m = wm * 64 + mt * 32 + (lane & 31);
+                    ar[mt] = *reinterpret_cast<const uint4 *>(&a_s[0][m][kk]);
+                    ai[mt] = *reinterpret_cast<const uint4 *>(&a_s[1][m][kk]);
+                    nai[mt] = neg8(ai[mt]);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    int cn = wn * 64 + nt * 32 + (lane & 31);
+                    br[nt] = *reinterpret_cast<const uint4 *>(&b_s[0][cn][kk]);
+                    bi[nt] = *reinterpret_cast<const uint4 *>(&b_s[1][cn][kk]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(br[nt]),
+                                                     acc_re[mt][nt]);
+                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(nai[mt]), as_vec<T>(bi[nt]),
+                                                     acc_re[mt][nt]);
+                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(bi[nt]),
+                                                     acc_im[mt][nt]);
+                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ai[mt]), as_vec<T>(br[nt]),
+                                                     acc_im[mt][nt]);
+                    }
+            }
+            __syncthreads();
+        }
+        // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows per register group
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
+            if (gq >= n_cols) continue;
+            const T *er_row = Hc + (size_t)gq * n;
+            const T *ei_row = Hc + hplane + (size_t)gq * n;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    int ge = row0 + wm * 64 + mt * 32 + g * 8 + (lane >> 5) * 4;
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) {
+                        if (ge + z < n) {
+                            float er = from_lp<T>(er_row[ge + z]);
+                            float ei = from_lp<T>(ei_row[ge + z]);
+                            float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
+                            cs_re[nt] += er * yr - ei * yi;
+                            cs_im[nt] += er * yi + ei * yr;
+                        }
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        cs_re[nt] += __shfl_xor(cs_re[nt], 32);
+        cs_im[nt] += __shfl_xor(cs_im[nt], 32);
+        if (lane < 32) {
+            red[0][wm][wn * 64 + nt * 32 + lane] = cs_re[nt];
+            red[1][wm][wn * 64 + nt * 32 + lane] = cs_im[nt];
+        }
+    }
+    __syncthreads();
+    if (tid < LR_BN) {
+        int gc = col0 + tid;
+        if (gc < n_cols) {
+            float sr = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
+            float si = red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
+            parts[(size_t)mb * n_cols + gc] = sr;
+            parts[(size_t)(mblocks + mb) * n_cols + gc] = si;
+        }
+    }
+}
+
+// Forward: d[e][r] = sum_q G[e][q] v[q] G[r][q] on 16-bit operands, split-K, upper tiles ----
+constexpr int LF_B = 128, LF_BK = 32, LF_LD = LF_BK + 8;
+
+__device__ __forceinline__ void upper_tile(int idx, int T_, int &tm, int &tn) {
+    int r = 0, rem = idx;
+    while (rem >= T_ - r) {
+        rem -= T_ - r;
+        ++r;
+    }
+    tm = r;
+    tn = r + rem;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ Gp,
+                                                         const float2 *__restrict__ w,
+                                                         const float *__restrict__ delta, int n,
+                                                         int K, int nT, int kchunk,
+                                                         const float *__restrict__ vscale,
+                                                         float2 *__restrict__ dpart) {
+    __shared__ __attribute__((aligned(16))) T a_s[2][LF_B][LF_LD];
+    const float vs = vscale[0];
+    __shared__ __attribute__((aligned(16))) T b_s[2][LF_B][LF_LD];
+    int tm, tn;
+    upper_tile(blockIdx.x, nT, tm, tn);
+    const int split = blockIdx.y;
+    const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int row0 = tm * LF_B, col0 = tn * LF_B;
+    const size_t gplane = (size_t)n * K;
+
+    floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                acc_re[mt][nt][i] = 0.f;
+                acc_im[mt][nt][i] = 0.f;
+            }
+
+    // each tile: 128 rows x 4 chunks of 8 K = 512 (row, chunk) pairs, 2 per thread
+    const bool kvec = (K % 8) == 0;
+    for (int k0 = kbeg; k0 < kend; k0 += LF_BK) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            int idx = tid + u * 256;
+            int ch = idx & 3, row = idx >> 2;
+            int gk = k0 + ch * 8;
+            int ge = row0 + row, gr = col0 + row;
+            // v = w delta for the 8 node indices of this chunk
+            float vr[8], vi[8];
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                int k = gk + z;
+                float2 wv = make_float2(0.f, 0.f);
+                float dl = 0.f;
+                if (k < kend) {
+                    wv = w[k];
+                    dl = delta[k] * vs;
+                }
+                vr[z] = wv.x * dl;
+                vi[z] = wv.y * dl;
+            }
+            // 8 consecutive K of one row of G (both parts), zero beyond the chunk end
+            auto row8 = [&](int grow, T *re, T *im) {
+                if (grow < n && kvec && gk + 7 < kend) {
+                    uint4 a = *reinterpret_cast<const uint4 *>(Gp + (size_t)grow * K + gk);
+                    uint4 b = *reinterpret_cast<const uint4 *>(Gp + gplane + (size_t)grow * K + gk);
+                    __builtin_memcpy(re, &a, 16);
+                    __builtin_memcpy(im, &b, 16);
+                } else {
+#pragma unroll
+                    for (int z = 0; z < 8; ++z) {
+                        bool ok = grow < n && gk + z < kend;
+                        re[z] = ok ? Gp[(size_t)grow * K + gk + z] : to_lp<T>(0.f);
+                        im[z] = ok ? Gp[gplane + (size_t)grow * K + gk + z] : to_lp<T>(0.f);
+                    }
+                }
+            };
+            T ar[8], ai[8], br[8], bi[8];
+            row8(ge, ar, ai);
+            row8(gr, br, bi);
+            // A = G v, complex product in FP32 rounded once to the operand type
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                float gre = from_lp<T>(ar[z]), gim = from_lp<T>(ai[z]);
+                ar[z] = to_lp<T>(gre * vr[z] - gim * vi[z]);
+                ai[z] = to_lp<T>(gre * vi[z] + gim * vr[z]);
+            }
+            *reinterpret_cast<uint4 *>(&a_s[0][row][ch * 8]) = __builtin_bit_cast(uint4, ar);
+            *reinterpret_cast<uint4 *>(&a_s[1][row][ch * 8]) = __builtin_bit_cast(uint4, ai);
+            *reinterpret_cast<uint4 *>(&b_s[0][row][ch * 8]) = __builtin_bit_cast(uint4, br);
+            *reinterpret_cast<uint4 *>(&b_s[1][row][ch * 8]) = __builtin_bit_cast(uint4, bi);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < LF_BK; ks += 16) {
+            int kk = ks + (lane >> 5) * 8;
+            uint4 ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                int m = wm * 64 + mt * 32 + (lane & 31);
+                ar[mt] = *reinterpret_cast<const uint4 *>(&a_s[0][m][kk]);
+                ai[mt] = *reinterpret_cast<const uint4 *>(&a_s[1][m][kk]);
+                nai[mt] = neg8(ai[mt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                int cn = wn * 64 + nt * 32 + (lane & 31);
+                br[nt] = *reinterpret_cast<const uint4 *>(&b_s[0][cn][kk]);
+                bi[nt] = *reinterpret_cast<const uint4 *>(&b_s[1][cn][kk]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    acc_re[mt][nt] =
+                        Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(br[nt]), acc_re[mt][nt]);
+                    acc_re[mt][nt] =
+                        Lp<T>::mfma(as_vec<T>(nai[mt]), as_vec<T>(bi[nt]), acc_re[mt][nt]);
+                    acc_im[mt][nt] =
+                        Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(bi[nt]), acc_im[mt][nt]);
+                    acc_im[mt][nt] =
+                        Lp<T>::mfma(as_vec<T>(ai[mt]), as_vec<T>(br[nt]), acc_im[mt][nt]);
+                }
+        }
+        __syncthreads();
+    }
+    float2 *out = dpart + (size_t)split * n * n;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            int gc = col0 + wn * 64 + nt * 32 + (lane & 31);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                int gr = row0 + wm * 64 + mt * 32 + mfma_row(lane, i);
+                if (gr < n && gc < n)
+                    out[(size_t)gr * n + gc] = make_float2(acc_re[mt][nt][i], acc_im[mt][nt][i]);
+            }
+        }
+}
+
+__global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int splitk,
+                                  const float *__restrict__ vscale, float2 *__restrict__ d) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
+    if (r >= n) return;
+    size_t src = (e <= r) ? (size_t)e * n + r : (size_t)r * n + e;
+    float sr = 0.f, si = 0.f;
+    for (int s = 0; s < splitk; ++s) {
+        float2 v = dpart[(size_t)s * n * n + src];
+        sr += v.x;
+        si += v.y;
+    }
+    float inv = vscale[1];
+    d[(size_t)e * n + r] = make_float2(sr * inv, si * inv);
+}
+
+}  // namespace
+
+// Launchers ------------------------------------------------------------------------------
+rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
+                             const rb_green *out) {
+    dim3 grd((tb->n_mask + GT - 1) / GT, (tb->n + GT - 1) / GT);
+    rb_prof_begin(ctx, ST_GREEN);
+    if (out->prec == RB_BF16)
+        hipLaunchKernelGGL(green_lp_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
+                           tb->n_mask, omega, c0, (__bf16 *)out->G, (__bf16 *)out->H);
+    else
+        hipLaunchKernelGGL(green_lp_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
+                           tb->n_mask, omega, c0, (_Float16 *)out->G, (_Float16 *)out->H);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
+                              float *scale) {
+    size_t nn = (size_t)n * n;
+    rb_prof_begin(ctx, ST_RESIDUAL);
+    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
+                       (const float2 *)R, nn, (const float *)nullptr, scale);
+    RB_CHECK_LAUNCH(ctx);
+    dim3 grd((unsigned)((nn + 255) / 256));
+    if (prec == RB_BF16)
+        hipLaunchKernelGGL(to_planar_kernel<__bf16>, grd, dim3(256), 0, ctx->stream,
+                           (const float2 *)R, n, scale, (__bf16 *)Rp);
+    else
+        hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
+                           (const float2 *)R, n, scale, (_Float16 *)Rp);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale) {
+    hipLaunchKernelGGL(unscale_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       ctx->stream, parts, count, scale);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+int rb_rowred_lp_mblocks(int n) { return (n + LR_BM - 1) / LR_BM; }
+
+rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
+                              const void *Ht, int n_comp, float *parts, int *mblocks_out) {
+    int mblocks = rb_rowred_lp_mblocks(n);
+    int nblocks = (n_mask + LR_BN - 1) / LR_BN;
+    int total = mblocks * nblocks;
+    int grid = ((total + 7) / 8) * 8;
+    rb_prof_begin(ctx, ST_BACKPROJECT);
+    if (prec == RB_BF16)
+        hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(512), 0, ctx->stream,
+                           (const __bf16 *)Rp, (const __bf16 *)Ht, n, n_mask, n_comp, mblocks,
+                           nblocks, parts);
+    else
+        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(512), 0, ctx->stream,
+                           (const _Float16 *)Rp, (const _Float16 *)Ht, n, n_mask, n_comp, mblocks,
+                           nblocks, parts);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    if (mblocks_out) *mblocks_out = mblocks;
+    return RB_OK;
+}
+
+rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
+                               const float *delta, float *d) {
+    const int n = gr->n, K = gr->n_mask;
+    const int nT = (n + LF_B - 1) / LF_B;
+    const int tiles = nT * (nT + 1) / 2;
+    int ksteps = (K + LF_BK - 1) / LF_BK;
+    int splitk = (1024 + tiles - 1) / tiles;
+    splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
+    int kchunk = ((ksteps + splitk - 1) / splitk) * LF_BK;
+    splitk = (K + kchunk - 1) / kchunk;
+    ctx->ws.used = 0;
+    rb_status st = rb_arena_reserve(
+        ctx, &ctx->ws, rb_align((size_t)splitk * n * n * sizeof(float2)) + rb_align(8));
+    if (st != RB_OK) return st;
+    float2 *dpart = rb_carve<float2>(&ctx->ws, (size_t)splitk * n * n);
+    float *vscale = rb_carve<float>(&ctx->ws, 2);
+    rb_prof_begin(ctx, ST_FORWARD);
+    // range scale of v = w delta (the node weights are folded into the A operand)
+    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
+                       (const float2 *)w, (size_t)K, delta, vscale);
+    RB_CHECK_LAUNCH(ctx);
+    if (gr->prec == RB_BF16)
+        hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(tiles, splitk), dim3(256), 0,
+                           ctx->stream, (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, nT,
+                           kchunk, vscale, dpart);
+    else
+        hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(tiles, splitk), dim3(256), 0,
+                           ctx->stream, (const _Float16 *)gr->G, (const float2 *)w, delta, n, K,
+                           nT, kchunk, vscale, dpart);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    rb_prof_begin(ctx, ST_FORWARD_REDUCE);
+    hipLaunchKernelGGL(forward_reduce_lp, dim3((n + 255) / 256, n), dim3(256), 0, ctx->stream,
+                       dpart, n, splitk, vscale, (float2 *)d);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}

@@ -268,3 +268,105 @@ def test_nonfinite_update_leaves_model_unchanged(ctx):
                            torch.as_tensor(data, device="cuda:0"), 0.12)
     assert e.value.status == _lib.RB_ENONFINITE
     assert np.array_equal(to_np(c_g), c)
+
+
+# Reduced-precision form (16-bit operands, FP32 accumulation) -----------------------------
+# Tolerances follow the unit roundoff u of the operand type (bf16 2^-9, fp16 2^-12 relative
+# for round-to-nearest): operands <= 8u, contractions (two rounded factors, random-phase
+# sums, a rounded epilogue factor) <= 40u; the reconstructed image <= 2e-3 relative.
+LOWP = {"bf16": (2, 2.0 ** -9), "fp16": (3, 2.0 ** -12)}
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
+def test_build_green_lowp(ctx, name, pname):
+    prec, u = LOWP[pname]
+    st, c = case(name)
+    tb_o, _ = oracle_tables(name)
+    om = 2 * math.pi * 500e3
+    _say(f"build_green {pname} {name}")
+    gr = ctx.build_green(tables_to_gpu(tb_o), om, C0, prec=prec)
+    G, H, Hx, Hy = green.build_green(tb_o, om)
+    assert rel_l2(to_np(gr.complex_G()), G) <= 8 * u
+    Hs = to_np(gr.complex_H())
+    for k, ref in enumerate((H, Hx, Hy)):
+        assert rel_l2(Hs[k], ref) <= 8 * u
+
+
+def _green_gpu_lowp(ctx, name, om, prec):
+    tb_o, _ = oracle_tables(name)
+    return tb_o, green.build_green(tb_o, om), ctx.build_green(tables_to_gpu(tb_o), om, C0,
+                                                             prec=prec)
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
+def test_born_forward_lowp(ctx, name, pname):
+    import torch
+
+    prec, u = LOWP[pname]
+    st, c = case(name)
+    om = 2 * math.pi * 300e3
+    tb_o, (G, H, Hx, Hy), gr = _green_gpu_lowp(ctx, name, om, prec)
+    q = st.grid.mask_index()
+    w = np.full(q.size, om ** 2 * st.grid.dx ** 2)
+    delta = (1.0 / c.ravel()[q] ** 2 - 1.0 / C0 ** 2)
+    _say(f"born_forward {pname} {name}")
+    d = to_np(ctx.born_forward(gr, torch.as_tensor(w.astype(np.complex64), device="cuda:0"),
+                               torch.as_tensor(delta.astype(np.float32), device="cuda:0")))
+    ref = born.forward(G, w, delta)
+    err = rel_l2(d, ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 40 * u
+    assert np.array_equal(d, d.T)
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
+def test_backproject_lowp(ctx, name, pname):
+    import torch
+
+    prec, u = LOWP[pname]
+    st, c = case(name)
+    om = 2 * math.pi * 350e3
+    tb_o, (G, H, Hx, Hy), gr = _green_gpu_lowp(ctx, name, om, prec)
+    N = G.shape[0]
+    rng = np.random.default_rng(9)
+    R = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).astype(np.complex64)
+    cq = c.ravel()[st.grid.mask_index()]
+    _say(f"backproject {pname} {name}")
+    dm = to_np(ctx.backproject(gr, torch.as_tensor(R, device="cuda:0"),
+                               torch.as_tensor(cq, device="cuda:0"), om, 0.5 * om))
+    S = born.backproject_weight(om, 0.5 * om, cq)
+    ref = born.backproject(R.astype(np.complex128), H, Hx, Hy, S)
+    err = rel_l2(dm, ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 40 * u
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("name,window", [("ring64", 1), ("ragged", 5)])
+def test_frequency_step_lowp_image(ctx, name, window, pname):
+    import torch
+    import phantoms as ph
+
+    prec, u = LOWP[pname]
+    st, c_true = case(name)
+    N = st.ring.n
+    om = [2 * math.pi * 250e3]
+    data = ostep.synthesize(c_true, st, om, ph.complex_noise((1, N, N), 2), background="water")
+    c0 = np.full_like(c_true, C0)
+    c_ref = ostep.frequency_step(c0, st, om, om, data, 0.12, window=window)
+    grid, ring, tp = abi_structs(st)
+    _say(f"frequency_step {pname} {name} w={window}")
+    c_g = torch.as_tensor(c0.copy(), device="cuda:0")
+    ctx.frequency_step(grid, ring, tp, c_g, window, om, om,
+                       torch.as_tensor(data.astype(np.complex64), device="cuda:0"), 0.12,
+                       prec=prec)
+    q = st.grid.mask_index()
+    c_new = to_np(c_g).ravel()[q]
+    img = rel_l2(c_new, c_ref.ravel()[q])
+    upd = rel_l2(c_new - C0, (c_ref - c0).ravel()[q])
+    _say(f"  image rel L2 {img:.2e}, update rel L2 {upd:.2e}")
+    assert img <= 2e-3
+    assert upd <= 40 * u
