@@ -137,9 +137,16 @@ rb_status rb_refractive_index(rb_ctx *ctx, const rb_grid *grid, const double *c,
  * the uniform cubic B-spline of these samples is the medium; Section 4.5) with the paraxial
  * Heun scheme of Algorithm 1, bin the rays onto the mask nodes by linear interpolation over
  * the triangulated ray samples (Section 4.5), and fill the receiver tables from the rays'
- * exit points (Section 6.3). Writes every field of `out` (sizes must match). */
+ * exit points (Section 6.3). Writes every field of `out` (sizes must match). Where several
+ * triangles cover a node (a folded fan), the smallest travel time wins, ties to the lowest
+ * triangle id. */
 rb_status rb_trace_rays(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                         const rb_trace_params *tp, const float *n_s, const rb_tables *out);
+
+/* Diagnostic of the last rb_trace_rays / rb_frequency_step on this context: the number of
+ * (transducer, mask node) pairs that the mesh walk of an unfolded fan could not place in a
+ * triangle (reported as invalid table entries). Zero in normal operation. */
+int64_t rb_trace_lost_nodes(const rb_ctx *ctx);
 
 /* Assemble G and the back-projection operands H of angular frequency omega from the tables
  * (Eqs. 2D_greens, phase-discretised, greens-time-reversed). The phase omega T + pi/4 -

@@ -23,7 +23,7 @@ SYMBOLS = (
     "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
-    "rb_stage_name",
+    "rb_stage_name", "rb_trace_lost_nodes",
 )
 N_STAGES = 12
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "rb_profile_enable": ([P, I32], ctypes.c_int),
         "rb_profile_read": ([P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "rb_stage_name": ([I32], ctypes.c_char_p),
+        "rb_trace_lost_nodes": ([P], ctypes.c_int64),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +227,10 @@ class Context:
     def _check(self, st):
         if st != RB_OK:
             raise RayBornError(st, self.lib.rb_last_error(self._h).decode())
+
+    def lost_nodes(self) -> int:
+        """Mask nodes the last binning could not place (diagnostic; 0 normally)."""
+        return int(self.lib.rb_trace_lost_nodes(self._h))
 
     # measurement ------------------------------------------------------------------------
     def profile_enable(self, on: bool = True):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq);
@@ -142,6 +143,18 @@ rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
                           hipMemcpyHostToDevice));
     RB_HIP(ctx, hipMemcpy(ctx->d_qmap, map.data(), map.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
+    int imin = g->nx, imax = -1, jmin = g->ny, jmax = -1;
+    for (int32_t p : idx) {
+        int i = p % g->nx, j = p / g->nx;
+        imin = std::min(imin, i);
+        imax = std::max(imax, i);
+        jmin = std::min(jmin, j);
+        jmax = std::max(jmax, j);
+    }
+    ctx->tile_i0 = imin;
+    ctx->tile_j0 = jmin;
+    ctx->tiles_x = (imax - imin + 16) / 16;
+    ctx->tiles_y = (jmax - jmin + 16) / 16;
     ctx->grid = *g;
     ctx->n_mask = n;
     ctx->have_grid = true;
@@ -189,7 +202,7 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     if (hipMalloc(&ctx->d_flag, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(&ctx->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&ctx->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
@@ -215,6 +228,8 @@ void rb_destroy(rb_ctx *ctx) {
 }
 
 const char *rb_last_error(const rb_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int64_t rb_trace_lost_nodes(const rb_ctx *ctx) { return ctx ? ctx->lost_nodes : -1; }
 
 rb_status rb_profile_enable(rb_ctx *ctx, int32_t on) {
     if (!ctx) return RB_EINVAL;

@@ -31,6 +31,8 @@ struct rb_ctx {
     int64_t n_mask = 0;
     int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
     int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
+    int tile_i0 = 0, tile_j0 = 0;     // 16 x 16 node tiles covering the mask's bounding box
+    int tiles_x = 0, tiles_y = 0;
 
     // per-stage event timing (rb_profile_enable / rb_profile_read)
     bool prof = false;
@@ -42,7 +44,8 @@ struct rb_ctx {
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
     int32_t *d_flag = nullptr;        // device error flags (ray overflow, non-finite update)
-    int32_t *h_flag = nullptr;        // pinned host mirror
+    int32_t *h_flag = nullptr;        // pinned host mirror (2 ints)
+    int64_t lost_nodes = 0;           // mask nodes the last binning could not place
 };
 
 // Stages timed by the profiler (order = rb_stage_name).

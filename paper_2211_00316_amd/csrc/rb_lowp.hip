@@ -58,20 +58,21 @@ __device__ __forceinline__ double reduce_phase(double ph) {
 }
 
 // Green's functions --------------------------------------------------------------------
-constexpr int GT = 64;  // tile: 64 transducers x 64 mask nodes
+constexpr int GQ = 64;  // tile: 64 mask nodes (lanes) x GE transducers
+constexpr int GE = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
                                                        double omega, double c0, T *__restrict__ Gp,
                                                        T *__restrict__ Ht) {
-    __shared__ float s_ux[GT + 2][GT], s_uy[GT + 2][GT];
-    __shared__ uint8_t s_f[GT + 2][GT];
-    __shared__ T s_h[3][2][GT][GT + 8];
-    const int q0 = blockIdx.x * GT, e0 = blockIdx.y * GT;
+    __shared__ float s_ux[GE + 2][GQ], s_uy[GE + 2][GQ];
+    __shared__ uint8_t s_f[GE + 2][GQ];
+    __shared__ __attribute__((aligned(16))) T s_h[3][2][GQ][GE + 8];
+    const int q0 = blockIdx.x * GQ, e0 = blockIdx.y * GE;
     const int tid = threadIdx.x, tq = tid & 63, tr = tid >> 6;
     const int q = q0 + tq;
-    // halo rows e0-1 .. e0+64 (mod N) of directions and flags
-    for (int r = tr; r < GT + 2; r += 4) {
+    // halo rows e0-1 .. e0+GE (mod N) of directions and flags
+    for (int r = tr; r < GE + 2; r += 4) {
         int e = (e0 - 1 + r + N) % N;
         float ux = 0.f, uy = 0.f;
         uint8_t f = 0;
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
     const double k0 = omega / c0;
     const float sk = (float)sqrt(k0);
     const size_t gplane = (size_t)N * n_mask;
-    for (int r = tr; r < GT; r += 4) {
+    for (int r = tr; r < GE; r += 4) {
         int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, ux = 0.f, uy = 0.f;
         if (e < N && q < n_mask) {
@@ -134,20 +135,21 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         s_h[2][1][tq][r] = to_lp<T>(hi * uy);
     }
     __syncthreads();
-    // transposed store: rows (c, part, q), 64 transducers each, 8 bytes per thread
+    // transposed store: rows (c, part, q) of GE transducers, 16 bytes (8 values) per store
     const size_t hplane = (size_t)n_mask * N;
-    for (int idx = tid; idx < 3 * 2 * GT * (GT / 4); idx += 256) {
-        int chunk = idx % (GT / 4), row = idx / (GT / 4);
-        int qq = row % GT, cp = row / GT;
+    constexpr int CH = GE / 8;
+    for (int idx = tid; idx < 3 * 2 * GQ * CH; idx += 256) {
+        int chunk = idx % CH, row = idx / CH;
+        int qq = row % GQ, cp = row / GQ;
         int c = cp >> 1, part = cp & 1;
-        int gq = q0 + qq, ge = e0 + chunk * 4;
+        int gq = q0 + qq, ge = e0 + chunk * 8;
         if (gq >= n_mask) continue;
         T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * N + ge;
-        const T *src = &s_h[c][part][qq][chunk * 4];
-        if (ge + 3 < N && ((N & 3) == 0)) {
-            *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+        const T *src = &s_h[c][part][qq][chunk * 8];
+        if (ge + 7 < N && ((N & 7) == 0)) {
+            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
         } else {
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 8; ++u)
                 if (ge + u < N) dst[u] = src[u];
         }
     }
@@ -545,7 +547,7 @@ __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int s
 // Launchers ------------------------------------------------------------------------------
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const rb_green *out) {
-    dim3 grd((tb->n_mask + GT - 1) / GT, (tb->n + GT - 1) / GT);
+    dim3 grd((tb->n_mask + GQ - 1) / GQ, (tb->n + GE - 1) / GE);
     rb_prof_begin(ctx, ST_GREEN);
     if (out->prec == RB_BF16)
         hipLaunchKernelGGL(green_lp_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,

@@ -13,10 +13,16 @@
 // transducer, so the per-step sample stores are coalesced ([emitter][step][ray] planes).
 // Positions and the travel time are kept in FP64 (one FMA each per step); the rest of the
 // ray and paraxial state is FP32. The spline at the new point is reused as the first
-// evaluation of the next step. Binning: one lane per quad of neighbouring samples; each
-// covered mask node keeps the smallest (travel-time, triangle-id) 64-bit key by atomicMin
-// (order independent, hence deterministic); a resolve pass per node re-interpolates the
-// winning triangle and writes the tables with coalesced stores.
+// evaluation of the next step.
+//
+// Binning. The samples of one transducer form a structured mesh (ray j, step i). Where the
+// fan does not fold (no ray of that transducer meets a caustic), every mask node lies in
+// exactly one triangle (up to shared edges), so each (transducer, node) lane walks the mesh
+// from the straight-ray guess to its triangle and writes the tables directly: no atomics,
+// coalesced stores. A transducer whose fan folds goes through the general path instead:
+// one lane per quad keeps, per covered node, the smallest (travel-time, triangle-id) 64-bit
+// key by atomicMin (order independent, hence deterministic), and a resolve pass
+// re-interpolates the winning triangle.
 #include "rb_internal.h"
 
 #include <cmath>
@@ -25,7 +31,7 @@ namespace {
 
 struct GridP {
     int nx, ny;
-    double dx, x0, y0;
+    double dx, x0, y0, idx;  // idx = 1 / dx
 };
 
 struct Spline {
@@ -52,7 +58,7 @@ __device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], f
 // Value, gradient and Hessian (per metre) of the spline of f at (x, y).
 __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const GridP &g,
                                               double x, double y) {
-    double u = (x - g.x0) / g.dx, v = (y - g.y0) / g.dx;
+    double u = (x - g.x0) * g.idx, v = (y - g.y0) * g.idx;
     double fu = floor(u), fv = floor(v);
     int iu = (int)fu, iv = (int)fv;
     float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
@@ -81,7 +87,7 @@ __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const
         s_xy = fmaf(dv[b], r1, s_xy);
         s_yy = fmaf(ddv[b], r0, s_yy);
     }
-    float ih = (float)(1.0 / g.dx), ih2 = ih * ih;
+    float ih = (float)g.idx, ih2 = ih * ih;
     return Spline{s_v, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
 }
 
@@ -138,12 +144,14 @@ __device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const Gri
 }
 
 struct SampleBufs {
-    float *u, *v, *dT, *L, *tx, *ty;  // [E][S][n_rays]
+    float2 *pos;                       // [E][S][n_rays] position in node-index units
+    float4 *fld;                       // [E][S][n_rays] (dT, L, t_x, t_y)
     uint8_t *K;
     int32_t *M;                        // [E][n_rays] last sample index, -1 if invalid
     double *ex_beta;                   // [E][n_rays] exit angle from psi_e in [0, 2 pi)
     float *ex_dT, *ex_L;
     uint8_t *ex_K;
+    int32_t *folded;                   // [E] nonzero if a ray of the transducer met a caustic
 };
 
 __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns, GridP g,
@@ -174,21 +182,16 @@ __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns
     double T = 0.0;
 
     size_t base = (size_t)el * S * n_rays + j;
-    const float idx = (float)(1.0 / g.dx);
-    sb.u[base] = (float)((r.x - g.x0) / g.dx);
-    sb.v[base] = (float)((r.y - g.y0) / g.dx);
-    sb.dT[base] = 0.0f;
-    sb.L[base] = 0.0f;
-    sb.tx[base] = (float)cg;
-    sb.ty[base] = (float)sg;
+    sb.pos[base] = make_float2((float)((r.x - g.x0) * g.idx), (float)((r.y - g.y0) * g.idx));
+    sb.fld[base] = make_float4(0.0f, 0.0f, (float)cg, (float)sg);
     sb.K[base] = 0;
-    (void)idx;
 
     float J_prev = 0.0f, J1 = 0.0f, n1 = 1.0f;
     float inv_sqrt_8pi_s1 = 0.0f;
     int K = 0;
     int M = -1;
     const double R2 = R * R;
+    const double ic0 = 1.0 / c0;
     for (int i = 0; i < max_steps; ++i) {
         Ray nr = heun_step(ns, g, sc, r, ds);
         double h = ds;
@@ -207,34 +210,31 @@ __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns
         r = nr;
         sc = spline_eval(ns, g, r.x, r.y);
         float n_new = sc.v;
-        T += h * ((double)n_cur + (double)n_new) / (2.0 * c0);
+        T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
         float kn = sqrtf(r.kx * r.kx + r.ky * r.ky);
         float tx = r.kx / kn, ty = r.ky / kn;
         float J = r.dxx * (-ty) + r.dxy * tx;
         if (i >= 1 && J * J_prev < 0.0f) ++K;
         double d = sqrt((r.x - xe) * (r.x - xe) + (r.y - ye) * (r.y - ye));
+        float df = (float)d;
         if (i == 0) {
             J1 = J;
             n1 = n_new;
-            inv_sqrt_8pi_s1 = (float)(1.0 / sqrt(8.0 * RB_PI * d));
+            inv_sqrt_8pi_s1 = 1.0f / sqrtf(8.0f * (float)RB_PI * df);
         }
         float A = sqrtf(n1 / n_new * J1 / fabsf(J)) * inv_sqrt_8pi_s1;
-        float dT = (float)(T - d / c0);
-        float L = logf(A) + 0.5f * (float)log(d);
+        float dT = (float)(T - d * ic0);
+        float L = logf(A) + 0.5f * logf(df);
         size_t o = base + (size_t)(i + 1) * n_rays;
-        sb.u[o] = (float)((r.x - g.x0) / g.dx);
-        sb.v[o] = (float)((r.y - g.y0) / g.dx);
-        sb.dT[o] = dT;
-        sb.L[o] = L;
-        sb.tx[o] = tx;
-        sb.ty[o] = ty;
+        sb.pos[o] = make_float2((float)((r.x - g.x0) * g.idx), (float)((r.y - g.y0) * g.idx));
+        sb.fld[o] = make_float4(dT, L, tx, ty);
         sb.K[o] = (uint8_t)min(K, 255);
         J_prev = J;
         n_cur = n_new;
         if (last) {
             M = i + 1;
             double beta = atan2(r.y, r.x) - psi;
-            beta = beta - RB_TWO_PI * floor(beta / RB_TWO_PI);
+            beta = beta - RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
             size_t x = (size_t)el * n_rays + j;
             sb.ex_beta[x] = beta;
             sb.ex_dT[x] = dT;
@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns
     }
     sb.M[(size_t)el * n_rays + j] = M;
     if (M < 0) atomicOr(flag, 1);
+    if (K > 0) atomicOr(sb.folded + el, 1);
 }
 
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -269,6 +270,131 @@ __device__ __forceinline__ bool barycentric(float au, float av, float bu, float 
 // both triangles (the smallest-key rule picks one), so no node falls between triangles.
 #define RB_BARY_EPS 1e-5f
 
+// Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`.
+__device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t vb[3],
+                                            const float lam[3], double d, double c0,
+                                            const rb_tables &tb, size_t out) {
+    float dT = 0, L = 0, tx = 0, ty = 0;
+    int K = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float4 f = sb.fld[vb[k]];
+        dT += lam[k] * f.x;
+        L += lam[k] * f.y;
+        tx += lam[k] * f.z;
+        ty += lam[k] * f.w;
+        K = max(K, (int)sb.K[vb[k]]);
+    }
+    float tn = sqrtf(tx * tx + ty * ty);
+    tb.T[out] = (double)dT + d / c0;
+    tb.A[out] = expf(L) * rsqrtf((float)d);
+    tb.ux[out] = tx / tn;
+    tb.uy[out] = ty / tn;
+    tb.flags[out] = (uint8_t)(0x80 | (K & 3));
+}
+
+__device__ __forceinline__ void write_invalid(const rb_tables &tb, size_t out) {
+    tb.T[out] = 0.0;
+    tb.A[out] = 0.0f;
+    tb.ux[out] = 0.0f;
+    tb.uy[out] = 0.0f;
+    tb.flags[out] = 0;
+}
+
+// Walk of one (transducer, mask node) lane to the triangle that contains the node. A
+// workgroup covers a 16 x 16 tile of grid nodes of one transducer, so its walks touch a
+// compact patch of that transducer's ray mesh.
+constexpr int LOCATE_MAX_IT = 96;
+constexpr int LT = 16;
+
+__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                     int e0, GridP g, double R, double psi0,
+                                                     int N, double ds, double c0, int n_mask,
+                                                     int tile_i0, int tile_j0, int tiles_x,
+                                                     const int32_t *__restrict__ qmap,
+                                                     rb_tables tb, int *lost) {
+    const int el = blockIdx.y;
+    if (sb.folded[el]) return;  // general path
+    const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
+    const int ii = tile_i0 + ti * LT + (threadIdx.x % LT);
+    const int jj = tile_j0 + tj * LT + (threadIdx.x / LT);
+    if (ii >= g.nx || jj >= g.ny) return;
+    const int q = qmap[(size_t)jj * g.nx + ii];
+    if (q < 0) return;
+    const int e = e0 + el;
+    const size_t out = (size_t)e * n_mask + q;
+    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    double xe = R * cos(psi), ye = R * sin(psi);
+    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
+    double ddx = px - xe, ddy = py - ye;
+    double d = sqrt(ddx * ddx + ddy * ddy);
+    if (d < 2.0 * ds) {
+        write_invalid(tb, out);
+        return;
+    }
+    // straight-ray guess: launch angle and arc length of the node seen from the source
+    float rel = atan2f((float)ddy, (float)ddx) - (float)(psi + RB_PI);
+    rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
+    int j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
+    j = min(max(j, 0), n_rays - 2);
+    int i = min(max((int)(d / ds), 1), S - 2);
+    const float pu = (float)ii, pv = (float)jj;
+    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
+    const size_t ebase = (size_t)el * S * n_rays;
+    for (int it = 0; it < LOCATE_MAX_IT; ++it) {
+        int Mj = Mrow[j], Mj1 = Mrow[j + 1];
+        int top = min(Mj, Mj1) - 1;  // last quad index along the rays
+        if (Mj < 0 || Mj1 < 0 || top < 1) break;
+        if (i > top) i = top;
+        size_t b00 = ebase + (size_t)i * n_rays + j, b01 = b00 + n_rays;
+        float2 p00 = sb.pos[b00], p10 = sb.pos[b00 + 1], p01 = sb.pos[b01], p11 = sb.pos[b01 + 1];
+        float la, lb, lc;
+        if (barycentric(p00.x, p00.y, p10.x, p10.y, p11.x, p11.y, pu, pv, la, lb, lc) &&
+            la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
+            size_t vb[3] = {b00, b00 + 1, b01 + 1};
+            float lam[3] = {la, lb, lc};
+            write_entry(sb, vb, lam, d, c0, tb, out);
+            return;
+        }
+        if (barycentric(p00.x, p00.y, p11.x, p11.y, p01.x, p01.y, pu, pv, la, lb, lc) &&
+            la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
+            size_t vb[3] = {b00, b01 + 1, b01};
+            float lam[3] = {la, lb, lc};
+            write_entry(sb, vb, lam, d, c0, tb, out);
+            return;
+        }
+        // step across the quad edge the node lies farthest outside of
+        float area = (p10.x - p00.x) * (p01.y - p00.y) - (p10.y - p00.y) * (p01.x - p00.x);
+        float sg = area >= 0.f ? 1.f : -1.f;
+        auto side = [&](float2 a, float2 b) {
+            float ex = b.x - a.x, ey = b.y - a.y;
+            float cr = ex * (pv - a.y) - ey * (pu - a.x);
+            return sg * cr * rsqrtf(ex * ex + ey * ey + 1e-30f);
+        };
+        float s_i0 = side(p00, p10);   // edge at step i
+        float s_j1 = side(p10, p11);   // edge along ray j+1
+        float s_i1 = side(p11, p01);   // edge at step i+1
+        float s_j0 = side(p01, p00);   // edge along ray j
+        float worst = fminf(fminf(s_i0, s_j1), fminf(s_i1, s_j0));
+        if (worst >= 0.f) break;  // inside the quad but in neither triangle: degenerate
+        if (worst == s_i0) {
+            if (i <= 1) break;
+            --i;
+        } else if (worst == s_i1) {
+            if (i >= top) break;
+            ++i;
+        } else if (worst == s_j0) {
+            if (j <= 0) break;
+            --j;
+        } else {
+            if (j >= n_rays - 2) break;
+            ++j;
+        }
+    }
+    write_invalid(tb, out);
+    atomicAdd(lost, 1);
+}
+
 __device__ __forceinline__ void raster_tri(const float *tu, const float *tv, const float *tdT,
                                            int nx, int ny, const int32_t *__restrict__ qmap,
                                            unsigned long long *__restrict__ keys, uint32_t tid) {
@@ -292,7 +418,8 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv, con
     }
 }
 
-// One lane per quad (ray j, j+1; samples i, i+1), i >= 1, i + 1 <= min(M_j, M_j+1).
+// General path, folded fans only: one lane per quad (ray j, j+1; samples i, i+1), i >= 1,
+// i + 1 <= min(M_j, M_j+1).
 __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int nx, int ny, int n_mask,
                                                      const int32_t *__restrict__ qmap,
@@ -305,14 +432,16 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
     size_t rest = tid / nq;
     int i = (int)(rest % S);
     int el = (int)(rest / S);
-    if (i < 1) return;
+    if (i < 1 || !sb.folded[el]) return;
     int Mj = sb.M[(size_t)el * n_rays + j], Mj1 = sb.M[(size_t)el * n_rays + j + 1];
     if (Mj < 0 || Mj1 < 0 || i + 1 > min(Mj, Mj1)) return;
     size_t b00 = ((size_t)el * S + i) * n_rays + j;
     size_t b01 = b00 + n_rays;  // (j, i+1)
-    float u00 = sb.u[b00], u10 = sb.u[b00 + 1], u11 = sb.u[b01 + 1], u01 = sb.u[b01];
-    float v00 = sb.v[b00], v10 = sb.v[b00 + 1], v11 = sb.v[b01 + 1], v01 = sb.v[b01];
-    float d00 = sb.dT[b00], d10 = sb.dT[b00 + 1], d11 = sb.dT[b01 + 1], d01 = sb.dT[b01];
+    float2 p00 = sb.pos[b00], p10 = sb.pos[b00 + 1], p11 = sb.pos[b01 + 1], p01 = sb.pos[b01];
+    float u00 = p00.x, u10 = p10.x, u11 = p11.x, u01 = p01.x;
+    float v00 = p00.y, v10 = p10.y, v11 = p11.y, v01 = p01.y;
+    float d00 = sb.fld[b00].x, d10 = sb.fld[b00 + 1].x, d11 = sb.fld[b01 + 1].x,
+          d01 = sb.fld[b01].x;
     unsigned long long *ek = keys + (size_t)el * n_mask;
     uint32_t id0 = (uint32_t)(((size_t)j * S + i) * 2);
     {
@@ -325,12 +454,13 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
     }
 }
 
-__global__ void fill_keys(unsigned long long *keys, size_t n) {
+__global__ void fill_keys(unsigned long long *keys, size_t n, int n_mask,
+                          const int32_t *__restrict__ folded) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) keys[i] = ~0ull;
+    if (i < n && folded[i / n_mask]) keys[i] = ~0ull;
 }
 
-// Per (emitter, mask node): interpolate the winning triangle and write the tables.
+// General path: per (folded transducer, mask node) interpolate the winning triangle.
 __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                       int e0, GridP g, double R, double psi0,
                                                       int N, double ds, double c0, int n_mask,
@@ -340,6 +470,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= (size_t)E * n_mask) return;
     int el = (int)(tid / n_mask), q = (int)(tid - (size_t)el * n_mask);
+    if (!sb.folded[el]) return;
     int e = e0 + el;
     size_t out = (size_t)e * n_mask + q;
     unsigned long long key = keys[tid];
@@ -350,11 +481,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double d = sqrt((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
-        tb.T[out] = 0.0;
-        tb.A[out] = 0.0f;
-        tb.ux[out] = 0.0f;
-        tb.uy[out] = 0.0f;
-        tb.flags[out] = 0;
+        write_invalid(tb, out);
         return;
     }
     uint32_t tri = (uint32_t)(key & 0xffffffffu);
@@ -370,33 +497,20 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     float tu[3], tv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        tu[k] = sb.u[vb[k]];
-        tv[k] = sb.v[vb[k]];
+        float2 pk = sb.pos[vb[k]];
+        tu[k] = pk.x;
+        tv[k] = pk.y;
     }
     float la, lb, lc;
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
-    float dT = 0, L = 0, tx = 0, ty = 0;
-    int K = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        dT += lam[k] * sb.dT[vb[k]];
-        L += lam[k] * sb.L[vb[k]];
-        tx += lam[k] * sb.tx[vb[k]];
-        ty += lam[k] * sb.ty[vb[k]];
-        K = max(K, (int)sb.K[vb[k]]);
-    }
-    float tn = sqrtf(tx * tx + ty * ty);
-    tb.T[out] = (double)dT + d / c0;
-    tb.A[out] = expf(L) / (float)sqrt(d);
-    tb.ux[out] = tx / tn;
-    tb.uy[out] = ty / tn;
-    tb.flags[out] = (uint8_t)(0x80 | (K & 3));
+    write_entry(sb, vb, lam, d, c0, tb, out);
 }
 
 // Receiver tables: per emitter, bracket each receiver's angle between neighbouring exit
 // angles and interpolate dT and L linearly; the smallest travel time wins (lowest ray on a
-// tie); unbracketed pairs are invalid.
+// tie); unbracketed pairs are invalid. When every ray is valid and the exit angles increase
+// strictly with the ray index, the bracket of a receiver is unique and found by bisection.
 __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays, int e0, double R,
                                                        double psi0, int N, double c0,
                                                        rb_tables tb) {
@@ -406,7 +520,9 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
     float *Ls = dTs + n_rays;
     int *ok = reinterpret_cast<int *>(Ls + n_rays);
     uint8_t *Ks = reinterpret_cast<uint8_t *>(ok + n_rays);
+    __shared__ int not_monotone;
     int el = blockIdx.x, e = e0 + el;
+    if (threadIdx.x == 0) not_monotone = 0;
     for (int j = threadIdx.x; j < n_rays; j += blockDim.x) {
         size_t x = (size_t)el * n_rays + j;
         int good = sb.M[x] >= 0;
@@ -417,6 +533,10 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
         Ks[j] = good ? sb.ex_K[x] : 0;
     }
     __syncthreads();
+    for (int j = threadIdx.x; j + 1 < n_rays; j += blockDim.x)
+        if (!(ok[j] && ok[j + 1] && beta[j + 1] > beta[j])) not_monotone = 1;
+    __syncthreads();
+    const bool mono = !not_monotone;
     double psi_e = psi0 + RB_TWO_PI * (double)e / (double)N;
     double xe = R * cos(psi_e), ye = R * sin(psi_e);
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
@@ -426,18 +546,37 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
         bool found = false;
         double best = 0.0, bestL = 0.0;
         int bestK = 0;
+        auto take = [&](int j) {
+            double b0 = beta[j], b1 = beta[j + 1];
+            double lam = (br - b0) / (b1 - b0);
+            double dT = (1.0 - lam) * (double)dTs[j] + lam * (double)dTs[j + 1];
+            if (!found || dT < best) {
+                found = true;
+                best = dT;
+                bestL = (1.0 - lam) * (double)Ls[j] + lam * (double)Ls[j + 1];
+                bestK = max((int)Ks[j], (int)Ks[j + 1]);
+            }
+        };
         if (r != e) {
-            for (int j = 0; j + 1 < n_rays; ++j) {
-                if (!(ok[j] && ok[j + 1])) continue;
-                double b0 = beta[j], b1 = beta[j + 1];
-                if (b0 == b1 || br < fmin(b0, b1) || br > fmax(b0, b1)) continue;
-                double lam = (br - b0) / (b1 - b0);
-                double dT = (1.0 - lam) * (double)dTs[j] + lam * (double)dTs[j + 1];
-                if (!found || dT < best) {
-                    found = true;
-                    best = dT;
-                    bestL = (1.0 - lam) * (double)Ls[j] + lam * (double)Ls[j + 1];
-                    bestK = max((int)Ks[j], (int)Ks[j + 1]);
+            if (mono) {
+                if (br >= beta[0] && br <= beta[n_rays - 1]) {
+                    int lo = 0, hi = n_rays - 1;  // beta[lo] <= br <= beta[hi]
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (beta[mid] <= br) lo = mid;
+                        else hi = mid;
+                    }
+                    // a receiver exactly on a ray's exit angle is bracketed on both sides;
+                    // the lower pair wins the tie as in the full scan
+                    if (lo > 0 && beta[lo] == br) take(lo - 1);
+                    take(lo);
+                }
+            } else {
+                for (int j = 0; j + 1 < n_rays; ++j) {
+                    if (!(ok[j] && ok[j + 1])) continue;
+                    double b0 = beta[j], b1 = beta[j + 1];
+                    if (b0 == b1 || br < fmin(b0, b1) || br > fmax(b0, b1)) continue;
+                    take(j);
                 }
             }
         }
@@ -483,6 +622,11 @@ __global__ void box_cols(const double *__restrict__ tmp, int nx, int ny, int w,
     out[(size_t)j * nx + i] = (float)(acc / w);
 }
 
+__global__ void zero_i32(int32_t *x, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
 }  // namespace
 
 rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
@@ -505,7 +649,7 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
 // Emitters per chunk so that the ray samples of one chunk stay below ~6 GiB.
 static int trace_chunk(const rb_ring *r, const rb_trace_params *tp, int64_t n_mask) {
     size_t S = (size_t)tp->max_steps + 1;
-    size_t per = S * tp->n_rays * (6 * sizeof(float) + 1) + (size_t)n_mask * 8 +
+    size_t per = S * tp->n_rays * (sizeof(float2) + sizeof(float4) + 1) + (size_t)n_mask * 8 +
                  (size_t)tp->n_rays * 32;
     size_t budget = (size_t)6 << 30;
     size_t c = budget / per;
@@ -520,54 +664,62 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     const int n_mask = (int)ctx->n_mask;
     const int C = trace_chunk(r, tp, n_mask);
     size_t plane = (size_t)C * S * nr;
-    size_t bytes = 6 * rb_align(plane * sizeof(float)) + rb_align(plane) +
+    size_t bytes = rb_align(plane * sizeof(float2)) + rb_align(plane * sizeof(float4)) +
+                   rb_align(plane) +
                    rb_align((size_t)C * nr * sizeof(int32_t)) +
                    rb_align((size_t)C * nr * sizeof(double)) +
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
+                   rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long));
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
     if (st != RB_OK) return st;
     SampleBufs sb;
-    sb.u = rb_carve<float>(&ctx->ws, plane);
-    sb.v = rb_carve<float>(&ctx->ws, plane);
-    sb.dT = rb_carve<float>(&ctx->ws, plane);
-    sb.L = rb_carve<float>(&ctx->ws, plane);
-    sb.tx = rb_carve<float>(&ctx->ws, plane);
-    sb.ty = rb_carve<float>(&ctx->ws, plane);
+    sb.pos = rb_carve<float2>(&ctx->ws, plane);
+    sb.fld = rb_carve<float4>(&ctx->ws, plane);
     sb.K = rb_carve<uint8_t>(&ctx->ws, plane);
     sb.M = rb_carve<int32_t>(&ctx->ws, (size_t)C * nr);
     sb.ex_beta = rb_carve<double>(&ctx->ws, (size_t)C * nr);
     sb.ex_dT = rb_carve<float>(&ctx->ws, (size_t)C * nr);
     sb.ex_L = rb_carve<float>(&ctx->ws, (size_t)C * nr);
     sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
+    sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
+    int32_t *lost = rb_carve<int32_t>(&ctx->ws, 2);
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
 
-    GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0};
+    GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
     RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
+    RB_HIP(ctx, hipMemsetAsync(lost, 0, sizeof(int32_t), ctx->stream));
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
         int nthreads = E * nr;
+        hipLaunchKernelGGL(zero_i32, dim3((E + 255) / 256), dim3(256), 0, ctx->stream, sb.folded,
+                           E);
+        RB_CHECK_LAUNCH(ctx);
         rb_prof_begin(ctx, ST_TRACE);
         hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
                            n_s, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0, e0,
                            E, sb, ctx->d_flag);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
-        rb_prof_begin(ctx, ST_RASTER);
+        // unfolded fans: direct walk per (transducer, node)
         size_t nk = (size_t)E * n_mask;
+        rb_prof_begin(ctx, ST_RESOLVE);
+        hipLaunchKernelGGL(locate_kernel, dim3(ctx->tiles_x * ctx->tiles_y, E), dim3(LT * LT), 0,
+                           ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
+                           tp->c0, n_mask, ctx->tile_i0, ctx->tile_j0, ctx->tiles_x,
+                           ctx->d_qmap, *out, lost);
+        RB_CHECK_LAUNCH(ctx);
+        rb_prof_end(ctx);
+        // folded fans: smallest-key rasterisation and resolve
+        rb_prof_begin(ctx, ST_RASTER);
         hipLaunchKernelGGL(fill_keys, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
-                           ctx->stream, keys, nk);
+                           ctx->stream, keys, nk, n_mask, sb.folded);
         RB_CHECK_LAUNCH(ctx);
         size_t nquad = (size_t)E * S * (nr - 1);
-        if (nr > 1) {
-            hipLaunchKernelGGL(raster_kernel, dim3((unsigned)((nquad + 255) / 256)), dim3(256), 0,
-                               ctx->stream, sb, nr, S, E, g->nx, g->ny, n_mask, ctx->d_qmap,
-                               keys);
-            RB_CHECK_LAUNCH(ctx);
-        }
-        rb_prof_end(ctx);
-        rb_prof_begin(ctx, ST_RESOLVE);
+        hipLaunchKernelGGL(raster_kernel, dim3((unsigned)((nquad + 255) / 256)), dim3(256), 0,
+                           ctx->stream, sb, nr, S, E, g->nx, g->ny, n_mask, ctx->d_qmap, keys);
+        RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(resolve_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
                            tp->c0, n_mask, ctx->d_mask_index, keys, *out);
@@ -582,7 +734,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     }
     RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag + 1, lost, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->lost_nodes = ctx->h_flag[1];
     if (*ctx->h_flag & 1)
         return rb_fail(ctx, RB_ENONFINITE, "a ray did not reach the ring within max_steps=%d",
                        tp->max_steps);

@@ -26,6 +26,9 @@ def case(name):
         N, R, dx, nr, seed, amp, sig = 32, 0.02, 0.4e-3, 180, 11, 45.0, 4e-3
     elif name == "ragged":
         N, R, dx, nr, seed, amp, sig = 37, 0.021, 0.37e-3, 101, 12, -30.0, 3e-3
+    elif name == "folded":
+        # a strong slow lens: rays through it cross (caustics), the fans fold
+        N, R, dx, nr, seed, amp, sig = 32, 0.02, 0.4e-3, 180, 14, -300.0, 3e-3
     elif name == "ring64":
         w = ph.SMALL
         grid = Grid(w.nx, w.ny, w.dx, w.x0, w.y0, w.mask_radius)
