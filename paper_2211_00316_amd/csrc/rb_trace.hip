@@ -55,6 +55,9 @@ __device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], f
     dd[3] = t;
 }
 
+// Four consecutive floats of a row, 4-byte aligned: one 16-byte load.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
 // Value, gradient and Hessian (per metre) of the spline of f at (x, y).
 __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const GridP &g,
                                               double x, double y) {
@@ -64,6 +67,7 @@ __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const
     float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
     bspline_basis((float)(u - fu), bu, du, ddu);
     bspline_basis((float)(v - fv), bv, dv, ddv);
+    const bool interior = iu >= 1 && iu + 2 < g.nx;  // no clamping along the row
     int ii[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) ii[a] = min(max(iu - 1 + a, 0), g.nx - 1);
@@ -72,10 +76,21 @@ __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const
     for (int b = 0; b < 4; ++b) {
         int jj = min(max(iv - 1 + b, 0), g.ny - 1);
         const float *row = f + (size_t)jj * g.nx;
+        float fr[4];
+        if (interior) {
+            f4u q = *reinterpret_cast<const f4u *>(row + iu - 1);
+            fr[0] = q.x;
+            fr[1] = q.y;
+            fr[2] = q.z;
+            fr[3] = q.w;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fr[a] = row[ii[a]];
+        }
         float r0 = 0, r1 = 0, r2 = 0;  // row sums with B, B', B''
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            float fab = __ldg(row + ii[a]);
+            float fab = fr[a];
             r0 = fmaf(bu[a], fab, r0);
             r1 = fmaf(du[a], fab, r1);
             r2 = fmaf(ddu[a], fab, r2);
@@ -301,69 +316,44 @@ __device__ __forceinline__ void write_invalid(const rb_tables &tb, size_t out) {
     tb.flags[out] = 0;
 }
 
-// Walk of one (transducer, mask node) lane to the triangle that contains the node. A
-// workgroup covers a 16 x 16 tile of grid nodes of one transducer, so its walks touch a
-// compact patch of that transducer's ray mesh.
+// Walk over the ray mesh of one transducer, from quad (j, i), to the triangle that
+// contains the point (pu, pv) (node-index units). Returns false if the walk leaves the
+// mesh or does not settle within LOCATE_MAX_IT quads.
 constexpr int LOCATE_MAX_IT = 96;
 constexpr int LT = 16;
 
-__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
-                                                     int e0, GridP g, double R, double psi0,
-                                                     int N, double ds, double c0, int n_mask,
-                                                     int tile_i0, int tile_j0, int tiles_x,
-                                                     const int32_t *__restrict__ qmap,
-                                                     rb_tables tb, int *lost) {
-    const int el = blockIdx.y;
-    if (sb.folded[el]) return;  // general path
-    const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
-    const int ii = tile_i0 + ti * LT + (threadIdx.x % LT);
-    const int jj = tile_j0 + tj * LT + (threadIdx.x / LT);
-    if (ii >= g.nx || jj >= g.ny) return;
-    const int q = qmap[(size_t)jj * g.nx + ii];
-    if (q < 0) return;
-    const int e = e0 + el;
-    const size_t out = (size_t)e * n_mask + q;
-    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    double xe = R * cos(psi), ye = R * sin(psi);
-    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
-    double ddx = px - xe, ddy = py - ye;
-    double d = sqrt(ddx * ddx + ddy * ddy);
-    if (d < 2.0 * ds) {
-        write_invalid(tb, out);
-        return;
-    }
-    // straight-ray guess: launch angle and arc length of the node seen from the source
-    float rel = atan2f((float)ddy, (float)ddx) - (float)(psi + RB_PI);
-    rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
-    int j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
-    j = min(max(j, 0), n_rays - 2);
-    int i = min(max((int)(d / ds), 1), S - 2);
-    const float pu = (float)ii, pv = (float)jj;
-    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
-    const size_t ebase = (size_t)el * S * n_rays;
+__device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
+                                          size_t ebase, int n_rays, float pu, float pv, int &j,
+                                          int &i, size_t vb[3], float lam[3]) {
     for (int it = 0; it < LOCATE_MAX_IT; ++it) {
         int Mj = Mrow[j], Mj1 = Mrow[j + 1];
         int top = min(Mj, Mj1) - 1;  // last quad index along the rays
-        if (Mj < 0 || Mj1 < 0 || top < 1) break;
+        if (Mj < 0 || Mj1 < 0 || top < 1) return false;
         if (i > top) i = top;
         size_t b00 = ebase + (size_t)i * n_rays + j, b01 = b00 + n_rays;
         float2 p00 = sb.pos[b00], p10 = sb.pos[b00 + 1], p01 = sb.pos[b01], p11 = sb.pos[b01 + 1];
         float la, lb, lc;
         if (barycentric(p00.x, p00.y, p10.x, p10.y, p11.x, p11.y, pu, pv, la, lb, lc) &&
             la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
-            size_t vb[3] = {b00, b00 + 1, b01 + 1};
-            float lam[3] = {la, lb, lc};
-            write_entry(sb, vb, lam, d, c0, tb, out);
-            return;
+            vb[0] = b00;
+            vb[1] = b00 + 1;
+            vb[2] = b01 + 1;
+            lam[0] = la;
+            lam[1] = lb;
+            lam[2] = lc;
+            return true;
         }
         if (barycentric(p00.x, p00.y, p11.x, p11.y, p01.x, p01.y, pu, pv, la, lb, lc) &&
             la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
-            size_t vb[3] = {b00, b01 + 1, b01};
-            float lam[3] = {la, lb, lc};
-            write_entry(sb, vb, lam, d, c0, tb, out);
-            return;
+            vb[0] = b00;
+            vb[1] = b01 + 1;
+            vb[2] = b01;
+            lam[0] = la;
+            lam[1] = lb;
+            lam[2] = lc;
+            return true;
         }
-        // step across the quad edge the node lies farthest outside of
+        // step across the quad edge the point lies farthest outside of
         float area = (p10.x - p00.x) * (p01.y - p00.y) - (p10.y - p00.y) * (p01.x - p00.x);
         float sg = area >= 0.f ? 1.f : -1.f;
         auto side = [&](float2 a, float2 b) {
@@ -376,23 +366,94 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
         float s_i1 = side(p11, p01);   // edge at step i+1
         float s_j0 = side(p01, p00);   // edge along ray j
         float worst = fminf(fminf(s_i0, s_j1), fminf(s_i1, s_j0));
-        if (worst >= 0.f) break;  // inside the quad but in neither triangle: degenerate
+        if (worst >= 0.f) return false;  // inside the quad but in neither triangle
         if (worst == s_i0) {
-            if (i <= 1) break;
+            if (i <= 1) return false;
             --i;
         } else if (worst == s_i1) {
-            if (i >= top) break;
+            if (i >= top) return false;
             ++i;
         } else if (worst == s_j0) {
-            if (j <= 0) break;
+            if (j <= 0) return false;
             --j;
         } else {
-            if (j >= n_rays - 2) break;
+            if (j >= n_rays - 2) return false;
             ++j;
         }
     }
-    write_invalid(tb, out);
-    atomicAdd(lost, 1);
+    return false;
+}
+
+// Straight-ray guess of the quad holding the point at (ddx, ddy) from the source: launch
+// angle and arc length of the straight ray.
+__device__ __forceinline__ void straight_guess(double ddx, double ddy, double d, double psi,
+                                               double ds, int n_rays, int S, int &j, int &i) {
+    float rel = atan2f((float)ddy, (float)ddx) - (float)(psi + RB_PI);
+    rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
+    j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
+    j = min(max(j, 0), n_rays - 2);
+    i = min(max((int)(d / ds), 1), S - 2);
+}
+
+// One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
+// one transducer. The tile centre is walked first from its straight-ray guess; the offset
+// between the two (the bending of the rays, smooth over a tile) starts every node's walk.
+__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                     int e0, GridP g, double R, double psi0,
+                                                     int N, double ds, double c0, int n_mask,
+                                                     int tile_i0, int tile_j0, int tiles_x,
+                                                     const int32_t *__restrict__ qmap,
+                                                     rb_tables tb, int *lost) {
+    __shared__ int s_off[2];
+    const int el = blockIdx.y;
+    if (sb.folded[el]) return;  // general path (uniform over the block)
+    const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
+    const int e = e0 + el;
+    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const double xe = R * cos(psi), ye = R * sin(psi);
+    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
+    const size_t ebase = (size_t)el * S * n_rays;
+    if (threadIdx.x == 0) {
+        double cu = tile_i0 + ti * LT + 0.5 * (LT - 1), cv = tile_j0 + tj * LT + 0.5 * (LT - 1);
+        double ddx = g.x0 + cu * g.dx - xe, ddy = g.y0 + cv * g.dx - ye;
+        double d = sqrt(ddx * ddx + ddy * ddy);
+        int j, i, jw, iw;
+        straight_guess(ddx, ddy, d, psi, ds, n_rays, S, jw, iw);
+        j = jw;
+        i = iw;
+        size_t vb[3];
+        float lam[3];
+        bool ok = d >= 2.0 * ds && mesh_walk(sb, Mrow, ebase, n_rays, (float)cu, (float)cv, j,
+                                             i, vb, lam);
+        s_off[0] = ok ? j - jw : 0;
+        s_off[1] = ok ? i - iw : 0;
+    }
+    __syncthreads();
+    const int ii = tile_i0 + ti * LT + (threadIdx.x % LT);
+    const int jj = tile_j0 + tj * LT + (threadIdx.x / LT);
+    if (ii >= g.nx || jj >= g.ny) return;
+    const int q = qmap[(size_t)jj * g.nx + ii];
+    if (q < 0) return;
+    const size_t out = (size_t)e * n_mask + q;
+    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
+    double ddx = px - xe, ddy = py - ye;
+    double d = sqrt(ddx * ddx + ddy * ddy);
+    if (d < 2.0 * ds) {
+        write_invalid(tb, out);
+        return;
+    }
+    int j, i;
+    straight_guess(ddx, ddy, d, psi, ds, n_rays, S, j, i);
+    j = min(max(j + s_off[0], 0), n_rays - 2);
+    i = min(max(i + s_off[1], 1), S - 2);
+    size_t vb[3];
+    float lam[3];
+    if (mesh_walk(sb, Mrow, ebase, n_rays, (float)ii, (float)jj, j, i, vb, lam)) {
+        write_entry(sb, vb, lam, d, c0, tb, out);
+    } else {
+        write_invalid(tb, out);
+        atomicAdd(lost, 1);
+    }
 }
 
 __device__ __forceinline__ void raster_tri(const float *tu, const float *tv, const float *tdT,
