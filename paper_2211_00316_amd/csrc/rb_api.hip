@@ -153,8 +153,8 @@ rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
     }
     ctx->tile_i0 = imin;
     ctx->tile_j0 = jmin;
-    ctx->tiles_x = (imax - imin + 16) / 16;
-    ctx->tiles_y = (jmax - jmin + 16) / 16;
+    ctx->tiles_x = (imax - imin + 32) / 32;
+    ctx->tiles_y = (jmax - jmin + 8) / 8;
     ctx->grid = *g;
     ctx->n_mask = n;
     ctx->have_grid = true;

@@ -31,7 +31,7 @@ struct rb_ctx {
     int64_t n_mask = 0;
     int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
     int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
-    int tile_i0 = 0, tile_j0 = 0;     // 16 x 16 node tiles covering the mask's bounding box
+    int tile_i0 = 0, tile_j0 = 0;     // 32 x 8 node tiles covering the mask's bounding box
     int tiles_x = 0, tiles_y = 0;
 
     // per-stage event timing (rb_profile_enable / rb_profile_read)

@@ -114,7 +114,7 @@ struct Ray {
 // Paraxial right-hand side (Eq. ray-equation-paraxial with k -> n).
 __device__ __forceinline__ void paraxial_rhs(const Spline &s, float kx, float ky, float dxx,
                                              float dxy, float dkx, float dky, float q[4]) {
-    float n = s.v, in = 1.0f / n, in2 = in * in;
+    float n = s.v, in = __builtin_amdgcn_rcpf(n), in2 = in * in;
     float gdx = s.gx * dxx + s.gy * dxy;
     float kdk = kx * dkx + ky * dky;
     q[0] = -gdx * in2 * kx + dkx * in;
@@ -128,22 +128,22 @@ __device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const Gri
                                          const Spline &s1, const Ray &r, double h) {
     float hf = (float)h;
     float n = s1.v;
-    float kn = sqrtf(r.kx * r.kx + r.ky * r.ky);
-    float kx = n * r.kx / kn, ky = n * r.ky / kn;          // normalise the ray direction
-    float qxx = kx / n, qxy = ky / n;
+    float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
+    float qxx = r.kx * ikn, qxy = r.ky * ikn;               // unit ray direction
+    float kx = n * qxx, ky = n * qxy;                       // normalised wave vector
     float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
     double xp = r.x + h * (double)qxx, yp = r.y + h * (double)qxy;
     Spline s2 = spline_eval(ns, g, xp, yp);                 // auxiliary wavenumber
     float n2 = s2.v;
-    float kpn = sqrtf(kpx * kpx + kpy * kpy);
-    kpx = n2 * kpx / kpn;
-    kpy = n2 * kpy / kpn;
-    float qxx2 = kpx / n2, qxy2 = kpy / n2;
+    float ikpn = rsqrtf(kpx * kpx + kpy * kpy);
+    float qxx2 = kpx * ikpn, qxy2 = kpy * ikpn;
+    kpx = n2 * qxx2;
+    kpy = n2 * qxy2;
     float sx = qxx + qxx2, sy = qxy + qxy2;
-    float sn = sqrtf(sx * sx + sy * sy);
+    float isn = rsqrtf(sx * sx + sy * sy);
     Ray o;
-    o.x = r.x + h * (double)(sx / sn);                      // position along mean direction
-    o.y = r.y + h * (double)(sy / sn);
+    o.x = r.x + h * (double)(sx * isn);                     // position along mean direction
+    o.y = r.y + h * (double)(sy * isn);
     o.kx = kx + hf * (s1.gx + s2.gx) * 0.5f;
     o.ky = ky + hf * (s1.gy + s2.gy) * 0.5f;
     float a[4], b[4];
@@ -167,6 +167,7 @@ struct SampleBufs {
     float *ex_dT, *ex_L;
     uint8_t *ex_K;
     int32_t *folded;                   // [E] nonzero if a ray of the transducer met a caustic
+    const double2 *ring;               // [N] transducer positions
 };
 
 __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns, GridP g,
@@ -226,8 +227,8 @@ __global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns
         sc = spline_eval(ns, g, r.x, r.y);
         float n_new = sc.v;
         T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
-        float kn = sqrtf(r.kx * r.kx + r.ky * r.ky);
-        float tx = r.kx / kn, ty = r.ky / kn;
+        float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
+        float tx = r.kx * ikn, ty = r.ky * ikn;
         float J = r.dxx * (-ty) + r.dxy * tx;
         if (i >= 1 && J * J_prev < 0.0f) ++K;
         double d = sqrt((r.x - xe) * (r.x - xe) + (r.y - ye) * (r.y - ye));
@@ -320,7 +321,7 @@ __device__ __forceinline__ void write_invalid(const rb_tables &tb, size_t out) {
 // contains the point (pu, pv) (node-index units). Returns false if the walk leaves the
 // mesh or does not settle within LOCATE_MAX_IT quads.
 constexpr int LOCATE_MAX_IT = 96;
-constexpr int LT = 16;
+constexpr int LTX = 32, LTY = 8;  // node tile of one locate workgroup
 
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
                                           size_t ebase, int n_rays, float pu, float pv, int &j,
@@ -395,7 +396,7 @@ __device__ __forceinline__ void straight_guess(double ddx, double ddy, double d,
     i = min(max((int)(d / ds), 1), S - 2);
 }
 
-// One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
+// One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
 // one transducer. The tile centre is walked first from its straight-ray guess; the offset
 // between the two (the bending of the rays, smooth over a tile) starts every node's walk.
 __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
@@ -410,11 +411,12 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
     const int e = e0 + el;
     const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    const double xe = R * cos(psi), ye = R * sin(psi);
+    const double2 xy = sb.ring[e];
+    const double xe = xy.x, ye = xy.y;
     const int32_t *Mrow = sb.M + (size_t)el * n_rays;
     const size_t ebase = (size_t)el * S * n_rays;
     if (threadIdx.x == 0) {
-        double cu = tile_i0 + ti * LT + 0.5 * (LT - 1), cv = tile_j0 + tj * LT + 0.5 * (LT - 1);
+        double cu = tile_i0 + ti * LTX + 0.5 * (LTX - 1), cv = tile_j0 + tj * LTY + 0.5 * (LTY - 1);
         double ddx = g.x0 + cu * g.dx - xe, ddy = g.y0 + cv * g.dx - ye;
         double d = sqrt(ddx * ddx + ddy * ddy);
         int j, i, jw, iw;
@@ -429,8 +431,8 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
         s_off[1] = ok ? i - iw : 0;
     }
     __syncthreads();
-    const int ii = tile_i0 + ti * LT + (threadIdx.x % LT);
-    const int jj = tile_j0 + tj * LT + (threadIdx.x / LT);
+    const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
+    const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
     if (ii >= g.nx || jj >= g.ny) return;
     const int q = qmap[(size_t)jj * g.nx + ii];
     if (q < 0) return;
@@ -537,8 +539,8 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     unsigned long long key = keys[tid];
     int p = mask_index[q];
     int ii = p % g.nx, jj = p / g.nx;
-    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    double xe = R * cos(psi), ye = R * sin(psi);
+    const double2 xy = sb.ring[e];
+    double xe = xy.x, ye = xy.y;
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double d = sqrt((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
@@ -598,8 +600,8 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
         if (!(ok[j] && ok[j + 1] && beta[j + 1] > beta[j])) not_monotone = 1;
     __syncthreads();
     const bool mono = !not_monotone;
-    double psi_e = psi0 + RB_TWO_PI * (double)e / (double)N;
-    double xe = R * cos(psi_e), ye = R * sin(psi_e);
+    const double2 xy = sb.ring[e];
+    double xe = xy.x, ye = xy.y;
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
         size_t out = (size_t)e * N + r;
         int rel = ((r - e) % N + N) % N;
@@ -642,8 +644,8 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
             }
         }
         if (found) {
-            double psi_r = psi0 + RB_TWO_PI * (double)r / (double)N;
-            double xr = R * cos(psi_r), yr = R * sin(psi_r);
+            const double2 rr = sb.ring[r];
+            double xr = rr.x, yr = rr.y;
             double dist = sqrt((xr - xe) * (xr - xe) + (yr - ye) * (yr - ye));
             tb.rx_T[out] = best + dist / c0;
             tb.rx_A[out] = (float)(exp(bestL) / sqrt(dist));
@@ -681,6 +683,14 @@ __global__ void box_cols(const double *__restrict__ tmp, int nx, int ny, int w,
         acc += tmp[(size_t)k * nx + i];
     }
     out[(size_t)j * nx + i] = (float)(acc / w);
+}
+
+__global__ void ring_positions(double R, double psi0, int N, double2 *pos) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < N) {
+        double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+        pos[e] = make_double2(R * cos(psi), R * sin(psi));
+    }
 }
 
 __global__ void zero_i32(int32_t *x, int n) {
@@ -731,6 +741,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    rb_align((size_t)C * nr * sizeof(double)) +
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
                    rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
+                   rb_align((size_t)N * sizeof(double2)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long));
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
@@ -746,11 +757,16 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
     int32_t *lost = rb_carve<int32_t>(&ctx->ws, 2);
+    double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
+    sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
 
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
     RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
     RB_HIP(ctx, hipMemsetAsync(lost, 0, sizeof(int32_t), ctx->stream));
+    hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
+                       r->radius, r->psi0, N, ringpos);
+    RB_CHECK_LAUNCH(ctx);
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
         int nthreads = E * nr;
@@ -766,7 +782,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         // unfolded fans: direct walk per (transducer, node)
         size_t nk = (size_t)E * n_mask;
         rb_prof_begin(ctx, ST_RESOLVE);
-        hipLaunchKernelGGL(locate_kernel, dim3(ctx->tiles_x * ctx->tiles_y, E), dim3(LT * LT), 0,
+        hipLaunchKernelGGL(locate_kernel, dim3(ctx->tiles_x * ctx->tiles_y, E), dim3(LTX * LTY), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
                            tp->c0, n_mask, ctx->tile_i0, ctx->tile_j0, ctx->tiles_x,
                            ctx->d_qmap, *out, lost);
