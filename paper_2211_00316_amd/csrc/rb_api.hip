@@ -9,8 +9,8 @@
 #include <vector>
 
 rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq);
-rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0, float w,
-                               float *wv, float *delta);
+rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0,
+                               double w, float *sv);
 rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float *parts,
                                            const double *c_mask, double omega, double d_omega,
                                            double *dm_acc);
@@ -304,8 +304,9 @@ rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double 
     if (!finite_pos(omega) || !finite_pos(c0))
         return rb_fail(ctx, RB_EINVAL, "omega and c0 must be positive");
     RB_HIP(ctx, hipSetDevice(ctx->device));
-    if (out->prec != RB_F32) return rb_launch_green_lp(ctx, tb, omega, c0, out);
-    return rb_launch_green(ctx, tb, omega, c0, out);
+    if (out->prec != RB_F32)
+        return rb_launch_green_lp(ctx, tb, omega, c0, out, nullptr, nullptr, 1);
+    return rb_launch_green(ctx, tb, omega, c0, out, nullptr, nullptr, 1);
 }
 
 rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
@@ -314,8 +315,8 @@ rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const
     RB_TRY(check_green(ctx, gr));
     if (!w || !delta || !d) return rb_fail(ctx, RB_EINVAL, "w, delta and d must be non-NULL");
     RB_HIP(ctx, hipSetDevice(ctx->device));
-    if (gr->prec != RB_F32) return rb_launch_forward_lp(ctx, gr, w, delta, d);
-    return rb_launch_forward(ctx, gr, w, delta, d);
+    if (gr->prec != RB_F32) return rb_launch_forward_lp(ctx, gr, w, delta, d, nullptr);
+    return rb_launch_forward(ctx, gr, w, delta, d, nullptr);
 }
 
 rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const float *R,
@@ -439,7 +440,7 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NN);
     float *rscale = rb_carve<float>(a, 2);
     float *wv = rb_carve<float>(a, 2 * (size_t)nm);
-    float *delta = rb_carve<float>(a, nm);
+    float *svscale = rb_carve<float>(a, 2);
     double *cq = rb_carve<double>(a, nm);
     double *dm = rb_carve<double>(a, nm);
     double *c_new = rb_carve<double>(a, nm);
@@ -453,20 +454,27 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     if (residual_norm) RB_HIP(ctx, hipMemsetAsync(residual_norm, 0, sizeof(double), ctx->stream));
     for (int k = 0; k < n_omega; ++k) {
         const double om = omega[k];
-        // a4: Green's functions and back-projection operands
+        // a4: Green's functions and back-projection operands. In ray_born mode G is
+        // stored as G sqrt(v), v = omega^2 h^2 (m - m_s), so that a5 is the plain
+        // symmetric product; ray_only needs no G.
+        const bool born_term = mode == RB_RAY_BORN;
+        if (born_term) {
+            RB_TRY(rb_launch_rough_part(ctx, cq, n_s, tp->c0, om * om * grid->dx * grid->dx, wv));
+            // power-of-two scale that brings max |sqrt(v)| to [1, 2) (range of 16-bit types)
+            RB_TRY(rb_launch_range_scale(ctx, wv, (size_t)nm, 1, svscale));
+        }
+        const float *gs = born_term ? wv : nullptr;
         if (lp)
-            RB_TRY(rb_launch_green_lp(ctx, &tb, om, tp->c0, &gr));
+            RB_TRY(rb_launch_green_lp(ctx, &tb, om, tp->c0, &gr, gs, svscale, born_term));
         else
-            RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr));
+            RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr, gs, svscale, born_term));
         // a5-a6: predicted data (ray part + Born term of the rough part) and residual
         const float *born = nullptr;
-        if (mode == RB_RAY_BORN) {
-            RB_TRY(rb_launch_rough_part(ctx, cq, n_s, tp->c0, (float)(om * om * grid->dx * grid->dx),
-                                        wv, delta));
+        if (born_term) {
             if (lp)
-                RB_TRY(rb_launch_forward_lp(ctx, &gr, wv, delta, d_born));
+                RB_TRY(rb_launch_forward_lp(ctx, &gr, nullptr, nullptr, d_born, svscale));
             else
-                RB_TRY(rb_launch_forward(ctx, &gr, wv, delta, d_born));
+                RB_TRY(rb_launch_forward(ctx, &gr, nullptr, nullptr, d_born, svscale));
             born = d_born;
         }
         RB_TRY(rb_launch_residual(ctx, &tb, om, tp->c0, born, data + 2 * NN * (size_t)k, R,

@@ -216,10 +216,15 @@ __global__ void __launch_bounds__(256) forward_kernel(const float2 *__restrict__
                 int gk = k0 + kh + u;
                 float2 g = make_float2(0.f, 0.f);
                 if (gr < n && gk < kend) {
-                    float2 gv = src[u], wv = w[gk];
-                    float dl = delta[gk];
-                    float vr = wv.x * dl, vi = wv.y * dl;
-                    g = make_float2(gv.x * vr - gv.y * vi, gv.x * vi + gv.y * vr);
+                    float2 gv = src[u];
+                    if (w) {  // v = w delta (absent: the operand already carries it)
+                        float2 wv = w[gk];
+                        float dl = delta[gk];
+                        float vr = wv.x * dl, vi = wv.y * dl;
+                        g = make_float2(gv.x * vr - gv.y * vi, gv.x * vi + gv.y * vr);
+                    } else {
+                        g = gv;
+                    }
                 }
                 a_re[kh + u][lr] = g.x;
                 a_im[kh + u][lr] = g.y;
@@ -285,7 +290,7 @@ __global__ void __launch_bounds__(256) forward_kernel(const float2 *__restrict__
 // d[e][r] = d[r][e] = sum over splits of the partial at (min(e,r), max(e,r)), which lies in
 // a computed upper tile; both entries come from the same sums, so d is exactly symmetric.
 __global__ void forward_reduce(const float2 *__restrict__ dpart, int n, int splitk,
-                               float2 *__restrict__ d) {
+                               const float *__restrict__ gscale, float2 *__restrict__ d) {
     int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
     if (r >= n) return;
     size_t src = (e <= r) ? (size_t)e * n + r : (size_t)r * n + e;
@@ -295,7 +300,8 @@ __global__ void forward_reduce(const float2 *__restrict__ dpart, int n, int spli
         sr += v.x;
         si += v.y;
     }
-    d[(size_t)e * n + r] = make_float2(sr, si);
+    float inv = gscale ? gscale[1] * gscale[1] : 1.f;  // the operand carried sqrt(v) s
+    d[(size_t)e * n + r] = make_float2(sr * inv, si * inv);
 }
 
 }  // namespace
@@ -319,7 +325,7 @@ rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const
 }
 
 rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
-                            float *d) {
+                            float *d, const float *gscale) {
     const int n = gr->n, K = gr->n_mask;
     const int T = (n + FW_B - 1) / FW_B;
     const int tiles = T * (T + 1) / 2;
@@ -340,7 +346,7 @@ rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, con
     rb_prof_end(ctx);
     rb_prof_begin(ctx, ST_FORWARD_REDUCE);
     hipLaunchKernelGGL(forward_reduce, dim3((n + 255) / 256, n), dim3(256), 0, ctx->stream, dpart,
-                       n, splitk, (float2 *)d);
+                       n, splitk, gscale, (float2 *)d);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;

@@ -19,8 +19,12 @@ __device__ __forceinline__ double reduce_phase(double ph) {
 }
 
 // One thread per (transducer e, mask node q); grid.y = e.
+// gs (nullable): per-node complex factor applied to G (the frequency step stores
+// G sqrt(v), so that the Born term is the plain symmetric product); write_g = 0 skips G.
 __global__ void __launch_bounds__(256) green_kernel(rb_tables tb, int N, int n_mask,
                                                     double omega, double c0,
+                                                    const float2 *__restrict__ gs,
+                                                    const float *__restrict__ gscale, int write_g,
                                                     float2 *__restrict__ G,
                                                     float2 *__restrict__ H) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,7 +34,7 @@ __global__ void __launch_bounds__(256) green_kernel(rb_tables tb, int N, int n_m
     size_t plane = (size_t)N * n_mask;
     uint8_t f = tb.flags[o];
     if (!(f & 0x80)) {
-        G[o] = make_float2(0.f, 0.f);
+        if (write_g) G[o] = make_float2(0.f, 0.f);
         H[o] = make_float2(0.f, 0.f);
         H[plane + o] = make_float2(0.f, 0.f);
         H[2 * plane + o] = make_float2(0.f, 0.f);
@@ -43,7 +47,17 @@ __global__ void __launch_bounds__(256) green_kernel(rb_tables tb, int N, int n_m
     float A = tb.A[o];
     float sk = (float)sqrt(k0);
     float ga = A / sk;
-    G[o] = make_float2(ga * c, ga * s);
+    if (write_g) {
+        float gr = ga * c, gi = ga * s;
+        if (gs) {
+            float2 f2 = gs[q];
+            float sc = gscale[0];
+            float tr = (gr * f2.x - gi * f2.y) * sc;
+            gi = (gr * f2.y + gi * f2.x) * sc;
+            gr = tr;
+        }
+        G[o] = make_float2(gr, gi);
+    }
 
     // angular weight: angle between the ray directions of the neighbouring transducers
     int em = (e + N - 1) % N, ep = (e + 1) % N;
@@ -139,17 +153,20 @@ __global__ void gather_mask(const double *__restrict__ c, const int32_t *__restr
     if (q < n_mask) cq[q] = c[mask_index[q]];
 }
 
-// w = omega^2 h^2 (complex, imaginary part 0) and delta = m - m_s at the mask nodes, where
-// m_s = (n_s / c0)^2 is the squared slowness of the smoothed map the rays were traced on.
+// sv = sqrt(w delta) at the mask nodes (complex: i sqrt(w |delta|) for delta < 0), with
+// w = omega^2 h^2 and delta = m - m_s, where m_s = (n_s / c0)^2 is the squared slowness of
+// the smoothed map the rays were traced on. Then sum_q G[e,q] v[q] G[r,q] with v = w delta
+// is the symmetric product of G sv with itself.
 __global__ void rough_part(const double *__restrict__ cq, const float *__restrict__ n_s,
                            const int32_t *__restrict__ mask_index, int n_mask, double c0,
-                           float w, float2 *__restrict__ wv, float *__restrict__ delta) {
+                           double w, float2 *__restrict__ sv) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_mask) return;
     double c = cq[q];
     double ns = (double)n_s[mask_index[q]];
-    delta[q] = (float)(1.0 / (c * c) - ns * ns / (c0 * c0));
-    wv[q] = make_float2(w, 0.f);
+    double v = w * (1.0 / (c * c) - ns * ns / (c0 * c0));
+    float r = (float)sqrt(fabs(v));
+    sv[q] = v >= 0.0 ? make_float2(r, 0.f) : make_float2(0.f, r);
 }
 
 // m <- m + tau dm (FP64); the candidate c is kept aside until every value is finite.
@@ -181,11 +198,13 @@ inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
-                          const rb_green *out) {
+                          const rb_green *out, const float *gs, const float *gscale,
+                          int write_g) {
     dim3 grd(blocks(tb->n_mask), tb->n);
     rb_prof_begin(ctx, ST_GREEN);
     hipLaunchKernelGGL(green_kernel, grd, dim3(256), 0, ctx->stream, *tb, tb->n, tb->n_mask, omega,
-                       c0, (float2 *)out->G, (float2 *)out->H);
+                       c0, (const float2 *)gs, gscale, write_g, (float2 *)out->G,
+                       (float2 *)out->H);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -235,11 +254,11 @@ rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq) {
     return RB_OK;
 }
 
-rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0, float w,
-                               float *wv, float *delta) {
+rb_status rb_launch_rough_part(rb_ctx *ctx, const double *cq, const float *n_s, double c0,
+                               double w, float *sv) {
     int n = (int)ctx->n_mask;
     hipLaunchKernelGGL(rough_part, dim3(blocks(n)), dim3(256), 0, ctx->stream, cq, n_s,
-                       ctx->d_mask_index, n, c0, w, (float2 *)wv, delta);
+                       ctx->d_mask_index, n, c0, w, (float2 *)sv);
     RB_CHECK_LAUNCH(ctx);
     return RB_OK;
 }

@@ -91,13 +91,18 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
                                      int w, float *n_s);
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out);
+// gs (nullable): complex per-node factor on G; write_g = 0 leaves G unwritten.
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
-                          const rb_green *out);
+                          const rb_green *out, const float *gs, const float *gscale,
+                          int write_g);
 rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const float *d_born, const float *data, float *R,
                              double *residual_norm);
+// w, delta nullable together: then v = 1 (the operand already carries the node weights).
+// gscale (nullable, device): the operand carries sqrt(v) gscale[0]; d is divided by
+// gscale[0]^2 (multiplied by gscale[1]^2).
 rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
-                            float *d);
+                            float *d, const float *gscale);
 // Row-reduced complex GEMM: parts[2][mblocks][n_mask] (re, im) of
 // sum_e E_c[e][q] (R B_c)[e][q] summed over the n_comp components c.
 rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const float *B,
@@ -111,7 +116,8 @@ int rb_rowred_mblocks(int n);
 
 // Reduced-precision (BF16 / FP16 operand) form: layouts in rb_lowp.hip.
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
-                             const rb_green *out);
+                             const rb_green *out, const float *gs, const float *gscale,
+                             int write_g);
 // R -> planar 16-bit, scaled by a power of two kept in scale[0..1] (device, 2 floats).
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
                               float *scale);
@@ -119,5 +125,7 @@ rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
-                               const float *delta, float *d);
+                               const float *delta, float *d, const float *gscale);
+// scale[0] = 2^(top - e), scale[1] = 1 / scale[0] with 2^(e-1) <= max |x| < 2^e (complex x).
+rb_status rb_launch_range_scale(rb_ctx *ctx, const float *x, size_t count, int top, float *scale);
 int rb_rowred_lp_mblocks(int n);

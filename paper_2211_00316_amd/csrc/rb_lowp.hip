@@ -63,11 +63,15 @@ constexpr int GE = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
-                                                       double omega, double c0, T *__restrict__ Gp,
+                                                       double omega, double c0,
+                                                       const float2 *__restrict__ gs,
+                                                       const float *__restrict__ gscale,
+                                                       int write_g, T *__restrict__ Gp,
                                                        T *__restrict__ Ht) {
     __shared__ float s_ux[GE + 2][GQ], s_uy[GE + 2][GQ];
     __shared__ uint8_t s_f[GE + 2][GQ];
-    __shared__ __attribute__((aligned(16))) T s_h[3][2][GQ][GE + 8];
+    // rows of GE + 2 values (17 dwords): lanes writing one column hit distinct banks
+    __shared__ __attribute__((aligned(16))) T s_h[3][2][GQ][GE + 2];
     const int q0 = blockIdx.x * GQ, e0 = blockIdx.y * GE;
     const int tid = threadIdx.x, tq = tid & 63, tr = tid >> 6;
     const int q = q0 + tq;
@@ -124,8 +128,17 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
                 hr = ha * c;
                 hi = -ha * s;
             }
-            Gp[o] = to_lp<T>(gr);
-            Gp[gplane + o] = to_lp<T>(gi);
+            if (write_g) {
+                if (gs) {
+                    float2 f2 = gs[q];
+                    float sc = gscale[0];
+                    float tr = (gr * f2.x - gi * f2.y) * sc;
+                    gi = (gr * f2.y + gi * f2.x) * sc;
+                    gr = tr;
+                }
+                Gp[o] = to_lp<T>(gr);
+                Gp[gplane + o] = to_lp<T>(gi);
+            }
         }
         s_h[0][0][tq][r] = to_lp<T>(hr);
         s_h[0][1][tq][r] = to_lp<T>(hi);
@@ -145,22 +158,23 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         int gq = q0 + qq, ge = e0 + chunk * 8;
         if (gq >= n_mask) continue;
         T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * N + ge;
-        const T *src = &s_h[c][part][qq][chunk * 8];
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&s_h[c][part][qq][chunk * 8]);
         if (ge + 7 < N && ((N & 7) == 0)) {
-            *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+            *reinterpret_cast<uint4 *>(dst) = make_uint4(src[0], src[1], src[2], src[3]);
         } else {
+            const T *sv = &s_h[c][part][qq][chunk * 8];
             for (int u = 0; u < 8; ++u)
-                if (ge + u < N) dst[u] = src[u];
+                if (ge + u < N) dst[u] = sv[u];
         }
     }
 }
 
-// Power-of-two range scale of an operand: scale[0] = 2^(14 - e) and scale[1] = 1/scale[0]
-// with 2^(e-1) <= max |x| < 2^e, so the largest scaled magnitude lies in [2^13, 2^14)
-// (inside the FP16 range, far from its subnormals). One block; exact (powers of two).
+// Power-of-two range scale of an operand: scale[0] = 2^(top - e) and scale[1] = 1/scale[0]
+// with 2^(e-1) <= max |x| < 2^e, so the largest scaled magnitude lies in [2^(top-1), 2^top)
+// (top = 14: inside the FP16 range, far from its subnormals). One block; exact.
 __global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restrict__ x,
                                                            size_t count, const float *__restrict__ y,
-                                                           float *__restrict__ scale) {
+                                                           int top, float *__restrict__ scale) {
     __shared__ float red[16];
     float m = 0.f;
     for (size_t i = threadIdx.x; i < count; i += blockDim.x) {
@@ -177,7 +191,7 @@ __global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restr
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mm = fmaxf(mm, red[i]);
         int e = 0;
         if (mm > 0.f && isfinite(mm)) frexpf(mm, &e);
-        float s = ldexpf(1.f, 14 - e);
+        float s = ldexpf(1.f, top - e);
         scale[0] = s;
         scale[1] = 1.f / s;
     }
@@ -194,6 +208,12 @@ __global__ void to_planar_kernel(const float2 *__restrict__ src, int n,
     float2 v = src[i];
     dst[i] = to_lp<T>(v.x * s);
     dst[nn + i] = to_lp<T>(v.y * s);
+}
+
+__global__ void square_scale_kernel(const float *__restrict__ g, float *scale) {
+    float inv = g ? g[1] : 1.f;
+    scale[0] = 1.f;
+    scale[1] = inv * inv;
 }
 
 // parts *= scale[1] (undo the residual's range scale before the final sum)
@@ -433,19 +453,21 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
             int ch = idx & 3, row = idx >> 2;
             int gk = k0 + ch * 8;
             int ge = row0 + row, gr = col0 + row;
-            // v = w delta for the 8 node indices of this chunk
+            // v = w delta for the 8 node indices of this chunk (absent: G carries it)
             float vr[8], vi[8];
+            if (w) {
 #pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                int k = gk + z;
-                float2 wv = make_float2(0.f, 0.f);
-                float dl = 0.f;
-                if (k < kend) {
-                    wv = w[k];
-                    dl = delta[k] * vs;
+                for (int z = 0; z < 8; ++z) {
+                    int k = gk + z;
+                    float2 wv = make_float2(0.f, 0.f);
+                    float dl = 0.f;
+                    if (k < kend) {
+                        wv = w[k];
+                        dl = delta[k] * vs;
+                    }
+                    vr[z] = wv.x * dl;
+                    vi[z] = wv.y * dl;
                 }
-                vr[z] = wv.x * dl;
-                vi[z] = wv.y * dl;
             }
             // 8 consecutive K of one row of G (both parts), zero beyond the chunk end
             auto row8 = [&](int grow, T *re, T *im) {
@@ -467,11 +489,13 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
             row8(ge, ar, ai);
             row8(gr, br, bi);
             // A = G v, complex product in FP32 rounded once to the operand type
+            if (w) {
 #pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                float gre = from_lp<T>(ar[z]), gim = from_lp<T>(ai[z]);
-                ar[z] = to_lp<T>(gre * vr[z] - gim * vi[z]);
-                ai[z] = to_lp<T>(gre * vi[z] + gim * vr[z]);
+                for (int z = 0; z < 8; ++z) {
+                    float gre = from_lp<T>(ar[z]), gim = from_lp<T>(ai[z]);
+                    ar[z] = to_lp<T>(gre * vr[z] - gim * vi[z]);
+                    ai[z] = to_lp<T>(gre * vi[z] + gim * vr[z]);
+                }
             }
             *reinterpret_cast<uint4 *>(&a_s[0][row][ch * 8]) = __builtin_bit_cast(uint4, ar);
             *reinterpret_cast<uint4 *>(&a_s[1][row][ch * 8]) = __builtin_bit_cast(uint4, ai);
@@ -546,15 +570,18 @@ __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int s
 
 // Launchers ------------------------------------------------------------------------------
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
-                             const rb_green *out) {
+                             const rb_green *out, const float *gs, const float *gscale,
+                             int write_g) {
     dim3 grd((tb->n_mask + GQ - 1) / GQ, (tb->n + GE - 1) / GE);
     rb_prof_begin(ctx, ST_GREEN);
     if (out->prec == RB_BF16)
         hipLaunchKernelGGL(green_lp_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
-                           tb->n_mask, omega, c0, (__bf16 *)out->G, (__bf16 *)out->H);
+                           tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
+                           (__bf16 *)out->G, (__bf16 *)out->H);
     else
         hipLaunchKernelGGL(green_lp_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
-                           tb->n_mask, omega, c0, (_Float16 *)out->G, (_Float16 *)out->H);
+                           tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
+                           (_Float16 *)out->G, (_Float16 *)out->H);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -565,7 +592,7 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
     size_t nn = (size_t)n * n;
     rb_prof_begin(ctx, ST_RESIDUAL);
     hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
-                       (const float2 *)R, nn, (const float *)nullptr, scale);
+                       (const float2 *)R, nn, (const float *)nullptr, 14, scale);
     RB_CHECK_LAUNCH(ctx);
     dim3 grd((unsigned)((nn + 255) / 256));
     if (prec == RB_BF16)
@@ -576,6 +603,13 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
                            (const float2 *)R, n, scale, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_range_scale(rb_ctx *ctx, const float *x, size_t count, int top, float *scale) {
+    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream, (const float2 *)x,
+                       count, (const float *)nullptr, top, scale);
+    RB_CHECK_LAUNCH(ctx);
     return RB_OK;
 }
 
@@ -610,7 +644,7 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
 }
 
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
-                               const float *delta, float *d) {
+                               const float *delta, float *d, const float *gscale) {
     const int n = gr->n, K = gr->n_mask;
     const int nT = (n + LF_B - 1) / LF_B;
     const int tiles = nT * (nT + 1) / 2;
@@ -626,9 +660,14 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     float2 *dpart = rb_carve<float2>(&ctx->ws, (size_t)splitk * n * n);
     float *vscale = rb_carve<float>(&ctx->ws, 2);
     rb_prof_begin(ctx, ST_FORWARD);
-    // range scale of v = w delta (the node weights are folded into the A operand)
-    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
-                       (const float2 *)w, (size_t)K, delta, vscale);
+    if (w) {
+        // range scale of v = w delta (the node weights are folded into the A operand)
+        hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
+                           (const float2 *)w, (size_t)K, delta, 14, vscale);
+    } else {
+        // G already carries sqrt(v) s: undo s^2 (or nothing) in the reduction
+        hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale, vscale);
+    }
     RB_CHECK_LAUNCH(ctx);
     if (gr->prec == RB_BF16)
         hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(tiles, splitk), dim3(256), 0,

@@ -403,12 +403,19 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
                                                      int tile_i0, int tile_j0, int tiles_x,
-                                                     const int32_t *__restrict__ qmap,
+                                                     int tiles_y, const int32_t *__restrict__ qmap,
                                                      rb_tables tb, int *lost) {
     __shared__ int s_off[2];
     const int el = blockIdx.y;
     if (sb.folded[el]) return;  // general path (uniform over the block)
-    const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
+    // Workgroups are dealt to the 8 XCDs round robin (id mod 8); give each XCD one
+    // contiguous band of tiles so that the part of the ray mesh it walks stays in its L2.
+    // (the grid is padded to a multiple of 8, so this is a bijection onto 0 .. grid-1)
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = gridDim.x / 8;
+    const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const int ti = t % tiles_x, tj = t / tiles_x;
     const int e = e0 + el;
     const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
     const double2 xy = sb.ring[e];
@@ -782,10 +789,11 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         // unfolded fans: direct walk per (transducer, node)
         size_t nk = (size_t)E * n_mask;
         rb_prof_begin(ctx, ST_RESOLVE);
-        hipLaunchKernelGGL(locate_kernel, dim3(ctx->tiles_x * ctx->tiles_y, E), dim3(LTX * LTY), 0,
+        int ntiles = ctx->tiles_x * ctx->tiles_y;
+        hipLaunchKernelGGL(locate_kernel, dim3(((ntiles + 7) / 8) * 8, E), dim3(LTX * LTY), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
                            tp->c0, n_mask, ctx->tile_i0, ctx->tile_j0, ctx->tiles_x,
-                           ctx->d_qmap, *out, lost);
+                           ctx->tiles_y, ctx->d_qmap, *out, lost);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation and resolve
