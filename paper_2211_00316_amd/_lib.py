@@ -158,7 +158,8 @@ class Green:
     """Device tensors of rb_green.
 
     RB_F32: G complex64 [n][n_mask], H complex64 [3][n][n_mask].
-    RB_BF16 / RB_F16: G planar [2][n][n_mask], H planar node-major [3][2][n_mask][n]."""
+    RB_BF16 / RB_F16: G planar [2][n][n_mask], H planar node-major [3][2][n_mask][n_pad]
+    (n_pad = n rounded up to 8)."""
 
     G: torch.Tensor
     H: torch.Tensor
@@ -170,8 +171,9 @@ class Green:
             return cls(torch.empty(n, n_mask, dtype=torch.complex64, device=device),
                        torch.empty(3, n, n_mask, dtype=torch.complex64, device=device), prec)
         dt = _LP_DTYPE[prec]
+        n_pad = (n + 7) // 8 * 8
         return cls(torch.empty(2, n, n_mask, dtype=dt, device=device),
-                   torch.empty(3, 2, n_mask, n, dtype=dt, device=device), prec)
+                   torch.empty(3, 2, n_mask, n_pad, dtype=dt, device=device), prec)
 
     @property
     def n(self):
@@ -191,7 +193,9 @@ class Green:
         """H, H u_x, H u_y as complex [3][n][n_mask], for checks."""
         if self.prec == RB_F32:
             return self.H
-        return torch.complex(self.H[:, 0].float(), self.H[:, 1].float()).transpose(1, 2)
+        n = self.n
+        return torch.complex(self.H[:, 0, :, :n].float(),
+                             self.H[:, 1, :, :n].float()).transpose(1, 2)
 
     def struct(self):
         return _Green(self.n, self.n_mask, self.prec, self.G.data_ptr(), self.H.data_ptr())

@@ -359,11 +359,12 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
     int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
     size_t nn = (size_t)gr->n * gr->n;
     ctx->ws.used = 0;
+    const size_t nnp = (size_t)gr->n * ((gr->n + 7) & ~7);
     RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
-                                               rb_align(2 * nn * sizeof(uint16_t)) + rb_align(8)));
+                                               rb_align(2 * nnp * sizeof(uint16_t)) + rb_align(8)));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
     if (lp) {
-        uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nn);
+        uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nnp);
         float *rscale = rb_carve<float>(&ctx->ws, 2);
         RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
         RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb));
@@ -405,12 +406,14 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     const int nm = (int)ctx->n_mask;
     const size_t P = (size_t)grid->nx * grid->ny;
     const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
+    const size_t NPp = (size_t)((N + 7) & ~7) * nm;  // padded operand rows (16-bit form)
+    const size_t NNp = (size_t)((N + 7) & ~7) * N;
     const bool lp = prec != RB_F32;
     const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand
     size_t bytes = rb_align(P * 4) + rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP) +
                    rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
-                   rb_align(3 * NP * opb) + 2 * rb_align(NN * 8) + rb_align(NN * 4) +
+                   rb_align(3 * NPp * opb) + 2 * rb_align(NN * 8) + rb_align(NNp * 4) +
                    rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
                    3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
                    rb_align(8);
@@ -434,10 +437,10 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     gr.n_mask = nm;
     gr.prec = prec;
     gr.G = rb_carve<char>(a, NP * opb);
-    gr.H = rb_carve<char>(a, 3 * NP * opb);
+    gr.H = rb_carve<char>(a, 3 * (lp ? NPp : NP) * opb);
     float *d_born = rb_carve<float>(a, 2 * NN);
     float *R = rb_carve<float>(a, 2 * NN);
-    uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NN);
+    uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NNp);
     float *rscale = rb_carve<float>(a, 2);
     float *wv = rb_carve<float>(a, 2 * (size_t)nm);
     float *svscale = rb_carve<float>(a, 2);

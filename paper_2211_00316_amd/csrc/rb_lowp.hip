@@ -10,9 +10,11 @@
 // Layouts (planar re / im, so that one 16-byte load gives 8 consecutive K of one part):
 //   Gp  [2][N][P_m]      G rows (transducer-major, node-contiguous): the forward operator
 //                        d = G diag(v) G^T contracts over nodes, K-contiguous for both sides;
-//   Ht  [3][2][P_m][N]   H, H u_x, H u_y transposed (node-major, transducer-contiguous): the
+//   Ht  [3][2][P_m][Np]  H, H u_x, H u_y transposed (node-major, transducer-contiguous): the
 //                        back-projection Y_c = R H_c contracts over transducers;
-//   Rp  [2][N][N]        residual rows.
+//   Rp  [2][N][Np]       residual rows.
+// Np = N rounded up to a multiple of 8 (zeros beyond N), so that every operand row starts
+// 16-byte aligned and the contraction loads only full 16-byte chunks.
 // The green kernel transposes H through LDS so that both layouts are written coalesced.
 #include "rb_internal.h"
 
@@ -148,24 +150,20 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         s_h[2][1][tq][r] = to_lp<T>(hi * uy);
     }
     __syncthreads();
-    // transposed store: rows (c, part, q) of GE transducers, 16 bytes (8 values) per store
-    const size_t hplane = (size_t)n_mask * N;
+    // transposed store: rows (c, part, q) of GE transducers, 16 bytes (8 values) per store;
+    // rows are Np long (zeros past N, written by the tile that holds them)
+    const int Np = (N + 7) & ~7;
+    const size_t hplane = (size_t)n_mask * Np;
     constexpr int CH = GE / 8;
     for (int idx = tid; idx < 3 * 2 * GQ * CH; idx += 256) {
         int chunk = idx % CH, row = idx / CH;
         int qq = row % GQ, cp = row / GQ;
         int c = cp >> 1, part = cp & 1;
         int gq = q0 + qq, ge = e0 + chunk * 8;
-        if (gq >= n_mask) continue;
-        T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * N + ge;
+        if (gq >= n_mask || ge >= Np) continue;
+        T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * Np + ge;
         const uint32_t *src = reinterpret_cast<const uint32_t *>(&s_h[c][part][qq][chunk * 8]);
-        if (ge + 7 < N && ((N & 7) == 0)) {
-            *reinterpret_cast<uint4 *>(dst) = make_uint4(src[0], src[1], src[2], src[3]);
-        } else {
-            const T *sv = &s_h[c][part][qq][chunk * 8];
-            for (int u = 0; u < 8; ++u)
-                if (ge + u < N) dst[u] = sv[u];
-        }
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(src[0], src[1], src[2], src[3]);
     }
 }
 
@@ -197,15 +195,17 @@ __global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restr
     }
 }
 
-// complex64 [n][n] -> planar T [2][n][n], multiplied by scale[0]
+// complex64 [n][n] -> planar T [2][n][np] (np = n rounded up to 8, zero padded),
+// multiplied by scale[0]
 template <typename T>
-__global__ void to_planar_kernel(const float2 *__restrict__ src, int n,
+__global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np,
                                  const float *__restrict__ scale, T *__restrict__ dst) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t nn = (size_t)n * n;
+    size_t nn = (size_t)n * np;
     if (i >= nn) return;
+    int row = (int)(i / np), col = (int)(i - (size_t)row * np);
     float s = scale[0];
-    float2 v = src[i];
+    float2 v = col < n ? src[(size_t)row * n + col] : make_float2(0.f, 0.f);
     dst[i] = to_lp<T>(v.x * s);
     dst[nn + i] = to_lp<T>(v.y * s);
 }
@@ -224,16 +224,20 @@ __global__ void unscale_kernel(float *__restrict__ parts, size_t count,
 }
 
 // Back-projection: Y_c = R H_c, epilogue sums over the tile's rows of H_c[e][q] Y_c[e][q] --
-constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_PAD = 8, LR_LD = LR_BK + LR_PAD;
+// Workgroup tile 256 (transducers e) x 128 (nodes q), four waves of 128 x 64 complex (eight
+// 32 x 32 MFMA tiles, 256 FP32 accumulators per lane). K (transducers r) in steps of 32,
+// double-buffered in LDS with one barrier per step; the next step's operands are fetched
+// into registers while the current one is multiplied.
+constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_LD = LR_BK + 8;
 
 template <typename T>
-__global__ void __launch_bounds__(512) rowred_lp_kernel(const T *__restrict__ Rp,
+__global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp,
                                                         const T *__restrict__ Ht, int n,
                                                         int n_cols, int n_comp, int mblocks,
                                                         int nblocks, float *__restrict__ parts) {
-    __shared__ __attribute__((aligned(16))) T a_s[2][LR_BM][LR_LD];
-    __shared__ __attribute__((aligned(16))) T b_s[2][LR_BN][LR_LD];
-    __shared__ float red[2][4][LR_BN];
+    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_BM][LR_LD];
+    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BN][LR_LD];
+    __shared__ float red[2][2][LR_BN];
 
     const int total = mblocks * nblocks;
     const int per_xcd = (total + 7) / 8;
@@ -243,21 +247,31 @@ __global__ void __launch_bounds__(512) rowred_lp_kernel(const T *__restrict__ Rp
     const int nb = t / mblocks, mb = t - nb * mblocks;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 waves, 64 x 64 each
+    const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 64
     const int row0 = mb * LR_BM, col0 = nb * LR_BN;
-    const size_t rplane = (size_t)n * n;
-    const size_t hplane = (size_t)n_cols * n;
-    const bool kvec = (n % 8) == 0;
+    const int np = (n + 7) & ~7;  // padded row length (zeros past n)
+    const size_t rplane = (size_t)n * np;
+    const size_t hplane = (size_t)n_cols * np;
+    const int KT = (np + LR_BK - 1) / LR_BK;
 
     float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
 
-    // loader assignment: A tile 256 rows x 2 parts x 4 chunks of 8 -> 2048 chunks, 4 each;
-    // B tile 128 rows x 2 parts x 4 chunks -> 1024 chunks, 2 each.
+    // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row
+    // (tid >> 3) + 32 u; A rows u = 0..7, B rows u = 0..3.
+    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
+    const T *a_src = Rp + l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8;
+    const size_t a_step = (size_t)32 * np;
+    uint32_t a_ok = 0, b_ok = 0;  // rows inside the matrix
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a_ok |= (row0 + l_row + 32 * u < n) ? (1u << u) : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) b_ok |= (col0 + l_row + 32 * u < n_cols) ? (1u << u) : 0u;
+
     for (int c = 0; c < n_comp; ++c) {
         const T *Hc = Ht + (size_t)(2 * c) * hplane;
-        floatx16 acc_re[2][2], acc_im[2][2];
+        floatx16 acc_re[4][2], acc_im[4][2];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
@@ -265,117 +279,96 @@ __global__ void __launch_bounds__(512) rowred_lp_kernel(const T *__restrict__ Rp
                     acc_re[mt][nt][i] = 0.f;
                     acc_im[mt][nt][i] = 0.f;
                 }
-        uint4 ra[4], rb[2];
-        auto load = [&](int k0) {
+        // A: 256 rows x 2 parts x 4 chunks (8 per thread); B: 128 x 2 x 4 (4 per thread)
+        const T *b_src = Hc + l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8;
+        uint4 ra[8], rb[4];
+        auto fetch = [&](int kt) {
+            const int k0 = kt * LR_BK;
+            const bool kin = k0 + l_ch * 8 < np;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int idx = tid + u * 512;
-                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
-                int gr = row0 + row, gk = k0 + ch * 8;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (gr < n) {
-                    const T *src = Rp + part * rplane + (size_t)gr * n + gk;
-                    if (kvec && gk + 7 < n) {
-                        v = *reinterpret_cast<const uint4 *>(src);
-                    } else {
-                        T tmp[8];
+            for (int u = 0; u < 8; ++u)
+                ra[u] = (kin && (a_ok >> u & 1u))
+                            ? *reinterpret_cast<const uint4 *>(a_src + u * a_step + k0)
+                            : make_uint4(0, 0, 0, 0);
 #pragma unroll
-                        for (int z = 0; z < 8; ++z) tmp[z] = (gk + z < n) ? src[z] : to_lp<T>(0.f);
-                        v = __builtin_bit_cast(uint4, tmp);
-                    }
-                }
-                ra[u] = v;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                int idx = tid + u * 512;
-                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
-                int gq = col0 + row, gk = k0 + ch * 8;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (gq < n_cols) {
-                    const T *src = Hc + part * hplane + (size_t)gq * n + gk;
-                    if (kvec && gk + 7 < n) {
-                        v = *reinterpret_cast<const uint4 *>(src);
-                    } else {
-                        T tmp[8];
-#pragma unroll
-                        for (int z = 0; z < 8; ++z) tmp[z] = (gk + z < n) ? src[z] : to_lp<T>(0.f);
-                        v = __builtin_bit_cast(uint4, tmp);
-                    }
-                }
-                rb[u] = v;
-            }
+            for (int u = 0; u < 4; ++u)
+                rb[u] = (kin && (b_ok >> u & 1u))
+                            ? *reinterpret_cast<const uint4 *>(b_src + (size_t)u * 32 * np + k0)
+                            : make_uint4(0, 0, 0, 0);
         };
-        load(0);
-        for (int k0 = 0; k0 < n; k0 += LR_BK) {
+        auto stash = [&](int buf) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int idx = tid + u * 512;
-                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
-                *reinterpret_cast<uint4 *>(&a_s[part][row][ch * 8]) = ra[u];
-            }
+            for (int u = 0; u < 8; ++u)
+                *reinterpret_cast<uint4 *>(&a_s[buf][l_part][l_row + 32 * u][l_ch * 8]) = ra[u];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                int idx = tid + u * 512;
-                int ch = idx & 3, part = (idx >> 2) & 1, row = idx >> 3;
-                *reinterpret_cast<uint4 *>(&b_s[part][row][ch * 8]) = rb[u];
-            }
-            __syncthreads();
-            if (k0 + LR_BK < n) load(k0 + LR_BK);
-#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                *reinterpret_cast<uint4 *>(&b_s[buf][l_part][l_row + 32 * u][l_ch * 8]) = rb[u];
+        };
+        fetch(0);
+        stash(0);
+        if (KT > 1) fetch(1);
+        __syncthreads();
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = kt & 1;
+#pragma unroll 1
             for (int ks = 0; ks < LR_BK; ks += 16) {
                 int kk = ks + (lane >> 5) * 8;
-                uint4 ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    int m = wm * 64 + mt * 32 + (lane & 31);
-                    ar[mt] = *reinterpret_cast<const uint4 *>(&a_s[0][m][kk]);
-                    ai[mt] = *reinterpret_cast<const uint4 *>(&a_s[1][m][kk]);
-                    nai[mt] = neg8(ai[mt]);
-                }
+                uint4 br[2], bi[2];
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
                     int cn = wn * 64 + nt * 32 + (lane & 31);
-                    br[nt] = *reinterpret_cast<const uint4 *>(&b_s[0][cn][kk]);
-                    bi[nt] = *reinterpret_cast<const uint4 *>(&b_s[1][cn][kk]);
+                    br[nt] = *reinterpret_cast<const uint4 *>(&b_s[cur][0][cn][kk]);
+                    bi[nt] = *reinterpret_cast<const uint4 *>(&b_s[cur][1][cn][kk]);
                 }
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt)
+                for (int mt = 0; mt < 4; ++mt) {
+                    int m = wm * 128 + mt * 32 + (lane & 31);
+                    uint4 ar = *reinterpret_cast<const uint4 *>(&a_s[cur][0][m][kk]);
+                    uint4 ai = *reinterpret_cast<const uint4 *>(&a_s[cur][1][m][kk]);
+                    uint4 nai = neg8(ai);
 #pragma unroll
                     for (int nt = 0; nt < 2; ++nt) {
-                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(br[nt]),
+                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(ar), as_vec<T>(br[nt]),
                                                      acc_re[mt][nt]);
-                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(nai[mt]), as_vec<T>(bi[nt]),
+                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(nai), as_vec<T>(bi[nt]),
                                                      acc_re[mt][nt]);
-                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ar[mt]), as_vec<T>(bi[nt]),
+                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ar), as_vec<T>(bi[nt]),
                                                      acc_im[mt][nt]);
-                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ai[mt]), as_vec<T>(br[nt]),
+                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ai), as_vec<T>(br[nt]),
                                                      acc_im[mt][nt]);
                     }
+                }
             }
+            if (kt + 1 < KT) stash(cur ^ 1);   // tile kt+1 into the idle buffer
+            if (kt + 2 < KT) fetch(kt + 2);    // tile kt+2 into registers
             __syncthreads();
         }
-        // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows per register group
+        // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
+        // 8-byte load per part (rows are padded with zeros to np, a multiple of 8, and
+        // rows beyond n carry Y = 0)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
             if (gq >= n_cols) continue;
-            const T *er_row = Hc + (size_t)gq * n;
-            const T *ei_row = Hc + hplane + (size_t)gq * n;
+            const T *er_row = Hc + (size_t)gq * np;
+            const T *ei_row = Hc + hplane + (size_t)gq * np;
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    int ge = row0 + wm * 64 + mt * 32 + g * 8 + (lane >> 5) * 4;
+                    int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
+                    if (ge >= np) continue;
+                    uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
+                    uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
+                    T vr[4], vi[4];
+                    __builtin_memcpy(vr, &pr, 8);
+                    __builtin_memcpy(vi, &pi, 8);
 #pragma unroll
                     for (int z = 0; z < 4; ++z) {
-                        if (ge + z < n) {
-                            float er = from_lp<T>(er_row[ge + z]);
-                            float ei = from_lp<T>(ei_row[ge + z]);
-                            float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
-                            cs_re[nt] += er * yr - ei * yi;
-                            cs_im[nt] += er * yi + ei * yr;
-                        }
+                        float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
+                        float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
+                        cs_re[nt] += er * yr - ei * yi;
+                        cs_im[nt] += er * yi + ei * yr;
                     }
                 }
         }
@@ -393,10 +386,8 @@ __global__ void __launch_bounds__(512) rowred_lp_kernel(const T *__restrict__ Rp
     if (tid < LR_BN) {
         int gc = col0 + tid;
         if (gc < n_cols) {
-            float sr = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
-            float si = red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
-            parts[(size_t)mb * n_cols + gc] = sr;
-            parts[(size_t)(mblocks + mb) * n_cols + gc] = si;
+            parts[(size_t)mb * n_cols + gc] = red[0][0][tid] + red[0][1][tid];
+            parts[(size_t)(mblocks + mb) * n_cols + gc] = red[1][0][tid] + red[1][1][tid];
         }
     }
 }
@@ -590,17 +581,19 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
                               float *scale) {
     size_t nn = (size_t)n * n;
+    const int np = (n + 7) & ~7;
     rb_prof_begin(ctx, ST_RESIDUAL);
     hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
                        (const float2 *)R, nn, (const float *)nullptr, 14, scale);
     RB_CHECK_LAUNCH(ctx);
-    dim3 grd((unsigned)((nn + 255) / 256));
+    size_t npad = (size_t)n * np;
+    dim3 grd((unsigned)((npad + 255) / 256));
     if (prec == RB_BF16)
         hipLaunchKernelGGL(to_planar_kernel<__bf16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, scale, (__bf16 *)Rp);
+                           (const float2 *)R, n, np, scale, (__bf16 *)Rp);
     else
         hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, scale, (_Float16 *)Rp);
+                           (const float2 *)R, n, np, scale, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -630,11 +623,11 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
     int grid = ((total + 7) / 8) * 8;
     rb_prof_begin(ctx, ST_BACKPROJECT);
     if (prec == RB_BF16)
-        hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(512), 0, ctx->stream,
+        hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(256), 0, ctx->stream,
                            (const __bf16 *)Rp, (const __bf16 *)Ht, n, n_mask, n_comp, mblocks,
                            nblocks, parts);
     else
-        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(512), 0, ctx->stream,
+        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(256), 0, ctx->stream,
                            (const _Float16 *)Rp, (const _Float16 *)Ht, n, n_mask, n_comp, mblocks,
                            nblocks, parts);
     RB_CHECK_LAUNCH(ctx);

@@ -396,35 +396,26 @@ __device__ __forceinline__ void straight_guess(double ddx, double ddy, double d,
     i = min(max((int)(d / ds), 1), S - 2);
 }
 
-// One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
-// one transducer. The tile centre is walked first from its straight-ray guess; the offset
-// between the two (the bending of the rays, smooth over a tile) starts every node's walk.
-__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
-                                                     int e0, GridP g, double R, double psi0,
-                                                     int N, double ds, double c0, int n_mask,
-                                                     int tile_i0, int tile_j0, int tiles_x,
-                                                     int tiles_y, const int32_t *__restrict__ qmap,
-                                                     rb_tables tb, int *lost) {
-    __shared__ int s_off[2];
-    const int el = blockIdx.y;
-    if (sb.folded[el]) return;  // general path (uniform over the block)
-    // Workgroups are dealt to the 8 XCDs round robin (id mod 8); give each XCD one
-    // contiguous band of tiles so that the part of the ray mesh it walks stays in its L2.
-    // (the grid is padded to a multiple of 8, so this is a bijection onto 0 .. grid-1)
+// Pre-pass: one lane per (transducer, node tile) walks the tile centre from its straight-ray
+// guess and stores the offset of the quad it reached (the local bending of the rays).
+__global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                          int e0, GridP g, double psi0, int N,
+                                                          double ds, int tile_i0, int tile_j0,
+                                                          int tiles_x, int tiles_y,
+                                                          int2 *__restrict__ off) {
     const int ntiles = tiles_x * tiles_y;
-    const int per_xcd = gridDim.x / 8;
-    const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (t >= ntiles) return;
-    const int ti = t % tiles_x, tj = t / tiles_x;
-    const int e = e0 + el;
-    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    const double2 xy = sb.ring[e];
-    const double xe = xy.x, ye = xy.y;
-    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
-    const size_t ebase = (size_t)el * S * n_rays;
-    if (threadIdx.x == 0) {
-        double cu = tile_i0 + ti * LTX + 0.5 * (LTX - 1), cv = tile_j0 + tj * LTY + 0.5 * (LTY - 1);
-        double ddx = g.x0 + cu * g.dx - xe, ddy = g.y0 + cv * g.dx - ye;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= E * ntiles) return;
+    const int el = tid / ntiles, t = tid - el * ntiles;
+    int2 o = make_int2(0, 0);
+    if (!sb.folded[el]) {
+        const int ti = t % tiles_x, tj = t / tiles_x;
+        const int e = e0 + el;
+        const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+        const double2 xy = sb.ring[e];
+        double cu = tile_i0 + ti * LTX + 0.5 * (LTX - 1);
+        double cv = tile_j0 + tj * LTY + 0.5 * (LTY - 1);
+        double ddx = g.x0 + cu * g.dx - xy.x, ddy = g.y0 + cv * g.dx - xy.y;
         double d = sqrt(ddx * ddx + ddy * ddy);
         int j, i, jw, iw;
         straight_guess(ddx, ddy, d, psi, ds, n_rays, S, jw, iw);
@@ -432,20 +423,38 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
         i = iw;
         size_t vb[3];
         float lam[3];
-        bool ok = d >= 2.0 * ds && mesh_walk(sb, Mrow, ebase, n_rays, (float)cu, (float)cv, j,
-                                             i, vb, lam);
-        s_off[0] = ok ? j - jw : 0;
-        s_off[1] = ok ? i - iw : 0;
+        if (d >= 2.0 * ds && mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays,
+                                       n_rays, (float)cu, (float)cv, j, i, vb, lam))
+            o = make_int2(j - jw, i - iw);
     }
-    __syncthreads();
+    off[tid] = o;
+}
+
+// One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
+// one transducer and starts every walk from the straight-ray guess plus the tile's offset.
+__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
+                                                     int e0, GridP g, double R, double psi0,
+                                                     int N, double ds, double c0, int n_mask,
+                                                     int tile_i0, int tile_j0, int tiles_x,
+                                                     int tiles_y, const int32_t *__restrict__ qmap,
+                                                     const int2 *__restrict__ off, rb_tables tb,
+                                                     int *lost) {
+    const int el = blockIdx.y;
+    if (sb.folded[el]) return;  // general path (uniform over the block)
+    const int ntiles = tiles_x * tiles_y;
+    const int t = blockIdx.x;
+    const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
     if (ii >= g.nx || jj >= g.ny) return;
     const int q = qmap[(size_t)jj * g.nx + ii];
     if (q < 0) return;
+    const int e = e0 + el;
     const size_t out = (size_t)e * n_mask + q;
+    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const double2 xy = sb.ring[e];
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
-    double ddx = px - xe, ddy = py - ye;
+    double ddx = px - xy.x, ddy = py - xy.y;
     double d = sqrt(ddx * ddx + ddy * ddy);
     if (d < 2.0 * ds) {
         write_invalid(tb, out);
@@ -453,11 +462,13 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     }
     int j, i;
     straight_guess(ddx, ddy, d, psi, ds, n_rays, S, j, i);
-    j = min(max(j + s_off[0], 0), n_rays - 2);
-    i = min(max(i + s_off[1], 1), S - 2);
+    const int2 o = off[(size_t)el * ntiles + t];
+    j = min(max(j + o.x, 0), n_rays - 2);
+    i = min(max(i + o.y, 1), S - 2);
     size_t vb[3];
     float lam[3];
-    if (mesh_walk(sb, Mrow, ebase, n_rays, (float)ii, (float)jj, j, i, vb, lam)) {
+    if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
+                  (float)jj, j, i, vb, lam)) {
         write_entry(sb, vb, lam, d, c0, tb, out);
     } else {
         write_invalid(tb, out);
@@ -749,6 +760,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
                    rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
                    rb_align((size_t)N * sizeof(double2)) +
+                   rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long));
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
@@ -765,6 +777,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
     int32_t *lost = rb_carve<int32_t>(&ctx->ws, 2);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
+    int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
 
@@ -790,10 +803,14 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         size_t nk = (size_t)E * n_mask;
         rb_prof_begin(ctx, ST_RESOLVE);
         int ntiles = ctx->tiles_x * ctx->tiles_y;
-        hipLaunchKernelGGL(locate_kernel, dim3(((ntiles + 7) / 8) * 8, E), dim3(LTX * LTY), 0,
-                           ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
-                           tp->c0, n_mask, ctx->tile_i0, ctx->tile_j0, ctx->tiles_x,
-                           ctx->tiles_y, ctx->d_qmap, *out, lost);
+        hipLaunchKernelGGL(tile_offset_kernel, dim3((E * ntiles + 255) / 256), dim3(256), 0,
+                           ctx->stream, sb, nr, S, E, e0, gp, r->psi0, N, tp->ds, ctx->tile_i0,
+                           ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, toff);
+        RB_CHECK_LAUNCH(ctx);
+        hipLaunchKernelGGL(locate_kernel, dim3(ntiles, E), dim3(LTX * LTY), 0, ctx->stream, sb, nr,
+                           S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
+                           ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
+                           toff, *out, lost);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation and resolve
