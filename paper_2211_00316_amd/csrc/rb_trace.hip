@@ -34,6 +34,18 @@ struct GridP {
     double dx, x0, y0, idx;  // idx = 1 / dx
 };
 
+// The spline map is stored with MPAD replicated nodes on every side, so the four control
+// points of a cell are always in the array. Clamping the cell index to [-2, n] then gives
+// exactly the values of clamping each control point index to [0, n-1]: beyond that range all
+// four control points are the edge value either way.
+constexpr int MPAD = 3;
+
+struct SplineMap {
+    const float *f;  // [ny + 2 MPAD][nx + 2 MPAD]
+    int nx, ny, nxp;
+    float ih;        // 1 / dx
+};
+
 struct Spline {
     float v, gx, gy, hxx, hxy, hyy;
 };
@@ -58,42 +70,25 @@ __device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], f
 // Four consecutive floats of a row, 4-byte aligned: one 16-byte load.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
-// Value, gradient and Hessian (per metre) of the spline of f at (x, y).
-__device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const GridP &g,
-                                              double x, double y) {
-    double u = (x - g.x0) * g.idx, v = (y - g.y0) * g.idx;
+// Value, gradient and Hessian (per metre) of the spline at node-index coordinates (u, v).
+__device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, double v) {
     double fu = floor(u), fv = floor(v);
-    int iu = (int)fu, iv = (int)fv;
     float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
     bspline_basis((float)(u - fu), bu, du, ddu);
     bspline_basis((float)(v - fv), bv, dv, ddv);
-    const bool interior = iu >= 1 && iu + 2 < g.nx;  // no clamping along the row
-    int ii[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) ii[a] = min(max(iu - 1 + a, 0), g.nx - 1);
+    int iu = min(max((int)fu, -2), m.nx), iv = min(max((int)fv, -2), m.ny);
+    const float *p = m.f + ((iv - 1 + MPAD) * m.nxp + (iu - 1 + MPAD));
     float s_v = 0, s_gx = 0, s_gy = 0, s_xx = 0, s_xy = 0, s_yy = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        int jj = min(max(iv - 1 + b, 0), g.ny - 1);
-        const float *row = f + (size_t)jj * g.nx;
-        float fr[4];
-        if (interior) {
-            f4u q = *reinterpret_cast<const f4u *>(row + iu - 1);
-            fr[0] = q.x;
-            fr[1] = q.y;
-            fr[2] = q.z;
-            fr[3] = q.w;
-        } else {
-#pragma unroll
-            for (int a = 0; a < 4; ++a) fr[a] = row[ii[a]];
-        }
+        f4u q = *reinterpret_cast<const f4u *>(p + b * m.nxp);
+        float fr[4] = {q.x, q.y, q.z, q.w};
         float r0 = 0, r1 = 0, r2 = 0;  // row sums with B, B', B''
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            float fab = fr[a];
-            r0 = fmaf(bu[a], fab, r0);
-            r1 = fmaf(du[a], fab, r1);
-            r2 = fmaf(ddu[a], fab, r2);
+            r0 = fmaf(bu[a], fr[a], r0);
+            r1 = fmaf(du[a], fr[a], r1);
+            r2 = fmaf(ddu[a], fr[a], r2);
         }
         s_v = fmaf(bv[b], r0, s_v);
         s_gx = fmaf(bv[b], r1, s_gx);
@@ -102,12 +97,13 @@ __device__ __forceinline__ Spline spline_eval(const float *__restrict__ f, const
         s_xy = fmaf(dv[b], r1, s_xy);
         s_yy = fmaf(ddv[b], r0, s_yy);
     }
-    float ih = (float)g.idx, ih2 = ih * ih;
+    float ih = m.ih, ih2 = ih * ih;
     return Spline{s_v, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
 }
 
+// Ray state; the position is in node-index units (u, v) = ((x - x0) / dx, (y - y0) / dx).
 struct Ray {
-    double x, y;
+    double u, v;
     float kx, ky, dxx, dxy, dkx, dky;
 };
 
@@ -123,17 +119,17 @@ __device__ __forceinline__ void paraxial_rhs(const Spline &s, float kx, float ky
     q[3] = s.hxy * dxx + s.hyy * dxy - gdx * in * s.gy + kdk * in2 * s.gy;
 }
 
-// One step of Algorithm 1 of length h, given the spline at the current point.
-__device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const GridP &g,
-                                         const Spline &s1, const Ray &r, double h) {
+// One step of Algorithm 1 of length h (metres), given the spline at the current point.
+__device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, const Ray &r,
+                                         double h, double idx) {
     float hf = (float)h;
+    double hu = h * idx;                                    // step in node units
     float n = s1.v;
     float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
     float qxx = r.kx * ikn, qxy = r.ky * ikn;               // unit ray direction
     float kx = n * qxx, ky = n * qxy;                       // normalised wave vector
     float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
-    double xp = r.x + h * (double)qxx, yp = r.y + h * (double)qxy;
-    Spline s2 = spline_eval(ns, g, xp, yp);                 // auxiliary wavenumber
+    Spline s2 = spline_eval(m, r.u + hu * (double)qxx, r.v + hu * (double)qxy);
     float n2 = s2.v;
     float ikpn = rsqrtf(kpx * kpx + kpy * kpy);
     float qxx2 = kpx * ikpn, qxy2 = kpy * ikpn;
@@ -142,8 +138,8 @@ __device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const Gri
     float sx = qxx + qxx2, sy = qxy + qxy2;
     float isn = rsqrtf(sx * sx + sy * sy);
     Ray o;
-    o.x = r.x + h * (double)(sx * isn);                     // position along mean direction
-    o.y = r.y + h * (double)(sy * isn);
+    o.u = r.u + hu * (double)(sx * isn);                    // position along mean direction
+    o.v = r.v + hu * (double)(sy * isn);
     o.kx = kx + hf * (s1.gx + s2.gx) * 0.5f;
     o.ky = ky + hf * (s1.gy + s2.gy) * 0.5f;
     float a[4], b[4];
@@ -158,6 +154,14 @@ __device__ __forceinline__ Ray heun_step(const float *__restrict__ ns, const Gri
     return o;
 }
 
+// Square root of a positive double from the FP32 estimate and one Newton step (relative
+// error about the square of the FP32 one).
+__device__ __forceinline__ double sqrt_newton(double a) {
+    float s0 = sqrtf((float)a);
+    double s = (double)s0;
+    return fma(a - s * s, (double)(0.5f * __builtin_amdgcn_rcpf(s0)), s);
+}
+
 struct SampleBufs {
     float2 *pos;                       // [E][S][n_rays] position in node-index units
     float4 *fld;                       // [E][S][n_rays] (dT, L, t_x, t_y)
@@ -170,98 +174,118 @@ struct SampleBufs {
     const double2 *ring;               // [N] transducer positions
 };
 
-__global__ void __launch_bounds__(256) trace_kernel(const float *__restrict__ ns, GridP g,
-                                                    double R, double psi0, int N, int n_rays,
-                                                    int max_steps, double ds, double c0, int e0,
-                                                    int E, SampleBufs sb, int *flag) {
+__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double R, double psi0,
+                                                    int N, int n_rays, int max_steps, double ds,
+                                                    double c0, int e0, int E, SampleBufs sb,
+                                                    int *flag) {
     int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= E * n_rays) return;
     int el = tid / n_rays, j = tid - el * n_rays;
     int e = e0 + el;
     const int S = max_steps + 1;
-    double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    double xe = R * cos(psi), ye = R * sin(psi);
-    double gam = psi + RB_PI + ((double)j + 0.5 - 0.5 * (double)n_rays) * RB_PI / (double)n_rays;
-    double cg = cos(gam), sg = sin(gam);
+    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const double2 xy = sb.ring[e];
+    // launch angle gamma = psi + pi + delta, |delta| < pi / 2 (Section 4.4 fan)
+    float sd, cd;
+    sincospif(((float)j + 0.5f - 0.5f * (float)n_rays) / (float)n_rays, &sd, &cd);
+    const float cp = (float)(xy.x / R), sp = (float)(xy.y / R);
+    const float cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
 
+    const double ue = (xy.x - g.x0) * g.idx, ve = (xy.y - g.y0) * g.idx;
+    const double uc = -g.x0 * g.idx, vc = -g.y0 * g.idx;  // ring centre
+    const double Ru2 = R * R * g.idx * g.idx;              // ring radius squared, node units
     Ray r;
-    r.x = xe;
-    r.y = ye;
-    Spline sc = spline_eval(ns, g, r.x, r.y);
+    r.u = ue;
+    r.v = ve;
+    Spline sc = spline_eval(m, r.u, r.v);
     float n_cur = sc.v;
-    r.kx = n_cur * (float)cg;
-    r.ky = n_cur * (float)sg;
+    r.kx = n_cur * cg;
+    r.ky = n_cur * sg;
     r.dxx = 0.0f;
     r.dxy = 0.0f;
-    r.dkx = -n_cur * (float)sg;
-    r.dky = n_cur * (float)cg;
+    r.dkx = -n_cur * sg;
+    r.dky = n_cur * cg;
     double T = 0.0;
 
-    size_t base = (size_t)el * S * n_rays + j;
-    sb.pos[base] = make_float2((float)((r.x - g.x0) * g.idx), (float)((r.y - g.y0) * g.idx));
-    sb.fld[base] = make_float4(0.0f, 0.0f, (float)cg, (float)sg);
-    sb.K[base] = 0;
+    size_t o = (size_t)el * S * n_rays + j;
+    sb.pos[o] = make_float2((float)r.u, (float)r.v);
+    sb.fld[o] = make_float4(0.0f, 0.0f, cg, sg);
+    sb.K[o] = 0;
 
-    float J_prev = 0.0f, J1 = 0.0f, n1 = 1.0f;
-    float inv_sqrt_8pi_s1 = 0.0f;
+    float J_prev = 0.0f;
+    float lnc1 = 0.0f;  // (1/2) ln(n_1 J_1 / (8 pi s_1)) of the first sample
     int K = 0;
     int M = -1;
-    const double R2 = R * R;
     const double ic0 = 1.0 / c0;
-    for (int i = 0; i < max_steps; ++i) {
-        Ray nr = heun_step(ns, g, sc, r, ds);
-        double h = ds;
-        bool last = nr.x * nr.x + nr.y * nr.y >= R2;
-        if (last) {
-            // Definition 1: redo the step with ds' = distance along the unit direction to
-            // the ring.
-            double kn = sqrt((double)r.kx * r.kx + (double)r.ky * r.ky);
-            double tx = r.kx / kn, ty = r.ky / kn;
-            double b = r.x * tx + r.y * ty;
-            double disc = b * b + R2 - (r.x * r.x + r.y * r.y);
-            h = -b + sqrt(fmax(disc, 0.0));
-            h = fmin(fmax(h, 0.0), ds);
-            nr = heun_step(ns, g, sc, r, h);
+    double h = ds;
+    bool last = false;
+    int i = 0;
+    while (i < max_steps) {
+        Ray nr = heun_step(m, sc, r, h, g.idx);
+        if (!last) {
+            double pu = nr.u - uc, pv = nr.v - vc;
+            if (pu * pu + pv * pv >= Ru2) {
+                // Definition 1: redo the step with ds' = distance along the unit direction
+                // to the ring.
+                double kn = sqrt((double)r.kx * r.kx + (double)r.ky * r.ky);
+                double tx = r.kx / kn, ty = r.ky / kn;
+                double qu = r.u - uc, qv = r.v - vc;
+                double b = (qu * tx + qv * ty) * g.dx;
+                double disc = b * b + R * R - (qu * qu + qv * qv) * g.dx * g.dx;
+                h = fmin(fmax(-b + sqrt(fmax(disc, 0.0)), 0.0), ds);
+                last = true;
+                continue;
+            }
         }
         r = nr;
-        sc = spline_eval(ns, g, r.x, r.y);
+        sc = spline_eval(m, r.u, r.v);
         float n_new = sc.v;
         T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
         float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
         float tx = r.kx * ikn, ty = r.ky * ikn;
         float J = r.dxx * (-ty) + r.dxy * tx;
         if (i >= 1 && J * J_prev < 0.0f) ++K;
-        double d = sqrt((r.x - xe) * (r.x - xe) + (r.y - ye) * (r.y - ye));
+        double du = r.u - ue, dv = r.v - ve;
+        double d = sqrt_newton(du * du + dv * dv) * g.dx;   // distance from the source
         float df = (float)d;
-        if (i == 0) {
-            J1 = J;
-            n1 = n_new;
-            inv_sqrt_8pi_s1 = 1.0f / sqrtf(8.0f * (float)RB_PI * df);
-        }
-        float A = sqrtf(n1 / n_new * J1 / fabsf(J)) * inv_sqrt_8pi_s1;
+        float nJ = n_new * fabsf(J);
+        // Eq. attenuation_geom_reference with the first sample as reference, as a logarithm:
+        // L = ln A + ln(d)/2 = lnc1 + ln(d / (n |J|)) / 2
+        if (i == 0) lnc1 = 0.5f * __logf(nJ * __builtin_amdgcn_rcpf(8.0f * (float)RB_PI * df));
+        float L = lnc1 + 0.5f * __logf(df * __builtin_amdgcn_rcpf(nJ));
         float dT = (float)(T - d * ic0);
-        float L = logf(A) + 0.5f * logf(df);
-        size_t o = base + (size_t)(i + 1) * n_rays;
-        sb.pos[o] = make_float2((float)((r.x - g.x0) * g.idx), (float)((r.y - g.y0) * g.idx));
+        ++i;
+        o += n_rays;
+        sb.pos[o] = make_float2((float)r.u, (float)r.v);
         sb.fld[o] = make_float4(dT, L, tx, ty);
         sb.K[o] = (uint8_t)min(K, 255);
         J_prev = J;
         n_cur = n_new;
         if (last) {
-            M = i + 1;
-            double beta = atan2(r.y, r.x) - psi;
-            beta = beta - RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
+            M = i;
             size_t x = (size_t)el * n_rays + j;
-            sb.ex_beta[x] = beta;
             sb.ex_dT[x] = dT;
             sb.ex_L[x] = L;
             sb.ex_K[x] = (uint8_t)min(K, 255);
             break;
         }
     }
+    if (M >= 0) {
+        double beta = atan2(r.v - vc, r.u - uc) - psi;
+        sb.ex_beta[(size_t)el * n_rays + j] = beta - RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
+    }
     sb.M[(size_t)el * n_rays + j] = M;
     if (M < 0) atomicOr(flag, 1);
     if (K > 0) atomicOr(sb.folded + el, 1);
+}
+
+// Spline map with MPAD replicated nodes on every side.
+__global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float *__restrict__ out) {
+    const int nxp = nx + 2 * MPAD;
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nxp) return;
+    int si = min(max(i - MPAD, 0), nx - 1), sj = min(max(j - MPAD, 0), ny - 1);
+    out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si];
 }
 
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -761,7 +785,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
                    rb_align((size_t)N * sizeof(double2)) +
                    rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
-                   rb_align((size_t)C * n_mask * sizeof(unsigned long long));
+                   rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
+                   rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float));
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
     if (st != RB_OK) return st;
@@ -780,12 +805,18 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
+    const int nxp = g->nx + 2 * MPAD, nyp = g->ny + 2 * MPAD;
+    float *padded = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
+    SplineMap smap{padded, g->nx, g->ny, nxp, (float)(1.0 / g->dx)};
 
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
     RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
     RB_HIP(ctx, hipMemsetAsync(lost, 0, sizeof(int32_t), ctx->stream));
     hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
                        r->radius, r->psi0, N, ringpos);
+    RB_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, n_s,
+                       g->nx, g->ny, padded);
     RB_CHECK_LAUNCH(ctx);
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
@@ -795,8 +826,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         RB_CHECK_LAUNCH(ctx);
         rb_prof_begin(ctx, ST_TRACE);
         hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
-                           n_s, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0, e0,
-                           E, sb, ctx->d_flag);
+                           smap, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0,
+                           e0, E, sb, ctx->d_flag);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // unfolded fans: direct walk per (transducer, node)
