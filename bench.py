@@ -24,8 +24,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import hashlib
+import re
+
 FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix
 HBM_PEAK_GBS = 8000.0
+# FP32 vector arithmetic without packed FP32 instructions (the library is built without
+# them): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 78.6
+
+# Algorithmic units of the hot kernels
+TRACE_FLOP_PER_SAMPLE = 550     # two spline value+gradient+Hessian evaluations, Heun, paraxial
+TABLE_BYTES = 21                # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
+SAMPLE_BYTES = 25               # one ray sample: position 8, (dT, L, t_x, t_y) 16, K 1
+OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16}   # G (complex) + H, H_x, H_y per entry
+
+CSRC = os.path.join(ROOT, "paper_2211_00316_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+# stage -> kernels it launches (FP32 form, 16-bit forms)
+STAGE_KERNELS = {
+    "trace": (["trace_kernel"], ["trace_kernel"]),
+    "resolve": (["tile_offset_kernel", "locate_kernel"], ["tile_offset_kernel", "locate_kernel"]),
+    "build_green": (["green_kernel"], ["green_lp_kernel"]),
+    "forward_gemm": (["forward_kernel"], ["forward_lp_kernel"]),
+    "backproject_gemm": (["rowred_kernel"], ["rowred_lp_kernel"]),
+}
 
 
 def synthesize_data(ctx, w, grid, ring, tp, c_true, freq_idx):
@@ -163,6 +187,68 @@ def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag):
     return 1000.0 * elapsed / steps, stages, c
 
 
+def source_hash(fname):
+    with open(os.path.join(CSRC, fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per dispatch from the committed PMC summary, keyed by kernel; entries whose
+    source file changed since the counters were taken are dropped."""
+    path = os.path.join(PROFILES, f"hbm_traffic_{workload}_{prec}.md")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    row = re.compile(r"^\|\s*(\w+)\s*\|\s*([\w.]+)\s*\|\s*([0-9a-f]{16})\s*\|"
+                     r"\s*(\d+)\s*\|\s*([0-9.eE+]+)\s*\|\s*([0-9.eE+]+)\s*\|\s*([0-9.eE+]+)\s*\|")
+    for line in open(path):
+        m = row.match(line)
+        if m and source_hash(m.group(2)) == m.group(3):
+            out[m.group(1)] = float(m.group(7))
+    return out
+
+
+def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
+    """Per hot kernel: algorithmic work per launch / average launch time, against the peak
+    of what bounds it. `samples` = ray samples per step."""
+    peak, peak_name = PEAKS[prec]
+    traffic = measured_traffic(workload, prec)
+    work = {  # stage -> (bound, algorithmic units per step, unit, peak, peak name, what)
+        "trace": ("alu", TRACE_FLOP_PER_SAMPLE * samples / 1e12, "TFLOP/s",
+                  FP32_VECTOR_PEAK_TFLOPS, "fp32 vector (no packed FP32)",
+                  f"{TRACE_FLOP_PER_SAMPLE} flop per ray sample"),
+        "resolve": ("hbm", (TABLE_BYTES * N * Pm + SAMPLE_BYTES * samples) / 1e9, "GB/s",
+                    HBM_PEAK_GBS, "HBM3E",
+                    f"{TABLE_BYTES} B per table entry written + {SAMPLE_BYTES} B per ray sample read"),
+        "build_green": ("hbm", (TABLE_BYTES + OPERAND_BYTES[prec]) * N * Pm / 1e9, "GB/s",
+                        HBM_PEAK_GBS, "HBM3E",
+                        f"{TABLE_BYTES} B read + {OPERAND_BYTES[prec]} B written per (e, p)"),
+        "forward_gemm": ("mfma", 8.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,
+                         "8 N^2 P_m flop (complex N x N x P_m, symmetric)"),
+        "backproject_gemm": ("mfma", 24.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,
+                             "24 N^2 P_m flop (3 complex GEMMs N x N x P_m)"),
+    }
+    out = {}
+    for stage, (bound, units, unit, pk, pk_name, what) in work.items():
+        if stage not in stages:
+            continue
+        ms, n = stages[stage]
+        launches = n / steps
+        avg_ms = ms / max(n, 1)
+        achieved = units * steps / (ms * 1e-3)
+        kernels = STAGE_KERNELS[stage][0 if prec == "f32" else 1]
+        have = all(k in traffic for k in kernels)
+        out[stage] = {
+            "kernel": "+".join(kernels),
+            "bound": bound, "achieved": round(achieved, 2), "peak": pk, "unit": unit,
+            "frac": round(achieved / pk, 4),
+            "traffic": round(sum(traffic[k] for k in kernels)) if have else None,
+            "peak_is": pk_name, "per_unit": what, "avg_launch_ms": round(avg_ms, 3),
+            "launches_per_step": round(launches, 2), "ms_per_step": round(ms / steps, 3),
+        }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +259,9 @@ def main():
                     help="operand type of the headline (reduced-precision) form")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the frequency step on a single "
@@ -186,6 +275,12 @@ def main():
     import phantoms as ph
     from paper_2211_00316_amd import _lib, setup_for
 
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     w = ph.WORKLOADS[args.workload]
     grid, ring, tp = setup_for(w)
     ctx = _lib.Context("cuda:0")
@@ -210,23 +305,10 @@ def main():
     N = w.n_trans
     mask = _mask_index(w)
     Pm = mask.numel()
-    bp_ms, bp_n = stages["backproject_gemm"]
-    avg_bp = bp_ms / max(bp_n, 1)
-    flops_bp = 24.0 * N * N * Pm            # 3 complex GEMMs of N x N x P_m per launch
-    achieved = flops_bp / (avg_bp * 1e-3) / 1e12
-    peak, peak_name = PEAKS[args.prec]
-    roofline = {
-        "kernel": "rowred (Hessian-free back-projection, 3 complex GEMMs N x N x P_m)",
-        "bound": "mfma",
-        "achieved": round(achieved, 2),
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4),
-        "traffic": None,
-        "peak_is": peak_name,
-        "avg_launch_ms": round(avg_bp, 3),
-        "flops_per_launch": flops_bp,
-    }
+    samples = ctx.trace_samples()
+    rl = kernel_rooflines(stages, args.steps, N, Pm, samples, args.prec, w.name)
+    dominant = max(rl, key=lambda k: rl[k]["ms_per_step"])
+    roofline = dict(rl[dominant], stage=dominant)
     line = {
         "metric": "frequency-step updates/s at 1024 elems, 1024^2 grid (reduced-precision form; "
                   "FP32 form alongside)",
@@ -248,6 +330,8 @@ def main():
                    "parallelism": "single GPU"},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
+        "rooflines": rl,
+        "ray_samples_per_step": samples,
     }
     if "f32" in forms and args.prec != "f32":
         ms32, st32, c32 = forms["f32"]

@@ -149,6 +149,11 @@ rb_status rb_trace_rays(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
  * triangle (reported as invalid table entries). Zero in normal operation. */
 int64_t rb_trace_lost_nodes(const rb_ctx *ctx);
 
+/* Diagnostic of the last rb_trace_rays / rb_frequency_step on this context: the number of ray
+ * samples the tracer wrote (source samples included), summed over all rays that reached the
+ * ring; the unit of the tracer's work. -1 for a null context. */
+int64_t rb_trace_samples(const rb_ctx *ctx);
+
 /* Assemble G and the back-projection operands H of angular frequency omega from the tables
  * (Eqs. 2D_greens, phase-discretised, greens-time-reversed). The phase omega T + pi/4 -
  * K pi/2 is reduced modulo 2 pi in FP64. Invalid table entries give zeros. */

@@ -23,7 +23,7 @@ SYMBOLS = (
     "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
-    "rb_stage_name", "rb_trace_lost_nodes",
+    "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples",
 )
 N_STAGES = 12
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "rb_profile_read": ([P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "rb_stage_name": ([I32], ctypes.c_char_p),
         "rb_trace_lost_nodes": ([P], ctypes.c_int64),
+        "rb_trace_samples": ([P], ctypes.c_int64),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -235,6 +236,10 @@ class Context:
     def lost_nodes(self) -> int:
         """Mask nodes the last binning could not place (diagnostic; 0 normally)."""
         return int(self.lib.rb_trace_lost_nodes(self._h))
+
+    def trace_samples(self) -> int:
+        """Ray samples written by the last trace (the tracer's unit of work)."""
+        return int(self.lib.rb_trace_samples(self._h))
 
     # measurement ------------------------------------------------------------------------
     def profile_enable(self, on: bool = True):

@@ -202,7 +202,7 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     if (hipMalloc(&ctx->d_flag, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(&ctx->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&ctx->h_flag, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
@@ -230,6 +230,8 @@ void rb_destroy(rb_ctx *ctx) {
 const char *rb_last_error(const rb_ctx *ctx) { return ctx ? ctx->err : "no context"; }
 
 int64_t rb_trace_lost_nodes(const rb_ctx *ctx) { return ctx ? ctx->lost_nodes : -1; }
+
+int64_t rb_trace_samples(const rb_ctx *ctx) { return ctx ? ctx->ray_samples : -1; }
 
 rb_status rb_profile_enable(rb_ctx *ctx, int32_t on) {
     if (!ctx) return RB_EINVAL;

@@ -44,8 +44,9 @@ struct rb_ctx {
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
     int32_t *d_flag = nullptr;        // device error flags (ray overflow, non-finite update)
-    int32_t *h_flag = nullptr;        // pinned host mirror (2 ints)
+    int32_t *h_flag = nullptr;        // pinned host mirror (flags, lost nodes, int64 samples)
     int64_t lost_nodes = 0;           // mask nodes the last binning could not place
+    int64_t ray_samples = 0;          // ray samples written by the last trace
 };
 
 // Stages timed by the profiler (order = rb_stage_name).

@@ -60,8 +60,27 @@ __device__ __forceinline__ double reduce_phase(double ph) {
 }
 
 // Green's functions --------------------------------------------------------------------
-constexpr int GQ = 64;  // tile: 64 mask nodes (lanes) x GE transducers
-constexpr int GE = 32;
+// A workgroup covers 64 mask nodes (one per lane) x 64 transducers (16 consecutive ones per
+// wave). A lane keeps the directions and flags of its 16 transducers and their two
+// neighbours in registers, writes G rows coalesced over the nodes, and writes its 16 entries
+// of each transposed H row as two 16-byte stores.
+constexpr int GQ = 64;
+constexpr int GW = 16;       // transducers per wave
+constexpr int GE = 4 * GW;   // transducers per workgroup
+
+// Bit pattern of a value rounded to the 16-bit type.
+template <typename T>
+__device__ __forceinline__ uint32_t lp_bits(float x) {
+    T b = to_lp<T>(x);
+    uint16_t u;
+    __builtin_memcpy(&u, &b, 2);
+    return u;
+}
+
+// Angle between two unit directions.
+__device__ __forceinline__ float angle_between(float ax, float ay, float bx, float by) {
+    return fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
@@ -70,100 +89,85 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
                                                        const float *__restrict__ gscale,
                                                        int write_g, T *__restrict__ Gp,
                                                        T *__restrict__ Ht) {
-    __shared__ float s_ux[GE + 2][GQ], s_uy[GE + 2][GQ];
-    __shared__ uint8_t s_f[GE + 2][GQ];
-    // rows of GE + 2 values (17 dwords): lanes writing one column hit distinct banks
-    __shared__ __attribute__((aligned(16))) T s_h[3][2][GQ][GE + 2];
-    const int q0 = blockIdx.x * GQ, e0 = blockIdx.y * GE;
-    const int tid = threadIdx.x, tq = tid & 63, tr = tid >> 6;
-    const int q = q0 + tq;
-    // halo rows e0-1 .. e0+GE (mod N) of directions and flags
-    for (int r = tr; r < GE + 2; r += 4) {
-        int e = (e0 - 1 + r + N) % N;
-        float ux = 0.f, uy = 0.f;
-        uint8_t f = 0;
-        if (q < n_mask) {
-            size_t o = (size_t)e * n_mask + q;
-            f = tb.flags[o];
-            ux = tb.ux[o];
-            uy = tb.uy[o];
-        }
-        s_ux[r][tq] = ux;
-        s_uy[r][tq] = uy;
-        s_f[r][tq] = f;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = blockIdx.x * GQ + lane;
+    const int e0 = blockIdx.y * GE + w * GW;
+    const int Np = (N + 7) & ~7;
+    if (q >= n_mask || e0 >= Np) return;  // no barrier in this kernel
+    // rows e0 - 1 .. e0 + GW (indices mod N)
+    float ux[GW + 2], uy[GW + 2];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int r = 0; r < GW + 2; ++r) {
+        int e = e0 - 1 + r;
+        e = e < 0 ? e + N : (e >= N ? e - N : e);
+        if (e >= N) e = 0;  // rows past the padding end: never used
+        size_t o = (size_t)e * n_mask + q;
+        valid |= (tb.flags[o] & 0x80) ? (1u << r) : 0u;
+        ux[r] = tb.ux[o];
+        uy[r] = tb.uy[o];
     }
-    __syncthreads();
     const double k0 = omega / c0;
-    const float sk = (float)sqrt(k0);
+    const float sk = (float)sqrt(k0), isk = 1.0f / sk;
     const size_t gplane = (size_t)N * n_mask;
-    for (int r = tr; r < GE; r += 4) {
-        int e = e0 + r;
-        float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, ux = 0.f, uy = 0.f;
-        if (e < N && q < n_mask) {
+    float2 f2 = make_float2(1.f, 0.f);
+    if (write_g && gs) {
+        f2 = gs[q];
+        float sc = gscale[0];
+        f2.x *= sc;
+        f2.y *= sc;
+    }
+    uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
+#pragma unroll
+    for (int r = 0; r < GW; ++r) {
+        const int e = e0 + r;
+        float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
+        if (e < N) {
             size_t o = (size_t)e * n_mask + q;
-            uint8_t f = s_f[r + 1][tq];
-            if (f & 0x80) {
-                double ph = reduce_phase(omega * tb.T[o] + 0.25 * RB_PI -
-                                         (double)(f & 3) * 0.5 * RB_PI);
-                float s, c;
-                sincosf((float)ph, &s, &c);
+            if (valid >> (r + 1) & 1u) {
+                uint32_t f = tb.flags[o];
+                double ph = omega * tb.T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI;
+                ph -= RB_TWO_PI * floor(ph * (1.0 / RB_TWO_PI));
+                float sn, cs;
+                __sincosf((float)ph, &sn, &cs);
                 float A = tb.A[o];
-                float ga = A / sk;
-                gr = ga * c;
-                gi = ga * s;
-                ux = s_ux[r + 1][tq];
-                uy = s_uy[r + 1][tq];
-                bool vm = s_f[r][tq] & 0x80, vp = s_f[r + 2][tq] & 0x80;
+                float ga = A * isk;
+                gr = ga * cs;
+                gi = ga * sn;
+                vx = ux[r + 1];
+                vy = uy[r + 1];
+                const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
                 float a = 0.f;
-                if (vm && vp) {
-                    float ax = s_ux[r][tq], ay = s_uy[r][tq];
-                    float bx = s_ux[r + 2][tq], by = s_uy[r + 2][tq];
-                    a = 0.5f * fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
-                } else if (vp) {
-                    float bx = s_ux[r + 2][tq], by = s_uy[r + 2][tq];
-                    a = fabsf(atan2f(ux * by - uy * bx, ux * bx + uy * by));
-                } else if (vm) {
-                    float ax = s_ux[r][tq], ay = s_uy[r][tq];
-                    a = fabsf(atan2f(ax * uy - ay * ux, ax * ux + ay * uy));
-                }
-                float ha = a * sk / A;
-                hr = ha * c;
-                hi = -ha * s;
+                if (vm && vp) a = 0.5f * angle_between(ux[r], uy[r], ux[r + 2], uy[r + 2]);
+                else if (vp) a = angle_between(vx, vy, ux[r + 2], uy[r + 2]);
+                else if (vm) a = angle_between(ux[r], uy[r], vx, vy);
+                float ha = a * sk * __builtin_amdgcn_rcpf(A);
+                hr = ha * cs;
+                hi = -ha * sn;
             }
             if (write_g) {
-                if (gs) {
-                    float2 f2 = gs[q];
-                    float sc = gscale[0];
-                    float tr = (gr * f2.x - gi * f2.y) * sc;
-                    gi = (gr * f2.y + gi * f2.x) * sc;
-                    gr = tr;
-                }
-                Gp[o] = to_lp<T>(gr);
+                float tr = gr * f2.x - gi * f2.y;
+                gi = gr * f2.y + gi * f2.x;
+                Gp[o] = to_lp<T>(tr);
                 Gp[gplane + o] = to_lp<T>(gi);
             }
         }
-        s_h[0][0][tq][r] = to_lp<T>(hr);
-        s_h[0][1][tq][r] = to_lp<T>(hi);
-        s_h[1][0][tq][r] = to_lp<T>(hr * ux);
-        s_h[1][1][tq][r] = to_lp<T>(hi * ux);
-        s_h[2][0][tq][r] = to_lp<T>(hr * uy);
-        s_h[2][1][tq][r] = to_lp<T>(hi * uy);
+        float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
+#pragma unroll
+        for (int cp = 0; cp < 6; ++cp) {
+            if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
+            else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
+        }
     }
-    __syncthreads();
-    // transposed store: rows (c, part, q) of GE transducers, 16 bytes (8 values) per store;
-    // rows are Np long (zeros past N, written by the tile that holds them)
-    const int Np = (N + 7) & ~7;
+    // transposed rows (c, part, q), Np long (zeros past N)
     const size_t hplane = (size_t)n_mask * Np;
-    constexpr int CH = GE / 8;
-    for (int idx = tid; idx < 3 * 2 * GQ * CH; idx += 256) {
-        int chunk = idx % CH, row = idx / CH;
-        int qq = row % GQ, cp = row / GQ;
-        int c = cp >> 1, part = cp & 1;
-        int gq = q0 + qq, ge = e0 + chunk * 8;
-        if (gq >= n_mask || ge >= Np) continue;
-        T *dst = Ht + (size_t)(2 * c + part) * hplane + (size_t)gq * Np + ge;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&s_h[c][part][qq][chunk * 8]);
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(src[0], src[1], src[2], src[3]);
+#pragma unroll
+    for (int cp = 0; cp < 6; ++cp) {
+        T *dst = Ht + (size_t)cp * hplane + (size_t)q * Np + e0;
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
+        if (e0 + 8 < Np)
+            *reinterpret_cast<uint4 *>(dst + 8) =
+                make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
     }
 }
 

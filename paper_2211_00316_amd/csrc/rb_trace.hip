@@ -174,13 +174,12 @@ struct SampleBufs {
     const double2 *ring;               // [N] transducer positions
 };
 
-__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double R, double psi0,
-                                                    int N, int n_rays, int max_steps, double ds,
-                                                    double c0, int e0, int E, SampleBufs sb,
-                                                    int *flag) {
-    int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= E * n_rays) return;
-    int el = tid / n_rays, j = tid - el * n_rays;
+// One ray (transducer e0 + el, fan index j); returns the index of its last sample, -1 if it
+// did not reach the ring within max_steps.
+__device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, double R,
+                                         double psi0, int N, int n_rays, int max_steps,
+                                         double ds, double c0, int e0, int el, int j,
+                                         const SampleBufs &sb, int *flag) {
     int e = e0 + el;
     const int S = max_steps + 1;
     const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
@@ -277,6 +276,26 @@ __global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double
     sb.M[(size_t)el * n_rays + j] = M;
     if (M < 0) atomicOr(flag, 1);
     if (K > 0) atomicOr(sb.folded + el, 1);
+    return M;
+}
+
+// One lane per ray; the lanes of a wavefront are neighbouring rays of one transducer, so the
+// per-step sample stores are coalesced. Also counts the samples written (one atomic per
+// wavefront; the workgroup size is a multiple of 64, so every wavefront is whole).
+__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double R, double psi0,
+                                                    int N, int n_rays, int max_steps, double ds,
+                                                    double c0, int e0, int E, SampleBufs sb,
+                                                    int *flag, unsigned long long *n_samples) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    int M = -1;
+    if (tid < E * n_rays) {
+        const int el = tid / n_rays, j = tid - el * n_rays;
+        M = trace_ray(m, g, R, psi0, N, n_rays, max_steps, ds, c0, e0, el, j, sb, flag);
+    }
+    int cnt = M >= 0 ? M + 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt > 0) atomicAdd(n_samples, (unsigned long long)cnt);
 }
 
 // Spline map with MPAD replicated nodes on every side.
@@ -299,7 +318,7 @@ __device__ __forceinline__ bool barycentric(float au, float av, float bu, float 
                                             float &lc) {
     float area = (bu - au) * (cv - av) - (bv - av) * (cu - au);
     if (!(fabsf(area) > 1e-30f)) return false;
-    float ia = 1.0f / area;
+    float ia = __builtin_amdgcn_rcpf(area);
     la = ((bu - pu) * (cv - pv) - (bv - pv) * (cu - pu)) * ia;
     lb = ((cu - pu) * (av - pv) - (cv - pv) * (au - pu)) * ia;
     lc = ((au - pu) * (bv - pv) - (av - pv) * (bu - pu)) * ia;
@@ -325,11 +344,11 @@ __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t v
         ty += lam[k] * f.w;
         K = max(K, (int)sb.K[vb[k]]);
     }
-    float tn = sqrtf(tx * tx + ty * ty);
+    float itn = rsqrtf(tx * tx + ty * ty);
     tb.T[out] = (double)dT + d / c0;
-    tb.A[out] = expf(L) * rsqrtf((float)d);
-    tb.ux[out] = tx / tn;
-    tb.uy[out] = ty / tn;
+    tb.A[out] = __expf(L) * rsqrtf((float)d);
+    tb.ux[out] = tx * itn;
+    tb.uy[out] = ty * itn;
     tb.flags[out] = (uint8_t)(0x80 | (K & 3));
 }
 
@@ -456,6 +475,9 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
 
 // One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
+// Workgroups are dealt to the 8 XCDs round-robin; the x extent of the launch is a multiple of
+// 8 and each XCD gets a contiguous band of tiles, so neighbouring tiles share the ray
+// samples through one L2.
 __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
@@ -466,7 +488,8 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const int el = blockIdx.y;
     if (sb.folded[el]) return;  // general path (uniform over the block)
     const int ntiles = tiles_x * tiles_y;
-    const int t = blockIdx.x;
+    const int t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (t >= ntiles) return;
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
@@ -479,7 +502,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const double2 xy = sb.ring[e];
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double ddx = px - xy.x, ddy = py - xy.y;
-    double d = sqrt(ddx * ddx + ddy * ddy);
+    double d = sqrt_newton(ddx * ddx + ddy * ddy);
     if (d < 2.0 * ds) {
         write_invalid(tb, out);
         return;
@@ -523,21 +546,26 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv, con
     }
 }
 
-// General path, folded fans only: one lane per quad (ray j, j+1; samples i, i+1), i >= 1,
-// i + 1 <= min(M_j, M_j+1).
-__global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int E,
-                                                     int nx, int ny, int n_mask,
-                                                     const int32_t *__restrict__ qmap,
-                                                     unsigned long long *__restrict__ keys) {
-    size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int nq = n_rays - 1;
-    size_t total = (size_t)E * S * nq;
-    if (tid >= total) return;
-    int j = (int)(tid % nq);
-    size_t rest = tid / nq;
-    int i = (int)(rest % S);
-    int el = (int)(rest / S);
-    if (i < 1 || !sb.folded[el]) return;
+// The general path runs over the folded transducers of a chunk only: flist[0] = their count,
+// flist[1 ..] = their chunk indices in increasing order. Its kernels are grid-stride loops
+// over that list, so a chunk without folded fans costs one short launch each.
+__global__ void folded_list(const int32_t *__restrict__ folded, int E, int32_t *flist) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int c = 0;
+        for (int el = 0; el < E; ++el)
+            if (folded[el]) flist[1 + c++] = el;
+        flist[0] = c;
+    }
+}
+
+constexpr int FOLD_GRID = 2048;  // workgroups of the grid-stride kernels
+
+// One item per quad (ray j, j+1; samples i, i+1) with i >= 1, i + 1 <= min(M_j, M_j+1).
+__device__ __forceinline__ void raster_quad(const SampleBufs &sb, int n_rays, int S, int el,
+                                            int i, int j, int nx, int ny, int n_mask,
+                                            const int32_t *__restrict__ qmap,
+                                            unsigned long long *__restrict__ keys) {
+    if (i < 1) return;
     int Mj = sb.M[(size_t)el * n_rays + j], Mj1 = sb.M[(size_t)el * n_rays + j + 1];
     if (Mj < 0 || Mj1 < 0 || i + 1 > min(Mj, Mj1)) return;
     size_t b00 = ((size_t)el * S + i) * n_rays + j;
@@ -559,23 +587,38 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
     }
 }
 
-__global__ void fill_keys(unsigned long long *keys, size_t n, int n_mask,
-                          const int32_t *__restrict__ folded) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && folded[i / n_mask]) keys[i] = ~0ull;
+__global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int nx,
+                                                     int ny, int n_mask,
+                                                     const int32_t *__restrict__ qmap,
+                                                     const int32_t *__restrict__ flist,
+                                                     unsigned long long *__restrict__ keys) {
+    const size_t nq = (size_t)n_rays - 1, per = (size_t)S * nq;
+    const size_t total = (size_t)flist[0] * per;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int f = (int)(t / per);
+        const size_t rest = t - (size_t)f * per;
+        const int i = (int)(rest / nq), j = (int)(rest - (size_t)i * nq);
+        raster_quad(sb, n_rays, S, flist[1 + f], i, j, nx, ny, n_mask, qmap, keys);
+    }
+}
+
+__global__ void fill_keys(unsigned long long *keys, int n_mask, const int32_t *__restrict__ flist) {
+    const size_t total = (size_t)flist[0] * n_mask;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int f = (int)(t / n_mask);
+        keys[(size_t)flist[1 + f] * n_mask + (t - (size_t)f * n_mask)] = ~0ull;
+    }
 }
 
 // General path: per (folded transducer, mask node) interpolate the winning triangle.
-__global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int E,
-                                                      int e0, GridP g, double R, double psi0,
-                                                      int N, double ds, double c0, int n_mask,
-                                                      const int32_t *__restrict__ mask_index,
-                                                      const unsigned long long *__restrict__ keys,
-                                                      rb_tables tb) {
-    size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= (size_t)E * n_mask) return;
-    int el = (int)(tid / n_mask), q = (int)(tid - (size_t)el * n_mask);
-    if (!sb.folded[el]) return;
+__device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, int S, int el,
+                                             int q, int e0, const GridP &g, double ds, double c0,
+                                             int n_mask, const int32_t *__restrict__ mask_index,
+                                             const unsigned long long *__restrict__ keys,
+                                             const rb_tables &tb) {
+    const size_t tid = (size_t)el * n_mask + q;
     int e = e0 + el;
     size_t out = (size_t)e * n_mask + q;
     unsigned long long key = keys[tid];
@@ -584,7 +627,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     const double2 xy = sb.ring[e];
     double xe = xy.x, ye = xy.y;
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
-    double d = sqrt((px - xe) * (px - xe) + (py - ye) * (py - ye));
+    double d = sqrt_newton((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
         write_invalid(tb, out);
         return;
@@ -610,6 +653,21 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
     write_entry(sb, vb, lam, d, c0, tb, out);
+}
+
+__global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int e0,
+                                                      GridP g, double ds, double c0, int n_mask,
+                                                      const int32_t *__restrict__ mask_index,
+                                                      const int32_t *__restrict__ flist,
+                                                      const unsigned long long *__restrict__ keys,
+                                                      rb_tables tb) {
+    const size_t total = (size_t)flist[0] * n_mask;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        const int f = (int)(t / n_mask);
+        resolve_node(sb, n_rays, S, flist[1 + f], (int)(t - (size_t)f * n_mask), e0, g, ds, c0,
+                     n_mask, mask_index, keys, tb);
+    }
 }
 
 // Receiver tables: per emitter, bracket each receiver's angle between neighbouring exit
@@ -783,6 +841,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    rb_align((size_t)C * nr * sizeof(double)) +
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
                    rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
+                   rb_align(sizeof(unsigned long long)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
                    rb_align((size_t)N * sizeof(double2)) +
                    rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
@@ -801,6 +860,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
     int32_t *lost = rb_carve<int32_t>(&ctx->ws, 2);
+    unsigned long long *nsamp = rb_carve<unsigned long long>(&ctx->ws, 1);
+    int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     sb.ring = ringpos;
@@ -812,6 +873,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
     RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
     RB_HIP(ctx, hipMemsetAsync(lost, 0, sizeof(int32_t), ctx->stream));
+    RB_HIP(ctx, hipMemsetAsync(nsamp, 0, sizeof(unsigned long long), ctx->stream));
     hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
                        r->radius, r->psi0, N, ringpos);
     RB_CHECK_LAUNCH(ctx);
@@ -827,18 +889,18 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         rb_prof_begin(ctx, ST_TRACE);
         hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
                            smap, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0,
-                           e0, E, sb, ctx->d_flag);
+                           e0, E, sb, ctx->d_flag, nsamp);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // unfolded fans: direct walk per (transducer, node)
-        size_t nk = (size_t)E * n_mask;
         rb_prof_begin(ctx, ST_RESOLVE);
         int ntiles = ctx->tiles_x * ctx->tiles_y;
         hipLaunchKernelGGL(tile_offset_kernel, dim3((E * ntiles + 255) / 256), dim3(256), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->psi0, N, tp->ds, ctx->tile_i0,
                            ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, toff);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(locate_kernel, dim3(ntiles, E), dim3(LTX * LTY), 0, ctx->stream, sb, nr,
+        hipLaunchKernelGGL(locate_kernel, dim3((ntiles + 7) / 8 * 8, E), dim3(LTX * LTY), 0,
+                           ctx->stream, sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
                            toff, *out, lost);
@@ -846,16 +908,16 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation and resolve
         rb_prof_begin(ctx, ST_RASTER);
-        hipLaunchKernelGGL(fill_keys, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
-                           ctx->stream, keys, nk, n_mask, sb.folded);
+        hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
         RB_CHECK_LAUNCH(ctx);
-        size_t nquad = (size_t)E * S * (nr - 1);
-        hipLaunchKernelGGL(raster_kernel, dim3((unsigned)((nquad + 255) / 256)), dim3(256), 0,
-                           ctx->stream, sb, nr, S, E, g->nx, g->ny, n_mask, ctx->d_qmap, keys);
+        hipLaunchKernelGGL(fill_keys, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, keys, n_mask,
+                           flist);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(resolve_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0,
-                           ctx->stream, sb, nr, S, E, e0, gp, r->radius, r->psi0, N, tp->ds,
-                           tp->c0, n_mask, ctx->d_mask_index, keys, *out);
+        hipLaunchKernelGGL(raster_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
+                           g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys);
+        RB_CHECK_LAUNCH(ctx);
+        hipLaunchKernelGGL(resolve_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
+                           e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys, *out);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         rb_prof_begin(ctx, ST_RECEIVERS);
@@ -869,8 +931,11 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                                ctx->stream));
     RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag + 1, lost, sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag + 2, nsamp, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, ctx->stream));
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->lost_nodes = ctx->h_flag[1];
+    ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + 2);
     if (*ctx->h_flag & 1)
         return rb_fail(ctx, RB_ENONFINITE, "a ray did not reach the ring within max_steps=%d",
                        tp->max_steps);

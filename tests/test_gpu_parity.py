@@ -111,6 +111,26 @@ def test_trace_rays_is_deterministic(ctx):
         assert torch.equal(x, y)
 
 
+def test_trace_samples_count(ctx):
+    # The tracer's unit of work: samples per ray are M + 1 (Definition 1 sampling, the source
+    # sample included). A ray whose last full step lands within rounding of the ring may take
+    # one step more or less on one side.
+    import torch
+
+    from oracle.trace import trace
+
+    st, c = case("small")
+    grid, ring, tp = abi_structs(st)
+    ns = oracle_tables("small")[1]
+    s = trace(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps, c0=st.c0)
+    expect = int(np.sum(s.M[s.valid] + 1))
+    ctx.trace_rays(grid, ring, tp, torch.as_tensor(ns.astype(np.float32), device="cuda:0"))
+    torch.cuda.synchronize()
+    got = ctx.trace_samples()
+    _say(f"trace samples {got} (oracle {expect})")
+    assert abs(got - expect) <= 2
+
+
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("f", [150e3, 800e3])
 def test_build_green(ctx, name, f):
