@@ -475,9 +475,8 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
 
 // One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
-// Workgroups are dealt to the 8 XCDs round-robin; the x extent of the launch is a multiple of
-// 8 and each XCD gets a contiguous band of tiles, so neighbouring tiles share the ray
-// samples through one L2.
+// Tiles go to the XCDs round-robin in launch order, which balances the disk-shaped mask over
+// them (contiguous bands per XCD measured slower).
 __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
@@ -488,7 +487,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const int el = blockIdx.y;
     if (sb.folded[el]) return;  // general path (uniform over the block)
     const int ntiles = tiles_x * tiles_y;
-    const int t = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int t = blockIdx.x;
     if (t >= ntiles) return;
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
@@ -899,8 +898,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            ctx->stream, sb, nr, S, E, e0, gp, r->psi0, N, tp->ds, ctx->tile_i0,
                            ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, toff);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(locate_kernel, dim3((ntiles + 7) / 8 * 8, E), dim3(LTX * LTY), 0,
-                           ctx->stream, sb, nr,
+        hipLaunchKernelGGL(locate_kernel, dim3(ntiles, E), dim3(LTX * LTY), 0, ctx->stream, sb,
+                           nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
                            toff, *out, lost);
