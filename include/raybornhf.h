@@ -108,7 +108,7 @@ typedef struct {
  *   RB_BF16, RB_F16 (16-bit operands, FP32 accumulation in every contraction):
  *            G planar [2 (re, im)][n][n_mask];  H planar, node-major
  *            [3][2 (re, im)][n_mask][n_pad] (transducer index contiguous), n_pad = n
- *            rounded up to a multiple of 8; rb_build_green writes zeros past n. */
+ *            rounded up to a multiple of 32; rb_build_green writes zeros past n. */
 typedef struct {
     int32_t n;
     int32_t n_mask;

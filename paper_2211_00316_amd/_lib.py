@@ -160,7 +160,7 @@ class Green:
 
     RB_F32: G complex64 [n][n_mask], H complex64 [3][n][n_mask].
     RB_BF16 / RB_F16: G planar [2][n][n_mask], H planar node-major [3][2][n_mask][n_pad]
-    (n_pad = n rounded up to 8)."""
+    (n_pad = n rounded up to 32)."""
 
     G: torch.Tensor
     H: torch.Tensor
@@ -172,7 +172,7 @@ class Green:
             return cls(torch.empty(n, n_mask, dtype=torch.complex64, device=device),
                        torch.empty(3, n, n_mask, dtype=torch.complex64, device=device), prec)
         dt = _LP_DTYPE[prec]
-        n_pad = (n + 7) // 8 * 8
+        n_pad = (n + 31) // 32 * 32
         return cls(torch.empty(2, n, n_mask, dtype=dt, device=device),
                    torch.empty(3, 2, n_mask, n_pad, dtype=dt, device=device), prec)
 

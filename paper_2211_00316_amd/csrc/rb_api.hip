@@ -361,7 +361,7 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
     int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
     size_t nn = (size_t)gr->n * gr->n;
     ctx->ws.used = 0;
-    const size_t nnp = (size_t)gr->n * ((gr->n + 7) & ~7);
+    const size_t nnp = (size_t)gr->n * rb_lp_pad(gr->n);
     RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
                                                rb_align(2 * nnp * sizeof(uint16_t)) + rb_align(8)));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
@@ -408,8 +408,8 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     const int nm = (int)ctx->n_mask;
     const size_t P = (size_t)grid->nx * grid->ny;
     const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
-    const size_t NPp = (size_t)((N + 7) & ~7) * nm;  // padded operand rows (16-bit form)
-    const size_t NNp = (size_t)((N + 7) & ~7) * N;
+    const size_t NPp = (size_t)rb_lp_pad(N) * nm;  // padded operand rows (16-bit form)
+    const size_t NNp = (size_t)rb_lp_pad(N) * N;
     const bool lp = prec != RB_F32;
     const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand

@@ -74,6 +74,10 @@ rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...);
 // Ensure the arena holds at least `bytes` (reallocates, dropping old contents).
 rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes);
 inline size_t rb_align(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Transducer dimension of the 16-bit operand rows (H, residual): a whole number of 32-deep
+// contraction steps, zeros past n.
+__host__ __device__ inline int rb_lp_pad(int n) { return (n + 31) & ~31; }
 template <typename T> T *rb_carve(rb_arena *a, size_t count) {
     T *p = reinterpret_cast<T *>(a->base + a->used);
     a->used += rb_align(count * sizeof(T));

@@ -13,8 +13,8 @@
 //   Ht  [3][2][P_m][Np]  H, H u_x, H u_y transposed (node-major, transducer-contiguous): the
 //                        back-projection Y_c = R H_c contracts over transducers;
 //   Rp  [2][N][Np]       residual rows.
-// Np = N rounded up to a multiple of 8 (zeros beyond N), so that every operand row starts
-// 16-byte aligned and the contraction loads only full 16-byte chunks.
+// Np = N rounded up to a multiple of 32 (zeros beyond N), so that every operand row starts
+// 16-byte aligned and the contraction runs over whole 32-deep steps.
 // The green kernel transposes H through LDS so that both layouts are written coalesced.
 #include "rb_internal.h"
 
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = blockIdx.x * GQ + lane;
     const int e0 = blockIdx.y * GE + w * GW;
-    const int Np = (N + 7) & ~7;
+    const int Np = rb_lp_pad(N);
     if (q >= n_mask || e0 >= Np) return;  // no barrier in this kernel
     // rows e0 - 1 .. e0 + GW (indices mod N)
     float ux[GW + 2], uy[GW + 2];
@@ -229,18 +229,80 @@ __global__ void unscale_kernel(float *__restrict__ parts, size_t count,
 
 // Back-projection: Y_c = R H_c, epilogue sums over the tile's rows of H_c[e][q] Y_c[e][q] --
 // Workgroup tile 256 (transducers e) x 128 (nodes q), four waves of 128 x 64 complex (eight
-// 32 x 32 MFMA tiles, 256 FP32 accumulators per lane). K (transducers r) in steps of 32,
-// double-buffered in LDS with one barrier per step; the next step's operands are fetched
-// into registers while the current one is multiplied.
+// 32 x 32 MFMA tiles, 256 FP32 accumulators per lane). K (transducers r) in steps of 32
+// (two MFMA sub-steps of 16), double-buffered in LDS with one barrier per step. Software
+// pipeline: the MFMA fragments of the next sub-step are read from LDS while the current
+// sub-step's MFMAs run (across the barrier for the first sub-step of the next tile), and the
+// global operands of step k+2 are fetched into registers during step k.
+// Global operands are read through one wave-uniform buffer descriptor per operand spanning
+// its two part planes (loads past the end return zero); rows are whole K steps long. Rows
+// past the last transducer or node read other (finite) data: they only reach output rows
+// that meet zero padding or are never stored.
 constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_LD = LR_BK + 8;
+constexpr int LR_THREADS = 256;
+// part planes padded by 64 bytes so that the two parts a loader group stores fall on
+// different LDS banks
+constexpr int LR_APLANE = LR_BM * LR_LD + 32, LR_BPLANE = LR_BN * LR_LD + 32;
+constexpr size_t LR_SPAN = 0xfffffff0u;  // vector + scalar byte offsets stay below this
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ uint4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(uint4,
+                              __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
+}
+
+// MFMA operands of one 16-deep sub-step of a wave: A rows (re, im) of its four 32-row
+// tiles, B columns (re, im, -im) of its two 32-column tiles.
+struct LrFrag {
+    uint4 ar[4], ai[4], br[2], bi[2], bn[2];
+};
 
 template <typename T>
-__global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp,
-                                                        const T *__restrict__ Ht, int n,
-                                                        int n_cols, int n_comp, int mblocks,
-                                                        int nblocks, float *__restrict__ parts) {
-    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_BM][LR_LD];
-    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BN][LR_LD];
+__device__ __forceinline__ void lr_read(LrFrag &f, const T *a0, const T *a1, const T *b0,
+                                        const T *b1, int wm, int wn, int lane, int ks) {
+    const int kk = ks + (lane >> 5) * 8;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int o = (wn * 64 + nt * 32 + (lane & 31)) * LR_LD + kk;
+        f.br[nt] = *reinterpret_cast<const uint4 *>(b0 + o);
+        f.bi[nt] = *reinterpret_cast<const uint4 *>(b1 + o);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int o = (wm * 128 + mt * 32 + (lane & 31)) * LR_LD + kk;
+        f.ar[mt] = *reinterpret_cast<const uint4 *>(a0 + o);
+        f.ai[mt] = *reinterpret_cast<const uint4 *>(a1 + o);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[4][2],
+                                        floatx16 (&acc_im)[4][2]) {
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) f.bn[nt] = neg8(f.bi[nt]);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(f.ar[mt]), as_vec<T>(f.br[nt]), acc_re[mt][nt]);
+            acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(f.ar[mt]), as_vec<T>(f.bi[nt]), acc_im[mt][nt]);
+            acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(f.ai[mt]), as_vec<T>(f.bn[nt]), acc_re[mt][nt]);
+            acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(f.ai[mt]), as_vec<T>(f.br[nt]), acc_im[mt][nt]);
+        }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restrict__ Rp,
+                                                               const T *__restrict__ Ht, int n,
+                                                               int n_cols, int n_comp,
+                                                               int mblocks, int nblocks,
+                                                               float *__restrict__ parts) {
+    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
+    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
     __shared__ float red[2][2][LR_BN];
 
     const int total = mblocks * nblocks;
@@ -253,26 +315,26 @@ __global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 64
     const int row0 = mb * LR_BM, col0 = nb * LR_BN;
-    const int np = (n + 7) & ~7;  // padded row length (zeros past n)
+    const int np = rb_lp_pad(n);  // padded row length (zeros past n), a multiple of LR_BK
     const size_t rplane = (size_t)n * np;
     const size_t hplane = (size_t)n_cols * np;
-    const int KT = (np + LR_BK - 1) / LR_BK;
+    const int KT = np / LR_BK;
 
     float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
 
-    // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row
-    // (tid >> 3) + 32 u; A rows u = 0..7, B rows u = 0..3.
+    // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row (tid >> 3) +
+    // 32 u; A rows u = 0..7, B rows u = 0..3. Byte offsets within the operand's planes.
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
-    const T *a_src = Rp + l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8;
-    const size_t a_step = (size_t)32 * np;
-    uint32_t a_ok = 0, b_ok = 0;  // rows inside the matrix
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a_ok |= (row0 + l_row + 32 * u < n) ? (1u << u) : 0u;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) b_ok |= (col0 + l_row + 32 * u < n_cols) ? (1u << u) : 0u;
+    const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
+    const uint32_t a_off =
+        (uint32_t)((l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8) * sizeof(T));
+    const uint32_t b_off =
+        (uint32_t)((l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8) * sizeof(T));
+    const uint32_t row_step = (uint32_t)(32 * (size_t)np * sizeof(T));
 
     for (int c = 0; c < n_comp; ++c) {
         const T *Hc = Ht + (size_t)(2 * c) * hplane;
+        const __amdgpu_buffer_rsrc_t rb_rsrc = plane_rsrc(Hc, 2 * hplane * sizeof(T));
         floatx16 acc_re[4][2], acc_im[4][2];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
@@ -283,76 +345,48 @@ __global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp
                     acc_re[mt][nt][i] = 0.f;
                     acc_im[mt][nt][i] = 0.f;
                 }
-        // A: 256 rows x 2 parts x 4 chunks (8 per thread); B: 128 x 2 x 4 (4 per thread)
-        const T *b_src = Hc + l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8;
         uint4 ra[8], rb[4];
-        auto fetch = [&](int kt) {
-            const int k0 = kt * LR_BK;
-            const bool kin = k0 + l_ch * 8 < np;
+        auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
+            const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                ra[u] = (kin && (a_ok >> u & 1u))
-                            ? *reinterpret_cast<const uint4 *>(a_src + u * a_step + k0)
-                            : make_uint4(0, 0, 0, 0);
+            for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                rb[u] = (kin && (b_ok >> u & 1u))
-                            ? *reinterpret_cast<const uint4 *>(b_src + (size_t)u * 32 * np + k0)
-                            : make_uint4(0, 0, 0, 0);
+            for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
         };
         auto stash = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                *reinterpret_cast<uint4 *>(&a_s[buf][l_part][l_row + 32 * u][l_ch * 8]) = ra[u];
+                *reinterpret_cast<uint4 *>(
+                    &a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = ra[u];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                *reinterpret_cast<uint4 *>(&b_s[buf][l_part][l_row + 32 * u][l_ch * 8]) = rb[u];
+                *reinterpret_cast<uint4 *>(
+                    &b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = rb[u];
         };
         fetch(0);
         stash(0);
         if (KT > 1) fetch(1);
         __syncthreads();
+        LrFrag f0, f1;
+        lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
         for (int kt = 0; kt < KT; ++kt) {
             const int cur = kt & 1;
-#pragma unroll 1
-            for (int ks = 0; ks < LR_BK; ks += 16) {
-                int kk = ks + (lane >> 5) * 8;
-                uint4 br[2], bi[2];
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    int cn = wn * 64 + nt * 32 + (lane & 31);
-                    br[nt] = *reinterpret_cast<const uint4 *>(&b_s[cur][0][cn][kk]);
-                    bi[nt] = *reinterpret_cast<const uint4 *>(&b_s[cur][1][cn][kk]);
-                }
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    int m = wm * 128 + mt * 32 + (lane & 31);
-                    uint4 ar = *reinterpret_cast<const uint4 *>(&a_s[cur][0][m][kk]);
-                    uint4 ai = *reinterpret_cast<const uint4 *>(&a_s[cur][1][m][kk]);
-                    uint4 nai = neg8(ai);
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) {
-                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(ar), as_vec<T>(br[nt]),
-                                                     acc_re[mt][nt]);
-                        acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(nai), as_vec<T>(bi[nt]),
-                                                     acc_re[mt][nt]);
-                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ar), as_vec<T>(bi[nt]),
-                                                     acc_im[mt][nt]);
-                        acc_im[mt][nt] = Lp<T>::mfma(as_vec<T>(ai), as_vec<T>(br[nt]),
-                                                     acc_im[mt][nt]);
-                    }
-                }
-            }
+            lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
+            lr_mfma<T>(f0, acc_re, acc_im);
             if (kt + 1 < KT) stash(cur ^ 1);   // tile kt+1 into the idle buffer
             if (kt + 2 < KT) fetch(kt + 2);    // tile kt+2 into registers
             __syncthreads();
+            if (kt + 1 < KT)
+                lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0],
+                           b_s[cur ^ 1][1], wm, wn, lane, 0);
+            lr_mfma<T>(f1, acc_re, acc_im);
         }
         // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
-        // 8-byte load per part (rows are padded with zeros to np, a multiple of 8, and
+        // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
         // rows beyond n carry Y = 0)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-            int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
+            const int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
             if (gq >= n_cols) continue;
             const T *er_row = Hc + (size_t)gq * np;
             const T *ei_row = Hc + hplane + (size_t)gq * np;
@@ -360,22 +394,23 @@ __global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
+                    const int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
                     if (ge >= np) continue;
-                    uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
-                    uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
+                    const uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
+                    const uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
                     T vr[4], vi[4];
                     __builtin_memcpy(vr, &pr, 8);
                     __builtin_memcpy(vi, &pi, 8);
 #pragma unroll
                     for (int z = 0; z < 4; ++z) {
-                        float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
-                        float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
+                        const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
+                        const float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
                         cs_re[nt] += er * yr - ei * yi;
                         cs_im[nt] += er * yi + ei * yr;
                     }
                 }
         }
+        __syncthreads();  // LDS buffers are refilled by the next component
     }
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -388,7 +423,7 @@ __global__ void __launch_bounds__(256) rowred_lp_kernel(const T *__restrict__ Rp
     }
     __syncthreads();
     if (tid < LR_BN) {
-        int gc = col0 + tid;
+        const int gc = col0 + tid;
         if (gc < n_cols) {
             parts[(size_t)mb * n_cols + gc] = red[0][0][tid] + red[0][1][tid];
             parts[(size_t)(mblocks + mb) * n_cols + gc] = red[1][0][tid] + red[1][1][tid];
@@ -585,7 +620,7 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
                               float *scale) {
     size_t nn = (size_t)n * n;
-    const int np = (n + 7) & ~7;
+    const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
     hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
                        (const float2 *)R, nn, (const float *)nullptr, 14, scale);
@@ -625,13 +660,21 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
     int nblocks = (n_mask + LR_BN - 1) / LR_BN;
     int total = mblocks * nblocks;
     int grid = ((total + 7) / 8) * 8;
+    // byte offsets into the two part planes of an operand, padding rows included, must stay
+    // below LR_SPAN (32-bit buffer offsets)
+    const size_t np = (size_t)rb_lp_pad(n);
+    const size_t span = (2 * (size_t)n_mask + LR_BN + (size_t)mblocks * LR_BM) * np * 2 + 64;
+    if (span >= LR_SPAN)
+        return rb_fail(ctx, RB_EUNSUPPORTED,
+                       "16-bit back-projection: H planes of %d nodes x %zu exceed 4 GiB",
+                       n_mask, np);
     rb_prof_begin(ctx, ST_BACKPROJECT);
     if (prec == RB_BF16)
-        hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(LR_THREADS), 0, ctx->stream,
                            (const __bf16 *)Rp, (const __bf16 *)Ht, n, n_mask, n_comp, mblocks,
                            nblocks, parts);
     else
-        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(LR_THREADS), 0, ctx->stream,
                            (const _Float16 *)Rp, (const _Float16 *)Ht, n, n_mask, n_comp, mblocks,
                            nblocks, parts);
     RB_CHECK_LAUNCH(ctx);
