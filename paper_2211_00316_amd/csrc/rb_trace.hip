@@ -365,6 +365,7 @@ __device__ __forceinline__ void write_invalid(const rb_tables &tb, size_t out) {
 // mesh or does not settle within LOCATE_MAX_IT quads.
 constexpr int LOCATE_MAX_IT = 96;
 constexpr int LTX = 32, LTY = 8;  // node tile of one locate workgroup
+constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
                                           size_t ebase, int n_rays, float pu, float pv, int &j,
@@ -475,8 +476,10 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
 
 // One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
-// Tiles go to the XCDs round-robin in launch order, which balances the disk-shaped mask over
-// them (contiguous bands per XCD measured slower).
+// Workgroups are dealt to the 8 XCDs round-robin by launch index. The (transducer, tile)
+// sequence is cut into groups of LOCATE_GROUP_ROWS tile rows and group g goes to XCD g mod 8,
+// so neighbouring tiles share their ray samples through one L2 while every XCD still gets an
+// even mix of the disk-shaped mask. The launch is padded to a multiple of 8 groups.
 __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
@@ -484,11 +487,13 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                                                      int tiles_y, const int32_t *__restrict__ qmap,
                                                      const int2 *__restrict__ off, rb_tables tb,
                                                      int *lost) {
-    const int el = blockIdx.y;
-    if (sb.folded[el]) return;  // general path (uniform over the block)
     const int ntiles = tiles_x * tiles_y;
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
+    const int G = LOCATE_GROUP_ROWS * tiles_x;
+    const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
+    const int item = ((k / G) * 8 + xcd) * G + k % G;
+    if (item >= E * ntiles) return;
+    const int el = item / ntiles, t = item - el * ntiles;
+    if (sb.folded[el]) return;  // general path (uniform over the block)
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
@@ -898,8 +903,11 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            ctx->stream, sb, nr, S, E, e0, gp, r->psi0, N, tp->ds, ctx->tile_i0,
                            ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, toff);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(locate_kernel, dim3(ntiles, E), dim3(LTX * LTY), 0, ctx->stream, sb,
-                           nr,
+        const long G = (long)LOCATE_GROUP_ROWS * ctx->tiles_x;
+        const long groups = ((long)E * ntiles + G - 1) / G;
+        const long nblk = (groups + 7) / 8 * 8 * G;
+        hipLaunchKernelGGL(locate_kernel, dim3((unsigned)nblk), dim3(LTX * LTY), 0, ctx->stream,
+                           sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
                            toff, *out, lost);
