@@ -201,6 +201,28 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             const float *data, double tau, rb_mode mode, rb_prec prec,
                             double *residual_norm);
 
+/* Several frequency steps in a row: the frequency continuation of Section 6.3.2 (one step
+ * per frequency set, sets ordered low to high by the caller). Step k uses smoothing window
+ * smooth_w[k] and the next n_omega[k] entries of omega / d_omega (HOST arrays, sets
+ * concatenated) with the matching [n][n] slices of data (complex64, one slice per frequency,
+ * in the same order). No step synchronises with the host: a ray exceeding max_steps or a
+ * non-finite update is recorded on the device, that step and every later one commit
+ * nothing (c keeps the model from before the failing step), and the call returns
+ * RB_ENONFINITE naming the step after the last kernel. residual_norms: device
+ * double[n_steps] (per-step sum |g_res|^2) or NULL.
+ * use_graph != 0: the whole sweep is captured into one HIP graph on a stream of the
+ * library and replayed on the context's stream (one launch for all steps). The graph is
+ * kept in the context and replayed while the arguments (pointer values included) and the
+ * context's workspace are unchanged; otherwise it is captured again. The caller keeps c,
+ * data and residual_norms valid between replays. Returns after the last kernel (the
+ * host waits for the context's stream). */
+rb_status rb_frequency_sweep(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                             const rb_trace_params *tp, double *c, int32_t n_steps,
+                             const int32_t *smooth_w, const int32_t *n_omega,
+                             const double *omega, const double *d_omega, const float *data,
+                             double tau, rb_mode mode, rb_prec prec, int32_t use_graph,
+                             double *residual_norms);
+
 /* Measurement: per-stage GPU time from HIP events recorded around every kernel launch on
  * the context's stream while profiling is on (small overhead; off by default). Stages are
  * numbered 0 .. RB_N_STAGES-1 (rb_stage_name). rb_profile_read synchronizes the stream,

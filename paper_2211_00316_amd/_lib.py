@@ -23,7 +23,7 @@ SYMBOLS = (
     "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
-    "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples",
+    "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
 )
 N_STAGES = 12
 
@@ -91,6 +91,10 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(TraceParams), P, I32, I32,
                                ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int,
                                ctypes.c_int, P], ctypes.c_int),
+        "rb_frequency_sweep": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                                ctypes.POINTER(TraceParams), P, I32, ctypes.POINTER(I32),
+                                ctypes.POINTER(I32), ctypes.POINTER(D), ctypes.POINTER(D), P, D,
+                                ctypes.c_int, ctypes.c_int, I32, P], ctypes.c_int),
         "rb_profile_enable": ([P, I32], ctypes.c_int),
         "rb_profile_read": ([P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "rb_stage_name": ([I32], ctypes.c_char_p),
@@ -333,4 +337,33 @@ class Context:
             self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
             int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), int(prec),
             _ptr(residual_norm)))
+        return c
+
+    def frequency_sweep(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
+                        smooth_ws, omega_sets, d_omega_sets, data: torch.Tensor, tau: float,
+                        mode: int = RB_RAY_BORN, prec: int = RB_F32, use_graph: bool = False,
+                        residual_norms: torch.Tensor | None = None):
+        """Steps k = 0.. of the frequency continuation in one call (no host synchronisation
+        between steps; one graph launch with use_graph). omega_sets[k], d_omega_sets[k]: the
+        frequencies of step k; data: complex64 [total frequencies][n][n] in the same order.
+        Updates c (float64 [ny][nx], on the GPU) in place."""
+        _dev(c, torch.float64)
+        _dev(data, torch.complex64)
+        n = len(omega_sets)
+        if len(smooth_ws) != n or len(d_omega_sets) != n:
+            raise ValueError("one window, frequency set and spacing set per step")
+        flat = [float(o) for s in omega_sets for o in s]
+        dflat = [float(o) for s in d_omega_sets for o in s]
+        if data.shape[0] != len(flat):
+            raise ValueError(f"data holds {data.shape[0]} frequencies, the steps use {len(flat)}")
+        if residual_norms is not None:
+            _dev(residual_norms, torch.float64)
+        sw = (ctypes.c_int32 * n)(*[int(w) for w in smooth_ws])
+        no = (ctypes.c_int32 * n)(*[len(s) for s in omega_sets])
+        om = (ctypes.c_double * len(flat))(*flat)
+        dom = (ctypes.c_double * len(dflat))(*dflat)
+        self._check(self.lib.rb_frequency_sweep(
+            self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c), n, sw,
+            no, om, dom, _ptr(data), float(tau), int(mode), int(prec), int(bool(use_graph)),
+            _ptr(residual_norms)))
         return c

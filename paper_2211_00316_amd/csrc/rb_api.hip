@@ -17,7 +17,8 @@ rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float
 rb_status rb_launch_zero_f64(rb_ctx *ctx, double *x, int n);
 rb_status rb_launch_update(rb_ctx *ctx, const double *cq, const double *dm, double tau,
                            double *c_new);
-rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c);
+rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c, const int32_t *flag);
+rb_status rb_launch_note_fail(rb_ctx *ctx, int step);
 
 rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...) {
     if (ctx) {
@@ -52,6 +53,11 @@ void rb_prof_end(rb_ctx *ctx) {
 
 rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes) {
     if (bytes <= a->cap) return RB_OK;
+    if (ctx->capturing) {  // no allocation inside a graph capture: grow it and capture again
+        a->want = std::max(a->want, bytes);
+        return RB_ERETRY;
+    }
+    ++ctx->gen;
     if (a->base) {
         // kernels queued on the stream may still read the old block
         RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -128,6 +134,8 @@ static int64_t mask_list(const rb_grid *g, std::vector<int32_t> *idx, std::vecto
 
 rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
     if (ctx->have_grid && std::memcmp(&ctx->grid, g, sizeof(rb_grid)) == 0) return RB_OK;
+    if (ctx->capturing) return rb_fail(ctx, RB_EINVAL, "grid changed inside a graph capture");
+    ++ctx->gen;
     std::vector<int32_t> idx, map;
     int64_t n = mask_list(g, &idx, &map);
     if (n < 1) return rb_fail(ctx, RB_EINVAL, "the imaging mask holds no grid node");
@@ -181,11 +189,28 @@ static rb_status check_green(rb_ctx *ctx, const rb_green *gr) {
     return RB_OK;
 }
 
-#define RB_TRY(x)                       \
-    do {                                \
-        rb_status s_ = (x);             \
-        if (s_ != RB_OK) return s_;     \
-    } while (0)
+static rb_status check_step_args(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                                 const rb_trace_params *tp, const double *c, int32_t smooth_w,
+                                 int32_t n_omega, const double *omega, const double *d_omega,
+                                 const float *data, double tau, rb_mode mode, rb_prec prec) {
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    RB_TRY(rb_check_trace(ctx, tp));
+    if (!c || !data) return rb_fail(ctx, RB_EINVAL, "c and data must be device pointers");
+    if (n_omega < 1 || !omega || !d_omega)
+        return rb_fail(ctx, RB_EINVAL, "need at least one frequency (host arrays)");
+    for (int k = 0; k < n_omega; ++k)
+        if (!finite_pos(omega[k]) || !finite_pos(d_omega[k]))
+            return rb_fail(ctx, RB_EINVAL, "frequencies and spacings must be positive");
+    if (smooth_w < 1 || (smooth_w & 1) == 0)
+        return rb_fail(ctx, RB_EINVAL, "smoothing window must be odd and >= 1");
+    if (!std::isfinite(tau)) return rb_fail(ctx, RB_EINVAL, "tau must be finite");
+    if (mode != RB_RAY_BORN && mode != RB_RAY_ONLY)
+        return rb_fail(ctx, RB_EINVAL, "unknown mode");
+    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
+    return RB_OK;
+}
 
 extern "C" {
 
@@ -201,8 +226,10 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
     rb_ctx *ctx = new rb_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipMalloc(&ctx->d_flag, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(&ctx->h_flag, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipMalloc(&ctx->d_flag, RB_W_COUNT * sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(&ctx->h_flag, RB_W_COUNT * sizeof(int32_t), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMemset(ctx->d_flag, 0, RB_W_COUNT * sizeof(int32_t)) != hipSuccess) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
@@ -219,6 +246,8 @@ void rb_destroy(rb_ctx *ctx) {
     if (ctx->d_mask_index) (void)hipFree(ctx->d_mask_index);
     if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     for (int i = 0; i < ctx->n_ev_created; ++i) {
         (void)hipEventDestroy(ctx->ev[i][0]);
@@ -379,29 +408,13 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
                                         accumulate);
 }
 
-rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
-                            const rb_trace_params *tp, double *c, int32_t smooth_w,
-                            int32_t n_omega, const double *omega, const double *d_omega,
-                            const float *data, double tau, rb_mode mode, rb_prec prec,
-                            double *residual_norm) {
-    if (!ctx) return RB_EINVAL;
-    RB_TRY(rb_check_grid(ctx, grid));
-    RB_TRY(rb_check_ring(ctx, grid, ring));
-    RB_TRY(rb_check_trace(ctx, tp));
-    if (!c || !data) return rb_fail(ctx, RB_EINVAL, "c and data must be device pointers");
-    if (n_omega < 1 || !omega || !d_omega)
-        return rb_fail(ctx, RB_EINVAL, "need at least one frequency (host arrays)");
-    for (int k = 0; k < n_omega; ++k)
-        if (!finite_pos(omega[k]) || !finite_pos(d_omega[k]))
-            return rb_fail(ctx, RB_EINVAL, "frequencies and spacings must be positive");
-    if (smooth_w < 1 || (smooth_w & 1) == 0)
-        return rb_fail(ctx, RB_EINVAL, "smoothing window must be odd and >= 1");
-    if (!std::isfinite(tau)) return rb_fail(ctx, RB_EINVAL, "tau must be finite");
-    if (mode != RB_RAY_BORN && mode != RB_RAY_ONLY)
-        return rb_fail(ctx, RB_EINVAL, "unknown mode");
-    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
-        return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
-    RB_HIP(ctx, hipSetDevice(ctx->device));
+// One frequency step (rows a1-a9) enqueued on ctx->stream. With ctx->deferred nothing
+// synchronises with the host: errors stay in d_flag and the commit kernel checks them.
+static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                              const rb_trace_params *tp, double *c, int32_t smooth_w,
+                              int32_t n_omega, const double *omega, const double *d_omega,
+                              const float *data, double tau, rb_mode mode, rb_prec prec,
+                              double *residual_norm, int step_index) {
     RB_TRY(rb_prepare_grid(ctx, grid));
 
     const int N = ring->n;
@@ -456,7 +469,7 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     RB_TRY(rb_launch_trace(ctx, grid, ring, tp, n_s, &tb));
     RB_TRY(rb_launch_gather_mask(ctx, c, cq));
     RB_TRY(rb_launch_zero_f64(ctx, dm, nm));
-    if (residual_norm) RB_HIP(ctx, hipMemsetAsync(residual_norm, 0, sizeof(double), ctx->stream));
+    if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
     for (int k = 0; k < n_omega; ++k) {
         const double om = omega[k];
         // a4: Green's functions and back-projection operands. In ray_born mode G is
@@ -496,14 +509,185 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
         RB_TRY(rb_launch_backproject_finish_acc(ctx, mbo, parts, cq, om, d_omega[k], dm));
     }
     // a9: model update, committed only if every value is finite
-    RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
+    if (ctx->deferred) {
+        RB_TRY(rb_launch_update(ctx, cq, dm, tau, c_new));
+        RB_TRY(rb_launch_note_fail(ctx, step_index));
+        return rb_launch_commit(ctx, c_new, c, ctx->d_flag);
+    }
+    RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, 1, 0));
     RB_TRY(rb_launch_update(ctx, cq, dm, tau, c_new));
     RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (*ctx->h_flag & 2)
         return rb_fail(ctx, RB_ENONFINITE, "non-finite model update rejected; c unchanged");
-    RB_TRY(rb_launch_commit(ctx, c_new, c));
+    return rb_launch_commit(ctx, c_new, c, nullptr);
+}
+
+
+rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            int32_t n_omega, const double *omega, const double *d_omega,
+                            const float *data, double tau, rb_mode mode, rb_prec prec,
+                            double *residual_norm) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
+                           mode, prec));
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    ctx->deferred = false;
+    return step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
+                        mode, prec, residual_norm, 0);
+}
+
+// The steps of a sweep, enqueued with deferred checks (also the body of the captured graph).
+static rb_status sweep_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                               const rb_trace_params *tp, double *c, int32_t n_steps,
+                               const int32_t *smooth_w, const int32_t *n_omega,
+                               const double *omega, const double *d_omega, const float *data,
+                               double tau, rb_mode mode, rb_prec prec, double *residual_norms) {
+    const size_t NN = (size_t)ring->n * ring->n;
+    RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0));
+    RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_FAIL_STEP, 1, -1));
+    size_t f0 = 0;
+    for (int k = 0; k < n_steps; ++k) {
+        RB_TRY(step_enqueue(ctx, grid, ring, tp, c, smooth_w[k], n_omega[k], omega + f0,
+                            d_omega + f0, data + 2 * NN * f0, tau, mode, prec,
+                            residual_norms ? residual_norms + k : nullptr, k));
+        f0 += (size_t)n_omega[k];
+    }
+    return RB_OK;
+}
+
+static void key_add(std::string &key, const void *p, size_t n) {
+    key.append(static_cast<const char *>(p), n);
+}
+
+// Capture the sweep into a graph on the library stream; workspaces that must grow are grown
+// outside the capture and the capture is redone.
+static rb_status sweep_capture(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                               const rb_trace_params *tp, double *c, int32_t n_steps,
+                               const int32_t *smooth_w, const int32_t *n_omega,
+                               const double *omega, const double *d_omega, const float *data,
+                               double tau, rb_mode mode, rb_prec prec, double *residual_norms,
+                               hipGraphExec_t *exec) {
+    if (!ctx->cap_stream)
+        RB_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        hipStream_t user = ctx->stream;
+        const bool prof = ctx->prof;
+        ctx->stream = ctx->cap_stream;
+        ctx->prof = false;
+        ctx->capturing = true;
+        rb_status st = RB_OK;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess)
+            st = sweep_enqueue(ctx, grid, ring, tp, c, n_steps, smooth_w, n_omega, omega,
+                               d_omega, data, tau, mode, prec, residual_norms);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(ctx->cap_stream, &graph) : e;
+        ctx->capturing = false;
+        ctx->stream = user;
+        ctx->prof = prof;
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return rb_fail(ctx, RB_EDEVICE, "graph capture failed: %s",
+                           hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        if (st == RB_ERETRY) {
+            (void)hipGraphDestroy(graph);
+            RB_TRY(rb_arena_reserve(ctx, &ctx->ws, ctx->ws.want));
+            RB_TRY(rb_arena_reserve(ctx, &ctx->step, ctx->step.want));
+            continue;
+        }
+        if (st != RB_OK) {
+            (void)hipGraphDestroy(graph);
+            return st;
+        }
+        hipError_t e3 = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess)
+            return rb_fail(ctx, RB_EDEVICE, "graph instantiation failed: %s",
+                           hipGetErrorString(e3));
+        return RB_OK;
+    }
+    return rb_fail(ctx, RB_EDEVICE, "graph capture did not settle its workspace");
+}
+
+rb_status rb_frequency_sweep(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                             const rb_trace_params *tp, double *c, int32_t n_steps,
+                             const int32_t *smooth_w, const int32_t *n_omega,
+                             const double *omega, const double *d_omega, const float *data,
+                             double tau, rb_mode mode, rb_prec prec, int32_t use_graph,
+                             double *residual_norms) {
+    if (!ctx) return RB_EINVAL;
+    if (n_steps < 1 || !smooth_w || !n_omega)
+        return rb_fail(ctx, RB_EINVAL, "need n_steps >= 1 and host arrays smooth_w, n_omega");
+    size_t f0 = 0;
+    for (int k = 0; k < n_steps; ++k) {
+        if (n_omega[k] < 1) return rb_fail(ctx, RB_EINVAL, "step %d has no frequency", k);
+        RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w[k], n_omega[k],
+                               omega ? omega + f0 : nullptr, d_omega ? d_omega + f0 : nullptr,
+                               data, tau, mode, prec));
+        f0 += (size_t)n_omega[k];
+    }
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    ctx->deferred = true;
+    rb_status st = RB_OK;
+    if (use_graph) {
+        std::string key;
+        key_add(key, grid, sizeof(*grid));
+        key_add(key, ring, sizeof(*ring));
+        key_add(key, tp, sizeof(*tp));
+        key_add(key, &c, sizeof(c));
+        key_add(key, &n_steps, sizeof(n_steps));
+        key_add(key, smooth_w, n_steps * sizeof(int32_t));
+        key_add(key, n_omega, n_steps * sizeof(int32_t));
+        key_add(key, omega, f0 * sizeof(double));
+        key_add(key, d_omega, f0 * sizeof(double));
+        key_add(key, &data, sizeof(data));
+        key_add(key, &tau, sizeof(tau));
+        key_add(key, &mode, sizeof(mode));
+        key_add(key, &prec, sizeof(prec));
+        key_add(key, &residual_norms, sizeof(residual_norms));
+        std::string full = key;
+        key_add(full, &ctx->gen, sizeof(ctx->gen));
+        if (!ctx->gexec || ctx->gkey != full) {
+            if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+            ctx->gexec = nullptr;
+            ctx->gkey.clear();
+            hipGraphExec_t exec = nullptr;
+            st = sweep_capture(ctx, grid, ring, tp, c, n_steps, smooth_w, n_omega, omega, d_omega,
+                               data, tau, mode, prec, residual_norms, &exec);
+            if (st == RB_OK) {
+                ctx->gexec = exec;
+                ctx->gkey = key;
+                key_add(ctx->gkey, &ctx->gen, sizeof(ctx->gen));
+            }
+        }
+        if (st == RB_OK && hipGraphLaunch(ctx->gexec, ctx->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            st = rb_fail(ctx, RB_EDEVICE, "graph launch failed");
+        }
+    } else {
+        st = sweep_enqueue(ctx, grid, ring, tp, c, n_steps, smooth_w, n_omega, omega, d_omega,
+                           data, tau, mode, prec, residual_norms);
+    }
+    ctx->deferred = false;
+    if (st != RB_OK) return st;
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, RB_W_COUNT * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->lost_nodes = ctx->h_flag[RB_W_LOST];
+    ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + RB_W_SAMPLES);
+    const int32_t fl = ctx->h_flag[RB_W_FLAGS];
+    if (fl)
+        return rb_fail(ctx, RB_ENONFINITE,
+                       "step %d of the sweep failed (%s); c holds the model before it",
+                       ctx->h_flag[RB_W_FAIL_STEP],
+                       (fl & 1) ? "a ray did not reach the ring within max_steps"
+                                : "non-finite model update");
     return RB_OK;
 }
 

@@ -181,11 +181,25 @@ __global__ void update_kernel(const double *__restrict__ cq, const double *__res
     c_new[q] = cn;
 }
 
+// Writes the new model on the mask; with `flag` (deferred checks) only while no error bit
+// is set, so a failed step and every later one leave c as it was.
 __global__ void commit_kernel(const double *__restrict__ c_new,
                               const int32_t *__restrict__ mask_index, int n_mask,
-                              double *__restrict__ c) {
+                              const int32_t *__restrict__ flag, double *__restrict__ c) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n_mask) c[mask_index[q]] = c_new[q];
+    if (q >= n_mask || (flag && flag[RB_W_FLAGS] != 0)) return;
+    c[mask_index[q]] = c_new[q];
+}
+
+// Deferred checks: remember the first step that raised an error bit.
+__global__ void note_fail_kernel(int32_t *flag, int step) {
+    if (threadIdx.x == 0 && flag[RB_W_FLAGS] != 0 && flag[RB_W_FAIL_STEP] < 0)
+        flag[RB_W_FAIL_STEP] = step;
+}
+
+__global__ void fill_i32(int32_t *x, int n, int32_t v) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) x[q] = v;
 }
 
 __global__ void zero_f64(double *x, int n) {
@@ -292,10 +306,22 @@ rb_status rb_launch_update(rb_ctx *ctx, const double *cq, const double *dm, doub
     return RB_OK;
 }
 
-rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c) {
+rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c, const int32_t *flag) {
     int n = (int)ctx->n_mask;
     hipLaunchKernelGGL(commit_kernel, dim3(blocks(n)), dim3(256), 0, ctx->stream, c_new,
-                       ctx->d_mask_index, n, c);
+                       ctx->d_mask_index, n, flag, c);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_note_fail(rb_ctx *ctx, int step) {
+    hipLaunchKernelGGL(note_fail_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_flag, step);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_fill_i32(rb_ctx *ctx, int32_t *x, int n, int32_t value) {
+    hipLaunchKernelGGL(fill_i32, dim3(blocks(n)), dim3(256), 0, ctx->stream, x, n, value);
     RB_CHECK_LAUNCH(ctx);
     return RB_OK;
 }

@@ -18,7 +18,17 @@ struct rb_arena {
     char *base = nullptr;
     size_t cap = 0;
     size_t used = 0;
+    size_t want = 0;  // largest size asked for during a graph capture
 };
+
+// Internal status (never returned through the ABI): a workspace had to grow while a graph
+// was being captured; the capture is discarded, the workspace grown, and the capture redone.
+#define RB_ERETRY ((rb_status)-100)
+
+// Words of rb_ctx::d_flag: error bits (1 ray overflow, 2 non-finite update), index of the
+// first failing step of a sweep, mask nodes the binning could not place, and (as int64 at
+// word 4) the ray samples of the last trace.
+enum { RB_W_FLAGS = 0, RB_W_FAIL_STEP = 1, RB_W_LOST = 2, RB_W_SAMPLES = 4, RB_W_COUNT = 8 };
 
 struct rb_ctx {
     int device = 0;
@@ -43,10 +53,19 @@ struct rb_ctx {
 
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
-    int32_t *d_flag = nullptr;        // device error flags (ray overflow, non-finite update)
-    int32_t *h_flag = nullptr;        // pinned host mirror (flags, lost nodes, int64 samples)
+    int32_t *d_flag = nullptr;        // device words RB_W_* (flags, counters)
+    int32_t *h_flag = nullptr;        // pinned host mirror of d_flag
     int64_t lost_nodes = 0;           // mask nodes the last binning could not place
     int64_t ray_samples = 0;          // ray samples written by the last trace
+
+    // Deferred checks (rb_frequency_sweep): no host synchronisation inside a step; errors
+    // stay in d_flag and the commit kernel skips the update once any is set.
+    bool deferred = false;
+    bool capturing = false;           // a graph capture is in progress on `stream`
+    uint64_t gen = 0;                 // bumped whenever a device buffer is reallocated
+    hipStream_t cap_stream = nullptr; // library stream the sweep is captured on
+    hipGraphExec_t gexec = nullptr;   // cached sweep graph
+    std::string gkey;                 // the arguments (and gen) it was captured with
 };
 
 // Stages timed by the profiler (order = rb_stage_name).
@@ -54,6 +73,8 @@ enum rb_stage {
     ST_SMOOTH = 0, ST_TRACE, ST_RASTER, ST_RESOLVE, ST_RECEIVERS, ST_GREEN, ST_FORWARD,
     ST_FORWARD_REDUCE, ST_RESIDUAL, ST_BACKPROJECT, ST_FINISH, ST_UPDATE
 };
+// Fill n int32 words with a value (a kernel: also inside graph captures).
+rb_status rb_launch_fill_i32(rb_ctx *ctx, int32_t *x, int n, int32_t value);
 // Record the start / end event of a launch of `stage` (no-ops unless profiling is on).
 void rb_prof_begin(rb_ctx *ctx, int stage);
 void rb_prof_end(rb_ctx *ctx);
@@ -69,6 +90,12 @@ rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...);
     } while (0)
 
 #define RB_CHECK_LAUNCH(ctx) RB_HIP(ctx, hipGetLastError())
+
+#define RB_TRY(x)                       \
+    do {                                \
+        rb_status s_ = (x);             \
+        if (s_ != RB_OK) return s_;     \
+    } while (0)
 
 // Workspace -------------------------------------------------------------------------------
 // Ensure the arena holds at least `bytes` (reallocates, dropping old contents).

@@ -844,8 +844,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    rb_align((size_t)C * nr * sizeof(int32_t)) +
                    rb_align((size_t)C * nr * sizeof(double)) +
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
-                   rb_align((size_t)C * sizeof(int32_t)) + rb_align(2 * sizeof(int32_t)) +
-                   rb_align(sizeof(unsigned long long)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
+                   rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
                    rb_align((size_t)N * sizeof(double2)) +
                    rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
@@ -863,8 +862,6 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.ex_L = rb_carve<float>(&ctx->ws, (size_t)C * nr);
     sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
-    int32_t *lost = rb_carve<int32_t>(&ctx->ws, 2);
-    unsigned long long *nsamp = rb_carve<unsigned long long>(&ctx->ws, 1);
     int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
@@ -875,9 +872,11 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     SplineMap smap{padded, g->nx, g->ny, nxp, (float)(1.0 / g->dx)};
 
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
-    RB_HIP(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
-    RB_HIP(ctx, hipMemsetAsync(lost, 0, sizeof(int32_t), ctx->stream));
-    RB_HIP(ctx, hipMemsetAsync(nsamp, 0, sizeof(unsigned long long), ctx->stream));
+    // counters of this trace; the error bits start clear unless a sweep collects them
+    int32_t *lost = ctx->d_flag + RB_W_LOST;
+    unsigned long long *nsamp = reinterpret_cast<unsigned long long *>(ctx->d_flag + RB_W_SAMPLES);
+    if (!ctx->deferred) RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0));
+    else RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_LOST, RB_W_COUNT - RB_W_LOST, 0));
     hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
                        r->radius, r->psi0, N, ringpos);
     RB_CHECK_LAUNCH(ctx);
@@ -934,16 +933,13 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
     }
-    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag + 1, lost, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag + 2, nsamp, sizeof(unsigned long long),
+    if (ctx->deferred) return RB_OK;  // read back at the end of the sweep
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, RB_W_COUNT * sizeof(int32_t),
                                hipMemcpyDeviceToHost, ctx->stream));
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->lost_nodes = ctx->h_flag[1];
-    ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + 2);
-    if (*ctx->h_flag & 1)
+    ctx->lost_nodes = ctx->h_flag[RB_W_LOST];
+    ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + RB_W_SAMPLES);
+    if (ctx->h_flag[RB_W_FLAGS] & 1)
         return rb_fail(ctx, RB_ENONFINITE, "a ray did not reach the ring within max_steps=%d",
                        tp->max_steps);
     return RB_OK;
