@@ -233,6 +233,9 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        ctx->sample_budget = std::min(std::max(free_b / 4, (size_t)1 << 30), (size_t)48 << 30);
     *out = ctx;
     return RB_OK;
 }

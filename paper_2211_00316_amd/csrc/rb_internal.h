@@ -57,6 +57,10 @@ struct rb_ctx {
     int32_t *h_flag = nullptr;        // pinned host mirror of d_flag
     int64_t lost_nodes = 0;           // mask nodes the last binning could not place
     int64_t ray_samples = 0;          // ray samples written by the last trace
+    // Bytes of ray samples one tracer launch may hold: a quarter of the device memory free
+    // when the context was created, at most 48 GiB. All transducers in one launch keeps the
+    // GPU full until the longest rays finish (one chunk at N = 1024 on a 288 GB device).
+    size_t sample_budget = (size_t)6 << 30;
 
     // Deferred checks (rb_frequency_sweep): no host synchronisation inside a step; errors
     // stay in d_flag and the commit kernel skips the update once any is set.

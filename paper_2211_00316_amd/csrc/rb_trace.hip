@@ -821,12 +821,13 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
     return RB_OK;
 }
 
-// Emitters per chunk so that the ray samples of one chunk stay below ~6 GiB.
-static int trace_chunk(const rb_ring *r, const rb_trace_params *tp, int64_t n_mask) {
+// Emitters per tracer launch so that the ray samples of one chunk fit the context's budget.
+static int trace_chunk(const rb_ctx *ctx, const rb_ring *r, const rb_trace_params *tp,
+                       int64_t n_mask) {
     size_t S = (size_t)tp->max_steps + 1;
     size_t per = S * tp->n_rays * (sizeof(float2) + sizeof(float4) + 1) + (size_t)n_mask * 8 +
                  (size_t)tp->n_rays * 32;
-    size_t budget = (size_t)6 << 30;
+    size_t budget = ctx->sample_budget;
     size_t c = budget / per;
     if (c < 1) c = 1;
     if (c > (size_t)r->n) c = r->n;
@@ -837,7 +838,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out) {
     const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
     const int n_mask = (int)ctx->n_mask;
-    const int C = trace_chunk(r, tp, n_mask);
+    const int C = trace_chunk(ctx, r, tp, n_mask);
     size_t plane = (size_t)C * S * nr;
     size_t bytes = rb_align(plane * sizeof(float2)) + rb_align(plane * sizeof(float4)) +
                    rb_align(plane) +
