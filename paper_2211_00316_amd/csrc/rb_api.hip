@@ -233,6 +233,10 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        ctx->n_cu = ncu;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
         ctx->sample_budget = std::min(std::max(free_b / 4, (size_t)1 << 30), (size_t)48 << 30);
@@ -363,9 +367,13 @@ rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const
     RB_HIP(ctx, hipSetDevice(ctx->device));
     int mb = rb_rowred_mblocks(gr->n);
     ctx->ws.used = 0;
-    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float))));
+    const size_t nn = (size_t)gr->n * gr->n;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
+                                               rb_align(2 * nn * sizeof(float))));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
-    RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->G, 1, 1, parts, &mb));
+    float *rsym = rb_carve<float>(&ctx->ws, 2 * nn);
+    RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->G, 1, 1, rsym, parts,
+                            &mb));
     return rb_launch_adjoint_finish(ctx, gr->n_mask, mb, parts, w, grad);
 }
 
@@ -395,7 +403,8 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
     ctx->ws.used = 0;
     const size_t nnp = (size_t)gr->n * rb_lp_pad(gr->n);
     RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
-                                               rb_align(2 * nnp * sizeof(uint16_t)) + rb_align(8)));
+                                               rb_align(2 * nnp * sizeof(uint16_t)) + rb_align(8) +
+                                               rb_align(2 * nn * sizeof(float))));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
     if (lp) {
         uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nnp);
@@ -404,8 +413,9 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
         RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb));
         RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
     } else {
-        RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, parts,
-                                &mb));
+        float *rsym = rb_carve<float>(&ctx->ws, 2 * nn);
+        RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, rsym,
+                                parts, &mb));
     }
     return rb_launch_backproject_finish(ctx, gr->n_mask, mb, parts, c_mask, omega, d_omega, dm,
                                         accumulate);
@@ -431,7 +441,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand
     size_t bytes = rb_align(P * 4) + rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP) +
                    rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
-                   rb_align(3 * NPp * opb) + 2 * rb_align(NN * 8) + rb_align(NNp * 4) +
+                   rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) + rb_align(NNp * 4) +
                    rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
                    3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
                    rb_align(8);
@@ -458,6 +468,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     gr.H = rb_carve<char>(a, 3 * (lp ? NPp : NP) * opb);
     float *d_born = rb_carve<float>(a, 2 * NN);
     float *R = rb_carve<float>(a, 2 * NN);
+    float *rsym = rb_carve<float>(a, 2 * NN);
     uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NNp);
     float *rscale = rb_carve<float>(a, 2);
     float *wv = rb_carve<float>(a, 2 * (size_t)nm);
@@ -507,7 +518,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
             RB_TRY(rb_launch_rowred_lp(ctx, prec, N, nm, Rp, gr.H, 3, parts, &mbo));
             RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mbo * nm, rscale));
         } else {
-            RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, parts, &mbo));
+            RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, rsym, parts, &mbo));
         }
         RB_TRY(rb_launch_backproject_finish_acc(ctx, mbo, parts, cq, om, d_omega[k], dm));
     }

@@ -31,6 +31,25 @@ __device__ __forceinline__ int mfma_row(int lane, int i) {
 
 constexpr int RR_BM = 256, RR_BN = 64, RR_BK = 16;
 
+// The row-reduced products are bilinear forms x^T R x (the same operand E = B on both
+// sides), which see only the symmetric part Rs = (R + R^T) / 2. With row and column blocks
+// of RR_BM transducers, x^T Rs x = sum_I x_I^T Rs_II x_I + 2 sum_{J > I} x_I^T Rs_IJ x_J, so
+// the operand is the block upper triangle R' = Rs on diagonal blocks, R + R^T above them, 0
+// below, and row block I contracts over columns from its own block on.
+__global__ void sym_upper_kernel(const float2 *__restrict__ R, int n, float2 *__restrict__ Rs) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)n * n) return;
+    const int row = (int)(i / n), col = (int)(i - (size_t)row * n);
+    const int bi = row / RR_BM, bj = col / RR_BM;
+    float2 v = make_float2(0.f, 0.f);
+    if (bj >= bi) {
+        const float2 a = R[i], b = R[(size_t)col * n + row];
+        const float f = bj == bi ? 0.5f : 1.0f;
+        v = make_float2(f * (a.x + b.x), f * (a.y + b.y));
+    }
+    Rs[i] = v;
+}
+
 // parts: [2][mblocks][n_cols] (re plane, then im plane).
 // Grid: 1D over (col block, row block) pairs, ordered so that the row blocks of one column
 // block land on the same XCD (workgroup id mod 8) and share its B tile in that XCD's L2.
@@ -68,7 +87,7 @@ __global__ void __launch_bounds__(256) rowred_kernel(const float2 *__restrict__ 
                     acc_re[mt][nt][i] = 0.f;
                     acc_im[mt][nt][i] = 0.f;
                 }
-        for (int k0 = 0; k0 < n; k0 += RR_BK) {
+        for (int k0 = row0; k0 < n; k0 += RR_BK) {  // R' is zero left of the diagonal block
             // A tile: row (row0 + tid), 16 consecutive k of R
             {
                 int gr = row0 + tid;
@@ -309,15 +328,18 @@ __global__ void forward_reduce(const float2 *__restrict__ dpart, int n, int spli
 int rb_rowred_mblocks(int n) { return (n + RR_BM - 1) / RR_BM; }
 
 rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const float *B,
-                           int n_comp, int conj_b, float *parts, int *mblocks_out) {
+                           int n_comp, int conj_b, float *rsym, float *parts, int *mblocks_out) {
     int mblocks = rb_rowred_mblocks(n);
     int nblocks = (n_mask + RR_BN - 1) / RR_BN;
     int total = mblocks * nblocks;
     int grid = ((total + 7) / 8) * 8;
     rb_prof_begin(ctx, ST_BACKPROJECT);
+    hipLaunchKernelGGL(sym_upper_kernel, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256),
+                       0, ctx->stream, (const float2 *)R, n, (float2 *)rsym);
+    RB_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(rowred_kernel, dim3(grid), dim3(256), 0, ctx->stream,
-                       (const float2 *)R, (const float2 *)B, n, n_mask, n_comp, conj_b, mblocks,
-                       nblocks, parts);
+                       (const float2 *)rsym, (const float2 *)B, n, n_mask, n_comp, conj_b,
+                       mblocks, nblocks, parts);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     if (mblocks_out) *mblocks_out = mblocks;

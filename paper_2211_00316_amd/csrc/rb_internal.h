@@ -61,6 +61,7 @@ struct rb_ctx {
     // when the context was created, at most 48 GiB. All transducers in one launch keeps the
     // GPU full until the longest rays finish (one chunk at N = 1024 on a 288 GB device).
     size_t sample_budget = (size_t)6 << 30;
+    int n_cu = 256;                   // compute units of the device (persistent grids)
 
     // Deferred checks (rb_frequency_sweep): no host synchronisation inside a step; errors
     // stay in d_flag and the commit kernel skips the update once any is set.
@@ -140,9 +141,11 @@ rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, dou
 rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
                             float *d, const float *gscale);
 // Row-reduced complex GEMM: parts[2][mblocks][n_mask] (re, im) of
-// sum_e E_c[e][q] (R B_c)[e][q] summed over the n_comp components c.
+// sum_e E_c[e][q] (R B_c)[e][q] summed over the n_comp components c (E_c = B_c, conjugated
+// with conj_b). rsym: workspace of n x n complex64 for the block upper triangle of the
+// symmetric part of R (rb_gemm.hip).
 rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const float *B,
-                           int n_comp, int conj_b, float *parts, int *mblocks);
+                           int n_comp, int conj_b, float *rsym, float *parts, int *mblocks);
 rb_status rb_launch_adjoint_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
                                    const float *w, float *grad);
 rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, const float *parts,
@@ -154,7 +157,9 @@ int rb_rowred_mblocks(int n);
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const rb_green *out, const float *gs, const float *gscale,
                              int write_g);
-// R -> planar 16-bit, scaled by a power of two kept in scale[0..1] (device, 2 floats).
+// R -> planar 16-bit operand of the back-projection: the block upper triangle of the
+// symmetric part of R (the bilinear forms h^T R h see nothing else; rb_lowp.hip), scaled by
+// a power of two kept in scale[0..1] (device, 2 floats).
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
                               float *scale);
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);

@@ -199,17 +199,28 @@ __global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restr
     }
 }
 
-// complex64 [n][n] -> planar T [2][n][np] (np = n rounded up to 8, zero padded),
-// multiplied by scale[0]
+// The back-projection needs R only through the bilinear forms h^T R h (the same operand on
+// both sides), which depend on R only through its symmetric part Rs = (R + R^T) / 2. With
+// row and column blocks of `bm` transducers, h^T Rs h = sum_I h_I^T Rs_II h_I +
+// 2 sum_{J > I} h_I^T Rs_IJ h_J, so the operand is the block upper triangle
+//   R'[e][r] = Rs[e][r] (same block), 2 Rs[e][r] = R[e][r] + R[r][e] (block J > I), 0 (J < I)
+// and the product for row block I runs over column blocks J >= I only.
+// complex64 [n][n] -> planar T [2][n][np] of R' (zero past n), multiplied by scale[0].
 template <typename T>
-__global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np,
+__global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np, int bm,
                                  const float *__restrict__ scale, T *__restrict__ dst) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t nn = (size_t)n * np;
     if (i >= nn) return;
     int row = (int)(i / np), col = (int)(i - (size_t)row * np);
     float s = scale[0];
-    float2 v = col < n ? src[(size_t)row * n + col] : make_float2(0.f, 0.f);
+    float2 v = make_float2(0.f, 0.f);
+    const int bi = row / bm, bj = col / bm;
+    if (col < n && bj >= bi) {
+        const float2 a = src[(size_t)row * n + col], b = src[(size_t)col * n + row];
+        const float f = bj == bi ? 0.5f : 1.0f;
+        v = make_float2(f * (a.x + b.x), f * (a.y + b.y));
+    }
     dst[i] = to_lp<T>(v.x * s);
     dst[nn + i] = to_lp<T>(v.y * s);
 }
@@ -305,128 +316,141 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restri
     __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
     __shared__ float red[2][2][LR_BN];
 
-    const int total = mblocks * nblocks;
-    const int per_xcd = (total + 7) / 8;
-    const int gid = blockIdx.x;
-    const int t = (gid & 7) * per_xcd + (gid >> 3);
-    if (t >= total) return;
-    const int nb = t / mblocks, mb = t - nb * mblocks;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 64
-    const int row0 = mb * LR_BM, col0 = nb * LR_BN;
     const int np = rb_lp_pad(n);  // padded row length (zeros past n), a multiple of LR_BK
     const size_t rplane = (size_t)n * np;
     const size_t hplane = (size_t)n_cols * np;
     const int KT = np / LR_BK;
-
-    float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
-
     // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row (tid >> 3) +
     // 32 u; A rows u = 0..7, B rows u = 0..3. Byte offsets within the operand's planes.
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
     const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
-    const uint32_t a_off =
-        (uint32_t)((l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8) * sizeof(T));
-    const uint32_t b_off =
-        (uint32_t)((l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8) * sizeof(T));
     const uint32_t row_step = (uint32_t)(32 * (size_t)np * sizeof(T));
 
-    for (int c = 0; c < n_comp; ++c) {
-        const T *Hc = Ht + (size_t)(2 * c) * hplane;
-        const __amdgpu_buffer_rsrc_t rb_rsrc = plane_rsrc(Hc, 2 * hplane * sizeof(T));
-        floatx16 acc_re[4][2], acc_im[4][2];
+    // Persistent: one workgroup per CU walks a static list of work items. An item is one
+    // node tile and a pair of row slabs (i, mblocks - 1 - i), whose contractions start at
+    // their diagonal blocks and together span mblocks + 1 blocks of K, so every item costs the
+    // same. Workgroups are dealt to the 8 XCDs round-robin; each XCD walks a contiguous range
+    // of items (both pairs of a node tile next to each other, sharing its H tile in L2).
+    const int n_pairs = (mblocks + 1) / 2, n_items = nblocks * n_pairs;
+    const int L = gridDim.x >> 3, xcd = blockIdx.x & 7;
+    const int per = (((n_items + 7) / 8) + 1) & ~1;
+    for (int k = blockIdx.x >> 3; k < per; k += L) {
+        const int item = xcd * per + k;
+        if (item >= n_items) break;
+        const int nb = item / n_pairs, pr = item - nb * n_pairs;
+        for (int half = 0; half < 2; ++half) {
+            const int mb = half == 0 ? pr : mblocks - 1 - pr;
+            if (half == 1 && mb == pr) break;  // middle slab of an odd count
+            const int row0 = mb * LR_BM, col0 = nb * LR_BN;
+            const int KT0 = row0 / LR_BK;  // R' is zero left of the diagonal block
+            float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
+            const uint32_t a_off = (uint32_t)(
+                (l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8) * sizeof(T));
+            const uint32_t b_off = (uint32_t)(
+                (l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8) * sizeof(T));
+
+            for (int c = 0; c < n_comp; ++c) {
+                const T *Hc = Ht + (size_t)(2 * c) * hplane;
+                const __amdgpu_buffer_rsrc_t rb_rsrc = plane_rsrc(Hc, 2 * hplane * sizeof(T));
+                floatx16 acc_re[4][2], acc_im[4][2];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+                for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
+                    for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    acc_re[mt][nt][i] = 0.f;
-                    acc_im[mt][nt][i] = 0.f;
+                        for (int i = 0; i < 16; ++i) {
+                            acc_re[mt][nt][i] = 0.f;
+                            acc_im[mt][nt][i] = 0.f;
+                        }
+                uint4 ra[8], rb[4];
+                auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
+                    const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
+                };
+                auto stash = [&](int buf) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        *reinterpret_cast<uint4 *>(
+                            &a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = ra[u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        *reinterpret_cast<uint4 *>(
+                            &b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = rb[u];
+                };
+                fetch(KT0);
+                stash(0);
+                if (KT0 + 1 < KT) fetch(KT0 + 1);
+                __syncthreads();
+                LrFrag f0, f1;
+                lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
+                for (int kt = KT0; kt < KT; ++kt) {
+                    const int cur = (kt - KT0) & 1;
+                    lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn,
+                               lane, 16);
+                    lr_mfma<T>(f0, acc_re, acc_im);
+                    if (kt + 1 < KT) stash(cur ^ 1);   // tile kt+1 into the idle buffer
+                    if (kt + 2 < KT) fetch(kt + 2);    // tile kt+2 into registers
+                    __syncthreads();
+                    if (kt + 1 < KT)
+                        lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0],
+                                   b_s[cur ^ 1][1], wm, wn, lane, 0);
+                    lr_mfma<T>(f1, acc_re, acc_im);
                 }
-        uint4 ra[8], rb[4];
-        auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
-            const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
+                // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
+                // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
+                // rows beyond n carry Y = 0)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
+                    if (gq >= n_cols) continue;
+                    const T *er_row = Hc + (size_t)gq * np;
+                    const T *ei_row = Hc + hplane + (size_t)gq * np;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
-        };
-        auto stash = [&](int buf) {
+                    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                *reinterpret_cast<uint4 *>(
-                    &a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = ra[u];
+                        for (int g = 0; g < 4; ++g) {
+                            const int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
+                            if (ge >= np) continue;
+                            const uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
+                            const uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
+                            T vr[4], vi[4];
+                            __builtin_memcpy(vr, &pr, 8);
+                            __builtin_memcpy(vi, &pi, 8);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                *reinterpret_cast<uint4 *>(
-                    &b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = rb[u];
-        };
-        fetch(0);
-        stash(0);
-        if (KT > 1) fetch(1);
-        __syncthreads();
-        LrFrag f0, f1;
-        lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
-        for (int kt = 0; kt < KT; ++kt) {
-            const int cur = kt & 1;
-            lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
-            lr_mfma<T>(f0, acc_re, acc_im);
-            if (kt + 1 < KT) stash(cur ^ 1);   // tile kt+1 into the idle buffer
-            if (kt + 2 < KT) fetch(kt + 2);    // tile kt+2 into registers
+                            for (int z = 0; z < 4; ++z) {
+                                const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
+                                const float yr = acc_re[mt][nt][g * 4 + z];
+                                const float yi = acc_im[mt][nt][g * 4 + z];
+                                cs_re[nt] += er * yr - ei * yi;
+                                cs_im[nt] += er * yi + ei * yr;
+                            }
+                        }
+                }
+                __syncthreads();  // LDS buffers are refilled by the next component
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                cs_re[nt] += __shfl_xor(cs_re[nt], 32);
+                cs_im[nt] += __shfl_xor(cs_im[nt], 32);
+                if (lane < 32) {
+                    red[0][wm][wn * 64 + nt * 32 + lane] = cs_re[nt];
+                    red[1][wm][wn * 64 + nt * 32 + lane] = cs_im[nt];
+                }
+            }
             __syncthreads();
-            if (kt + 1 < KT)
-                lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0],
-                           b_s[cur ^ 1][1], wm, wn, lane, 0);
-            lr_mfma<T>(f1, acc_re, acc_im);
-        }
-        // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
-        // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
-        // rows beyond n carry Y = 0)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
-            if (gq >= n_cols) continue;
-            const T *er_row = Hc + (size_t)gq * np;
-            const T *ei_row = Hc + hplane + (size_t)gq * np;
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
-                    if (ge >= np) continue;
-                    const uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
-                    const uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
-                    T vr[4], vi[4];
-                    __builtin_memcpy(vr, &pr, 8);
-                    __builtin_memcpy(vi, &pi, 8);
-#pragma unroll
-                    for (int z = 0; z < 4; ++z) {
-                        const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
-                        const float yr = acc_re[mt][nt][g * 4 + z], yi = acc_im[mt][nt][g * 4 + z];
-                        cs_re[nt] += er * yr - ei * yi;
-                        cs_im[nt] += er * yi + ei * yr;
-                    }
+            if (tid < LR_BN) {
+                const int gc = col0 + tid;
+                if (gc < n_cols) {
+                    parts[(size_t)mb * n_cols + gc] = red[0][0][tid] + red[0][1][tid];
+                    parts[(size_t)(mblocks + mb) * n_cols + gc] = red[1][0][tid] + red[1][1][tid];
                 }
-        }
-        __syncthreads();  // LDS buffers are refilled by the next component
-    }
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        cs_re[nt] += __shfl_xor(cs_re[nt], 32);
-        cs_im[nt] += __shfl_xor(cs_im[nt], 32);
-        if (lane < 32) {
-            red[0][wm][wn * 64 + nt * 32 + lane] = cs_re[nt];
-            red[1][wm][wn * 64 + nt * 32 + lane] = cs_im[nt];
-        }
-    }
-    __syncthreads();
-    if (tid < LR_BN) {
-        const int gc = col0 + tid;
-        if (gc < n_cols) {
-            parts[(size_t)mb * n_cols + gc] = red[0][0][tid] + red[0][1][tid];
-            parts[(size_t)(mblocks + mb) * n_cols + gc] = red[1][0][tid] + red[1][1][tid];
+            }
+            __syncthreads();  // red[] and the LDS tiles are reused by the next slab
         }
     }
 }
@@ -622,17 +646,18 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
     size_t nn = (size_t)n * n;
     const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
+    // |R'| <= 2 max |R|: scale max |R| to [2^12, 2^13) so R' stays below 2^14
     hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
-                       (const float2 *)R, nn, (const float *)nullptr, 14, scale);
+                       (const float2 *)R, nn, (const float *)nullptr, 13, scale);
     RB_CHECK_LAUNCH(ctx);
     size_t npad = (size_t)n * np;
     dim3 grd((unsigned)((npad + 255) / 256));
     if (prec == RB_BF16)
         hipLaunchKernelGGL(to_planar_kernel<__bf16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, np, scale, (__bf16 *)Rp);
+                           (const float2 *)R, n, np, LR_BM, scale, (__bf16 *)Rp);
     else
         hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, np, scale, (_Float16 *)Rp);
+                           (const float2 *)R, n, np, LR_BM, scale, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -658,8 +683,7 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
                               const void *Ht, int n_comp, float *parts, int *mblocks_out) {
     int mblocks = rb_rowred_lp_mblocks(n);
     int nblocks = (n_mask + LR_BN - 1) / LR_BN;
-    int total = mblocks * nblocks;
-    int grid = ((total + 7) / 8) * 8;
+    int grid = std::max(8, ctx->n_cu / 8 * 8);  // one workgroup per CU (persistent)
     // byte offsets into the two part planes of an operand, padding rows included, must stay
     // below LR_SPAN (32-bit buffer offsets)
     const size_t np = (size_t)rb_lp_pad(n);
