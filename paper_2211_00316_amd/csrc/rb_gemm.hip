@@ -51,8 +51,6 @@ __global__ void sym_upper_kernel(const float2 *__restrict__ R, int n, float2 *__
 }
 
 // parts: [2][mblocks][n_cols] (re plane, then im plane).
-// Grid: 1D over (col block, row block) pairs, ordered so that the row blocks of one column
-// block land on the same XCD (workgroup id mod 8) and share its B tile in that XCD's L2.
 __global__ void __launch_bounds__(256) rowred_kernel(const float2 *__restrict__ R,
                                                      const float2 *__restrict__ B, int n,
                                                      int n_cols, int n_comp, int conj_b,
@@ -62,125 +60,136 @@ __global__ void __launch_bounds__(256) rowred_kernel(const float2 *__restrict__ 
     __shared__ float b_re[RR_BK][RR_BN], b_im[RR_BK][RR_BN];
     __shared__ float red[2][4][RR_BN];
 
-    const int total = mblocks * nblocks;
-    const int per_xcd = (total + 7) / 8;
-    const int gid = blockIdx.x;
-    const int t = (gid & 7) * per_xcd + (gid >> 3);
-    if (t >= total) return;
-    const int nb = t / mblocks, mb = t - nb * mblocks;
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = mb * RR_BM, col0 = nb * RR_BN;
     const float bsign = conj_b ? -1.f : 1.f;
+    // Persistent: one workgroup per CU walks a static list of items, each one column block
+    // and a pair of row blocks (i, mblocks - 1 - i) whose contractions (from the diagonal
+    // block on) together span mblocks + 1 blocks, so every item costs the same. Each XCD
+    // walks a contiguous range of items.
+    const int n_pairs = (mblocks + 1) / 2, n_items = nblocks * n_pairs;
+    const int L = gridDim.x >> 3, xcd = blockIdx.x & 7;
+    const int per = (((n_items + 7) / 8) + 1) & ~1;
+    for (int k = blockIdx.x >> 3; k < per; k += L) {
+        const int item = xcd * per + k;
+        if (item >= n_items) break;
+        const int nb = item / n_pairs, pr = item - nb * n_pairs;
+        for (int half = 0; half < 2; ++half) {
+            const int mb = half == 0 ? pr : mblocks - 1 - pr;
+            if (half == 1 && mb == pr) break;  // middle block of an odd count
 
-    float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};  // per n-tile column sums
+            const int row0 = mb * RR_BM, col0 = nb * RR_BN;
 
-    for (int c = 0; c < n_comp; ++c) {
-        const float2 *Bc = B + (size_t)c * n * n_cols;
-        floatx16 acc_re[2][2], acc_im[2][2];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    acc_re[mt][nt][i] = 0.f;
-                    acc_im[mt][nt][i] = 0.f;
-                }
-        for (int k0 = row0; k0 < n; k0 += RR_BK) {  // R' is zero left of the diagonal block
-            // A tile: row (row0 + tid), 16 consecutive k of R
-            {
-                int gr = row0 + tid;
-                const float2 *src = R + (size_t)gr * n + k0;
-#pragma unroll
-                for (int kk = 0; kk < RR_BK; ++kk) {
-                    float2 v = make_float2(0.f, 0.f);
-                    if (gr < n && k0 + kk < n) v = src[kk];
-                    a_re[kk][tid] = v.x;
-                    a_im[kk][tid] = v.y;
-                }
-            }
-            // B tile: 16 rows (k) x 64 columns; each thread 4 consecutive columns
-            {
-                int kk = tid >> 4, cc = (tid & 15) * 4;
-                int gk = k0 + kk;
-                const float2 *src = Bc + (size_t)gk * n_cols + col0 + cc;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    float2 v = make_float2(0.f, 0.f);
-                    if (gk < n && col0 + cc + u < n_cols) v = src[u];
-                    b_re[kk][cc + u] = v.x;
-                    b_im[kk][cc + u] = bsign * v.y;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kp = 0; kp < RR_BK / 2; ++kp) {
-                int k = 2 * kp + (lane >> 5);
-                float ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    int m = wave * 64 + mt * 32 + (lane & 31);
-                    ar[mt] = a_re[k][m];
-                    ai[mt] = a_im[k][m];
-                    nai[mt] = -ai[mt];
-                }
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    int cn = nt * 32 + (lane & 31);
-                    br[nt] = b_re[k][cn];
-                    bi[nt] = b_im[k][cn];
-                }
+            float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};  // per n-tile column sums
+
+            for (int c = 0; c < n_comp; ++c) {
+                const float2 *Bc = B + (size_t)c * n * n_cols;
+                floatx16 acc_re[2][2], acc_im[2][2];
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) {
-                        acc_re[mt][nt] = mfma32(ar[mt], br[nt], acc_re[mt][nt]);
-                        acc_re[mt][nt] = mfma32(nai[mt], bi[nt], acc_re[mt][nt]);
-                        acc_im[mt][nt] = mfma32(ar[mt], bi[nt], acc_im[mt][nt]);
-                        acc_im[mt][nt] = mfma32(ai[mt], br[nt], acc_im[mt][nt]);
+                    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            acc_re[mt][nt][i] = 0.f;
+                            acc_im[mt][nt][i] = 0.f;
+                        }
+                for (int k0 = row0; k0 < n; k0 += RR_BK) {  // R' is zero left of the diagonal block
+                    // A tile: row (row0 + tid), 16 consecutive k of R
+                    {
+                        int gr = row0 + tid;
+                        const float2 *src = R + (size_t)gr * n + k0;
+#pragma unroll
+                        for (int kk = 0; kk < RR_BK; ++kk) {
+                            float2 v = make_float2(0.f, 0.f);
+                            if (gr < n && k0 + kk < n) v = src[kk];
+                            a_re[kk][tid] = v.x;
+                            a_im[kk][tid] = v.y;
+                        }
                     }
+                    // B tile: 16 rows (k) x 64 columns; each thread 4 consecutive columns
+                    {
+                        int kk = tid >> 4, cc = (tid & 15) * 4;
+                        int gk = k0 + kk;
+                        const float2 *src = Bc + (size_t)gk * n_cols + col0 + cc;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            float2 v = make_float2(0.f, 0.f);
+                            if (gk < n && col0 + cc + u < n_cols) v = src[u];
+                            b_re[kk][cc + u] = v.x;
+                            b_im[kk][cc + u] = bsign * v.y;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int kp = 0; kp < RR_BK / 2; ++kp) {
+                        int k = 2 * kp + (lane >> 5);
+                        float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+                        for (int mt = 0; mt < 2; ++mt) {
+                            int m = wave * 64 + mt * 32 + (lane & 31);
+                            ar[mt] = a_re[k][m];
+                            ai[mt] = a_im[k][m];
+                            nai[mt] = -ai[mt];
+                        }
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+                            int cn = nt * 32 + (lane & 31);
+                            br[nt] = b_re[k][cn];
+                            bi[nt] = b_im[k][cn];
+                        }
+#pragma unroll
+                        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                            for (int nt = 0; nt < 2; ++nt) {
+                                acc_re[mt][nt] = mfma32(ar[mt], br[nt], acc_re[mt][nt]);
+                                acc_re[mt][nt] = mfma32(nai[mt], bi[nt], acc_re[mt][nt]);
+                                acc_im[mt][nt] = mfma32(ar[mt], bi[nt], acc_im[mt][nt]);
+                                acc_im[mt][nt] = mfma32(ai[mt], br[nt], acc_im[mt][nt]);
+                            }
+                    }
+                    __syncthreads();
+                }
+                // epilogue: sum over the rows of E_c[e][q] Y_c[e][q]
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    int gc = col0 + nt * 32 + (lane & 31);
+                    if (gc >= n_cols) continue;
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            int gr = row0 + wave * 64 + mt * 32 + mfma_row(lane, i);
+                            if (gr < n) {
+                                float2 ev = Bc[(size_t)gr * n_cols + gc];
+                                float er = ev.x, ei = bsign * ev.y;
+                                float yr = acc_re[mt][nt][i], yi = acc_im[mt][nt][i];
+                                cs_re[nt] += er * yr - ei * yi;
+                                cs_im[nt] += er * yi + ei * yr;
+                            }
+                        }
+                }
+            }
+            // combine the two lane halves (rows 4..7 of each group of 8), then the four waves
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                cs_re[nt] += __shfl_xor(cs_re[nt], 32);
+                cs_im[nt] += __shfl_xor(cs_im[nt], 32);
+                if (lane < 32) {
+                    red[0][wave][nt * 32 + lane] = cs_re[nt];
+                    red[1][wave][nt * 32 + lane] = cs_im[nt];
+                }
             }
             __syncthreads();
-        }
-        // epilogue: sum over the rows of E_c[e][q] Y_c[e][q]
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            int gc = col0 + nt * 32 + (lane & 31);
-            if (gc >= n_cols) continue;
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    int gr = row0 + wave * 64 + mt * 32 + mfma_row(lane, i);
-                    if (gr < n) {
-                        float2 ev = Bc[(size_t)gr * n_cols + gc];
-                        float er = ev.x, ei = bsign * ev.y;
-                        float yr = acc_re[mt][nt][i], yi = acc_im[mt][nt][i];
-                        cs_re[nt] += er * yr - ei * yi;
-                        cs_im[nt] += er * yi + ei * yr;
-                    }
+            if (tid < RR_BN) {
+                int gc = col0 + tid;
+                if (gc < n_cols) {
+                    float sr = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
+                    float si = red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
+                    parts[(size_t)mb * n_cols + gc] = sr;
+                    parts[(size_t)(mblocks + mb) * n_cols + gc] = si;
                 }
-        }
-    }
-    // combine the two lane halves (rows 4..7 of each group of 8), then the four waves
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        cs_re[nt] += __shfl_xor(cs_re[nt], 32);
-        cs_im[nt] += __shfl_xor(cs_im[nt], 32);
-        if (lane < 32) {
-            red[0][wave][nt * 32 + lane] = cs_re[nt];
-            red[1][wave][nt * 32 + lane] = cs_im[nt];
-        }
-    }
-    __syncthreads();
-    if (tid < RR_BN) {
-        int gc = col0 + tid;
-        if (gc < n_cols) {
-            float sr = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
-            float si = red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
-            parts[(size_t)mb * n_cols + gc] = sr;
-            parts[(size_t)(mblocks + mb) * n_cols + gc] = si;
+            }
+            __syncthreads();  // red[] and the LDS tiles are reused by the next block
         }
     }
 }
@@ -331,8 +340,7 @@ rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const
                            int n_comp, int conj_b, float *rsym, float *parts, int *mblocks_out) {
     int mblocks = rb_rowred_mblocks(n);
     int nblocks = (n_mask + RR_BN - 1) / RR_BN;
-    int total = mblocks * nblocks;
-    int grid = ((total + 7) / 8) * 8;
+    int grid = std::max(8, ctx->n_cu / 8 * 8);  // one workgroup per CU (persistent)
     rb_prof_begin(ctx, ST_BACKPROJECT);
     hipLaunchKernelGGL(sym_upper_kernel, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256),
                        0, ctx->stream, (const float2 *)R, n, (float2 *)rsym);
