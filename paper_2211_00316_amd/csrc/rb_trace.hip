@@ -70,19 +70,39 @@ __device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], f
 // Four consecutive floats of a row, 4-byte aligned: one 16-byte load.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
+// The 4 x 4 control points of the cell a lane evaluated last. A step is shorter than a
+// cell, so consecutive evaluations (predictor, corrector, next predictor) mostly fall in the
+// same cell and reuse them instead of loading again.
+struct Patch {
+    float f[16];
+    int cell = -1;  // (iv + 2) (nx + 3) + iu + 2 of the stored cell, -1 for none
+};
+
 // Value, gradient and Hessian (per metre) of the spline at node-index coordinates (u, v).
-__device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, double v) {
+__device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, double v,
+                                              Patch &pc) {
     double fu = floor(u), fv = floor(v);
     float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
     bspline_basis((float)(u - fu), bu, du, ddu);
     bspline_basis((float)(v - fv), bv, dv, ddv);
     int iu = min(max((int)fu, -2), m.nx), iv = min(max((int)fv, -2), m.ny);
-    const float *p = m.f + ((iv - 1 + MPAD) * m.nxp + (iu - 1 + MPAD));
+    const int cell = (iv + 2) * (m.nx + 3) + (iu + 2);
+    if (cell != pc.cell) {
+        const float *p = m.f + ((iv - 1 + MPAD) * m.nxp + (iu - 1 + MPAD));
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            f4u q = *reinterpret_cast<const f4u *>(p + b * m.nxp);
+            pc.f[4 * b] = q.x;
+            pc.f[4 * b + 1] = q.y;
+            pc.f[4 * b + 2] = q.z;
+            pc.f[4 * b + 3] = q.w;
+        }
+        pc.cell = cell;
+    }
     float s_v = 0, s_gx = 0, s_gy = 0, s_xx = 0, s_xy = 0, s_yy = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        f4u q = *reinterpret_cast<const f4u *>(p + b * m.nxp);
-        float fr[4] = {q.x, q.y, q.z, q.w};
+        const float *fr = pc.f + 4 * b;
         float r0 = 0, r1 = 0, r2 = 0;  // row sums with B, B', B''
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -121,7 +141,7 @@ __device__ __forceinline__ void paraxial_rhs(const Spline &s, float kx, float ky
 
 // One step of Algorithm 1 of length h (metres), given the spline at the current point.
 __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, const Ray &r,
-                                         double h, double idx) {
+                                         double h, double idx, Patch &pc) {
     float hf = (float)h;
     double hu = h * idx;                                    // step in node units
     float n = s1.v;
@@ -129,7 +149,7 @@ __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, c
     float qxx = r.kx * ikn, qxy = r.ky * ikn;               // unit ray direction
     float kx = n * qxx, ky = n * qxy;                       // normalised wave vector
     float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
-    Spline s2 = spline_eval(m, r.u + hu * (double)qxx, r.v + hu * (double)qxy);
+    Spline s2 = spline_eval(m, r.u + hu * (double)qxx, r.v + hu * (double)qxy, pc);
     float n2 = s2.v;
     float ikpn = rsqrtf(kpx * kpx + kpy * kpy);
     float qxx2 = kpx * ikpn, qxy2 = kpy * ikpn;
@@ -193,10 +213,11 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     const double ue = (xy.x - g.x0) * g.idx, ve = (xy.y - g.y0) * g.idx;
     const double uc = -g.x0 * g.idx, vc = -g.y0 * g.idx;  // ring centre
     const double Ru2 = R * R * g.idx * g.idx;              // ring radius squared, node units
+    Patch pc;
     Ray r;
     r.u = ue;
     r.v = ve;
-    Spline sc = spline_eval(m, r.u, r.v);
+    Spline sc = spline_eval(m, r.u, r.v, pc);
     float n_cur = sc.v;
     r.kx = n_cur * cg;
     r.ky = n_cur * sg;
@@ -220,7 +241,7 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     bool last = false;
     int i = 0;
     while (i < max_steps) {
-        Ray nr = heun_step(m, sc, r, h, g.idx);
+        Ray nr = heun_step(m, sc, r, h, g.idx, pc);
         if (!last) {
             double pu = nr.u - uc, pv = nr.v - vc;
             if (pu * pu + pv * pv >= Ru2) {
@@ -237,7 +258,7 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
             }
         }
         r = nr;
-        sc = spline_eval(m, r.u, r.v);
+        sc = spline_eval(m, r.u, r.v, pc);
         float n_new = sc.v;
         T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
         float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
