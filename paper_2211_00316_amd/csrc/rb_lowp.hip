@@ -472,15 +472,21 @@ template <typename T>
 __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ Gp,
                                                          const float2 *__restrict__ w,
                                                          const float *__restrict__ delta, int n,
-                                                         int K, int nT, int kchunk,
+                                                         int K, int nT, int kchunk, int splitk,
                                                          const float *__restrict__ vscale,
                                                          float2 *__restrict__ dpart) {
     __shared__ __attribute__((aligned(16))) T a_s[2][LF_B][LF_LD];
     const float vs = vscale[0];
     __shared__ __attribute__((aligned(16))) T b_s[2][LF_B][LF_LD];
+    // Workgroups are dealt to the 8 XCDs round-robin. Every tile of one K chunk goes to the
+    // same XCD (chunk s to XCD s mod 8), so the chunk's columns of G come from HBM once and
+    // serve all tiles from that XCD's L2.
+    const int tiles = nT * (nT + 1) / 2;
+    const int kq = blockIdx.x >> 3;
+    const int split = (kq / tiles) * 8 + (blockIdx.x & 7);
+    if (split >= splitk) return;
     int tm, tn;
-    upper_tile(blockIdx.x, nT, tm, tn);
-    const int split = blockIdx.y;
+    upper_tile(kq % tiles, nT, tm, tn);
     const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -715,8 +721,10 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     int ksteps = (K + LF_BK - 1) / LF_BK;
     int splitk = (1024 + tiles - 1) / tiles;
     splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
+    splitk = (splitk + 7) / 8 * 8;  // K chunks spread evenly over the 8 XCDs
     int kchunk = ((ksteps + splitk - 1) / splitk) * LF_BK;
     splitk = (K + kchunk - 1) / kchunk;
+    const unsigned nblk = (unsigned)(tiles * ((splitk + 7) / 8) * 8);
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(
         ctx, &ctx->ws, rb_align((size_t)splitk * n * n * sizeof(float2)) + rb_align(8));
@@ -734,13 +742,13 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     }
     RB_CHECK_LAUNCH(ctx);
     if (gr->prec == RB_BF16)
-        hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(tiles, splitk), dim3(256), 0,
-                           ctx->stream, (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, nT,
-                           kchunk, vscale, dpart);
+        hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(nblk), dim3(256), 0, ctx->stream,
+                           (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, nT, kchunk,
+                           splitk, vscale, dpart);
     else
-        hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(tiles, splitk), dim3(256), 0,
-                           ctx->stream, (const _Float16 *)gr->G, (const float2 *)w, delta, n, K,
-                           nT, kchunk, vscale, dpart);
+        hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(nblk), dim3(256), 0, ctx->stream,
+                           (const _Float16 *)gr->G, (const float2 *)w, delta, n, K, nT, kchunk,
+                           splitk, vscale, dpart);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     rb_prof_begin(ctx, ST_FORWARD_REDUCE);
