@@ -300,18 +300,26 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     return M;
 }
 
-// One lane per ray; the lanes of a wavefront are neighbouring rays of one transducer, so the
-// per-step sample stores are coalesced. Also counts the samples written (one atomic per
-// wavefront; the workgroup size is a multiple of 64, so every wavefront is whole).
+// One lane per ray; a wavefront holds 64 neighbouring rays of one transducer, so the
+// per-step sample stores are coalesced. Rays near the middle of a fan cross the whole disk
+// and take the most steps, so wavefronts are dispatched by the distance of their ray group
+// from the fan's middle (rank r: groups mid, mid - 1, mid + 1, ...), over all transducers:
+// the longest run first and the shortest fill the end of the launch. Also counts the
+// samples written (one atomic per wavefront; the workgroup is a whole number of them).
 __global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double R, double psi0,
                                                     int N, int n_rays, int max_steps, double ds,
                                                     double c0, int e0, int E, SampleBufs sb,
                                                     int *flag, unsigned long long *n_samples) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int n_groups = (n_rays + 63) / 64;
+    const int el = wave % E, rank = wave / E;
     int M = -1;
-    if (tid < E * n_rays) {
-        const int el = tid / n_rays, j = tid - el * n_rays;
-        M = trace_ray(m, g, R, psi0, N, n_rays, max_steps, ds, c0, e0, el, j, sb, flag);
+    if (rank < n_groups) {
+        const int mid = n_groups / 2;
+        const int grp = (rank & 1) ? mid - 1 - (rank >> 1) : mid + (rank >> 1);
+        const int j = grp * 64 + (threadIdx.x & 63);
+        if (j < n_rays)
+            M = trace_ray(m, g, R, psi0, N, n_rays, max_steps, ds, c0, e0, el, j, sb, flag);
     }
     int cnt = M >= 0 ? M + 1 : 0;
 #pragma unroll
@@ -907,12 +915,12 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     RB_CHECK_LAUNCH(ctx);
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
-        int nthreads = E * nr;
         hipLaunchKernelGGL(zero_i32, dim3((E + 255) / 256), dim3(256), 0, ctx->stream, sb.folded,
                            E);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_begin(ctx, ST_TRACE);
-        hipLaunchKernelGGL(trace_kernel, dim3((nthreads + 255) / 256), dim3(256), 0, ctx->stream,
+        const int waves = E * ((nr + 63) / 64);
+        hipLaunchKernelGGL(trace_kernel, dim3((waves + 3) / 4), dim3(256), 0, ctx->stream,
                            smap, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0,
                            e0, E, sb, ctx->d_flag, nsamp);
         RB_CHECK_LAUNCH(ctx);
