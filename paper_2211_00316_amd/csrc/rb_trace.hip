@@ -185,7 +185,8 @@ __device__ __forceinline__ double sqrt_newton(double a) {
 struct SampleBufs {
     float2 *pos;                       // [E][S][n_rays] position in node-index units
     float4 *fld;                       // [E][S][n_rays] (dT, L, t_x, t_y)
-    uint8_t *K;
+    uint8_t *K;                        // [E][S][n_rays] caustic count, stored where > 0 only
+    int32_t *kfirst;                   // [E][n_rays] first sample with K > 0, S if none
     int32_t *M;                        // [E][n_rays] last sample index, -1 if invalid
     double *ex_beta;                   // [E][n_rays] exit angle from psi_e in [0, 2 pi)
     float *ex_dT, *ex_L;
@@ -230,7 +231,7 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     size_t o = (size_t)el * S * n_rays + j;
     sb.pos[o] = make_float2((float)r.u, (float)r.v);
     sb.fld[o] = make_float4(0.0f, 0.0f, cg, sg);
-    sb.K[o] = 0;
+    int kfirst = S;  // K is monotone along a ray: zero before kfirst, stored from it on
 
     float J_prev = 0.0f;
     float lnc1 = 0.0f;  // (1/2) ln(n_1 J_1 / (8 pi s_1)) of the first sample
@@ -278,7 +279,10 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
         o += n_rays;
         sb.pos[o] = make_float2((float)r.u, (float)r.v);
         sb.fld[o] = make_float4(dT, L, tx, ty);
-        sb.K[o] = (uint8_t)min(K, 255);
+        if (K > 0) {
+            sb.K[o] = (uint8_t)min(K, 255);
+            if (kfirst == S) kfirst = i;
+        }
         J_prev = J;
         n_cur = n_new;
         if (last) {
@@ -295,6 +299,7 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
         sb.ex_beta[(size_t)el * n_rays + j] = beta - RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
     }
     sb.M[(size_t)el * n_rays + j] = M;
+    sb.kfirst[(size_t)el * n_rays + j] = kfirst;
     if (M < 0) atomicOr(flag, 1);
     if (K > 0) atomicOr(sb.folded + el, 1);
     return M;
@@ -358,12 +363,12 @@ __device__ __forceinline__ bool barycentric(float au, float av, float bu, float 
 // both triangles (the smallest-key rule picks one), so no node falls between triangles.
 #define RB_BARY_EPS 1e-5f
 
-// Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`.
+// Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`;
+// K: the largest caustic count of the three vertices.
 __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t vb[3],
-                                            const float lam[3], double d, double c0,
+                                            const float lam[3], int K, double d, double c0,
                                             const rb_tables &tb, size_t out) {
     float dT = 0, L = 0, tx = 0, ty = 0;
-    int K = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float4 f = sb.fld[vb[k]];
@@ -371,7 +376,6 @@ __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t v
         L += lam[k] * f.y;
         tx += lam[k] * f.z;
         ty += lam[k] * f.w;
-        K = max(K, (int)sb.K[vb[k]]);
     }
     float itn = rsqrtf(tx * tx + ty * ty);
     tb.T[out] = (double)dT + d / c0;
@@ -549,7 +553,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     float lam[3];
     if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
                   (float)jj, j, i, vb, lam)) {
-        write_entry(sb, vb, lam, d, c0, tb, out);
+        write_entry(sb, vb, lam, 0, d, c0, tb, out);  // no ray of an unfolded fan has K > 0
     } else {
         write_invalid(tb, out);
         atomicAdd(lost, 1);
@@ -685,7 +689,13 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     float la, lb, lc;
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
-    write_entry(sb, vb, lam, d, c0, tb, out);
+    // vertices (ray, sample): (j, i), (j + 1, half ? i + 1 : i), (half ? j : j + 1, i + 1)
+    const int vj[3] = {j, j + 1, half ? j : j + 1}, vi[3] = {i, half ? i + 1 : i, i + 1};
+    int K = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (vi[k] >= sb.kfirst[(size_t)el * n_rays + vj[k]]) K = max(K, (int)sb.K[vb[k]]);
+    write_entry(sb, vb, lam, K, d, c0, tb, out);
 }
 
 __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int e0,
@@ -871,7 +881,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     size_t plane = (size_t)C * S * nr;
     size_t bytes = rb_align(plane * sizeof(float2)) + rb_align(plane * sizeof(float4)) +
                    rb_align(plane) +
-                   rb_align((size_t)C * nr * sizeof(int32_t)) +
+                   2 * rb_align((size_t)C * nr * sizeof(int32_t)) +
                    rb_align((size_t)C * nr * sizeof(double)) +
                    2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
                    rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
@@ -887,6 +897,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.fld = rb_carve<float4>(&ctx->ws, plane);
     sb.K = rb_carve<uint8_t>(&ctx->ws, plane);
     sb.M = rb_carve<int32_t>(&ctx->ws, (size_t)C * nr);
+    sb.kfirst = rb_carve<int32_t>(&ctx->ws, (size_t)C * nr);
     sb.ex_beta = rb_carve<double>(&ctx->ws, (size_t)C * nr);
     sb.ex_dT = rb_carve<float>(&ctx->ws, (size_t)C * nr);
     sb.ex_L = rb_carve<float>(&ctx->ws, (size_t)C * nr);
