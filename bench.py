@@ -35,7 +35,8 @@ FP32_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic units of the hot kernels
 TRACE_FLOP_PER_SAMPLE = 550     # two spline value+gradient+Hessian evaluations, Heun, paraxial
-TABLE_BYTES = 21                # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
+TABLE_BYTES = {"f32": 21,       # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
+               "bf16": 16, "f16": 16}   # compact record: dT, A, theta, flags (4 B each)
 SAMPLE_BYTES = 25               # one ray sample: position 8, (dT, L, t_x, t_y) 16, K 1
 OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16}   # G (complex) + H, H_x, H_y per entry
 
@@ -46,7 +47,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 STAGE_KERNELS = {
     "trace": (["trace_kernel"], ["trace_kernel"]),
     "resolve": (["tile_offset_kernel", "locate_kernel"], ["tile_offset_kernel", "locate_kernel"]),
-    "build_green": (["green_kernel"], ["green_lp_kernel"]),
+    "build_green": (["green_kernel"], ["green_lp_rec_kernel"]),
     "forward_gemm": (["forward_kernel"], ["forward_lp_kernel"]),
     "backproject_gemm": (["rowred_kernel"], ["rowred_lp_kernel"]),
 }
@@ -238,17 +239,18 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
     """Per hot kernel: algorithmic work per launch / average launch time, against the peak
     of what bounds it. `samples` = ray samples per step."""
     peak, peak_name = PEAKS[prec]
+    tab = TABLE_BYTES[prec]
     traffic = measured_traffic(workload, prec)
     work = {  # stage -> (bound, algorithmic units per step, unit, peak, peak name, what)
         "trace": ("alu", TRACE_FLOP_PER_SAMPLE * samples / 1e12, "TFLOP/s",
                   FP32_VECTOR_PEAK_TFLOPS, "fp32 vector (no packed FP32)",
                   f"{TRACE_FLOP_PER_SAMPLE} flop per ray sample"),
-        "resolve": ("hbm", (TABLE_BYTES * N * Pm + SAMPLE_BYTES * samples) / 1e9, "GB/s",
+        "resolve": ("hbm", (tab * N * Pm + SAMPLE_BYTES * samples) / 1e9, "GB/s",
                     HBM_PEAK_GBS, "HBM3E",
-                    f"{TABLE_BYTES} B per table entry written + {SAMPLE_BYTES} B per ray sample read"),
-        "build_green": ("hbm", (TABLE_BYTES + OPERAND_BYTES[prec]) * N * Pm / 1e9, "GB/s",
+                    f"{tab} B per table entry written + {SAMPLE_BYTES} B per ray sample read"),
+        "build_green": ("hbm", (tab + OPERAND_BYTES[prec]) * N * Pm / 1e9, "GB/s",
                         HBM_PEAK_GBS, "HBM3E",
-                        f"{TABLE_BYTES} B read + {OPERAND_BYTES[prec]} B written per (e, p)"),
+                        f"{tab} B read + {OPERAND_BYTES[prec]} B written per (e, p)"),
         "forward_gemm": ("mfma", 8.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,
                          "8 N^2 P_m flop (complex N x N x P_m, symmetric)"),
         "backproject_gemm": ("mfma", 24.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,

@@ -439,8 +439,10 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     const bool lp = prec != RB_F32;
     const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand
-    size_t bytes = rb_align(P * 4) + rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP) +
-                   rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
+    // node tables: ABI layout for the FP32 form, compact records (+ ring) for 16-bit
+    const size_t tab_bytes = lp ? rb_align(NP * 16) + rb_align((size_t)N * 16)
+                                : rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP);
+    size_t bytes = rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
                    rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) + rb_align(NNp * 4) +
                    rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
                    3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
@@ -452,11 +454,21 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     rb_tables tb;
     tb.n = N;
     tb.n_mask = nm;
-    tb.T = rb_carve<double>(a, NP);
-    tb.A = rb_carve<float>(a, NP);
-    tb.ux = rb_carve<float>(a, NP);
-    tb.uy = rb_carve<float>(a, NP);
-    tb.flags = rb_carve<uint8_t>(a, NP);
+    float4 *rec = nullptr;
+    double2 *ringpos = nullptr;
+    if (lp) {
+        tb.T = nullptr;
+        tb.A = tb.ux = tb.uy = nullptr;
+        tb.flags = nullptr;
+        rec = rb_carve<float4>(a, NP);
+        ringpos = rb_carve<double2>(a, N);
+    } else {
+        tb.T = rb_carve<double>(a, NP);
+        tb.A = rb_carve<float>(a, NP);
+        tb.ux = rb_carve<float>(a, NP);
+        tb.uy = rb_carve<float>(a, NP);
+        tb.flags = rb_carve<uint8_t>(a, NP);
+    }
     tb.rx_T = rb_carve<double>(a, NN);
     tb.rx_A = rb_carve<float>(a, NN);
     tb.rx_flags = rb_carve<uint8_t>(a, NN);
@@ -480,7 +492,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
 
     // a1: tracing map; a2-a3: rays and tables (independent of omega when lossless)
     RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, n_s));
-    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, n_s, &tb));
+    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, n_s, &tb, rec, ringpos));
     RB_TRY(rb_launch_gather_mask(ctx, c, cq));
     RB_TRY(rb_launch_zero_f64(ctx, dm, nm));
     if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
@@ -497,7 +509,8 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
         }
         const float *gs = born_term ? wv : nullptr;
         if (lp)
-            RB_TRY(rb_launch_green_lp(ctx, &tb, om, tp->c0, &gr, gs, svscale, born_term));
+            RB_TRY(rb_launch_green_lp_rec(ctx, rec, ringpos, N, om, tp->c0, &gr, gs, svscale,
+                                          born_term));
         else
             RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr, gs, svscale, born_term));
         // a5-a6: predicted data (ray part + Born term of the rough part) and residual

@@ -126,8 +126,15 @@ rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g);
 // Stage launchers (each validates nothing; callers have validated) -------------------------
 rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
                                      int w, float *n_s);
+// Trace and bin. The receiver tables always go to `out`. The node tables go to `out` as well
+// unless `rec` is given ([n][n_mask] float4, inside a frequency step): then each
+// (transducer, node) gets one compact record (dT, A, theta, flags) with dT = T - d / c0 (d:
+// distance from the transducer, recomputed by the reader), theta = atan2(u_y, u_x) and the
+// flag bits of rb_tables stored as the bits of the fourth float. ring_out (nullable, double2
+// [n]) receives the transducer positions.
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
-                          const rb_trace_params *tp, const float *n_s, const rb_tables *out);
+                          const rb_trace_params *tp, const float *n_s, const rb_tables *out,
+                          float4 *rec = nullptr, double2 *ring_out = nullptr);
 // gs (nullable): complex per-node factor on G; write_g = 0 leaves G unwritten.
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                           const rb_green *out, const float *gs, const float *gscale,
@@ -157,6 +164,10 @@ int rb_rowred_mblocks(int n);
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const rb_green *out, const float *gs, const float *gscale,
                              int write_g);
+// The same from the compact records of rb_launch_trace (ring: transducer positions).
+rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
+                                 double omega, double c0, const rb_green *out, const float *gs,
+                                 const float *gscale, int write_g);
 // R -> planar 16-bit operand of the back-projection: the block upper triangle of the
 // symmetric part of R (the bilinear forms h^T R h see nothing else; rb_lowp.hip), scaled by
 // a power of two kept in scale[0..1] (device, 2 floats).

@@ -82,6 +82,23 @@ __device__ __forceinline__ float angle_between(float ax, float ay, float bx, flo
     return fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
 }
 
+// G = A k0^-1/2 e^{i phi} and H = a k0^1/2 A^-1 e^{-i phi}, phi = omega T + pi/4 - K pi/2
+// reduced modulo 2 pi in FP64 (Eqs. 2D_greens, greens-time-reversed; a: angular weight).
+__device__ __forceinline__ void green_entry(double omega, double Tt, uint32_t K, float A, float a,
+                                            float sk, float isk, float &gr, float &gi, float &hr,
+                                            float &hi) {
+    double ph = omega * Tt + 0.25 * RB_PI - (double)(K & 3) * 0.5 * RB_PI;
+    ph -= RB_TWO_PI * floor(ph * (1.0 / RB_TWO_PI));
+    float sn, cs;
+    __sincosf((float)ph, &sn, &cs);
+    const float ga = A * isk;
+    gr = ga * cs;
+    gi = ga * sn;
+    const float ha = a * sk * __builtin_amdgcn_rcpf(A);
+    hr = ha * cs;
+    hi = -ha * sn;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
                                                        double omega, double c0,
@@ -125,15 +142,6 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         if (e < N) {
             size_t o = (size_t)e * n_mask + q;
             if (valid >> (r + 1) & 1u) {
-                uint32_t f = tb.flags[o];
-                double ph = omega * tb.T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI;
-                ph -= RB_TWO_PI * floor(ph * (1.0 / RB_TWO_PI));
-                float sn, cs;
-                __sincosf((float)ph, &sn, &cs);
-                float A = tb.A[o];
-                float ga = A * isk;
-                gr = ga * cs;
-                gi = ga * sn;
                 vx = ux[r + 1];
                 vy = uy[r + 1];
                 const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
@@ -141,9 +149,101 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
                 if (vm && vp) a = 0.5f * angle_between(ux[r], uy[r], ux[r + 2], uy[r + 2]);
                 else if (vp) a = angle_between(vx, vy, ux[r + 2], uy[r + 2]);
                 else if (vm) a = angle_between(ux[r], uy[r], vx, vy);
-                float ha = a * sk * __builtin_amdgcn_rcpf(A);
-                hr = ha * cs;
-                hi = -ha * sn;
+                green_entry(omega, tb.T[o], tb.flags[o], tb.A[o], a, sk, isk, gr, gi, hr, hi);
+            }
+            if (write_g) {
+                float tr = gr * f2.x - gi * f2.y;
+                gi = gr * f2.y + gi * f2.x;
+                Gp[o] = to_lp<T>(tr);
+                Gp[gplane + o] = to_lp<T>(gi);
+            }
+        }
+        float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
+#pragma unroll
+        for (int cp = 0; cp < 6; ++cp) {
+            if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
+            else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
+        }
+    }
+    // transposed rows (c, part, q), Np long (zeros past N)
+    const size_t hplane = (size_t)n_mask * Np;
+#pragma unroll
+    for (int cp = 0; cp < 6; ++cp) {
+        T *dst = Ht + (size_t)cp * hplane + (size_t)q * Np + e0;
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
+        if (e0 + 8 < Np)
+            *reinterpret_cast<uint4 *>(dst + 8) =
+                make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
+    }
+}
+
+// The same assembly from the compact records of a frequency step (rb_launch_trace): one
+// 16-byte load per (transducer, node) gives dT, A, the ray angle theta and the flags;
+// T = dT + d / c0 with d the node's distance from the transducer, and the angle between
+// neighbouring transducers' rays is the wrapped difference of their thetas.
+__device__ __forceinline__ float wrap_pi(float x) {
+    return x - (float)RB_TWO_PI * rintf(x * (float)(1.0 / RB_TWO_PI));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) green_lp_rec_kernel(
+    const float4 *__restrict__ rec, const int32_t *__restrict__ mask_index,
+    const double2 *__restrict__ ring, double x0, double y0, double dx, int nx, int N, int n_mask,
+    double omega, double c0, const float2 *__restrict__ gs, const float *__restrict__ gscale,
+    int write_g, T *__restrict__ Gp, T *__restrict__ Ht) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = blockIdx.x * GQ + lane;
+    const int e0 = blockIdx.y * GE + w * GW;
+    const int Np = rb_lp_pad(N);
+    if (q >= n_mask || e0 >= Np) return;  // no barrier in this kernel
+    const int p = mask_index[q];
+    const double px = x0 + (p % nx) * dx, py = y0 + (p / nx) * dx;
+    // records of rows e0 - 1 .. e0 + GW (indices mod N)
+    float th[GW + 2], dTr[GW], Ar[GW];
+    uint32_t valid = 0, Kb = 0;
+#pragma unroll
+    for (int r = 0; r < GW + 2; ++r) {
+        int e = e0 - 1 + r;
+        e = e < 0 ? e + N : (e >= N ? e - N : e);
+        if (e >= N) e = 0;  // rows past the padding end: never used
+        const float4 v = rec[(size_t)e * n_mask + q];
+        const uint32_t f = __float_as_uint(v.w);
+        valid |= (f & 0x80) ? (1u << r) : 0u;
+        th[r] = v.z;
+        if (r >= 1 && r <= GW) {
+            dTr[r - 1] = v.x;
+            Ar[r - 1] = v.y;
+            Kb |= (f & 3) << (2 * (r - 1));
+        }
+    }
+    const double k0 = omega / c0, ic0 = 1.0 / c0;
+    const float sk = (float)sqrt(k0), isk = 1.0f / sk;
+    const size_t gplane = (size_t)N * n_mask;
+    float2 f2 = make_float2(1.f, 0.f);
+    if (write_g && gs) {
+        f2 = gs[q];
+        float sc = gscale[0];
+        f2.x *= sc;
+        f2.y *= sc;
+    }
+    uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
+#pragma unroll
+    for (int r = 0; r < GW; ++r) {
+        const int e = e0 + r;
+        float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
+        if (e < N) {
+            size_t o = (size_t)e * n_mask + q;
+            if (valid >> (r + 1) & 1u) {
+                __sincosf(th[r + 1], &vy, &vx);
+                const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
+                float a = 0.f;
+                if (vm && vp) a = 0.5f * fabsf(wrap_pi(th[r + 2] - th[r]));
+                else if (vp) a = fabsf(wrap_pi(th[r + 2] - th[r + 1]));
+                else if (vm) a = fabsf(wrap_pi(th[r + 1] - th[r]));
+                const double2 xe = ring[e];
+                const double ddx = px - xe.x, ddy = py - xe.y;
+                const double Tt = (double)dTr[r] + sqrt(ddx * ddx + ddy * ddy) * ic0;
+                green_entry(omega, Tt, Kb >> (2 * r), Ar[r], a, sk, isk, gr, gi, hr, hi);
             }
             if (write_g) {
                 float tr = gr * f2.x - gi * f2.y;
@@ -642,6 +742,28 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
         hipLaunchKernelGGL(green_lp_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
                            tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
                            (_Float16 *)out->G, (_Float16 *)out->H);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
+                                 double omega, double c0, const rb_green *out, const float *gs,
+                                 const float *gscale, int write_g) {
+    const int nm = (int)ctx->n_mask;
+    const rb_grid &g = ctx->grid;
+    dim3 grd((nm + GQ - 1) / GQ, (n + GE - 1) / GE);
+    rb_prof_begin(ctx, ST_GREEN);
+    if (out->prec == RB_BF16)
+        hipLaunchKernelGGL(green_lp_rec_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, rec,
+                           ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega, c0,
+                           (const float2 *)gs, gscale, write_g, (__bf16 *)out->G,
+                           (__bf16 *)out->H);
+    else
+        hipLaunchKernelGGL(green_lp_rec_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, rec,
+                           ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega, c0,
+                           (const float2 *)gs, gscale, write_g, (_Float16 *)out->G,
+                           (_Float16 *)out->H);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;

@@ -363,11 +363,18 @@ __device__ __forceinline__ bool barycentric(float au, float av, float bu, float 
 // both triangles (the smallest-key rule picks one), so no node falls between triangles.
 #define RB_BARY_EPS 1e-5f
 
+// Where binning writes: the tables of the C ABI, or (rec != nullptr, inside a frequency step)
+// one compact record per (transducer, node), see rb_launch_trace.
+struct TableOut {
+    rb_tables tb;
+    float4 *rec;
+};
+
 // Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`;
 // K: the largest caustic count of the three vertices.
 __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t vb[3],
                                             const float lam[3], int K, double d, double c0,
-                                            const rb_tables &tb, size_t out) {
+                                            const TableOut &to, size_t out) {
     float dT = 0, L = 0, tx = 0, ty = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -377,15 +384,26 @@ __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t v
         tx += lam[k] * f.z;
         ty += lam[k] * f.w;
     }
+    const float A = __expf(L) * rsqrtf((float)d);
+    if (to.rec) {
+        to.rec[out] = make_float4(dT, A, atan2f(ty, tx), __int_as_float(0x80 | (K & 3)));
+        return;
+    }
+    const rb_tables &tb = to.tb;
     float itn = rsqrtf(tx * tx + ty * ty);
     tb.T[out] = (double)dT + d / c0;
-    tb.A[out] = __expf(L) * rsqrtf((float)d);
+    tb.A[out] = A;
     tb.ux[out] = tx * itn;
     tb.uy[out] = ty * itn;
     tb.flags[out] = (uint8_t)(0x80 | (K & 3));
 }
 
-__device__ __forceinline__ void write_invalid(const rb_tables &tb, size_t out) {
+__device__ __forceinline__ void write_invalid(const TableOut &to, size_t out) {
+    if (to.rec) {
+        to.rec[out] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const rb_tables &tb = to.tb;
     tb.T[out] = 0.0;
     tb.A[out] = 0.0f;
     tb.ux[out] = 0.0f;
@@ -518,7 +536,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                                                      int N, double ds, double c0, int n_mask,
                                                      int tile_i0, int tile_j0, int tiles_x,
                                                      int tiles_y, const int32_t *__restrict__ qmap,
-                                                     const int2 *__restrict__ off, rb_tables tb,
+                                                     const int2 *__restrict__ off, TableOut to,
                                                      int *lost) {
     const int ntiles = tiles_x * tiles_y;
     const int G = LOCATE_GROUP_ROWS * tiles_x;
@@ -541,7 +559,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     double ddx = px - xy.x, ddy = py - xy.y;
     double d = sqrt_newton(ddx * ddx + ddy * ddy);
     if (d < 2.0 * ds) {
-        write_invalid(tb, out);
+        write_invalid(to, out);
         return;
     }
     int j, i;
@@ -553,9 +571,9 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     float lam[3];
     if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
                   (float)jj, j, i, vb, lam)) {
-        write_entry(sb, vb, lam, 0, d, c0, tb, out);  // no ray of an unfolded fan has K > 0
+        write_entry(sb, vb, lam, 0, d, c0, to, out);  // no ray of an unfolded fan has K > 0
     } else {
-        write_invalid(tb, out);
+        write_invalid(to, out);
         atomicAdd(lost, 1);
     }
 }
@@ -654,7 +672,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
                                              int q, int e0, const GridP &g, double ds, double c0,
                                              int n_mask, const int32_t *__restrict__ mask_index,
                                              const unsigned long long *__restrict__ keys,
-                                             const rb_tables &tb) {
+                                             const TableOut &to) {
     const size_t tid = (size_t)el * n_mask + q;
     int e = e0 + el;
     size_t out = (size_t)e * n_mask + q;
@@ -666,7 +684,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double d = sqrt_newton((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
-        write_invalid(tb, out);
+        write_invalid(to, out);
         return;
     }
     uint32_t tri = (uint32_t)(key & 0xffffffffu);
@@ -695,7 +713,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (vi[k] >= sb.kfirst[(size_t)el * n_rays + vj[k]]) K = max(K, (int)sb.K[vb[k]]);
-    write_entry(sb, vb, lam, K, d, c0, tb, out);
+    write_entry(sb, vb, lam, K, d, c0, to, out);
 }
 
 __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int e0,
@@ -703,13 +721,13 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
                                                       const int32_t *__restrict__ mask_index,
                                                       const int32_t *__restrict__ flist,
                                                       const unsigned long long *__restrict__ keys,
-                                                      rb_tables tb) {
+                                                      TableOut to) {
     const size_t total = (size_t)flist[0] * n_mask;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
         const int f = (int)(t / n_mask);
         resolve_node(sb, n_rays, S, flist[1 + f], (int)(t - (size_t)f * n_mask), e0, g, ds, c0,
-                     n_mask, mask_index, keys, tb);
+                     n_mask, mask_index, keys, to);
     }
 }
 
@@ -874,7 +892,8 @@ static int trace_chunk(const rb_ctx *ctx, const rb_ring *r, const rb_trace_param
 }
 
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
-                          const rb_trace_params *tp, const float *n_s, const rb_tables *out) {
+                          const rb_trace_params *tp, const float *n_s, const rb_tables *out,
+                          float4 *rec, double2 *ring_out) {
     const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
     const int n_mask = (int)ctx->n_mask;
     const int C = trace_chunk(ctx, r, tp, n_mask);
@@ -905,6 +924,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
     int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
+    if (ring_out) ringpos = ring_out;
+    const TableOut to{*out, rec};
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
@@ -950,7 +971,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
-                           toff, *out, lost);
+                           toff, to, lost);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation and resolve
@@ -964,7 +985,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(resolve_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
-                           e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys, *out);
+                           e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys, to);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         rb_prof_begin(ctx, ST_RECEIVERS);
