@@ -37,7 +37,7 @@ FP32_VECTOR_PEAK_TFLOPS = 78.6
 TRACE_FLOP_PER_SAMPLE = 550     # two spline value+gradient+Hessian evaluations, Heun, paraxial
 TABLE_BYTES = {"f32": 21,       # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
                "bf16": 16, "f16": 16}   # compact record: dT, A, theta, flags (4 B each)
-SAMPLE_BYTES = 25               # one ray sample: position 8, (dT, L, t_x, t_y) 16, K 1
+SAMPLE_BYTES = 24               # one ray sample: position 8, (dT, L, t_x, t_y) 16 (K only in folds)
 OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16}   # G (complex) + H, H_x, H_y per entry
 
 CSRC = os.path.join(ROOT, "paper_2211_00316_amd", "csrc")

@@ -106,9 +106,10 @@ typedef struct {
  * Layout by precision:
  *   RB_F32:  G complex64 [n][n_mask];  H complex64 [3][n][n_mask].
  *   RB_BF16, RB_F16 (16-bit operands, FP32 accumulation in every contraction):
- *            G planar [2 (re, im)][n][n_mask];  H planar, node-major
- *            [3][2 (re, im)][n_mask][n_pad] (transducer index contiguous), n_pad = n
- *            rounded up to a multiple of 32; rb_build_green writes zeros past n. */
+ *            G planar [2 (re, im)][n][m_pad], m_pad = n_mask rounded up to a multiple of
+ *            32;  H planar, node-major [3][2 (re, im)][n_mask][n_pad] (transducer index
+ *            contiguous), n_pad = n rounded up to a multiple of 32. rb_build_green writes
+ *            zeros past n_mask in G and past n in H. */
 typedef struct {
     int32_t n;
     int32_t n_mask;
@@ -162,7 +163,9 @@ rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double 
 
 /* Born forward operator (Eqs. perturb1, derivative): d[e][r] = sum_q G[e][q] w[q] delta[q]
  * G[r][q] for all (e, r) including e = r. w: complex64 [n_mask] (Upsilon h^2, e.g.
- * omega^2 dx^2 for dm = delta m); delta: float [n_mask]; d: complex64 [n][n]. */
+ * omega^2 dx^2 for dm = delta m); delta: float [n_mask]; d: complex64 [n][n]. w and delta
+ * may both be NULL: then w delta = 1, for operands that already carry sqrt(w delta) (as G
+ * does inside rb_frequency_step). */
 rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
                           float *d);
 

@@ -177,7 +177,8 @@ class Green:
                        torch.empty(3, n, n_mask, dtype=torch.complex64, device=device), prec)
         dt = _LP_DTYPE[prec]
         n_pad = (n + 31) // 32 * 32
-        return cls(torch.empty(2, n, n_mask, dtype=dt, device=device),
+        m_pad = (n_mask + 31) // 32 * 32
+        return cls(torch.empty(2, n, m_pad, dtype=dt, device=device),
                    torch.empty(3, 2, n_mask, n_pad, dtype=dt, device=device), prec)
 
     @property
@@ -186,13 +187,14 @@ class Green:
 
     @property
     def n_mask(self):
-        return self.G.shape[-1]
+        return self.G.shape[-1] if self.prec == RB_F32 else self.H.shape[2]
 
     def complex_G(self):
         """G as complex [n][n_mask] (float32 parts), for checks."""
         if self.prec == RB_F32:
             return self.G
-        return torch.complex(self.G[0].float(), self.G[1].float())
+        m = self.n_mask
+        return torch.complex(self.G[0, :, :m].float(), self.G[1, :, :m].float())
 
     def complex_H(self):
         """H, H u_x, H u_y as complex [3][n][n_mask], for checks."""
@@ -280,10 +282,12 @@ class Context:
         self._check(self.lib.rb_build_green(self._h, ctypes.byref(s), omega, c0, ctypes.byref(g)))
         return gr
 
-    def born_forward(self, gr: Green, w: torch.Tensor, delta: torch.Tensor,
+    def born_forward(self, gr: Green, w: torch.Tensor | None, delta: torch.Tensor | None,
                      out: torch.Tensor | None = None) -> torch.Tensor:
-        _dev(w, torch.complex64)
-        _dev(delta, torch.float32)
+        """w = delta = None: the operands already carry sqrt(w delta)."""
+        if w is not None or delta is not None:
+            _dev(w, torch.complex64)
+            _dev(delta, torch.float32)
         n = gr.n
         d = out if out is not None else torch.empty(n, n, dtype=torch.complex64, device=self.device)
         g = gr.struct()

@@ -227,6 +227,7 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     if (hipMalloc(&ctx->d_flag, RB_W_COUNT * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&ctx->d_red, RB_RED_PARTS * sizeof(float)) != hipSuccess ||
         hipHostMalloc(&ctx->h_flag, RB_W_COUNT * sizeof(int32_t), hipHostMallocDefault) !=
             hipSuccess ||
         hipMemset(ctx->d_flag, 0, RB_W_COUNT * sizeof(int32_t)) != hipSuccess) {
@@ -253,6 +254,7 @@ void rb_destroy(rb_ctx *ctx) {
     if (ctx->d_mask_index) (void)hipFree(ctx->d_mask_index);
     if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->d_red) (void)hipFree(ctx->d_red);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
@@ -351,7 +353,8 @@ rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const
                           float *d) {
     if (!ctx) return RB_EINVAL;
     RB_TRY(check_green(ctx, gr));
-    if (!w || !delta || !d) return rb_fail(ctx, RB_EINVAL, "w, delta and d must be non-NULL");
+    if (!d || !w != !delta)
+        return rb_fail(ctx, RB_EINVAL, "d must be non-NULL, w and delta both given or both NULL");
     RB_HIP(ctx, hipSetDevice(ctx->device));
     if (gr->prec != RB_F32) return rb_launch_forward_lp(ctx, gr, w, delta, d, nullptr);
     return rb_launch_forward(ctx, gr, w, delta, d, nullptr);
@@ -437,12 +440,13 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     const size_t NPp = (size_t)rb_lp_pad(N) * nm;  // padded operand rows (16-bit form)
     const size_t NNp = (size_t)rb_lp_pad(N) * N;
     const bool lp = prec != RB_F32;
+    const size_t NG = lp ? (size_t)N * rb_lp_pad(nm) : NP;  // G rows padded (16-bit form)
     const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand
     // node tables: ABI layout for the FP32 form, compact records (+ ring) for 16-bit
     const size_t tab_bytes = lp ? rb_align(NP * 16) + rb_align((size_t)N * 16)
                                 : rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP);
-    size_t bytes = rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NP * opb) +
+    size_t bytes = rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NG * opb) +
                    rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) + rb_align(NNp * 4) +
                    rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
                    3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
@@ -476,7 +480,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     gr.n = N;
     gr.n_mask = nm;
     gr.prec = prec;
-    gr.G = rb_carve<char>(a, NP * opb);
+    gr.G = rb_carve<char>(a, NG * opb);
     gr.H = rb_carve<char>(a, 3 * (lp ? NPp : NP) * opb);
     float *d_born = rb_carve<float>(a, 2 * NN);
     float *R = rb_carve<float>(a, 2 * NN);

@@ -82,7 +82,8 @@ __global__ void __launch_bounds__(256) green_kernel(rb_tables tb, int N, int n_m
     H[2 * plane + o] = make_float2(hr * uy, hi * uy);
 }
 
-// R[e][r] = g_rx + d_born - data on valid pairs with e != r; sum |R|^2 into *norm.
+// R[e][r] = g_rx + d_born - data on valid pairs with e != r; sum |R|^2 into *norm. One
+// workgroup per emitter row e: one atomic per row for the norm.
 __global__ void __launch_bounds__(256) residual_kernel(const double *__restrict__ rx_T,
                                                        const float *__restrict__ rx_A,
                                                        const uint8_t *__restrict__ rx_flags,
@@ -90,31 +91,36 @@ __global__ void __launch_bounds__(256) residual_kernel(const double *__restrict_
                                                        const float2 *__restrict__ d_born,
                                                        const float2 *__restrict__ data,
                                                        float2 *__restrict__ R, double *norm) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
-    bool in = r < N;
-    size_t o = (size_t)e * N + (in ? r : 0);
-    uint8_t f = in ? rx_flags[o] : 0;
-    float2 out = make_float2(0.f, 0.f);
-    if ((f & 0x80) && r != e) {
-        double k0 = omega / c0;
-        double ph = reduce_phase(omega * rx_T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI);
-        double s, c;
-        sincos(ph, &s, &c);
-        double a = (double)rx_A[o] / sqrt(k0);
-        double gr = a * c, gi = a * s;
-        if (d_born) {
-            gr += d_born[o].x;
-            gi += d_born[o].y;
+    __shared__ double red[4];
+    const int e = blockIdx.x;
+    const double isk = 1.0 / sqrt(omega / c0);
+    double v = 0.0;
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        const size_t o = (size_t)e * N + r;
+        const uint8_t f = rx_flags[o];
+        float2 out = make_float2(0.f, 0.f);
+        if ((f & 0x80) && r != e) {
+            double ph =
+                reduce_phase(omega * rx_T[o] + 0.25 * RB_PI - (double)(f & 3) * 0.5 * RB_PI);
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            double a = (double)rx_A[o] * isk;
+            double gr = a * cs, gi = a * sn;
+            if (d_born) {
+                gr += d_born[o].x;
+                gi += d_born[o].y;
+            }
+            float2 dd = data[o];
+            out = make_float2((float)(gr - dd.x), (float)(gi - dd.y));
         }
-        float2 dd = data[o];
-        out = make_float2((float)(gr - dd.x), (float)(gi - dd.y));
+        R[o] = out;
+        v += (double)out.x * out.x + (double)out.y * out.y;
     }
-    if (in) R[o] = out;
     if (norm) {
-        double v = (double)out.x * out.x + (double)out.y * out.y;
-        // wavefront sum, then one atomic per wavefront
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-        if ((threadIdx.x & 63) == 0) atomicAdd(norm, v);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(norm, (red[0] + red[1]) + (red[2] + red[3]));
     }
 }
 
@@ -227,9 +233,8 @@ rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double
 rb_status rb_launch_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const float *d_born, const float *data, float *R,
                              double *residual_norm) {
-    dim3 grd(blocks(tb->n), tb->n);
     rb_prof_begin(ctx, ST_RESIDUAL);
-    hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, ctx->stream, tb->rx_T, tb->rx_A,
+    hipLaunchKernelGGL(residual_kernel, dim3(tb->n), dim3(256), 0, ctx->stream, tb->rx_T, tb->rx_A,
                        tb->rx_flags, tb->n, omega, c0, (const float2 *)d_born,
                        (const float2 *)data, (float2 *)R, residual_norm);
     RB_CHECK_LAUNCH(ctx);

@@ -25,6 +25,9 @@ struct rb_arena {
 // was being captured; the capture is discarded, the workspace grown, and the capture redone.
 #define RB_ERETRY ((rb_status)-100)
 
+// Workgroups (and partial maxima) of a range-scale reduction.
+#define RB_RED_PARTS 512
+
 // Words of rb_ctx::d_flag: error bits (1 ray overflow, 2 non-finite update), index of the
 // first failing step of a sweep, mask nodes the binning could not place, and (as int64 at
 // word 4) the ray samples of the last trace.
@@ -54,6 +57,7 @@ struct rb_ctx {
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
     int32_t *d_flag = nullptr;        // device words RB_W_* (flags, counters)
+    float *d_red = nullptr;           // [RB_RED_PARTS] per-block partials of range scales
     int32_t *h_flag = nullptr;        // pinned host mirror of d_flag
     int64_t lost_nodes = 0;           // mask nodes the last binning could not place
     int64_t ray_samples = 0;          // ray samples written by the last trace

@@ -82,6 +82,20 @@ __device__ __forceinline__ float angle_between(float ax, float ay, float bx, flo
     return fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
 }
 
+// Lanes of the nodes past the last one write G's zero padding (rows are rb_lp_pad(n_mask)
+// long) and nothing else.
+template <typename T>
+__device__ __forceinline__ void green_pad_g(T *Gp, size_t gplane, int Mp, int N, int e0, int q) {
+#pragma unroll
+    for (int r = 0; r < GW; ++r) {
+        const int e = e0 + r;
+        if (e < N) {
+            Gp[(size_t)e * Mp + q] = to_lp<T>(0.f);
+            Gp[gplane + (size_t)e * Mp + q] = to_lp<T>(0.f);
+        }
+    }
+}
+
 // G = A k0^-1/2 e^{i phi} and H = a k0^1/2 A^-1 e^{-i phi}, phi = omega T + pi/4 - K pi/2
 // reduced modulo 2 pi in FP64 (Eqs. 2D_greens, greens-time-reversed; a: angular weight).
 __device__ __forceinline__ void green_entry(double omega, double Tt, uint32_t K, float A, float a,
@@ -109,8 +123,13 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = blockIdx.x * GQ + lane;
     const int e0 = blockIdx.y * GE + w * GW;
-    const int Np = rb_lp_pad(N);
-    if (q >= n_mask || e0 >= Np) return;  // no barrier in this kernel
+    const int Np = rb_lp_pad(N), Mp = rb_lp_pad(n_mask);
+    const size_t gplane = (size_t)N * Mp;
+    if (q >= Mp || e0 >= Np) return;  // no barrier in this kernel
+    if (q >= n_mask) {
+        if (write_g) green_pad_g(Gp, gplane, Mp, N, e0, q);
+        return;
+    }
     // rows e0 - 1 .. e0 + GW (indices mod N)
     float ux[GW + 2], uy[GW + 2];
     uint32_t valid = 0;
@@ -126,7 +145,6 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
     }
     const double k0 = omega / c0;
     const float sk = (float)sqrt(k0), isk = 1.0f / sk;
-    const size_t gplane = (size_t)N * n_mask;
     float2 f2 = make_float2(1.f, 0.f);
     if (write_g && gs) {
         f2 = gs[q];
@@ -152,10 +170,11 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
                 green_entry(omega, tb.T[o], tb.flags[o], tb.A[o], a, sk, isk, gr, gi, hr, hi);
             }
             if (write_g) {
+                const size_t og = (size_t)e * Mp + q;
                 float tr = gr * f2.x - gi * f2.y;
                 gi = gr * f2.y + gi * f2.x;
-                Gp[o] = to_lp<T>(tr);
-                Gp[gplane + o] = to_lp<T>(gi);
+                Gp[og] = to_lp<T>(tr);
+                Gp[gplane + og] = to_lp<T>(gi);
             }
         }
         float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
@@ -185,73 +204,79 @@ __device__ __forceinline__ float wrap_pi(float x) {
     return x - (float)RB_TWO_PI * rintf(x * (float)(1.0 / RB_TWO_PI));
 }
 
+// Stores go through LDS: the workgroup's 64 x 64 tile of G leaves as 16-byte pieces of
+// rows (over nodes), and each node's 64 transducers of H as one 128-byte row piece written by
+// eight consecutive threads (H in two halves of three planes; one 28 KB buffer for all).
+constexpr int GH_LD = GE + 8;  // H staging pitch (elements): 16-byte lane writes miss no bank
+
 template <typename T>
 __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     const float4 *__restrict__ rec, const int32_t *__restrict__ mask_index,
     const double2 *__restrict__ ring, double x0, double y0, double dx, int nx, int N, int n_mask,
     double omega, double c0, const float2 *__restrict__ gs, const float *__restrict__ gscale,
     int write_g, T *__restrict__ Gp, T *__restrict__ Ht) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = blockIdx.x * GQ + lane;
-    const int e0 = blockIdx.y * GE + w * GW;
-    const int Np = rb_lp_pad(N);
-    if (q >= n_mask || e0 >= Np) return;  // no barrier in this kernel
-    const int p = mask_index[q];
-    const double px = x0 + (p % nx) * dx, py = y0 + (p / nx) * dx;
-    // records of rows e0 - 1 .. e0 + GW (indices mod N)
+    __shared__ __attribute__((aligned(16))) T stage[3 * GQ * GH_LD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int q0 = blockIdx.x * GQ, E0 = blockIdx.y * GE;
+    const int q = q0 + lane;
+    const int e0 = E0 + w * GW;
+    const int Np = rb_lp_pad(N), Mp = rb_lp_pad(n_mask);
+    const size_t gplane = (size_t)N * Mp;
+    const bool node = q < n_mask;
     float th[GW + 2], dTr[GW], Ar[GW];
     uint32_t valid = 0, Kb = 0;
+    double px = 0.0, py = 0.0;
+    float2 f2 = make_float2(1.f, 0.f);
+    if (node) {
+        const int p = mask_index[q];
+        px = x0 + (p % nx) * dx;
+        py = y0 + (p / nx) * dx;
+        // records of rows e0 - 1 .. e0 + GW (indices mod N)
 #pragma unroll
-    for (int r = 0; r < GW + 2; ++r) {
-        int e = e0 - 1 + r;
-        e = e < 0 ? e + N : (e >= N ? e - N : e);
-        if (e >= N) e = 0;  // rows past the padding end: never used
-        const float4 v = rec[(size_t)e * n_mask + q];
-        const uint32_t f = __float_as_uint(v.w);
-        valid |= (f & 0x80) ? (1u << r) : 0u;
-        th[r] = v.z;
-        if (r >= 1 && r <= GW) {
-            dTr[r - 1] = v.x;
-            Ar[r - 1] = v.y;
-            Kb |= (f & 3) << (2 * (r - 1));
+        for (int r = 0; r < GW + 2; ++r) {
+            int e = e0 - 1 + r;
+            e = e < 0 ? e + N : (e >= N ? e - N : e);
+            if (e >= N) e = 0;  // rows past the padding end: never used
+            const float4 v = rec[(size_t)e * n_mask + q];
+            const uint32_t f = __float_as_uint(v.w);
+            valid |= (f & 0x80) ? (1u << r) : 0u;
+            th[r] = v.z;
+            if (r >= 1 && r <= GW) {
+                dTr[r - 1] = v.x;
+                Ar[r - 1] = v.y;
+                Kb |= (f & 3) << (2 * (r - 1));
+            }
+        }
+        if (write_g && gs) {
+            f2 = gs[q];
+            float sc = gscale[0];
+            f2.x *= sc;
+            f2.y *= sc;
         }
     }
     const double k0 = omega / c0, ic0 = 1.0 / c0;
     const float sk = (float)sqrt(k0), isk = 1.0f / sk;
-    const size_t gplane = (size_t)N * n_mask;
-    float2 f2 = make_float2(1.f, 0.f);
-    if (write_g && gs) {
-        f2 = gs[q];
-        float sc = gscale[0];
-        f2.x *= sc;
-        f2.y *= sc;
-    }
+    T *sg = stage;  // G tile [2][GE][GQ]
     uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
 #pragma unroll
     for (int r = 0; r < GW; ++r) {
         const int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
-        if (e < N) {
-            size_t o = (size_t)e * n_mask + q;
-            if (valid >> (r + 1) & 1u) {
-                __sincosf(th[r + 1], &vy, &vx);
-                const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
-                float a = 0.f;
-                if (vm && vp) a = 0.5f * fabsf(wrap_pi(th[r + 2] - th[r]));
-                else if (vp) a = fabsf(wrap_pi(th[r + 2] - th[r + 1]));
-                else if (vm) a = fabsf(wrap_pi(th[r + 1] - th[r]));
-                const double2 xe = ring[e];
-                const double ddx = px - xe.x, ddy = py - xe.y;
-                const double Tt = (double)dTr[r] + sqrt(ddx * ddx + ddy * ddy) * ic0;
-                green_entry(omega, Tt, Kb >> (2 * r), Ar[r], a, sk, isk, gr, gi, hr, hi);
-            }
-            if (write_g) {
-                float tr = gr * f2.x - gi * f2.y;
-                gi = gr * f2.y + gi * f2.x;
-                Gp[o] = to_lp<T>(tr);
-                Gp[gplane + o] = to_lp<T>(gi);
-            }
+        if (node && e < N && (valid >> (r + 1) & 1u)) {
+            __sincosf(th[r + 1], &vy, &vx);
+            const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
+            float a = 0.f;
+            if (vm && vp) a = 0.5f * fabsf(wrap_pi(th[r + 2] - th[r]));
+            else if (vp) a = fabsf(wrap_pi(th[r + 2] - th[r + 1]));
+            else if (vm) a = fabsf(wrap_pi(th[r + 1] - th[r]));
+            const double2 xe = ring[e];
+            const double ddx = px - xe.x, ddy = py - xe.y;
+            const double Tt = (double)dTr[r] + sqrt(ddx * ddx + ddy * ddy) * ic0;
+            green_entry(omega, Tt, Kb >> (2 * r), Ar[r], a, sk, isk, gr, gi, hr, hi);
         }
+        const float tr = gr * f2.x - gi * f2.y, ti = gr * f2.y + gi * f2.x;
+        sg[(w * GW + r) * GQ + lane] = to_lp<T>(tr);
+        sg[(GE + w * GW + r) * GQ + lane] = to_lp<T>(ti);
         float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
 #pragma unroll
         for (int cp = 0; cp < 6; ++cp) {
@@ -259,27 +284,57 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
         }
     }
-    // transposed rows (c, part, q), Np long (zeros past N)
+    __syncthreads();
+    if (write_g) {
+        // 2 planes x GE rows x 8 pieces of 8 nodes: four per thread
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int id = tid + 256 * k;
+            const int part = id >> 9, row = (id >> 3) & (GE - 1), ch = id & 7;
+            const int e = E0 + row, qq = q0 + ch * 8;
+            if (e < N && qq < Mp)
+                *reinterpret_cast<uint4 *>(Gp + part * gplane + (size_t)e * Mp + qq) =
+                    *reinterpret_cast<const uint4 *>(&sg[(part * GE + row) * GQ + ch * 8]);
+        }
+    }
     const size_t hplane = (size_t)n_mask * Np;
 #pragma unroll
-    for (int cp = 0; cp < 6; ++cp) {
-        T *dst = Ht + (size_t)cp * hplane + (size_t)q * Np + e0;
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
-        if (e0 + 8 < Np)
-            *reinterpret_cast<uint4 *>(dst + 8) =
-                make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();  // the staging buffer is free again
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int cp = 3 * half + k;
+            uint4 *dst = reinterpret_cast<uint4 *>(&stage[(k * GQ + lane) * GH_LD + w * GW]);
+            dst[0] = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
+            dst[1] = make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
+        }
+        __syncthreads();
+        // 3 planes x GQ node rows x 8 pieces of 8 transducers: six per thread
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int id = tid + 256 * k;
+            const int pl = id >> 9, qr = (id >> 3) & (GQ - 1), ch = id & 7;
+            const int qq = q0 + qr, e = E0 + ch * 8;
+            if (qq < n_mask && e < Np)
+                *reinterpret_cast<uint4 *>(Ht + (size_t)(3 * half + pl) * hplane +
+                                           (size_t)qq * Np + e) =
+                    *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GH_LD + ch * 8]);
+        }
     }
 }
 
 // Power-of-two range scale of an operand: scale[0] = 2^(top - e) and scale[1] = 1/scale[0]
 // with 2^(e-1) <= max |x| < 2^e, so the largest scaled magnitude lies in [2^(top-1), 2^top)
-// (top = 14: inside the FP16 range, far from its subnormals). One block; exact.
-__global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restrict__ x,
-                                                           size_t count, const float *__restrict__ y,
-                                                           int top, float *__restrict__ scale) {
-    __shared__ float red[16];
+// (top = 14: inside the FP16 range, far from its subnormals). |x| of a complex value is the
+// larger of |re| and |im| (times |y| when y is given). Exact: per-workgroup maxima, then one
+// workgroup over them.
+__global__ void __launch_bounds__(256) range_max_kernel(const float2 *__restrict__ x,
+                                                        size_t count, const float *__restrict__ y,
+                                                        float *__restrict__ part) {
+    __shared__ float red[4];
     float m = 0.f;
-    for (size_t i = threadIdx.x; i < count; i += blockDim.x) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x) {
         float2 v = x[i];
         float a = fmaxf(fabsf(v.x), fabsf(v.y));
         if (y) a *= fabsf(y[i]);
@@ -288,15 +343,38 @@ __global__ void __launch_bounds__(1024) range_scale_kernel(const float2 *__restr
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ void __launch_bounds__(256) range_finish_kernel(const float *__restrict__ part,
+                                                           int n_part, int top,
+                                                           float *__restrict__ scale) {
+    __shared__ float red[4];
+    float m = 0.f;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) m = fmaxf(m, part[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        float mm = 0.f;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mm = fmaxf(mm, red[i]);
+        float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
         int e = 0;
         if (mm > 0.f && isfinite(mm)) frexpf(mm, &e);
         float s = ldexpf(1.f, top - e);
         scale[0] = s;
         scale[1] = 1.f / s;
     }
+}
+
+rb_status launch_range_scale(rb_ctx *ctx, const float2 *x, size_t count, const float *y, int top,
+                             float *scale) {
+    const int nb = (int)std::min<size_t>(RB_RED_PARTS, std::max<size_t>(1, (count + 1023) / 1024));
+    hipLaunchKernelGGL(range_max_kernel, dim3(nb), dim3(256), 0, ctx->stream, x, count, y,
+                       ctx->d_red);
+    RB_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(range_finish_kernel, dim3(1), dim3(256), 0, ctx->stream,
+                       (const float *)ctx->d_red, nb, top, scale);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
 }
 
 // The back-projection needs R only through the bilinear forms h^T R h (the same operand on
@@ -406,6 +484,97 @@ __device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[4][2],
         }
 }
 
+// The pipelined K loop: acc += A B^T over K steps [kt0, kt1) of LR_BK, complex operands in two
+// part planes. A: the tile's LR_BM rows, B: its LR_BN rows; each loader lane (chunk tid & 3 of
+// part (tid >> 2) & 1) reads rows (tid >> 3) + 32 u, whose first bytes are a_off / b_off
+// (+ u row_step) in the descriptors ra / rb. Global operands of step k+2 are fetched into
+// registers during step k; LDS is double-buffered with one barrier per step. The LDS tiles
+// are still being read when it returns: a barrier must precede their next fill.
+template <typename T>
+__device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][LR_BPLANE],
+                                            __amdgpu_buffer_rsrc_t ra_rsrc, uint32_t a_off,
+                                            __amdgpu_buffer_rsrc_t rb_rsrc, uint32_t b_off,
+                                            uint32_t row_step, int kt0, int kt1,
+                                            floatx16 (&acc_re)[4][2], floatx16 (&acc_im)[4][2]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
+    uint4 ra[8], rb[4];
+    auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
+        const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            *reinterpret_cast<uint4 *>(&a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) =
+                ra[u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            *reinterpret_cast<uint4 *>(&b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) =
+                rb[u];
+    };
+    fetch(kt0);
+    stash(0);
+    if (kt0 + 1 < kt1) fetch(kt0 + 1);
+    __syncthreads();
+    LrFrag f0, f1;
+    lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
+    int kt = kt0;
+    // Steady state (tiles kt+1 and kt+2 exist): branch-free, so that the LDS reads, the
+    // stash of tile kt+1 and the fetch of tile kt+2 are spread between the MFMAs of the
+    // first sub-step, and the LDS reads of the next step between those of the second.
+    for (; kt + 2 < kt1; ++kt) {
+        const int cur = (kt - kt0) & 1;
+        lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
+        lr_mfma<T>(f0, acc_re, acc_im);
+        stash(cur ^ 1);
+        fetch(kt + 2);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // DS write
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);  // VMEM read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __syncthreads();
+        lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1], wm, wn,
+                   lane, 0);
+        lr_mfma<T>(f1, acc_re, acc_im);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 20, 0);
+    }
+    // the last one or two steps
+    for (; kt < kt1; ++kt) {
+        const int cur = (kt - kt0) & 1;
+        lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
+        lr_mfma<T>(f0, acc_re, acc_im);
+        if (kt + 1 < kt1) {
+            stash(cur ^ 1);
+            __syncthreads();
+            lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1],
+                       wm, wn, lane, 0);
+        }
+        lr_mfma<T>(f1, acc_re, acc_im);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restrict__ Rp,
                                                                const T *__restrict__ Ht, int n,
@@ -464,43 +633,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restri
                             acc_re[mt][nt][i] = 0.f;
                             acc_im[mt][nt][i] = 0.f;
                         }
-                uint4 ra[8], rb[4];
-                auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
-                    const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
-                };
-                auto stash = [&](int buf) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        *reinterpret_cast<uint4 *>(
-                            &a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = ra[u];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        *reinterpret_cast<uint4 *>(
-                            &b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) = rb[u];
-                };
-                fetch(KT0);
-                stash(0);
-                if (KT0 + 1 < KT) fetch(KT0 + 1);
-                __syncthreads();
-                LrFrag f0, f1;
-                lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
-                for (int kt = KT0; kt < KT; ++kt) {
-                    const int cur = (kt - KT0) & 1;
-                    lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn,
-                               lane, 16);
-                    lr_mfma<T>(f0, acc_re, acc_im);
-                    if (kt + 1 < KT) stash(cur ^ 1);   // tile kt+1 into the idle buffer
-                    if (kt + 2 < KT) fetch(kt + 2);    // tile kt+2 into registers
-                    __syncthreads();
-                    if (kt + 1 < KT)
-                        lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0],
-                                   b_s[cur ^ 1][1], wm, wn, lane, 0);
-                    lr_mfma<T>(f1, acc_re, acc_im);
-                }
+                lr_mainloop<T>(a_s, b_s, ra_rsrc, a_off, rb_rsrc, b_off, row_step, KT0, KT, acc_re,
+                               acc_im);
                 // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
                 // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
                 // rows beyond n carry Y = 0)
@@ -572,7 +706,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ Gp,
                                                          const float2 *__restrict__ w,
                                                          const float *__restrict__ delta, int n,
-                                                         int K, int nT, int kchunk, int splitk,
+                                                         int K, int ld, int nT, int kchunk,
+                                                         int splitk,
                                                          const float *__restrict__ vscale,
                                                          float2 *__restrict__ dpart) {
     __shared__ __attribute__((aligned(16))) T a_s[2][LF_B][LF_LD];
@@ -591,7 +726,7 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int row0 = tm * LF_B, col0 = tn * LF_B;
-    const size_t gplane = (size_t)n * K;
+    const size_t gplane = (size_t)n * ld;
 
     floatx16 acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -605,7 +740,7 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
             }
 
     // each tile: 128 rows x 4 chunks of 8 K = 512 (row, chunk) pairs, 2 per thread
-    const bool kvec = (K % 8) == 0;
+    const bool kvec = (ld % 8) == 0;
     for (int k0 = kbeg; k0 < kend; k0 += LF_BK) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -632,16 +767,16 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
             // 8 consecutive K of one row of G (both parts), zero beyond the chunk end
             auto row8 = [&](int grow, T *re, T *im) {
                 if (grow < n && kvec && gk + 7 < kend) {
-                    uint4 a = *reinterpret_cast<const uint4 *>(Gp + (size_t)grow * K + gk);
-                    uint4 b = *reinterpret_cast<const uint4 *>(Gp + gplane + (size_t)grow * K + gk);
+                    uint4 a = *reinterpret_cast<const uint4 *>(Gp + (size_t)grow * ld + gk);
+                    uint4 b = *reinterpret_cast<const uint4 *>(Gp + gplane + (size_t)grow * ld + gk);
                     __builtin_memcpy(re, &a, 16);
                     __builtin_memcpy(im, &b, 16);
                 } else {
 #pragma unroll
                     for (int z = 0; z < 8; ++z) {
                         bool ok = grow < n && gk + z < kend;
-                        re[z] = ok ? Gp[(size_t)grow * K + gk + z] : to_lp<T>(0.f);
-                        im[z] = ok ? Gp[gplane + (size_t)grow * K + gk + z] : to_lp<T>(0.f);
+                        re[z] = ok ? Gp[(size_t)grow * ld + gk + z] : to_lp<T>(0.f);
+                        im[z] = ok ? Gp[gplane + (size_t)grow * ld + gk + z] : to_lp<T>(0.f);
                     }
                 }
             };
@@ -711,6 +846,72 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
         }
 }
 
+// Forward on operands that already carry sqrt(v): d[e][r] = sum_q G[e][q] G[r][q], on the
+// pipelined K loop of the back-projection. Tiles LR_BM (e) x LR_BN (r) cover the upper
+// triangle (row block tm takes column blocks from tm LR_BM / LR_BN on); K (nodes) is split
+// into chunks of kchunk steps, each workgroup writing its chunk's partial sums of the tile's
+// elements with e <= r. Workgroups are dealt to the 8 XCDs round-robin: every tile of one
+// chunk goes to the same XCD, so the chunk's columns of G come from HBM once. Rows of G are
+// ld long with zeros past the last node; rows past n read other finite data or zeros and
+// only reach outputs that are not stored.
+template <typename T>
+__global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const T *__restrict__ Gp,
+                                                                  int n, int ld, int nTn,
+                                                                  int tiles, int kchunk,
+                                                                  int splitk,
+                                                                  float2 *__restrict__ dpart) {
+    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
+    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
+    const int kq = blockIdx.x >> 3;
+    const int split = (kq / tiles) * 8 + (blockIdx.x & 7);
+    if (split >= splitk) return;  // whole workgroup: no barrier is skipped by part of it
+    constexpr int RB = LR_BM / LR_BN;  // column blocks per row block
+    int rem = kq % tiles, tm = 0;
+    while (rem >= nTn - tm * RB) {
+        rem -= nTn - tm * RB;
+        ++tm;
+    }
+    const int tn = tm * RB + rem;
+    const int row0 = tm * LR_BM, col0 = tn * LR_BN;
+    const int KT = ld / LR_BK;
+    const int kt0 = split * kchunk, kt1 = min(KT, kt0 + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
+    const size_t gplane = (size_t)n * ld;
+    const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(Gp, 2 * gplane * sizeof(T));
+    const uint32_t row_step = (uint32_t)(32 * (size_t)ld * sizeof(T));
+    const uint32_t a_off =
+        (uint32_t)((l_part * gplane + (size_t)(row0 + l_row) * ld + l_ch * 8) * sizeof(T));
+    const uint32_t b_off =
+        (uint32_t)((l_part * gplane + (size_t)(col0 + l_row) * ld + l_ch * 8) * sizeof(T));
+    floatx16 acc_re[4][2], acc_im[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                acc_re[mt][nt][i] = 0.f;
+                acc_im[mt][nt][i] = 0.f;
+            }
+    lr_mainloop<T>(a_s, b_s, rsrc, a_off, rsrc, b_off, row_step, kt0, kt1, acc_re, acc_im);
+    float2 *out = dpart + (size_t)split * n * n;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int gc = col0 + wn * 64 + nt * 32 + (lane & 31);
+        if (gc >= n) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int gr = row0 + wm * 128 + mt * 32 + mfma_row(lane, i);
+                if (gr <= gc)
+                    out[(size_t)gr * n + gc] = make_float2(acc_re[mt][nt][i], acc_im[mt][nt][i]);
+            }
+    }
+}
+
 __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int splitk,
                                   const float *__restrict__ vscale, float2 *__restrict__ d) {
     int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
@@ -775,9 +976,7 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
     const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
     // |R'| <= 2 max |R|: scale max |R| to [2^12, 2^13) so R' stays below 2^14
-    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
-                       (const float2 *)R, nn, (const float *)nullptr, 13, scale);
-    RB_CHECK_LAUNCH(ctx);
+    RB_TRY(launch_range_scale(ctx, (const float2 *)R, nn, nullptr, 13, scale));
     size_t npad = (size_t)n * np;
     dim3 grd((unsigned)((npad + 255) / 256));
     if (prec == RB_BF16)
@@ -792,10 +991,7 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
 }
 
 rb_status rb_launch_range_scale(rb_ctx *ctx, const float *x, size_t count, int top, float *scale) {
-    hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream, (const float2 *)x,
-                       count, (const float *)nullptr, top, scale);
-    RB_CHECK_LAUNCH(ctx);
-    return RB_OK;
+    return launch_range_scale(ctx, (const float2 *)x, count, nullptr, top, scale);
 }
 
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale) {
@@ -837,15 +1033,36 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
 
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale) {
-    const int n = gr->n, K = gr->n_mask;
-    const int nT = (n + LF_B - 1) / LF_B;
-    const int tiles = nT * (nT + 1) / 2;
-    int ksteps = (K + LF_BK - 1) / LF_BK;
-    int splitk = (1024 + tiles - 1) / tiles;
-    splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
-    splitk = (splitk + 7) / 8 * 8;  // K chunks spread evenly over the 8 XCDs
-    int kchunk = ((ksteps + splitk - 1) / splitk) * LF_BK;
-    splitk = (K + kchunk - 1) / kchunk;
+    const int n = gr->n, K = gr->n_mask, ld = rb_lp_pad(K);
+    // Operands that carry sqrt(v) take the pipelined kernel while G's two planes fit one
+    // buffer descriptor; the node weights of the standalone call are folded in on the fly.
+    const bool pipe = !w && 2 * (size_t)n * ld * 2 <= LR_SPAN;
+    int nT, tiles, kchunk, splitk;
+    const int ksteps = pipe ? ld / LR_BK : (K + LF_BK - 1) / LF_BK;
+    if (pipe) {
+        nT = (n + LR_BN - 1) / LR_BN;
+        tiles = 0;
+        for (int tm = 0; tm * (LR_BM / LR_BN) < nT; ++tm) tiles += nT - tm * (LR_BM / LR_BN);
+        // K chunks in multiples of 8 (one XCD per chunk group): the fewest that fill the
+        // device at least 1.5 times over with at most 7 % of the last round idle
+        const int cu = std::max(8, ctx->n_cu);
+        splitk = 8;
+        for (int s8 = 8; s8 <= 1024; s8 += 8) {
+            const long blocks = (long)tiles * s8, rounds = (blocks + cu - 1) / cu;
+            splitk = s8;
+            if (ksteps / s8 < 8) break;
+            if (2 * blocks >= 3L * cu && (double)blocks / (double)(rounds * cu) >= 0.93) break;
+        }
+        splitk = std::max(1, std::min(splitk, ksteps));
+    } else {
+        nT = (n + LF_B - 1) / LF_B;
+        tiles = nT * (nT + 1) / 2;
+        splitk = (1024 + tiles - 1) / tiles;
+        splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
+        splitk = (splitk + 7) / 8 * 8;  // K chunks spread evenly over the 8 XCDs
+    }
+    kchunk = (ksteps + splitk - 1) / splitk;
+    splitk = (ksteps + kchunk - 1) / kchunk;
     const unsigned nblk = (unsigned)(tiles * ((splitk + 7) / 8) * 8);
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(
@@ -856,21 +1073,28 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     rb_prof_begin(ctx, ST_FORWARD);
     if (w) {
         // range scale of v = w delta (the node weights are folded into the A operand)
-        hipLaunchKernelGGL(range_scale_kernel, dim3(1), dim3(1024), 0, ctx->stream,
-                           (const float2 *)w, (size_t)K, delta, 14, vscale);
+        RB_TRY(launch_range_scale(ctx, (const float2 *)w, (size_t)K, delta, 14, vscale));
     } else {
         // G already carries sqrt(v) s: undo s^2 (or nothing) in the reduction
         hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale, vscale);
+        RB_CHECK_LAUNCH(ctx);
     }
-    RB_CHECK_LAUNCH(ctx);
-    if (gr->prec == RB_BF16)
+    if (pipe && gr->prec == RB_BF16)
+        hipLaunchKernelGGL(forward_pipe_kernel<__bf16>, dim3(nblk), dim3(LR_THREADS), 0,
+                           ctx->stream, (const __bf16 *)gr->G, n, ld, nT, tiles, kchunk, splitk,
+                           dpart);
+    else if (pipe)
+        hipLaunchKernelGGL(forward_pipe_kernel<_Float16>, dim3(nblk), dim3(LR_THREADS), 0,
+                           ctx->stream, (const _Float16 *)gr->G, n, ld, nT, tiles, kchunk, splitk,
+                           dpart);
+    else if (gr->prec == RB_BF16)
         hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, nT, kchunk,
-                           splitk, vscale, dpart);
+                           (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, ld, nT,
+                           kchunk * LF_BK, splitk, vscale, dpart);
     else
         hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const _Float16 *)gr->G, (const float2 *)w, delta, n, K, nT, kchunk,
-                           splitk, vscale, dpart);
+                           (const _Float16 *)gr->G, (const float2 *)w, delta, n, K, ld, nT,
+                           kchunk * LF_BK, splitk, vscale, dpart);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     rb_prof_begin(ctx, ST_FORWARD_REDUCE);

@@ -40,8 +40,12 @@ struct GridP {
 // four control points are the edge value either way.
 constexpr int MPAD = 3;
 
+// The map holds n - 1, not n: the index stays within a few percent of 1, and weighted sums
+// of control points near 1 would lose most of the FP32 digits of the Hessian (about 1e-4
+// per node^2) to cancellation. Near a focus the amplitude is sensitive to exactly those
+// digits.
 struct SplineMap {
-    const float *f;  // [ny + 2 MPAD][nx + 2 MPAD]
+    const float *f;  // [ny + 2 MPAD][nx + 2 MPAD] of n - 1
     int nx, ny, nxp;
     float ih;        // 1 / dx
 };
@@ -69,6 +73,7 @@ __device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], f
 
 // Four consecutive floats of a row, 4-byte aligned: one 16-byte load.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int i2u __attribute__((ext_vector_type(2), aligned(4)));
 
 // The 4 x 4 control points of the cell a lane evaluated last. A step is shorter than a
 // cell, so consecutive evaluations (predictor, corrector, next predictor) mostly fall in the
@@ -118,14 +123,26 @@ __device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, doub
         s_yy = fmaf(ddv[b], r0, s_yy);
     }
     float ih = m.ih, ih2 = ih * ih;
-    return Spline{s_v, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
+    return Spline{s_v + 1.0f, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
 }
 
 // Ray state; the position is in node-index units (u, v) = ((x - x0) / dx, (y - y0) / dx).
+// What a ray integrates over its whole length is FP64: position, wave vector and the
+// paraxial dx (FP32 rounding of the direction, repeated every step, moves the far end of
+// the ray by about 1e-3 node, enough to shift the interpolation in the thin triangles of a
+// focus by percents). The right-hand sides are evaluated in FP32.
 struct Ray {
     double u, v;
-    float kx, ky, dxx, dxy, dkx, dky;
+    double kx, ky, dxx, dxy;
+    float dkx, dky;
 };
+
+// 1 / sqrt(a) from the FP32 estimate and one Newton step (relative error about the square
+// of the FP32 one).
+__device__ __forceinline__ double rsqrt_newton(double a) {
+    const double y = (double)rsqrtf((float)a);
+    return y * fma(-0.5 * a * y, y, 1.5);
+}
 
 // Paraxial right-hand side (Eq. ray-equation-paraxial with k -> n).
 __device__ __forceinline__ void paraxial_rhs(const Spline &s, float kx, float ky, float dxx,
@@ -145,9 +162,10 @@ __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, c
     float hf = (float)h;
     double hu = h * idx;                                    // step in node units
     float n = s1.v;
-    float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
-    float qxx = r.kx * ikn, qxy = r.ky * ikn;               // unit ray direction
-    float kx = n * qxx, ky = n * qxy;                       // normalised wave vector
+    const double ikn = rsqrt_newton(r.kx * r.kx + r.ky * r.ky);
+    const double kxd = (double)n * (r.kx * ikn), kyd = (double)n * (r.ky * ikn);
+    float qxx = (float)(r.kx * ikn), qxy = (float)(r.ky * ikn);  // unit ray direction
+    float kx = (float)kxd, ky = (float)kyd;                 // normalised wave vector
     float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
     Spline s2 = spline_eval(m, r.u + hu * (double)qxx, r.v + hu * (double)qxy, pc);
     float n2 = s2.v;
@@ -160,15 +178,16 @@ __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, c
     Ray o;
     o.u = r.u + hu * (double)(sx * isn);                    // position along mean direction
     o.v = r.v + hu * (double)(sy * isn);
-    o.kx = kx + hf * (s1.gx + s2.gx) * 0.5f;
-    o.ky = ky + hf * (s1.gy + s2.gy) * 0.5f;
+    o.kx = kxd + (double)(hf * (s1.gx + s2.gx) * 0.5f);
+    o.ky = kyd + (double)(hf * (s1.gy + s2.gy) * 0.5f);
     float a[4], b[4];
-    paraxial_rhs(s1, kx, ky, r.dxx, r.dxy, r.dkx, r.dky, a);
+    const float dxx = (float)r.dxx, dxy = (float)r.dxy;
+    paraxial_rhs(s1, kx, ky, dxx, dxy, r.dkx, r.dky, a);
     float dkpx = r.dkx + hf * a[2], dkpy = r.dky + hf * a[3];
-    float dxpx = r.dxx + hf * a[0], dxpy = r.dxy + hf * a[1];
+    float dxpx = dxx + hf * a[0], dxpy = dxy + hf * a[1];
     paraxial_rhs(s2, kpx, kpy, dxpx, dxpy, dkpx, dkpy, b);
-    o.dxx = r.dxx + hf * (a[0] + b[0]) * 0.5f;
-    o.dxy = r.dxy + hf * (a[1] + b[1]) * 0.5f;
+    o.dxx = r.dxx + (double)(hf * (a[0] + b[0]) * 0.5f);
+    o.dxy = r.dxy + (double)(hf * (a[1] + b[1]) * 0.5f);
     o.dkx = r.dkx + hf * (a[2] + b[2]) * 0.5f;
     o.dky = r.dky + hf * (a[3] + b[3]) * 0.5f;
     return o;
@@ -206,10 +225,10 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
     const double2 xy = sb.ring[e];
     // launch angle gamma = psi + pi + delta, |delta| < pi / 2 (Section 4.4 fan)
-    float sd, cd;
-    sincospif(((float)j + 0.5f - 0.5f * (float)n_rays) / (float)n_rays, &sd, &cd);
-    const float cp = (float)(xy.x / R), sp = (float)(xy.y / R);
-    const float cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
+    double sd, cd;
+    sincospi(((double)j + 0.5 - 0.5 * (double)n_rays) / (double)n_rays, &sd, &cd);
+    const double cp = xy.x / R, sp = xy.y / R;
+    const double cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
 
     const double ue = (xy.x - g.x0) * g.idx, ve = (xy.y - g.y0) * g.idx;
     const double uc = -g.x0 * g.idx, vc = -g.y0 * g.idx;  // ring centre
@@ -220,17 +239,17 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     r.v = ve;
     Spline sc = spline_eval(m, r.u, r.v, pc);
     float n_cur = sc.v;
-    r.kx = n_cur * cg;
-    r.ky = n_cur * sg;
-    r.dxx = 0.0f;
-    r.dxy = 0.0f;
-    r.dkx = -n_cur * sg;
-    r.dky = n_cur * cg;
+    r.kx = (double)n_cur * cg;
+    r.ky = (double)n_cur * sg;
+    r.dxx = 0.0;
+    r.dxy = 0.0;
+    r.dkx = (float)(-(double)n_cur * sg);
+    r.dky = (float)((double)n_cur * cg);
     double T = 0.0;
 
     size_t o = (size_t)el * S * n_rays + j;
     sb.pos[o] = make_float2((float)r.u, (float)r.v);
-    sb.fld[o] = make_float4(0.0f, 0.0f, cg, sg);
+    sb.fld[o] = make_float4(0.0f, 0.0f, (float)cg, (float)sg);
     int kfirst = S;  // K is monotone along a ray: zero before kfirst, stored from it on
 
     float J_prev = 0.0f;
@@ -248,7 +267,7 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
             if (pu * pu + pv * pv >= Ru2) {
                 // Definition 1: redo the step with ds' = distance along the unit direction
                 // to the ring.
-                double kn = sqrt((double)r.kx * r.kx + (double)r.ky * r.ky);
+                double kn = sqrt(r.kx * r.kx + r.ky * r.ky);
                 double tx = r.kx / kn, ty = r.ky / kn;
                 double qu = r.u - uc, qv = r.v - vc;
                 double b = (qu * tx + qv * ty) * g.dx;
@@ -262,9 +281,10 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
         sc = spline_eval(m, r.u, r.v, pc);
         float n_new = sc.v;
         T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
-        float ikn = rsqrtf(r.kx * r.kx + r.ky * r.ky);
-        float tx = r.kx * ikn, ty = r.ky * ikn;
-        float J = r.dxx * (-ty) + r.dxy * tx;
+        const float kxf = (float)r.kx, kyf = (float)r.ky;
+        float ikn = rsqrtf(kxf * kxf + kyf * kyf);
+        float tx = kxf * ikn, ty = kyf * ikn;
+        float J = (float)r.dxx * (-ty) + (float)r.dxy * tx;
         if (i >= 1 && J * J_prev < 0.0f) ++K;
         double du = r.u - ue, dv = r.v - ve;
         double d = sqrt_newton(du * du + dv * dv) * g.dx;   // distance from the source
@@ -332,13 +352,14 @@ __global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double
     if ((threadIdx.x & 63) == 0 && cnt > 0) atomicAdd(n_samples, (unsigned long long)cnt);
 }
 
-// Spline map with MPAD replicated nodes on every side.
+// Spline map of n - 1 (exact in FP32 for n in [1/2, 2]) with MPAD replicated nodes on every
+// side.
 __global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float *__restrict__ out) {
     const int nxp = nx + 2 * MPAD;
     int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
     if (i >= nxp) return;
     int si = min(max(i - MPAD, 0), nx - 1), sj = min(max(j - MPAD, 0), ny - 1);
-    out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si];
+    out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si] - 1.0f;
 }
 
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -422,12 +443,17 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
                                           size_t ebase, int n_rays, float pu, float pv, int &j,
                                           int &i, size_t vb[3], float lam[3]) {
     for (int it = 0; it < LOCATE_MAX_IT; ++it) {
-        int Mj = Mrow[j], Mj1 = Mrow[j + 1];
+        // rays j and j+1 are adjacent in memory: one load per pair (j <= n_rays - 2)
+        const i2u Mv = *reinterpret_cast<const i2u *>(Mrow + j);
+        const int Mj = Mv.x, Mj1 = Mv.y;
         int top = min(Mj, Mj1) - 1;  // last quad index along the rays
         if (Mj < 0 || Mj1 < 0 || top < 1) return false;
         if (i > top) i = top;
         size_t b00 = ebase + (size_t)i * n_rays + j, b01 = b00 + n_rays;
-        float2 p00 = sb.pos[b00], p10 = sb.pos[b00 + 1], p01 = sb.pos[b01], p11 = sb.pos[b01 + 1];
+        const f4u q0 = *reinterpret_cast<const f4u *>(sb.pos + b00);
+        const f4u q1 = *reinterpret_cast<const f4u *>(sb.pos + b01);
+        const float2 p00 = make_float2(q0.x, q0.y), p10 = make_float2(q0.z, q0.w);
+        const float2 p01 = make_float2(q1.x, q1.y), p11 = make_float2(q1.z, q1.w);
         float la, lb, lc;
         if (barycentric(p00.x, p00.y, p10.x, p10.y, p11.x, p11.y, pu, pv, la, lb, lc) &&
             la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {

@@ -368,6 +368,44 @@ def test_born_forward_lowp(ctx, name, pname):
     assert np.array_equal(d, d.T)
 
 
+@pytest.mark.parametrize("pname", ["f32", "bf16", "fp16"])
+@pytest.mark.parametrize("n,n_mask", [(64, 37), (300, 1000), (1024, 4133)])
+def test_born_forward_carried_weights(ctx, n, n_mask, pname):
+    # Operands that already carry sqrt(v) (w = delta = NULL), as inside a frequency step:
+    # d = G G^T. Seeded G rounded to the operand type on the host; the oracle takes the
+    # rounded values, so only the FP32 accumulation differs. Shapes: one tile; several
+    # 256 x 128 tiles with a ragged last row and column block and a ragged node count (zeros
+    # past n_mask); the ring size of the large workload.
+    import torch
+    from paper_2211_00316_amd import _lib
+
+    rng = np.random.default_rng(n * 7919 + n_mask)
+    G = rng.standard_normal((n, n_mask)) + 1j * rng.standard_normal((n, n_mask))
+    if pname == "f32":
+        prec = _lib.RB_F32
+        Gq = G.astype(np.complex64)
+        gr = _lib.Green.empty(n, n_mask, "cuda:0", prec)
+        gr.G.copy_(torch.as_tensor(Gq))
+        Gq = Gq.astype(np.complex128)
+    else:
+        prec = LOWP[pname][0]
+        dt = torch.bfloat16 if pname == "bf16" else torch.float16
+        re = torch.as_tensor(G.real).to(dt)
+        im = torch.as_tensor(G.imag).to(dt)
+        Gq = re.double().numpy() + 1j * im.double().numpy()
+        gr = _lib.Green.empty(n, n_mask, "cuda:0", prec)
+        gr.G.zero_()
+        gr.G[0, :, :n_mask].copy_(re)
+        gr.G[1, :, :n_mask].copy_(im)
+    _say(f"born_forward carried weights {pname} n={n} n_mask={n_mask}")
+    d = to_np(ctx.born_forward(gr, None, None))
+    ref = born.forward(Gq, np.ones(n_mask), np.ones(n_mask))
+    err = rel_l2(d, ref)
+    _say(f"  rel L2 {err:.2e}")
+    assert err <= 1e-5
+    assert np.array_equal(d, d.T)
+
+
 @pytest.mark.parametrize("pname", ["bf16", "fp16"])
 @pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
 def test_backproject_lowp(ctx, name, pname):
