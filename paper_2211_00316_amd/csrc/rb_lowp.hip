@@ -489,8 +489,9 @@ __device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[4][2],
 // part (tid >> 2) & 1) reads rows (tid >> 3) + 32 u, whose first bytes are a_off / b_off
 // (+ u row_step) in the descriptors ra / rb. Global operands of step k+2 are fetched into
 // registers during step k; LDS is double-buffered with one barrier per step. The LDS tiles
-// are still being read when it returns: a barrier must precede their next fill.
-template <typename T>
+// are still being read when it returns: a barrier must precede their next fill. DESC walks
+// the K steps from kt1 - 1 down to kt0.
+template <typename T, bool DESC>
 __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][LR_BPLANE],
                                             __amdgpu_buffer_rsrc_t ra_rsrc, uint32_t a_off,
                                             __amdgpu_buffer_rsrc_t rb_rsrc, uint32_t b_off,
@@ -501,7 +502,8 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
     uint4 ra[8], rb[4];
     auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
-        const uint32_t kb = (uint32_t)(kt * LR_BK * sizeof(T));
+        const int kp = DESC ? kt0 + kt1 - 1 - kt : kt;
+        const uint32_t kb = (uint32_t)(kp * LR_BK * sizeof(T));
 #pragma unroll
         for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
 #pragma unroll
@@ -526,7 +528,9 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
     int kt = kt0;
     // Steady state (tiles kt+1 and kt+2 exist): branch-free, so that the LDS reads, the
     // stash of tile kt+1 and the fetch of tile kt+2 are spread between the MFMAs of the
-    // first sub-step, and the LDS reads of the next step between those of the second.
+    // first sub-step, and the LDS reads of the next step between those of the second. The
+    // four waves run in step between barriers; bunched LDS operations would saturate the
+    // LDS while the MFMAs wait, so each group of eight MFMAs carries a few of them.
     for (; kt + 2 < kt1; ++kt) {
         const int cur = (kt - kt0) & 1;
         lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
@@ -534,31 +538,38 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
         stash(cur ^ 1);
         fetch(kt + 2);
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+        for (int i = 0; i < 4; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
         }
-#pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // DS write
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);  // VMEM read
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
         __syncthreads();
         lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1], wm, wn,
                    lane, 0);
         lr_mfma<T>(f1, acc_re, acc_im);
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+        for (int i = 0; i < 4; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 20, 0);
     }
     // the last one or two steps
     for (; kt < kt1; ++kt) {
@@ -602,6 +613,9 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restri
     // their diagonal blocks and together span mblocks + 1 blocks of K, so every item costs the
     // same. Workgroups are dealt to the 8 XCDs round-robin; each XCD walks a contiguous range
     // of items (both pairs of a node tile next to each other, sharing its H tile in L2).
+    // Every slab walks K from the last block down: the two workgroups of a node tile read the
+    // same rows of H at the same time for most of their first slabs, and each slab's epilogue
+    // finds its diagonal block, read last, still in L2.
     const int n_pairs = (mblocks + 1) / 2, n_items = nblocks * n_pairs;
     const int L = gridDim.x >> 3, xcd = blockIdx.x & 7;
     const int per = (((n_items + 7) / 8) + 1) & ~1;
@@ -633,8 +647,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restri
                             acc_re[mt][nt][i] = 0.f;
                             acc_im[mt][nt][i] = 0.f;
                         }
-                lr_mainloop<T>(a_s, b_s, ra_rsrc, a_off, rb_rsrc, b_off, row_step, KT0, KT, acc_re,
-                               acc_im);
+                lr_mainloop<T, true>(a_s, b_s, ra_rsrc, a_off, rb_rsrc, b_off, row_step, KT0, KT,
+                                     acc_re, acc_im);
                 // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
                 // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
                 // rows beyond n carry Y = 0)
@@ -895,7 +909,7 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const T *__res
                 acc_re[mt][nt][i] = 0.f;
                 acc_im[mt][nt][i] = 0.f;
             }
-    lr_mainloop<T>(a_s, b_s, rsrc, a_off, rsrc, b_off, row_step, kt0, kt1, acc_re, acc_im);
+    lr_mainloop<T, false>(a_s, b_s, rsrc, a_off, rsrc, b_off, row_step, kt0, kt1, acc_re, acc_im);
     float2 *out = dpart + (size_t)split * n * n;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
