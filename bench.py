@@ -48,7 +48,7 @@ STAGE_KERNELS = {
     "trace": (["trace_kernel"], ["trace_kernel"]),
     "resolve": (["tile_offset_kernel", "locate_kernel"], ["tile_offset_kernel", "locate_kernel"]),
     "build_green": (["green_kernel"], ["green_lp_rec_kernel"]),
-    "forward_gemm": (["forward_kernel"], ["forward_lp_kernel"]),
+    "forward_gemm": (["forward_kernel"], ["forward_pipe_kernel"]),
     "backproject_gemm": (["rowred_kernel"], ["rowred_lp_kernel"]),
 }
 
