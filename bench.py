@@ -157,14 +157,24 @@ PEAKS = {"f32": (FP32_MFMA_PEAK_TFLOPS, "fp32 MFMA"), "bf16": (2500.0, "bf16 MFM
          "f16": (2500.0, "fp16 MFMA dense")}
 
 
-def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag):
-    """Time `steps` frequency steps of one form from the water model (after `warmup`)."""
+def start_model(w, start, c_true):
+    """Model the timed steps start from: water (the first steps of the frequency
+    continuation) or the true phantom (a late stage, with folded fans)."""
+    import torch
+
+    if start == "truth":
+        return torch.as_tensor(c_true, dtype=torch.float64, device="cuda:0")
+    return torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
+
+
+def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start):
+    """Time `steps` frequency steps of one form from c_start (after `warmup`)."""
     import torch
 
     from paper_2211_00316_amd import _lib
 
     d_om = 2 * math.pi * (w.freqs[1] - w.freqs[0]) if len(w.freqs) > 1 else None
-    c = torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
+    c = c_start.clone()
     rn = torch.zeros(1, dtype=torch.float64, device="cuda:0")
 
     def one_step(k):
@@ -188,9 +198,9 @@ def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag):
     return 1000.0 * elapsed / steps, stages, c
 
 
-def run_sweep(ctx, w, grid, ring, tp, data, prec, steps, warmup):
+def run_sweep(ctx, w, grid, ring, tp, data, prec, steps, warmup, c_start):
     """The same `steps` frequency steps as one graph launch (rb_frequency_sweep): captured and
-    run once from water (untimed), then replayed from water (timed)."""
+    run once from c_start (untimed), then replayed from c_start (timed)."""
     import torch
 
     d_om = 2 * math.pi * (w.freqs[1] - w.freqs[0]) if len(w.freqs) > 1 else None
@@ -199,11 +209,11 @@ def run_sweep(ctx, w, grid, ring, tp, data, prec, steps, warmup):
     dsets = [[d_om or s[0]] for s in sets]
     wins = [w.smooth_window(k) for k in ks]
     sweep_data = data[warmup:warmup + steps]
-    c = torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
+    c = c_start.clone()
     ctx.frequency_sweep(grid, ring, tp, c, wins, sets, dsets, sweep_data, w.tau, prec=prec,
                         use_graph=True)
     print("[bench] graph sweep captured", file=sys.stderr, flush=True)
-    c.fill_(1500.0)
+    c.copy_(c_start)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.frequency_sweep(grid, ring, tp, c, wins, sets, dsets, sweep_data, w.tau, prec=prec,
@@ -287,6 +297,9 @@ def main():
                     help="operand type of the headline (reduced-precision) form")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--start", default="water", choices=["water", "truth"],
+                    help="model of the timed steps: water (first steps of the continuation) "
+                         "or the true phantom (a late stage: heterogeneous, folded fans)")
     ap.add_argument("--no-graph", action="store_true",
                     help="report the eager per-step form only (no graph-captured sweep)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -324,18 +337,19 @@ def main():
     prec_code = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
 
     forms = {}
+    c_start = start_model(w, args.start, c_true)
     if not args.no_fp32 and args.prec != "f32":
         ms32, st32, c32 = run_form(ctx, w, grid, ring, tp, data, _lib.RB_F32, args.steps,
-                                   args.warmup, "f32")
+                                   args.warmup, "f32", c_start)
         forms["f32"] = (ms32, st32, c32)
     ms, stages, c_lp = run_form(ctx, w, grid, ring, tp, data, prec_code, args.steps,
-                                args.warmup, args.prec)
+                                args.warmup, args.prec, c_start)
     forms[args.prec] = (ms, stages, c_lp)
     ms_eager = ms
     graph = None
     if not args.no_graph:
         ms_graph, _ = run_sweep(ctx, w, grid, ring, tp, data, prec_code, args.steps,
-                                      args.warmup)
+                                args.warmup, c_start)
         graph = {"ms_per_step": round(ms_graph, 2), "value": round(1000.0 / ms_graph, 4)}
         ms = ms_graph
 
@@ -366,6 +380,7 @@ def main():
                    "dx_mm": w.dx * 1e3, "rays_per_transducer": w.n_rays,
                    "mask_nodes": int(Pm), "freqs_hz": [w.freqs[k] for k in
                                                         range(args.warmup, n_total)],
+                   "start_model": args.start,
                    "parallelism": "single GPU"},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,

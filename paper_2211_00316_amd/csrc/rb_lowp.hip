@@ -650,34 +650,49 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restri
                 lr_mainloop<T, true>(a_s, b_s, ra_rsrc, a_off, rb_rsrc, b_off, row_step, KT0, KT,
                                      acc_re, acc_im);
                 // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
-                // 8-byte load per part (rows are padded with zeros to np, a multiple of 32, and
-                // rows beyond n carry Y = 0)
+                // 8-byte load per part. Rows are padded with zeros to np, a multiple of 32, so a
+                // 32-row group lies wholly inside np or wholly past it (uniform; such groups get
+                // weight 0), and rows beyond n carry E = 0. Lanes of nodes past the last read the
+                // last node's row; their sums are never stored. No branch: the loads of the next
+                // 32-row group go out before the arithmetic of the current one.
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
-                    const int gq = col0 + wn * 64 + nt * 32 + (lane & 31);
-                    if (gq >= n_cols) continue;
+                    const int gq = min(col0 + wn * 64 + nt * 32 + (lane & 31), n_cols - 1);
                     const T *er_row = Hc + (size_t)gq * np;
-                    const T *ei_row = Hc + hplane + (size_t)gq * np;
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
+                    const T *ei_row = er_row + hplane;
+                    uint2 pr[2][4], pi[2][4];
+                    auto load_group = [&](int mt, int buf) {
+                        const int gb = min(row0 + wm * 128 + mt * 32, np - 32);
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
-                            const int ge = row0 + wm * 128 + mt * 32 + g * 8 + (lane >> 5) * 4;
-                            if (ge >= np) continue;
-                            const uint2 pr = *reinterpret_cast<const uint2 *>(er_row + ge);
-                            const uint2 pi = *reinterpret_cast<const uint2 *>(ei_row + ge);
+                            const int ge = gb + g * 8 + (lane >> 5) * 4;
+                            pr[buf][g] = *reinterpret_cast<const uint2 *>(er_row + ge);
+                            pi[buf][g] = *reinterpret_cast<const uint2 *>(ei_row + ge);
+                        }
+                    };
+                    load_group(0, 0);
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        if (mt < 3) load_group(mt + 1, (mt + 1) & 1);
+                        const float rm = row0 + wm * 128 + mt * 32 < np ? 1.f : 0.f;
+                        float sr = 0.f, si = 0.f;
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
                             T vr[4], vi[4];
-                            __builtin_memcpy(vr, &pr, 8);
-                            __builtin_memcpy(vi, &pi, 8);
+                            __builtin_memcpy(vr, &pr[mt & 1][g], 8);
+                            __builtin_memcpy(vi, &pi[mt & 1][g], 8);
 #pragma unroll
                             for (int z = 0; z < 4; ++z) {
                                 const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
                                 const float yr = acc_re[mt][nt][g * 4 + z];
                                 const float yi = acc_im[mt][nt][g * 4 + z];
-                                cs_re[nt] += er * yr - ei * yi;
-                                cs_im[nt] += er * yi + ei * yr;
+                                sr += er * yr - ei * yi;
+                                si += er * yi + ei * yr;
                             }
                         }
+                        cs_re[nt] += rm * sr;
+                        cs_im[nt] += rm * si;
+                    }
                 }
                 __syncthreads();  // LDS buffers are refilled by the next component
             }

@@ -362,6 +362,11 @@ __global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float *__r
     out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si] - 1.0f;
 }
 
+__device__ __forceinline__ unsigned long long ordered_bits64(double f) {
+    unsigned long long u = (unsigned long long)__double_as_longlong(f);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
     uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -391,24 +396,54 @@ struct TableOut {
     float4 *rec;
 };
 
+// Travel-time residual of a triangle at barycentric (la, lb, lc): one fixed order of
+// operations, so that binning by walk and by rasterisation build identical keys.
+__device__ __forceinline__ float tri_dT(float la, float lb, float lc, float d0, float d1,
+                                        float d2) {
+    return fmaf(lc, d2, fmaf(lb, d1, la * d0));
+}
+
+// Key of a candidate triangle at a node: smallest travel time first, then lowest triangle id.
+__device__ __forceinline__ unsigned long long tri_key(float dT, uint32_t id) {
+    return ((unsigned long long)ordered_bits(dT) << 32) | id;
+}
+
+// Nodes in 8 x 8 tiles, one mark byte per (transducer, tile): set where more than one
+// triangle may cover a node. In a fan whose triangles all keep one orientation (negative
+// area in node coordinates, rays in launch order) no point is covered twice; in general the
+// positive minus the negative covers of a point is the winding number of the fan's boundary
+// about it (0 or 1), so a point covered twice is covered by an inverted triangle. Inverted
+// and near-degenerate triangles mark the tiles their bounding box touches, and a node whose
+// walk failed marks its own tile; the rasterisation skips triangles that touch no marked tile.
+constexpr int MT_SHIFT = 3;
+constexpr float AREA_MARK = -1e-3f;  // node^2: above this a triangle counts as inverted
+
+__device__ __forceinline__ void bbox_tiles(const float *tu, const float *tv, int nx, int ny,
+                                           int &ti0, int &ti1, int &tj0, int &tj1) {
+    float umin = fminf(fminf(tu[0], tu[1]), tu[2]), umax = fmaxf(fmaxf(tu[0], tu[1]), tu[2]);
+    float vmin = fminf(fminf(tv[0], tv[1]), tv[2]), vmax = fmaxf(fmaxf(tv[0], tv[1]), tv[2]);
+    int i0 = max((int)ceilf(umin - 1e-4f), 0), i1 = min((int)floorf(umax + 1e-4f), nx - 1);
+    int j0 = max((int)ceilf(vmin - 1e-4f), 0), j1 = min((int)floorf(vmax + 1e-4f), ny - 1);
+    ti0 = i0 >> MT_SHIFT;
+    ti1 = i1 >> MT_SHIFT;
+    tj0 = j0 >> MT_SHIFT;
+    tj1 = j1 >> MT_SHIFT;
+}
+
 // Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`;
-// K: the largest caustic count of the three vertices.
-__device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t vb[3],
-                                            const float lam[3], int K, double d, double c0,
-                                            const TableOut &to, size_t out) {
-    float dT = 0, L = 0, tx = 0, ty = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        float4 f = sb.fld[vb[k]];
-        dT += lam[k] * f.x;
-        L += lam[k] * f.y;
-        tx += lam[k] * f.z;
-        ty += lam[k] * f.w;
-    }
+// K: the largest caustic count of the three vertices. Returns the interpolated dT.
+__device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
+                                             const float lam[3], int K, double d, double c0,
+                                             const TableOut &to, size_t out) {
+    const float4 f0 = sb.fld[vb[0]], f1 = sb.fld[vb[1]], f2 = sb.fld[vb[2]];
+    const float dT = tri_dT(lam[0], lam[1], lam[2], f0.x, f1.x, f2.x);
+    const float L = tri_dT(lam[0], lam[1], lam[2], f0.y, f1.y, f2.y);
+    const float tx = tri_dT(lam[0], lam[1], lam[2], f0.z, f1.z, f2.z);
+    const float ty = tri_dT(lam[0], lam[1], lam[2], f0.w, f1.w, f2.w);
     const float A = __expf(L) * rsqrtf((float)d);
     if (to.rec) {
         to.rec[out] = make_float4(dT, A, atan2f(ty, tx), __int_as_float(0x80 | (K & 3)));
-        return;
+        return dT;
     }
     const rb_tables &tb = to.tb;
     float itn = rsqrtf(tx * tx + ty * ty);
@@ -417,6 +452,7 @@ __device__ __forceinline__ void write_entry(const SampleBufs &sb, const size_t v
     tb.ux[out] = tx * itn;
     tb.uy[out] = ty * itn;
     tb.flags[out] = (uint8_t)(0x80 | (K & 3));
+    return dT;
 }
 
 __device__ __forceinline__ void write_invalid(const TableOut &to, size_t out) {
@@ -436,13 +472,17 @@ __device__ __forceinline__ void write_invalid(const TableOut &to, size_t out) {
 // contains the point (pu, pv) (node-index units). Returns false if the walk leaves the
 // mesh or does not settle within LOCATE_MAX_IT quads.
 constexpr int LOCATE_MAX_IT = 96;
+// In a fan that folds, inverted triangles mislead the walk's edge tests; a walk that does not
+// settle soon is given up and its node left to the rasterisation.
+constexpr int LOCATE_MAX_IT_FOLD = 16;
 constexpr int LTX = 32, LTY = 8;  // node tile of one locate workgroup
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
                                           size_t ebase, int n_rays, float pu, float pv, int &j,
-                                          int &i, size_t vb[3], float lam[3]) {
-    for (int it = 0; it < LOCATE_MAX_IT; ++it) {
+                                          int &i, size_t vb[3], float lam[3], int &half,
+                                          int max_it = LOCATE_MAX_IT) {
+    for (int it = 0; it < max_it; ++it) {
         // rays j and j+1 are adjacent in memory: one load per pair (j <= n_rays - 2)
         const i2u Mv = *reinterpret_cast<const i2u *>(Mrow + j);
         const int Mj = Mv.x, Mj1 = Mv.y;
@@ -463,6 +503,7 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
             lam[0] = la;
             lam[1] = lb;
             lam[2] = lc;
+            half = 0;
             return true;
         }
         if (barycentric(p00.x, p00.y, p11.x, p11.y, p01.x, p01.y, pu, pv, la, lb, lc) &&
@@ -473,6 +514,7 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
             lam[0] = la;
             lam[1] = lb;
             lam[2] = lc;
+            half = 1;
             return true;
         }
         // step across the quad edge the point lies farthest outside of
@@ -529,7 +571,7 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
     if (tid >= E * ntiles) return;
     const int el = tid / ntiles, t = tid - el * ntiles;
     int2 o = make_int2(0, 0);
-    if (!sb.folded[el]) {
+    {
         const int ti = t % tiles_x, tj = t / tiles_x;
         const int e = e0 + el;
         const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
@@ -544,15 +586,34 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
         i = iw;
         size_t vb[3];
         float lam[3];
+        int half;
         if (d >= 2.0 * ds && mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays,
-                                       n_rays, (float)cu, (float)cv, j, i, vb, lam))
+                                       n_rays, (float)cu, (float)cv, j, i, vb, lam, half))
             o = make_int2(j - jw, i - iw);
     }
     off[tid] = o;
 }
 
+// Caustic count of a triangle (vertices (ray, sample): (j, i), (j + 1, i), (j + 1, i + 1) for
+// half 0; (j, i), (j + 1, i + 1), (j, i + 1) for half 1): the largest of its vertices', K being
+// stored from the first sample of a ray where it is positive.
+__device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int el, int j, int i,
+                                     int half, const size_t vb[3]) {
+    const int kf0 = sb.kfirst[(size_t)el * n_rays + j], kf1 = sb.kfirst[(size_t)el * n_rays + j + 1];
+    const int vi[3] = {i, half ? i + 1 : i, i + 1};
+    const int kf[3] = {kf0, kf1, half ? kf0 : kf1};
+    int K = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (vi[k] >= kf[k]) K = max(K, (int)sb.K[vb[k]]);
+    return K;
+}
+
 // One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
+// In a fan that folds, the walk's triangle is one candidate of the smallest-key rule: its
+// record is written and its key seeds keys[] (changed[] cleared); the rasterisation of the
+// fan then replaces it where a triangle with a smaller key covers the node.
 // Workgroups are dealt to the 8 XCDs round-robin by launch index. The (transducer, tile)
 // sequence is cut into groups of LOCATE_GROUP_ROWS tile rows and group g goes to XCD g mod 8,
 // so neighbouring tiles share their ray samples through one L2 while every XCD still gets an
@@ -563,14 +624,17 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                                                      int tile_i0, int tile_j0, int tiles_x,
                                                      int tiles_y, const int32_t *__restrict__ qmap,
                                                      const int2 *__restrict__ off, TableOut to,
-                                                     int *lost) {
+                                                     unsigned long long *__restrict__ keys,
+                                                     uint8_t *__restrict__ changed,
+                                                     uint8_t *__restrict__ marks, int mtx,
+                                                     int mtiles, int *lost) {
     const int ntiles = tiles_x * tiles_y;
     const int G = LOCATE_GROUP_ROWS * tiles_x;
     const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
     const int item = ((k / G) * 8 + xcd) * G + k % G;
     if (item >= E * ntiles) return;
     const int el = item / ntiles, t = item - el * ntiles;
-    if (sb.folded[el]) return;  // general path (uniform over the block)
+    const bool fold = sb.folded[el] != 0;  // uniform over the block
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
@@ -579,6 +643,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     if (q < 0) return;
     const int e = e0 + el;
     const size_t out = (size_t)e * n_mask + q;
+    const size_t kq = (size_t)el * n_mask + q;
     const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
     const double2 xy = sb.ring[e];
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
@@ -586,6 +651,10 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     double d = sqrt_newton(ddx * ddx + ddy * ddy);
     if (d < 2.0 * ds) {
         write_invalid(to, out);
+        if (fold) {
+            keys[kq] = ~0ull;
+            changed[kq] = 0;
+        }
         return;
     }
     int j, i;
@@ -595,18 +664,47 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     i = min(max(i + o.y, 1), S - 2);
     size_t vb[3];
     float lam[3];
+    int half;
     if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
-                  (float)jj, j, i, vb, lam)) {
-        write_entry(sb, vb, lam, 0, d, c0, to, out);  // no ray of an unfolded fan has K > 0
+                  (float)jj, j, i, vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
+        // no ray of an unfolded fan has K > 0
+        const int K = fold ? tri_K(sb, n_rays, el, j, i, half, vb) : 0;
+        const float dT = write_entry(sb, vb, lam, K, d, c0, to, out);
+        if (fold) {
+            keys[kq] = tri_key(dT, (uint32_t)(((size_t)j * S + i) * 2 + half));
+            changed[kq] = 0;
+        }
     } else {
         write_invalid(to, out);
-        atomicAdd(lost, 1);
+        if (fold) {  // left to the rasterisation
+            keys[kq] = ~0ull;
+            changed[kq] = 0;
+            marks[(size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT)] = 1;
+        } else {
+            atomicAdd(lost, 1);
+        }
     }
 }
 
-__device__ __forceinline__ void raster_tri(const float *tu, const float *tv, const float *tdT,
+// Offer triangle tid to every mask node it covers. Keys only decrease, so a stale read of a
+// node's key costs at most a needless atomic; a node whose key this triangle lowers is
+// marked changed (its record is then rebuilt by the resolve pass).
+__device__ __forceinline__ void raster_tri(const float *tu, const float *tv,
+                                           const float4 *__restrict__ fld, const size_t *vb,
                                            int nx, int ny, const int32_t *__restrict__ qmap,
-                                           unsigned long long *__restrict__ keys, uint32_t tid) {
+                                           unsigned long long *__restrict__ keys,
+                                           uint8_t *__restrict__ changed,
+                                           const uint8_t *__restrict__ marks, int mtx,
+                                           uint32_t tid) {
+    {
+        int ti0, ti1, tj0, tj1;
+        bbox_tiles(tu, tv, nx, ny, ti0, ti1, tj0, tj1);
+        bool any = false;
+        for (int tj = tj0; tj <= tj1; ++tj)
+            for (int ti = ti0; ti <= ti1; ++ti) any |= marks[tj * mtx + ti] != 0;
+        if (!any) return;
+    }
+    const float tdT[3] = {fld[vb[0]].x, fld[vb[1]].x, fld[vb[2]].x};
     float umin = fminf(fminf(tu[0], tu[1]), tu[2]), umax = fmaxf(fmaxf(tu[0], tu[1]), tu[2]);
     float vmin = fminf(fminf(tv[0], tv[1]), tv[2]), vmax = fmaxf(fmaxf(tv[0], tv[1]), tv[2]);
     int i0 = max((int)ceilf(umin - 1e-4f), 0), i1 = min((int)floorf(umax + 1e-4f), nx - 1);
@@ -620,9 +718,11 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv, con
                              lb, lc))
                 return;
             if (la < -RB_BARY_EPS || lb < -RB_BARY_EPS || lc < -RB_BARY_EPS) continue;
-            float dT = la * tdT[0] + lb * tdT[1] + lc * tdT[2];
-            unsigned long long key = ((unsigned long long)ordered_bits(dT) << 32) | tid;
-            atomicMin(keys + q, key);
+            const unsigned long long key = tri_key(tri_dT(la, lb, lc, tdT[0], tdT[1], tdT[2]), tid);
+            if (key < keys[q]) {
+                const unsigned long long old = atomicMin(keys + q, key);
+                if (key < old) changed[q] = 1;
+            }
         }
     }
 }
@@ -641,65 +741,93 @@ __global__ void folded_list(const int32_t *__restrict__ folded, int E, int32_t *
 
 constexpr int FOLD_GRID = 2048;  // workgroups of the grid-stride kernels
 
-// One item per quad (ray j, j+1; samples i, i+1) with i >= 1, i + 1 <= min(M_j, M_j+1).
-__device__ __forceinline__ void raster_quad(const SampleBufs &sb, int n_rays, int S, int el,
-                                            int i, int j, int nx, int ny, int n_mask,
-                                            const int32_t *__restrict__ qmap,
-                                            unsigned long long *__restrict__ keys) {
-    if (i < 1) return;
-    int Mj = sb.M[(size_t)el * n_rays + j], Mj1 = sb.M[(size_t)el * n_rays + j + 1];
-    if (Mj < 0 || Mj1 < 0 || i + 1 > min(Mj, Mj1)) return;
-    size_t b00 = ((size_t)el * S + i) * n_rays + j;
-    size_t b01 = b00 + n_rays;  // (j, i+1)
-    float2 p00 = sb.pos[b00], p10 = sb.pos[b00 + 1], p11 = sb.pos[b01 + 1], p01 = sb.pos[b01];
-    float u00 = p00.x, u10 = p10.x, u11 = p11.x, u01 = p01.x;
-    float v00 = p00.y, v10 = p10.y, v11 = p11.y, v01 = p01.y;
-    float d00 = sb.fld[b00].x, d10 = sb.fld[b00 + 1].x, d11 = sb.fld[b01 + 1].x,
-          d01 = sb.fld[b01].x;
+// One item per run of RCH quads along a pair of neighbouring rays (j, j+1; samples i to
+// i + RCH, i >= 1, i + 1 <= min(M_j, M_j+1)). The edge at sample i + 1 of one quad is the
+// edge at sample i of the next, so each step loads one new pair of positions (one 16-byte
+// load: rays j, j+1 are adjacent) and the two travel-time residuals; consecutive items
+// are consecutive ray pairs, so their loads are coalesced.
+constexpr int RCH = 8;
+
+template <bool MARK>
+__device__ __forceinline__ void raster_run(const SampleBufs &sb, int n_rays, int S, int el,
+                                           int c, int j, int nx, int ny, int n_mask,
+                                           const int32_t *__restrict__ qmap,
+                                           unsigned long long *__restrict__ keys,
+                                           uint8_t *__restrict__ changed,
+                                           uint8_t *__restrict__ marks, int mtx, int mtiles) {
+    const i2u Mv = *reinterpret_cast<const i2u *>(sb.M + (size_t)el * n_rays + j);
+    if (Mv.x < 0 || Mv.y < 0) return;
+    const int top = min(Mv.x, Mv.y);  // quads i with i + 1 <= top
+    const int i0 = max(c * RCH, 1), i1 = min(c * RCH + RCH, top);
+    if (i0 >= i1) return;
     unsigned long long *ek = keys + (size_t)el * n_mask;
-    uint32_t id0 = (uint32_t)(((size_t)j * S + i) * 2);
-    {
-        float tu[3] = {u00, u10, u11}, tv[3] = {v00, v10, v11}, td[3] = {d00, d10, d11};
-        raster_tri(tu, tv, td, nx, ny, qmap, ek, id0);
-    }
-    {
-        float tu[3] = {u00, u11, u01}, tv[3] = {v00, v11, v01}, td[3] = {d00, d11, d01};
-        raster_tri(tu, tv, td, nx, ny, qmap, ek, id0 + 1);
+    uint8_t *ec = changed + (size_t)el * n_mask;
+    uint8_t *em = marks + (size_t)el * mtiles;
+    size_t b = ((size_t)el * S + i0) * n_rays + j;
+    f4u q = *reinterpret_cast<const f4u *>(sb.pos + b);
+    float u0 = q.x, v0 = q.y, u1 = q.z, v1 = q.w;
+    for (int i = i0; i < i1; ++i) {
+        const size_t bp = b;  // row i
+        b += n_rays;          // row i + 1
+        q = *reinterpret_cast<const f4u *>(sb.pos + b);
+        const float u2 = q.z, v2 = q.w, u3 = q.x, v3 = q.y;  // (j+1, i+1), (j, i+1)
+        const uint32_t id0 = (uint32_t)(((size_t)j * S + i) * 2);
+        float tu0[3] = {u0, u1, u2}, tv0[3] = {v0, v1, v2};
+        float tu1[3] = {u0, u2, u3}, tv1[3] = {v0, v2, v3};
+        const size_t vb0[3] = {bp, bp + 1, b + 1}, vb1[3] = {bp, b + 1, b};
+        if (MARK) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float *tu = h ? tu1 : tu0, *tv = h ? tv1 : tv0;
+                const float area =
+                    (tu[1] - tu[0]) * (tv[2] - tv[0]) - (tv[1] - tv[0]) * (tu[2] - tu[0]);
+                if (area > AREA_MARK) {
+                    int ti0, ti1, tj0, tj1;
+                    bbox_tiles(tu, tv, nx, ny, ti0, ti1, tj0, tj1);
+                    for (int tj = tj0; tj <= tj1; ++tj)
+                        for (int ti = ti0; ti <= ti1; ++ti) em[tj * mtx + ti] = 1;
+                }
+            }
+        } else {
+            raster_tri(tu0, tv0, sb.fld, vb0, nx, ny, qmap, ek, ec, em, mtx, id0);
+            raster_tri(tu1, tv1, sb.fld, vb1, nx, ny, qmap, ek, ec, em, mtx, id0 + 1);
+        }
+        u0 = u3; v0 = v3;  // (j, i+1)
+        u1 = u2; v1 = v2;  // (j+1, i+1)
     }
 }
 
+template <bool MARK>
 __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int nx,
                                                      int ny, int n_mask,
                                                      const int32_t *__restrict__ qmap,
                                                      const int32_t *__restrict__ flist,
-                                                     unsigned long long *__restrict__ keys) {
-    const size_t nq = (size_t)n_rays - 1, per = (size_t)S * nq;
+                                                     unsigned long long *__restrict__ keys,
+                                                     uint8_t *__restrict__ changed,
+                                                     uint8_t *__restrict__ marks, int mtx,
+                                                     int mtiles) {
+    const size_t nq = (size_t)n_rays - 1, nc = (size_t)(S + RCH - 1) / RCH, per = nc * nq;
     const size_t total = (size_t)flist[0] * per;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
         const int f = (int)(t / per);
         const size_t rest = t - (size_t)f * per;
-        const int i = (int)(rest / nq), j = (int)(rest - (size_t)i * nq);
-        raster_quad(sb, n_rays, S, flist[1 + f], i, j, nx, ny, n_mask, qmap, keys);
+        const int c = (int)(rest / nq), j = (int)(rest - (size_t)c * nq);
+        raster_run<MARK>(sb, n_rays, S, flist[1 + f], c, j, nx, ny, n_mask, qmap, keys, changed,
+                         marks, mtx, mtiles);
     }
 }
 
-__global__ void fill_keys(unsigned long long *keys, int n_mask, const int32_t *__restrict__ flist) {
-    const size_t total = (size_t)flist[0] * n_mask;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        const int f = (int)(t / n_mask);
-        keys[(size_t)flist[1 + f] * n_mask + (t - (size_t)f * n_mask)] = ~0ull;
-    }
-}
-
-// General path: per (folded transducer, mask node) interpolate the winning triangle.
+// General path: per (folded transducer, mask node) whose walk result the rasterisation
+// replaced, interpolate the winning triangle.
 __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, int S, int el,
                                              int q, int e0, const GridP &g, double ds, double c0,
                                              int n_mask, const int32_t *__restrict__ mask_index,
                                              const unsigned long long *__restrict__ keys,
+                                             const uint8_t *__restrict__ changed,
                                              const TableOut &to) {
     const size_t tid = (size_t)el * n_mask + q;
+    if (!changed[tid]) return;
     int e = e0 + el;
     size_t out = (size_t)e * n_mask + q;
     unsigned long long key = keys[tid];
@@ -733,12 +861,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     float la, lb, lc;
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
-    // vertices (ray, sample): (j, i), (j + 1, half ? i + 1 : i), (half ? j : j + 1, i + 1)
-    const int vj[3] = {j, j + 1, half ? j : j + 1}, vi[3] = {i, half ? i + 1 : i, i + 1};
-    int K = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        if (vi[k] >= sb.kfirst[(size_t)el * n_rays + vj[k]]) K = max(K, (int)sb.K[vb[k]]);
+    const int K = tri_K(sb, n_rays, el, j, i, half, vb);
     write_entry(sb, vb, lam, K, d, c0, to, out);
 }
 
@@ -747,13 +870,14 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
                                                       const int32_t *__restrict__ mask_index,
                                                       const int32_t *__restrict__ flist,
                                                       const unsigned long long *__restrict__ keys,
+                                                      const uint8_t *__restrict__ changed,
                                                       TableOut to) {
     const size_t total = (size_t)flist[0] * n_mask;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
         const int f = (int)(t / n_mask);
         resolve_node(sb, n_rays, S, flist[1 + f], (int)(t - (size_t)f * n_mask), e0, g, ds, c0,
-                     n_mask, mask_index, keys, to);
+                     n_mask, mask_index, keys, changed, to);
     }
 }
 
@@ -764,12 +888,16 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
 __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays, int e0, double R,
                                                        double psi0, int N, double c0,
                                                        rb_tables tb) {
-    extern __shared__ char smem[];
+    extern __shared__ __attribute__((aligned(16))) char smem[];  // 64-bit LDS atomics below
     double *beta = reinterpret_cast<double *>(smem);
     float *dTs = reinterpret_cast<float *>(beta + n_rays);
     float *Ls = dTs + n_rays;
     int *ok = reinterpret_cast<int *>(Ls + n_rays);
     uint8_t *Ks = reinterpret_cast<uint8_t *>(ok + n_rays);
+    // per receiver (index rel = (r - e) mod N): smallest travel time, then its lowest ray pair
+    unsigned long long *rkey =
+        reinterpret_cast<unsigned long long *>(smem + ((n_rays * 21 + 7) & ~7));
+    int *rwin = reinterpret_cast<int *>(rkey + N);
     __shared__ int not_monotone;
     int el = blockIdx.x, e = e0 + el;
     if (threadIdx.x == 0) not_monotone = 0;
@@ -787,6 +915,45 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
         if (!(ok[j] && ok[j + 1] && beta[j + 1] > beta[j])) not_monotone = 1;
     __syncthreads();
     const bool mono = !not_monotone;
+    // Without monotone exit angles every ray pair offers itself to the receivers whose angle
+    // it brackets (the scan's test and interpolation): the smallest travel time wins, then the
+    // lowest pair, as in a scan over the pairs in order.
+    auto dT_at = [&](int j, double br) {
+        double b0 = beta[j], b1 = beta[j + 1];
+        double lam = (br - b0) / (b1 - b0);
+        return (1.0 - lam) * (double)dTs[j] + lam * (double)dTs[j + 1];
+    };
+    auto pair_range = [&](int j, int &rl0, int &rl1) {  // receivers (rel) pair j may bracket
+        const double lo = fmin(beta[j], beta[j + 1]), hi = fmax(beta[j], beta[j + 1]);
+        rl0 = max(1, (int)floor(lo * (double)N / RB_TWO_PI) - 1);
+        rl1 = min(N - 1, (int)ceil(hi * (double)N / RB_TWO_PI) + 1);
+    };
+    auto brackets = [&](int j, double br) {
+        double b0 = beta[j], b1 = beta[j + 1];
+        return ok[j] && ok[j + 1] && !(b0 == b1 || br < fmin(b0, b1) || br > fmax(b0, b1));
+    };
+    if (!mono) {
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            rkey[k] = ~0ull;
+            rwin[k] = INT_MAX;
+        }
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j = threadIdx.x; j + 1 < n_rays; j += blockDim.x) {
+                if (!(ok[j] && ok[j + 1])) continue;
+                int rl0, rl1;
+                pair_range(j, rl0, rl1);
+                for (int rel = rl0; rel <= rl1; ++rel) {
+                    const double br = RB_TWO_PI * (double)rel / (double)N;
+                    if (!brackets(j, br)) continue;
+                    const unsigned long long k = ordered_bits64(dT_at(j, br));
+                    if (pass == 0) atomicMin(rkey + rel, k);
+                    else if (k == rkey[rel]) atomicMin(rwin + rel, j);
+                }
+            }
+            __syncthreads();
+        }
+    }
     const double2 xy = sb.ring[e];
     double xe = xy.x, ye = xy.y;
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
@@ -821,13 +988,8 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
                     if (lo > 0 && beta[lo] == br) take(lo - 1);
                     take(lo);
                 }
-            } else {
-                for (int j = 0; j + 1 < n_rays; ++j) {
-                    if (!(ok[j] && ok[j + 1])) continue;
-                    double b0 = beta[j], b1 = beta[j + 1];
-                    if (b0 == b1 || br < fmin(b0, b1) || br > fmax(b0, b1)) continue;
-                    take(j);
-                }
+            } else if (rwin[rel] != INT_MAX) {
+                take(rwin[rel]);
             }
         }
         if (found) {
@@ -917,6 +1079,12 @@ static int trace_chunk(const rb_ctx *ctx, const rb_ring *r, const rb_trace_param
     return (int)c;
 }
 
+static size_t mtiles_of(const rb_grid *g) {
+    const size_t mtx = (g->nx + (1 << MT_SHIFT) - 1) >> MT_SHIFT;
+    const size_t mty = (g->ny + (1 << MT_SHIFT) - 1) >> MT_SHIFT;
+    return mtx * mty;
+}
+
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
                           float4 *rec, double2 *ring_out) {
@@ -933,6 +1101,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                    rb_align((size_t)N * sizeof(double2)) +
                    rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
                    rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
+                   rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
                    rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float));
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
@@ -955,6 +1124,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
+    uint8_t *changed = rb_carve<uint8_t>(&ctx->ws, (size_t)C * n_mask);
+    const int mtx = (g->nx + (1 << MT_SHIFT) - 1) >> MT_SHIFT;
+    const int mtiles = (int)mtiles_of(g);
+    uint8_t *marks = rb_carve<uint8_t>(&ctx->ws, (size_t)C * mtiles + 4);  // whole words zeroed
     const int nxp = g->nx + 2 * MPAD, nyp = g->ny + 2 * MPAD;
     float *padded = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
     SplineMap smap{padded, g->nx, g->ny, nxp, (float)(1.0 / g->dx)};
@@ -976,6 +1149,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         hipLaunchKernelGGL(zero_i32, dim3((E + 255) / 256), dim3(256), 0, ctx->stream, sb.folded,
                            E);
         RB_CHECK_LAUNCH(ctx);
+        const int mwords = (int)(((size_t)E * mtiles + 3) / 4);
+        hipLaunchKernelGGL(zero_i32, dim3((mwords + 255) / 256), dim3(256), 0, ctx->stream,
+                           reinterpret_cast<int32_t *>(marks), mwords);
+        RB_CHECK_LAUNCH(ctx);
         rb_prof_begin(ctx, ST_TRACE);
         const int waves = E * ((nr + 63) / 64);
         hipLaunchKernelGGL(trace_kernel, dim3((waves + 3) / 4), dim3(256), 0, ctx->stream,
@@ -983,7 +1160,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            e0, E, sb, ctx->d_flag, nsamp);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
-        // unfolded fans: direct walk per (transducer, node)
+        // every fan: walk per (transducer, node); for folded fans also the seed keys
         rb_prof_begin(ctx, ST_RESOLVE);
         int ntiles = ctx->tiles_x * ctx->tiles_y;
         hipLaunchKernelGGL(tile_offset_kernel, dim3((E * ntiles + 255) / 256), dim3(256), 0,
@@ -997,25 +1174,36 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
-                           toff, to, lost);
+                           toff, to, keys, changed, marks, mtx, mtiles, lost);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
-        // folded fans: smallest-key rasterisation and resolve
+        // folded fans: smallest-key rasterisation against the walk's keys, and resolve of
+        // the nodes it changed
         rb_prof_begin(ctx, ST_RASTER);
         hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(fill_keys, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, keys, n_mask,
-                           flist);
+        hipLaunchKernelGGL(raster_kernel<true>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
+                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
+                           mtx, mtiles);
         RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(raster_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
-                           g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys);
+        hipLaunchKernelGGL(raster_kernel<false>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
+                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
+                           mtx, mtiles);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(resolve_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
-                           e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys, to);
+                           e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys,
+                           changed, to);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         rb_prof_begin(ctx, ST_RECEIVERS);
-        size_t smem = (size_t)nr * (sizeof(double) + 2 * sizeof(float) + sizeof(int) + 1);
+        size_t smem = (((size_t)nr * 21 + 7) & ~(size_t)7) + (size_t)N * 12;
+        if (smem > (size_t)160 * 1024)
+            return rb_fail(ctx, RB_EINVAL, "n_rays=%d with n=%d needs %zu bytes of LDS for the "
+                           "receiver tables (at most 160 KiB)", nr, N, smem);
+        if (smem > (size_t)64 * 1024)
+            RB_HIP(ctx, hipFuncSetAttribute((const void *)receiver_kernel,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)smem));
         hipLaunchKernelGGL(receiver_kernel, dim3(E), dim3(256), smem, ctx->stream, sb, nr, e0,
                            r->radius, r->psi0, N, tp->c0, *out);
         RB_CHECK_LAUNCH(ctx);
