@@ -649,7 +649,10 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double ddx = px - xy.x, ddy = py - xy.y;
     double d = sqrt_newton(ddx * ddx + ddy * ddy);
-    if (d < 2.0 * ds) {
+    const size_t mq = (size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT);
+    // a node near a fold (marked tile) is left to the rasterisation, which offers it every
+    // triangle that touches its tile
+    if (d < 2.0 * ds || (fold && marks[mq])) {
         write_invalid(to, out);
         if (fold) {
             keys[kq] = ~0ull;
@@ -679,7 +682,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
         if (fold) {  // left to the rasterisation
             keys[kq] = ~0ull;
             changed[kq] = 0;
-            marks[(size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT)] = 1;
+            marks[mq] = 1;
         } else {
             atomicAdd(lost, 1);
         }
@@ -1160,6 +1163,15 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            e0, E, sb, ctx->d_flag, nsamp);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
+        // folded fans: tiles near inverted triangles
+        rb_prof_begin(ctx, ST_RASTER);
+        hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
+        RB_CHECK_LAUNCH(ctx);
+        hipLaunchKernelGGL(raster_kernel<true>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
+                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
+                           mtx, mtiles);
+        RB_CHECK_LAUNCH(ctx);
+        rb_prof_end(ctx);
         // every fan: walk per (transducer, node); for folded fans also the seed keys
         rb_prof_begin(ctx, ST_RESOLVE);
         int ntiles = ctx->tiles_x * ctx->tiles_y;
@@ -1180,12 +1192,6 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         // folded fans: smallest-key rasterisation against the walk's keys, and resolve of
         // the nodes it changed
         rb_prof_begin(ctx, ST_RASTER);
-        hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
-        RB_CHECK_LAUNCH(ctx);
-        hipLaunchKernelGGL(raster_kernel<true>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
-                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
-                           mtx, mtiles);
-        RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(raster_kernel<false>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
                            nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
                            mtx, mtiles);
