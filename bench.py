@@ -287,6 +287,108 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
     return out
 
 
+def run_serve(args):
+    """Serving mix: requests of three scan classes (ring 256 / 512 / 1024 on 256^2 / 512^2 /
+    1024^2 grids), 8-32 frequency steps each, admitted by HBM budget and stepped with
+    continuous batching (paper_2211_00316_amd.serve). A closed-loop run (every request
+    waiting at time 0) measures the capacity; the reported run has Poisson arrivals at
+    rate_frac of it. Some requests are then run alone and compared with their result in the
+    mix."""
+    import numpy as np
+    import torch
+
+    import phantoms as ph
+    from paper_2211_00316_amd import _lib, serve, setup_for
+
+    prec = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
+    classes = ph.SERVE_CLASSES
+    draws0 = ph.serve_draws(args.requests, seed=5, rate=None)
+    ctx = _lib.Context("cuda:0")
+    store = {}
+    for k, sd in sorted({(d.cls, d.phantom_seed) for d in draws0}):
+        w = classes[k]
+        grid, ring, tp = setup_for(w)
+        print(f"[serve] data of {w.name} phantom {sd}", file=sys.stderr, flush=True)
+        store[(k, sd)] = synthesize_data(ctx, w, grid, ring, tp, ph.phantom_for(w, seed=sd),
+                                         list(range(len(w.freqs))))
+    ctx.close()
+
+    def make(draws):
+        reqs = []
+        for d in draws:
+            w = classes[d.cls]
+            grid, ring, tp = setup_for(w)
+            idx = ph.step_frequencies(d.n_steps, len(w.freqs))
+            om = [2 * math.pi * w.freqs[i] for i in idx]
+            dom = [2 * math.pi * (w.freqs[-1] - w.freqs[0]) / max(1, d.n_steps - 1)] * d.n_steps
+            data = store[(d.cls, d.phantom_seed)][torch.as_tensor(idx, device="cuda:0")]
+            c0 = torch.full((w.ny, w.nx), ph.C_WATER, dtype=torch.float64, device="cuda:0")
+            reqs.append(serve.Request(d.rid, d.arrival, grid, ring, tp, om, dom,
+                                      [w.smooth_window(i) for i in idx], data.contiguous(), c0,
+                                      w.tau, tag=w.name))
+        return reqs
+
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    budget = int(0.9 * torch.cuda.mem_get_info()[0])
+    ex = serve.GpuExecutor(prec)
+    # warm-up: one step of one request per class (module loads, first allocations)
+    warm = []
+    for k in range(len(classes)):
+        first = next((d for d in draws0 if d.cls == k), None)
+        if first is not None:
+            warm.append(ph.ServeDraw(1000 + k, k, first.phantom_seed, 1, 0.0))
+    serve.Server(ex, budget).run(make(warm))
+    print("[serve] warm-up done", file=sys.stderr, flush=True)
+
+    closed = serve.Server(ex, budget).run(make(draws0))
+    cap = len(draws0) / closed.makespan
+    rate = args.rate_frac * cap
+    print(f"[serve] closed loop: {closed.summary()}", file=sys.stderr, flush=True)
+    draws = ph.serve_draws(args.requests, seed=5, rate=rate)
+    mix = serve.Server(ex, budget).run(make(draws))
+    print(f"[serve] open loop at {rate:.3f} requests/s: {mix.summary()}", file=sys.stderr,
+          flush=True)
+    # alone vs in the mix: the first request of each class
+    by_id = {r.rid: r for r in mix.requests}
+    picks = [next(d for d in draws if d.cls == k) for k in range(len(classes))
+             if any(d.cls == k for d in draws)]
+    diffs = {}
+    for d in picks:
+        alone = serve.Server(ex, budget).run(make([ph.ServeDraw(d.rid, d.cls, d.phantom_seed,
+                                                                d.n_steps, 0.0)]))
+        a, m = alone.requests[0], by_id[d.rid]
+        diffs[d.rid] = float((a.c - m.c).abs().max().item())
+        print(f"[serve] request {d.rid} ({classes[d.cls].name}, {d.n_steps} steps): "
+              f"max |c_alone - c_mix| = {diffs[d.rid]:.3e}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "serving frequency-step updates/s (mixed scans, continuous batching)",
+        "value": round(mix.steps_per_s, 3),
+        "unit": "frequency-step updates/s",
+        "n_gpus": 1,
+        "steps": mix.steps,
+        "warmup": len(warm),
+        "ms_per_step": round(1000.0 / mix.steps_per_s, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "p50_latency_s": round(mix.latency_pct(50), 4),
+        "p99_latency_s": round(mix.latency_pct(99), 4),
+        "config": {"workload": f"serve_mix{len(draws)}",
+                   "classes": [c.name for c in classes],
+                   "requests": len(draws), "steps_per_request": "8-32",
+                   "arrivals": "poisson", "rate_per_s": round(rate, 4),
+                   "rate_frac_of_capacity": args.rate_frac,
+                   "budget_bytes": budget},
+        "open_loop": mix.summary(),
+        "closed_loop": closed.summary(),
+        "alone_vs_mix_max_abs_diff": diffs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,12 +407,22 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
                          "(reference for the HBM byte counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mix of scans of three sizes with continuous batching "
+                         "(prints its own JSON line)")
+    ap.add_argument("--requests", type=int, default=64, help="requests of the serving mix")
+    ap.add_argument("--rate-frac", type=float, default=0.8,
+                    help="arrival rate of the serving mix, as a fraction of its capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the frequency step on a single "
               "MI355X (see the sharding design); --gpus above 1 is not supported.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        run_serve(args)
+        return
 
     import numpy as np
     import torch

@@ -226,6 +226,51 @@ rb_status rb_frequency_sweep(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ri
                              double tau, rb_mode mode, rb_prec prec, int32_t use_graph,
                              double *residual_norms);
 
+/* One scan's step inside a batch: the arguments of rb_frequency_step for that scan. */
+typedef struct {
+    rb_ctx *ctx;                 /* the scan's context (its stream, workspace and mask) */
+    const rb_grid *grid;         /* HOST structs, as in rb_frequency_step */
+    const rb_ring *ring;
+    const rb_trace_params *tp;
+    double *c;                   /* device [ny][nx] model, updated in place */
+    int32_t smooth_w;
+    int32_t n_omega;
+    const double *omega;         /* HOST [n_omega] */
+    const double *d_omega;       /* HOST [n_omega] */
+    const float *data;           /* device complex64 [n_omega][n][n] */
+    double tau;
+    rb_mode mode;
+    double *residual_norm;       /* device double or NULL */
+} rb_scan_step;
+
+/* The frequency steps of `count` scans (1 <= count <= 16) at once: each scan's step is the
+ * one rb_frequency_step computes for it (the same kernels on the same values, so results are
+ * identical to the scan stepped alone). This is the serving form of the continuation
+ * (Section 6.3.2) over several reconstructions: the per-scan stages (map, rays, binning,
+ * Green's functions) of different scans run on their contexts' streams and overlap on the
+ * device; for each frequency index k, the Born forward terms (Eq. perturb1) of all scans
+ * with a k-th frequency run as one grouped launch, and so do their back-projections (Eq.
+ * sound_speed_update2), on the stream of steps[0].ctx, ordered against the scans' streams by
+ * events. Scans may differ in n, grid and frequency count. The contexts must be distinct and
+ * on one device; prec applies to every scan. Returns after the last kernel of every scan
+ * (the host waits). status (HOST rb_status[count], may be NULL) receives each scan's result:
+ * a scan whose step fails (ray beyond max_steps, non-finite update) keeps its model and gets
+ * RB_ENONFINITE (its context's rb_last_error says why) while the other scans commit; the
+ * return value is the first non-OK status. Arguments are validated before any launch. */
+rb_status rb_frequency_step_batch(const rb_scan_step *steps, int32_t count, rb_prec prec,
+                                  rb_status *status);
+
+/* Peak device bytes a context holds for frequency steps of this geometry and precision
+ * (workspaces, tables, operands, mask lists), for a tracer sample budget of sample_budget
+ * bytes (rb_set_sample_budget). For admission by memory; 0 if the geometry is invalid. */
+size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
+                     rb_prec prec, size_t sample_budget);
+
+/* Bytes of ray samples one tracer launch of this context may hold (default: a quarter of the
+ * device memory free at rb_create, at most 48 GiB). Emitters are traced in chunks that fit;
+ * a smaller budget means more launches. RB_EINVAL below 1 MiB. */
+rb_status rb_set_sample_budget(rb_ctx *ctx, size_t bytes);
+
 /* Measurement: per-stage GPU time from HIP events recorded around every kernel launch on
  * the context's stream while profiling is on (small overhead; off by default). Stages are
  * numbered 0 .. RB_N_STAGES-1 (rb_stage_name). rb_profile_read synchronizes the stream,

@@ -24,7 +24,9 @@ SYMBOLS = (
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
+    "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget",
 )
+GROUP_MAX = 16  # scans per rb_frequency_step_batch call
 N_STAGES = 12
 
 
@@ -53,6 +55,16 @@ class _Tables(ctypes.Structure):
 class _Green(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32), ("prec", ctypes.c_int),
                 ("G", ctypes.c_void_p), ("H", ctypes.c_void_p)]
+
+
+class _ScanStep(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("grid", ctypes.POINTER(Grid)),
+                ("ring", ctypes.POINTER(Ring)), ("tp", ctypes.POINTER(TraceParams)),
+                ("c", ctypes.c_void_p), ("smooth_w", ctypes.c_int32),
+                ("n_omega", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("d_omega", ctypes.POINTER(ctypes.c_double)), ("data", ctypes.c_void_p),
+                ("tau", ctypes.c_double), ("mode", ctypes.c_int),
+                ("residual_norm", ctypes.c_void_p)]
 
 
 class RayBornError(RuntimeError):
@@ -100,6 +112,12 @@ def load(path: str = LIB_PATH):
         "rb_stage_name": ([I32], ctypes.c_char_p),
         "rb_trace_lost_nodes": ([P], ctypes.c_int64),
         "rb_trace_samples": ([P], ctypes.c_int64),
+        "rb_frequency_step_batch": ([ctypes.POINTER(_ScanStep), I32, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rb_step_bytes": ([ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                           ctypes.POINTER(TraceParams), ctypes.c_int, ctypes.c_size_t],
+                          ctypes.c_size_t),
+        "rb_set_sample_budget": ([P, ctypes.c_size_t], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -111,6 +129,63 @@ def load(path: str = LIB_PATH):
 
 def mask_count(grid: Grid) -> int:
     return int(load().rb_mask_count(ctypes.byref(grid)))
+
+
+def step_bytes(grid: Grid, ring: Ring, tp: TraceParams, prec: int, sample_budget: int) -> int:
+    """Peak device bytes of a context stepping this geometry (rb_step_bytes)."""
+    return int(load().rb_step_bytes(ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp),
+                                    int(prec), int(sample_budget)))
+
+
+@dataclasses.dataclass
+class ScanStep:
+    """Arguments of one scan's step in a batch (rb_scan_step)."""
+
+    ctx: "Context"
+    grid: Grid
+    ring: Ring
+    tp: TraceParams
+    c: torch.Tensor
+    smooth_w: int
+    omegas: list
+    d_omegas: list
+    data: torch.Tensor
+    tau: float
+    mode: int = RB_RAY_BORN
+    residual_norm: torch.Tensor | None = None
+
+
+def frequency_step_batch(steps, prec: int = RB_BF16):
+    """One frequency step of each scan (rb_frequency_step_batch); returns each scan's status
+    (RB_OK, or RB_ENONFINITE for a scan whose step was rejected and left its model as it
+    was). Raises if the batch could not be launched."""
+    lib = load()
+    n = len(steps)
+    if not 1 <= n <= GROUP_MAX:
+        raise ValueError(f"a batch holds 1..{GROUP_MAX} scans, got {n}")
+    arr = (_ScanStep * n)()
+    keep = []
+    for i, s in enumerate(steps):
+        _dev(s.c, torch.float64)
+        _dev(s.data, torch.complex64)
+        if s.residual_norm is not None:
+            _dev(s.residual_norm, torch.float64)
+        if len(s.omegas) != len(s.d_omegas) or s.data.shape[0] < len(s.omegas):
+            raise ValueError(f"scan {i}: one spacing and one data slice per frequency")
+        om = (ctypes.c_double * len(s.omegas))(*[float(o) for o in s.omegas])
+        dom = (ctypes.c_double * len(s.d_omegas))(*[float(o) for o in s.d_omegas])
+        keep += [om, dom]
+        arr[i] = _ScanStep(s.ctx._h, ctypes.pointer(s.grid), ctypes.pointer(s.ring),
+                           ctypes.pointer(s.tp), s.c.data_ptr(), int(s.smooth_w),
+                           len(s.omegas), om, dom, s.data.data_ptr(), float(s.tau), int(s.mode),
+                           s.residual_norm.data_ptr() if s.residual_norm is not None else None)
+    status = (ctypes.c_int * n)()
+    st = lib.rb_frequency_step_batch(arr, n, int(prec), status)
+    out = [int(v) for v in status]
+    if st != RB_OK and all(v == RB_OK for v in out):
+        bad = next((s.ctx for s in steps if lib.rb_last_error(s.ctx._h)), steps[0].ctx)
+        raise RayBornError(st, lib.rb_last_error(bad._h).decode())
+    return out
 
 
 def _ptr(t):
@@ -209,15 +284,15 @@ class Green:
 
 
 class Context:
-    """One rb_ctx bound to a torch device and its current stream."""
+    """One rb_ctx bound to a torch device and a stream (default: the current one)."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, stream: torch.cuda.Stream | None = None):
         if not torch.cuda.is_available():
             raise RuntimeError("raybornhf needs a GPU (torch.cuda.is_available() is False)")
         self.lib = load()
         self.device = torch.device(device if device is not None else "cuda:0")
         idx = self.device.index or 0
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         st = self.lib.rb_create(ctypes.byref(h), idx, ctypes.c_void_p(self.stream.cuda_stream))
         if st != RB_OK:
@@ -238,6 +313,10 @@ class Context:
     def _check(self, st):
         if st != RB_OK:
             raise RayBornError(st, self.lib.rb_last_error(self._h).decode())
+
+    def set_sample_budget(self, nbytes: int):
+        """Bytes of ray samples one tracer launch may hold (rb_set_sample_budget)."""
+        self._check(self.lib.rb_set_sample_budget(self._h, int(nbytes)))
 
     def lost_nodes(self) -> int:
         """Mask nodes the last binning could not place (diagnostic; 0 normally)."""

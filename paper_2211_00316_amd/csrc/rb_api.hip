@@ -257,6 +257,7 @@ void rb_destroy(rb_ctx *ctx) {
     if (ctx->d_red) (void)hipFree(ctx->d_red);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     for (int i = 0; i < ctx->n_ev_created; ++i) {
         (void)hipEventDestroy(ctx->ev[i][0]);
@@ -426,16 +427,25 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
 
 // One frequency step (rows a1-a9) enqueued on ctx->stream. With ctx->deferred nothing
 // synchronises with the host: errors stay in d_flag and the commit kernel checks them.
-static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
-                              const rb_trace_params *tp, double *c, int32_t smooth_w,
-                              int32_t n_omega, const double *omega, const double *d_omega,
-                              const float *data, double tau, rb_mode mode, rb_prec prec,
-                              double *residual_norm, int step_index) {
-    RB_TRY(rb_prepare_grid(ctx, grid));
+// Device buffers of one frequency step, carved from the context's step arena.
+struct StepBufs {
+    int N = 0, nm = 0, mb = 0;
+    bool lp = false;
+    size_t NN = 0;
+    float *n_s = nullptr;
+    rb_tables tb{};
+    float4 *rec = nullptr;
+    double2 *ringpos = nullptr;
+    rb_green gr{};
+    float *d_born = nullptr, *R = nullptr, *rsym = nullptr;
+    uint16_t *Rp = nullptr;
+    float *rscale = nullptr, *wv = nullptr, *svscale = nullptr;
+    double *cq = nullptr, *dm = nullptr, *c_new = nullptr;
+    float *parts = nullptr;
+};
 
-    const int N = ring->n;
-    const int nm = (int)ctx->n_mask;
-    const size_t P = (size_t)grid->nx * grid->ny;
+// Bytes of the step arena for N transducers, nm mask nodes and P grid nodes.
+static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
     const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
     const size_t NPp = (size_t)rb_lp_pad(N) * nm;  // padded operand rows (16-bit form)
     const size_t NNp = (size_t)rb_lp_pad(N) * N;
@@ -446,26 +456,43 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     // node tables: ABI layout for the FP32 form, compact records (+ ring) for 16-bit
     const size_t tab_bytes = lp ? rb_align(NP * 16) + rb_align((size_t)N * 16)
                                 : rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP);
-    size_t bytes = rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) + rb_align(NG * opb) +
-                   rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) + rb_align(NNp * 4) +
-                   rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
-                   3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
-                   rb_align(8);
+    return rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) +
+           rb_align(NG * opb) + rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) +
+           rb_align(NNp * 4) + rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
+           3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
+           rb_align(8);
+}
+
+static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_prec prec,
+                            StepBufs *b) {
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    const int N = ring->n;
+    const int nm = (int)ctx->n_mask;
+    const size_t P = (size_t)grid->nx * grid->ny;
+    const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
+    const size_t NPp = (size_t)rb_lp_pad(N) * nm;
+    const size_t NNp = (size_t)rb_lp_pad(N) * N;
+    const bool lp = prec != RB_F32;
+    const size_t NG = lp ? (size_t)N * rb_lp_pad(nm) : NP;
+    const size_t opb = lp ? 4 : 8;
     ctx->step.used = 0;
-    RB_TRY(rb_arena_reserve(ctx, &ctx->step, bytes));
+    RB_TRY(rb_arena_reserve(ctx, &ctx->step, step_arena_bytes(N, nm, P, prec)));
     rb_arena *a = &ctx->step;
-    float *n_s = rb_carve<float>(a, P);
-    rb_tables tb;
+    b->N = N;
+    b->nm = nm;
+    b->NN = NN;
+    b->lp = lp;
+    b->mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
+    b->n_s = rb_carve<float>(a, P);
+    rb_tables &tb = b->tb;
     tb.n = N;
     tb.n_mask = nm;
-    float4 *rec = nullptr;
-    double2 *ringpos = nullptr;
     if (lp) {
         tb.T = nullptr;
         tb.A = tb.ux = tb.uy = nullptr;
         tb.flags = nullptr;
-        rec = rb_carve<float4>(a, NP);
-        ringpos = rb_carve<double2>(a, N);
+        b->rec = rb_carve<float4>(a, NP);
+        b->ringpos = rb_carve<double2>(a, N);
     } else {
         tb.T = rb_carve<double>(a, NP);
         tb.A = rb_carve<float>(a, NP);
@@ -476,83 +503,123 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
     tb.rx_T = rb_carve<double>(a, NN);
     tb.rx_A = rb_carve<float>(a, NN);
     tb.rx_flags = rb_carve<uint8_t>(a, NN);
-    rb_green gr;
+    rb_green &gr = b->gr;
     gr.n = N;
     gr.n_mask = nm;
     gr.prec = prec;
     gr.G = rb_carve<char>(a, NG * opb);
     gr.H = rb_carve<char>(a, 3 * (lp ? NPp : NP) * opb);
-    float *d_born = rb_carve<float>(a, 2 * NN);
-    float *R = rb_carve<float>(a, 2 * NN);
-    float *rsym = rb_carve<float>(a, 2 * NN);
-    uint16_t *Rp = rb_carve<uint16_t>(a, 2 * NNp);
-    float *rscale = rb_carve<float>(a, 2);
-    float *wv = rb_carve<float>(a, 2 * (size_t)nm);
-    float *svscale = rb_carve<float>(a, 2);
-    double *cq = rb_carve<double>(a, nm);
-    double *dm = rb_carve<double>(a, nm);
-    double *c_new = rb_carve<double>(a, nm);
-    float *parts = rb_carve<float>(a, (size_t)2 * mb * nm);
+    b->d_born = rb_carve<float>(a, 2 * NN);
+    b->R = rb_carve<float>(a, 2 * NN);
+    b->rsym = rb_carve<float>(a, 2 * NN);
+    b->Rp = rb_carve<uint16_t>(a, 2 * NNp);
+    b->rscale = rb_carve<float>(a, 2);
+    b->wv = rb_carve<float>(a, 2 * (size_t)nm);
+    b->svscale = rb_carve<float>(a, 2);
+    b->cq = rb_carve<double>(a, nm);
+    b->dm = rb_carve<double>(a, nm);
+    b->c_new = rb_carve<double>(a, nm);
+    b->parts = rb_carve<float>(a, (size_t)2 * b->mb * nm);
+    return RB_OK;
+}
 
-    // a1: tracing map; a2-a3: rays and tables (independent of omega when lossless)
-    RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, n_s));
-    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, n_s, &tb, rec, ringpos));
-    RB_TRY(rb_launch_gather_mask(ctx, c, cq));
-    RB_TRY(rb_launch_zero_f64(ctx, dm, nm));
+// a1: tracing map; a2-a3: rays and tables (independent of omega when lossless).
+static rb_status step_begin(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            double *residual_norm, StepBufs &b) {
+    RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, b.n_s));
+    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos));
+    RB_TRY(rb_launch_gather_mask(ctx, c, b.cq));
+    RB_TRY(rb_launch_zero_f64(ctx, b.dm, b.nm));
     if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
-    for (int k = 0; k < n_omega; ++k) {
-        const double om = omega[k];
-        // a4: Green's functions and back-projection operands. In ray_born mode G is
-        // stored as G sqrt(v), v = omega^2 h^2 (m - m_s), so that a5 is the plain
-        // symmetric product; ray_only needs no G.
-        const bool born_term = mode == RB_RAY_BORN;
-        if (born_term) {
-            RB_TRY(rb_launch_rough_part(ctx, cq, n_s, tp->c0, om * om * grid->dx * grid->dx, wv));
-            // power-of-two scale that brings max |sqrt(v)| to [1, 2) (range of 16-bit types)
-            RB_TRY(rb_launch_range_scale(ctx, wv, (size_t)nm, 1, svscale));
-        }
-        const float *gs = born_term ? wv : nullptr;
-        if (lp)
-            RB_TRY(rb_launch_green_lp_rec(ctx, rec, ringpos, N, om, tp->c0, &gr, gs, svscale,
-                                          born_term));
-        else
-            RB_TRY(rb_launch_green(ctx, &tb, om, tp->c0, &gr, gs, svscale, born_term));
-        // a5-a6: predicted data (ray part + Born term of the rough part) and residual
-        const float *born = nullptr;
-        if (born_term) {
-            if (lp)
-                RB_TRY(rb_launch_forward_lp(ctx, &gr, nullptr, nullptr, d_born, svscale));
-            else
-                RB_TRY(rb_launch_forward(ctx, &gr, nullptr, nullptr, d_born, svscale));
-            born = d_born;
-        }
-        RB_TRY(rb_launch_residual(ctx, &tb, om, tp->c0, born, data + 2 * NN * (size_t)k, R,
-                                  residual_norm));
-        // a8: Hessian-free back-projection, accumulated over the set in FP64
-        int mbo = mb;
-        if (lp) {
-            RB_TRY(rb_launch_to_planar(ctx, prec, R, N, Rp, rscale));
-            RB_TRY(rb_launch_rowred_lp(ctx, prec, N, nm, Rp, gr.H, 3, parts, &mbo));
-            RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mbo * nm, rscale));
-        } else {
-            RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gr.H, 3, 0, rsym, parts, &mbo));
-        }
-        RB_TRY(rb_launch_backproject_finish_acc(ctx, mbo, parts, cq, om, d_omega[k], dm));
+    return RB_OK;
+}
+
+// a4: Green's functions and back-projection operands. In ray_born mode G is stored as
+// G sqrt(v), v = omega^2 h^2 (m - m_s), so that a5 is the plain symmetric product; ray_only
+// needs no G.
+static rb_status step_green(rb_ctx *ctx, const rb_grid *grid, const rb_trace_params *tp,
+                            double om, rb_mode mode, StepBufs &b) {
+    const bool born_term = mode == RB_RAY_BORN;
+    if (born_term) {
+        RB_TRY(rb_launch_rough_part(ctx, b.cq, b.n_s, tp->c0, om * om * grid->dx * grid->dx,
+                                    b.wv));
+        // power-of-two scale that brings max |sqrt(v)| to [1, 2) (range of 16-bit types)
+        RB_TRY(rb_launch_range_scale(ctx, b.wv, (size_t)b.nm, 1, b.svscale));
     }
-    // a9: model update, committed only if every value is finite
+    const float *gs = born_term ? b.wv : nullptr;
+    if (b.lp)
+        return rb_launch_green_lp_rec(ctx, b.rec, b.ringpos, b.N, om, tp->c0, &b.gr, gs,
+                                      b.svscale, born_term);
+    return rb_launch_green(ctx, &b.tb, om, tp->c0, &b.gr, gs, b.svscale, born_term);
+}
+
+// a6: residual of the predicted data (ray part + Born term in b.d_born if `born`), and the
+// 16-bit back-projection operand.
+static rb_status step_residual(rb_ctx *ctx, const rb_trace_params *tp, double om, bool born,
+                               const float *data_k, double *residual_norm, rb_prec prec,
+                               StepBufs &b) {
+    RB_TRY(rb_launch_residual(ctx, &b.tb, om, tp->c0, born ? b.d_born : nullptr, data_k, b.R,
+                              residual_norm));
+    if (b.lp) RB_TRY(rb_launch_to_planar(ctx, prec, b.R, b.N, b.Rp, b.rscale));
+    return RB_OK;
+}
+
+// a8 tail: undo the operand scale and accumulate the direction over the set in FP64.
+static rb_status step_accumulate(rb_ctx *ctx, double om, double d_om, StepBufs &b) {
+    if (b.lp) RB_TRY(rb_launch_unscale(ctx, b.parts, (size_t)2 * b.mb * b.nm, b.rscale));
+    return rb_launch_backproject_finish_acc(ctx, b.mb, b.parts, b.cq, om, d_om, b.dm);
+}
+
+// a9: model update, committed only if every value is finite.
+static rb_status step_end(rb_ctx *ctx, double *c, double tau, int step_index, StepBufs &b) {
     if (ctx->deferred) {
-        RB_TRY(rb_launch_update(ctx, cq, dm, tau, c_new));
+        RB_TRY(rb_launch_update(ctx, b.cq, b.dm, tau, b.c_new));
         RB_TRY(rb_launch_note_fail(ctx, step_index));
-        return rb_launch_commit(ctx, c_new, c, ctx->d_flag);
+        return rb_launch_commit(ctx, b.c_new, c, ctx->d_flag);
     }
     RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, 1, 0));
-    RB_TRY(rb_launch_update(ctx, cq, dm, tau, c_new));
+    RB_TRY(rb_launch_update(ctx, b.cq, b.dm, tau, b.c_new));
     RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost,
                                ctx->stream));
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (*ctx->h_flag & 2)
         return rb_fail(ctx, RB_ENONFINITE, "non-finite model update rejected; c unchanged");
-    return rb_launch_commit(ctx, c_new, c, nullptr);
+    return rb_launch_commit(ctx, b.c_new, c, nullptr);
+}
+
+static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                              const rb_trace_params *tp, double *c, int32_t smooth_w,
+                              int32_t n_omega, const double *omega, const double *d_omega,
+                              const float *data, double tau, rb_mode mode, rb_prec prec,
+                              double *residual_norm, int step_index) {
+    StepBufs b;
+    RB_TRY(step_carve(ctx, grid, ring, prec, &b));
+    RB_TRY(step_begin(ctx, grid, ring, tp, c, smooth_w, residual_norm, b));
+    for (int k = 0; k < n_omega; ++k) {
+        const double om = omega[k];
+        const bool born = mode == RB_RAY_BORN;
+        RB_TRY(step_green(ctx, grid, tp, om, mode, b));
+        // a5: Born term of the rough part in the predicted data
+        if (born) {
+            if (b.lp)
+                RB_TRY(rb_launch_forward_lp(ctx, &b.gr, nullptr, nullptr, b.d_born, b.svscale));
+            else
+                RB_TRY(rb_launch_forward(ctx, &b.gr, nullptr, nullptr, b.d_born, b.svscale));
+        }
+        RB_TRY(step_residual(ctx, tp, om, born, data + 2 * b.NN * (size_t)k, residual_norm, prec,
+                             b));
+        // a8: Hessian-free back-projection
+        if (b.lp) {
+            RB_TRY(rb_launch_rowred_lp(ctx, prec, b.N, b.nm, b.Rp, b.gr.H, 3, b.parts, nullptr));
+        } else {
+            int mbo = b.mb;
+            RB_TRY(rb_launch_rowred(ctx, b.N, b.nm, b.R, (const float *)b.gr.H, 3, 0, b.rsym,
+                                    b.parts, &mbo));
+        }
+        RB_TRY(step_accumulate(ctx, om, d_omega[k], b));
+    }
+    return step_end(ctx, c, tau, step_index, b);
 }
 
 
@@ -568,6 +635,208 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     ctx->deferred = false;
     return step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
                         mode, prec, residual_norm, 0);
+}
+
+size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
+                     rb_prec prec, size_t sample_budget) {
+    if (!grid || !ring || !tp || grid->nx < 1 || grid->ny < 1 || ring->n < 1 || tp->n_rays < 1 ||
+        tp->max_steps < 1)
+        return 0;
+    std::vector<int32_t> idx;
+    const int64_t nm = mask_list(grid, &idx, nullptr);
+    if (nm < 1) return 0;
+    int imin = grid->nx, imax = -1, jmin = grid->ny, jmax = -1;
+    for (int32_t p : idx) {
+        const int i = p % grid->nx, j = p / grid->nx;
+        imin = std::min(imin, i);
+        imax = std::max(imax, i);
+        jmin = std::min(jmin, j);
+        jmax = std::max(jmax, j);
+    }
+    const size_t tiles = (size_t)((imax - imin + 32) / 32) * ((jmax - jmin + 8) / 8);
+    const size_t P = (size_t)grid->nx * grid->ny;
+    const int N = ring->n;
+    int n_cu = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetLastError();
+    size_t ws = rb_align(P * sizeof(double));  // smoothing
+    ws = std::max(ws, rb_trace_ws_bytes(grid, ring, tp, nm, tiles, sample_budget));
+    ws = std::max(ws, prec == RB_F32 ? rb_forward_ws_bytes(N, (int)nm)
+                                     : rb_forward_lp_ws_bytes(N, (int)nm, std::max(8, n_cu)));
+    const size_t fixed = (size_t)nm * 4 + P * 4 + RB_W_COUNT * 4 + RB_RED_PARTS * 4;
+    return step_arena_bytes(N, (int)nm, P, prec) + ws + fixed;
+}
+
+rb_status rb_set_sample_budget(rb_ctx *ctx, size_t bytes) {
+    if (!ctx) return RB_EINVAL;
+    if (bytes < ((size_t)1 << 20)) return rb_fail(ctx, RB_EINVAL, "sample budget below 1 MiB");
+    ctx->sample_budget = bytes;
+    return RB_OK;
+}
+
+// Frequency steps of several scans, enqueued together. The per-scan stages run on each scan's
+// own stream (the batch's scans overlap on the device); for each frequency index k, the Born
+// forward terms and the back-projections of every scan with a k-th frequency run as one
+// grouped launch each, on the first scan's stream, ordered by events.
+static rb_status batch_enqueue(const rb_scan_step *st, int count, rb_prec prec,
+                               StepBufs *bufs) {
+    rb_ctx *lead = st[0].ctx;
+    hipStream_t ls = lead->stream;
+    int kmax = 0;
+    for (int i = 0; i < count; ++i) {
+        rb_ctx *ctx = st[i].ctx;
+        RB_TRY(step_carve(ctx, st[i].grid, st[i].ring, prec, &bufs[i]));
+        RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0));
+        RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_FAIL_STEP, 1, -1));
+        RB_TRY(step_begin(ctx, st[i].grid, st[i].ring, st[i].tp, st[i].c, st[i].smooth_w,
+                          st[i].residual_norm, bufs[i]));
+        kmax = std::max(kmax, st[i].n_omega);
+    }
+    for (int k = 0; k < kmax; ++k) {
+        int act[RB_GROUP_MAX], na = 0;
+        for (int i = 0; i < count; ++i)
+            if (st[i].n_omega > k) act[na++] = i;
+        for (int a = 0; a < na; ++a) {
+            const rb_scan_step &s = st[act[a]];
+            RB_TRY(step_green(s.ctx, s.grid, s.tp, s.omega[k], s.mode, bufs[act[a]]));
+            if (s.ctx->stream != ls) {
+                RB_HIP(s.ctx, hipEventRecord(s.ctx->ev_join, s.ctx->stream));
+                RB_HIP(lead, hipStreamWaitEvent(ls, s.ctx->ev_join, 0));
+            }
+        }
+        // contractions and residuals of every active scan on the lead stream
+        rb_status res = RB_OK;
+        hipStream_t saved[RB_GROUP_MAX];
+        for (int a = 0; a < na; ++a) {
+            saved[a] = st[act[a]].ctx->stream;
+            st[act[a]].ctx->stream = ls;
+        }
+        do {
+            rb_fwd_plan plans[RB_GROUP_MAX];
+            int np = 0, born[RB_GROUP_MAX] = {0};
+            for (int a = 0; a < na && res == RB_OK; ++a) {
+                const rb_scan_step &s = st[act[a]];
+                StepBufs &b = bufs[act[a]];
+                if (s.mode != RB_RAY_BORN) continue;
+                born[a] = 1;
+                if (b.lp) {
+                    res = rb_forward_lp_plan(s.ctx, &b.gr, b.svscale, &plans[np]);
+                    if (res == RB_OK && !plans[np].pipe)  // too large for the grouped kernel
+                        res = rb_launch_forward_lp(s.ctx, &b.gr, nullptr, nullptr, b.d_born,
+                                                   b.svscale);
+                    else if (res == RB_OK)
+                        ++np;
+                } else {
+                    res = rb_launch_forward(s.ctx, &b.gr, nullptr, nullptr, b.d_born, b.svscale);
+                }
+            }
+            if (res != RB_OK) break;
+            if (np > 0) res = rb_launch_forward_lp_group(lead, prec, plans, np);
+            for (int a = 0, j = 0; a < na && res == RB_OK; ++a) {
+                const rb_scan_step &s = st[act[a]];
+                StepBufs &b = bufs[act[a]];
+                if (born[a] && b.lp && j < np && plans[j].gr.G == b.gr.G)
+                    res = rb_forward_lp_reduce(s.ctx, &plans[j++], b.d_born);
+                if (res == RB_OK)
+                    res = step_residual(s.ctx, s.tp, s.omega[k], born[a] != 0,
+                                        s.data + 2 * b.NN * (size_t)k, s.residual_norm, prec, b);
+            }
+            if (res != RB_OK) break;
+            if (prec != RB_F32) {
+                rb_rowred_prob pr[RB_GROUP_MAX];
+                for (int a = 0; a < na; ++a) {
+                    StepBufs &b = bufs[act[a]];
+                    pr[a] = rb_rowred_prob{b.Rp, b.gr.H, b.parts, b.N, b.nm};
+                }
+                res = rb_launch_rowred_lp_group(lead, prec, pr, na, 3);
+            } else {
+                for (int a = 0; a < na && res == RB_OK; ++a) {
+                    StepBufs &b = bufs[act[a]];
+                    res = rb_launch_rowred(st[act[a]].ctx, b.N, b.nm, b.R, (const float *)b.gr.H,
+                                           3, 0, b.rsym, b.parts, nullptr);
+                }
+            }
+        } while (false);
+        for (int a = 0; a < na; ++a) st[act[a]].ctx->stream = saved[a];
+        if (res != RB_OK) return res;
+        RB_HIP(lead, hipEventRecord(lead->ev_join, ls));
+        for (int a = 0; a < na; ++a) {
+            const rb_scan_step &s = st[act[a]];
+            if (s.ctx->stream != ls) RB_HIP(s.ctx, hipStreamWaitEvent(s.ctx->stream, lead->ev_join, 0));
+            RB_TRY(step_accumulate(s.ctx, s.omega[k], s.d_omega[k], bufs[act[a]]));
+        }
+    }
+    for (int i = 0; i < count; ++i)
+        RB_TRY(step_end(st[i].ctx, st[i].c, st[i].tau, 0, bufs[i]));
+    // later work on the lead stream waits for every scan's last kernel
+    for (int i = 1; i < count; ++i) {
+        rb_ctx *ctx = st[i].ctx;
+        if (ctx->stream == ls) continue;
+        RB_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->stream));
+        RB_HIP(lead, hipStreamWaitEvent(ls, ctx->ev_join, 0));
+    }
+    return RB_OK;
+}
+
+rb_status rb_frequency_step_batch(const rb_scan_step *steps, int32_t count, rb_prec prec,
+                                  rb_status *status) {
+    if (!steps || count < 1 || count > RB_GROUP_MAX) return RB_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        rb_ctx *ctx = steps[i].ctx;
+        if (!ctx) return RB_EINVAL;
+        ctx->err[0] = 0;
+        if (status) status[i] = RB_OK;
+        for (int j = 0; j < i; ++j)
+            if (steps[j].ctx == ctx)
+                return rb_fail(ctx, RB_EINVAL, "a batch takes each context once");
+        if (ctx->device != steps[0].ctx->device)
+            return rb_fail(ctx, RB_EINVAL, "the scans of a batch share one device");
+        RB_TRY(check_step_args(ctx, steps[i].grid, steps[i].ring, steps[i].tp, steps[i].c,
+                               steps[i].smooth_w, steps[i].n_omega, steps[i].omega,
+                               steps[i].d_omega, steps[i].data, steps[i].tau, steps[i].mode,
+                               prec));
+    }
+    rb_ctx *lead = steps[0].ctx;
+    RB_HIP(lead, hipSetDevice(lead->device));
+    bool prof[RB_GROUP_MAX];
+    for (int i = 0; i < count; ++i) {
+        rb_ctx *ctx = steps[i].ctx;
+        if (!ctx->ev_join)
+            RB_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    }
+    for (int i = 0; i < count; ++i) {
+        prof[i] = steps[i].ctx->prof;
+        steps[i].ctx->prof = false;
+        steps[i].ctx->deferred = true;
+    }
+    StepBufs bufs[RB_GROUP_MAX];
+    rb_status st = batch_enqueue(steps, count, prec, bufs);
+    for (int i = 0; i < count; ++i) {
+        steps[i].ctx->prof = prof[i];
+        steps[i].ctx->deferred = false;
+    }
+    if (st != RB_OK) return st;
+    // each scan's checks: a failed step left its model unchanged
+    rb_status first = RB_OK;
+    for (int i = 0; i < count; ++i) {
+        rb_ctx *ctx = steps[i].ctx;
+        RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, RB_W_COUNT * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->lost_nodes = ctx->h_flag[RB_W_LOST];
+        ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + RB_W_SAMPLES);
+        const int32_t fl = ctx->h_flag[RB_W_FLAGS];
+        rb_status si = RB_OK;
+        if (fl)
+            si = rb_fail(ctx, RB_ENONFINITE, "the step failed (%s); c holds the model before it",
+                         (fl & 1) ? "a ray did not reach the ring within max_steps"
+                                  : "non-finite model update");
+        if (status) status[i] = si;
+        if (first == RB_OK) first = si;
+    }
+    return first;
 }
 
 // The steps of a sweep, enqueued with deferred checks (also the body of the captured graph).

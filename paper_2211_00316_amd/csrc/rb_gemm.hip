@@ -354,6 +354,17 @@ rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const
     return RB_OK;
 }
 
+size_t rb_forward_ws_bytes(int n, int n_mask) {
+    const int T = (n + FW_B - 1) / FW_B;
+    const int tiles = T * (T + 1) / 2;
+    const int ksteps = (n_mask + FW_BK - 1) / FW_BK;
+    int splitk = (1024 + tiles - 1) / tiles;
+    splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
+    const int kchunk = ((ksteps + splitk - 1) / splitk) * FW_BK;
+    splitk = (n_mask + kchunk - 1) / kchunk;
+    return rb_align((size_t)splitk * n * n * sizeof(float2));
+}
+
 rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
                             float *d, const float *gscale) {
     const int n = gr->n, K = gr->n_mask;

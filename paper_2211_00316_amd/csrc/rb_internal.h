@@ -28,6 +28,9 @@ struct rb_arena {
 // Workgroups (and partial maxima) of a range-scale reduction.
 #define RB_RED_PARTS 512
 
+// Scans one batch (and one grouped launch) may hold.
+#define RB_GROUP_MAX 16
+
 // Words of rb_ctx::d_flag: error bits (1 ray overflow, 2 non-finite update), index of the
 // first failing step of a sweep, mask nodes the binning could not place, and (as int64 at
 // word 4) the ray samples of the last trace.
@@ -74,6 +77,7 @@ struct rb_ctx {
     uint64_t gen = 0;                 // bumped whenever a device buffer is reallocated
     hipStream_t cap_stream = nullptr; // library stream the sweep is captured on
     hipGraphExec_t gexec = nullptr;   // cached sweep graph
+    hipEvent_t ev_join = nullptr;     // orders this context's stream in a batch
     std::string gkey;                 // the arguments (and gen) it was captured with
 };
 
@@ -163,6 +167,11 @@ rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, con
                                        const double *c_mask, double omega, double d_omega,
                                        float *dm, int accumulate);
 int rb_rowred_mblocks(int n);
+// Workspace bytes the FP32 forward of n transducers over n_mask nodes reserves.
+size_t rb_forward_ws_bytes(int n, int n_mask);
+// Workspace bytes of one tracer launch under a sample budget (tiles: 32 x 8 walk tiles).
+size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
+                         int64_t n_mask, size_t tiles, size_t sample_budget);
 
 // Reduced-precision (BF16 / FP16 operand) form: layouts in rb_lowp.hip.
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
@@ -182,6 +191,36 @@ rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, cons
                               const void *Ht, int n_comp, float *parts, int *mblocks);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale);
+
+// Grouped launches (rb_frequency_step_batch): the contractions of several scans in one launch,
+// each problem computing exactly what its single launch computes.
+struct rb_rowred_prob {
+    const void *Rp;   // planar 16-bit block upper triangle of R (rb_launch_to_planar)
+    const void *Ht;   // 16-bit H planes of the green record
+    float *parts;     // [2][mblocks][n_mask] partial sums
+    int n, n_mask;
+};
+rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_prob *probs,
+                                    int count, int n_comp);
+// Launch plan of the pipelined forward on operands that carry sqrt(v) (w = delta = NULL):
+// tiles, K split and partial-sum buffer (in the workspace of the context that planned it).
+struct rb_fwd_plan {
+    rb_green gr;
+    const float *gscale;
+    bool pipe;  // the pipelined kernel applies (G's planes fit one buffer descriptor)
+    int n, ld, nT, tiles, kchunk, splitk;
+    unsigned nblk;
+    float2 *dpart;
+    float *vscale;
+};
+rb_status rb_forward_lp_plan(rb_ctx *ctx, const rb_green *gr, const float *gscale,
+                             rb_fwd_plan *plan);
+// Plans of pipe == true, one prec; the range-scale factors of each plan are applied first.
+rb_status rb_launch_forward_lp_group(rb_ctx *ctx, rb_prec prec, const rb_fwd_plan *plans,
+                                     int count);
+rb_status rb_forward_lp_reduce(rb_ctx *ctx, const rb_fwd_plan *plan, float *d);
+// Workspace bytes the forward of n transducers over n_mask nodes reserves.
+size_t rb_forward_lp_ws_bytes(int n, int n_mask, int n_cu);
 // scale[0] = 2^(top - e), scale[1] = 1 / scale[0] with 2^(e-1) <= max |x| < 2^e (complex x).
 rb_status rb_launch_range_scale(rb_ctx *ctx, const float *x, size_t count, int top, float *scale);
 int rb_rowred_lp_mblocks(int n);

@@ -586,43 +586,57 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
     }
 }
 
+// The back-projection contractions of one launch: `count` independent problems (one per scan
+// of a batch; count = 1 for a single call). Problem p owns items item0[p] .. item0[p+1]-1 of
+// the launch's item list; XCD x walks items xcd0[x] .. xcd0[x+1]-1.
+struct RowGroup {
+    int count;
+    int item0[RB_GROUP_MAX + 1];
+    int xcd0[9];
+    int n[RB_GROUP_MAX], n_cols[RB_GROUP_MAX];
+    const void *Rp[RB_GROUP_MAX];
+    const void *Ht[RB_GROUP_MAX];
+    float *parts[RB_GROUP_MAX];
+};
+
 template <typename T>
-__global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const T *__restrict__ Rp,
-                                                               const T *__restrict__ Ht, int n,
-                                                               int n_cols, int n_comp,
-                                                               int mblocks, int nblocks,
-                                                               float *__restrict__ parts) {
+__global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup grp, int n_comp) {
     __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
     __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
     __shared__ float red[2][2][LR_BN];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 64
-    const int np = rb_lp_pad(n);  // padded row length (zeros past n), a multiple of LR_BK
-    const size_t rplane = (size_t)n * np;
-    const size_t hplane = (size_t)n_cols * np;
-    const int KT = np / LR_BK;
     // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row (tid >> 3) +
     // 32 u; A rows u = 0..7, B rows u = 0..3. Byte offsets within the operand's planes.
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
-    const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
-    const uint32_t row_step = (uint32_t)(32 * (size_t)np * sizeof(T));
 
     // Persistent: one workgroup per CU walks a static list of work items. An item is one
     // node tile and a pair of row slabs (i, mblocks - 1 - i), whose contractions start at
-    // their diagonal blocks and together span mblocks + 1 blocks of K, so every item costs the
-    // same. Workgroups are dealt to the 8 XCDs round-robin; each XCD walks a contiguous range
-    // of items (both pairs of a node tile next to each other, sharing its H tile in L2).
-    // Every slab walks K from the last block down: the two workgroups of a node tile read the
-    // same rows of H at the same time for most of their first slabs, and each slab's epilogue
-    // finds its diagonal block, read last, still in L2.
-    const int n_pairs = (mblocks + 1) / 2, n_items = nblocks * n_pairs;
+    // their diagonal blocks and together span mblocks + 1 blocks of K, so every item of a
+    // problem costs the same. Workgroups are dealt to the 8 XCDs round-robin; each XCD walks
+    // a contiguous range of items (both pairs of a node tile next to each other, sharing its
+    // H tile in L2). Every slab walks K from the last block down: the two workgroups of a
+    // node tile read the same rows of H at the same time for most of their first slabs, and
+    // each slab's epilogue finds its diagonal block, read last, still in L2.
     const int L = gridDim.x >> 3, xcd = blockIdx.x & 7;
-    const int per = (((n_items + 7) / 8) + 1) & ~1;
-    for (int k = blockIdx.x >> 3; k < per; k += L) {
-        const int item = xcd * per + k;
-        if (item >= n_items) break;
-        const int nb = item / n_pairs, pr = item - nb * n_pairs;
+    const int x1 = grp.xcd0[xcd + 1];
+    for (int item = grp.xcd0[xcd] + (blockIdx.x >> 3); item < x1; item += L) {
+        int p = 0;
+        while (p + 1 < grp.count && item >= grp.item0[p + 1]) ++p;
+        const T *__restrict__ Rp = static_cast<const T *>(grp.Rp[p]);
+        const T *__restrict__ Ht = static_cast<const T *>(grp.Ht[p]);
+        float *__restrict__ parts = grp.parts[p];
+        const int n = grp.n[p], n_cols = grp.n_cols[p];
+        const int mblocks = (n + LR_BM - 1) / LR_BM, n_pairs = (mblocks + 1) / 2;
+        const int np = rb_lp_pad(n);  // padded row length (zeros past n), a multiple of LR_BK
+        const size_t rplane = (size_t)n * np;
+        const size_t hplane = (size_t)n_cols * np;
+        const int KT = np / LR_BK;
+        const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
+        const uint32_t row_step = (uint32_t)(32 * (size_t)np * sizeof(T));
+        const int local = item - grp.item0[p];
+        const int nb = local / n_pairs, pr = local - nb * n_pairs;
         for (int half = 0; half < 2; ++half) {
             const int mb = half == 0 ? pr : mblocks - 1 - pr;
             if (half == 1 && mb == pr) break;  // middle slab of an odd count
@@ -882,17 +896,31 @@ __global__ void __launch_bounds__(256) forward_lp_kernel(const T *__restrict__ G
 // elements with e <= r. Workgroups are dealt to the 8 XCDs round-robin: every tile of one
 // chunk goes to the same XCD, so the chunk's columns of G come from HBM once. Rows of G are
 // ld long with zeros past the last node; rows past n read other finite data or zeros and
-// only reach outputs that are not stored.
+// only reach outputs that are not stored. A launch serves `count` independent problems (the
+// scans of a batch; one for a single call): problem p takes workgroups blk0[p] ..
+// blk0[p+1]-1, blk0[p] a multiple of 8, so the XCD of a workgroup is that of its local index.
+struct FwdGroup {
+    int count;
+    int blk0[RB_GROUP_MAX + 1];
+    int n[RB_GROUP_MAX], ld[RB_GROUP_MAX], nT[RB_GROUP_MAX], tiles[RB_GROUP_MAX];
+    int kchunk[RB_GROUP_MAX], splitk[RB_GROUP_MAX];
+    const void *G[RB_GROUP_MAX];
+    float2 *dpart[RB_GROUP_MAX];
+};
+
 template <typename T>
-__global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const T *__restrict__ Gp,
-                                                                  int n, int ld, int nTn,
-                                                                  int tiles, int kchunk,
-                                                                  int splitk,
-                                                                  float2 *__restrict__ dpart) {
+__global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup grp) {
     __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
     __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
-    const int kq = blockIdx.x >> 3;
-    const int split = (kq / tiles) * 8 + (blockIdx.x & 7);
+    int p = 0;
+    while (p + 1 < grp.count && (int)blockIdx.x >= grp.blk0[p + 1]) ++p;
+    const T *__restrict__ Gp = static_cast<const T *>(grp.G[p]);
+    float2 *__restrict__ dpart = grp.dpart[p];
+    const int n = grp.n[p], ld = grp.ld[p], nTn = grp.nT[p], tiles = grp.tiles[p];
+    const int kchunk = grp.kchunk[p], splitk = grp.splitk[p];
+    const int blk = (int)blockIdx.x - grp.blk0[p];
+    const int kq = blk >> 3;
+    const int split = (kq / tiles) * 8 + (blk & 7);
     if (split >= splitk) return;  // whole workgroup: no barrier is skipped by part of it
     constexpr int RB = LR_BM / LR_BN;  // column blocks per row block
     int rem = kq % tiles, tm = 0;
@@ -1032,31 +1060,205 @@ rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float
 
 int rb_rowred_lp_mblocks(int n) { return (n + LR_BM - 1) / LR_BM; }
 
-rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
-                              const void *Ht, int n_comp, float *parts, int *mblocks_out) {
-    int mblocks = rb_rowred_lp_mblocks(n);
-    int nblocks = (n_mask + LR_BN - 1) / LR_BN;
-    int grid = std::max(8, ctx->n_cu / 8 * 8);  // one workgroup per CU (persistent)
-    // byte offsets into the two part planes of an operand, padding rows included, must stay
-    // below LR_SPAN (32-bit buffer offsets)
-    const size_t np = (size_t)rb_lp_pad(n);
-    const size_t span = (2 * (size_t)n_mask + LR_BN + (size_t)mblocks * LR_BM) * np * 2 + 64;
-    if (span >= LR_SPAN)
-        return rb_fail(ctx, RB_EUNSUPPORTED,
-                       "16-bit back-projection: H planes of %d nodes x %zu exceed 4 GiB",
-                       n_mask, np);
+rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_prob *pr,
+                                    int count, int n_comp) {
+    if (count < 1 || count > RB_GROUP_MAX)
+        return rb_fail(ctx, RB_EINVAL, "grouped back-projection of %d problems", count);
+    RowGroup g{};
+    g.count = count;
+    int64_t items = 0, cost = 0;
+    int64_t pcost[RB_GROUP_MAX];  // cost of one item of each problem (K blocks it walks)
+    for (int i = 0; i < count; ++i) {
+        const int n = pr[i].n, n_mask = pr[i].n_mask;
+        const int mblocks = rb_rowred_lp_mblocks(n);
+        const int nblocks = (n_mask + LR_BN - 1) / LR_BN;
+        // byte offsets into the two part planes of an operand, padding rows included, must
+        // stay below LR_SPAN (32-bit buffer offsets)
+        const size_t np = (size_t)rb_lp_pad(n);
+        const size_t span = (2 * (size_t)n_mask + LR_BN + (size_t)mblocks * LR_BM) * np * 2 + 64;
+        if (span >= LR_SPAN)
+            return rb_fail(ctx, RB_EUNSUPPORTED,
+                           "16-bit back-projection: H planes of %d nodes x %zu exceed 4 GiB",
+                           n_mask, np);
+        g.item0[i] = (int)items;
+        g.n[i] = n;
+        g.n_cols[i] = n_mask;
+        g.Rp[i] = pr[i].Rp;
+        g.Ht[i] = pr[i].Ht;
+        g.parts[i] = pr[i].parts;
+        const int64_t it = (int64_t)nblocks * ((mblocks + 1) / 2);
+        pcost[i] = mblocks + 1;
+        items += it;
+        cost += it * pcost[i];
+    }
+    if (items >= (int64_t)1 << 30)
+        return rb_fail(ctx, RB_EUNSUPPORTED, "grouped back-projection of %lld items",
+                       (long long)items);
+    g.item0[count] = (int)items;
+    if (count == 1) {
+        // even-sized ranges: both slab pairs of a node tile stay on one XCD
+        const int per = (int)((((items + 7) / 8) + 1) & ~int64_t(1));
+        for (int x = 0; x <= 8; ++x) g.xcd0[x] = (int)std::min<int64_t>((int64_t)x * per, items);
+    } else {
+        // XCD ranges of equal cost: the items of different problems cost differently
+        g.xcd0[0] = 0;
+        for (int x = 1; x < 8; ++x) {
+            const int64_t target = cost * x / 8;
+            int64_t cum = 0;
+            int i = 0;
+            for (; i + 1 < count; ++i) {
+                const int64_t c_i = (int64_t)(g.item0[i + 1] - g.item0[i]) * pcost[i];
+                if (cum + c_i > target) break;
+                cum += c_i;
+            }
+            const int64_t n_i = g.item0[i + 1] - g.item0[i];
+            int64_t local = (target - cum + pcost[i] - 1) / pcost[i];
+            local = std::min<int64_t>((local + 1) & ~int64_t(1), n_i);
+            g.xcd0[x] = std::max<int>(g.xcd0[x - 1], (int)(g.item0[i] + local));
+        }
+        g.xcd0[8] = (int)items;
+    }
+    const int grid = std::max(8, ctx->n_cu / 8 * 8);  // one workgroup per CU (persistent)
     rb_prof_begin(ctx, ST_BACKPROJECT);
     if (prec == RB_BF16)
         hipLaunchKernelGGL(rowred_lp_kernel<__bf16>, dim3(grid), dim3(LR_THREADS), 0, ctx->stream,
-                           (const __bf16 *)Rp, (const __bf16 *)Ht, n, n_mask, n_comp, mblocks,
-                           nblocks, parts);
+                           g, n_comp);
     else
-        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(LR_THREADS), 0, ctx->stream,
-                           (const _Float16 *)Rp, (const _Float16 *)Ht, n, n_mask, n_comp, mblocks,
-                           nblocks, parts);
+        hipLaunchKernelGGL(rowred_lp_kernel<_Float16>, dim3(grid), dim3(LR_THREADS), 0,
+                           ctx->stream, g, n_comp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
-    if (mblocks_out) *mblocks_out = mblocks;
+    return RB_OK;
+}
+
+rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
+                              const void *Ht, int n_comp, float *parts, int *mblocks_out) {
+    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask};
+    RB_TRY(rb_launch_rowred_lp_group(ctx, prec, &pr, 1, n_comp));
+    if (mblocks_out) *mblocks_out = rb_rowred_lp_mblocks(n);
+    return RB_OK;
+}
+
+namespace {
+struct FwdShape {
+    int nT, tiles, kchunk, splitk;
+    unsigned nblk;
+};
+
+// Tiles and K split of the 16-bit forward for n transducers over K nodes (rows ld long).
+// pipe: the pipelined kernel (256 x 128 upper tiles); else the standalone-call kernel.
+FwdShape forward_shape(int n, int K, int ld, bool pipe, int n_cu) {
+    FwdShape f{};
+    const int ksteps = pipe ? ld / LR_BK : (K + LF_BK - 1) / LF_BK;
+    if (pipe) {
+        f.nT = (n + LR_BN - 1) / LR_BN;
+        f.tiles = 0;
+        for (int tm = 0; tm * (LR_BM / LR_BN) < f.nT; ++tm) f.tiles += f.nT - tm * (LR_BM / LR_BN);
+        // K chunks in multiples of 8 (one XCD per chunk group): the fewest that fill the
+        // device at least 1.5 times over with at most 7 % of the last round idle
+        const int cu = std::max(8, n_cu);
+        f.splitk = 8;
+        for (int s8 = 8; s8 <= 1024; s8 += 8) {
+            const long blocks = (long)f.tiles * s8, rounds = (blocks + cu - 1) / cu;
+            f.splitk = s8;
+            if (ksteps / s8 < 8) break;
+            if (2 * blocks >= 3L * cu && (double)blocks / (double)(rounds * cu) >= 0.93) break;
+        }
+        f.splitk = std::max(1, std::min(f.splitk, ksteps));
+    } else {
+        f.nT = (n + LF_B - 1) / LF_B;
+        f.tiles = f.nT * (f.nT + 1) / 2;
+        f.splitk = (1024 + f.tiles - 1) / f.tiles;
+        f.splitk = std::max(1, std::min(f.splitk, std::max(1, ksteps / 4)));
+        f.splitk = (f.splitk + 7) / 8 * 8;  // K chunks spread evenly over the 8 XCDs
+    }
+    f.kchunk = (ksteps + f.splitk - 1) / f.splitk;
+    f.splitk = (ksteps + f.kchunk - 1) / f.kchunk;
+    f.nblk = (unsigned)(f.tiles * ((f.splitk + 7) / 8) * 8);
+    return f;
+}
+
+bool forward_pipe_fits(int n, int n_mask) {
+    return 2 * (size_t)n * rb_lp_pad(n_mask) * 2 <= LR_SPAN;
+}
+}  // namespace
+
+size_t rb_forward_lp_ws_bytes(int n, int n_mask, int n_cu) {
+    const int ld = rb_lp_pad(n_mask);
+    const FwdShape f = forward_shape(n, n_mask, ld, forward_pipe_fits(n, n_mask), n_cu);
+    return rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8);
+}
+
+rb_status rb_forward_lp_plan(rb_ctx *ctx, const rb_green *gr, const float *gscale,
+                             rb_fwd_plan *pl) {
+    const int n = gr->n, K = gr->n_mask, ld = rb_lp_pad(K);
+    pl->pipe = forward_pipe_fits(n, K);
+    const FwdShape f = forward_shape(n, K, ld, pl->pipe, ctx->n_cu);
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(
+        ctx, &ctx->ws, rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8)));
+    pl->gr = *gr;
+    pl->gscale = gscale;
+    pl->n = n;
+    pl->ld = ld;
+    pl->nT = f.nT;
+    pl->tiles = f.tiles;
+    pl->kchunk = f.kchunk;
+    pl->splitk = f.splitk;
+    pl->nblk = f.nblk;
+    pl->dpart = rb_carve<float2>(&ctx->ws, (size_t)f.splitk * n * n);
+    pl->vscale = rb_carve<float>(&ctx->ws, 2);
+    return RB_OK;
+}
+
+rb_status rb_launch_forward_lp_group(rb_ctx *ctx, rb_prec prec, const rb_fwd_plan *pl,
+                                     int count) {
+    if (count < 1 || count > RB_GROUP_MAX)
+        return rb_fail(ctx, RB_EINVAL, "grouped forward of %d problems", count);
+    FwdGroup g{};
+    g.count = count;
+    int64_t blk = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!pl[i].pipe || pl[i].gr.prec != prec)
+            return rb_fail(ctx, RB_EINVAL, "grouped forward: problem %d does not fit", i);
+        g.blk0[i] = (int)blk;
+        g.n[i] = pl[i].n;
+        g.ld[i] = pl[i].ld;
+        g.nT[i] = pl[i].nT;
+        g.tiles[i] = pl[i].tiles;
+        g.kchunk[i] = pl[i].kchunk;
+        g.splitk[i] = pl[i].splitk;
+        g.G[i] = pl[i].gr.G;
+        g.dpart[i] = pl[i].dpart;
+        blk += pl[i].nblk;
+    }
+    if (blk >= (int64_t)1 << 30)
+        return rb_fail(ctx, RB_EUNSUPPORTED, "grouped forward of %lld workgroups", (long long)blk);
+    g.blk0[count] = (int)blk;
+    rb_prof_begin(ctx, ST_FORWARD);
+    // G already carries sqrt(v) s: undo s^2 (or nothing) in the reduction
+    for (int i = 0; i < count; ++i) {
+        hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, pl[i].gscale,
+                           pl[i].vscale);
+        RB_CHECK_LAUNCH(ctx);
+    }
+    if (prec == RB_BF16)
+        hipLaunchKernelGGL(forward_pipe_kernel<__bf16>, dim3((unsigned)blk), dim3(LR_THREADS), 0,
+                           ctx->stream, g);
+    else
+        hipLaunchKernelGGL(forward_pipe_kernel<_Float16>, dim3((unsigned)blk), dim3(LR_THREADS),
+                           0, ctx->stream, g);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_forward_lp_reduce(rb_ctx *ctx, const rb_fwd_plan *pl, float *d) {
+    rb_prof_begin(ctx, ST_FORWARD_REDUCE);
+    hipLaunchKernelGGL(forward_reduce_lp, dim3((pl->n + 255) / 256, pl->n), dim3(256), 0,
+                       ctx->stream, pl->dpart, pl->n, pl->splitk, pl->vscale, (float2 *)d);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
     return RB_OK;
 }
 
@@ -1065,71 +1267,39 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     const int n = gr->n, K = gr->n_mask, ld = rb_lp_pad(K);
     // Operands that carry sqrt(v) take the pipelined kernel while G's two planes fit one
     // buffer descriptor; the node weights of the standalone call are folded in on the fly.
-    const bool pipe = !w && 2 * (size_t)n * ld * 2 <= LR_SPAN;
-    int nT, tiles, kchunk, splitk;
-    const int ksteps = pipe ? ld / LR_BK : (K + LF_BK - 1) / LF_BK;
-    if (pipe) {
-        nT = (n + LR_BN - 1) / LR_BN;
-        tiles = 0;
-        for (int tm = 0; tm * (LR_BM / LR_BN) < nT; ++tm) tiles += nT - tm * (LR_BM / LR_BN);
-        // K chunks in multiples of 8 (one XCD per chunk group): the fewest that fill the
-        // device at least 1.5 times over with at most 7 % of the last round idle
-        const int cu = std::max(8, ctx->n_cu);
-        splitk = 8;
-        for (int s8 = 8; s8 <= 1024; s8 += 8) {
-            const long blocks = (long)tiles * s8, rounds = (blocks + cu - 1) / cu;
-            splitk = s8;
-            if (ksteps / s8 < 8) break;
-            if (2 * blocks >= 3L * cu && (double)blocks / (double)(rounds * cu) >= 0.93) break;
-        }
-        splitk = std::max(1, std::min(splitk, ksteps));
-    } else {
-        nT = (n + LF_B - 1) / LF_B;
-        tiles = nT * (nT + 1) / 2;
-        splitk = (1024 + tiles - 1) / tiles;
-        splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
-        splitk = (splitk + 7) / 8 * 8;  // K chunks spread evenly over the 8 XCDs
+    if (!w && forward_pipe_fits(n, K)) {
+        rb_fwd_plan pl;
+        RB_TRY(rb_forward_lp_plan(ctx, gr, gscale, &pl));
+        RB_TRY(rb_launch_forward_lp_group(ctx, gr->prec, &pl, 1));
+        return rb_forward_lp_reduce(ctx, &pl, d);
     }
-    kchunk = (ksteps + splitk - 1) / splitk;
-    splitk = (ksteps + kchunk - 1) / kchunk;
-    const unsigned nblk = (unsigned)(tiles * ((splitk + 7) / 8) * 8);
+    const FwdShape f = forward_shape(n, K, ld, false, ctx->n_cu);
     ctx->ws.used = 0;
-    rb_status st = rb_arena_reserve(
-        ctx, &ctx->ws, rb_align((size_t)splitk * n * n * sizeof(float2)) + rb_align(8));
-    if (st != RB_OK) return st;
-    float2 *dpart = rb_carve<float2>(&ctx->ws, (size_t)splitk * n * n);
-    float *vscale = rb_carve<float>(&ctx->ws, 2);
+    RB_TRY(rb_arena_reserve(
+        ctx, &ctx->ws, rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8)));
+    rb_fwd_plan pl;
+    pl.n = n;
+    pl.splitk = f.splitk;
+    pl.dpart = rb_carve<float2>(&ctx->ws, (size_t)f.splitk * n * n);
+    pl.vscale = rb_carve<float>(&ctx->ws, 2);
     rb_prof_begin(ctx, ST_FORWARD);
     if (w) {
         // range scale of v = w delta (the node weights are folded into the A operand)
-        RB_TRY(launch_range_scale(ctx, (const float2 *)w, (size_t)K, delta, 14, vscale));
+        RB_TRY(launch_range_scale(ctx, (const float2 *)w, (size_t)K, delta, 14, pl.vscale));
     } else {
-        // G already carries sqrt(v) s: undo s^2 (or nothing) in the reduction
-        hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale, vscale);
+        hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale,
+                           pl.vscale);
         RB_CHECK_LAUNCH(ctx);
     }
-    if (pipe && gr->prec == RB_BF16)
-        hipLaunchKernelGGL(forward_pipe_kernel<__bf16>, dim3(nblk), dim3(LR_THREADS), 0,
-                           ctx->stream, (const __bf16 *)gr->G, n, ld, nT, tiles, kchunk, splitk,
-                           dpart);
-    else if (pipe)
-        hipLaunchKernelGGL(forward_pipe_kernel<_Float16>, dim3(nblk), dim3(LR_THREADS), 0,
-                           ctx->stream, (const _Float16 *)gr->G, n, ld, nT, tiles, kchunk, splitk,
-                           dpart);
-    else if (gr->prec == RB_BF16)
-        hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, ld, nT,
-                           kchunk * LF_BK, splitk, vscale, dpart);
+    if (gr->prec == RB_BF16)
+        hipLaunchKernelGGL(forward_lp_kernel<__bf16>, dim3(f.nblk), dim3(256), 0, ctx->stream,
+                           (const __bf16 *)gr->G, (const float2 *)w, delta, n, K, ld, f.nT,
+                           f.kchunk * LF_BK, f.splitk, pl.vscale, pl.dpart);
     else
-        hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const _Float16 *)gr->G, (const float2 *)w, delta, n, K, ld, nT,
-                           kchunk * LF_BK, splitk, vscale, dpart);
+        hipLaunchKernelGGL(forward_lp_kernel<_Float16>, dim3(f.nblk), dim3(256), 0, ctx->stream,
+                           (const _Float16 *)gr->G, (const float2 *)w, delta, n, K, ld, f.nT,
+                           f.kchunk * LF_BK, f.splitk, pl.vscale, pl.dpart);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
-    rb_prof_begin(ctx, ST_FORWARD_REDUCE);
-    hipLaunchKernelGGL(forward_reduce_lp, dim3((n + 255) / 256, n), dim3(256), 0, ctx->stream,
-                       dpart, n, splitk, vscale, (float2 *)d);
-    RB_CHECK_LAUNCH(ctx);
-    rb_prof_end(ctx);
-    return RB_OK;
+    return rb_forward_lp_reduce(ctx, &pl, d);
 }

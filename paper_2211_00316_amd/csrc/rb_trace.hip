@@ -1069,13 +1069,12 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
     return RB_OK;
 }
 
-// Emitters per tracer launch so that the ray samples of one chunk fit the context's budget.
-static int trace_chunk(const rb_ctx *ctx, const rb_ring *r, const rb_trace_params *tp,
+// Emitters per tracer launch so that the ray samples of one chunk fit the budget.
+static int trace_chunk(size_t budget, const rb_ring *r, const rb_trace_params *tp,
                        int64_t n_mask) {
     size_t S = (size_t)tp->max_steps + 1;
     size_t per = S * tp->n_rays * (sizeof(float2) + sizeof(float4) + 1) + (size_t)n_mask * 8 +
                  (size_t)tp->n_rays * 32;
-    size_t budget = ctx->sample_budget;
     size_t c = budget / per;
     if (c < 1) c = 1;
     if (c > (size_t)r->n) c = r->n;
@@ -1088,24 +1087,36 @@ static size_t mtiles_of(const rb_grid *g) {
     return mtx * mty;
 }
 
+// Workspace of one tracer launch of C emitters (`tiles` 32 x 8 walk tiles over the mask).
+static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
+                          int64_t n_mask, int C, size_t tiles) {
+    const size_t nr = tp->n_rays, S = (size_t)tp->max_steps + 1;
+    const size_t plane = (size_t)C * S * nr;
+    return rb_align(plane * sizeof(float2)) + rb_align(plane * sizeof(float4)) +
+           rb_align(plane) + 2 * rb_align((size_t)C * nr * sizeof(int32_t)) +
+           rb_align((size_t)C * nr * sizeof(double)) +
+           2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
+           rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
+           rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)C * tiles * sizeof(int2)) +
+           rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
+           rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
+           rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float));
+}
+
+size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
+                         int64_t n_mask, size_t tiles, size_t sample_budget) {
+    return trace_bytes(g, r, tp, n_mask, trace_chunk(sample_budget, r, tp, n_mask), tiles);
+}
+
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
                           float4 *rec, double2 *ring_out) {
     const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
     const int n_mask = (int)ctx->n_mask;
-    const int C = trace_chunk(ctx, r, tp, n_mask);
+    const int C = trace_chunk(ctx->sample_budget, r, tp, n_mask);
     size_t plane = (size_t)C * S * nr;
-    size_t bytes = rb_align(plane * sizeof(float2)) + rb_align(plane * sizeof(float4)) +
-                   rb_align(plane) +
-                   2 * rb_align((size_t)C * nr * sizeof(int32_t)) +
-                   rb_align((size_t)C * nr * sizeof(double)) +
-                   2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
-                   rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
-                   rb_align((size_t)N * sizeof(double2)) +
-                   rb_align((size_t)C * ctx->tiles_x * ctx->tiles_y * sizeof(int2)) +
-                   rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
-                   rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
-                   rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float));
+    const size_t bytes =
+        trace_bytes(g, r, tp, n_mask, C, (size_t)ctx->tiles_x * ctx->tiles_y);
     ctx->ws.used = 0;
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);
     if (st != RB_OK) return st;

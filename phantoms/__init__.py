@@ -93,6 +93,53 @@ LARGE = Workload(
 
 WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE)}
 
+# Serving mix: three scan classes on the 110 mm ring with one ray per transducer per
+# transducer count (n_rays = N); 32 frequencies each from 100 kHz to the class's highest,
+# about four grid spacings per wavelength in water at the top.
+SERVE_CLASSES = tuple(
+    Workload(name=f"serve_ring{n}_grid{nx}", n_trans=n, radius=0.11, nx=nx, dx=dx,
+             mask_radius=0.099, freqs=tuple(np.linspace(100e3, fmax, 32).tolist()), n_rays=n,
+             ds=0.2e-3, phantom="breast", n_lesions=lesions, smooth_1mm=(13, 11, 9, 7))
+    for n, nx, dx, fmax, lesions in ((256, 256, 0.9e-3, 400e3, 3),
+                                     (512, 512, 0.45e-3, 800e3, 3),
+                                     (1024, 1024, 0.22e-3, 1.2e6, 10)))
+
+
+@dataclasses.dataclass(frozen=True)
+class ServeDraw:
+    """One request of a serving run: scan class, phantom seed, number of steps, arrival (s)."""
+
+    rid: int
+    cls: int
+    phantom_seed: int
+    n_steps: int
+    arrival: float
+
+
+def serve_draws(n_requests: int = 64, seed: int = 5, rate: float | None = None,
+                n_classes: int = 3, seeds_per_class: int = 3, min_steps: int = 8,
+                max_steps: int = 32) -> list:
+    """Seeded requests: class uniform, phantom seed from a pool of seeds_per_class per class,
+    steps uniform in [min_steps, max_steps], Poisson arrivals at `rate` per second (unit
+    exponential gaps scaled by 1 / rate, so one seed gives the same pattern at every rate;
+    every request at time 0 if rate is None)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cls = rng.integers(0, n_classes, n_requests)
+    pseed = 11 + rng.integers(0, seeds_per_class, n_requests)
+    steps = rng.integers(min_steps, max_steps + 1, n_requests)
+    gaps = rng.exponential(1.0, n_requests)
+    t = np.cumsum(gaps) / rate if rate else np.zeros(n_requests)
+    return [ServeDraw(i, int(cls[i]), int(pseed[i]), int(steps[i]), float(t[i]))
+            for i in range(n_requests)]
+
+
+def step_frequencies(n_steps: int, n_freqs: int) -> list:
+    """Indices into a class's frequency list of a request with n_steps steps: spread evenly
+    from the lowest to the highest, low to high."""
+    if n_steps == 1:
+        return [0]
+    return [int(round(k * (n_freqs - 1) / (n_steps - 1))) for k in range(n_steps)]
+
 
 def node_coords(nx: int, ny: int, dx: float, x0: float, y0: float):
     """Cartesian coordinates of the nodes, arrays of shape (ny, nx), x fastest."""
