@@ -331,7 +331,15 @@ def run_serve(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     budget = int(0.9 * torch.cuda.mem_get_info()[0])
-    ex = serve.GpuExecutor(prec)
+    ex = serve.GpuExecutor(prec, budget=budget)
+    last = [0.0]
+
+    def progress(msg):   # at most one line every 5 s
+        now = time.perf_counter()
+        if now - last[0] >= 5.0:
+            last[0] = now
+            print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
     # warm-up: one step of one request per class (module loads, first allocations)
     warm = []
     for k in range(len(classes)):
@@ -341,12 +349,15 @@ def run_serve(args):
     serve.Server(ex, budget).run(make(warm))
     print("[serve] warm-up done", file=sys.stderr, flush=True)
 
-    closed = serve.Server(ex, budget).run(make(draws0))
+    # one request at a time (no batching), then the closed loop with batching
+    seq = serve.Server(ex, budget, max_batch=1, log=progress).run(make(draws0))
+    print(f"[serve] one at a time: {seq.summary()}", file=sys.stderr, flush=True)
+    closed = serve.Server(ex, budget, log=progress).run(make(draws0))
     cap = len(draws0) / closed.makespan
     rate = args.rate_frac * cap
     print(f"[serve] closed loop: {closed.summary()}", file=sys.stderr, flush=True)
     draws = ph.serve_draws(args.requests, seed=5, rate=rate)
-    mix = serve.Server(ex, budget).run(make(draws))
+    mix = serve.Server(ex, budget, log=progress).run(make(draws))
     print(f"[serve] open loop at {rate:.3f} requests/s: {mix.summary()}", file=sys.stderr,
           flush=True)
     # alone vs in the mix: the first request of each class
@@ -384,6 +395,7 @@ def run_serve(args):
                    "budget_bytes": budget},
         "open_loop": mix.summary(),
         "closed_loop": closed.summary(),
+        "one_at_a_time": seq.summary(),
         "alone_vs_mix_max_abs_diff": diffs,
     }
     print(json.dumps(out), flush=True)

@@ -158,10 +158,13 @@ class Server:
 
 class GpuExecutor:
     """Runs the requests' steps with the library: one context per running request, on one of
-    a few streams (default priority), with a tracer sample budget per request."""
+    a few streams (default priority), with a tracer sample budget per request. A finished
+    request's context is kept (its workspaces and mask lists stay allocated) and reused by
+    the next request of the same geometry; kept contexts are destroyed when a new one would
+    not fit beside them and the running requests within `budget` bytes."""
 
     def __init__(self, prec, device="cuda:0", n_streams: int = 4,
-                 sample_budget: int = 12 << 30):
+                 sample_budget: int = 12 << 30, budget: int | None = None, pool: bool = True):
         import torch
 
         from . import _lib
@@ -172,8 +175,38 @@ class GpuExecutor:
         self.device = device
         self.streams = [torch.cuda.Stream(device) for _ in range(n_streams)]
         self.sample_budget = int(sample_budget)
+        self.budget = budget
+        self.pool_on = pool
         self.ctx = {}
+        self.active_bytes = 0
+        self.pool = collections.OrderedDict()   # key -> list of (context, bytes), oldest first
         self._next = 0
+
+    @staticmethod
+    def _key(r):
+        g, n, t = r.grid, r.ring, r.tp
+        return (g.nx, g.ny, g.dx, g.x0, g.y0, g.mask_radius, n.n, n.radius, n.psi0, t.n_rays,
+                t.max_steps, t.ds, t.c0)
+
+    def pooled_bytes(self) -> int:
+        return sum(b for lst in self.pool.values() for _, b in lst)
+
+    def _evict(self, room: int):
+        """Destroy kept contexts, oldest first, until `room` more bytes fit the budget."""
+        while self.pool and self.budget is not None and \
+                self.active_bytes + self.pooled_bytes() + room > self.budget:
+            key = next(iter(self.pool))
+            ctx, _ = self.pool[key].pop(0)
+            if not self.pool[key]:
+                del self.pool[key]
+            ctx.close()
+
+    def drain(self):
+        """Destroy every kept context."""
+        for lst in self.pool.values():
+            for ctx, _ in lst:
+                ctx.close()
+        self.pool.clear()
 
     def _budget_for(self, r) -> int:
         # all emitters in one tracer launch when that fits, else chunks of the budget
@@ -188,10 +221,18 @@ class GpuExecutor:
 
     def open(self, r):
         torch = self.torch
-        stream = self.streams[self._next % len(self.streams)]
-        self._next += 1
-        ctx = self._lib.Context(self.device, stream=stream)
-        ctx.set_sample_budget(self._budget_for(r))
+        key = self._key(r)
+        if self.pool.get(key):
+            ctx, _ = self.pool[key].pop()
+            if not self.pool[key]:
+                del self.pool[key]
+        else:
+            self._evict(r.bytes)
+            stream = self.streams[self._next % len(self.streams)]
+            self._next += 1
+            ctx = self._lib.Context(self.device, stream=stream)
+            ctx.set_sample_budget(self._budget_for(r))
+        self.active_bytes += r.bytes
         r.c = r.c_start.clone()
         torch.cuda.current_stream().synchronize()   # the copy is done before the scan's stream reads it
         self.ctx[r.rid] = ctx
@@ -207,4 +248,8 @@ class GpuExecutor:
 
     def close(self, r):
         ctx = self.ctx.pop(r.rid)
-        ctx.close()
+        self.active_bytes -= r.bytes
+        if self.pool_on:
+            self.pool.setdefault(self._key(r), []).append((ctx, r.bytes))
+        else:
+            ctx.close()
