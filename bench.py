@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
                          "(reference for the HBM byte counters)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="built-in forward launch configuration instead of the autotuner's")
     ap.add_argument("--serve", action="store_true",
                     help="serving mix of scans of three sizes with continuous batching "
                          "(prints its own JSON line)")
@@ -459,6 +461,17 @@ def main():
           flush=True)
     data = synthesize_data(ctx, w, grid, ring, tp, c_true, list(range(n_total)))
     prec_code = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
+
+    # forward tiles and K splits of each form from the autotuner (untimed)
+    tuning = {}
+    if not args.no_tune:
+        for name, code in ([("f32", _lib.RB_F32)] if not args.no_fp32 and args.prec != "f32"
+                           else []) + [(args.prec, prec_code)]:
+            t = ctx.autotune(grid, ring, code)
+            tuning[name] = {"forward_tile": "256x128" if t.fwd_tile == _lib.RB_TILE_256x128
+                            else "128x128", "forward_splitk": t.fwd_splitk,
+                            "forward_ms": round(t.fwd_ms, 3)}
+            print(f"[bench] autotune {name}: {tuning[name]}", file=sys.stderr, flush=True)
 
     forms = {}
     c_start = start_model(w, args.start, c_true)
@@ -505,7 +518,8 @@ def main():
                    "mask_nodes": int(Pm), "freqs_hz": [w.freqs[k] for k in
                                                         range(args.warmup, n_total)],
                    "start_model": args.start,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "autotuned_forward": tuning or None},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
         "rooflines": rl,

@@ -271,6 +271,38 @@ size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_pa
  * a smaller budget means more launches. RB_EINVAL below 1 MiB. */
 rb_status rb_set_sample_budget(rb_ctx *ctx, size_t bytes);
 
+/* Launch configuration of the Born forward contraction (Eq. perturb1) for one shape: the
+ * workgroup tile (rows e x columns r of d) and the number of K chunks (mask nodes split over
+ * workgroups, partial sums added in a fixed order). Applies to calls with n, n_mask and prec
+ * equal to the record's and, for 16-bit operands, to operands that carry sqrt(v)
+ * (rb_frequency_step, rb_frequency_sweep, rb_frequency_step_batch, rb_born_forward with
+ * w = delta = NULL); FP32 calls with weights use it too. Other calls use a built-in rule. */
+typedef enum { RB_TILE_256x128 = 0, RB_TILE_128x128 = 1 } rb_tile;
+typedef struct {
+    int32_t n, n_mask;
+    rb_prec prec;
+    rb_tile fwd_tile;      /* RB_TILE_256x128: pipelined 16-bit kernel; FP32 takes 128x128 */
+    int32_t fwd_splitk;    /* K chunks, 1 .. 1024 */
+    float fwd_ms;          /* rb_autotune: measured time of this configuration (ms) */
+} rb_tuning;
+
+/* Autotuner: times every candidate forward configuration (both tiles for 16-bit operands,
+ * K splits from 8 to 64 and the built-in choice) on this context's device, on operands of
+ * the shape of `grid`'s mask and `ring` (seeded values in the context's step workspace, so
+ * nothing else is overwritten), keeps the fastest in the context and writes it to *out
+ * (may be NULL). A context keeps up to 16 tunings, one per (n, n_mask, prec). Synchronizes
+ * the context's stream. Results of the tuned and untuned launches differ only by the order
+ * of the FP32 partial sums. */
+rb_status rb_autotune(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_prec prec,
+                      rb_tuning *out);
+/* Install a tuning (e.g. one saved from rb_autotune), replacing the record of its shape;
+ * NULL removes every tuning. RB_EINVAL for a configuration that is not valid for its
+ * precision. rb_step_bytes covers K splits up to 64 (the autotuner's range); a larger one
+ * set here takes more workspace. */
+rb_status rb_set_tuning(rb_ctx *ctx, const rb_tuning *t);
+/* The tuning of the shape given in out->n, out->n_mask, out->prec; RB_EINVAL if none. */
+rb_status rb_get_tuning(const rb_ctx *ctx, rb_tuning *out);
+
 /* Measurement: per-stage GPU time from HIP events recorded around every kernel launch on
  * the context's stream while profiling is on (small overhead; off by default). Stages are
  * numbered 0 .. RB_N_STAGES-1 (rb_stage_name). rb_profile_read synchronizes the stream,

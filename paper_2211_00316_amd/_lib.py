@@ -24,8 +24,10 @@ SYMBOLS = (
     "rb_trace_rays", "rb_build_green", "rb_born_forward", "rb_born_adjoint", "rb_residual",
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
-    "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget",
+    "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
+    "rb_set_tuning", "rb_get_tuning",
 )
+RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
 N_STAGES = 12
 
@@ -65,6 +67,16 @@ class _ScanStep(ctypes.Structure):
                 ("d_omega", ctypes.POINTER(ctypes.c_double)), ("data", ctypes.c_void_p),
                 ("tau", ctypes.c_double), ("mode", ctypes.c_int),
                 ("residual_norm", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    """rb_tuning: forward launch configuration of one shape."""
+    _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32), ("prec", ctypes.c_int),
+                ("fwd_tile", ctypes.c_int), ("fwd_splitk", ctypes.c_int32),
+                ("fwd_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RayBornError(RuntimeError):
@@ -118,6 +130,10 @@ def load(path: str = LIB_PATH):
                            ctypes.POINTER(TraceParams), ctypes.c_int, ctypes.c_size_t],
                           ctypes.c_size_t),
         "rb_set_sample_budget": ([P, ctypes.c_size_t], ctypes.c_int),
+        "rb_autotune": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring), ctypes.c_int,
+                         ctypes.POINTER(Tuning)], ctypes.c_int),
+        "rb_set_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
+        "rb_get_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -317,6 +333,22 @@ class Context:
     def set_sample_budget(self, nbytes: int):
         """Bytes of ray samples one tracer launch may hold (rb_set_sample_budget)."""
         self._check(self.lib.rb_set_sample_budget(self._h, int(nbytes)))
+
+    def autotune(self, grid: Grid, ring: Ring, prec: int) -> Tuning:
+        """Time the forward's configurations for this shape and keep the fastest."""
+        t = Tuning()
+        self._check(self.lib.rb_autotune(self._h, ctypes.byref(grid), ctypes.byref(ring),
+                                         int(prec), ctypes.byref(t)))
+        return t
+
+    def set_tuning(self, t: Tuning | dict | None):
+        if isinstance(t, dict):
+            t = Tuning(**{k: t[k] for k, _ in Tuning._fields_ if k in t})
+        self._check(self.lib.rb_set_tuning(self._h, ctypes.byref(t) if t is not None else None))
+
+    def get_tuning(self, n: int, n_mask: int, prec: int) -> Tuning | None:
+        t = Tuning(n, n_mask, prec)
+        return t if self.lib.rb_get_tuning(self._h, ctypes.byref(t)) == RB_OK else None
 
     def lost_nodes(self) -> int:
         """Mask nodes the last binning could not place (diagnostic; 0 normally)."""

@@ -2,10 +2,10 @@
 // orchestration of one frequency step (Section 3 and Section 6.3.2(a) of the paper).
 #include "rb_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
-#include <algorithm>
 #include <vector>
 
 rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq);
@@ -673,6 +673,142 @@ rb_status rb_set_sample_budget(rb_ctx *ctx, size_t bytes) {
     if (!ctx) return RB_EINVAL;
     if (bytes < ((size_t)1 << 20)) return rb_fail(ctx, RB_EINVAL, "sample budget below 1 MiB");
     ctx->sample_budget = bytes;
+    return RB_OK;
+}
+
+// Install t in the context's table (replacing the record of its shape), or remove the record
+// of t's shape with remove = true.
+static rb_status tune_put(rb_ctx *ctx, const rb_tuning &t, bool remove = false) {
+    int i = 0;
+    while (i < ctx->n_tune && !(ctx->tune[i].n == t.n && ctx->tune[i].n_mask == t.n_mask &&
+                                ctx->tune[i].prec == t.prec))
+        ++i;
+    if (remove) {
+        if (i < ctx->n_tune) ctx->tune[i] = ctx->tune[--ctx->n_tune];
+    } else if (i < ctx->n_tune) {
+        ctx->tune[i] = t;
+    } else {
+        if (ctx->n_tune == rb_ctx::kMaxTune)
+            return rb_fail(ctx, RB_EUNSUPPORTED, "at most %d tunings per context",
+                           rb_ctx::kMaxTune);
+        ctx->tune[ctx->n_tune++] = t;
+    }
+    ++ctx->gen;  // cached graphs hold the old launches
+    return RB_OK;
+}
+
+rb_status rb_set_tuning(rb_ctx *ctx, const rb_tuning *t) {
+    if (!ctx) return RB_EINVAL;
+    if (!t) {
+        if (ctx->n_tune) ++ctx->gen;
+        ctx->n_tune = 0;
+        return RB_OK;
+    }
+    if (t->n < 1 || t->n_mask < 1)
+        return rb_fail(ctx, RB_EINVAL, "tuning for n = %d, n_mask = %d", t->n, t->n_mask);
+    if (t->prec != RB_F32 && t->prec != RB_BF16 && t->prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "tuning for an unknown precision %d", (int)t->prec);
+    if (t->fwd_tile != RB_TILE_256x128 && t->fwd_tile != RB_TILE_128x128)
+        return rb_fail(ctx, RB_EINVAL, "unknown forward tile %d", (int)t->fwd_tile);
+    if (t->prec == RB_F32 && t->fwd_tile != RB_TILE_128x128)
+        return rb_fail(ctx, RB_EINVAL, "the FP32 forward has 128 x 128 tiles only");
+    if (t->fwd_splitk < 1 || t->fwd_splitk > 1024)
+        return rb_fail(ctx, RB_EINVAL, "forward K split %d outside 1..1024", t->fwd_splitk);
+    return tune_put(ctx, *t);
+}
+
+rb_status rb_get_tuning(const rb_ctx *ctx, rb_tuning *out) {
+    if (!ctx || !out) return RB_EINVAL;
+    const rb_tuning *t = rb_tuned(ctx, out->n, out->n_mask, out->prec);
+    if (!t) return RB_EINVAL;
+    *out = *t;
+    return RB_OK;
+}
+
+rb_status rb_autotune(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_prec prec,
+                      rb_tuning *out) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "unknown precision %d", (int)prec);
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    StepBufs b;
+    RB_TRY(step_carve(ctx, grid, ring, prec, &b));
+    RB_TRY(rb_launch_tune_fill(ctx, &b.gr, b.svscale));
+    const int N = b.N, nm = b.nm;
+    // candidates: each tile with K splits 8, 16, ..., RB_TUNE_SPLITK_MAX and its built-in one
+    std::vector<rb_tuning> cand;
+    const rb_tile tiles[2] = {RB_TILE_256x128, RB_TILE_128x128};
+    for (int ti = prec == RB_F32 ? 1 : 0; ti < 2; ++ti) {
+        std::vector<int> splits;
+        for (int s = 8; s <= RB_TUNE_SPLITK_MAX; s += 8) splits.push_back(s);
+        splits.push_back(prec == RB_F32 ? rb_forward_default_splitk(N, nm)
+                                        : rb_forward_lp_default_splitk(N, nm, ti == 0,
+                                                                       ctx->n_cu));
+        std::sort(splits.begin(), splits.end());
+        splits.erase(std::unique(splits.begin(), splits.end()), splits.end());
+        for (int sk : splits) {
+            rb_tuning t{};
+            t.n = N;
+            t.n_mask = nm;
+            t.prec = prec;
+            t.fwd_tile = tiles[ti];
+            t.fwd_splitk = sk;
+            cand.push_back(t);
+        }
+    }
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    // the shape's current record, restored if tuning fails
+    const rb_tuning *cur = rb_tuned(ctx, N, nm, prec);
+    const bool had = cur != nullptr;
+    const rb_tuning old = had ? *cur : rb_tuning{};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rb_status st = RB_OK;
+    rb_tuning best{};
+    float best_ms = 3.0e38f;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        st = rb_fail(ctx, RB_EDEVICE, "event creation failed");
+    }
+    auto forward = [&]() {
+        return prec == RB_F32
+                   ? rb_launch_forward(ctx, &b.gr, nullptr, nullptr, b.d_born, b.svscale)
+                   : rb_launch_forward_lp(ctx, &b.gr, nullptr, nullptr, b.d_born, b.svscale);
+    };
+    constexpr int kReps = 3;
+    for (size_t i = 0; i < cand.size() && st == RB_OK; ++i) {
+        st = tune_put(ctx, cand[i]);
+        if (st == RB_OK) st = forward();  // first launch of the configuration, untimed
+        if (st == RB_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) st = RB_EDEVICE;
+        for (int r = 0; r < kReps && st == RB_OK; ++r) st = forward();
+        float ms = 0.f;
+        if (st == RB_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+            (void)hipGetLastError();
+            st = rb_fail(ctx, RB_EDEVICE, "timing the forward failed");
+        }
+        if (st == RB_OK && ms / kReps < best_ms) {
+            best_ms = ms / kReps;
+            best = cand[i];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ctx->prof = prof;
+    if (st != RB_OK) {
+        rb_tuning key{};
+        key.n = N;
+        key.n_mask = nm;
+        key.prec = prec;
+        (void)(had ? tune_put(ctx, old) : tune_put(ctx, key, true));
+        return st;
+    }
+    best.fwd_ms = best_ms;
+    RB_TRY(tune_put(ctx, best));
+    if (out) *out = best;
     return RB_OK;
 }
 

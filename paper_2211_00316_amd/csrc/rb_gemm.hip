@@ -354,15 +354,25 @@ rb_status rb_launch_rowred(rb_ctx *ctx, int n, int n_mask, const float *R, const
     return RB_OK;
 }
 
-size_t rb_forward_ws_bytes(int n, int n_mask) {
+// K split of the FP32 forward: the built-in rule, or `want` (a tuned configuration).
+static int forward_splitk(int n, int n_mask, int want, int *kchunk_out) {
     const int T = (n + FW_B - 1) / FW_B;
     const int tiles = T * (T + 1) / 2;
     const int ksteps = (n_mask + FW_BK - 1) / FW_BK;
-    int splitk = (1024 + tiles - 1) / tiles;
-    splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
+    int splitk = want > 0 ? want : (1024 + tiles - 1) / tiles;
+    splitk = want > 0 ? std::max(1, std::min(splitk, ksteps))
+                      : std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
     const int kchunk = ((ksteps + splitk - 1) / splitk) * FW_BK;
-    splitk = (n_mask + kchunk - 1) / kchunk;
-    return rb_align((size_t)splitk * n * n * sizeof(float2));
+    if (kchunk_out) *kchunk_out = kchunk;
+    return (n_mask + kchunk - 1) / kchunk;
+}
+
+int rb_forward_default_splitk(int n, int n_mask) { return forward_splitk(n, n_mask, 0, nullptr); }
+
+size_t rb_forward_ws_bytes(int n, int n_mask) {
+    const int spk = std::max(rb_forward_default_splitk(n, n_mask),
+                             forward_splitk(n, n_mask, RB_TUNE_SPLITK_MAX, nullptr));
+    return rb_align((size_t)spk * n * n * sizeof(float2));
 }
 
 rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const float *delta,
@@ -370,11 +380,9 @@ rb_status rb_launch_forward(rb_ctx *ctx, const rb_green *gr, const float *w, con
     const int n = gr->n, K = gr->n_mask;
     const int T = (n + FW_B - 1) / FW_B;
     const int tiles = T * (T + 1) / 2;
-    int ksteps = (K + FW_BK - 1) / FW_BK;
-    int splitk = (1024 + tiles - 1) / tiles;
-    splitk = std::max(1, std::min(splitk, std::max(1, ksteps / 4)));
-    int kchunk = ((ksteps + splitk - 1) / splitk) * FW_BK;
-    splitk = (K + kchunk - 1) / kchunk;
+    const rb_tuning *t = rb_tuned(ctx, n, K, RB_F32);
+    int kchunk = 0;
+    const int splitk = forward_splitk(n, K, t ? t->fwd_splitk : 0, &kchunk);
     ctx->ws.used = 0;
     size_t bytes = rb_align((size_t)splitk * n * n * sizeof(float2));
     rb_status st = rb_arena_reserve(ctx, &ctx->ws, bytes);

@@ -78,6 +78,9 @@ struct rb_ctx {
     hipStream_t cap_stream = nullptr; // library stream the sweep is captured on
     hipGraphExec_t gexec = nullptr;   // cached sweep graph
     hipEvent_t ev_join = nullptr;     // orders this context's stream in a batch
+    static constexpr int kMaxTune = 16;
+    rb_tuning tune[kMaxTune] = {};    // forward launch configurations (rb_autotune), by shape
+    int n_tune = 0;
     std::string gkey;                 // the arguments (and gen) it was captured with
 };
 
@@ -219,8 +222,23 @@ rb_status rb_forward_lp_plan(rb_ctx *ctx, const rb_green *gr, const float *gscal
 rb_status rb_launch_forward_lp_group(rb_ctx *ctx, rb_prec prec, const rb_fwd_plan *plans,
                                      int count);
 rb_status rb_forward_lp_reduce(rb_ctx *ctx, const rb_fwd_plan *plan, float *d);
-// Workspace bytes the forward of n transducers over n_mask nodes reserves.
+// Workspace bytes the forward of n transducers over n_mask nodes reserves (at most, over
+// the configurations the autotuner may choose).
 size_t rb_forward_lp_ws_bytes(int n, int n_mask, int n_cu);
+// K splits the autotuner tries besides the built-in choice.
+#define RB_TUNE_SPLITK_MAX 64
+// The context's tuning if it applies to this shape and precision, else NULL.
+inline const rb_tuning *rb_tuned(const rb_ctx *ctx, int n, int n_mask, rb_prec prec) {
+    for (int i = 0; i < ctx->n_tune; ++i)
+        if (ctx->tune[i].n == n && ctx->tune[i].n_mask == n_mask && ctx->tune[i].prec == prec)
+            return &ctx->tune[i];
+    return nullptr;
+}
+// Seeded operand values of the shape of gr (autotuner input) and gscale = {1, 1}.
+rb_status rb_launch_tune_fill(rb_ctx *ctx, const rb_green *gr, float *gscale);
+// Built-in K splits of the forwards (the autotuner's reference candidates).
+int rb_forward_lp_default_splitk(int n, int n_mask, int pipe, int n_cu);
+int rb_forward_default_splitk(int n, int n_mask);
 // scale[0] = 2^(top - e), scale[1] = 1 / scale[0] with 2^(e-1) <= max |x| < 2^e (complex x).
 rb_status rb_launch_range_scale(rb_ctx *ctx, const float *x, size_t count, int top, float *scale);
 int rb_rowred_lp_mblocks(int n);

@@ -984,7 +984,60 @@ __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int s
     d[(size_t)e * n + r] = make_float2(sr * inv, si * inv);
 }
 
+// Seeded operand of the autotuner: magnitude in [0.5, 1), sign and phase from a hash of the
+// index; zeros in the padding past n_mask (as rb_build_green writes).
+template <typename T>
+__global__ void tune_fill_kernel(T *__restrict__ G, int n, int ld, int n_mask) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = 2 * (size_t)n * ld;
+    if (i >= total) return;
+    const int k = (int)(i % (size_t)ld);
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const float v = (0.5f + 0.5f * (float)(h & 0xffff) / 65536.f) * ((h & 0x10000) ? -1.f : 1.f);
+    G[i] = to_lp<T>(k < n_mask ? v : 0.f);
+}
+
+__global__ void tune_fill_f32_kernel(float *__restrict__ G, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    G[i] = (0.5f + 0.5f * (float)(h & 0xffff) / 65536.f) * ((h & 0x10000) ? -1.f : 1.f);
+}
+
+__global__ void unit_scale_kernel(float *s) {
+    s[0] = 1.f;
+    s[1] = 1.f;
+}
+
 }  // namespace
+
+rb_status rb_launch_tune_fill(rb_ctx *ctx, const rb_green *gr, float *gscale) {
+    const int n = gr->n, nm = gr->n_mask;
+    if (gr->prec == RB_F32) {
+        const size_t count = 2 * (size_t)n * nm;
+        hipLaunchKernelGGL(tune_fill_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256),
+                           0, ctx->stream, (float *)gr->G, count);
+    } else {
+        const int ld = rb_lp_pad(nm);
+        const size_t total = 2 * (size_t)n * ld;
+        if (gr->prec == RB_BF16)
+            hipLaunchKernelGGL(tune_fill_kernel<__bf16>, dim3((unsigned)((total + 255) / 256)),
+                               dim3(256), 0, ctx->stream, (__bf16 *)gr->G, n, ld, nm);
+        else
+            hipLaunchKernelGGL(tune_fill_kernel<_Float16>, dim3((unsigned)((total + 255) / 256)),
+                               dim3(256), 0, ctx->stream, (_Float16 *)gr->G, n, ld, nm);
+    }
+    RB_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(unit_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
 
 // Launchers ------------------------------------------------------------------------------
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
@@ -1146,11 +1199,21 @@ struct FwdShape {
 };
 
 // Tiles and K split of the 16-bit forward for n transducers over K nodes (rows ld long).
-// pipe: the pipelined kernel (256 x 128 upper tiles); else the standalone-call kernel.
-FwdShape forward_shape(int n, int K, int ld, bool pipe, int n_cu) {
+// pipe: the pipelined kernel (256 x 128 upper tiles); else the 128 x 128 kernel. splitk > 0
+// overrides the built-in K split (a tuned configuration).
+FwdShape forward_shape(int n, int K, int ld, bool pipe, int n_cu, int splitk = 0) {
     FwdShape f{};
     const int ksteps = pipe ? ld / LR_BK : (K + LF_BK - 1) / LF_BK;
-    if (pipe) {
+    if (splitk > 0) {
+        f.nT = pipe ? (n + LR_BN - 1) / LR_BN : (n + LF_B - 1) / LF_B;
+        f.tiles = 0;
+        if (pipe)
+            for (int tm = 0; tm * (LR_BM / LR_BN) < f.nT; ++tm)
+                f.tiles += f.nT - tm * (LR_BM / LR_BN);
+        else
+            f.tiles = f.nT * (f.nT + 1) / 2;
+        f.splitk = std::max(1, std::min(splitk, ksteps));
+    } else if (pipe) {
         f.nT = (n + LR_BN - 1) / LR_BN;
         f.tiles = 0;
         for (int tm = 0; tm * (LR_BM / LR_BN) < f.nT; ++tm) f.tiles += f.nT - tm * (LR_BM / LR_BN);
@@ -1183,17 +1246,34 @@ bool forward_pipe_fits(int n, int n_mask) {
 }
 }  // namespace
 
+int rb_forward_lp_default_splitk(int n, int n_mask, int pipe, int n_cu) {
+    return forward_shape(n, n_mask, rb_lp_pad(n_mask), pipe && forward_pipe_fits(n, n_mask),
+                         n_cu).splitk;
+}
+
 size_t rb_forward_lp_ws_bytes(int n, int n_mask, int n_cu) {
-    const int ld = rb_lp_pad(n_mask);
-    const FwdShape f = forward_shape(n, n_mask, ld, forward_pipe_fits(n, n_mask), n_cu);
-    return rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8);
+    int spk = RB_TUNE_SPLITK_MAX;
+    spk = std::max(spk, rb_forward_lp_default_splitk(n, n_mask, 1, n_cu));
+    spk = std::max(spk, rb_forward_lp_default_splitk(n, n_mask, 0, n_cu));
+    return rb_align((size_t)spk * n * n * sizeof(float2)) + rb_align(8);
+}
+
+// Tuned configuration of the forward on operands that carry sqrt(v): kernel and K split.
+static void forward_choice(const rb_ctx *ctx, const rb_green *gr, bool *pipe, int *splitk) {
+    *pipe = forward_pipe_fits(gr->n, gr->n_mask);
+    *splitk = 0;
+    if (const rb_tuning *t = rb_tuned(ctx, gr->n, gr->n_mask, gr->prec)) {
+        *pipe = *pipe && t->fwd_tile == RB_TILE_256x128;
+        *splitk = t->fwd_splitk;
+    }
 }
 
 rb_status rb_forward_lp_plan(rb_ctx *ctx, const rb_green *gr, const float *gscale,
                              rb_fwd_plan *pl) {
     const int n = gr->n, K = gr->n_mask, ld = rb_lp_pad(K);
-    pl->pipe = forward_pipe_fits(n, K);
-    const FwdShape f = forward_shape(n, K, ld, pl->pipe, ctx->n_cu);
+    int spk = 0;
+    forward_choice(ctx, gr, &pl->pipe, &spk);
+    const FwdShape f = forward_shape(n, K, ld, pl->pipe, ctx->n_cu, spk);
     ctx->ws.used = 0;
     RB_TRY(rb_arena_reserve(
         ctx, &ctx->ws, rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8)));
@@ -1266,14 +1346,18 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale) {
     const int n = gr->n, K = gr->n_mask, ld = rb_lp_pad(K);
     // Operands that carry sqrt(v) take the pipelined kernel while G's two planes fit one
-    // buffer descriptor; the node weights of the standalone call are folded in on the fly.
-    if (!w && forward_pipe_fits(n, K)) {
+    // buffer descriptor (unless a tuning chose the 128 x 128 tiles); the node weights of the
+    // standalone call are folded in on the fly.
+    bool pipe = false;
+    int spk = 0;
+    if (!w) forward_choice(ctx, gr, &pipe, &spk);
+    if (pipe) {
         rb_fwd_plan pl;
         RB_TRY(rb_forward_lp_plan(ctx, gr, gscale, &pl));
         RB_TRY(rb_launch_forward_lp_group(ctx, gr->prec, &pl, 1));
         return rb_forward_lp_reduce(ctx, &pl, d);
     }
-    const FwdShape f = forward_shape(n, K, ld, false, ctx->n_cu);
+    const FwdShape f = forward_shape(n, K, ld, false, ctx->n_cu, spk);
     ctx->ws.used = 0;
     RB_TRY(rb_arena_reserve(
         ctx, &ctx->ws, rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8)));
