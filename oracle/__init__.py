@@ -14,6 +14,7 @@ Modules:
   medium  - ring and grid geometry, refractive index, box smoothing, cubic B-spline
   trace   - Hamiltonian ray + paraxial system by Heun's method (Algorithm 1, Section 4)
   binning - ray-to-grid triangulation and receiver tables (Section 4.5, Section 6.3)
+  linking - secant ray linking of every emitter-receiver pair (Sections 4 and 6.3)
   green   - ray Green's functions and reciprocal operands (Eqs. 2D_greens, greens-time-reversed)
   born    - Born forward operator, Q=1 adjoint, Hessian-free back-projection (Section 3)
   step    - predicted data, residual, model update, one frequency step, data synthesis
