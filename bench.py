@@ -421,6 +421,9 @@ def main():
                          "(reference for the HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="built-in forward launch configuration instead of the autotuner's")
+    ap.add_argument("--linked", action="store_true",
+                    help="also time the headline form with receiver tables by secant ray "
+                         "linking (rb_set_receiver_linking)")
     ap.add_argument("--serve", action="store_true",
                     help="serving mix of scans of three sizes with continuous batching "
                          "(prints its own JSON line)")
@@ -539,6 +542,15 @@ def main():
         line["image_rel_diff_vs_fp32"] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
         da, db = a - 1500.0, b - 1500.0
         line["update_rel_diff_vs_fp32"] = float(torch.linalg.norm(da - db) / torch.linalg.norm(db))
+    if args.linked:
+        ctx.set_receiver_linking(12, 1e-8)
+        msl, stl, _ = run_form(ctx, w, grid, ring, tp, data, prec_code, args.steps, args.warmup,
+                               args.prec + "-linked", c_start)
+        ctx.set_receiver_linking(0)
+        line["linked_receivers_form"] = {
+            "ms_per_step": round(msl, 2), "value": round(1000.0 / msl, 4),
+            "linking": "secant, at most 12 rays per pair, exit-angle tolerance 1e-8 rad",
+            "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stl.items()}}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

@@ -266,6 +266,18 @@ rb_status rb_frequency_step_batch(const rb_scan_step *steps, int32_t count, rb_p
 size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
                      rb_prec prec, size_t sample_budget);
 
+/* Receiver tables by ray linking (Sections 4 and 6.3: one ray per emitter-receiver pair,
+ * its launch angle adjusted by the secant method until it crosses the ring at the
+ * receiver). With max_iter > 0, every later rb_trace_rays and frequency step of this
+ * context computes rx_T, rx_A and rx_flags from the linked ray's terminal sample instead of
+ * interpolating the fan in exit angle. Per pair: starting points are the two fan rays of the
+ * receiver's bracket; at most max_iter rays are traced, stopping once the exit angle is
+ * within tol radians of the receiver's (0 < tol <= 1e-6); the traced ray closest to the
+ * receiver is taken if within 1e-6 radians, else the pair is invalid. Pairs without a
+ * bracket are invalid as before. max_iter = 0 returns to interpolation (the default).
+ * RB_EINVAL for max_iter outside 0 .. 64 or tol outside (0, 1e-6]. */
+rb_status rb_set_receiver_linking(rb_ctx *ctx, int32_t max_iter, double tol);
+
 /* Bytes of ray samples one tracer launch of this context may hold (default: a quarter of the
  * device memory free at rb_create, at most 48 GiB). Emitters are traced in chunks that fit;
  * a smaller budget means more launches. RB_EINVAL below 1 MiB. */

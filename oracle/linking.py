@@ -166,11 +166,12 @@ def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
 
 
 def link_receivers(ns, grid: Grid, ring: Ring, n_rays: int, ds: float, max_steps: int,
-                   emitters=None, c0: float = C0, **kw) -> Linked:
-    """Linked receiver tables of the listed emitters (all by default)."""
+                   emitters=None, c0: float = C0, fan=None, **kw) -> Linked:
+    """Linked receiver tables of the listed emitters (all by default). fan: the traced fan
+    of these emitters, if at hand (else traced per emitter)."""
     if emitters is None:
         emitters = np.arange(ring.n)
-    out = [link_emitter(ns, grid, ring, n_rays, ds, max_steps, int(e), c0, **kw)
+    out = [link_emitter(ns, grid, ring, n_rays, ds, max_steps, int(e), c0, fan=fan, **kw)
            for e in emitters]
     st = lambda k: np.stack([o[k] for o in out])
     return Linked(valid=st(0), T=st(1), A=st(2), K=st(3), gamma=st(4), miss=st(5),

@@ -20,7 +20,7 @@ import math
 
 import numpy as np
 
-from . import binning, born, green
+from . import binning, born, green, linking
 from .medium import C0, Grid, Ring, box_smooth, refractive_index
 from .trace import trace
 
@@ -35,12 +35,18 @@ class StepSetup:
     c0: float = C0
 
 
-def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None):
-    """Trace on box_window(c0/c) and bin; returns (Tables, n_s)."""
+def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None, link=None):
+    """Trace on box_window(c0/c) and bin; returns (Tables, n_s). link (None, or a dict of
+    oracle.linking options): receiver tables from the linked rays instead of the fan's
+    interpolation in exit angle."""
     ns = box_smooth(refractive_index(c, st.c0), window)
     s = trace(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps, emitters=emitters,
               c0=st.c0)
     tb = binning.tables(s, st.grid, st.ring, st.ds, st.max_steps, emitters=emitters, c0=st.c0)
+    if link is not None:
+        lk = linking.link_receivers(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps,
+                                    emitters=emitters, c0=st.c0, fan=s, **link)
+        tb = dataclasses.replace(tb, rx_valid=lk.valid, rx_T=lk.T, rx_A=lk.A, rx_K=lk.K)
     return tb, ns
 
 
@@ -77,10 +83,10 @@ def update(c: np.ndarray, dm_mask: np.ndarray, tau: float, grid: Grid):
 
 
 def frequency_step(c, st: StepSetup, omegas, d_omegas, data, tau, window=1,
-                   mode="ray_born", isochron_sign=1.0, return_parts=False):
+                   mode="ray_born", isochron_sign=1.0, return_parts=False, link=None):
     """One Hessian-free update of the sound speed c (ny, nx) from the data of the frequency
-    set omegas (data shape (n_omega, N_e, N_r))."""
-    tb, ns = tables_for(c, st, window)
+    set omegas (data shape (n_omega, N_e, N_r)); link as in tables_for."""
+    tb, ns = tables_for(c, st, window, link=link)
     q = st.grid.mask_index()
     cq = c.ravel()[q]
     dm = np.zeros(q.size)

@@ -25,7 +25,7 @@ SYMBOLS = (
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
     "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
-    "rb_set_tuning", "rb_get_tuning",
+    "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking",
 )
 RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH):
                          ctypes.POINTER(Tuning)], ctypes.c_int),
         "rb_set_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
         "rb_get_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
+        "rb_set_receiver_linking": ([P, I32, D], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -329,6 +330,10 @@ class Context:
     def _check(self, st):
         if st != RB_OK:
             raise RayBornError(st, self.lib.rb_last_error(self._h).decode())
+
+    def set_receiver_linking(self, max_iter: int, tol: float = 1e-8):
+        """Receiver tables by secant ray linking (max_iter > 0) or fan interpolation (0)."""
+        self._check(self.lib.rb_set_receiver_linking(self._h, int(max_iter), float(tol)))
 
     def set_sample_budget(self, nbytes: int):
         """Bytes of ray samples one tracer launch may hold (rb_set_sample_budget)."""

@@ -669,6 +669,19 @@ size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_pa
     return step_arena_bytes(N, (int)nm, P, prec) + ws + fixed;
 }
 
+rb_status rb_set_receiver_linking(rb_ctx *ctx, int32_t max_iter, double tol) {
+    if (!ctx) return RB_EINVAL;
+    if (max_iter < 0 || max_iter > 64)
+        return rb_fail(ctx, RB_EINVAL, "linking takes 0 .. 64 rays per pair, not %d", max_iter);
+    if (max_iter > 0 && !(tol > 0.0 && tol <= RB_LINK_ACCEPT))
+        return rb_fail(ctx, RB_EINVAL, "linking tolerance %g outside (0, %g] radians", tol,
+                       RB_LINK_ACCEPT);
+    if (max_iter != ctx->link_iter || (max_iter > 0 && tol != ctx->link_tol)) ++ctx->gen;
+    ctx->link_iter = max_iter;
+    if (max_iter > 0) ctx->link_tol = tol;
+    return RB_OK;
+}
+
 rb_status rb_set_sample_budget(rb_ctx *ctx, size_t bytes) {
     if (!ctx) return RB_EINVAL;
     if (bytes < ((size_t)1 << 20)) return rb_fail(ctx, RB_EINVAL, "sample budget below 1 MiB");

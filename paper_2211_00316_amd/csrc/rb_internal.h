@@ -28,6 +28,10 @@ struct rb_arena {
 // Workgroups (and partial maxima) of a range-scale reduction.
 #define RB_RED_PARTS 512
 
+// Ray linking: a linked ray further from its receiver than this (radians of exit angle) is
+// not accepted.
+#define RB_LINK_ACCEPT 1e-6
+
 // Scans one batch (and one grouped launch) may hold.
 #define RB_GROUP_MAX 16
 
@@ -78,6 +82,10 @@ struct rb_ctx {
     hipStream_t cap_stream = nullptr; // library stream the sweep is captured on
     hipGraphExec_t gexec = nullptr;   // cached sweep graph
     hipEvent_t ev_join = nullptr;     // orders this context's stream in a batch
+    // Receiver tables by secant ray linking (rb_set_receiver_linking): traced rays per pair
+    // (0: interpolation in exit angle over the fan) and the exit-angle tolerance (radians).
+    int link_iter = 0;
+    double link_tol = 1e-8;
     static constexpr int kMaxTune = 16;
     rb_tuning tune[kMaxTune] = {};    // forward launch configurations (rb_autotune), by shape
     int n_tune = 0;

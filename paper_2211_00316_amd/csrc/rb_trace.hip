@@ -214,22 +214,26 @@ struct SampleBufs {
     const double2 *ring;               // [N] transducer positions
 };
 
-// One ray (transducer e0 + el, fan index j); returns the index of its last sample, -1 if it
-// did not reach the ring within max_steps.
-__device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, double R,
-                                         double psi0, int N, int n_rays, int max_steps,
-                                         double ds, double c0, int e0, int el, int j,
-                                         const SampleBufs &sb, int *flag) {
-    int e = e0 + el;
-    const int S = max_steps + 1;
-    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-    const double2 xy = sb.ring[e];
-    // launch angle gamma = psi + pi + delta, |delta| < pi / 2 (Section 4.4 fan)
-    double sd, cd;
-    sincospi(((double)j + 0.5 - 0.5 * (double)n_rays) / (double)n_rays, &sd, &cd);
-    const double cp = xy.x / R, sp = xy.y / R;
-    const double cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
+// Terminal state of a traced ray (linking): travel time, distance from the source, exit
+// angle from psi_e in [0, 2 pi), log-amplitude L = ln A + ln(d) / 2 and caustic count.
+struct RayEnd {
+    double T, d, beta;
+    float L;
+    int K;
+};
 
+// One ray from the transducer at xy (angle psi on the ring) with launch direction (cg, sg):
+// Algorithm 1 with the paraxial system, Definition 1's last step. STORE: the samples of fan
+// ray j of chunk transducer el go to sb; otherwise only the terminal state goes to *end.
+// Returns the index of the last sample, -1 if the ray did not reach the ring within
+// max_steps.
+template <bool STORE>
+__device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, double R,
+                                          double psi, double2 xy, double cg, double sg,
+                                          int n_rays, int max_steps, double ds, double c0,
+                                          int el, int j, const SampleBufs &sb, int *flag,
+                                          RayEnd *end) {
+    const int S = max_steps + 1;
     const double ue = (xy.x - g.x0) * g.idx, ve = (xy.y - g.y0) * g.idx;
     const double uc = -g.x0 * g.idx, vc = -g.y0 * g.idx;  // ring centre
     const double Ru2 = R * R * g.idx * g.idx;              // ring radius squared, node units
@@ -248,8 +252,10 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     double T = 0.0;
 
     size_t o = (size_t)el * S * n_rays + j;
-    sb.pos[o] = make_float2((float)r.u, (float)r.v);
-    sb.fld[o] = make_float4(0.0f, 0.0f, (float)cg, (float)sg);
+    if constexpr (STORE) {
+        sb.pos[o] = make_float2((float)r.u, (float)r.v);
+        sb.fld[o] = make_float4(0.0f, 0.0f, (float)cg, (float)sg);
+    }
     int kfirst = S;  // K is monotone along a ray: zero before kfirst, stored from it on
 
     float J_prev = 0.0f;
@@ -297,32 +303,62 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
         float dT = (float)(T - d * ic0);
         ++i;
         o += n_rays;
-        sb.pos[o] = make_float2((float)r.u, (float)r.v);
-        sb.fld[o] = make_float4(dT, L, tx, ty);
-        if (K > 0) {
-            sb.K[o] = (uint8_t)min(K, 255);
-            if (kfirst == S) kfirst = i;
+        if constexpr (STORE) {
+            sb.pos[o] = make_float2((float)r.u, (float)r.v);
+            sb.fld[o] = make_float4(dT, L, tx, ty);
+            if (K > 0) {
+                sb.K[o] = (uint8_t)min(K, 255);
+                if (kfirst == S) kfirst = i;
+            }
         }
         J_prev = J;
         n_cur = n_new;
         if (last) {
             M = i;
-            size_t x = (size_t)el * n_rays + j;
-            sb.ex_dT[x] = dT;
-            sb.ex_L[x] = L;
-            sb.ex_K[x] = (uint8_t)min(K, 255);
+            if constexpr (STORE) {
+                size_t x = (size_t)el * n_rays + j;
+                sb.ex_dT[x] = dT;
+                sb.ex_L[x] = L;
+                sb.ex_K[x] = (uint8_t)min(K, 255);
+            } else {
+                end->T = T;
+                end->d = d;
+                end->L = L;
+                end->K = K;
+            }
             break;
         }
     }
     if (M >= 0) {
         double beta = atan2(r.v - vc, r.u - uc) - psi;
-        sb.ex_beta[(size_t)el * n_rays + j] = beta - RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
+        beta -= RB_TWO_PI * floor(beta * (1.0 / RB_TWO_PI));
+        if constexpr (STORE) sb.ex_beta[(size_t)el * n_rays + j] = beta;
+        else end->beta = beta;
     }
-    sb.M[(size_t)el * n_rays + j] = M;
-    sb.kfirst[(size_t)el * n_rays + j] = kfirst;
-    if (M < 0) atomicOr(flag, 1);
-    if (K > 0) atomicOr(sb.folded + el, 1);
+    if constexpr (STORE) {
+        sb.M[(size_t)el * n_rays + j] = M;
+        sb.kfirst[(size_t)el * n_rays + j] = kfirst;
+        if (M < 0) atomicOr(flag, 1);
+        if (K > 0) atomicOr(sb.folded + el, 1);
+    }
     return M;
+}
+
+// Fan ray j of transducer e0 + el (Section 4.4: launch angle gamma = psi + pi + delta,
+// |delta| < pi / 2), samples to sb.
+__device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, double R,
+                                         double psi0, int N, int n_rays, int max_steps,
+                                         double ds, double c0, int e0, int el, int j,
+                                         const SampleBufs &sb, int *flag) {
+    const int e = e0 + el;
+    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const double2 xy = sb.ring[e];
+    double sd, cd;
+    sincospi(((double)j + 0.5 - 0.5 * (double)n_rays) / (double)n_rays, &sd, &cd);
+    const double cp = xy.x / R, sp = xy.y / R;
+    const double cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
+    return trace_core<true>(m, g, R, psi, xy, cg, sg, n_rays, max_steps, ds, c0, el, j, sb,
+                            flag, nullptr);
 }
 
 // One lane per ray; a wavefront holds 64 neighbouring rays of one transducer, so the
@@ -888,9 +924,11 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
 // angles and interpolate dT and L linearly; the smallest travel time wins (lowest ray on a
 // tie); unbracketed pairs are invalid. When every ray is valid and the exit angles increase
 // strictly with the ray index, the bracket of a receiver is unique and found by bisection.
+// rx_j (nullable, [E][N]): the fan ray j of the chosen bracket (j, j + 1) of each receiver,
+// -1 if none (the starting points of ray linking).
 __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays, int e0, double R,
                                                        double psi0, int N, double c0,
-                                                       rb_tables tb) {
+                                                       rb_tables tb, int32_t *rx_j) {
     extern __shared__ __attribute__((aligned(16))) char smem[];  // 64-bit LDS atomics below
     double *beta = reinterpret_cast<double *>(smem);
     float *dTs = reinterpret_cast<float *>(beta + n_rays);
@@ -965,13 +1003,14 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
         double br = RB_TWO_PI * (double)rel / (double)N;
         bool found = false;
         double best = 0.0, bestL = 0.0;
-        int bestK = 0;
+        int bestK = 0, bestJ = -1;
         auto take = [&](int j) {
             double b0 = beta[j], b1 = beta[j + 1];
             double lam = (br - b0) / (b1 - b0);
             double dT = (1.0 - lam) * (double)dTs[j] + lam * (double)dTs[j + 1];
             if (!found || dT < best) {
                 found = true;
+                bestJ = j;
                 best = dT;
                 bestL = (1.0 - lam) * (double)Ls[j] + lam * (double)Ls[j + 1];
                 bestK = max((int)Ks[j], (int)Ks[j + 1]);
@@ -1007,6 +1046,76 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
             tb.rx_A[out] = 0.0f;
             tb.rx_flags[out] = 0;
         }
+        if (rx_j) rx_j[(size_t)el * N + r] = found ? bestJ : -1;
+    }
+}
+
+// Ray linking (Sections 4 and 6.3): one lane per (chunk transducer el, receiver r). The
+// launch angle is adjusted by a safeguarded secant on f(gamma) = beta(gamma) - beta_r, from
+// the two fan rays of the receiver's bracket (their exit angles are known): the secant
+// point of the last two iterates when it lies inside the bracket, else the bracket's
+// midpoint; each traced ray keeps a sign change of f inside the bracket. Stops at |f| <=
+// tol or after max_iter rays; the traced ray closest to its receiver gives the receiver
+// tables if |f| <= accept, else the pair is invalid. Pairs without a bracket keep the
+// receiver kernel's invalid entry.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) link_kernel(SplineMap m, GridP g, double R, double psi0,
+                                                   int N, int n_rays, int max_steps, double ds,
+                                                   double c0, int e0, int E, SampleBufs sb,
+                                                   const int32_t *__restrict__ rx_j,
+                                                   int max_iter, double tol, double accept,
+                                                   rb_tables tb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * N) return;
+    const int el = t / N, r = t - el * N, e = e0 + el;
+    const int j = rx_j[t];
+    if (j < 0) return;
+    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const double br = RB_TWO_PI * (double)(((r - e) % N + N) % N) / (double)N;
+    const double2 xy = sb.ring[e];
+    const double dgam = RB_PI / (double)n_rays;
+    double lo = psi + RB_PI + ((double)j + 0.5 - 0.5 * (double)n_rays) * dgam;
+    double hi = lo + dgam;
+    const size_t x = (size_t)el * n_rays + j;
+    double flo = sb.ex_beta[x] - br, fhi = sb.ex_beta[x + 1] - br;
+    double xp = lo, fp = flo, xc = hi, fc = fhi;
+    double best_f = 1e300;
+    RayEnd best{};
+    for (int it = 0; it < max_iter && best_f > tol; ++it) {
+        double cand = xc - fc * (xc - xp) / (fc - fp);
+        const double a = fmin(lo, hi), b = fmax(lo, hi);
+        if (!(cand > a && cand < b)) cand = 0.5 * (lo + hi);  // also catches NaN
+        double sgm, cgm;
+        sincos(cand, &sgm, &cgm);
+        RayEnd end;
+        if (trace_core<false>(m, g, R, psi, xy, cgm, sgm, n_rays, max_steps, ds, c0, el, 0, sb,
+                              nullptr, &end) < 0)
+            break;  // the ray did not reach the ring: the pair ends here
+        const double f = end.beta - br;
+        if (fabs(f) < best_f) {
+            best_f = fabs(f);
+            best = end;
+        }
+        if ((f < 0.0) == (flo < 0.0)) {
+            lo = cand;
+            flo = f;
+        } else {
+            hi = cand;
+            fhi = f;
+        }
+        xp = xc;
+        fp = fc;
+        xc = cand;
+        fc = f;
+    }
+    const size_t out = (size_t)e * N + r;
+    if (best_f <= accept) {
+        tb.rx_T[out] = best.T;
+        tb.rx_A[out] = (float)(exp((double)best.L) / sqrt(best.d));
+        tb.rx_flags[out] = (uint8_t)(0x80 | (best.K & 3));
+    } else {
+        tb.rx_T[out] = 0.0;
+        tb.rx_A[out] = 0.0f;
+        tb.rx_flags[out] = 0;
     }
 }
 
@@ -1100,7 +1209,8 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)C * tiles * sizeof(int2)) +
            rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
            rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
-           rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float));
+           rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
+           rb_align((size_t)C * r->n * sizeof(int32_t));
 }
 
 size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
@@ -1144,6 +1254,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     uint8_t *marks = rb_carve<uint8_t>(&ctx->ws, (size_t)C * mtiles + 4);  // whole words zeroed
     const int nxp = g->nx + 2 * MPAD, nyp = g->ny + 2 * MPAD;
     float *padded = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
+    int32_t *rx_j = rb_carve<int32_t>(&ctx->ws, (size_t)C * N);
     SplineMap smap{padded, g->nx, g->ny, nxp, (float)(1.0 / g->dx)};
 
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
@@ -1222,8 +1333,17 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)smem));
         hipLaunchKernelGGL(receiver_kernel, dim3(E), dim3(256), smem, ctx->stream, sb, nr, e0,
-                           r->radius, r->psi0, N, tp->c0, *out);
+                           r->radius, r->psi0, N, tp->c0, *out,
+                           ctx->link_iter > 0 ? rx_j : nullptr);
         RB_CHECK_LAUNCH(ctx);
+        if (ctx->link_iter > 0) {
+            const long lanes = (long)E * N;
+            hipLaunchKernelGGL(link_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0,
+                               ctx->stream, smap, gp, r->radius, r->psi0, N, nr, tp->max_steps,
+                               tp->ds, tp->c0, e0, E, sb, rx_j, ctx->link_iter, ctx->link_tol,
+                               RB_LINK_ACCEPT, *out);
+            RB_CHECK_LAUNCH(ctx);
+        }
         rb_prof_end(ctx);
     }
     if (ctx->deferred) return RB_OK;  // read back at the end of the sweep
