@@ -44,40 +44,27 @@ constexpr int MPAD = 3;
 // of control points near 1 would lose most of the FP32 digits of the Hessian (about 1e-4
 // per node^2) to cancellation. Near a focus the amplitude is sensitive to exactly those
 // digits.
+// The cubic B-spline of the map n - 1 (Section 5: the map's samples as control points),
+// stored per cell as the bicubic in the cell's local coordinates (tx, ty) in [0, 1):
+// coef[cell][j] = (a_j0, a_j1, a_j2, a_j3) with value sum_{j,i} a_ji tx^i ty^j. Cells
+// (iu, iv), iu in [-2, nx], iv in [-2, ny], have index (iv + 2) (nx + 3) + iu + 2.
 struct SplineMap {
-    const float *f;  // [ny + 2 MPAD][nx + 2 MPAD] of n - 1
-    int nx, ny, nxp;
-    float ih;        // 1 / dx
+    const float4 *coef;  // [(ny + 3) (nx + 3)][4]
+    int nx, ny, ncx;     // ncx = nx + 3 cells per row
+    float ih;            // 1 / dx
 };
 
 struct Spline {
     float v, gx, gy, hxx, hxy, hyy;
 };
 
-// Uniform cubic B-spline weights of control points iu-1 .. iu+2 at offset t in [0, 1).
-__device__ __forceinline__ void bspline_basis(float t, float b[4], float d[4], float dd[4]) {
-    float t2 = t * t, t3 = t2 * t, s = 1.0f - t;
-    b[0] = s * s * s * (1.0f / 6.0f);
-    b[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
-    b[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
-    b[3] = t3 * (1.0f / 6.0f);
-    d[0] = -0.5f * s * s;
-    d[1] = 0.5f * (3.0f * t2 - 4.0f * t);
-    d[2] = 0.5f * (-3.0f * t2 + 2.0f * t + 1.0f);
-    d[3] = 0.5f * t2;
-    dd[0] = s;
-    dd[1] = 3.0f * t - 2.0f;
-    dd[2] = 1.0f - 3.0f * t;
-    dd[3] = t;
-}
-
 // Four consecutive floats of a row, 4-byte aligned: one 16-byte load.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef int i2u __attribute__((ext_vector_type(2), aligned(4)));
 
-// The 4 x 4 control points of the cell a lane evaluated last. A step is shorter than a
-// cell, so consecutive evaluations (predictor, corrector, next predictor) mostly fall in the
-// same cell and reuse them instead of loading again.
+// The 16 coefficients of the cell a lane evaluated last. A step is shorter than a cell, so
+// consecutive evaluations (predictor, corrector, next predictor) mostly fall in the same
+// cell and reuse them instead of loading again.
 struct Patch {
     float f[16];
     int cell = -1;  // (iv + 2) (nx + 3) + iu + 2 of the stored cell, -1 for none
@@ -87,16 +74,14 @@ struct Patch {
 __device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, double v,
                                               Patch &pc) {
     double fu = floor(u), fv = floor(v);
-    float bu[4], du[4], ddu[4], bv[4], dv[4], ddv[4];
-    bspline_basis((float)(u - fu), bu, du, ddu);
-    bspline_basis((float)(v - fv), bv, dv, ddv);
+    const float tx = (float)(u - fu), ty = (float)(v - fv);
     int iu = min(max((int)fu, -2), m.nx), iv = min(max((int)fv, -2), m.ny);
-    const int cell = (iv + 2) * (m.nx + 3) + (iu + 2);
+    const int cell = (iv + 2) * m.ncx + (iu + 2);
     if (cell != pc.cell) {
-        const float *p = m.f + ((iv - 1 + MPAD) * m.nxp + (iu - 1 + MPAD));
+        const float4 *p = m.coef + (size_t)cell * 4;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            f4u q = *reinterpret_cast<const f4u *>(p + b * m.nxp);
+            const float4 q = p[b];
             pc.f[4 * b] = q.x;
             pc.f[4 * b + 1] = q.y;
             pc.f[4 * b + 2] = q.z;
@@ -104,24 +89,25 @@ __device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, doub
         }
         pc.cell = cell;
     }
-    float s_v = 0, s_gx = 0, s_gy = 0, s_xx = 0, s_xy = 0, s_yy = 0;
+    // Row polynomials Q_j(tx) = sum_i a_ji tx^i and their first two tx-derivatives (Horner),
+    // then the same in ty: value, gradient and Hessian of the bicubic.
+    float q0[4], q1[4], q2[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const float *fr = pc.f + 4 * b;
-        float r0 = 0, r1 = 0, r2 = 0;  // row sums with B, B', B''
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            r0 = fmaf(bu[a], fr[a], r0);
-            r1 = fmaf(du[a], fr[a], r1);
-            r2 = fmaf(ddu[a], fr[a], r2);
-        }
-        s_v = fmaf(bv[b], r0, s_v);
-        s_gx = fmaf(bv[b], r1, s_gx);
-        s_gy = fmaf(dv[b], r0, s_gy);
-        s_xx = fmaf(bv[b], r2, s_xx);
-        s_xy = fmaf(dv[b], r1, s_xy);
-        s_yy = fmaf(ddv[b], r0, s_yy);
+    for (int j = 0; j < 4; ++j) {
+        const float a0 = pc.f[4 * j], a1 = pc.f[4 * j + 1], a2 = pc.f[4 * j + 2];
+        const float a3 = pc.f[4 * j + 3];
+        const float b3 = 3.0f * a3, b2 = a2 + a2;
+        q0[j] = fmaf(fmaf(fmaf(a3, tx, a2), tx, a1), tx, a0);
+        q1[j] = fmaf(fmaf(b3, tx, b2), tx, a1);
+        q2[j] = fmaf(b3 + b3, tx, b2);
     }
+    const float s_v = fmaf(fmaf(fmaf(q0[3], ty, q0[2]), ty, q0[1]), ty, q0[0]);
+    const float s_gx = fmaf(fmaf(fmaf(q1[3], ty, q1[2]), ty, q1[1]), ty, q1[0]);
+    const float s_xx = fmaf(fmaf(fmaf(q2[3], ty, q2[2]), ty, q2[1]), ty, q2[0]);
+    const float c3 = 3.0f * q0[3], c2 = q0[2] + q0[2];
+    const float s_gy = fmaf(fmaf(c3, ty, c2), ty, q0[1]);
+    const float s_xy = fmaf(fmaf(3.0f * q1[3], ty, q1[2] + q1[2]), ty, q1[1]);
+    const float s_yy = fmaf(c3 + c3, ty, c2);
     float ih = m.ih, ih2 = ih * ih;
     return Spline{s_v + 1.0f, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
 }
@@ -396,6 +382,42 @@ __global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float *__r
     if (i >= nxp) return;
     int si = min(max(i - MPAD, 0), nx - 1), sj = min(max(j - MPAD, 0), ny - 1);
     out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si] - 1.0f;
+}
+
+// Monomial coefficients of the uniform cubic B-spline on cell (iu, iv) = (ci - 2, cj - 2),
+// whose control points are the padded samples iu - 1 .. iu + 2, iv - 1 .. iv + 2. The
+// weights of control point k at offset t are sum_p B[k][p] t^p with 6 B = [[1, -3, 3, -1],
+// [4, 0, -6, 3], [1, 3, 3, -3], [0, 0, 0, 1]]; a = B^T C B (rows: powers of ty, columns:
+// powers of tx), formed in FP64 from the FP32 samples and rounded once.
+__global__ void spline_coef(const float *__restrict__ padded, int nx, int ny,
+                            float4 *__restrict__ coef) {
+    const int nxp = nx + 2 * MPAD, ncx = nx + 3;
+    const int ci = blockIdx.x * blockDim.x + threadIdx.x, cj = blockIdx.y;
+    if (ci >= ncx) return;
+    const int iu = ci - 2, iv = cj - 2;
+    constexpr double B[4][4] = {{1.0, -3.0, 3.0, -1.0},
+                                {4.0, 0.0, -6.0, 3.0},
+                                {1.0, 3.0, 3.0, -3.0},
+                                {0.0, 0.0, 0.0, 1.0}};
+    double D[4][4];  // D[b][p] = sum_k C[b][k] B[k][p] / 6 (row b of control points)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float *row = padded + (size_t)(iv - 1 + b + MPAD) * nxp + (iu - 1 + MPAD);
+        const double c0 = row[0], c1 = row[1], c2 = row[2], c3 = row[3];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            D[b][p] = (c0 * B[0][p] + c1 * B[1][p] + c2 * B[2][p] + c3 * B[3][p]) * (1.0 / 6.0);
+    }
+    float4 *out = coef + ((size_t)cj * ncx + ci) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // power of ty
+        double a[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            a[p] = (B[0][q] * D[0][p] + B[1][q] * D[1][p] + B[2][q] * D[2][p] +
+                    B[3][q] * D[3][p]) * (1.0 / 6.0);
+        out[q] = make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]);
+    }
 }
 
 __device__ __forceinline__ unsigned long long ordered_bits64(double f) {
@@ -1210,6 +1232,7 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
            rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
            rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
+           rb_align((size_t)(g->nx + 3) * (g->ny + 3) * 4 * sizeof(float4)) +
            rb_align((size_t)C * r->n * sizeof(int32_t));
 }
 
@@ -1255,7 +1278,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     const int nxp = g->nx + 2 * MPAD, nyp = g->ny + 2 * MPAD;
     float *padded = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
     int32_t *rx_j = rb_carve<int32_t>(&ctx->ws, (size_t)C * N);
-    SplineMap smap{padded, g->nx, g->ny, nxp, (float)(1.0 / g->dx)};
+    float4 *coef = rb_carve<float4>(&ctx->ws, (size_t)(g->nx + 3) * (g->ny + 3) * 4);
+    SplineMap smap{coef, g->nx, g->ny, g->nx + 3, (float)(1.0 / g->dx)};
 
     GridP gp{g->nx, g->ny, g->dx, g->x0, g->y0, 1.0 / g->dx};
     // counters of this trace; the error bits start clear unless a sweep collects them
@@ -1268,6 +1292,9 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     RB_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, n_s,
                        g->nx, g->ny, padded);
+    RB_CHECK_LAUNCH(ctx);
+    hipLaunchKernelGGL(spline_coef, dim3((g->nx + 3 + 255) / 256, g->ny + 3), dim3(256), 0,
+                       ctx->stream, padded, g->nx, g->ny, coef);
     RB_CHECK_LAUNCH(ctx);
     for (int e0 = 0; e0 < N; e0 += C) {
         int E = std::min(C, N - e0);
