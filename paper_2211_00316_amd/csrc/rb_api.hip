@@ -161,8 +161,8 @@ rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
     }
     ctx->tile_i0 = imin;
     ctx->tile_j0 = jmin;
-    ctx->tiles_x = (imax - imin + 32) / 32;
-    ctx->tiles_y = (jmax - jmin + 8) / 8;
+    ctx->tiles_x = (imax - imin + RB_WALK_TX) / RB_WALK_TX;
+    ctx->tiles_y = (jmax - jmin + RB_WALK_TY) / RB_WALK_TY;
     ctx->grid = *g;
     ctx->n_mask = n;
     ctx->have_grid = true;
@@ -653,7 +653,8 @@ size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_pa
         jmin = std::min(jmin, j);
         jmax = std::max(jmax, j);
     }
-    const size_t tiles = (size_t)((imax - imin + 32) / 32) * ((jmax - jmin + 8) / 8);
+    const size_t tiles = (size_t)((imax - imin + RB_WALK_TX) / RB_WALK_TX) *
+                         ((jmax - jmin + RB_WALK_TY) / RB_WALK_TY);
     const size_t P = (size_t)grid->nx * grid->ny;
     const int N = ring->n;
     int n_cu = 256;

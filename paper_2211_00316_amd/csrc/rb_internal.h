@@ -32,6 +32,10 @@ struct rb_arena {
 // not accepted.
 #define RB_LINK_ACCEPT 1e-6
 
+// Node tile of one binning-walk workgroup (the walk's starting offsets are per tile).
+#define RB_WALK_TX 16
+#define RB_WALK_TY 16
+
 // Scans one batch (and one grouped launch) may hold.
 #define RB_GROUP_MAX 16
 
@@ -51,7 +55,7 @@ struct rb_ctx {
     int64_t n_mask = 0;
     int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
     int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
-    int tile_i0 = 0, tile_j0 = 0;     // 32 x 8 node tiles covering the mask's bounding box
+    int tile_i0 = 0, tile_j0 = 0;     // walk tiles (RB_WALK_TX x RB_WALK_TY nodes) over the mask bbox
     int tiles_x = 0, tiles_y = 0;
 
     // per-stage event timing (rb_profile_enable / rb_profile_read)
@@ -180,7 +184,7 @@ rb_status rb_launch_backproject_finish(rb_ctx *ctx, int n_mask, int mblocks, con
 int rb_rowred_mblocks(int n);
 // Workspace bytes the FP32 forward of n transducers over n_mask nodes reserves.
 size_t rb_forward_ws_bytes(int n, int n_mask);
-// Workspace bytes of one tracer launch under a sample budget (tiles: 32 x 8 walk tiles).
+// Workspace bytes of one tracer launch under a sample budget (tiles: walk tiles).
 size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
                          int64_t n_mask, size_t tiles, size_t sample_budget);
 

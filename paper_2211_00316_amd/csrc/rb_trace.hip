@@ -533,7 +533,7 @@ constexpr int LOCATE_MAX_IT = 96;
 // In a fan that folds, inverted triangles mislead the walk's edge tests; a walk that does not
 // settle soon is given up and its node left to the rasterisation.
 constexpr int LOCATE_MAX_IT_FOLD = 16;
-constexpr int LTX = 32, LTY = 8;  // node tile of one locate workgroup
+constexpr int LTX = RB_WALK_TX, LTY = RB_WALK_TY;  // node tile of one locate workgroup
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
@@ -608,9 +608,23 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
 
 // Straight-ray guess of the quad holding the point at (ddx, ddy) from the source: launch
 // angle and arc length of the straight ray.
+// Polar angle of (x, y) in [-pi, pi] to about 1e-4 rad: octant reduction and an odd
+// polynomial for atan on [0, 1] (least-squares fit). Only the walk's starting quad depends on
+// it (a tenth of a ray spacing at 1024 rays), not where a walk ends.
+__device__ __forceinline__ float guess_atan2(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(fmaxf(ax, ay), 1e-30f));
+    const float t2 = t * t;
+    float a = t * fmaf(fmaf(fmaf(-0.03913415f, t2, 0.14661529f), t2, -0.32143048f), t2,
+                       0.99926772f);
+    if (ay > ax) a = 1.57079633f - a;
+    if (x < 0.f) a = 3.14159265f - a;
+    return y < 0.f ? -a : a;
+}
+
 __device__ __forceinline__ void straight_guess(double ddx, double ddy, double d, double psi,
                                                double ds, int n_rays, int S, int &j, int &i) {
-    float rel = atan2f((float)ddy, (float)ddx) - (float)(psi + RB_PI);
+    float rel = guess_atan2((float)ddy, (float)ddx) - (float)(psi + RB_PI);
     rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
     j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
     j = min(max(j, 0), n_rays - 2);
@@ -667,7 +681,7 @@ __device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int el, i
     return K;
 }
 
-// One lane per (transducer, mask node); a workgroup covers a 32 x 8 tile of grid nodes of
+// One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
 // In a fan that folds, the walk's triangle is one candidate of the smallest-key rule: its
 // record is written and its key seeds keys[] (changed[] cleared); the rasterisation of the
@@ -1218,7 +1232,7 @@ static size_t mtiles_of(const rb_grid *g) {
     return mtx * mty;
 }
 
-// Workspace of one tracer launch of C emitters (`tiles` 32 x 8 walk tiles over the mask).
+// Workspace of one tracer launch of C emitters (`tiles` walk tiles over the mask).
 static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
                           int64_t n_mask, int C, size_t tiles) {
     const size_t nr = tp->n_rays, S = (size_t)tp->max_steps + 1;
