@@ -622,13 +622,15 @@ __device__ __forceinline__ float guess_atan2(float y, float x) {
     return y < 0.f ? -a : a;
 }
 
-__device__ __forceinline__ void straight_guess(double ddx, double ddy, double d, double psi,
-                                               double ds, int n_rays, int S, int &j, int &i) {
-    float rel = guess_atan2((float)ddy, (float)ddx) - (float)(psi + RB_PI);
+// Fan ray and step of the straight ray from the transducer (angle psi on the ring, psi_pi =
+// psi + pi in FP32) to the node at offset (ddx, ddy), distance d; ids = 1 / ds. A guess only.
+__device__ __forceinline__ void straight_guess(double ddx, double ddy, double d, float psi_pi,
+                                               double ids, int n_rays, int S, int &j, int &i) {
+    float rel = guess_atan2((float)ddy, (float)ddx) - psi_pi;
     rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
     j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
     j = min(max(j, 0), n_rays - 2);
-    i = min(max((int)(d / ds), 1), S - 2);
+    i = min(max((int)(d * ids), 1), S - 2);
 }
 
 // Pre-pass: one lane per (transducer, node tile) walks the tile centre from its straight-ray
@@ -637,6 +639,7 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
                                                           int e0, GridP g, double psi0, int N,
                                                           double ds, int tile_i0, int tile_j0,
                                                           int tiles_x, int tiles_y,
+                                                          float dpsi, double ids,
                                                           int2 *__restrict__ off) {
     const int ntiles = tiles_x * tiles_y;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -646,14 +649,14 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
     {
         const int ti = t % tiles_x, tj = t / tiles_x;
         const int e = e0 + el;
-        const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+        const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;
         const double2 xy = sb.ring[e];
         double cu = tile_i0 + ti * LTX + 0.5 * (LTX - 1);
         double cv = tile_j0 + tj * LTY + 0.5 * (LTY - 1);
         double ddx = g.x0 + cu * g.dx - xy.x, ddy = g.y0 + cv * g.dx - xy.y;
         double d = sqrt(ddx * ddx + ddy * ddy);
         int j, i, jw, iw;
-        straight_guess(ddx, ddy, d, psi, ds, n_rays, S, jw, iw);
+        straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, jw, iw);
         j = jw;
         i = iw;
         size_t vb[3];
@@ -699,7 +702,8 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                                                      unsigned long long *__restrict__ keys,
                                                      uint8_t *__restrict__ changed,
                                                      uint8_t *__restrict__ marks, int mtx,
-                                                     int mtiles, int *lost) {
+                                                     int mtiles, int *lost, float dpsi,
+                                                     double ids) {
     const int ntiles = tiles_x * tiles_y;
     const int G = LOCATE_GROUP_ROWS * tiles_x;
     const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
@@ -716,7 +720,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const int e = e0 + el;
     const size_t out = (size_t)e * n_mask + q;
     const size_t kq = (size_t)el * n_mask + q;
-    const double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
+    const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;  // the walk's guess only
     const double2 xy = sb.ring[e];
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double ddx = px - xy.x, ddy = py - xy.y;
@@ -733,7 +737,7 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
         return;
     }
     int j, i;
-    straight_guess(ddx, ddy, d, psi, ds, n_rays, S, j, i);
+    straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, j, i);
     const int2 o = off[(size_t)el * ntiles + t];
     j = min(max(j + o.x, 0), n_rays - 2);
     i = min(max(i + o.y, 1), S - 2);
@@ -1340,7 +1344,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         int ntiles = ctx->tiles_x * ctx->tiles_y;
         hipLaunchKernelGGL(tile_offset_kernel, dim3((E * ntiles + 255) / 256), dim3(256), 0,
                            ctx->stream, sb, nr, S, E, e0, gp, r->psi0, N, tp->ds, ctx->tile_i0,
-                           ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, toff);
+                           ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, (float)(RB_TWO_PI / N),
+                           1.0 / tp->ds, toff);
         RB_CHECK_LAUNCH(ctx);
         const long G = (long)LOCATE_GROUP_ROWS * ctx->tiles_x;
         const long groups = ((long)E * ntiles + G - 1) / G;
@@ -1349,7 +1354,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
-                           toff, to, keys, changed, marks, mtx, mtiles, lost);
+                           toff, to, keys, changed, marks, mtx, mtiles, lost,
+                           (float)(RB_TWO_PI / N), 1.0 / tp->ds);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation against the walk's keys, and resolve of
