@@ -490,6 +490,26 @@ __device__ __forceinline__ void bbox_tiles(const float *tu, const float *tv, int
 
 // Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`;
 // K: the largest caustic count of the three vertices. Returns the interpolated dT.
+// Polar angle of (x, y) in [-pi, pi] within about 3e-7 rad (atan2f: 2 ulp): octant
+// reduction and an odd polynomial of degree 15 for atan on [0, 1] (least-squares fit).
+__device__ __forceinline__ float ray_atan2(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(fmaxf(ax, ay), 1e-30f));
+    const float t2 = t * t;
+    float p = -0.00405453f;
+    p = fmaf(p, t2, 0.02186283f);
+    p = fmaf(p, t2, -0.05591219f);
+    p = fmaf(p, t2, 0.09642192f);
+    p = fmaf(p, t2, -0.1390863f);
+    p = fmaf(p, t2, 0.19946567f);
+    p = fmaf(p, t2, -0.33329861f);
+    p = fmaf(p, t2, 0.99999934f);
+    float a = t * p;
+    if (ay > ax) a = 1.57079633f - a;
+    if (x < 0.f) a = 3.14159265f - a;
+    return y < 0.f ? -a : a;
+}
+
 __device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
                                              const float lam[3], int K, double d, double c0,
                                              const TableOut &to, size_t out) {
@@ -500,7 +520,7 @@ __device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t 
     const float ty = tri_dT(lam[0], lam[1], lam[2], f0.w, f1.w, f2.w);
     const float A = __expf(L) * rsqrtf((float)d);
     if (to.rec) {
-        to.rec[out] = make_float4(dT, A, atan2f(ty, tx), __int_as_float(0x80 | (K & 3)));
+        to.rec[out] = make_float4(dT, A, ray_atan2(ty, tx), __int_as_float(0x80 | (K & 3)));
         return dT;
     }
     const rb_tables &tb = to.tb;
