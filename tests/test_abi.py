@@ -65,3 +65,20 @@ def test_context_without_gpu_fails_loudly():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         _lib.Context()
+
+
+def test_step_bytes_is_host_arithmetic(lib):
+    # rb_step_bytes needs no GPU: positive for a valid geometry, growing with the tracer's
+    # sample budget until one launch holds every transducer, 0 for an invalid geometry.
+    from paper_2211_00316_amd import _lib
+
+    g = _lib.Grid(128, 128, 0.8e-3, -50.8e-3, -50.8e-3, 0.045)
+    r = _lib.Ring(64, 0.05, 0.0)
+    tp = _lib.TraceParams(360, 628, 0.2e-3, 1500.0)
+    small = _lib.step_bytes(g, r, tp, _lib.RB_BF16, 1 << 24)
+    big = _lib.step_bytes(g, r, tp, _lib.RB_BF16, 1 << 34)
+    huge = _lib.step_bytes(g, r, tp, _lib.RB_BF16, 1 << 40)
+    assert 0 < small < big == huge
+    assert _lib.step_bytes(g, r, tp, _lib.RB_F32, 1 << 34) > big   # FP32 operands are wider
+    bad = _lib.Grid(0, 128, 0.8e-3, -50.8e-3, -50.8e-3, 0.045)
+    assert _lib.step_bytes(bad, r, tp, _lib.RB_BF16, 1 << 30) == 0
