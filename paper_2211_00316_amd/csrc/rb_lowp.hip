@@ -417,8 +417,9 @@ __global__ void unscale_kernel(float *__restrict__ parts, size_t count,
 }
 
 // Back-projection: Y_c = R H_c, epilogue sums over the tile's rows of H_c[e][q] Y_c[e][q] --
-// Workgroup tile 256 (transducers e) x 128 (nodes q), four waves of 128 x 64 complex (eight
-// 32 x 32 MFMA tiles, 256 FP32 accumulators per lane). K (transducers r) in steps of 32
+// Workgroup tile 256 (transducers e) x 128 (nodes q), eight waves of 64 x 64 complex (four
+// 32 x 32 MFMA tiles, 128 FP32 accumulators per lane, two waves per SIMD so that one
+// wave's MFMAs run while the other waits for LDS). K (transducers r) in steps of 32
 // (two MFMA sub-steps of 16), double-buffered in LDS with one barrier per step. Software
 // pipeline: the MFMA fragments of the next sub-step are read from LDS while the current
 // sub-step's MFMAs run (across the barrier for the first sub-step of the next tile), and the
@@ -428,7 +429,13 @@ __global__ void unscale_kernel(float *__restrict__ parts, size_t count,
 // past the last transducer or node read other (finite) data: they only reach output rows
 // that meet zero padding or are never stored.
 constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_LD = LR_BK + 8;
-constexpr int LR_THREADS = 256;
+// Waves of a workgroup: LR_WM along M times 2 along N; a wave owns LR_BM / LR_WM rows and 64
+// columns (LR_MT tiles of 32 x 32 by 2). Loader lanes cover LR_LROWS rows per pass.
+constexpr int LR_WM = 4;
+constexpr int LR_MT = LR_BM / (32 * LR_WM);
+constexpr int LR_THREADS = 64 * 2 * LR_WM;
+constexpr int LR_LROWS = LR_THREADS / 8;
+constexpr int LR_AU = LR_BM / LR_LROWS, LR_BU = LR_BN / LR_LROWS;
 // part planes padded by 64 bytes so that the two parts a loader group stores fall on
 // different LDS banks
 constexpr int LR_APLANE = LR_BM * LR_LD + 32, LR_BPLANE = LR_BN * LR_LD + 32;
@@ -447,7 +454,7 @@ __device__ __forceinline__ uint4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off, 
 // MFMA operands of one 16-deep sub-step of a wave: A rows (re, im) of its four 32-row
 // tiles, B columns (re, im, -im) of its two 32-column tiles.
 struct LrFrag {
-    uint4 ar[4], ai[4], br[2], bi[2], bn[2];
+    uint4 ar[LR_MT], ai[LR_MT], br[2], bi[2], bn[2];
 };
 
 template <typename T>
@@ -461,20 +468,20 @@ __device__ __forceinline__ void lr_read(LrFrag &f, const T *a0, const T *a1, con
         f.bi[nt] = *reinterpret_cast<const uint4 *>(b1 + o);
     }
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int o = (wm * 128 + mt * 32 + (lane & 31)) * LR_LD + kk;
+    for (int mt = 0; mt < LR_MT; ++mt) {
+        const int o = (wm * (32 * LR_MT) + mt * 32 + (lane & 31)) * LR_LD + kk;
         f.ar[mt] = *reinterpret_cast<const uint4 *>(a0 + o);
         f.ai[mt] = *reinterpret_cast<const uint4 *>(a1 + o);
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[4][2],
-                                        floatx16 (&acc_im)[4][2]) {
+__device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[LR_MT][2],
+                                        floatx16 (&acc_im)[LR_MT][2]) {
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) f.bn[nt] = neg8(f.bi[nt]);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < LR_MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             acc_re[mt][nt] = Lp<T>::mfma(as_vec<T>(f.ar[mt]), as_vec<T>(f.br[nt]), acc_re[mt][nt]);
@@ -496,28 +503,29 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
                                             __amdgpu_buffer_rsrc_t ra_rsrc, uint32_t a_off,
                                             __amdgpu_buffer_rsrc_t rb_rsrc, uint32_t b_off,
                                             uint32_t row_step, int kt0, int kt1,
-                                            floatx16 (&acc_re)[4][2], floatx16 (&acc_im)[4][2]) {
+                                            floatx16 (&acc_re)[LR_MT][2],
+                                            floatx16 (&acc_im)[LR_MT][2]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
-    uint4 ra[8], rb[4];
+    uint4 ra[LR_AU], rb[LR_BU];
     auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
         const int kp = DESC ? kt0 + kt1 - 1 - kt : kt;
         const uint32_t kb = (uint32_t)(kp * LR_BK * sizeof(T));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
+        for (int u = 0; u < LR_AU; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
+        for (int u = 0; u < LR_BU; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            *reinterpret_cast<uint4 *>(&a_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) =
-                ra[u];
+        for (int u = 0; u < LR_AU; ++u)
+            *reinterpret_cast<uint4 *>(
+                &a_s[buf][l_part][(l_row + LR_LROWS * u) * LR_LD + l_ch * 8]) = ra[u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            *reinterpret_cast<uint4 *>(&b_s[buf][l_part][(l_row + 32 * u) * LR_LD + l_ch * 8]) =
-                rb[u];
+        for (int u = 0; u < LR_BU; ++u)
+            *reinterpret_cast<uint4 *>(
+                &b_s[buf][l_part][(l_row + LR_LROWS * u) * LR_LD + l_ch * 8]) = rb[u];
     };
     fetch(kt0);
     stash(0);
@@ -529,14 +537,16 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
     // Steady state (tiles kt+1 and kt+2 exist): branch-free, so that the LDS reads, the
     // stash of tile kt+1 and the fetch of tile kt+2 are spread between the MFMAs of the
     // first sub-step, and the LDS reads of the next step between those of the second. The
-    // four waves run in step between barriers; bunched LDS operations would saturate the
-    // LDS while the MFMAs wait, so each group of eight MFMAs carries a few of them.
+    // waves run in step between barriers; bunched LDS operations would saturate the LDS
+    // while the MFMAs wait, so each group of MFMAs carries a few of them. With eight waves
+    // (two per SIMD) one wave's MFMAs also cover the other's waits for its LDS reads.
     for (; kt + 2 < kt1; ++kt) {
         const int cur = (kt - kt0) & 1;
         lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
         lr_mfma<T>(f0, acc_re, acc_im);
         stash(cur ^ 1);
         fetch(kt + 2);
+        if constexpr (LR_MT == 4) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -557,10 +567,28 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
             __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
         }
         __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
+        } else if constexpr (LR_MT == 2) {
+        // 16 MFMAs of this sub-step carry the 8 LDS reads of the next, the 6 LDS writes of
+        // the stash and the 6 global loads of the fetch
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        }
         __syncthreads();
         lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1], wm, wn,
                    lane, 0);
         lr_mfma<T>(f1, acc_re, acc_im);
+        if constexpr (LR_MT == 4) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
@@ -569,6 +597,15 @@ __device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        } else if constexpr (LR_MT == 2) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
         }
     }
     // the last one or two steps
@@ -603,10 +640,10 @@ template <typename T>
 __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup grp, int n_comp) {
     __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
     __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
-    __shared__ float red[2][2][LR_BN];
+    __shared__ float red[2][LR_WM][LR_BN];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 64
+    const int wm = wave >> 1, wn = wave & 1;  // LR_WM x 2 waves of 32 LR_MT x 64
     // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row (tid >> 3) +
     // 32 u; A rows u = 0..7, B rows u = 0..3. Byte offsets within the operand's planes.
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
@@ -634,7 +671,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
         const size_t hplane = (size_t)n_cols * np;
         const int KT = np / LR_BK;
         const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
-        const uint32_t row_step = (uint32_t)(32 * (size_t)np * sizeof(T));
+        const uint32_t row_step = (uint32_t)(LR_LROWS * (size_t)np * sizeof(T));
         const int local = item - grp.item0[p];
         const int nb = local / n_pairs, pr = local - nb * n_pairs;
         for (int half = 0; half < 2; ++half) {
@@ -651,9 +688,9 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
             for (int c = 0; c < n_comp; ++c) {
                 const T *Hc = Ht + (size_t)(2 * c) * hplane;
                 const __amdgpu_buffer_rsrc_t rb_rsrc = plane_rsrc(Hc, 2 * hplane * sizeof(T));
-                floatx16 acc_re[4][2], acc_im[4][2];
+                floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
+                for (int mt = 0; mt < LR_MT; ++mt)
 #pragma unroll
                     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
@@ -676,7 +713,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                     const T *ei_row = er_row + hplane;
                     uint2 pr[2][4], pi[2][4];
                     auto load_group = [&](int mt, int buf) {
-                        const int gb = min(row0 + wm * 128 + mt * 32, np - 32);
+                        const int gb = min(row0 + wm * (32 * LR_MT) + mt * 32, np - 32);
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int ge = gb + g * 8 + (lane >> 5) * 4;
@@ -686,9 +723,9 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                     };
                     load_group(0, 0);
 #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt) {
-                        if (mt < 3) load_group(mt + 1, (mt + 1) & 1);
-                        const float rm = row0 + wm * 128 + mt * 32 < np ? 1.f : 0.f;
+                    for (int mt = 0; mt < LR_MT; ++mt) {
+                        if (mt + 1 < LR_MT) load_group(mt + 1, (mt + 1) & 1);
+                        const float rm = row0 + wm * (32 * LR_MT) + mt * 32 < np ? 1.f : 0.f;
                         float sr = 0.f, si = 0.f;
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
@@ -723,8 +760,14 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
             if (tid < LR_BN) {
                 const int gc = col0 + tid;
                 if (gc < n_cols) {
-                    parts[(size_t)mb * n_cols + gc] = red[0][0][tid] + red[0][1][tid];
-                    parts[(size_t)(mblocks + mb) * n_cols + gc] = red[1][0][tid] + red[1][1][tid];
+                    float sr = red[0][0][tid], si = red[1][0][tid];
+#pragma unroll
+                    for (int w2 = 1; w2 < LR_WM; ++w2) {
+                        sr += red[0][w2][tid];
+                        si += red[1][w2][tid];
+                    }
+                    parts[(size_t)mb * n_cols + gc] = sr;
+                    parts[(size_t)(mblocks + mb) * n_cols + gc] = si;
                 }
             }
             __syncthreads();  // red[] and the LDS tiles are reused by the next slab
@@ -937,14 +980,14 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup
     const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
     const size_t gplane = (size_t)n * ld;
     const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(Gp, 2 * gplane * sizeof(T));
-    const uint32_t row_step = (uint32_t)(32 * (size_t)ld * sizeof(T));
+    const uint32_t row_step = (uint32_t)(LR_LROWS * (size_t)ld * sizeof(T));
     const uint32_t a_off =
         (uint32_t)((l_part * gplane + (size_t)(row0 + l_row) * ld + l_ch * 8) * sizeof(T));
     const uint32_t b_off =
         (uint32_t)((l_part * gplane + (size_t)(col0 + l_row) * ld + l_ch * 8) * sizeof(T));
-    floatx16 acc_re[4][2], acc_im[4][2];
+    floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < LR_MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
@@ -959,10 +1002,10 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup
         const int gc = col0 + wn * 64 + nt * 32 + (lane & 31);
         if (gc >= n) continue;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < LR_MT; ++mt)
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int gr = row0 + wm * 128 + mt * 32 + mfma_row(lane, i);
+                const int gr = row0 + wm * (32 * LR_MT) + mt * 32 + mfma_row(lane, i);
                 if (gr <= gc)
                     out[(size_t)gr * n + gc] = make_float2(acc_re[mt][nt][i], acc_im[mt][nt][i]);
             }
