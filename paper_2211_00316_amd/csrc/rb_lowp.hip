@@ -420,25 +420,31 @@ __global__ void unscale_kernel(float *__restrict__ parts, size_t count,
 // Workgroup tile 256 (transducers e) x 128 (nodes q), eight waves of 64 x 64 complex (four
 // 32 x 32 MFMA tiles, 128 FP32 accumulators per lane, two waves per SIMD so that one
 // wave's MFMAs run while the other waits for LDS). K (transducers r) in steps of 32
-// (two MFMA sub-steps of 16), double-buffered in LDS with one barrier per step. Software
-// pipeline: the MFMA fragments of the next sub-step are read from LDS while the current
-// sub-step's MFMAs run (across the barrier for the first sub-step of the next tile), and the
-// global operands of step k+2 are fetched into registers during step k.
-// Global operands are read through one wave-uniform buffer descriptor per operand spanning
-// its two part planes (loads past the end return zero); rows are whole K steps long. Rows
-// past the last transducer or node read other (finite) data: they only reach output rows
-// that meet zero padding or are never stored.
-constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32, LR_LD = LR_BK + 8;
+// (two MFMA sub-steps of 16). The operands go from global memory straight into LDS
+// (buffer loads with the LDS bit, 16 bytes per lane), three K steps in flight: while step
+// k is multiplied, step k+1 has landed or is landing and step k+2 is being fetched; one
+// barrier per step. The MFMA fragments of the next sub-step are read from LDS while the
+// current sub-step's MFMAs run (across the barrier for the first sub-step of the next
+// step). Global operands are read through one wave-uniform buffer descriptor per operand
+// spanning its two part planes (loads past the end return zero); rows are whole K steps
+// long. Rows past the last transducer or node read other (finite) data: they only reach
+// output rows that meet zero padding or are never stored.
+constexpr int LR_BM = 256, LR_BN = 128, LR_BK = 32;
 // Waves of a workgroup: LR_WM along M times 2 along N; a wave owns LR_BM / LR_WM rows and 64
-// columns (LR_MT tiles of 32 x 32 by 2). Loader lanes cover LR_LROWS rows per pass.
+// columns (LR_MT tiles of 32 x 32 by 2).
 constexpr int LR_WM = 4;
 constexpr int LR_MT = LR_BM / (32 * LR_WM);
 constexpr int LR_THREADS = 64 * 2 * LR_WM;
-constexpr int LR_LROWS = LR_THREADS / 8;
-constexpr int LR_AU = LR_BM / LR_LROWS, LR_BU = LR_BN / LR_LROWS;
-// part planes padded by 64 bytes so that the two parts a loader group stores fall on
-// different LDS banks
-constexpr int LR_APLANE = LR_BM * LR_LD + 32, LR_BPLANE = LR_BN * LR_LD + 32;
+// One LDS stage holds one K step: the A part planes (LR_BM rows of LR_BK values each) then
+// the B part planes (LR_BN rows). A row is four 16-byte chunks; chunk c of row r sits in slot
+// c ^ ((r >> 2) & 3), so that the 16 lanes of a fragment read (16 consecutive rows, one
+// chunk) hit all 64 banks once. A loader instruction of a wave fills 1 KiB of a stage, 16
+// rows: lane l writes slot l & 3 of row l >> 2 and so fetches chunk (l & 3) ^ ((l >> 4) & 3).
+constexpr int LR_AP = LR_BM * LR_BK, LR_BP = LR_BN * LR_BK;  // part plane sizes (values)
+constexpr int LR_STAGE = 2 * LR_AP + 2 * LR_BP;                // values per stage
+constexpr int LR_AU = 2 * LR_AP * 2 / 1024 / (LR_THREADS / 64);  // A loads per lane and step
+constexpr int LR_BU = 2 * LR_BP * 2 / 1024 / (LR_THREADS / 64);  // B loads per lane and step
+static_assert(LR_THREADS == 512 && LR_AU == 4 && LR_BU == 2, "loader layout");
 constexpr size_t LR_SPAN = 0xfffffff0u;  // vector + scalar byte offsets stay below this
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, size_t bytes) {
@@ -446,32 +452,46 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *p, size
                                              0x00020000);
 }
 
-__device__ __forceinline__ uint4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
-    return __builtin_bit_cast(uint4,
-                              __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
+// 16 bytes per lane from the buffer to LDS: lane l writes lds + 16 l (lds wave-uniform).
+template <typename T>
+__device__ __forceinline__ void load_lds16(__amdgpu_buffer_rsrc_t r, T *lds, uint32_t off,
+                                           uint32_t soff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        r, (__attribute__((address_space(3))) void *)lds, 16, (int)off, (int)soff, 0, 0);
 }
 
-// MFMA operands of one 16-deep sub-step of a wave: A rows (re, im) of its four 32-row
-// tiles, B columns (re, im, -im) of its two 32-column tiles.
+// Wait until at most N global loads of this wave are outstanding and its LDS operations are
+// done, then meet the other waves. Loads return in order, so the older step's operands are in
+// LDS; after the barrier every wave's are.
+template <int N>
+__device__ __forceinline__ void lr_sync() {
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    if constexpr (N == 0) asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// MFMA operands of one 16-deep sub-step of a wave: A rows (re, im) of its 32-row tiles, B
+// columns (re, im, -im) of its two 32-column tiles.
 struct LrFrag {
     uint4 ar[LR_MT], ai[LR_MT], br[2], bi[2], bn[2];
 };
 
+// Fragments of sub-step `sub` (0 or 1) of the stage st.
 template <typename T>
-__device__ __forceinline__ void lr_read(LrFrag &f, const T *a0, const T *a1, const T *b0,
-                                        const T *b1, int wm, int wn, int lane, int ks) {
-    const int kk = ks + (lane >> 5) * 8;
+__device__ __forceinline__ void lr_read(LrFrag &f, const T *st, int wm, int wn, int lane,
+                                        int sub) {
+    const int co = (((sub * 2 + (lane >> 5)) ^ ((lane >> 2) & 3)) * 8);
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
-        const int o = (wn * 64 + nt * 32 + (lane & 31)) * LR_LD + kk;
-        f.br[nt] = *reinterpret_cast<const uint4 *>(b0 + o);
-        f.bi[nt] = *reinterpret_cast<const uint4 *>(b1 + o);
+        const int o = 2 * LR_AP + (wn * 64 + nt * 32 + (lane & 31)) * LR_BK + co;
+        f.br[nt] = *reinterpret_cast<const uint4 *>(st + o);
+        f.bi[nt] = *reinterpret_cast<const uint4 *>(st + o + LR_BP);
     }
 #pragma unroll
     for (int mt = 0; mt < LR_MT; ++mt) {
-        const int o = (wm * (32 * LR_MT) + mt * 32 + (lane & 31)) * LR_LD + kk;
-        f.ar[mt] = *reinterpret_cast<const uint4 *>(a0 + o);
-        f.ai[mt] = *reinterpret_cast<const uint4 *>(a1 + o);
+        const int o = (wm * (32 * LR_MT) + mt * 32 + (lane & 31)) * LR_BK + co;
+        f.ar[mt] = *reinterpret_cast<const uint4 *>(st + o);
+        f.ai[mt] = *reinterpret_cast<const uint4 *>(st + o + LR_AP);
     }
 }
 
@@ -491,135 +511,137 @@ __device__ __forceinline__ void lr_mfma(LrFrag &f, floatx16 (&acc_re)[LR_MT][2],
         }
 }
 
+// Loader offsets of a lane (bytes, buffer-relative): the A rows it fetches are
+// a_row0 + 16 w + (l >> 2) (+ 128) of both part planes, the B rows b_row0 + 16 w + (l >> 2)
+// of both planes; ld = values per row.
+struct LrLoad {
+    __amdgpu_buffer_rsrc_t ra, rb;
+    uint32_t a_off, a_half, a_plane, b_off, b_plane;
+};
+
+template <typename T>
+__device__ __forceinline__ LrLoad lr_load(const void *A, size_t a_plane, int a_row0,
+                                          const void *B, size_t b_plane, int b_row0, int ld) {
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int kc = (l & 3) ^ ((l >> 4) & 3);
+    LrLoad L;
+    L.ra = plane_rsrc(A, 2 * a_plane * sizeof(T));
+    L.rb = plane_rsrc(B, 2 * b_plane * sizeof(T));
+    L.a_off = (uint32_t)(((size_t)(a_row0 + 16 * w + (l >> 2)) * ld + kc * 8) * sizeof(T));
+    L.b_off = (uint32_t)(((size_t)(b_row0 + 16 * w + (l >> 2)) * ld + kc * 8) * sizeof(T));
+    L.a_half = (uint32_t)((size_t)128 * ld * sizeof(T));
+    L.a_plane = (uint32_t)(a_plane * sizeof(T));
+    L.b_plane = (uint32_t)(b_plane * sizeof(T));
+    return L;
+}
+
+// K step kp of both operands into stage st: LR_AU + LR_BU loads per lane.
+template <typename T>
+__device__ __forceinline__ void lr_fetch(const LrLoad &L, T *st, int kp) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t kb = (uint32_t)(kp * LR_BK * sizeof(T));
+#pragma unroll
+    for (int u = 0; u < LR_AU; ++u)  // A block w + 8 u: plane u >> 1, rows 16 w + 128 (u & 1)
+        load_lds16(L.ra, st + (w + 8 * u) * 512,
+                   L.a_off + (u & 1) * L.a_half + (u >> 1) * L.a_plane, kb);
+#pragma unroll
+    for (int u = 0; u < LR_BU; ++u)  // B block w + 8 u: plane u, rows 16 w
+        load_lds16(L.rb, st + 2 * LR_AP + (w + 8 * u) * 512, L.b_off + u * L.b_plane, kb);
+}
+
+// Issue order of one sub-step: its 16 MFMAs carry the 8 LDS reads of the next sub-step and,
+// in the first sub-step, the 6 loads of step k+2.
+__device__ __forceinline__ void lr_sched_first() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+}
+
+__device__ __forceinline__ void lr_sched_second() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+}
+
 // The pipelined K loop: acc += A B^T over K steps [kt0, kt1) of LR_BK, complex operands in two
-// part planes. A: the tile's LR_BM rows, B: its LR_BN rows; each loader lane (chunk tid & 3 of
-// part (tid >> 2) & 1) reads rows (tid >> 3) + 32 u, whose first bytes are a_off / b_off
-// (+ u row_step) in the descriptors ra / rb. Global operands of step k+2 are fetched into
-// registers during step k; LDS is double-buffered with one barrier per step. The LDS tiles
-// are still being read when it returns: a barrier must precede their next fill. DESC walks
-// the K steps from kt1 - 1 down to kt0.
+// part planes, through the LDS stages s0, s1, s2 (step kt0 + i in stage i mod 3). DESC walks
+// the K steps from kt1 - 1 down to kt0. The stages are distinct arrays so that the compiler
+// sees that the loads in flight into one do not feed the LDS reads of another. No load is
+// outstanding when it returns, but the stages are still being read: a barrier must precede
+// their next fill.
 template <typename T, bool DESC>
-__device__ __forceinline__ void lr_mainloop(T (*a_s)[2][LR_APLANE], T (*b_s)[2][LR_BPLANE],
-                                            __amdgpu_buffer_rsrc_t ra_rsrc, uint32_t a_off,
-                                            __amdgpu_buffer_rsrc_t rb_rsrc, uint32_t b_off,
-                                            uint32_t row_step, int kt0, int kt1,
-                                            floatx16 (&acc_re)[LR_MT][2],
+__device__ __forceinline__ void lr_mainloop(T *s0, T *s1, T *s2, const LrLoad &L, int kt0,
+                                            int kt1, floatx16 (&acc_re)[LR_MT][2],
                                             floatx16 (&acc_im)[LR_MT][2]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
-    uint4 ra[LR_AU], rb[LR_BU];
-    auto fetch = [&](int kt) {  // the K offset of the step goes in the scalar offset
-        const int kp = DESC ? kt0 + kt1 - 1 - kt : kt;
-        const uint32_t kb = (uint32_t)(kp * LR_BK * sizeof(T));
-#pragma unroll
-        for (int u = 0; u < LR_AU; ++u) ra[u] = load16(ra_rsrc, a_off + u * row_step, kb);
-#pragma unroll
-        for (int u = 0; u < LR_BU; ++u) rb[u] = load16(rb_rsrc, b_off + u * row_step, kb);
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < LR_AU; ++u)
-            *reinterpret_cast<uint4 *>(
-                &a_s[buf][l_part][(l_row + LR_LROWS * u) * LR_LD + l_ch * 8]) = ra[u];
-#pragma unroll
-        for (int u = 0; u < LR_BU; ++u)
-            *reinterpret_cast<uint4 *>(
-                &b_s[buf][l_part][(l_row + LR_LROWS * u) * LR_LD + l_ch * 8]) = rb[u];
-    };
-    fetch(kt0);
-    stash(0);
-    if (kt0 + 1 < kt1) fetch(kt0 + 1);
-    __syncthreads();
+    auto kp = [&](int kt) { return DESC ? kt0 + kt1 - 1 - kt : kt; };
     LrFrag f0, f1;
-    lr_read<T>(f0, a_s[0][0], a_s[0][1], b_s[0][0], b_s[0][1], wm, wn, lane, 0);
-    int kt = kt0;
-    // Steady state (tiles kt+1 and kt+2 exist): branch-free, so that the LDS reads, the
-    // stash of tile kt+1 and the fetch of tile kt+2 are spread between the MFMAs of the
-    // first sub-step, and the LDS reads of the next step between those of the second. The
-    // waves run in step between barriers; bunched LDS operations would saturate the LDS
-    // while the MFMAs wait, so each group of MFMAs carries a few of them. With eight waves
-    // (two per SIMD) one wave's MFMAs also cover the other's waits for its LDS reads.
-    for (; kt + 2 < kt1; ++kt) {
-        const int cur = (kt - kt0) & 1;
-        lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
+    // one K step whose successor is in flight and whose second successor is fetched now
+    auto step = [&](T *cur, T *nxt, T *nn, int kt) {
+        lr_read<T>(f1, cur, wm, wn, lane, 1);
         lr_mfma<T>(f0, acc_re, acc_im);
-        stash(cur ^ 1);
-        fetch(kt + 2);
-        if constexpr (LR_MT == 4) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
-        } else if constexpr (LR_MT == 2) {
-        // 16 MFMAs of this sub-step carry the 8 LDS reads of the next, the 6 LDS writes of
-        // the stash and the 6 global loads of the fetch
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
-        }
-        __syncthreads();
-        lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1], wm, wn,
-                   lane, 0);
+        lr_fetch<T>(L, nn, kp(kt + 2));
+        lr_sched_first();
+        lr_sync<LR_AU + LR_BU>();
+        lr_read<T>(f0, nxt, wm, wn, lane, 0);
         lr_mfma<T>(f1, acc_re, acc_im);
-        if constexpr (LR_MT == 4) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
-        } else if constexpr (LR_MT == 2) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
-        }
-    }
-    // the last one or two steps
-    for (; kt < kt1; ++kt) {
-        const int cur = (kt - kt0) & 1;
-        lr_read<T>(f1, a_s[cur][0], a_s[cur][1], b_s[cur][0], b_s[cur][1], wm, wn, lane, 16);
+        lr_sched_second();
+    };
+    // one of the last two K steps (nothing left to fetch)
+    auto last = [&](T *cur, T *nxt, int kt) {
+        lr_read<T>(f1, cur, wm, wn, lane, 1);
         lr_mfma<T>(f0, acc_re, acc_im);
         if (kt + 1 < kt1) {
-            stash(cur ^ 1);
-            __syncthreads();
-            lr_read<T>(f0, a_s[cur ^ 1][0], a_s[cur ^ 1][1], b_s[cur ^ 1][0], b_s[cur ^ 1][1],
-                       wm, wn, lane, 0);
+            lr_sync<0>();
+            lr_read<T>(f0, nxt, wm, wn, lane, 0);
         }
         lr_mfma<T>(f1, acc_re, acc_im);
+    };
+    lr_fetch<T>(L, s0, kp(kt0));
+    if (kt0 + 1 >= kt1) {  // a single step
+        lr_sync<0>();
+        lr_read<T>(f0, s0, wm, wn, lane, 0);
+        last(s0, s1, kt0);
+        return;
+    }
+    lr_fetch<T>(L, s1, kp(kt0 + 1));
+    lr_sync<LR_AU + LR_BU>();
+    lr_read<T>(f0, s0, wm, wn, lane, 0);
+    int kt = kt0;
+    // steady state, branch-free: the stages rotate with the unrolled steps, so that each
+    // step names its stages statically
+    for (; kt + 4 < kt1; kt += 3) {
+        step(s0, s1, s2, kt);
+        step(s1, s2, s0, kt + 1);
+        step(s2, s0, s1, kt + 2);
+    }
+    T *c0 = s0, *c1 = s1, *c2 = s2;
+    for (; kt + 2 < kt1; ++kt) {
+        step(c0, c1, c2, kt);
+        T *t = c0;
+        c0 = c1;
+        c1 = c2;
+        c2 = t;
+    }
+    for (; kt < kt1; ++kt) {
+        last(c0, c1, kt);
+        T *t = c0;
+        c0 = c1;
+        c1 = c2;
+        c2 = t;
     }
 }
 
@@ -638,15 +660,13 @@ struct RowGroup {
 
 template <typename T>
 __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup grp, int n_comp) {
-    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
-    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
+    __shared__ __attribute__((aligned(1024))) T s0[LR_STAGE];
+    __shared__ __attribute__((aligned(1024))) T s1[LR_STAGE];
+    __shared__ __attribute__((aligned(1024))) T s2[LR_STAGE];
     __shared__ float red[2][LR_WM][LR_BN];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;  // LR_WM x 2 waves of 32 LR_MT x 64
-    // Loader lanes: chunk (8 values) ch = tid & 3 of part (tid >> 2) & 1 of row (tid >> 3) +
-    // 32 u; A rows u = 0..7, B rows u = 0..3. Byte offsets within the operand's planes.
-    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
 
     // Persistent: one workgroup per CU walks a static list of work items. An item is one
     // node tile and a pair of row slabs (i, mblocks - 1 - i), whose contractions start at
@@ -670,8 +690,6 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
         const size_t rplane = (size_t)n * np;
         const size_t hplane = (size_t)n_cols * np;
         const int KT = np / LR_BK;
-        const __amdgpu_buffer_rsrc_t ra_rsrc = plane_rsrc(Rp, 2 * rplane * sizeof(T));
-        const uint32_t row_step = (uint32_t)(LR_LROWS * (size_t)np * sizeof(T));
         const int local = item - grp.item0[p];
         const int nb = local / n_pairs, pr = local - nb * n_pairs;
         for (int half = 0; half < 2; ++half) {
@@ -680,14 +698,10 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
             const int row0 = mb * LR_BM, col0 = nb * LR_BN;
             const int KT0 = row0 / LR_BK;  // R' is zero left of the diagonal block
             float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
-            const uint32_t a_off = (uint32_t)(
-                (l_part * rplane + (size_t)(row0 + l_row) * np + l_ch * 8) * sizeof(T));
-            const uint32_t b_off = (uint32_t)(
-                (l_part * hplane + (size_t)(col0 + l_row) * np + l_ch * 8) * sizeof(T));
 
             for (int c = 0; c < n_comp; ++c) {
                 const T *Hc = Ht + (size_t)(2 * c) * hplane;
-                const __amdgpu_buffer_rsrc_t rb_rsrc = plane_rsrc(Hc, 2 * hplane * sizeof(T));
+                const LrLoad ld = lr_load<T>(Rp, rplane, row0, Hc, hplane, col0, np);
                 floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
                 for (int mt = 0; mt < LR_MT; ++mt)
@@ -698,8 +712,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                             acc_re[mt][nt][i] = 0.f;
                             acc_im[mt][nt][i] = 0.f;
                         }
-                lr_mainloop<T, true>(a_s, b_s, ra_rsrc, a_off, rb_rsrc, b_off, row_step, KT0, KT,
-                                     acc_re, acc_im);
+                lr_mainloop<T, true>(s0, s1, s2, ld, KT0, KT, acc_re, acc_im);
                 // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
                 // 8-byte load per part. Rows are padded with zeros to np, a multiple of 32, so a
                 // 32-row group lies wholly inside np or wholly past it (uniform; such groups get
@@ -953,8 +966,9 @@ struct FwdGroup {
 
 template <typename T>
 __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup grp) {
-    __shared__ __attribute__((aligned(16))) T a_s[2][2][LR_APLANE];
-    __shared__ __attribute__((aligned(16))) T b_s[2][2][LR_BPLANE];
+    __shared__ __attribute__((aligned(1024))) T s0[LR_STAGE];
+    __shared__ __attribute__((aligned(1024))) T s1[LR_STAGE];
+    __shared__ __attribute__((aligned(1024))) T s2[LR_STAGE];
     int p = 0;
     while (p + 1 < grp.count && (int)blockIdx.x >= grp.blk0[p + 1]) ++p;
     const T *__restrict__ Gp = static_cast<const T *>(grp.G[p]);
@@ -977,14 +991,8 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup
     const int kt0 = split * kchunk, kt1 = min(KT, kt0 + kchunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int l_ch = tid & 3, l_part = (tid >> 2) & 1, l_row = tid >> 3;
     const size_t gplane = (size_t)n * ld;
-    const __amdgpu_buffer_rsrc_t rsrc = plane_rsrc(Gp, 2 * gplane * sizeof(T));
-    const uint32_t row_step = (uint32_t)(LR_LROWS * (size_t)ld * sizeof(T));
-    const uint32_t a_off =
-        (uint32_t)((l_part * gplane + (size_t)(row0 + l_row) * ld + l_ch * 8) * sizeof(T));
-    const uint32_t b_off =
-        (uint32_t)((l_part * gplane + (size_t)(col0 + l_row) * ld + l_ch * 8) * sizeof(T));
+    const LrLoad L = lr_load<T>(Gp, gplane, row0, Gp, gplane, col0, ld);
     floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
     for (int mt = 0; mt < LR_MT; ++mt)
@@ -995,7 +1003,7 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup
                 acc_re[mt][nt][i] = 0.f;
                 acc_im[mt][nt][i] = 0.f;
             }
-    lr_mainloop<T, false>(a_s, b_s, rsrc, a_off, rsrc, b_off, row_step, kt0, kt1, acc_re, acc_im);
+    lr_mainloop<T, false>(s0, s1, s2, L, kt0, kt1, acc_re, acc_im);
     float2 *out = dpart + (size_t)split * n * n;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
