@@ -549,6 +549,46 @@ __device__ __forceinline__ void lr_fetch(const LrLoad &L, T *st, int kp) {
         load_lds16(L.rb, st + 2 * LR_AP + (w + 8 * u) * 512, L.b_off + u * L.b_plane, kb);
 }
 
+// The back-projection epilogue's operand: Ht_c[col0 + q][row0 + e] for q < LR_BN, e < LR_BM,
+// both parts, into the stages: rows e in chunks of LR_ECH, LR_ECH, LR_BM - 2 LR_ECH (one
+// per stage), each stage laid out [part][q][e] with the 16-byte piece k of a row in slot
+// k ^ lr_eswz(q, pieces per row), so that 16 consecutive q of one read hit distinct banks. A loader
+// instruction fills 1 KiB of a stage lane-contiguously; each lane fetches the piece that
+// lands in its slot. Coalesced: a row's pieces are contiguous in Ht_c.
+constexpr int LR_ECH = 96;
+__device__ __forceinline__ int lr_eswz(int q, int pr) {
+    return pr == 8 ? (q >> 1) & 7 : (q >> 2) & 3;  // rows of 128 or 192 bytes
+}
+static_assert(LR_ECH % 32 == 0 && 2 * LR_ECH < LR_BM && LR_BM - 2 * LR_ECH <= LR_ECH &&
+                  2 * LR_BN * LR_ECH <= LR_STAGE,
+              "epilogue chunks");
+template <typename T>
+__device__ __forceinline__ void lr_fetch_e(const T *Hc, size_t hplane, int np, int row0,
+                                           int col0, T *s0, T *s1, T *s2) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(Hc, 2 * hplane * sizeof(T));
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        T *st = ch == 0 ? s0 : (ch == 1 ? s1 : s2);
+        constexpr int waves = LR_THREADS / 64;
+        const int len = ch == 2 ? LR_BM - 2 * LR_ECH : LR_ECH;
+        const int pr = len / 8;                 // pieces per row
+        const int nu = 2 * LR_BN * pr / 64 / waves;  // loads per lane
+#pragma unroll
+        for (int u = 0; u < nu; ++u) {
+            const int b = w + waves * u;
+            const int P = b * 64 + l;
+            const int row = P / pr, slot = P - row * pr;
+            const int part = row / LR_BN, q = row - part * LR_BN;
+            const int piece = slot ^ lr_eswz(q, pr);
+            const uint32_t off = (uint32_t)((part * hplane + (size_t)(col0 + q) * np + row0 +
+                                             ch * LR_ECH + piece * 8) *
+                                            sizeof(T));
+            load_lds16(r, st + b * 512, off, 0u);
+        }
+    }
+}
+
 // Issue order of one sub-step: its 16 MFMAs carry the 8 LDS reads of the next sub-step and,
 // in the first sub-step, the 6 loads of step k+2.
 __device__ __forceinline__ void lr_sched_first() {
@@ -713,38 +753,35 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                             acc_im[mt][nt][i] = 0.f;
                         }
                 lr_mainloop<T, true>(s0, s1, s2, ld, KT0, KT, acc_re, acc_im);
-                // epilogue: E_c[e][q] = Ht_c[q][e]; four consecutive rows e per register group, one
-                // 8-byte load per part. Rows are padded with zeros to np, a multiple of 32, so a
-                // 32-row group lies wholly inside np or wholly past it (uniform; such groups get
-                // weight 0), and rows beyond n carry E = 0. Lanes of nodes past the last read the
-                // last node's row; their sums are never stored. No branch: the loads of the next
-                // 32-row group go out before the arithmetic of the current one.
+                // epilogue: E_c[e][q] = Ht_c[q][e] for the tile's 256 rows e and 128 nodes q, staged
+                // through the three LDS stages (coalesced loads of row pieces of Ht_c), then four
+                // consecutive rows e per register group, one 8-byte LDS read per part. Rows are
+                // padded with zeros to np, a multiple of 32, so a 32-row group lies wholly inside
+                // np or wholly past it (uniform; such groups get weight 0 and read other finite
+                // data), and rows beyond n carry E = 0. Lanes of nodes past the last read other
+                // finite data; their sums are never stored.
+                __syncthreads();  // every wave is done with the K loop's stages
+                lr_fetch_e<T>(Hc, hplane, np, row0, col0, s0, s1, s2);
+                lr_sync<0>();
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
-                    const int gq = min(col0 + wn * 64 + nt * 32 + (lane & 31), n_cols - 1);
-                    const T *er_row = Hc + (size_t)gq * np;
-                    const T *ei_row = er_row + hplane;
-                    uint2 pr[2][4], pi[2][4];
-                    auto load_group = [&](int mt, int buf) {
-                        const int gb = min(row0 + wm * (32 * LR_MT) + mt * 32, np - 32);
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int ge = gb + g * 8 + (lane >> 5) * 4;
-                            pr[buf][g] = *reinterpret_cast<const uint2 *>(er_row + ge);
-                            pi[buf][g] = *reinterpret_cast<const uint2 *>(ei_row + ge);
-                        }
-                    };
-                    load_group(0, 0);
+                    const int q = wn * 64 + nt * 32 + (lane & 31);
 #pragma unroll
                     for (int mt = 0; mt < LR_MT; ++mt) {
-                        if (mt + 1 < LR_MT) load_group(mt + 1, (mt + 1) & 1);
-                        const float rm = row0 + wm * (32 * LR_MT) + mt * 32 < np ? 1.f : 0.f;
+                        const int eb = wm * (32 * LR_MT) + mt * 32;  // wave-uniform
+                        const int ch = eb / LR_ECH;
+                        const T *st = ch == 0 ? s0 : (ch == 1 ? s1 : s2);
+                        const int pr = ch == 2 ? (LR_BM - 2 * LR_ECH) / 8 : LR_ECH / 8;
+                        const int hq = lr_eswz(q, pr);
+                        const float rm = row0 + eb < np ? 1.f : 0.f;
                         float sr = 0.f, si = 0.f;
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
+                            const int el = eb - ch * LR_ECH + g * 8 + (lane >> 5) * 4;
+                            const int o = (q * pr + ((el >> 3) ^ hq)) * 8 + (el & 7);
                             T vr[4], vi[4];
-                            __builtin_memcpy(vr, &pr[mt & 1][g], 8);
-                            __builtin_memcpy(vi, &pi[mt & 1][g], 8);
+                            __builtin_memcpy(vr, st + o, 8);
+                            __builtin_memcpy(vi, st + o + LR_BN * pr * 8, 8);
 #pragma unroll
                             for (int z = 0; z < 4; ++z) {
                                 const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
