@@ -310,7 +310,7 @@ def run_serve(args):
         grid, ring, tp = setup_for(w)
         print(f"[serve] data of {w.name} phantom {sd}", file=sys.stderr, flush=True)
         store[(k, sd)] = synthesize_data(ctx, w, grid, ring, tp, ph.phantom_for(w, seed=sd),
-                                         list(range(len(w.freqs))))
+                                         list(range(len(w.freqs)))).cpu()
     ctx.close()
 
     def make(draws):
@@ -321,10 +321,11 @@ def run_serve(args):
             idx = ph.step_frequencies(d.n_steps, len(w.freqs))
             om = [2 * math.pi * w.freqs[i] for i in idx]
             dom = [2 * math.pi * (w.freqs[-1] - w.freqs[0]) / max(1, d.n_steps - 1)] * d.n_steps
-            data = store[(d.cls, d.phantom_seed)][torch.as_tensor(idx, device="cuda:0")]
-            c0 = torch.full((w.ny, w.nx), ph.C_WATER, dtype=torch.float64, device="cuda:0")
+            # host copy of the request's data: the server moves it to the device on admission
+            data = store[(d.cls, d.phantom_seed)][torch.as_tensor(idx)].pin_memory()
+            c0 = torch.full((w.ny, w.nx), ph.C_WATER, dtype=torch.float64)
             reqs.append(serve.Request(d.rid, d.arrival, grid, ring, tp, om, dom,
-                                      [w.smooth_window(i) for i in idx], data.contiguous(), c0,
+                                      [w.smooth_window(i) for i in idx], data, c0,
                                       w.tau, tag=w.name))
         return reqs
 

@@ -490,20 +490,21 @@ __device__ __forceinline__ void bbox_tiles(const float *tu, const float *tv, int
 
 // Interpolate the fields of triangle vb[] at barycentric lam[] and write table entry `out`;
 // K: the largest caustic count of the three vertices. Returns the interpolated dT.
-// Polar angle of (x, y) in [-pi, pi] within about 3e-7 rad (atan2f: 2 ulp): octant
-// reduction and an odd polynomial of degree 15 for atan on [0, 1] (least-squares fit).
+// Polar angle of (x, y) in [-pi, pi] within 3e-7 rad (atan2f: 2 ulp): octant reduction
+// and an odd polynomial of degree 15 for atan on [0, 1], the least-squares fit on 2000
+// Chebyshev nodes (4.1e-8 rad in exact arithmetic; fit_atan.py rebuilds it).
 __device__ __forceinline__ float ray_atan2(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
     const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(fmaxf(ax, ay), 1e-30f));
     const float t2 = t * t;
-    float p = -0.00405453f;
-    p = fmaf(p, t2, 0.02186283f);
-    p = fmaf(p, t2, -0.05591219f);
-    p = fmaf(p, t2, 0.09642192f);
-    p = fmaf(p, t2, -0.1390863f);
-    p = fmaf(p, t2, 0.19946567f);
-    p = fmaf(p, t2, -0.33329861f);
-    p = fmaf(p, t2, 0.99999934f);
+    float p = -0.0040733092f;
+    p = fmaf(p, t2, 0.021946611f);
+    p = fmaf(p, t2, -0.056063175f);
+    p = fmaf(p, t2, 0.096562564f);
+    p = fmaf(p, t2, -0.13915803f);
+    p = fmaf(p, t2, 0.19948509f);
+    p = fmaf(p, t2, -0.33330107f);
+    p = fmaf(p, t2, 0.99999946f);
     float a = t * p;
     if (ay > ax) a = 1.57079633f - a;
     if (x < 0.f) a = 3.14159265f - a;
@@ -628,15 +629,16 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
 
 // Straight-ray guess of the quad holding the point at (ddx, ddy) from the source: launch
 // angle and arc length of the straight ray.
-// Polar angle of (x, y) in [-pi, pi] to about 1e-4 rad: octant reduction and an odd
-// polynomial for atan on [0, 1] (least-squares fit). Only the walk's starting quad depends on
-// it (a tenth of a ray spacing at 1024 rays), not where a walk ends.
+// Polar angle of (x, y) in [-pi, pi] to 1e-4 rad: octant reduction and an odd polynomial of
+// degree 7 for atan on [0, 1], the least-squares fit on 2000 Chebyshev nodes (fit_atan.py).
+// Only the walk's starting quad depends on it (a tenth of a ray spacing at 1024 rays), not
+// where a walk ends.
 __device__ __forceinline__ float guess_atan2(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
     const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(fmaxf(ax, ay), 1e-30f));
     const float t2 = t * t;
-    float a = t * fmaf(fmaf(fmaf(-0.03913415f, t2, 0.14661529f), t2, -0.32143048f), t2,
-                       0.99926772f);
+    float a = t * fmaf(fmaf(fmaf(-0.039134149f, t2, 0.14661528f), t2, -0.32143047f), t2,
+                       0.9992677f);
     if (ay > ax) a = 1.57079633f - a;
     if (x < 0.f) a = 3.14159265f - a;
     return y < 0.f ? -a : a;

@@ -26,7 +26,8 @@ import numpy as np
 @dataclasses.dataclass
 class Request:
     """One reconstruction. omegas / d_omegas / windows: one entry per step. data: complex64
-    [n_steps][n][n] on the device; c_start: float64 [ny][nx] on the device."""
+    [n_steps][n][n] in host memory (pinned for an asynchronous copy), copied to the device
+    when the request is admitted and freed when it finishes; c_start: float64 [ny][nx]."""
 
     rid: int
     arrival: float
@@ -42,6 +43,7 @@ class Request:
     tag: str = ""
     # filled by the server
     c: object = None
+    data_dev: object = None
     bytes: int = 0
     steps_done: int = 0
     status: int = 0
@@ -217,7 +219,9 @@ class GpuExecutor:
         b = self._lib.step_bytes(r.grid, r.ring, r.tp, self.prec, self._budget_for(r))
         if b <= 0:
             raise ValueError(f"request {r.rid}: invalid geometry")
-        return b + 2 * r.grid.nx * r.grid.ny * 8   # model and its working copy
+        model = 2 * r.grid.nx * r.grid.ny * 8   # model and its working copy
+        data = r.n_steps * r.ring.n * r.ring.n * 8   # complex64 data of every step
+        return b + model + data
 
     def open(self, r):
         torch = self.torch
@@ -233,8 +237,9 @@ class GpuExecutor:
             ctx = self._lib.Context(self.device, stream=stream)
             ctx.set_sample_budget(self._budget_for(r))
         self.active_bytes += r.bytes
-        r.c = r.c_start.clone()
-        torch.cuda.current_stream().synchronize()   # the copy is done before the scan's stream reads it
+        r.c = r.c_start.to(self.device, copy=True)
+        r.data_dev = r.data.to(self.device, non_blocking=True)
+        torch.cuda.current_stream().synchronize()   # the copies are done before the scan's stream reads them
         self.ctx[r.rid] = ctx
 
     def step(self, reqs):
@@ -243,12 +248,13 @@ class GpuExecutor:
             k = r.steps_done
             steps.append(self._lib.ScanStep(
                 self.ctx[r.rid], r.grid, r.ring, r.tp, r.c, r.windows[k], [r.omegas[k]],
-                [r.d_omegas[k]], r.data[k:k + 1], r.tau))
+                [r.d_omegas[k]], r.data_dev[k:k + 1], r.tau))
         return self._lib.frequency_step_batch(steps, self.prec)
 
     def close(self, r):
         ctx = self.ctx.pop(r.rid)
         self.active_bytes -= r.bytes
+        r.data_dev = None   # the device copy of the data goes back to the allocator
         if self.pool_on:
             self.pool.setdefault(self._key(r), []).append((ctx, r.bytes))
         else:
