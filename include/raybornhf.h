@@ -21,6 +21,15 @@
  *   - Every array argument is a DEVICE pointer allocated and owned by the caller; the
  *     library never frees it. Complex numbers are interleaved (re, im) float pairs.
  *   - Calls are asynchronous on the context's stream; outputs are ready when that stream is.
+ *     Exceptions, which wait for the stream before they return: rb_trace_rays (it reports a
+ *     ray that exceeded max_steps), rb_frequency_step without a report, rb_frequency_sweep,
+ *     rb_frequency_step_batch, rb_autotune and rb_profile_read.
+ *   - Workspace: a context allocates device memory when a call first needs it and grows it
+ *     on demand (freeing the old block after waiting for the stream). After rb_reserve for a
+ *     geometry, no entry point allocates, frees or waits for the stream on account of its
+ *     workspace: a call that would need more than was reserved fails with RB_ENOMEM before
+ *     launching anything. A reserved context with a report pointer can therefore be captured
+ *     into a HIP graph one rb_frequency_step at a time.
  *   - Every entry point validates its arguments before launching anything and returns an
  *     rb_status; on RB_EINVAL / RB_EUNSUPPORTED nothing was launched (outputs unchanged).
  *     RB_ENONFINITE is reported after the kernels ran (outputs unspecified, except that
@@ -118,11 +127,35 @@ typedef struct {
     void *H;
 } rb_green;
 
+/* Status of one rb_frequency_step written to DEVICE memory by the step's last kernel, so
+ * that the call needs no host synchronisation (graph capture, tight loops). */
+typedef struct {
+    int32_t status;       /* RB_OK, or RB_ENONFINITE when the step committed nothing */
+    int32_t flags;        /* bit 0: a ray exceeded max_steps; bit 1: non-finite model update */
+    int32_t lost_nodes;   /* mask nodes the binning walk could not place (0 normally) */
+    int32_t reserved;
+    int64_t ray_samples;  /* ray samples the tracer wrote */
+} rb_report;
+
 typedef struct rb_ctx rb_ctx;
 
 /* Create a context on HIP device `device` that launches on `hip_stream` (a hipStream_t,
  * borrowed, may be NULL for the null stream). Returns RB_EDEVICE if the device is absent. */
 rb_status rb_create(rb_ctx **ctx, int device, void *hip_stream);
+/* Device bytes rb_reserve allocates for this geometry (workspace of every entry point with
+ * operands of any precision, the frequency step's buffers for `prec`, the mask lists), with
+ * ray samples of one tracer launch limited to sample_budget bytes (rb_set_sample_budget).
+ * Host arithmetic only; 0 if the geometry is invalid. */
+size_t rb_workspace_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
+                          rb_prec prec, size_t sample_budget);
+/* Allocate, once, every device buffer the context's entry points need for this geometry
+ * (rb_workspace_bytes with the context's sample budget) and fix it: afterwards no call
+ * allocates, frees or synchronises for workspace; a call on another grid returns RB_EINVAL,
+ * one needing more than the reservation (another ring, more rays, a frequency step of a
+ * wider precision, a larger sample budget) RB_ENOMEM, both before launching anything.
+ * Calling rb_reserve again replaces the reservation (it waits for the stream first). */
+rb_status rb_reserve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                     const rb_trace_params *tp, rb_prec prec);
 /* Release the context's workspace. The caller's buffers are untouched. */
 void rb_destroy(rb_ctx *ctx);
 /* Message of the last error of this context (static storage inside the context). */
@@ -171,7 +204,10 @@ rb_status rb_born_forward(rb_ctx *ctx, const rb_green *gr, const float *w, const
 
 /* Adjoint of rb_born_forward for real delta (Eq. functional-gradient with Q = 1):
  * grad[q] = Re{ conj(w[q]) sum_e conj(G[e][q]) sum_r R[e][r] conj(G[r][q]) }.
- * R: complex64 [n][n]; grad: float [n_mask]. RB_F32 operands only. */
+ * R: complex64 [n][n]; w: complex64 [n_mask]; grad: float [n_mask]. With 16-bit operands
+ * (RB_BF16, RB_F16) G is first transposed (node-major, conjugated) in the workspace and R is
+ * rounded to the operand type with a power-of-two range scale; every product accumulates in
+ * FP32. Only the symmetric part of R enters (the double sum is a bilinear form in conj(G)). */
 rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const float *R,
                           float *grad);
 
@@ -193,16 +229,20 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
 /* One frequency step (the unit of the benchmark). c: double [ny][nx] sound speed, updated
  * in place on the mask nodes (m <- m + tau sum_omega dm_omega, c = m^-1/2, FP64); omega and
  * d_omega: HOST arrays of n_omega values; data: complex64 [n_omega][n][n] measured Green's
- * functions (row = emitter). smooth_w: odd window of the tracing map. If any updated value
- * is not finite the model is left unchanged and RB_ENONFINITE is returned.
+ * functions (row = emitter). smooth_w: odd window of the tracing map. If a ray exceeds
+ * max_steps or any updated value is not finite the model is left unchanged.
  * residual_norm (device double, may be NULL) receives sum |g_res|^2 over all frequencies.
  * prec selects the operand type of the Born contractions (RB_F32 plain form; RB_BF16 /
- * RB_F16 reduced form); tracing, phases and the model update are the same in all forms. */
+ * RB_F16 reduced form); tracing, phases and the model update are the same in all forms.
+ * report == NULL: the call waits for the stream and returns RB_ENONFINITE for a step that
+ * committed nothing. report != NULL (device rb_report): nothing waits for the stream; the
+ * step's last kernel writes the status there and the call returns RB_OK once the step is
+ * enqueued (argument errors are still returned before any launch). */
 rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
                             int32_t n_omega, const double *omega, const double *d_omega,
                             const float *data, double tau, rb_mode mode, rb_prec prec,
-                            double *residual_norm);
+                            double *residual_norm, rb_report *report);
 
 /* Several frequency steps in a row: the frequency continuation of Section 6.3.2 (one step
  * per frequency set, sets ordered low to high by the caller). Step k uses smoothing window

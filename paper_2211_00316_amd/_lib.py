@@ -25,7 +25,8 @@ SYMBOLS = (
     "rb_backproject", "rb_frequency_step", "rb_profile_enable", "rb_profile_read",
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
     "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
-    "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking",
+    "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking", "rb_workspace_bytes",
+    "rb_reserve",
 )
 RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
@@ -57,6 +58,22 @@ class _Tables(ctypes.Structure):
 class _Green(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32), ("prec", ctypes.c_int),
                 ("G", ctypes.c_void_p), ("H", ctypes.c_void_p)]
+
+
+class Report(ctypes.Structure):
+    """rb_report (lives in device memory; this host mirror decodes a copy of it)."""
+    _fields_ = [("status", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("lost_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ray_samples", ctypes.c_int64)]
+
+
+REPORT_BYTES = ctypes.sizeof(Report)
+
+
+def decode_report(t: torch.Tensor) -> Report:
+    """A device rb_report (uint8 tensor of REPORT_BYTES) read back into a Report."""
+    raw = bytes(t.detach().cpu().numpy().tobytes())
+    return Report.from_buffer_copy(raw)
 
 
 class _ScanStep(ctypes.Structure):
@@ -114,7 +131,7 @@ def load(path: str = LIB_PATH):
         "rb_frequency_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                                ctypes.POINTER(TraceParams), P, I32, I32,
                                ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int,
-                               ctypes.c_int, P], ctypes.c_int),
+                               ctypes.c_int, P, P], ctypes.c_int),
         "rb_frequency_sweep": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                                 ctypes.POINTER(TraceParams), P, I32, ctypes.POINTER(I32),
                                 ctypes.POINTER(I32), ctypes.POINTER(D), ctypes.POINTER(D), P, D,
@@ -135,6 +152,11 @@ def load(path: str = LIB_PATH):
         "rb_set_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
         "rb_get_tuning": ([P, ctypes.POINTER(Tuning)], ctypes.c_int),
         "rb_set_receiver_linking": ([P, I32, D], ctypes.c_int),
+        "rb_workspace_bytes": ([ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                                ctypes.POINTER(TraceParams), ctypes.c_int, ctypes.c_size_t],
+                               ctypes.c_size_t),
+        "rb_reserve": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                        ctypes.POINTER(TraceParams), ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -152,6 +174,13 @@ def step_bytes(grid: Grid, ring: Ring, tp: TraceParams, prec: int, sample_budget
     """Peak device bytes of a context stepping this geometry (rb_step_bytes)."""
     return int(load().rb_step_bytes(ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp),
                                     int(prec), int(sample_budget)))
+
+
+def workspace_bytes(grid: Grid, ring: Ring, tp: TraceParams, prec: int,
+                    sample_budget: int) -> int:
+    """Device bytes rb_reserve takes for this geometry (rb_workspace_bytes)."""
+    return int(load().rb_workspace_bytes(ctypes.byref(grid), ctypes.byref(ring),
+                                         ctypes.byref(tp), int(prec), int(sample_budget)))
 
 
 @dataclasses.dataclass
@@ -335,6 +364,11 @@ class Context:
         """Receiver tables by secant ray linking (max_iter > 0) or fan interpolation (0)."""
         self._check(self.lib.rb_set_receiver_linking(self._h, int(max_iter), float(tol)))
 
+    def reserve(self, grid: Grid, ring: Ring, tp: TraceParams, prec: int):
+        """Allocate every workspace of this geometry now; later calls allocate nothing."""
+        self._check(self.lib.rb_reserve(self._h, ctypes.byref(grid), ctypes.byref(ring),
+                                        ctypes.byref(tp), int(prec)))
+
     def set_sample_budget(self, nbytes: int):
         """Bytes of ray samples one tracer launch may hold (rb_set_sample_budget)."""
         self._check(self.lib.rb_set_sample_budget(self._h, int(nbytes)))
@@ -446,17 +480,23 @@ class Context:
     def frequency_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
                        smooth_w: int, omegas, d_omegas, data: torch.Tensor, tau: float,
                        mode: int = RB_RAY_BORN, residual_norm: torch.Tensor | None = None,
-                       prec: int = RB_F32):
-        """Updates c (float64 [ny][nx], on the GPU) in place."""
+                       prec: int = RB_F32, report: torch.Tensor | None = None):
+        """Updates c (float64 [ny][nx], on the GPU) in place. report (uint8 GPU tensor of
+        REPORT_BYTES, optional): the step's status goes there and nothing waits for the
+        stream (decode it with decode_report)."""
         _dev(c, torch.float64)
         _dev(data, torch.complex64)
+        if report is not None:
+            _dev(report, torch.uint8)
+            if report.numel() < REPORT_BYTES or report.data_ptr() % 8:
+                raise ValueError("report needs REPORT_BYTES bytes, 8-byte aligned")
         k = len(omegas)
         om = (ctypes.c_double * k)(*omegas)
         dom = (ctypes.c_double * k)(*d_omegas)
         self._check(self.lib.rb_frequency_step(
             self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
             int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), int(prec),
-            _ptr(residual_norm)))
+            _ptr(residual_norm), _ptr(report)))
         return c
 
     def frequency_sweep(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,

@@ -53,6 +53,10 @@ void rb_prof_end(rb_ctx *ctx) {
 
 rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes) {
     if (bytes <= a->cap) return RB_OK;
+    if (ctx->fixed)
+        return rb_fail(ctx, RB_ENOMEM,
+                       "the call needs %zu workspace bytes, %zu were reserved (rb_reserve)", bytes,
+                       a->cap);
     if (ctx->capturing) {  // no allocation inside a graph capture: grow it and capture again
         a->want = std::max(a->want, bytes);
         return RB_ERETRY;
@@ -134,6 +138,8 @@ static int64_t mask_list(const rb_grid *g, std::vector<int32_t> *idx, std::vecto
 
 rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
     if (ctx->have_grid && std::memcmp(&ctx->grid, g, sizeof(rb_grid)) == 0) return RB_OK;
+    if (ctx->fixed)
+        return rb_fail(ctx, RB_EINVAL, "the grid differs from the one given to rb_reserve");
     if (ctx->capturing) return rb_fail(ctx, RB_EINVAL, "grid changed inside a graph capture");
     ++ctx->gen;
     std::vector<int32_t> idx, map;
@@ -210,6 +216,74 @@ static rb_status check_step_args(rb_ctx *ctx, const rb_grid *grid, const rb_ring
     if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
         return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
     return RB_OK;
+}
+
+// Workspace bytes of the standalone contractions (rb_born_adjoint, rb_backproject).
+static size_t adjoint_ws_bytes(int n, int nm, bool lp) {
+    if (!lp)
+        return rb_align((size_t)2 * rb_rowred_mblocks(n) * nm * sizeof(float)) +
+               rb_align((size_t)2 * n * n * sizeof(float));
+    const size_t np = (size_t)rb_lp_pad(n);
+    return rb_align((size_t)2 * rb_rowred_lp_mblocks(n) * nm * sizeof(float)) +
+           rb_align(2 * (size_t)n * np * sizeof(uint16_t)) + rb_align(8) +
+           rb_align(2 * (size_t)nm * np * sizeof(uint16_t));
+}
+
+static size_t backproject_ws_bytes(int n, int nm, bool lp) {
+    const int mb = lp ? rb_rowred_lp_mblocks(n) : rb_rowred_mblocks(n);
+    const size_t nnp = (size_t)n * rb_lp_pad(n);
+    return rb_align((size_t)2 * mb * nm * sizeof(float)) + rb_align(2 * nnp * sizeof(uint16_t)) +
+           rb_align(8) + rb_align(2 * (size_t)n * n * sizeof(float));
+}
+
+// Bytes of the step arena for N transducers, nm mask nodes and P grid nodes.
+static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec);
+
+struct GeomSizes {
+    int64_t nm = 0;
+    size_t tiles = 0;
+};
+
+static GeomSizes geom_sizes(const rb_grid *grid) {
+    GeomSizes gs;
+    std::vector<int32_t> idx;
+    gs.nm = mask_list(grid, &idx, nullptr);
+    if (gs.nm < 1) return gs;
+    int imin = grid->nx, imax = -1, jmin = grid->ny, jmax = -1;
+    for (int32_t p : idx) {
+        const int i = p % grid->nx, j = p / grid->nx;
+        imin = std::min(imin, i);
+        imax = std::max(imax, i);
+        jmin = std::min(jmin, j);
+        jmax = std::max(jmax, j);
+    }
+    gs.tiles = (size_t)((imax - imin + RB_WALK_TX) / RB_WALK_TX) *
+               ((jmax - jmin + RB_WALK_TY) / RB_WALK_TY);
+    return gs;
+}
+
+static int device_cus() {
+    int n_cu = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetLastError();
+    return n_cu > 0 ? n_cu : 256;
+}
+
+// Largest scratch arena any entry point takes for this geometry (any operand precision).
+static size_t ws_need(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
+                      const GeomSizes &gs, size_t sample_budget, int n_cu) {
+    const int N = ring->n, nm = (int)gs.nm;
+    const size_t P = (size_t)grid->nx * grid->ny;
+    size_t ws = rb_align(P * sizeof(double));  // smoothing
+    ws = std::max(ws, rb_trace_ws_bytes(grid, ring, tp, gs.nm, gs.tiles, sample_budget));
+    ws = std::max(ws, rb_forward_ws_bytes(N, nm));
+    ws = std::max(ws, rb_forward_lp_ws_bytes(N, nm, std::max(8, n_cu)));
+    for (int lp = 0; lp < 2; ++lp) {
+        ws = std::max(ws, adjoint_ws_bytes(N, nm, lp != 0));
+        ws = std::max(ws, backproject_ws_bytes(N, nm, lp != 0));
+    }
+    return ws;
 }
 
 extern "C" {
@@ -366,15 +440,25 @@ rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const
     if (!ctx) return RB_EINVAL;
     RB_TRY(check_green(ctx, gr));
     if (!w || !R || !grad) return rb_fail(ctx, RB_EINVAL, "w, R and grad must be non-NULL");
-    if (gr->prec != RB_F32)
-        return rb_fail(ctx, RB_EUNSUPPORTED, "the Q=1 adjoint takes RB_F32 operands only");
     RB_HIP(ctx, hipSetDevice(ctx->device));
-    int mb = rb_rowred_mblocks(gr->n);
+    const bool lp = gr->prec != RB_F32;
+    int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
     ctx->ws.used = 0;
     const size_t nn = (size_t)gr->n * gr->n;
-    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
-                                               rb_align(2 * nn * sizeof(float))));
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, adjoint_ws_bytes(gr->n, gr->n_mask, lp)));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
+    if (lp) {
+        // conj(G) node-major, R rounded with its range scale, the one-component contraction
+        const size_t np = (size_t)rb_lp_pad(gr->n);
+        uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * (size_t)gr->n * np);
+        float *rscale = rb_carve<float>(&ctx->ws, 2);
+        uint16_t *Gt = rb_carve<uint16_t>(&ctx->ws, 2 * (size_t)gr->n_mask * np);
+        RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
+        RB_TRY(rb_launch_transpose_conj(ctx, gr, Gt));
+        RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, Gt, 1, parts, &mb));
+        RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
+        return rb_launch_adjoint_finish(ctx, gr->n_mask, mb, parts, w, grad);
+    }
     float *rsym = rb_carve<float>(&ctx->ws, 2 * nn);
     RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->G, 1, 1, rsym, parts,
                             &mb));
@@ -406,9 +490,7 @@ rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const 
     size_t nn = (size_t)gr->n * gr->n;
     ctx->ws.used = 0;
     const size_t nnp = (size_t)gr->n * rb_lp_pad(gr->n);
-    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, rb_align((size_t)2 * mb * gr->n_mask * sizeof(float)) +
-                                               rb_align(2 * nnp * sizeof(uint16_t)) + rb_align(8) +
-                                               rb_align(2 * nn * sizeof(float))));
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, backproject_ws_bytes(gr->n, gr->n_mask, lp)));
     float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
     if (lp) {
         uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nnp);
@@ -444,7 +526,6 @@ struct StepBufs {
     float *parts = nullptr;
 };
 
-// Bytes of the step arena for N transducers, nm mask nodes and P grid nodes.
 static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
     const size_t NP = (size_t)N * nm, NN = (size_t)N * N;
     const size_t NPp = (size_t)rb_lp_pad(N) * nm;  // padded operand rows (16-bit form)
@@ -627,14 +708,73 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
                             int32_t n_omega, const double *omega, const double *d_omega,
                             const float *data, double tau, rb_mode mode, rb_prec prec,
-                            double *residual_norm) {
+                            double *residual_norm, rb_report *report) {
     if (!ctx) return RB_EINVAL;
     RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
                            mode, prec));
     RB_HIP(ctx, hipSetDevice(ctx->device));
+    if (!report) {
+        ctx->deferred = false;
+        return step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data,
+                            tau, mode, prec, residual_norm, 0);
+    }
+    // asynchronous form: the checks stay on the device (as in a sweep of one step) and the
+    // status goes to the caller's report
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    ctx->deferred = true;
+    rb_status st = rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0);
+    if (st == RB_OK) st = rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_FAIL_STEP, 1, -1);
+    if (st == RB_OK)
+        st = step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
+                          mode, prec, residual_norm, 0);
+    if (st == RB_OK) st = rb_launch_report(ctx, report);
     ctx->deferred = false;
-    return step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
-                        mode, prec, residual_norm, 0);
+    return st;
+}
+
+size_t rb_workspace_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
+                          rb_prec prec, size_t sample_budget) {
+    if (!grid || !ring || !tp || grid->nx < 1 || grid->ny < 1 || ring->n < 1 || tp->n_rays < 1 ||
+        tp->max_steps < 1 || (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16))
+        return 0;
+    const GeomSizes gs = geom_sizes(grid);
+    if (gs.nm < 1) return 0;
+    const size_t P = (size_t)grid->nx * grid->ny;
+    const size_t lists = rb_align((size_t)gs.nm * 4) + rb_align(P * 4);
+    return step_arena_bytes(ring->n, (int)gs.nm, P, prec) +
+           ws_need(grid, ring, tp, gs, sample_budget, device_cus()) + lists;
+}
+
+rb_status rb_reserve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                     const rb_trace_params *tp, rb_prec prec) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    RB_TRY(rb_check_trace(ctx, tp));
+    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
+        return rb_fail(ctx, RB_EINVAL, "unknown operand precision %d", (int)prec);
+    if (ctx->capturing) return rb_fail(ctx, RB_EINVAL, "rb_reserve inside a graph capture");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    ctx->fixed = false;
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    const GeomSizes gs = geom_sizes(grid);
+    const size_t P = (size_t)grid->nx * grid->ny;
+    const size_t step = step_arena_bytes(ring->n, (int)gs.nm, P, prec);
+    const size_t ws = ws_need(grid, ring, tp, gs, ctx->sample_budget, ctx->n_cu);
+    // exactly these sizes: release larger blocks of an earlier geometry as well
+    for (rb_arena *a : {&ctx->step, &ctx->ws}) {
+        const size_t want = a == &ctx->step ? step : ws;
+        if (a->base && a->cap != want) {
+            RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            RB_HIP(ctx, hipFree(a->base));
+            a->base = nullptr;
+            a->cap = 0;
+            ++ctx->gen;
+        }
+        RB_TRY(rb_arena_reserve(ctx, a, want));
+    }
+    ctx->fixed = true;
+    return RB_OK;
 }
 
 size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
@@ -642,26 +782,13 @@ size_t rb_step_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_pa
     if (!grid || !ring || !tp || grid->nx < 1 || grid->ny < 1 || ring->n < 1 || tp->n_rays < 1 ||
         tp->max_steps < 1)
         return 0;
-    std::vector<int32_t> idx;
-    const int64_t nm = mask_list(grid, &idx, nullptr);
+    const GeomSizes gs = geom_sizes(grid);
+    const int64_t nm = gs.nm;
     if (nm < 1) return 0;
-    int imin = grid->nx, imax = -1, jmin = grid->ny, jmax = -1;
-    for (int32_t p : idx) {
-        const int i = p % grid->nx, j = p / grid->nx;
-        imin = std::min(imin, i);
-        imax = std::max(imax, i);
-        jmin = std::min(jmin, j);
-        jmax = std::max(jmax, j);
-    }
-    const size_t tiles = (size_t)((imax - imin + RB_WALK_TX) / RB_WALK_TX) *
-                         ((jmax - jmin + RB_WALK_TY) / RB_WALK_TY);
+    const size_t tiles = gs.tiles;
     const size_t P = (size_t)grid->nx * grid->ny;
     const int N = ring->n;
-    int n_cu = 256;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipGetLastError();
+    const int n_cu = device_cus();
     size_t ws = rb_align(P * sizeof(double));  // smoothing
     ws = std::max(ws, rb_trace_ws_bytes(grid, ring, tp, nm, tiles, sample_budget));
     ws = std::max(ws, prec == RB_F32 ? rb_forward_ws_bytes(N, (int)nm)

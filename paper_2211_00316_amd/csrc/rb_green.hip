@@ -203,6 +203,17 @@ __global__ void note_fail_kernel(int32_t *flag, int step) {
         flag[RB_W_FAIL_STEP] = step;
 }
 
+// Status of a step for the caller, from the context's device words (no host round trip).
+__global__ void report_kernel(const int32_t *__restrict__ flag, rb_report *__restrict__ rep) {
+    if (threadIdx.x != 0) return;
+    const int32_t fl = flag[RB_W_FLAGS];
+    rep->status = fl ? (int32_t)RB_ENONFINITE : (int32_t)RB_OK;
+    rep->flags = fl;
+    rep->lost_nodes = flag[RB_W_LOST];
+    rep->reserved = 0;
+    rep->ray_samples = *reinterpret_cast<const int64_t *>(flag + RB_W_SAMPLES);
+}
+
 __global__ void fill_i32(int32_t *x, int n, int32_t v) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < n) x[q] = v;
@@ -321,6 +332,12 @@ rb_status rb_launch_commit(rb_ctx *ctx, const double *c_new, double *c, const in
 
 rb_status rb_launch_note_fail(rb_ctx *ctx, int step) {
     hipLaunchKernelGGL(note_fail_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_flag, step);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_report(rb_ctx *ctx, rb_report *rep) {
+    hipLaunchKernelGGL(report_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_flag, rep);
     RB_CHECK_LAUNCH(ctx);
     return RB_OK;
 }

@@ -82,6 +82,9 @@ struct rb_ctx {
     // stay in d_flag and the commit kernel skips the update once any is set.
     bool deferred = false;
     bool capturing = false;           // a graph capture is in progress on `stream`
+    // rb_reserve: workspaces are fixed (no allocation, free or host wait after it); a call
+    // needing more fails with RB_ENOMEM, a call on another grid with RB_EINVAL
+    bool fixed = false;
     uint64_t gen = 0;                 // bumped whenever a device buffer is reallocated
     hipStream_t cap_stream = nullptr; // library stream the sweep is captured on
     hipGraphExec_t gexec = nullptr;   // cached sweep graph
@@ -101,6 +104,8 @@ enum rb_stage {
     ST_SMOOTH = 0, ST_TRACE, ST_RASTER, ST_RESOLVE, ST_RECEIVERS, ST_GREEN, ST_FORWARD,
     ST_FORWARD_REDUCE, ST_RESIDUAL, ST_BACKPROJECT, ST_FINISH, ST_UPDATE
 };
+// Copy the context's status words into a caller's device rb_report (one small kernel).
+rb_status rb_launch_report(rb_ctx *ctx, rb_report *rep);
 // Fill n int32 words with a value (a kernel: also inside graph captures).
 rb_status rb_launch_fill_i32(rb_ctx *ctx, int32_t *x, int n, int32_t value);
 // Record the start / end event of a launch of `stage` (no-ops unless profiling is on).
@@ -202,6 +207,8 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
                               float *scale);
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);
+// 16-bit G [2][n][m_pad] -> conj(G) node-major [2][n_mask][n_pad] (operand of the adjoint).
+rb_status rb_launch_transpose_conj(rb_ctx *ctx, const rb_green *gr, void *Gt);
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,

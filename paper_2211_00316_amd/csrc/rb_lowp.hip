@@ -323,6 +323,39 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     }
 }
 
+// conj(G) in the back-projection's operand layout, for the 16-bit adjoint: G planar
+// [2][n][Mp] (rows over nodes) -> planar node-major [2][n_mask][Np] with the imaginary part
+// negated and zeros past n. The adjoint's double sum is the bilinear form h^T R h with
+// h = conj(G), the same contraction as the back-projection's with h = H. Raw 16-bit words
+// (both types keep the sign in bit 15); a 64 x 64 tile per workgroup through LDS.
+__global__ void __launch_bounds__(256) transpose_conj_kernel(const uint16_t *__restrict__ Gp,
+                                                             int n, int n_mask,
+                                                             uint16_t *__restrict__ Gt) {
+    __shared__ uint16_t tile[2][64][66];
+    const int q0 = blockIdx.x * 64, e0 = blockIdx.y * 64;
+    const int Mp = rb_lp_pad(n_mask), Np = rb_lp_pad(n);
+    const size_t gplane = (size_t)n * Mp, tplane = (size_t)n_mask * Np;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int e = e0 + r, q = q0 + tx;
+        uint16_t vr = 0, vi = 0;
+        if (e < n && q < n_mask) {
+            vr = Gp[(size_t)e * Mp + q];
+            vi = Gp[gplane + (size_t)e * Mp + q] ^ (uint16_t)0x8000u;
+        }
+        tile[0][r][tx] = vr;
+        tile[1][r][tx] = vi;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int q = q0 + r, e = e0 + tx;
+        if (q < n_mask && e < Np) {
+            Gt[(size_t)q * Np + e] = tile[0][tx][r];
+            Gt[tplane + (size_t)q * Np + e] = tile[1][tx][r];
+        }
+    }
+}
+
 // Power-of-two range scale of an operand: scale[0] = 2^(top - e) and scale[1] = 1/scale[0]
 // with 2^(e-1) <= max |x| < 2^e, so the largest scaled magnitude lies in [2^(top-1), 2^top)
 // (top = 14: inside the FP16 range, far from its subnormals). |x| of a complex value is the
@@ -1185,6 +1218,15 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
                            (const float2 *)R, n, np, LR_BM, scale, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_transpose_conj(rb_ctx *ctx, const rb_green *gr, void *Gt) {
+    const int Np = rb_lp_pad(gr->n);
+    dim3 grd((gr->n_mask + 63) / 64, (Np + 63) / 64);
+    hipLaunchKernelGGL(transpose_conj_kernel, grd, dim3(256), 0, ctx->stream,
+                       (const uint16_t *)gr->G, gr->n, gr->n_mask, (uint16_t *)Gt);
+    RB_CHECK_LAUNCH(ctx);
     return RB_OK;
 }
 

@@ -82,3 +82,24 @@ def test_step_bytes_is_host_arithmetic(lib):
     assert _lib.step_bytes(g, r, tp, _lib.RB_F32, 1 << 34) > big   # FP32 operands are wider
     bad = _lib.Grid(0, 128, 0.8e-3, -50.8e-3, -50.8e-3, 0.045)
     assert _lib.step_bytes(bad, r, tp, _lib.RB_BF16, 1 << 30) == 0
+
+
+def test_workspace_bytes_is_host_arithmetic(lib):
+    # rb_workspace_bytes (what rb_reserve allocates) needs no GPU: it covers the step's own
+    # buffers, grows with the sample budget until one tracer launch holds every transducer,
+    # and is 0 for an invalid geometry or precision.
+    from paper_2211_00316_amd import _lib
+
+    g = _lib.Grid(128, 128, 0.8e-3, -50.8e-3, -50.8e-3, 0.045)
+    r = _lib.Ring(64, 0.05, 0.0)
+    tp = _lib.TraceParams(360, 628, 0.2e-3, 1500.0)
+    for prec in (_lib.RB_F32, _lib.RB_BF16, _lib.RB_F16):
+        small = _lib.workspace_bytes(g, r, tp, prec, 1 << 24)
+        big = _lib.workspace_bytes(g, r, tp, prec, 1 << 34)
+        assert 0 < small < big == _lib.workspace_bytes(g, r, tp, prec, 1 << 40)
+        # the step buffers and every standalone entry point's workspace, beyond what a
+        # context that only steps needs (minus the context's few fixed words)
+        assert big >= _lib.step_bytes(g, r, tp, prec, 1 << 34) - 8192
+    bad = _lib.Grid(0, 128, 0.8e-3, -50.8e-3, -50.8e-3, 0.045)
+    assert _lib.workspace_bytes(bad, r, tp, _lib.RB_BF16, 1 << 30) == 0
+    assert _lib.workspace_bytes(g, r, tp, 7, 1 << 30) == 0
