@@ -124,7 +124,8 @@ def test_single_step_captured_by_the_caller(pname):
         torch.cuda.synchronize()
         _say(f"  replay {k}")
         assert torch.equal(c_g, c_eager)
-        assert torch.equal(rn, rn_eager)
+        # the residual norm adds per-workgroup sums with atomics: equal up to their order
+        assert torch.allclose(rn, rn_eager, rtol=1e-12, atol=0)
         assert _lib.decode_report(rep).status == _lib.RB_OK
         # eager work of the program between replays
         x = torch.randn(1 << 20, device="cuda:0")
