@@ -226,6 +226,20 @@ rb_status rb_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
 rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
                          double omega, double d_omega, float *dm, int32_t accumulate);
 
+/* rb_backproject without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, hosts that forbid it): the same kernels
+ * and result, with the partial sums and the rounded residual in a fixed 64 MiB device array
+ * of the library (one per GPU, held until the process ends) instead of the context's
+ * workspace. The array's address on a device is taken at the first rb_create there. Sizes
+ * whose scratch exceeds 64 MiB (about 2 (n/256 + 1) n_mask 4 + 12 n^2 bytes; n = 1024 with
+ * 636 160 mask nodes takes 33 MB) return RB_EINVAL before any launch. Every call on one GPU
+ * shares the array: calls that overlap on a GPU (different streams or contexts) race and
+ * must be ordered by the caller. Nothing needs to be zero beforehand: every scratch word a
+ * call reads it has written itself. */
+rb_status rb_backproject_noalloc(rb_ctx *ctx, const rb_green *gr, const float *R,
+                                 const double *c_mask, double omega, double d_omega, float *dm,
+                                 int32_t accumulate);
+
 /* One frequency step (the unit of the benchmark). c: double [ny][nx] sound speed, updated
  * in place on the mask nodes (m <- m + tau sum_omega dm_omega, c = m^-1/2, FP64); omega and
  * d_omega: HOST arrays of n_omega values; data: complex64 [n_omega][n][n] measured Green's

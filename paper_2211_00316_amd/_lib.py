@@ -26,7 +26,7 @@ SYMBOLS = (
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
     "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
     "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking", "rb_workspace_bytes",
-    "rb_reserve",
+    "rb_reserve", "rb_backproject_noalloc",
 )
 RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
         "rb_born_adjoint": ([P, ctypes.POINTER(_Green), P, P, P], ctypes.c_int),
         "rb_residual": ([P, ctypes.POINTER(_Tables), D, D, P, P, P], ctypes.c_int),
         "rb_backproject": ([P, ctypes.POINTER(_Green), P, P, D, D, P, I32], ctypes.c_int),
+        "rb_backproject_noalloc": ([P, ctypes.POINTER(_Green), P, P, D, D, P, I32],
+                                   ctypes.c_int),
         "rb_frequency_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                                ctypes.POINTER(TraceParams), P, I32, I32,
                                ctypes.POINTER(D), ctypes.POINTER(D), P, D, ctypes.c_int,
@@ -476,6 +478,20 @@ class Context:
         self._check(self.lib.rb_backproject(self._h, ctypes.byref(g), _ptr(R), _ptr(c_mask),
                                             omega, d_omega, _ptr(dm), int(accumulate)))
         return dm
+
+    def backproject_noalloc(self, gr: Green, R: torch.Tensor, c_mask: torch.Tensor,
+                            omega: float, d_omega: float, out: torch.Tensor,
+                            accumulate: bool = False) -> torch.Tensor:
+        """rb_backproject_noalloc: the back-projection into the caller's `out`, with the
+        library's fixed scratch (no device allocation by the library)."""
+        _dev(R, torch.complex64)
+        _dev(c_mask, torch.float64)
+        _dev(out, torch.float32)
+        g = gr.struct()
+        self._check(self.lib.rb_backproject_noalloc(self._h, ctypes.byref(g), _ptr(R),
+                                                    _ptr(c_mask), omega, d_omega, _ptr(out),
+                                                    int(accumulate)))
+        return out
 
     def frequency_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
                        smooth_w: int, omegas, d_omegas, data: torch.Tensor, tau: float,

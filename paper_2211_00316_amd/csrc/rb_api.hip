@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 rb_status rb_launch_gather_mask(rb_ctx *ctx, const double *c, double *cq);
@@ -218,6 +219,39 @@ static rb_status check_step_args(rb_ctx *ctx, const rb_grid *grid, const rb_ring
     return RB_OK;
 }
 
+// Scratch of the allocation-free back-projection (rb_backproject_noalloc): one file-scope
+// device array per GPU, held by the loaded code object until the process ends. In host code
+// `scratch` names a host-side stand-in; its device address on each GPU comes from
+// hipGetSymbolAddress (once per device, at the first rb_create there) and only that address
+// is used.
+static __device__ __align__(256) char scratch[RB_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// With ctx->device current: record the device address of `scratch` on this device.
+static rb_status scratch_setup(rb_ctx *ctx) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= kMaxDevices) return RB_OK;  // the allocation-free form reports it
+    if (g_scratch_ptr[ctx->device]) return RB_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return RB_EDEVICE;
+    }
+    g_scratch_ptr[ctx->device] = p;
+    return RB_OK;
+}
+
+static void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
 // Workspace bytes of the standalone contractions (rb_born_adjoint, rb_backproject).
 static size_t adjoint_ws_bytes(int n, int nm, bool lp) {
     if (!lp)
@@ -305,6 +339,10 @@ rb_status rb_create(rb_ctx **out, int device, void *hip_stream) {
         hipHostMalloc(&ctx->h_flag, RB_W_COUNT * sizeof(int32_t), hipHostMallocDefault) !=
             hipSuccess ||
         hipMemset(ctx->d_flag, 0, RB_W_COUNT * sizeof(int32_t)) != hipSuccess) {
+        rb_destroy(ctx);
+        return RB_EDEVICE;
+    }
+    if (scratch_setup(ctx) != RB_OK) {
         rb_destroy(ctx);
         return RB_EDEVICE;
     }
@@ -477,34 +515,77 @@ rb_status rb_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
     return rb_launch_residual(ctx, tb, omega, c0, d_born, data, R, nullptr);
 }
 
-rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
-                         double omega, double d_omega, float *dm, int32_t accumulate) {
-    if (!ctx) return RB_EINVAL;
+static rb_status check_backproject(rb_ctx *ctx, const rb_green *gr, const float *R,
+                                   const double *c_mask, double omega, double d_omega,
+                                   const float *dm) {
     RB_TRY(check_green(ctx, gr));
     if (!R || !c_mask || !dm) return rb_fail(ctx, RB_EINVAL, "R, c_mask and dm must be non-NULL");
     if (!finite_pos(omega) || !finite_pos(d_omega))
         return rb_fail(ctx, RB_EINVAL, "omega and d_omega must be positive");
-    RB_HIP(ctx, hipSetDevice(ctx->device));
+    return RB_OK;
+}
+
+// The back-projection's launches with their scratch (partial sums, the residual operand)
+// carved from `a`, which holds at least backproject_ws_bytes.
+static rb_status backproject_with(rb_ctx *ctx, rb_arena *a, const rb_green *gr, const float *R,
+                                  const double *c_mask, double omega, double d_omega, float *dm,
+                                  int32_t accumulate) {
     const bool lp = gr->prec != RB_F32;
     int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
-    size_t nn = (size_t)gr->n * gr->n;
-    ctx->ws.used = 0;
+    const size_t nn = (size_t)gr->n * gr->n;
     const size_t nnp = (size_t)gr->n * rb_lp_pad(gr->n);
-    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, backproject_ws_bytes(gr->n, gr->n_mask, lp)));
-    float *parts = rb_carve<float>(&ctx->ws, (size_t)2 * mb * gr->n_mask);
+    a->used = 0;
+    float *parts = rb_carve<float>(a, (size_t)2 * mb * gr->n_mask);
     if (lp) {
-        uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * nnp);
-        float *rscale = rb_carve<float>(&ctx->ws, 2);
+        uint16_t *Rp = rb_carve<uint16_t>(a, 2 * nnp);
+        float *rscale = rb_carve<float>(a, 2);
         RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
         RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb));
         RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
     } else {
-        float *rsym = rb_carve<float>(&ctx->ws, 2 * nn);
+        float *rsym = rb_carve<float>(a, 2 * nn);
         RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, rsym,
                                 parts, &mb));
     }
     return rb_launch_backproject_finish(ctx, gr->n_mask, mb, parts, c_mask, omega, d_omega, dm,
                                         accumulate);
+}
+
+rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
+                         double omega, double d_omega, float *dm, int32_t accumulate) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_backproject(ctx, gr, R, c_mask, omega, d_omega, dm));
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws,
+                            backproject_ws_bytes(gr->n, gr->n_mask, gr->prec != RB_F32)));
+    return backproject_with(ctx, &ctx->ws, gr, R, c_mask, omega, d_omega, dm, accumulate);
+}
+
+rb_status rb_backproject_noalloc(rb_ctx *ctx, const rb_green *gr, const float *R,
+                                 const double *c_mask, double omega, double d_omega, float *dm,
+                                 int32_t accumulate) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_backproject(ctx, gr, R, c_mask, omega, d_omega, dm));
+    const size_t need = backproject_ws_bytes(gr->n, gr->n_mask, gr->prec != RB_F32);
+    if (need > RB_SCRATCH_BYTES)
+        return rb_fail(ctx, RB_EINVAL,
+                       "n = %d, n_mask = %d needs %zu scratch bytes; the allocation-free "
+                       "back-projection holds %zu",
+                       gr->n, gr->n_mask, need, (size_t)RB_SCRATCH_BYTES);
+    void *base = scratch_of(ctx->device);
+    if (!base)
+        return rb_fail(ctx, RB_EDEVICE, "no scratch address for device %d", ctx->device);
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    rb_arena a;
+    a.base = static_cast<char *>(base);
+    a.cap = RB_SCRATCH_BYTES;
+    // profiling creates its events on first use: off for this call
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    const rb_status st = backproject_with(ctx, &a, gr, R, c_mask, omega, d_omega, dm, accumulate);
+    ctx->prof = prof;
+    return st;
 }
 
 // One frequency step (rows a1-a9) enqueued on ctx->stream. With ctx->deferred nothing

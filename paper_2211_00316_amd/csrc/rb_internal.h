@@ -36,6 +36,9 @@ struct rb_arena {
 #define RB_WALK_TX 16
 #define RB_WALK_TY 16
 
+// Scratch bytes of the allocation-free back-projection (one device array per GPU).
+#define RB_SCRATCH_BYTES ((size_t)64 << 20)
+
 // Scans one batch (and one grouped launch) may hold.
 #define RB_GROUP_MAX 16
 
