@@ -35,11 +35,33 @@ class StepSetup:
     c0: float = C0
 
 
-def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None, link=None):
+def _tables_of_chunk(args):
+    ns, st, emitters = args
+    s = trace(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps, emitters=emitters,
+              c0=st.c0)
+    return binning.tables(s, st.grid, st.ring, st.ds, st.max_steps, emitters=emitters, c0=st.c0)
+
+
+def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None, link=None,
+               workers=None):
     """Trace on box_window(c0/c) and bin; returns (Tables, n_s). link (None, or a dict of
     oracle.linking options): receiver tables from the linked rays instead of the fan's
-    interpolation in exit angle."""
+    interpolation in exit angle. workers > 1: the transducers are traced and binned in that
+    many processes, in chunks whose table rows are stacked in order (each row depends on its
+    own transducer's rays only, so the tables are the same)."""
     ns = box_smooth(refractive_index(c, st.c0), window)
+    if workers and workers > 1 and link is None:
+        import concurrent.futures
+        import multiprocessing
+
+        em = np.arange(st.ring.n) if emitters is None else np.asarray(emitters)
+        chunks = [ch for ch in np.array_split(em, min(len(em), 4 * workers)) if ch.size]
+        ctx = multiprocessing.get_context("fork")
+        with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+            parts = list(ex.map(_tables_of_chunk, [(ns, st, ch) for ch in chunks]))
+        cat = {f.name: np.concatenate([getattr(t, f.name) for t in parts])
+               for f in dataclasses.fields(binning.Tables)}
+        return binning.Tables(**cat), ns
     s = trace(ns, st.grid, st.ring, st.n_rays, st.ds, st.max_steps, emitters=emitters,
               c0=st.c0)
     tb = binning.tables(s, st.grid, st.ring, st.ds, st.max_steps, emitters=emitters, c0=st.c0)
@@ -83,10 +105,11 @@ def update(c: np.ndarray, dm_mask: np.ndarray, tau: float, grid: Grid):
 
 
 def frequency_step(c, st: StepSetup, omegas, d_omegas, data, tau, window=1,
-                   mode="ray_born", isochron_sign=1.0, return_parts=False, link=None):
+                   mode="ray_born", isochron_sign=1.0, return_parts=False, link=None,
+                   workers=None):
     """One Hessian-free update of the sound speed c (ny, nx) from the data of the frequency
-    set omegas (data shape (n_omega, N_e, N_r)); link as in tables_for."""
-    tb, ns = tables_for(c, st, window, link=link)
+    set omegas (data shape (n_omega, N_e, N_r)); link and workers as in tables_for."""
+    tb, ns = tables_for(c, st, window, link=link, workers=workers)
     q = st.grid.mask_index()
     cq = c.ravel()[q]
     dm = np.zeros(q.size)
@@ -105,7 +128,7 @@ def frequency_step(c, st: StepSetup, omegas, d_omegas, data, tau, window=1,
 
 
 def synthesize(c_true, st: StepSetup, omegas, noise, background="water", window=1,
-               noise_level=0.01):
+               noise_level=0.01, workers=None):
     """Synthetic measured data: ray-Born prediction about a background plus noise.
 
     background="water": g(water) + F[water](m_true - m_water) (first-order data about water);
@@ -115,11 +138,11 @@ def synthesize(c_true, st: StepSetup, omegas, noise, background="water", window=
     N = st.ring.n
     if background == "water":
         cw = np.full_like(c_true, st.c0)
-        tb, ns = tables_for(cw, st, 1)
+        tb, ns = tables_for(cw, st, 1, workers=workers)
         q = st.grid.mask_index()
         dm = 1.0 / c_true.ravel()[q] ** 2 - 1.0 / st.c0 ** 2
     else:
-        tb, ns = tables_for(c_true, st, window)
+        tb, ns = tables_for(c_true, st, window, workers=workers)
     out = np.zeros((len(omegas), N, N), dtype=np.complex128)
     keep = tb.rx_valid & ~np.eye(N, dtype=bool)
     for k, om in enumerate(omegas):

@@ -79,3 +79,20 @@ def test_residual_masks_diagonal_and_invalid_pairs():
     valid[1, 2] = False
     R = step.residual(g, data, valid)
     assert np.all(np.diag(R) == 0) and R[1, 2] == 0 and R[2, 1] == 1
+
+
+def test_tables_in_worker_processes_are_the_same():
+    # the process-parallel table builder stacks the rows of transducer chunks: identical
+    # tables to the one-process build
+    from oracle import step as ostep
+    from tests.oracle_fixtures import small_setup
+    import phantoms as ph
+
+    st = small_setup(N=12, R=0.012, dx=0.5e-3, n_rays=60)
+    g = st.grid
+    c = ph.gaussian_inclusion(g.nx, g.ny, g.dx, g.x0, g.y0, seed=4, amp=30.0, sigma=2e-3,
+                              centre_radius=3e-3, mask_radius=g.mask_radius)
+    a, _ = ostep.tables_for(c, st, 3)
+    b, _ = ostep.tables_for(c, st, 3, workers=3)
+    for f in ("valid", "T", "A", "ux", "uy", "K", "rx_valid", "rx_T", "rx_A", "rx_K"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
