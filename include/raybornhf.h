@@ -56,7 +56,12 @@ typedef enum {
     RB_EUNSUPPORTED = -5  /* requested mode / precision not available */
 } rb_status;
 
-typedef enum { RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3 } rb_prec;
+/* Operand type of the Born contractions. RB_F16X: FP16 operands, with the back-projection
+ * operand H stored as two FP16 parts, h = h_hi + h_lo (h_lo: the rounding error of h_hi),
+ * and the back-projection's epilogue weighting the low part twice against R h_hi (R's whole
+ * symmetric part): the bilinear form h^T R h is then free of the first-order rounding of h,
+ * which dominates the error of the plain 16-bit forms. */
+typedef enum { RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3, RB_F16X = 4 } rb_prec;
 
 /* Predicted data of the frequency step: ray Green's function at the receivers plus, in
  * RB_RAY_BORN mode, the first-order Born term of the part of the model removed by the
@@ -118,13 +123,21 @@ typedef struct {
  *            G planar [2 (re, im)][n][m_pad], m_pad = n_mask rounded up to a multiple of
  *            32;  H planar, node-major [3][2 (re, im)][n_mask][n_pad] (transducer index
  *            contiguous), n_pad = n rounded up to a multiple of 32. rb_build_green writes
- *            zeros past n_mask in G and past n in H. */
+ *            zeros past n_mask in G and past n in H.
+ *   RB_F16X: as RB_F16, with H followed by its low parts: [2 (hi, lo)][3][2][n_mask][n_pad].
+ *            scales float [2][n]: per-transducer powers of two s_e (row e of G) and t_e
+ *            (the rows of transducer e in H), chosen by rb_build_green from the largest
+ *            amplitude of each row so that the row's largest value sits near 2^13 before it
+ *            is rounded: the stored operands are s_e G[e] and t_e H[e]. The contractions
+ *            divide the scales out exactly. A caller filling 16-bit operands itself sets
+ *            them (ones: unscaled). Not used for RB_F32 (may be NULL). */
 typedef struct {
     int32_t n;
     int32_t n_mask;
     rb_prec prec;
     void *G;
     void *H;
+    float *scales;
 } rb_green;
 
 /* Status of one rb_frequency_step written to DEVICE memory by the step's last kernel, so

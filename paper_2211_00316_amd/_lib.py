@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libraybornhf.so")
 
 RB_OK, RB_EINVAL, RB_ENOMEM, RB_EDEVICE, RB_ENONFINITE, RB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-RB_F32, RB_BF16, RB_F16 = 1, 2, 3
+RB_F32, RB_BF16, RB_F16, RB_F16X = 1, 2, 3, 4
 RB_RAY_BORN, RB_RAY_ONLY = 0, 1
 
 SYMBOLS = (
@@ -57,7 +57,7 @@ class _Tables(ctypes.Structure):
 
 class _Green(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_mask", ctypes.c_int32), ("prec", ctypes.c_int),
-                ("G", ctypes.c_void_p), ("H", ctypes.c_void_p)]
+                ("G", ctypes.c_void_p), ("H", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -278,7 +278,7 @@ class Tables:
                                                        self.rx_flags)))
 
 
-_LP_DTYPE = {RB_BF16: torch.bfloat16, RB_F16: torch.float16}
+_LP_DTYPE = {RB_BF16: torch.bfloat16, RB_F16: torch.float16, RB_F16X: torch.float16}
 
 
 @dataclasses.dataclass
@@ -286,12 +286,14 @@ class Green:
     """Device tensors of rb_green.
 
     RB_F32: G complex64 [n][n_mask], H complex64 [3][n][n_mask].
-    RB_BF16 / RB_F16: G planar [2][n][n_mask], H planar node-major [3][2][n_mask][n_pad]
-    (n_pad = n rounded up to 32)."""
+    RB_BF16 / RB_F16: G planar [2][n][m_pad], H planar node-major [3][2][n_mask][n_pad]
+    (pads: rounded up to 32), scales float32 [2][n] (per-row powers of two of G and H; the
+    stored operands carry them). RB_F16X: as RB_F16 with H [2 (hi, lo)][3][2][n_mask][n_pad]."""
 
     G: torch.Tensor
     H: torch.Tensor
     prec: int = RB_F32
+    scales: torch.Tensor | None = None
 
     @classmethod
     def empty(cls, n, n_mask, device, prec=RB_F32):
@@ -301,8 +303,10 @@ class Green:
         dt = _LP_DTYPE[prec]
         n_pad = (n + 31) // 32 * 32
         m_pad = (n_mask + 31) // 32 * 32
+        hshape = (3, 2, n_mask, n_pad) if prec != RB_F16X else (2, 3, 2, n_mask, n_pad)
         return cls(torch.empty(2, n, m_pad, dtype=dt, device=device),
-                   torch.empty(3, 2, n_mask, n_pad, dtype=dt, device=device), prec)
+                   torch.empty(*hshape, dtype=dt, device=device), prec,
+                   torch.ones(2, n, dtype=torch.float32, device=device))
 
     @property
     def n(self):
@@ -310,25 +314,30 @@ class Green:
 
     @property
     def n_mask(self):
-        return self.G.shape[-1] if self.prec == RB_F32 else self.H.shape[2]
+        return self.G.shape[-1] if self.prec == RB_F32 else self.H.shape[-2]
 
     def complex_G(self):
-        """G as complex [n][n_mask] (float32 parts), for checks."""
+        """G as complex [n][n_mask] (float32 parts, row scales divided out), for checks."""
         if self.prec == RB_F32:
             return self.G
         m = self.n_mask
-        return torch.complex(self.G[0, :, :m].float(), self.G[1, :, :m].float())
+        s = self.scales[0][:, None]
+        return torch.complex(self.G[0, :, :m].float() / s, self.G[1, :, :m].float() / s)
 
     def complex_H(self):
-        """H, H u_x, H u_y as complex [3][n][n_mask], for checks."""
+        """H, H u_x, H u_y as complex [3][n][n_mask] (row scales divided out), for checks."""
         if self.prec == RB_F32:
             return self.H
         n = self.n
-        return torch.complex(self.H[:, 0, :, :n].float(),
-                             self.H[:, 1, :, :n].float()).transpose(1, 2)
+        t = self.scales[1][None, :, None]
+        H = self.H.float()
+        if self.prec == RB_F16X:
+            H = H[0] + H[1]   # high and low parts
+        return torch.complex(H[:, 0, :, :n], H[:, 1, :, :n]).transpose(1, 2) / t
 
     def struct(self):
-        return _Green(self.n, self.n_mask, self.prec, self.G.data_ptr(), self.H.data_ptr())
+        return _Green(self.n, self.n_mask, self.prec, self.G.data_ptr(), self.H.data_ptr(),
+                      self.scales.data_ptr() if self.scales is not None else None)
 
 
 class Context:

@@ -191,8 +191,10 @@ static rb_status check_green(rb_ctx *ctx, const rb_green *gr) {
     if (!gr) return rb_fail(ctx, RB_EINVAL, "green operands are NULL");
     if (gr->n < 1 || gr->n_mask < 1 || !gr->G || !gr->H)
         return rb_fail(ctx, RB_EINVAL, "green operands incomplete");
-    if (gr->prec != RB_F32 && gr->prec != RB_BF16 && gr->prec != RB_F16)
+    if (!rb_prec_valid(gr->prec))
         return rb_fail(ctx, RB_EINVAL, "unknown operand precision %d", (int)gr->prec);
+    if (gr->prec != RB_F32 && !gr->scales)
+        return rb_fail(ctx, RB_EINVAL, "16-bit operands need their per-row scales");
     return RB_OK;
 }
 
@@ -214,8 +216,7 @@ static rb_status check_step_args(rb_ctx *ctx, const rb_grid *grid, const rb_ring
     if (!std::isfinite(tau)) return rb_fail(ctx, RB_EINVAL, "tau must be finite");
     if (mode != RB_RAY_BORN && mode != RB_RAY_ONLY)
         return rb_fail(ctx, RB_EINVAL, "unknown mode");
-    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
-        return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
+    if (!rb_prec_valid(prec)) return rb_fail(ctx, RB_EINVAL, "unknown operand precision");
     return RB_OK;
 }
 
@@ -251,6 +252,16 @@ static void *scratch_of(int device) {
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
 }
+
+// Low parts of a split operand's H (they follow the three components' planes), or NULL.
+static const void *h_low(const rb_green *gr) {
+    if (!rb_prec_split(gr->prec)) return nullptr;
+    return static_cast<const char *>(gr->H) +
+           6 * (size_t)gr->n_mask * rb_lp_pad(gr->n) * sizeof(uint16_t);
+}
+
+// Workspace of rb_build_green with 16-bit operands: the tables' per-row amplitude maxima.
+static size_t green_ws_bytes(int n) { return rb_align((size_t)2 * n * sizeof(unsigned int)); }
 
 // Workspace bytes of the standalone contractions (rb_born_adjoint, rb_backproject).
 static size_t adjoint_ws_bytes(int n, int nm, bool lp) {
@@ -313,6 +324,7 @@ static size_t ws_need(const rb_grid *grid, const rb_ring *ring, const rb_trace_p
     ws = std::max(ws, rb_trace_ws_bytes(grid, ring, tp, gs.nm, gs.tiles, sample_budget));
     ws = std::max(ws, rb_forward_ws_bytes(N, nm));
     ws = std::max(ws, rb_forward_lp_ws_bytes(N, nm, std::max(8, n_cu)));
+    ws = std::max(ws, green_ws_bytes(N));
     for (int lp = 0; lp < 2; ++lp) {
         ws = std::max(ws, adjoint_ws_bytes(N, nm, lp != 0));
         ws = std::max(ws, backproject_ws_bytes(N, nm, lp != 0));
@@ -457,8 +469,12 @@ rb_status rb_build_green(rb_ctx *ctx, const rb_tables *tb, double omega, double 
     if (!finite_pos(omega) || !finite_pos(c0))
         return rb_fail(ctx, RB_EINVAL, "omega and c0 must be positive");
     RB_HIP(ctx, hipSetDevice(ctx->device));
-    if (out->prec != RB_F32)
-        return rb_launch_green_lp(ctx, tb, omega, c0, out, nullptr, nullptr, 1);
+    if (out->prec != RB_F32) {
+        ctx->ws.used = 0;
+        RB_TRY(rb_arena_reserve(ctx, &ctx->ws, green_ws_bytes(tb->n)));
+        unsigned int *rowmax = rb_carve<unsigned int>(&ctx->ws, 2 * (size_t)tb->n);
+        return rb_launch_green_lp(ctx, tb, omega, c0, out, nullptr, nullptr, 1, rowmax);
+    }
     return rb_launch_green(ctx, tb, omega, c0, out, nullptr, nullptr, 1);
 }
 
@@ -491,9 +507,11 @@ rb_status rb_born_adjoint(rb_ctx *ctx, const rb_green *gr, const float *w, const
         uint16_t *Rp = rb_carve<uint16_t>(&ctx->ws, 2 * (size_t)gr->n * np);
         float *rscale = rb_carve<float>(&ctx->ws, 2);
         uint16_t *Gt = rb_carve<uint16_t>(&ctx->ws, 2 * (size_t)gr->n_mask * np);
-        RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
+        // G is never split: the split form's adjoint is the FP16 one
+        const rb_prec kp = rb_prec_split(gr->prec) ? RB_F16 : gr->prec;
+        RB_TRY(rb_launch_to_planar(ctx, kp, R, gr->n, Rp, rscale, gr->scales));
         RB_TRY(rb_launch_transpose_conj(ctx, gr, Gt));
-        RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, Gt, 1, parts, &mb));
+        RB_TRY(rb_launch_rowred_lp(ctx, kp, gr->n, gr->n_mask, Rp, Gt, 1, parts, &mb));
         RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
         return rb_launch_adjoint_finish(ctx, gr->n_mask, mb, parts, w, grad);
     }
@@ -539,8 +557,9 @@ static rb_status backproject_with(rb_ctx *ctx, rb_arena *a, const rb_green *gr, 
     if (lp) {
         uint16_t *Rp = rb_carve<uint16_t>(a, 2 * nnp);
         float *rscale = rb_carve<float>(a, 2);
-        RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale));
-        RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb));
+        RB_TRY(rb_launch_to_planar(ctx, gr->prec, R, gr->n, Rp, rscale, gr->scales + gr->n));
+        RB_TRY(rb_launch_rowred_lp(ctx, gr->prec, gr->n, gr->n_mask, Rp, gr->H, 3, parts, &mb,
+                                   h_low(gr)));
         RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * gr->n_mask, rscale));
     } else {
         float *rsym = rb_carve<float>(a, 2 * nn);
@@ -603,6 +622,7 @@ struct StepBufs {
     float *d_born = nullptr, *R = nullptr, *rsym = nullptr;
     uint16_t *Rp = nullptr;
     float *rscale = nullptr, *wv = nullptr, *svscale = nullptr;
+    unsigned int *rowmax = nullptr;  // per-row amplitude maxima of the binning (16-bit form)
     double *cq = nullptr, *dm = nullptr, *c_new = nullptr;
     float *parts = nullptr;
 };
@@ -615,14 +635,15 @@ static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
     const size_t NG = lp ? (size_t)N * rb_lp_pad(nm) : NP;  // G rows padded (16-bit form)
     const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
     const size_t opb = lp ? 4 : 8;  // bytes per complex operand
+    const size_t hparts = rb_prec_split(prec) ? 2 : 1;  // H and its low parts
     // node tables: ABI layout for the FP32 form, compact records (+ ring) for 16-bit
     const size_t tab_bytes = lp ? rb_align(NP * 16) + rb_align((size_t)N * 16)
                                 : rb_align(NP * 8) + 3 * rb_align(NP * 4) + rb_align(NP);
     return rb_align(P * 4) + tab_bytes + rb_align(NN * 8) + rb_align(NN * 4) + rb_align(NN) +
-           rb_align(NG * opb) + rb_align(3 * NPp * opb) + 3 * rb_align(NN * 8) +
+           rb_align(NG * opb) + rb_align(hparts * 3 * NPp * opb) + 3 * rb_align(NN * 8) +
            rb_align(NNp * 4) + rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
            3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
-           rb_align(8);
+           rb_align(8) + 2 * rb_align((size_t)2 * N * 4);
 }
 
 static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_prec prec,
@@ -670,7 +691,9 @@ static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     gr.n_mask = nm;
     gr.prec = prec;
     gr.G = rb_carve<char>(a, NG * opb);
-    gr.H = rb_carve<char>(a, 3 * (lp ? NPp : NP) * opb);
+    gr.H = rb_carve<char>(a, (rb_prec_split(prec) ? 2 : 1) * 3 * (lp ? NPp : NP) * opb);
+    gr.scales = rb_carve<float>(a, 2 * (size_t)N);
+    b->rowmax = rb_carve<unsigned int>(a, 2 * (size_t)N);
     b->d_born = rb_carve<float>(a, 2 * NN);
     b->R = rb_carve<float>(a, 2 * NN);
     b->rsym = rb_carve<float>(a, 2 * NN);
@@ -690,7 +713,7 @@ static rb_status step_begin(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
                             double *residual_norm, StepBufs &b) {
     RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, b.n_s));
-    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos));
+    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos, b.rowmax));
     RB_TRY(rb_launch_gather_mask(ctx, c, b.cq));
     RB_TRY(rb_launch_zero_f64(ctx, b.dm, b.nm));
     if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
@@ -712,7 +735,7 @@ static rb_status step_green(rb_ctx *ctx, const rb_grid *grid, const rb_trace_par
     const float *gs = born_term ? b.wv : nullptr;
     if (b.lp)
         return rb_launch_green_lp_rec(ctx, b.rec, b.ringpos, b.N, om, tp->c0, &b.gr, gs,
-                                      b.svscale, born_term);
+                                      b.svscale, born_term, b.rowmax);
     return rb_launch_green(ctx, &b.tb, om, tp->c0, &b.gr, gs, b.svscale, born_term);
 }
 
@@ -723,7 +746,7 @@ static rb_status step_residual(rb_ctx *ctx, const rb_trace_params *tp, double om
                                StepBufs &b) {
     RB_TRY(rb_launch_residual(ctx, &b.tb, om, tp->c0, born ? b.d_born : nullptr, data_k, b.R,
                               residual_norm));
-    if (b.lp) RB_TRY(rb_launch_to_planar(ctx, prec, b.R, b.N, b.Rp, b.rscale));
+    if (b.lp) RB_TRY(rb_launch_to_planar(ctx, prec, b.R, b.N, b.Rp, b.rscale, b.gr.scales + b.N));
     return RB_OK;
 }
 
@@ -773,7 +796,8 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
                              b));
         // a8: Hessian-free back-projection
         if (b.lp) {
-            RB_TRY(rb_launch_rowred_lp(ctx, prec, b.N, b.nm, b.Rp, b.gr.H, 3, b.parts, nullptr));
+            RB_TRY(rb_launch_rowred_lp(ctx, prec, b.N, b.nm, b.Rp, b.gr.H, 3, b.parts, nullptr,
+                                       h_low(&b.gr)));
         } else {
             int mbo = b.mb;
             RB_TRY(rb_launch_rowred(ctx, b.N, b.nm, b.R, (const float *)b.gr.H, 3, 0, b.rsym,
@@ -816,7 +840,7 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
 size_t rb_workspace_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,
                           rb_prec prec, size_t sample_budget) {
     if (!grid || !ring || !tp || grid->nx < 1 || grid->ny < 1 || ring->n < 1 || tp->n_rays < 1 ||
-        tp->max_steps < 1 || (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16))
+        tp->max_steps < 1 || !rb_prec_valid(prec))
         return 0;
     const GeomSizes gs = geom_sizes(grid);
     if (gs.nm < 1) return 0;
@@ -832,7 +856,7 @@ rb_status rb_reserve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
     RB_TRY(rb_check_grid(ctx, grid));
     RB_TRY(rb_check_ring(ctx, grid, ring));
     RB_TRY(rb_check_trace(ctx, tp));
-    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
+    if (!rb_prec_valid(prec))
         return rb_fail(ctx, RB_EINVAL, "unknown operand precision %d", (int)prec);
     if (ctx->capturing) return rb_fail(ctx, RB_EINVAL, "rb_reserve inside a graph capture");
     RB_HIP(ctx, hipSetDevice(ctx->device));
@@ -928,7 +952,7 @@ rb_status rb_set_tuning(rb_ctx *ctx, const rb_tuning *t) {
     }
     if (t->n < 1 || t->n_mask < 1)
         return rb_fail(ctx, RB_EINVAL, "tuning for n = %d, n_mask = %d", t->n, t->n_mask);
-    if (t->prec != RB_F32 && t->prec != RB_BF16 && t->prec != RB_F16)
+    if (!rb_prec_valid(t->prec))
         return rb_fail(ctx, RB_EINVAL, "tuning for an unknown precision %d", (int)t->prec);
     if (t->fwd_tile != RB_TILE_256x128 && t->fwd_tile != RB_TILE_128x128)
         return rb_fail(ctx, RB_EINVAL, "unknown forward tile %d", (int)t->fwd_tile);
@@ -952,8 +976,7 @@ rb_status rb_autotune(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_
     if (!ctx) return RB_EINVAL;
     RB_TRY(rb_check_grid(ctx, grid));
     RB_TRY(rb_check_ring(ctx, grid, ring));
-    if (prec != RB_F32 && prec != RB_BF16 && prec != RB_F16)
-        return rb_fail(ctx, RB_EINVAL, "unknown precision %d", (int)prec);
+    if (!rb_prec_valid(prec)) return rb_fail(ctx, RB_EINVAL, "unknown precision %d", (int)prec);
     RB_HIP(ctx, hipSetDevice(ctx->device));
     StepBufs b;
     RB_TRY(step_carve(ctx, grid, ring, prec, &b));
@@ -1106,7 +1129,7 @@ static rb_status batch_enqueue(const rb_scan_step *st, int count, rb_prec prec,
                 rb_rowred_prob pr[RB_GROUP_MAX];
                 for (int a = 0; a < na; ++a) {
                     StepBufs &b = bufs[act[a]];
-                    pr[a] = rb_rowred_prob{b.Rp, b.gr.H, b.parts, b.N, b.nm};
+                    pr[a] = rb_rowred_prob{b.Rp, b.gr.H, b.parts, b.N, b.nm, h_low(&b.gr)};
                 }
                 res = rb_launch_rowred_lp_group(lead, prec, pr, na, 3);
             } else {

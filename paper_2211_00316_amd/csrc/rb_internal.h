@@ -138,6 +138,13 @@ rb_status rb_fail(rb_ctx *ctx, rb_status st, const char *fmt, ...);
 rb_status rb_arena_reserve(rb_ctx *ctx, rb_arena *a, size_t bytes);
 inline size_t rb_align(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Operand types: valid values of rb_prec, and the split form (FP16 operands with the
+// back-projection operand H stored as a high and a low FP16 part).
+inline bool rb_prec_valid(int p) {
+    return p == RB_F32 || p == RB_BF16 || p == RB_F16 || p == RB_F16X;
+}
+inline bool rb_prec_split(int p) { return p == RB_F16X; }
+
 // Transducer dimension of the 16-bit operand rows (H, residual): a whole number of 32-deep
 // contraction steps, zeros past n.
 __host__ __device__ inline int rb_lp_pad(int n) { return (n + 31) & ~31; }
@@ -162,10 +169,12 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
 // (transducer, node) gets one compact record (dT, A, theta, flags) with dT = T - d / c0 (d:
 // distance from the transducer, recomputed by the reader), theta = atan2(u_y, u_x) and the
 // flag bits of rb_tables stored as the bits of the fourth float. ring_out (nullable, double2
-// [n]) receives the transducer positions.
+// [n]) receives the transducer positions. rowmax (nullable, with rec; [n][2]) receives for
+// each transducer the bits of the largest A and of the largest 1/A over its valid records.
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
-                          float4 *rec = nullptr, double2 *ring_out = nullptr);
+                          float4 *rec = nullptr, double2 *ring_out = nullptr,
+                          unsigned int *rowmax = nullptr);
 // gs (nullable): complex per-node factor on G; write_g = 0 leaves G unwritten.
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                           const rb_green *out, const float *gs, const float *gscale,
@@ -197,23 +206,29 @@ size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_para
                          int64_t n_mask, size_t tiles, size_t sample_budget);
 
 // Reduced-precision (BF16 / FP16 operand) form: layouts in rb_lowp.hip.
+// Writes out->scales (per-row powers of two) with the operands; rowmax: workspace of [n][2]
+// words for the tables' row maxima.
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const rb_green *out, const float *gs, const float *gscale,
-                             int write_g);
-// The same from the compact records of rb_launch_trace (ring: transducer positions).
+                             int write_g, unsigned int *rowmax);
+// The same from the compact records of rb_launch_trace (ring: transducer positions; rowmax:
+// the binning's per-row amplitude maxima).
 rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
                                  double omega, double c0, const rb_green *out, const float *gs,
-                                 const float *gscale, int write_g);
+                                 const float *gscale, int write_g, const unsigned int *rowmax);
 // R -> planar 16-bit operand of the back-projection: the block upper triangle of the
-// symmetric part of R (the bilinear forms h^T R h see nothing else; rb_lowp.hip), scaled by
-// a power of two kept in scale[0..1] (device, 2 floats).
+// symmetric part of R (the bilinear forms h^T R h see nothing else; rb_lowp.hip), divided by
+// rows[e] rows[r] (the per-row scales of the other operand; nullable) and scaled by a power
+// of two kept in scale[0..1] (device, 2 floats).
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale);
+                              float *scale, const float *rows);
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);
 // 16-bit G [2][n][m_pad] -> conj(G) node-major [2][n_mask][n_pad] (operand of the adjoint).
 rb_status rb_launch_transpose_conj(rb_ctx *ctx, const rb_green *gr, void *Gt);
+// Hlo (nullable): low parts of a split operand (RB_F16X), added with weight 2 in the epilogue.
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
-                              const void *Ht, int n_comp, float *parts, int *mblocks);
+                              const void *Ht, int n_comp, float *parts, int *mblocks,
+                              const void *Hlo = nullptr);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale);
 
@@ -224,6 +239,7 @@ struct rb_rowred_prob {
     const void *Ht;   // 16-bit H planes of the green record
     float *parts;     // [2][mblocks][n_mask] partial sums
     int n, n_mask;
+    const void *Hlo;  // low parts of H (split form) or NULL
 };
 rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_prob *probs,
                                     int count, int n_comp);

@@ -77,6 +77,13 @@ __device__ __forceinline__ uint32_t lp_bits(float x) {
     return u;
 }
 
+// Bit pattern of the rounding error of x in the 16-bit type, itself rounded (the low part of
+// a split operand: x ~ hi + lo with hi = the rounded x).
+template <typename T>
+__device__ __forceinline__ uint32_t lp_lo_bits(float x) {
+    return lp_bits<T>(x - from_lp<T>(to_lp<T>(x)));
+}
+
 // Angle between two unit directions.
 __device__ __forceinline__ float angle_between(float ax, float ay, float bx, float by) {
     return fabsf(atan2f(ax * by - ay * bx, ax * bx + ay * by));
@@ -113,13 +120,69 @@ __device__ __forceinline__ void green_entry(double omega, double Tt, uint32_t K,
     hi = -ha * sn;
 }
 
-template <typename T>
+// Per-transducer operand scales. With the largest amplitude A and the largest 1/A of row e
+// (bits in rowmax[2e], rowmax[2e+1]), |G[e][q]| <= A k0^-1/2 gmax (gmax bounds the per-node
+// factor sqrt(v) carried by G) and |H_c[e][q]| <= pi k0^1/2 / A (angular weight <= pi, |u| <= 1).
+// The scale is the power of two that brings the bound to [2^13, 2^14): the largest stored
+// value stays below 2^14 (inside the FP16 range) and a row's small values stay far above the
+// FP16 subnormals. A row without a valid entry gets 1.
+__device__ __forceinline__ float pow2_scale(float bound) {
+    if (!(bound > 0.f) || !isfinite(bound)) return 1.f;
+    int e = 0;
+    frexpf(bound, &e);  // 2^(e-1) <= bound < 2^e
+    return ldexpf(1.f, 14 - e);
+}
+
+__device__ __forceinline__ void row_scales(const unsigned int *__restrict__ rowmax, int e,
+                                           float sk, float isk, float gmax, float &sg,
+                                           float &sh) {
+    const float amax = __uint_as_float(rowmax[2 * e]);
+    const float iamax = __uint_as_float(rowmax[2 * e + 1]);
+    sg = pow2_scale(amax * isk * gmax);
+    sh = pow2_scale((float)RB_PI * sk * iamax);
+}
+
+// Largest A and 1/A over the valid entries of each row of the ABI tables (one workgroup per
+// transducer), as the bits rowmax[2e], rowmax[2e+1].
+__global__ void __launch_bounds__(256) row_amax_kernel(rb_tables tb, int n_mask,
+                                                       unsigned int *__restrict__ rowmax) {
+    __shared__ float red[2][4];
+    const int e = blockIdx.x;
+    float m0 = 0.f, m1 = 0.f;
+    for (int q = threadIdx.x; q < n_mask; q += blockDim.x) {
+        const size_t o = (size_t)e * n_mask + q;
+        const float A = tb.A[o];
+        if ((tb.flags[o] & 0x80) && A > 0.f) {
+            m0 = fmaxf(m0, A);
+            m1 = fmaxf(m1, 1.0f / A);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmaxf(m0, __shfl_xor(m0, o));
+        m1 = fmaxf(m1, __shfl_xor(m1, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = m0;
+        red[1][threadIdx.x >> 6] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rowmax[2 * e] = __float_as_uint(fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3])));
+        rowmax[2 * e + 1] =
+            __float_as_uint(fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3])));
+    }
+}
+
+template <typename T, bool SPLIT>
 __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int n_mask,
                                                        double omega, double c0,
                                                        const float2 *__restrict__ gs,
                                                        const float *__restrict__ gscale,
                                                        int write_g, T *__restrict__ Gp,
-                                                       T *__restrict__ Ht) {
+                                                       T *__restrict__ Ht,
+                                                       const unsigned int *__restrict__ rowmax,
+                                                       float gmax, float *__restrict__ scales,
+                                                       T *__restrict__ Htlo) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = blockIdx.x * GQ + lane;
     const int e0 = blockIdx.y * GE + w * GW;
@@ -153,11 +216,18 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         f2.y *= sc;
     }
     uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
+    uint32_t hl[6][GW / 2];  // their low parts (split form)
 #pragma unroll
     for (int r = 0; r < GW; ++r) {
         const int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
         if (e < N) {
+            float sg, sh;
+            row_scales(rowmax, e, sk, isk, gmax, sg, sh);
+            if (blockIdx.x == 0 && lane == 0) {
+                scales[e] = sg;
+                scales[N + e] = sh;
+            }
             size_t o = (size_t)e * n_mask + q;
             if (valid >> (r + 1) & 1u) {
                 vx = ux[r + 1];
@@ -168,6 +238,10 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
                 else if (vp) a = angle_between(vx, vy, ux[r + 2], uy[r + 2]);
                 else if (vm) a = angle_between(ux[r], uy[r], vx, vy);
                 green_entry(omega, tb.T[o], tb.flags[o], tb.A[o], a, sk, isk, gr, gi, hr, hi);
+                gr *= sg;
+                gi *= sg;
+                hr *= sh;
+                hi *= sh;
             }
             if (write_g) {
                 const size_t og = (size_t)e * Mp + q;
@@ -182,18 +256,27 @@ __global__ void __launch_bounds__(256) green_lp_kernel(rb_tables tb, int N, int 
         for (int cp = 0; cp < 6; ++cp) {
             if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
+            if constexpr (SPLIT) {
+                if (r & 1) hl[cp][r >> 1] |= lp_lo_bits<T>(v[cp]) << 16;
+                else hl[cp][r >> 1] = lp_lo_bits<T>(v[cp]);
+            }
         }
     }
     // transposed rows (c, part, q), Np long (zeros past N)
     const size_t hplane = (size_t)n_mask * Np;
+    auto store = [&](const uint32_t (&src)[6][GW / 2], T *base) {
 #pragma unroll
-    for (int cp = 0; cp < 6; ++cp) {
-        T *dst = Ht + (size_t)cp * hplane + (size_t)q * Np + e0;
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
-        if (e0 + 8 < Np)
-            *reinterpret_cast<uint4 *>(dst + 8) =
-                make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
-    }
+        for (int cp = 0; cp < 6; ++cp) {
+            T *dst = base + (size_t)cp * hplane + (size_t)q * Np + e0;
+            *reinterpret_cast<uint4 *>(dst) =
+                make_uint4(src[cp][0], src[cp][1], src[cp][2], src[cp][3]);
+            if (e0 + 8 < Np)
+                *reinterpret_cast<uint4 *>(dst + 8) =
+                    make_uint4(src[cp][4], src[cp][5], src[cp][6], src[cp][7]);
+        }
+    };
+    store(hp, Ht);
+    if constexpr (SPLIT) store(hl, Htlo);
 }
 
 // The same assembly from the compact records of a frequency step (rb_launch_trace): one
@@ -209,12 +292,13 @@ __device__ __forceinline__ float wrap_pi(float x) {
 // eight consecutive threads (H in two halves of three planes; one 28 KB buffer for all).
 constexpr int GH_LD = GE + 8;  // H staging pitch (elements): 16-byte lane writes miss no bank
 
-template <typename T>
+template <typename T, bool SPLIT>
 __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     const float4 *__restrict__ rec, const int32_t *__restrict__ mask_index,
     const double2 *__restrict__ ring, double x0, double y0, double dx, int nx, int N, int n_mask,
     double omega, double c0, const float2 *__restrict__ gs, const float *__restrict__ gscale,
-    int write_g, T *__restrict__ Gp, T *__restrict__ Ht) {
+    int write_g, T *__restrict__ Gp, T *__restrict__ Ht, const unsigned int *__restrict__ rowmax,
+    float gmax, float *__restrict__ scales, T *__restrict__ Htlo) {
     __shared__ __attribute__((aligned(16))) T stage[3 * GQ * GH_LD];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q0 = blockIdx.x * GQ, E0 = blockIdx.y * GE;
@@ -258,10 +342,19 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     const float sk = (float)sqrt(k0), isk = 1.0f / sk;
     T *sg = stage;  // G tile [2][GE][GQ]
     uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
+    uint32_t hl[6][GW / 2];  // their low parts (split form)
 #pragma unroll
     for (int r = 0; r < GW; ++r) {
         const int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
+        float rsg = 1.f, rsh = 1.f;
+        if (e < N) {
+            row_scales(rowmax, e, sk, isk, gmax, rsg, rsh);
+            if (blockIdx.x == 0 && lane == 0) {
+                scales[e] = rsg;
+                scales[N + e] = rsh;
+            }
+        }
         if (node && e < N && (valid >> (r + 1) & 1u)) {
             __sincosf(th[r + 1], &vy, &vx);
             const bool vm = valid >> r & 1u, vp = valid >> (r + 2) & 1u;
@@ -273,6 +366,10 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
             const double ddx = px - xe.x, ddy = py - xe.y;
             const double Tt = (double)dTr[r] + sqrt(ddx * ddx + ddy * ddy) * ic0;
             green_entry(omega, Tt, Kb >> (2 * r), Ar[r], a, sk, isk, gr, gi, hr, hi);
+            gr *= rsg;
+            gi *= rsg;
+            hr *= rsh;
+            hi *= rsh;
         }
         const float tr = gr * f2.x - gi * f2.y, ti = gr * f2.y + gi * f2.x;
         sg[(w * GW + r) * GQ + lane] = to_lp<T>(tr);
@@ -282,6 +379,10 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
         for (int cp = 0; cp < 6; ++cp) {
             if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
+            if constexpr (SPLIT) {
+                if (r & 1) hl[cp][r >> 1] |= lp_lo_bits<T>(v[cp]) << 16;
+                else hl[cp][r >> 1] = lp_lo_bits<T>(v[cp]);
+            }
         }
     }
     __syncthreads();
@@ -298,29 +399,33 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
         }
     }
     const size_t hplane = (size_t)n_mask * Np;
+    auto store = [&](const uint32_t (&src)[6][GW / 2], T *base) {
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        __syncthreads();  // the staging buffer is free again
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();  // the staging buffer is free again
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int cp = 3 * half + k;
-            uint4 *dst = reinterpret_cast<uint4 *>(&stage[(k * GQ + lane) * GH_LD + w * GW]);
-            dst[0] = make_uint4(hp[cp][0], hp[cp][1], hp[cp][2], hp[cp][3]);
-            dst[1] = make_uint4(hp[cp][4], hp[cp][5], hp[cp][6], hp[cp][7]);
+            for (int k = 0; k < 3; ++k) {
+                const int cp = 3 * half + k;
+                uint4 *dst = reinterpret_cast<uint4 *>(&stage[(k * GQ + lane) * GH_LD + w * GW]);
+                dst[0] = make_uint4(src[cp][0], src[cp][1], src[cp][2], src[cp][3]);
+                dst[1] = make_uint4(src[cp][4], src[cp][5], src[cp][6], src[cp][7]);
+            }
+            __syncthreads();
+            // 3 planes x GQ node rows x 8 pieces of 8 transducers: six per thread
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int id = tid + 256 * k;
+                const int pl = id >> 9, qr = (id >> 3) & (GQ - 1), ch = id & 7;
+                const int qq = q0 + qr, e = E0 + ch * 8;
+                if (qq < n_mask && e < Np)
+                    *reinterpret_cast<uint4 *>(base + (size_t)(3 * half + pl) * hplane +
+                                               (size_t)qq * Np + e) =
+                        *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GH_LD + ch * 8]);
+            }
         }
-        __syncthreads();
-        // 3 planes x GQ node rows x 8 pieces of 8 transducers: six per thread
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int id = tid + 256 * k;
-            const int pl = id >> 9, qr = (id >> 3) & (GQ - 1), ch = id & 7;
-            const int qq = q0 + qr, e = E0 + ch * 8;
-            if (qq < n_mask && e < Np)
-                *reinterpret_cast<uint4 *>(Ht + (size_t)(3 * half + pl) * hplane +
-                                           (size_t)qq * Np + e) =
-                    *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GH_LD + ch * 8]);
-        }
-    }
+    };
+    store(hp, Ht);
+    if constexpr (SPLIT) store(hl, Htlo);
 }
 
 // conj(G) in the back-projection's operand layout, for the 16-bit adjoint: G planar
@@ -363,6 +468,7 @@ __global__ void __launch_bounds__(256) transpose_conj_kernel(const uint16_t *__r
 // workgroup over them.
 __global__ void __launch_bounds__(256) range_max_kernel(const float2 *__restrict__ x,
                                                         size_t count, const float *__restrict__ y,
+                                                        const float *__restrict__ rows, int n,
                                                         float *__restrict__ part) {
     __shared__ float red[4];
     float m = 0.f;
@@ -371,6 +477,7 @@ __global__ void __launch_bounds__(256) range_max_kernel(const float2 *__restrict
         float2 v = x[i];
         float a = fmaxf(fabsf(v.x), fabsf(v.y));
         if (y) a *= fabsf(y[i]);
+        if (rows) a /= rows[i / n] * rows[i % n];  // exact: powers of two
         m = fmaxf(m, a);
     }
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
@@ -399,10 +506,10 @@ __global__ void __launch_bounds__(256) range_finish_kernel(const float *__restri
 }
 
 rb_status launch_range_scale(rb_ctx *ctx, const float2 *x, size_t count, const float *y, int top,
-                             float *scale) {
+                             float *scale, const float *rows = nullptr, int n = 1) {
     const int nb = (int)std::min<size_t>(RB_RED_PARTS, std::max<size_t>(1, (count + 1023) / 1024));
-    hipLaunchKernelGGL(range_max_kernel, dim3(nb), dim3(256), 0, ctx->stream, x, count, y,
-                       ctx->d_red);
+    hipLaunchKernelGGL(range_max_kernel, dim3(nb), dim3(256), 0, ctx->stream, x, count, y, rows,
+                       n, ctx->d_red);
     RB_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(range_finish_kernel, dim3(1), dim3(256), 0, ctx->stream,
                        (const float *)ctx->d_red, nb, top, scale);
@@ -416,10 +523,13 @@ rb_status launch_range_scale(rb_ctx *ctx, const float2 *x, size_t count, const f
 // 2 sum_{J > I} h_I^T Rs_IJ h_J, so the operand is the block upper triangle
 //   R'[e][r] = Rs[e][r] (same block), 2 Rs[e][r] = R[e][r] + R[r][e] (block J > I), 0 (J < I)
 // and the product for row block I runs over column blocks J >= I only.
-// complex64 [n][n] -> planar T [2][n][np] of R' (zero past n), multiplied by scale[0].
+// complex64 [n][n] -> planar T [2][n][np] of R' (zero past n), multiplied by scale[0]. With
+// per-row operand scales (rows, nullable) the operand is R'[e][r] / (rows[e] rows[r]), so
+// that the bilinear form of the scaled operands h'_e = rows[e] h_e is unchanged.
 template <typename T>
 __global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np, int bm,
-                                 const float *__restrict__ scale, T *__restrict__ dst) {
+                                 const float *__restrict__ scale, const float *__restrict__ rows,
+                                 T *__restrict__ dst) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t nn = (size_t)n * np;
     if (i >= nn) return;
@@ -431,6 +541,11 @@ __global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np, 
         const float2 a = src[(size_t)row * n + col], b = src[(size_t)col * n + row];
         const float f = bj == bi ? 0.5f : 1.0f;
         v = make_float2(f * (a.x + b.x), f * (a.y + b.y));
+        if (rows) {
+            const float ir = 1.0f / (rows[row] * rows[col]);
+            v.x *= ir;
+            v.y *= ir;
+        }
     }
     dst[i] = to_lp<T>(v.x * s);
     dst[nn + i] = to_lp<T>(v.y * s);
@@ -721,15 +836,67 @@ __device__ __forceinline__ void lr_mainloop(T *s0, T *s1, T *s2, const LrLoad &L
 // The back-projection contractions of one launch: `count` independent problems (one per scan
 // of a batch; count = 1 for a single call). Problem p owns items item0[p] .. item0[p+1]-1 of
 // the launch's item list; XCD x walks items xcd0[x] .. xcd0[x+1]-1.
+// With `full`, R' is the whole symmetric part of R and every row slab contracts over all of
+// K (the split form: the epilogue's operand is h_hi + 2 h_lo, and the cross term
+// 2 h_lo^T Rs h_hi needs Rs h_hi in every row); Hlo[p] (nullable) are the low parts.
 struct RowGroup {
     int count;
+    int full;
     int item0[RB_GROUP_MAX + 1];
     int xcd0[9];
     int n[RB_GROUP_MAX], n_cols[RB_GROUP_MAX];
     const void *Rp[RB_GROUP_MAX];
     const void *Ht[RB_GROUP_MAX];
+    const void *Hlo[RB_GROUP_MAX];
     float *parts[RB_GROUP_MAX];
 };
+
+// Epilogue of one component: adds f sum_e E[e][q] Y[e][q] over the tile's rows to cs, with
+// E staged in the three LDS stages by lr_fetch_e: four consecutive rows e per register group,
+// one 8-byte LDS read per part. Rows are padded with zeros to np, a multiple of 32, so a
+// 32-row group lies wholly inside np or wholly past it (uniform; such groups get weight 0 and
+// read other finite data), and rows beyond n carry E = 0. Lanes of nodes past the last read
+// other finite data; their sums are never stored.
+template <typename T>
+__device__ __forceinline__ void lr_epilogue(const T *s0, const T *s1, const T *s2, int row0,
+                                            int np, const floatx16 (&acc_re)[LR_MT][2],
+                                            const floatx16 (&acc_im)[LR_MT][2], float f,
+                                            float (&cs_re)[2], float (&cs_im)[2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int q = wn * 64 + nt * 32 + (lane & 31);
+#pragma unroll
+        for (int mt = 0; mt < LR_MT; ++mt) {
+            const int eb = wm * (32 * LR_MT) + mt * 32;  // wave-uniform
+            const int ch = eb / LR_ECH;
+            const T *st = ch == 0 ? s0 : (ch == 1 ? s1 : s2);
+            const int pr = ch == 2 ? (LR_BM - 2 * LR_ECH) / 8 : LR_ECH / 8;
+            const int hq = lr_eswz(q, pr);
+            const float rm = row0 + eb < np ? f : 0.f;
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int el = eb - ch * LR_ECH + g * 8 + (lane >> 5) * 4;
+                const int o = (q * pr + ((el >> 3) ^ hq)) * 8 + (el & 7);
+                T vr[4], vi[4];
+                __builtin_memcpy(vr, st + o, 8);
+                __builtin_memcpy(vi, st + o + LR_BN * pr * 8, 8);
+#pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
+                    const float yr = acc_re[mt][nt][g * 4 + z];
+                    const float yi = acc_im[mt][nt][g * 4 + z];
+                    sr += er * yr - ei * yi;
+                    si += er * yi + ei * yr;
+                }
+            }
+            cs_re[nt] += rm * sr;
+            cs_im[nt] += rm * si;
+        }
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup grp, int n_comp) {
@@ -756,6 +923,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
         while (p + 1 < grp.count && item >= grp.item0[p + 1]) ++p;
         const T *__restrict__ Rp = static_cast<const T *>(grp.Rp[p]);
         const T *__restrict__ Ht = static_cast<const T *>(grp.Ht[p]);
+        const T *__restrict__ Hlo = static_cast<const T *>(grp.Hlo[p]);
         float *__restrict__ parts = grp.parts[p];
         const int n = grp.n[p], n_cols = grp.n_cols[p];
         const int mblocks = (n + LR_BM - 1) / LR_BM, n_pairs = (mblocks + 1) / 2;
@@ -769,7 +937,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
             const int mb = half == 0 ? pr : mblocks - 1 - pr;
             if (half == 1 && mb == pr) break;  // middle slab of an odd count
             const int row0 = mb * LR_BM, col0 = nb * LR_BN;
-            const int KT0 = row0 / LR_BK;  // R' is zero left of the diagonal block
+            // R' is zero left of the diagonal block (the whole row in the full form)
+            const int KT0 = grp.full ? 0 : row0 / LR_BK;
             float cs_re[2] = {0.f, 0.f}, cs_im[2] = {0.f, 0.f};
 
             for (int c = 0; c < n_comp; ++c) {
@@ -786,49 +955,22 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                             acc_im[mt][nt][i] = 0.f;
                         }
                 lr_mainloop<T, true>(s0, s1, s2, ld, KT0, KT, acc_re, acc_im);
-                // epilogue: E_c[e][q] = Ht_c[q][e] for the tile's 256 rows e and 128 nodes q, staged
-                // through the three LDS stages (coalesced loads of row pieces of Ht_c), then four
-                // consecutive rows e per register group, one 8-byte LDS read per part. Rows are
-                // padded with zeros to np, a multiple of 32, so a 32-row group lies wholly inside
-                // np or wholly past it (uniform; such groups get weight 0 and read other finite
-                // data), and rows beyond n carry E = 0. Lanes of nodes past the last read other
-                // finite data; their sums are never stored.
+                // epilogue: E_c[e][q] = Ht_c[q][e] for the tile's 256 rows e and 128 nodes q,
+                // staged through the three LDS stages (coalesced loads of row pieces of Ht_c);
+                // a split operand adds its low part with weight 2 (h_hi + 2 h_lo against
+                // Y = Rs h_hi: the first-order rounding of h on both sides)
                 __syncthreads();  // every wave is done with the K loop's stages
                 lr_fetch_e<T>(Hc, hplane, np, row0, col0, s0, s1, s2);
                 lr_sync<0>();
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    const int q = wn * 64 + nt * 32 + (lane & 31);
-#pragma unroll
-                    for (int mt = 0; mt < LR_MT; ++mt) {
-                        const int eb = wm * (32 * LR_MT) + mt * 32;  // wave-uniform
-                        const int ch = eb / LR_ECH;
-                        const T *st = ch == 0 ? s0 : (ch == 1 ? s1 : s2);
-                        const int pr = ch == 2 ? (LR_BM - 2 * LR_ECH) / 8 : LR_ECH / 8;
-                        const int hq = lr_eswz(q, pr);
-                        const float rm = row0 + eb < np ? 1.f : 0.f;
-                        float sr = 0.f, si = 0.f;
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int el = eb - ch * LR_ECH + g * 8 + (lane >> 5) * 4;
-                            const int o = (q * pr + ((el >> 3) ^ hq)) * 8 + (el & 7);
-                            T vr[4], vi[4];
-                            __builtin_memcpy(vr, st + o, 8);
-                            __builtin_memcpy(vi, st + o + LR_BN * pr * 8, 8);
-#pragma unroll
-                            for (int z = 0; z < 4; ++z) {
-                                const float er = from_lp<T>(vr[z]), ei = from_lp<T>(vi[z]);
-                                const float yr = acc_re[mt][nt][g * 4 + z];
-                                const float yi = acc_im[mt][nt][g * 4 + z];
-                                sr += er * yr - ei * yi;
-                                si += er * yi + ei * yr;
-                            }
-                        }
-                        cs_re[nt] += rm * sr;
-                        cs_im[nt] += rm * si;
-                    }
+                lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 1.f, cs_re, cs_im);
+                __syncthreads();  // LDS buffers are refilled next
+                if (Hlo) {
+                    lr_fetch_e<T>(Hlo + (size_t)(2 * c) * hplane, hplane, np, row0, col0, s0, s1,
+                                  s2);
+                    lr_sync<0>();
+                    lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 2.f, cs_re, cs_im);
+                    __syncthreads();
                 }
-                __syncthreads();  // LDS buffers are refilled by the next component
             }
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
@@ -1091,7 +1233,8 @@ __global__ void __launch_bounds__(LR_THREADS) forward_pipe_kernel(const FwdGroup
 }
 
 __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int splitk,
-                                  const float *__restrict__ vscale, float2 *__restrict__ d) {
+                                  const float *__restrict__ vscale,
+                                  const float *__restrict__ rows, float2 *__restrict__ d) {
     int r = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
     if (r >= n) return;
     size_t src = (e <= r) ? (size_t)e * n + r : (size_t)r * n + e;
@@ -1101,7 +1244,8 @@ __global__ void forward_reduce_lp(const float2 *__restrict__ dpart, int n, int s
         sr += v.x;
         si += v.y;
     }
-    float inv = vscale[1];
+    // the rows of G carry the per-transducer scales (powers of two: exact)
+    float inv = vscale[1] / (rows[e] * rows[r]);
     d[(size_t)e * n + r] = make_float2(sr * inv, si * inv);
 }
 
@@ -1131,6 +1275,11 @@ __global__ void tune_fill_f32_kernel(float *__restrict__ G, size_t count) {
     G[i] = (0.5f + 0.5f * (float)(h & 0xffff) / 65536.f) * ((h & 0x10000) ? -1.f : 1.f);
 }
 
+__global__ void ones_kernel(float *x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 1.f;
+}
+
 __global__ void unit_scale_kernel(float *s) {
     s[0] = 1.f;
     s[1] = 1.f;
@@ -1157,23 +1306,43 @@ rb_status rb_launch_tune_fill(rb_ctx *ctx, const rb_green *gr, float *gscale) {
     RB_CHECK_LAUNCH(ctx);
     hipLaunchKernelGGL(unit_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale);
     RB_CHECK_LAUNCH(ctx);
+    if (gr->prec != RB_F32 && gr->scales) {  // unscaled rows
+        hipLaunchKernelGGL(ones_kernel, dim3((2 * n + 255) / 256), dim3(256), 0, ctx->stream,
+                           gr->scales, 2 * n);
+        RB_CHECK_LAUNCH(ctx);
+    }
     return RB_OK;
 }
 
 // Launchers ------------------------------------------------------------------------------
+// Bound of |sqrt(v)| scaled to [1, 2) per part, as G carries it: |re|, |im| < 2.
+constexpr float GS_MAX = 2.8285f;
+
 rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                              const rb_green *out, const float *gs, const float *gscale,
-                             int write_g) {
+                             int write_g, unsigned int *rowmax) {
     dim3 grd((tb->n_mask + GQ - 1) / GQ, (tb->n + GE - 1) / GE);
     rb_prof_begin(ctx, ST_GREEN);
+    hipLaunchKernelGGL(row_amax_kernel, dim3(tb->n), dim3(256), 0, ctx->stream, *tb, tb->n_mask,
+                       rowmax);
+    RB_CHECK_LAUNCH(ctx);
+    const float gmax = gs ? GS_MAX : 1.f;
+    const size_t hlo = 6 * (size_t)tb->n_mask * rb_lp_pad(tb->n);  // low parts follow H
     if (out->prec == RB_BF16)
-        hipLaunchKernelGGL(green_lp_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
-                           tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
-                           (__bf16 *)out->G, (__bf16 *)out->H);
+        hipLaunchKernelGGL((green_lp_kernel<__bf16, false>), grd, dim3(256), 0, ctx->stream, *tb,
+                           tb->n, tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
+                           (__bf16 *)out->G, (__bf16 *)out->H, rowmax, gmax, out->scales,
+                           nullptr);
+    else if (rb_prec_split(out->prec))
+        hipLaunchKernelGGL((green_lp_kernel<_Float16, true>), grd, dim3(256), 0, ctx->stream, *tb,
+                           tb->n, tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
+                           (_Float16 *)out->G, (_Float16 *)out->H, rowmax, gmax, out->scales,
+                           (_Float16 *)out->H + hlo);
     else
-        hipLaunchKernelGGL(green_lp_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, *tb, tb->n,
-                           tb->n_mask, omega, c0, (const float2 *)gs, gscale, write_g,
-                           (_Float16 *)out->G, (_Float16 *)out->H);
+        hipLaunchKernelGGL((green_lp_kernel<_Float16, false>), grd, dim3(256), 0, ctx->stream,
+                           *tb, tb->n, tb->n_mask, omega, c0, (const float2 *)gs, gscale,
+                           write_g, (_Float16 *)out->G, (_Float16 *)out->H, rowmax, gmax,
+                           out->scales, nullptr);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -1181,41 +1350,52 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
 
 rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
                                  double omega, double c0, const rb_green *out, const float *gs,
-                                 const float *gscale, int write_g) {
+                                 const float *gscale, int write_g, const unsigned int *rowmax) {
     const int nm = (int)ctx->n_mask;
     const rb_grid &g = ctx->grid;
     dim3 grd((nm + GQ - 1) / GQ, (n + GE - 1) / GE);
+    const float gmax = gs ? GS_MAX : 1.f;
+    const size_t hlo = 6 * (size_t)nm * rb_lp_pad(n);  // low parts follow H
     rb_prof_begin(ctx, ST_GREEN);
     if (out->prec == RB_BF16)
-        hipLaunchKernelGGL(green_lp_rec_kernel<__bf16>, grd, dim3(256), 0, ctx->stream, rec,
-                           ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega, c0,
-                           (const float2 *)gs, gscale, write_g, (__bf16 *)out->G,
-                           (__bf16 *)out->H);
+        hipLaunchKernelGGL((green_lp_rec_kernel<__bf16, false>), grd, dim3(256), 0, ctx->stream,
+                           rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
+                           c0, (const float2 *)gs, gscale, write_g, (__bf16 *)out->G,
+                           (__bf16 *)out->H, rowmax, gmax, out->scales, nullptr);
+    else if (rb_prec_split(out->prec))
+        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, true>), grd, dim3(256), 0, ctx->stream,
+                           rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
+                           c0, (const float2 *)gs, gscale, write_g, (_Float16 *)out->G,
+                           (_Float16 *)out->H, rowmax, gmax, out->scales,
+                           (_Float16 *)out->H + hlo);
     else
-        hipLaunchKernelGGL(green_lp_rec_kernel<_Float16>, grd, dim3(256), 0, ctx->stream, rec,
-                           ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega, c0,
-                           (const float2 *)gs, gscale, write_g, (_Float16 *)out->G,
-                           (_Float16 *)out->H);
+        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, false>), grd, dim3(256), 0,
+                           ctx->stream, rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n,
+                           nm, omega, c0, (const float2 *)gs, gscale, write_g,
+                           (_Float16 *)out->G, (_Float16 *)out->H, rowmax, gmax, out->scales,
+                           nullptr);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
 }
 
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale) {
+                              float *scale, const float *rows) {
     size_t nn = (size_t)n * n;
     const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
     // |R'| <= 2 max |R|: scale max |R| to [2^12, 2^13) so R' stays below 2^14
-    RB_TRY(launch_range_scale(ctx, (const float2 *)R, nn, nullptr, 13, scale));
+    RB_TRY(launch_range_scale(ctx, (const float2 *)R, nn, nullptr, 13, scale, rows, n));
     size_t npad = (size_t)n * np;
     dim3 grd((unsigned)((npad + 255) / 256));
+    // block size of the triangle; one block (the whole symmetric part) for the split form
+    const int bm = rb_prec_split(prec) ? np : LR_BM;
     if (prec == RB_BF16)
         hipLaunchKernelGGL(to_planar_kernel<__bf16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, np, LR_BM, scale, (__bf16 *)Rp);
+                           (const float2 *)R, n, np, bm, scale, rows, (__bf16 *)Rp);
     else
         hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
-                           (const float2 *)R, n, np, LR_BM, scale, (_Float16 *)Rp);
+                           (const float2 *)R, n, np, bm, scale, rows, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -1249,6 +1429,7 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
         return rb_fail(ctx, RB_EINVAL, "grouped back-projection of %d problems", count);
     RowGroup g{};
     g.count = count;
+    g.full = rb_prec_split(prec) ? 1 : 0;
     int64_t items = 0, cost = 0;
     int64_t pcost[RB_GROUP_MAX];  // cost of one item of each problem (K blocks it walks)
     for (int i = 0; i < count; ++i) {
@@ -1268,9 +1449,10 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
         g.n_cols[i] = n_mask;
         g.Rp[i] = pr[i].Rp;
         g.Ht[i] = pr[i].Ht;
+        g.Hlo[i] = pr[i].Hlo;
         g.parts[i] = pr[i].parts;
         const int64_t it = (int64_t)nblocks * ((mblocks + 1) / 2);
-        pcost[i] = mblocks + 1;
+        pcost[i] = g.full ? 2 * mblocks : mblocks + 1;
         items += it;
         cost += it * pcost[i];
     }
@@ -1315,8 +1497,9 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
 }
 
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
-                              const void *Ht, int n_comp, float *parts, int *mblocks_out) {
-    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask};
+                              const void *Ht, int n_comp, float *parts, int *mblocks_out,
+                              const void *Hlo) {
+    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask, Hlo};
     RB_TRY(rb_launch_rowred_lp_group(ctx, prec, &pr, 1, n_comp));
     if (mblocks_out) *mblocks_out = rb_rowred_lp_mblocks(n);
     return RB_OK;
@@ -1466,7 +1649,8 @@ rb_status rb_launch_forward_lp_group(rb_ctx *ctx, rb_prec prec, const rb_fwd_pla
 rb_status rb_forward_lp_reduce(rb_ctx *ctx, const rb_fwd_plan *pl, float *d) {
     rb_prof_begin(ctx, ST_FORWARD_REDUCE);
     hipLaunchKernelGGL(forward_reduce_lp, dim3((pl->n + 255) / 256, pl->n), dim3(256), 0,
-                       ctx->stream, pl->dpart, pl->n, pl->splitk, pl->vscale, (float2 *)d);
+                       ctx->stream, pl->dpart, pl->n, pl->splitk, pl->vscale, pl->gr.scales,
+                       (float2 *)d);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
@@ -1492,14 +1676,16 @@ rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
     RB_TRY(rb_arena_reserve(
         ctx, &ctx->ws, rb_align((size_t)f.splitk * n * n * sizeof(float2)) + rb_align(8)));
     rb_fwd_plan pl;
+    pl.gr = *gr;
     pl.n = n;
     pl.splitk = f.splitk;
     pl.dpart = rb_carve<float2>(&ctx->ws, (size_t)f.splitk * n * n);
     pl.vscale = rb_carve<float>(&ctx->ws, 2);
     rb_prof_begin(ctx, ST_FORWARD);
     if (w) {
-        // range scale of v = w delta (the node weights are folded into the A operand)
-        RB_TRY(launch_range_scale(ctx, (const float2 *)w, (size_t)K, delta, 14, pl.vscale));
+        // range scale of v = w delta (the node weights are folded into the A operand): the
+        // parts of v below 1, so that |G v| < 2^15 with G's rows scaled below 2^14 per part
+        RB_TRY(launch_range_scale(ctx, (const float2 *)w, (size_t)K, delta, 0, pl.vscale));
     } else {
         hipLaunchKernelGGL(square_scale_kernel, dim3(1), dim3(1), 0, ctx->stream, gscale,
                            pl.vscale);

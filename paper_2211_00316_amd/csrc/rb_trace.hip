@@ -448,10 +448,16 @@ __device__ __forceinline__ bool barycentric(float au, float av, float bu, float 
 #define RB_BARY_EPS 1e-5f
 
 // Where binning writes: the tables of the C ABI, or (rec != nullptr, inside a frequency step)
-// one compact record per (transducer, node), see rb_launch_trace.
+// one compact record per (transducer, node), see rb_launch_trace. With compact records the
+// binning also keeps, per transducer, the largest A and 1/A it wrote (the per-row operand
+// scales of the 16-bit form come from them): per walk workgroup in tmax[2 (el ntiles + t)],
+// and, for nodes the folded-fan resolve writes, directly in rowmax[2 e] (bits of positive
+// floats, which order as unsigned integers).
 struct TableOut {
     rb_tables tb;
     float4 *rec;
+    float *tmax;
+    unsigned int *rowmax;
 };
 
 // Travel-time residual of a triangle at barycentric (la, lb, lc): one fixed order of
@@ -513,13 +519,13 @@ __device__ __forceinline__ float ray_atan2(float y, float x) {
 
 __device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
                                              const float lam[3], int K, double d, double c0,
-                                             const TableOut &to, size_t out) {
+                                             const TableOut &to, size_t out, float &A) {
     const float4 f0 = sb.fld[vb[0]], f1 = sb.fld[vb[1]], f2 = sb.fld[vb[2]];
     const float dT = tri_dT(lam[0], lam[1], lam[2], f0.x, f1.x, f2.x);
     const float L = tri_dT(lam[0], lam[1], lam[2], f0.y, f1.y, f2.y);
     const float tx = tri_dT(lam[0], lam[1], lam[2], f0.z, f1.z, f2.z);
     const float ty = tri_dT(lam[0], lam[1], lam[2], f0.w, f1.w, f2.w);
-    const float A = __expf(L) * rsqrtf((float)d);
+    A = __expf(L) * rsqrtf((float)d);
     if (to.rec) {
         to.rec[out] = make_float4(dT, A, ray_atan2(ty, tx), __int_as_float(0x80 | (K & 3)));
         return dT;
@@ -706,6 +712,68 @@ __device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int el, i
     return K;
 }
 
+// One (transducer, mask node) of the walk: writes its table entry (and, in a folded fan, its
+// seed key); returns the amplitude written (0 for an invalid entry or a node left to the
+// rasterisation).
+__device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, int S, int el,
+                                             int e0, const GridP &g, double ds, double c0,
+                                             int n_mask, int ii, int jj, int q, bool fold, int t,
+                                             int ntiles, const int2 *__restrict__ off,
+                                             const TableOut &to,
+                                             unsigned long long *__restrict__ keys,
+                                             uint8_t *__restrict__ changed,
+                                             uint8_t *__restrict__ marks, int mtx, int mtiles,
+                                             int *lost, double psi0, float dpsi, double ids) {
+    const int e = e0 + el;
+    const size_t out = (size_t)e * n_mask + q;
+    const size_t kq = (size_t)el * n_mask + q;
+    const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;  // the walk's guess only
+    const double2 xy = sb.ring[e];
+    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
+    double ddx = px - xy.x, ddy = py - xy.y;
+    double d = sqrt_newton(ddx * ddx + ddy * ddy);
+    const size_t mq = (size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT);
+    // a node near a fold (marked tile) is left to the rasterisation, which offers it every
+    // triangle that touches its tile
+    if (d < 2.0 * ds || (fold && marks[mq])) {
+        write_invalid(to, out);
+        if (fold) {
+            keys[kq] = ~0ull;
+            changed[kq] = 0;
+        }
+        return 0.f;
+    }
+    int j, i;
+    straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, j, i);
+    const int2 o = off[(size_t)el * ntiles + t];
+    j = min(max(j + o.x, 0), n_rays - 2);
+    i = min(max(i + o.y, 1), S - 2);
+    size_t vb[3];
+    float lam[3];
+    int half;
+    if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
+                  (float)jj, j, i, vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
+        // no ray of an unfolded fan has K > 0
+        const int K = fold ? tri_K(sb, n_rays, el, j, i, half, vb) : 0;
+        float A;
+        const float dT = write_entry(sb, vb, lam, K, d, c0, to, out, A);
+        if (fold) {
+            keys[kq] = tri_key(dT, (uint32_t)(((size_t)j * S + i) * 2 + half));
+            changed[kq] = 0;
+        }
+        return A;
+    }
+    write_invalid(to, out);
+    if (fold) {  // left to the rasterisation
+        keys[kq] = ~0ull;
+        changed[kq] = 0;
+        marks[mq] = 1;
+    } else {
+        atomicAdd(lost, 1);
+    }
+    return 0.f;
+}
+
 // One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
 // one transducer and starts every walk from the straight-ray guess plus the tile's offset.
 // In a fan that folds, the walk's triangle is one candidate of the smallest-key rule: its
@@ -730,62 +798,40 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
     const int G = LOCATE_GROUP_ROWS * tiles_x;
     const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
     const int item = ((k / G) * 8 + xcd) * G + k % G;
-    if (item >= E * ntiles) return;
+    if (item >= E * ntiles) return;  // the whole workgroup
     const int el = item / ntiles, t = item - el * ntiles;
     const bool fold = sb.folded[el] != 0;  // uniform over the block
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
-    if (ii >= g.nx || jj >= g.ny) return;
-    const int q = qmap[(size_t)jj * g.nx + ii];
-    if (q < 0) return;
-    const int e = e0 + el;
-    const size_t out = (size_t)e * n_mask + q;
-    const size_t kq = (size_t)el * n_mask + q;
-    const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;  // the walk's guess only
-    const double2 xy = sb.ring[e];
-    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
-    double ddx = px - xy.x, ddy = py - xy.y;
-    double d = sqrt_newton(ddx * ddx + ddy * ddy);
-    const size_t mq = (size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT);
-    // a node near a fold (marked tile) is left to the rasterisation, which offers it every
-    // triangle that touches its tile
-    if (d < 2.0 * ds || (fold && marks[mq])) {
-        write_invalid(to, out);
-        if (fold) {
-            keys[kq] = ~0ull;
-            changed[kq] = 0;
-        }
-        return;
+    float A = 0.f;
+    if (ii < g.nx && jj < g.ny) {
+        const int q = qmap[(size_t)jj * g.nx + ii];
+        if (q >= 0)
+            A = locate_node(sb, n_rays, S, el, e0, g, ds, c0, n_mask, ii, jj, q, fold, t, ntiles,
+                            off, to, keys, changed, marks, mtx, mtiles, lost, psi0, dpsi, ids);
     }
-    int j, i;
-    straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, j, i);
-    const int2 o = off[(size_t)el * ntiles + t];
-    j = min(max(j + o.x, 0), n_rays - 2);
-    i = min(max(i + o.y, 1), S - 2);
-    size_t vb[3];
-    float lam[3];
-    int half;
-    if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
-                  (float)jj, j, i, vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
-        // no ray of an unfolded fan has K > 0
-        const int K = fold ? tri_K(sb, n_rays, el, j, i, half, vb) : 0;
-        const float dT = write_entry(sb, vb, lam, K, d, c0, to, out);
-        if (fold) {
-            keys[kq] = tri_key(dT, (uint32_t)(((size_t)j * S + i) * 2 + half));
-            changed[kq] = 0;
+    if (to.tmax) {
+        // the workgroup's largest A and 1/A (0 where no record was written)
+        __shared__ float red[2][4];
+        float m0 = A, m1 = A > 0.f ? 1.0f / A : 0.f;
+        for (int o = 32; o > 0; o >>= 1) {
+            m0 = fmaxf(m0, __shfl_xor(m0, o));
+            m1 = fmaxf(m1, __shfl_xor(m1, o));
         }
-    } else {
-        write_invalid(to, out);
-        if (fold) {  // left to the rasterisation
-            keys[kq] = ~0ull;
-            changed[kq] = 0;
-            marks[mq] = 1;
-        } else {
-            atomicAdd(lost, 1);
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = m0;
+            red[1][threadIdx.x >> 6] = m1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            to.tmax[2 * (size_t)item] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+            to.tmax[2 * (size_t)item + 1] =
+                fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
         }
     }
 }
+
 
 // Offer triangle tid to every mask node it covers. Keys only decrease, so a stale read of a
 // node's key costs at most a needless atomic; a node whose key this triangle lowers is
@@ -963,7 +1009,12 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
     const int K = tri_K(sb, n_rays, el, j, i, half, vb);
-    write_entry(sb, vb, lam, K, d, c0, to, out);
+    float A;
+    write_entry(sb, vb, lam, K, d, c0, to, out, A);
+    if (to.rowmax && A > 0.f) {
+        atomicMax(to.rowmax + 2 * e, __float_as_uint(A));
+        atomicMax(to.rowmax + 2 * e + 1, __float_as_uint(1.0f / A));
+    }
 }
 
 __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int e0,
@@ -1216,6 +1267,35 @@ __global__ void ring_positions(double R, double psi0, int N, double2 *pos) {
     }
 }
 
+// Per-transducer maxima of the walk's workgroups (tmax, one pair per (transducer, tile) of a
+// chunk) folded into rowmax; one workgroup per transducer of the chunk.
+__global__ void __launch_bounds__(256) tile_max_fold(const float *__restrict__ tmax, int ntiles,
+                                                     int e0, unsigned int *__restrict__ rowmax) {
+    __shared__ float red[2][4];
+    const int el = blockIdx.x;
+    float m0 = 0.f, m1 = 0.f;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        const size_t o = 2 * ((size_t)el * ntiles + t);
+        m0 = fmaxf(m0, tmax[o]);
+        m1 = fmaxf(m1, tmax[o + 1]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmaxf(m0, __shfl_xor(m0, o));
+        m1 = fmaxf(m1, __shfl_xor(m1, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = m0;
+        red[1][threadIdx.x >> 6] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m0 = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+        m1 = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+        atomicMax(rowmax + 2 * (e0 + el), __float_as_uint(m0));
+        atomicMax(rowmax + 2 * (e0 + el) + 1, __float_as_uint(m1));
+    }
+}
+
 __global__ void zero_i32(int32_t *x, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0;
@@ -1273,7 +1353,8 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
            rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
            rb_align((size_t)(g->nx + 3) * (g->ny + 3) * 4 * sizeof(float4)) +
-           rb_align((size_t)C * r->n * sizeof(int32_t));
+           rb_align((size_t)C * r->n * sizeof(int32_t)) +
+           rb_align((size_t)C * tiles * 2 * sizeof(float));
 }
 
 size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
@@ -1283,7 +1364,7 @@ size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_para
 
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
-                          float4 *rec, double2 *ring_out) {
+                          float4 *rec, double2 *ring_out, unsigned int *rowmax) {
     const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
     const int n_mask = (int)ctx->n_mask;
     const int C = trace_chunk(ctx->sample_budget, r, tp, n_mask);
@@ -1307,8 +1388,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
     if (ring_out) ringpos = ring_out;
-    const TableOut to{*out, rec};
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
+    float *tmax = rb_carve<float>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y * 2);
+    const bool rows = rec && rowmax;
+    const TableOut to{*out, rec, rows ? tmax : nullptr, rows ? rowmax : nullptr};
     sb.ring = ringpos;
     unsigned long long *keys = rb_carve<unsigned long long>(&ctx->ws, (size_t)C * n_mask);
     uint8_t *changed = rb_carve<uint8_t>(&ctx->ws, (size_t)C * n_mask);
@@ -1330,6 +1413,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
                        r->radius, r->psi0, N, ringpos);
     RB_CHECK_LAUNCH(ctx);
+    if (rows) RB_TRY(rb_launch_fill_i32(ctx, reinterpret_cast<int32_t *>(rowmax), 2 * N, 0));
     hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, n_s,
                        g->nx, g->ny, padded);
     RB_CHECK_LAUNCH(ctx);
@@ -1379,6 +1463,11 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            toff, to, keys, changed, marks, mtx, mtiles, lost,
                            (float)(RB_TWO_PI / N), 1.0 / tp->ds);
         RB_CHECK_LAUNCH(ctx);
+        if (rows) {
+            hipLaunchKernelGGL(tile_max_fold, dim3(E), dim3(256), 0, ctx->stream, tmax, ntiles,
+                               e0, rowmax);
+            RB_CHECK_LAUNCH(ctx);
+        }
         rb_prof_end(ctx);
         // folded fans: smallest-key rasterisation against the walk's keys, and resolve of
         // the nodes it changed

@@ -319,18 +319,27 @@ def test_nonfinite_update_leaves_model_unchanged(ctx):
 # Reduced-precision form (16-bit operands, FP32 accumulation) -----------------------------
 # Tolerances follow the unit roundoff u of the operand type (bf16 2^-9, fp16 2^-12 relative
 # for round-to-nearest): operands <= 8u, contractions (two rounded factors, random-phase
-# sums, a rounded epilogue factor) <= 40u; the reconstructed image <= 2e-3 relative.
-LOWP = {"bf16": (2, 2.0 ** -9), "fp16": (3, 2.0 ** -12)}
+# sums, a rounded epilogue factor) <= 40u. The image gate is relative to what the oracle's
+# step changed, ||c_gpu - c_or|| / ||c_or - c_start|| over the mask, <= 2e-3: the split FP16
+# form (fp16x) meets it; the plain forms do not (their rounding of H is amplified by the
+# cancellation in the back-projection's double sum) and are held to 40u there.
+LOWP = {"bf16": (2, 2.0 ** -9), "fp16": (3, 2.0 ** -12), "fp16x": (4, 2.0 ** -12)}
+IMAGE_GATE = 2e-3
 
 
-@pytest.mark.parametrize("pname", ["bf16", "fp16"])
-@pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
-def test_build_green_lowp(ctx, name, pname):
+@pytest.mark.parametrize("pname", ["bf16", "fp16", "fp16x"])
+@pytest.mark.parametrize("name,f", [("small", 500e3), ("ragged", 500e3), ("ring64", 500e3),
+                                    ("ring64", 100e3), ("ring64", 1.2e6)])
+def test_build_green_lowp(ctx, name, f, pname):
+    # 16-bit operands with per-transducer power-of-two scales, at the lowest and highest
+    # frequency of the continuation and in between: the unscaled values match the oracle, and
+    # every stored row's largest value sits in [2^12, 2^14) for G (the bound from the row's
+    # largest amplitude is tight) and below 2^14 for H.
     prec, u = LOWP[pname]
     st, c = case(name)
     tb_o, _ = oracle_tables(name)
-    om = 2 * math.pi * 500e3
-    _say(f"build_green {pname} {name}")
+    om = 2 * math.pi * f
+    _say(f"build_green {pname} {name} {f:.0f} Hz")
     gr = ctx.build_green(tables_to_gpu(tb_o), om, C0, prec=prec)
     G, H, Hx, Hy = green.build_green(tb_o, om)
     errs = [rel_l2(to_np(gr.complex_G()), G)]
@@ -338,6 +347,15 @@ def test_build_green_lowp(ctx, name, pname):
     errs += [rel_l2(Hs[k], ref) for k, ref in enumerate((H, Hx, Hy))]
     _say("  rel L2 G %.2e, H %.2e, Hx %.2e, Hy %.2e" % tuple(errs))
     assert max(errs) <= 8 * u
+    sc = to_np(gr.scales).astype(np.float64)
+    assert np.all(sc > 0) and np.array_equal(np.exp2(np.round(np.log2(sc))), sc)
+    Gs = np.abs(to_np(gr.G.float()))[:, :, :G.shape[1]].max(axis=(0, 2))
+    rows = tb_o.valid.any(axis=1)
+    assert np.all(Gs < 2.0 ** 14) and np.all(Gs[rows] >= 2.0 ** 12)
+    assert np.abs(to_np(gr.H.float())).max() < 2.0 ** 14
+    if pname == "fp16x":
+        # the high and low parts together carry H to about u^2
+        assert max(errs[1:]) <= 4 * u * u + 1e-6
 
 
 def _green_gpu_lowp(ctx, name, om, prec):
@@ -406,7 +424,7 @@ def test_born_forward_carried_weights(ctx, n, n_mask, pname):
     assert np.array_equal(d, d.T)
 
 
-@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("pname", ["bf16", "fp16", "fp16x"])
 @pytest.mark.parametrize("name", ["small", "ragged", "ring64"])
 def test_backproject_lowp(ctx, name, pname):
     import torch
@@ -426,10 +444,10 @@ def test_backproject_lowp(ctx, name, pname):
     ref = born.backproject(R.astype(np.complex128), H, Hx, Hy, S)
     err = rel_l2(dm, ref)
     _say(f"  rel L2 {err:.2e}")
-    assert err <= 40 * u
+    assert err <= (4 * u if pname == "fp16x" else 40 * u)
 
 
-@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+@pytest.mark.parametrize("pname", ["bf16", "fp16", "fp16x"])
 @pytest.mark.parametrize("name,window", [("ring64", 1), ("ragged", 5)])
 def test_frequency_step_lowp_image(ctx, name, window, pname):
     import torch
@@ -450,8 +468,8 @@ def test_frequency_step_lowp_image(ctx, name, window, pname):
                        prec=prec)
     q = st.grid.mask_index()
     c_new = to_np(c_g).ravel()[q]
-    img = rel_l2(c_new, c_ref.ravel()[q])
-    upd = rel_l2(c_new - C0, (c_ref - c0).ravel()[q])
-    _say(f"  image rel L2 {img:.2e}, update rel L2 {upd:.2e}")
-    assert img <= 2e-3
-    assert upd <= 40 * u
+    img = rel_l2(c_new, c_ref.ravel()[q])   # ||c||-normalised (printed only)
+    re = float(np.linalg.norm(c_new - c_ref.ravel()[q]) /
+               np.linalg.norm((c_ref - c0).ravel()[q]))   # the gate: relative to the change
+    _say(f"  image RE {re:.2e} (||c||-normalised {img:.2e})")
+    assert re <= (IMAGE_GATE if pname == "fp16x" else 40 * u)

@@ -68,7 +68,8 @@ def test_noalloc_backprojection_rejects_sizes_beyond_its_scratch():
     tiny = torch.zeros(16, dtype=torch.float32, device="cuda:0")
     # n = 4096 transducers over 10^6 nodes: about 140 MB of scratch; rejected by the size check
     # before anything reads the (deliberately tiny) operands
-    g = _lib._Green(4096, 1_000_000, _lib.RB_BF16, tiny.data_ptr(), tiny.data_ptr())
+    g = _lib._Green(4096, 1_000_000, _lib.RB_BF16, tiny.data_ptr(), tiny.data_ptr(),
+                    tiny.data_ptr())
     st = lib.rb_backproject_noalloc(ctx._h, ctypes.byref(g), ctypes.c_void_p(tiny.data_ptr()),
                                     ctypes.c_void_p(tiny.data_ptr()), 1e6, 1e5,
                                     ctypes.c_void_p(tiny.data_ptr()), 0)
