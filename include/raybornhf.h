@@ -271,6 +271,35 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             const float *data, double tau, rb_mode mode, rb_prec prec,
                             double *residual_norm, rb_report *report);
 
+/* Green's functions of a Gauss-Newton step: traced rays (the Hessian-based ray-Born method of
+ * Section 6.3.2 b) or water's, computed analytically (App. B; the prototype Born method of
+ * Section 6.3.2 c, where the sound speed enters only the scattering potential). */
+typedef enum { RB_GREEN_RAY = 0, RB_GREEN_WATER = 1 } rb_green_model;
+
+/* One Gauss-Newton update of the frequency set (Section 6.3.2 b, c): the linearised
+ * subproblem (Eq. linearised-linearised-subproblem, Q = 1) solved by n_inner conjugate-
+ * gradient iterations on the Hessian action H x = Re sum_w J_w^H J_w x (Eq. hessian-action)
+ * from x = 0 against -grad, grad = Re sum_w J_w^H g_res,w (Eq. functional-gradient), with
+ * J_w the Born operator (Eqs. perturb1, derivative; w = omega^2 dx^2) on the pairs the
+ * residual keeps (valid, e != r); then m <- m + tau x on the mask (tau = 1: the Gauss-Newton
+ * step), c = m^-1/2, committed only if finite. The iteration stops early (keeps x) once
+ * r.r = 0 or p.Hp <= 0. RB_GREEN_RAY: tables, Green's functions and predicted data as in
+ * rb_frequency_step (rays on box_w(c0/c), smooth_w odd; the rough part m - m_s in the data);
+ * RB_GREEN_WATER: T = |x - x_e| / c0, A = (8 pi |x - x_e|)^-1/2, predicted data
+ * g0 + F0 (m - c0^-2); no rays are traced and smooth_w is ignored. prec as in
+ * rb_frequency_step (16-bit operands with FP32 accumulation; RB_F16X behaves as RB_F16);
+ * the CG vectors and scalars are FP64 on the device. omega: HOST [n_omega] (1..8); data:
+ * complex64 [n_omega][n][n]; 1 <= n_inner <= 256. residual_norm (device double or NULL):
+ * sum |g_res|^2 before the update; cg_norms (device double [n_inner + 1] or NULL): |r_k| of
+ * the normal equations at each iterate. report: as in rb_frequency_step. The operands of
+ * all n_omega frequencies stay resident during the iteration, in a workspace of their own
+ * that rb_reserve does not cover (allocated on first use, grown when a call needs more). */
+rb_status rb_gauss_newton_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                               const rb_trace_params *tp, double *c, int32_t smooth_w,
+                               int32_t n_omega, const double *omega, const float *data,
+                               double tau, int32_t n_inner, rb_green_model model, rb_prec prec,
+                               double *residual_norm, double *cg_norms, rb_report *report);
+
 /* Several frequency steps in a row: the frequency continuation of Section 6.3.2 (one step
  * per frequency set, sets ordered low to high by the caller). Step k uses smoothing window
  * smooth_w[k] and the next n_omega[k] entries of omega / d_omega (HOST arrays, sets

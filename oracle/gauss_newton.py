@@ -94,14 +94,14 @@ def cg(apply, b, n_iter):
 
 
 def gauss_newton_step(c, st: StepSetup, omegas, data, tau, n_inner, window=1, model="ray",
-                      return_parts=False, workers=None):
+                      return_parts=False, workers=None, map32=False):
     """One Gauss-Newton update of c (ny, nx) from the data of the frequency set omegas
     (data shape (n_omega, N_e, N_r)): model "ray" (Hessian-based ray-Born) or "water"
-    (prototype Born)."""
+    (prototype Born); workers and map32 as in oracle.step.tables_for."""
     q = st.grid.mask_index()
     N = st.ring.n
     if model == "ray":
-        tb, ns = tables_for(c, st, window, workers=workers)
+        tb, ns = tables_for(c, st, window, workers=workers, map32=map32)
     elif model == "water":
         tb = water_tables(st)
         dm_w = 1.0 / c.ravel()[q] ** 2 - 1.0 / st.c0 ** 2

@@ -43,13 +43,17 @@ def _tables_of_chunk(args):
 
 
 def tables_for(c: np.ndarray, st: StepSetup, window: int, emitters=None, link=None,
-               workers=None):
+               workers=None, map32=False):
     """Trace on box_window(c0/c) and bin; returns (Tables, n_s). link (None, or a dict of
     oracle.linking options): receiver tables from the linked rays instead of the fan's
     interpolation in exit angle. workers > 1: the transducers are traced and binned in that
     many processes, in chunks whose table rows are stacked in order (each row depends on its
-    own transducer's rays only, so the tables are the same)."""
+    own transducer's rays only, so the tables are the same). map32: the smoothed map is
+    rounded to FP32 first (the representation a device receives it in; everything after is
+    FP64), for comparisons with a path that stores the map in FP32."""
     ns = box_smooth(refractive_index(c, st.c0), window)
+    if map32:
+        ns = ns.astype(np.float32).astype(np.float64)
     if workers and workers > 1 and link is None:
         import concurrent.futures
         import multiprocessing
@@ -106,10 +110,10 @@ def update(c: np.ndarray, dm_mask: np.ndarray, tau: float, grid: Grid):
 
 def frequency_step(c, st: StepSetup, omegas, d_omegas, data, tau, window=1,
                    mode="ray_born", isochron_sign=1.0, return_parts=False, link=None,
-                   workers=None):
+                   workers=None, map32=False):
     """One Hessian-free update of the sound speed c (ny, nx) from the data of the frequency
-    set omegas (data shape (n_omega, N_e, N_r)); link and workers as in tables_for."""
-    tb, ns = tables_for(c, st, window, link=link, workers=workers)
+    set omegas (data shape (n_omega, N_e, N_r)); link, workers and map32 as in tables_for."""
+    tb, ns = tables_for(c, st, window, link=link, workers=workers, map32=map32)
     q = st.grid.mask_index()
     cq = c.ravel()[q]
     dm = np.zeros(q.size)

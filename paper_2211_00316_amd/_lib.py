@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libraybornhf.so")
 RB_OK, RB_EINVAL, RB_ENOMEM, RB_EDEVICE, RB_ENONFINITE, RB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RB_F32, RB_BF16, RB_F16, RB_F16X = 1, 2, 3, 4
 RB_RAY_BORN, RB_RAY_ONLY = 0, 1
+RB_GREEN_RAY, RB_GREEN_WATER = 0, 1
 
 SYMBOLS = (
     "rb_create", "rb_destroy", "rb_last_error", "rb_mask_count", "rb_refractive_index",
@@ -26,7 +27,7 @@ SYMBOLS = (
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
     "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
     "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking", "rb_workspace_bytes",
-    "rb_reserve", "rb_backproject_noalloc",
+    "rb_reserve", "rb_backproject_noalloc", "rb_gauss_newton_step",
 )
 RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
@@ -159,6 +160,10 @@ def load(path: str = LIB_PATH):
                                ctypes.c_size_t),
         "rb_reserve": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                         ctypes.POINTER(TraceParams), ctypes.c_int], ctypes.c_int),
+        "rb_gauss_newton_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                                  ctypes.POINTER(TraceParams), P, I32, I32, ctypes.POINTER(D),
+                                  P, D, I32, ctypes.c_int, ctypes.c_int, P, P, P],
+                                 ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -522,6 +527,32 @@ class Context:
             self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
             int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), int(prec),
             _ptr(residual_norm), _ptr(report)))
+        return c
+
+    def gauss_newton_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
+                          smooth_w: int, omegas, data: torch.Tensor, tau: float, n_inner: int,
+                          model: int = RB_GREEN_RAY, prec: int = RB_F32,
+                          residual_norm: torch.Tensor | None = None,
+                          cg_norms: torch.Tensor | None = None,
+                          report: torch.Tensor | None = None):
+        """rb_gauss_newton_step: one Gauss-Newton update of c (float64 [ny][nx], on the GPU)
+        in place; model RB_GREEN_RAY (Hessian-based ray-Born) or RB_GREEN_WATER (prototype
+        Born). cg_norms: float64 [n_inner + 1] receiving |r_k| of the CG iterates."""
+        _dev(c, torch.float64)
+        _dev(data, torch.complex64)
+        for t in (residual_norm, cg_norms):
+            if t is not None:
+                _dev(t, torch.float64)
+        if cg_norms is not None and cg_norms.numel() < n_inner + 1:
+            raise ValueError("cg_norms needs n_inner + 1 entries")
+        if report is not None:
+            _dev(report, torch.uint8)
+        k = len(omegas)
+        om = (ctypes.c_double * k)(*[float(o) for o in omegas])
+        self._check(self.lib.rb_gauss_newton_step(
+            self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
+            int(smooth_w), k, om, _ptr(data), float(tau), int(n_inner), int(model), int(prec),
+            _ptr(residual_norm), _ptr(cg_norms), _ptr(report)))
         return c
 
     def frequency_sweep(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,

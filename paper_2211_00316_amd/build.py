@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["rb_api.hip", "rb_trace.hip", "rb_green.hip", "rb_gemm.hip", "rb_lowp.hip"]
+SOURCES = ["rb_api.hip", "rb_trace.hip", "rb_green.hip", "rb_gemm.hip", "rb_lowp.hip",
+           "rb_gn.hip"]
 LIB = os.path.join(HERE, "libraybornhf.so")
 
 FLAGS = [

@@ -375,6 +375,7 @@ void rb_destroy(rb_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws.base) (void)hipFree(ctx->ws.base);
     if (ctx->step.base) (void)hipFree(ctx->step.base);
+    if (ctx->gn.base) (void)hipFree(ctx->gn.base);
     if (ctx->d_mask_index) (void)hipFree(ctx->d_mask_index);
     if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
@@ -835,6 +836,173 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     if (st == RB_OK) st = rb_launch_report(ctx, report);
     ctx->deferred = false;
     return st;
+}
+
+// Gauss-Newton step ----------------------------------------------------------------------
+// Its workspace lies outside rb_reserve: grown on demand whatever the reservation.
+static rb_status gn_reserve(rb_ctx *ctx, size_t bytes) {
+    rb_arena *a = &ctx->gn;
+    if (bytes <= a->cap) return RB_OK;
+    if (a->base) {
+        RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        RB_HIP(ctx, hipFree(a->base));
+        a->base = nullptr;
+        a->cap = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return rb_fail(ctx, RB_ENOMEM, "Gauss-Newton workspace of %zu bytes failed", bytes);
+    }
+    a->base = static_cast<char *>(p);
+    a->cap = bytes;
+    return RB_OK;
+}
+
+static rb_status gn_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            int32_t n_omega, const double *omega, const float *data, double tau,
+                            int32_t n_inner, rb_green_model model, rb_prec prec,
+                            double *residual_norm, double *cg_norms) {
+    StepBufs b;
+    RB_TRY(step_carve(ctx, grid, ring, prec, &b));
+    const int N = b.N, nm = b.nm;
+    const bool lp = b.lp;
+    const rb_prec kp = rb_prec_split(prec) ? RB_F16 : prec;  // G itself is never split
+    const size_t Np = (size_t)rb_lp_pad(N), Mp = (size_t)rb_lp_pad(nm);
+    const int mb = lp ? rb_rowred_lp_mblocks(N) : rb_rowred_mblocks(N);
+    const size_t gbytes = lp ? 2 * (size_t)N * Mp * 2 : (size_t)N * nm * 8;
+    const size_t gtbytes = lp ? 2 * (size_t)nm * Np * 2 : 0;
+    const size_t per = rb_align(gbytes) + rb_align(gtbytes) + rb_align(2 * (size_t)N * 4) +
+                       rb_align((size_t)nm * 8);
+    const size_t need = n_omega * per + 5 * rb_align((size_t)nm * 8) +
+                        2 * rb_align((size_t)nm * 4) + rb_align(b.NN * 8) +
+                        rb_align(2 * (size_t)N * Np * 2) + rb_align(8) + rb_align(b.NN * 8) +
+                        rb_align((size_t)2 * mb * nm * 4) + rb_gn_scalar_bytes() +
+                        rb_align((size_t)N * 16);
+    RB_TRY(gn_reserve(ctx, need));
+    rb_arena *a = &ctx->gn;
+    a->used = 0;
+    rb_green gk[8];
+    void *Gt[8];
+    float *wk[8];
+    for (int k = 0; k < n_omega; ++k) {
+        gk[k] = rb_green{N, nm, kp, rb_carve<char>(a, gbytes), b.gr.H, nullptr};
+        Gt[k] = lp ? rb_carve<char>(a, gtbytes) : nullptr;
+        gk[k].scales = rb_carve<float>(a, 2 * (size_t)N);
+        wk[k] = rb_carve<float>(a, 2 * (size_t)nm);
+    }
+    double *x = rb_carve<double>(a, nm), *r = rb_carve<double>(a, nm);
+    double *pv = rb_carve<double>(a, nm), *hp = rb_carve<double>(a, nm);
+    double *grad = rb_carve<double>(a, nm);
+    float *pf = rb_carve<float>(a, nm), *delta = rb_carve<float>(a, nm);
+    float *d = rb_carve<float>(a, 2 * b.NN);
+    uint16_t *Rp = rb_carve<uint16_t>(a, 2 * (size_t)N * Np);
+    float *rscale = rb_carve<float>(a, 2);
+    float *rsym = rb_carve<float>(a, 2 * b.NN);
+    float *parts = rb_carve<float>(a, (size_t)2 * mb * nm);
+    double *scal = reinterpret_cast<double *>(rb_carve<char>(a, rb_gn_scalar_bytes()));
+    double2 *ringpos = lp ? b.ringpos : rb_carve<double2>(a, N);
+
+    // a1-a3 or the analytic water tables
+    if (model == RB_GREEN_RAY) {
+        RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, b.n_s));
+        RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos, b.rowmax));
+    } else {
+        RB_TRY(rb_launch_water_tables(ctx, ring, tp->c0, &b.tb, b.rec, ringpos,
+                                      lp ? b.rowmax : nullptr));
+    }
+    RB_TRY(rb_launch_gather_mask(ctx, c, b.cq));
+    RB_TRY(rb_launch_gn_delta(ctx, b.cq, model == RB_GREEN_RAY ? b.n_s : nullptr, tp->c0, delta));
+    if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
+
+    auto forward = [&](int k, const float *dl, float *out) -> rb_status {
+        return lp ? rb_launch_forward_lp(ctx, &gk[k], wk[k], dl, out, nullptr)
+                  : rb_launch_forward(ctx, &gk[k], wk[k], dl, out, nullptr);
+    };
+    // Q = 1 adjoint of the pair data R (zero off the kept pairs), added to acc in FP64
+    auto adjoint = [&](int k, const float *R, double *acc, int first) -> rb_status {
+        int mbo = mb;
+        if (lp) {
+            RB_TRY(rb_launch_to_planar(ctx, kp, R, N, Rp, rscale, gk[k].scales));
+            RB_TRY(rb_launch_rowred_lp(ctx, kp, N, nm, Rp, Gt[k], 1, parts, &mbo));
+            RB_TRY(rb_launch_unscale(ctx, parts, (size_t)2 * mb * nm, rscale));
+        } else {
+            RB_TRY(rb_launch_rowred(ctx, N, nm, R, (const float *)gk[k].G, 1, 1, rsym, parts,
+                                    &mbo));
+        }
+        return rb_launch_gn_adjoint_acc(ctx, mb, parts, wk[k], acc, first);
+    };
+    // operands, predicted data, residual and gradient of every frequency of the set
+    const double h2 = grid->dx * grid->dx;
+    for (int k = 0; k < n_omega; ++k) {
+        const double om = omega[k];
+        RB_TRY(rb_launch_gn_weight(ctx, wk[k], nm, om * om * h2));
+        if (lp)
+            RB_TRY(rb_launch_green_lp_rec(ctx, b.rec, ringpos, N, om, tp->c0, &gk[k], nullptr,
+                                          nullptr, 1, b.rowmax));
+        else
+            RB_TRY(rb_launch_green(ctx, &b.tb, om, tp->c0, &gk[k], nullptr, nullptr, 1));
+        RB_TRY(forward(k, delta, d));  // Born term of m - m_s in the predicted data
+        RB_TRY(rb_launch_residual(ctx, &b.tb, om, tp->c0, d, data + 2 * b.NN * (size_t)k, b.R,
+                                  residual_norm));
+        if (lp) RB_TRY(rb_launch_transpose_conj(ctx, &gk[k], Gt[k]));
+        RB_TRY(adjoint(k, b.R, grad, k == 0));
+    }
+    // conjugate gradients on H x = -grad
+    RB_TRY(rb_launch_gn_cg(ctx, 0, x, r, pv, hp, pf, grad, scal, cg_norms, 0));
+    for (int it = 0; it < n_inner; ++it) {
+        for (int k = 0; k < n_omega; ++k) {
+            RB_TRY(forward(k, pf, d));
+            RB_TRY(rb_launch_gn_mask_pairs(ctx, d, b.tb.rx_flags, N));
+            RB_TRY(adjoint(k, d, hp, k == 0));
+        }
+        RB_TRY(rb_launch_gn_cg(ctx, 1, x, r, pv, hp, pf, nullptr, scal, cg_norms, it + 1));
+    }
+    // a9: m <- m + tau x, committed only if finite
+    RB_TRY(rb_launch_update(ctx, b.cq, x, tau, b.c_new));
+    RB_TRY(rb_launch_note_fail(ctx, 0));
+    return rb_launch_commit(ctx, b.c_new, c, ctx->d_flag);
+}
+
+rb_status rb_gauss_newton_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                               const rb_trace_params *tp, double *c, int32_t smooth_w,
+                               int32_t n_omega, const double *omega, const float *data,
+                               double tau, int32_t n_inner, rb_green_model model, rb_prec prec,
+                               double *residual_norm, double *cg_norms, rb_report *report) {
+    if (!ctx) return RB_EINVAL;
+    if (n_omega < 1 || n_omega > 8)
+        return rb_fail(ctx, RB_EINVAL, "a Gauss-Newton set holds 1..8 frequencies, not %d",
+                       n_omega);
+    if (n_inner < 1 || n_inner > 256)
+        return rb_fail(ctx, RB_EINVAL, "n_inner must be in 1..256, not %d", n_inner);
+    if (model != RB_GREEN_RAY && model != RB_GREEN_WATER)
+        return rb_fail(ctx, RB_EINVAL, "unknown Green's-function model %d", (int)model);
+    std::vector<double> dom(n_omega, 1.0);  // no spacing in this method; validated as positive
+    RB_TRY(check_step_args(ctx, grid, ring, tp, c, model == RB_GREEN_RAY ? smooth_w : 1, n_omega,
+                           omega, dom.data(), data, tau, RB_RAY_BORN, prec));
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    ctx->deferred = true;
+    rb_status st = rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0);
+    if (st == RB_OK) st = rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_FAIL_STEP, 1, -1);
+    if (st == RB_OK)
+        st = gn_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, data, tau, n_inner,
+                        model, prec, residual_norm, cg_norms);
+    if (st == RB_OK && report) st = rb_launch_report(ctx, report);
+    ctx->deferred = false;
+    if (st != RB_OK || report) return st;
+    RB_HIP(ctx, hipMemcpyAsync(ctx->h_flag, ctx->d_flag, RB_W_COUNT * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->lost_nodes = ctx->h_flag[RB_W_LOST];
+    ctx->ray_samples = *reinterpret_cast<const int64_t *>(ctx->h_flag + RB_W_SAMPLES);
+    const int32_t fl = ctx->h_flag[RB_W_FLAGS];
+    if (fl)
+        return rb_fail(ctx, RB_ENONFINITE, "the Gauss-Newton step failed (%s); c unchanged",
+                       (fl & 1) ? "a ray did not reach the ring within max_steps"
+                                : "non-finite model update");
+    return RB_OK;
 }
 
 size_t rb_workspace_bytes(const rb_grid *grid, const rb_ring *ring, const rb_trace_params *tp,

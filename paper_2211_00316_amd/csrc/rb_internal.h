@@ -70,6 +70,7 @@ struct rb_ctx {
 
     rb_arena ws;                      // scratch of the current call
     rb_arena step;                    // persistent buffers of rb_frequency_step
+    rb_arena gn;                      // per-frequency operands and CG state of a Gauss-Newton step
     int32_t *d_flag = nullptr;        // device words RB_W_* (flags, counters)
     float *d_red = nullptr;           // [RB_RED_PARTS] per-block partials of range scales
     int32_t *h_flag = nullptr;        // pinned host mirror of d_flag
@@ -107,6 +108,24 @@ enum rb_stage {
     ST_SMOOTH = 0, ST_TRACE, ST_RASTER, ST_RESOLVE, ST_RECEIVERS, ST_GREEN, ST_FORWARD,
     ST_FORWARD_REDUCE, ST_RESIDUAL, ST_BACKPROJECT, ST_FINISH, ST_UPDATE
 };
+// Gauss-Newton step (rb_gn.hip) ----------------------------------------------------------
+// Analytic water tables: the C-ABI tables (rec == NULL) or compact records, the receiver
+// tables, transducer positions and (nullable) the rows' amplitude maxima.
+rb_status rb_launch_water_tables(rb_ctx *ctx, const rb_ring *ring, double c0,
+                                 const rb_tables *tb, float4 *rec, double2 *ringpos,
+                                 unsigned int *rowmax);
+// delta = m - m_s on the mask nodes (n_s NULL: m_s = c0^-2).
+rb_status rb_launch_gn_delta(rb_ctx *ctx, const double *cq, const float *n_s, double c0,
+                             float *delta);
+rb_status rb_launch_gn_weight(rb_ctx *ctx, float *w, int n, double value);
+rb_status rb_launch_gn_mask_pairs(rb_ctx *ctx, float *d, const uint8_t *rx_flags, int N);
+rb_status rb_launch_gn_adjoint_acc(rb_ctx *ctx, int mblocks, const float *parts, const float *w,
+                                   double *acc, int first);
+size_t rb_gn_scalar_bytes();
+// op 0: start from grad (norms[k] = |r_0|); op 1: the update after H p (norms[k] = |r_k|).
+rb_status rb_launch_gn_cg(rb_ctx *ctx, int op, double *x, double *r, double *p, double *hp,
+                          float *pf, const double *grad, double *scal, double *norms, int k);
+
 // Copy the context's status words into a caller's device rb_report (one small kernel).
 rb_status rb_launch_report(rb_ctx *ctx, rb_report *rep);
 // Fill n int32 words with a value (a kernel: also inside graph captures).

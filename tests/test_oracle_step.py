@@ -96,3 +96,25 @@ def test_tables_in_worker_processes_are_the_same():
     b, _ = ostep.tables_for(c, st, 3, workers=3)
     for f in ("valid", "T", "A", "ux", "uy", "K", "rx_valid", "rx_T", "rx_A", "rx_K"):
         assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_fp32_map_option_rounds_only_the_map():
+    # map32 changes nothing but the map's representation: in water (exact in FP32) the tables
+    # are identical; in a heterogeneous medium they differ at the rounding level only
+    from oracle import step as ostep
+    from tests.oracle_fixtures import small_setup
+    import phantoms as ph
+
+    st = small_setup(N=12, R=0.012, dx=0.5e-3, n_rays=60)
+    g = st.grid
+    cw = np.full((g.ny, g.nx), C0)
+    a, _ = ostep.tables_for(cw, st, 1)
+    b, _ = ostep.tables_for(cw, st, 1, map32=True)
+    assert np.array_equal(a.T, b.T) and np.array_equal(a.A, b.A)
+    c = ph.gaussian_inclusion(g.nx, g.ny, g.dx, g.x0, g.y0, seed=4, amp=30.0, sigma=2e-3,
+                              centre_radius=3e-3, mask_radius=g.mask_radius)
+    a, ns = ostep.tables_for(c, st, 3)
+    b, ns32 = ostep.tables_for(c, st, 3, map32=True)
+    assert np.array_equal(ns32, ns.astype(np.float32).astype(np.float64))
+    v = a.valid & b.valid
+    assert np.max(np.abs(a.T[v] - b.T[v]) / a.T[v]) < 1e-6
