@@ -36,14 +36,17 @@ FP32_VECTOR_PEAK_TFLOPS = 78.6
 # Algorithmic units of the hot kernels
 TRACE_FLOP_PER_SAMPLE = 550     # two spline value+gradient+Hessian evaluations, Heun, paraxial
 TABLE_BYTES = {"f32": 21,       # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
-               "bf16": 16, "f16": 16}   # compact record: dT, A, theta, flags (4 B each)
+               "bf16": 16, "f16": 16, "f16x": 16}   # compact record: dT, A, theta, flags
 SAMPLE_BYTES = 24               # one ray sample: position 8, (dT, L, t_x, t_y) 16 (K only in folds)
-OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16}   # G (complex) + H, H_x, H_y per entry
+# operand bytes written per (e, p): G (complex) + H, H_x, H_y (+ their low parts when split)
+OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16, "f16x": 28}
 
 CSRC = os.path.join(ROOT, "paper_2211_00316_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
 # stage -> kernels it launches (FP32 form, 16-bit forms)
+PREC_CODES = {"f32": 1, "bf16": 2, "f16": 3, "f16x": 4}
+
 STAGE_KERNELS = {
     "trace": (["trace_kernel"], ["trace_kernel"]),
     "resolve": (["tile_offset_kernel", "locate_kernel"], ["tile_offset_kernel", "locate_kernel"]),
@@ -100,10 +103,11 @@ def _mask_index(w):
 
 
 def cpu_baseline(w):
-    """The FP64 oracle timed on the host on a bounded sample of the same workload: the full
-    trace + binning + receiver tables of one transducer (scaled by N), its Green's
-    functions, and the Born forward / back-projection products on a block of mask columns
-    (scaled by P_m / block); extrapolated to one frequency step."""
+    """The FP64 oracle timed on the host on a bounded sample of the same workload: trace +
+    binning + receiver tables of a sample of transducers in a process pool over the host
+    cores (two per worker, scaled by N), their Green's functions, and the Born forward /
+    back-projection products on a block of mask columns on the BLAS threads (scaled by
+    P_m / block); extrapolated to one frequency step."""
     import numpy as np
 
     import phantoms as ph
@@ -116,9 +120,12 @@ def cpu_baseline(w):
     N = w.n_trans
     Pm = grid.mask_index().size
     om = 2 * math.pi * w.freqs[0]
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    ns_sample = 2 * workers
     t0 = time.perf_counter()
-    sample = [k * N // 8 for k in range(8)]
-    tb, ns = ostep.tables_for(c, st, w.smooth_window(0), emitters=sample)
+    sample = [k * N // ns_sample for k in range(ns_sample)]
+    tb, ns = ostep.tables_for(c, st, w.smooth_window(0), emitters=sample, workers=workers)
     t_tab = time.perf_counter() - t0
     t0 = time.perf_counter()
     green.build_green(tb, om)
@@ -142,19 +149,50 @@ def cpu_baseline(w):
     return {
         "value": 1.0 / t_step,
         "unit": "frequency-step updates/s",
-        "cores": threads,
+        "cores": max(threads, workers),
         "kind": "oracle",
-        "sample": (f"FP64 oracle: trace+bin+receivers and Green's functions of "
-                   f"{len(sample)} of {N} transducers ({t_tab + t_green:.1f} s, "
-                   f"x{N / len(sample):.0f}) plus Born forward and "
-                   f"back-projection on {block} of {Pm} mask columns ({t_gemm:.1f} s, "
-                   f"x{Pm / block:.1f}); extrapolated step {t_step:.0f} s; trace/bin "
-                   f"single-threaded NumPy, products on {threads} BLAS threads"),
+        "sample": (f"FP64 oracle: trace+bin+receivers of {len(sample)} of {N} transducers "
+                   f"in {workers} processes and their Green's functions "
+                   f"({t_tab + t_green:.1f} s, x{N / len(sample):.0f}) plus Born forward and "
+                   f"back-projection on {block} of {Pm} mask columns on {threads} BLAS "
+                   f"threads ({t_gemm:.1f} s, x{Pm / block:.1f}); extrapolated step "
+                   f"{t_step:.0f} s"),
     }
 
 
 PEAKS = {"f32": (FP32_MFMA_PEAK_TFLOPS, "fp32 MFMA"), "bf16": (2500.0, "bf16 MFMA dense"),
-         "f16": (2500.0, "fp16 MFMA dense")}
+         "f16": (2500.0, "fp16 MFMA dense"), "f16x": (2500.0, "fp16 MFMA dense")}
+
+
+def _pad(x, m):
+    return (x + m - 1) // m * m
+
+
+def contraction_flops(stage, N, Pm, prec):
+    """(issued, own, dense) flop of one launch of a contraction. issued: what the kernel's
+    tiles compute (the MFMA instructions it issues); own: the symmetric products' unique
+    entries, 8 flop per complex multiply-add over N (N + 1) / 2 pairs; dense: the plain
+    complex GEMM count (8 N^2 P_m for the forward, three of them for the back-projection)."""
+    own_pairs = N * (N + 1) // 2
+    if stage == "forward_gemm":
+        if prec == "f32":   # 128 x 128 upper tiles over K = P_m
+            nT = _pad(N, 128) // 128
+            issued = 8.0 * nT * (nT + 1) // 2 * 128 * 128 * Pm
+        else:               # 256 x 128 upper tiles over K = P_m padded to 32
+            nT = _pad(N, 128) // 128
+            tiles = sum(nT - 2 * tm for tm in range((nT + 1) // 2))
+            issued = 8.0 * tiles * 256 * 128 * _pad(Pm, 32)
+        return issued, 8.0 * own_pairs * Pm, 8.0 * N * N * Pm
+    # back-projection: row slabs of 256, K over the transducers (block upper triangle of R, or
+    # the whole symmetric R in the split form), node tiles of 128 (64 in FP32)
+    Np = _pad(N, 32)
+    mb = _pad(N, 256) // 256
+    if prec == "f16x":
+        rows_k = mb * 256 * Np
+    else:
+        rows_k = sum(256 * (Np - 256 * i) for i in range(mb))
+    cols = _pad(Pm, 64 if prec == "f32" else 128)
+    return 24.0 * rows_k * cols, 24.0 * own_pairs * Pm, 24.0 * N * N * Pm
 
 
 def start_model(w, start, c_true):
@@ -261,10 +299,15 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
         "build_green": ("hbm", (tab + OPERAND_BYTES[prec]) * N * Pm / 1e9, "GB/s",
                         HBM_PEAK_GBS, "HBM3E",
                         f"{tab} B read + {OPERAND_BYTES[prec]} B written per (e, p)"),
-        "forward_gemm": ("mfma", 8.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,
-                         "8 N^2 P_m flop (complex N x N x P_m, symmetric)"),
-        "backproject_gemm": ("mfma", 24.0 * N * N * Pm / 1e12, "TFLOP/s", peak, peak_name,
-                             "24 N^2 P_m flop (3 complex GEMMs N x N x P_m)"),
+        "forward_gemm": ("mfma", contraction_flops("forward_gemm", N, Pm, prec)[0] / 1e12,
+                         "TFLOP/s", peak, peak_name,
+                         "flop the kernel issues (upper 256 x 128 tiles of the symmetric "
+                         "N x N product, 8 per complex multiply-add over P_m)"),
+        "backproject_gemm": ("mfma",
+                             contraction_flops("backproject_gemm", N, Pm, prec)[0] / 1e12,
+                             "TFLOP/s", peak, peak_name,
+                             "flop the kernel issues (3 complex products, row slabs of 256 "
+                             "over the block upper triangle of R, or all of R when split)"),
     }
     out = {}
     for stage, (bound, units, unit, pk, pk_name, what) in work.items():
@@ -284,25 +327,39 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
             "peak_is": pk_name, "per_unit": what, "avg_launch_ms": round(avg_ms, 3),
             "launches_per_step": round(launches, 2), "ms_per_step": round(ms / steps, 3),
         }
+        if stage in ("forward_gemm", "backproject_gemm"):
+            issued, own, dense = contraction_flops(stage, N, Pm, prec)
+            t = ms * 1e-3 / steps
+            out[stage]["own_work_frac"] = round(own / t / 1e12 / pk, 4)
+            out[stage]["dense_equivalent_frac"] = round(dense / t / 1e12 / pk, 4)
     return out
 
 
 def run_serve(args):
+    """Serving mix: prints its own JSON line (serve_runs with the full report)."""
+    print(json.dumps(serve_runs(args.requests, args.rate_frac, args.prec, full=True)),
+          flush=True)
+
+
+def serve_runs(n_requests, rate_frac, prec_name, full=False):
     """Serving mix: requests of three scan classes (ring 256 / 512 / 1024 on 256^2 / 512^2 /
     1024^2 grids), 8-32 frequency steps each, admitted by HBM budget and stepped with
     continuous batching (paper_2211_00316_amd.serve). A closed-loop run (every request
     waiting at time 0) measures the capacity; the reported run has Poisson arrivals at
     rate_frac of it. Some requests are then run alone and compared with their result in the
-    mix."""
+    mix. full=False (the bounded leg of the default run): one phantom per class, no
+    one-at-a-time run."""
     import numpy as np
     import torch
 
     import phantoms as ph
     from paper_2211_00316_amd import _lib, serve, setup_for
 
-    prec = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
+    prec = PREC_CODES[prec_name]
     classes = ph.SERVE_CLASSES
-    draws0 = ph.serve_draws(args.requests, seed=5, rate=None)
+    draws0 = ph.serve_draws(n_requests, seed=5, rate=None)
+    if not full:   # one phantom per class
+        draws0 = [ph.ServeDraw(d.rid, d.cls, 1, d.n_steps, d.arrival) for d in draws0]
     ctx = _lib.Context("cuda:0")
     store = {}
     for k, sd in sorted({(d.cls, d.phantom_seed) for d in draws0}):
@@ -351,13 +408,17 @@ def run_serve(args):
     print("[serve] warm-up done", file=sys.stderr, flush=True)
 
     # one request at a time (no batching), then the closed loop with batching
-    seq = serve.Server(ex, budget, max_batch=1, log=progress).run(make(draws0))
-    print(f"[serve] one at a time: {seq.summary()}", file=sys.stderr, flush=True)
+    seq = None
+    if full:
+        seq = serve.Server(ex, budget, max_batch=1, log=progress).run(make(draws0))
+        print(f"[serve] one at a time: {seq.summary()}", file=sys.stderr, flush=True)
     closed = serve.Server(ex, budget, log=progress).run(make(draws0))
     cap = len(draws0) / closed.makespan
-    rate = args.rate_frac * cap
+    rate = rate_frac * cap
     print(f"[serve] closed loop: {closed.summary()}", file=sys.stderr, flush=True)
-    draws = ph.serve_draws(args.requests, seed=5, rate=rate)
+    draws = ph.serve_draws(n_requests, seed=5, rate=rate)
+    if not full:
+        draws = [ph.ServeDraw(d.rid, d.cls, 1, d.n_steps, d.arrival) for d in draws]
     mix = serve.Server(ex, budget, log=progress).run(make(draws))
     print(f"[serve] open loop at {rate:.3f} requests/s: {mix.summary()}", file=sys.stderr,
           flush=True)
@@ -373,6 +434,10 @@ def run_serve(args):
         diffs[d.rid] = float((a.c - m.c).abs().max().item())
         print(f"[serve] request {d.rid} ({classes[d.cls].name}, {d.n_steps} steps): "
               f"max |c_alone - c_mix| = {diffs[d.rid]:.3e}", file=sys.stderr, flush=True)
+    ex.drain()
+    del store
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     out = {
         "metric": "serving frequency-step updates/s (mixed scans, continuous batching)",
         "value": round(mix.steps_per_s, 3),
@@ -384,22 +449,24 @@ def run_serve(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": prec_name,
         "data": "synthetic",
         "p50_latency_s": round(mix.latency_pct(50), 4),
         "p99_latency_s": round(mix.latency_pct(99), 4),
         "config": {"workload": f"serve_mix{len(draws)}",
                    "classes": [c.name for c in classes],
                    "requests": len(draws), "steps_per_request": "8-32",
+                   "phantoms_per_class": 3 if full else 1,
                    "arrivals": "poisson", "rate_per_s": round(rate, 4),
-                   "rate_frac_of_capacity": args.rate_frac,
+                   "rate_frac_of_capacity": rate_frac,
                    "budget_bytes": budget},
         "open_loop": mix.summary(),
         "closed_loop": closed.summary(),
-        "one_at_a_time": seq.summary(),
         "alone_vs_mix_max_abs_diff": diffs,
     }
-    print(json.dumps(out), flush=True)
+    if seq is not None:
+        out["one_at_a_time"] = seq.summary()
+    return out
 
 
 def main():
@@ -408,8 +475,21 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ring1024_grid1024")
-    ap.add_argument("--prec", default="bf16", choices=["bf16", "f16", "f32"],
-                    help="operand type of the headline (reduced-precision) form")
+    ap.add_argument("--prec", default="f16x", choices=["f16x", "bf16", "f16", "f32"],
+                    help="operand type of the headline (reduced-precision) form; f16x (FP16 "
+                         "with the back-projection operand split into two parts) is the form "
+                         "that meets the 2e-3 image tolerance")
+    ap.add_argument("--fast-form", default="bf16", choices=["bf16", "f16", "none"],
+                    help="plain 16-bit form timed beside the headline (faster, outside the "
+                         "image tolerance)")
+    ap.add_argument("--late-steps", type=int, default=3,
+                    help="steps timed from the true phantom (a late stage of the continuation: "
+                         "bent rays, folded fans); 0 skips them")
+    ap.add_argument("--no-gn", action="store_true",
+                    help="skip the Gauss-Newton (Hessian-based) and prototype Born steps")
+    ap.add_argument("--gn-inner", type=int, default=12, help="CG iterations of a Gauss-Newton step")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests of the bounded serving leg of the default run (0 skips it)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start", default="water", choices=["water", "truth"],
@@ -464,7 +544,7 @@ def main():
     print(f"[bench] {w.name}: synthesizing data for {n_total} frequencies", file=sys.stderr,
           flush=True)
     data = synthesize_data(ctx, w, grid, ring, tp, c_true, list(range(n_total)))
-    prec_code = {"bf16": _lib.RB_BF16, "f16": _lib.RB_F16, "f32": _lib.RB_F32}[args.prec]
+    prec_code = PREC_CODES[args.prec]
 
     # forward tiles and K splits of each form from the autotuner (untimed)
     tuning = {}
@@ -552,10 +632,88 @@ def main():
             "ms_per_step": round(msl, 2), "value": round(1000.0 / msl, 4),
             "linking": "secant, at most 12 rays per pair, exit-angle tolerance 1e-8 rad",
             "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stl.items()}}
+    if args.fast_form != "none" and args.fast_form != args.prec:
+        msf, stf, cf = run_form(ctx, w, grid, ring, tp, data, PREC_CODES[args.fast_form],
+                                args.steps, args.warmup, args.fast_form, c_start)
+        ff = {"ms_per_step": round(msf, 2), "value": round(1000.0 / msf, 4),
+              "note": "plain 16-bit operands: faster, outside the 2e-3 image tolerance",
+              "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stf.items()},
+              "rooflines": kernel_rooflines(stf, args.steps, N, Pm, samples, args.fast_form,
+                                            w.name)}
+        if "f32" in forms:
+            a, b = cf.reshape(-1)[mask] - 1500.0, forms["f32"][2].reshape(-1)[mask] - 1500.0
+            ff["update_rel_diff_vs_fp32"] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        line[f"{args.fast_form}_form"] = ff
+        del cf
+    if args.late_steps > 0:
+        c_late = start_model(w, "truth", c_true)
+        n_late = min(args.late_steps, len(w.freqs) - args.warmup)
+        msl, stl, _ = run_form(ctx, w, grid, ring, tp, data, prec_code, n_late,
+                               min(args.warmup, n_total - n_late), args.prec + "-late", c_late)
+        line["late_stage_form"] = {
+            "ms_per_step": round(msl, 2), "value": round(1000.0 / msl, 4), "steps": n_late,
+            "start_model": "true phantom (bent rays, folded fans)",
+            "stages_ms_per_step": {k: round(v[0] / n_late, 3) for k, v in stl.items()}}
+    if not args.no_gn:
+        line.update(gauss_newton_legs(ctx, w, grid, ring, tp, data, prec_code, args, c_start))
+    del data
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        print("[bench] bounded serving leg", file=sys.stderr, flush=True)
+        sv = serve_runs(args.serve_requests, args.rate_frac, args.prec, full=False)
+        line["serving"] = {k: sv[k] for k in ("value", "unit", "p50_latency_s",
+                                               "p99_latency_s", "steps", "config",
+                                               "closed_loop", "alone_vs_mix_max_abs_diff")}
+        line["p50_latency_s"] = sv["p50_latency_s"]
+        line["p99_latency_s"] = sv["p99_latency_s"]
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
+
+
+def gauss_newton_legs(ctx, w, grid, ring, tp, data, prec, args, c_start):
+    """The paper's comparison methods on the same workload and set of two frequencies: one
+    Hessian-based (Gauss-Newton, CG) step, one prototype Born step, and the Hessian-free step
+    of the same set (the paper reports the first about ten times as costly as the last)."""
+    import torch
+
+    from paper_2211_00316_amd import _lib
+
+    k0 = args.warmup
+    oms = [2 * math.pi * w.freqs[k0], 2 * math.pi * w.freqs[k0 + 1]]
+    d2 = data[k0:k0 + 2].contiguous()
+    win = w.smooth_window(k0)
+    d_om = oms[1] - oms[0]
+    out = {}
+
+    def timed(fn, reps=2):
+        c = c_start.clone()
+        fn(c)   # first call: workspaces
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.copy_(c_start)
+            fn(c)
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t0) / reps
+
+    ms_hf = timed(lambda c: ctx.frequency_step(grid, ring, tp, c, win, oms, [d_om, d_om], d2,
+                                               w.tau, prec=prec))
+    print(f"[bench] Hessian-free step of 2 frequencies: {ms_hf:.1f} ms", file=sys.stderr,
+          flush=True)
+    for name, model in (("gauss_newton_form", _lib.RB_GREEN_RAY),
+                        ("prototype_born_form", _lib.RB_GREEN_WATER)):
+        ms = timed(lambda c: ctx.gauss_newton_step(grid, ring, tp, c, win, oms, d2, 1.0,
+                                                   args.gn_inner, model=model, prec=prec))
+        print(f"[bench] {name}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        out[name] = {"ms_per_step": round(ms, 2), "value": round(1000.0 / ms, 4),
+                     "set": "2 frequencies", "cg_iterations": args.gn_inner,
+                     "hessian_free_ms_same_set": round(ms_hf, 2),
+                     "cost_vs_hessian_free": round(ms / ms_hf, 2)}
+    return out
 
 
 if __name__ == "__main__":

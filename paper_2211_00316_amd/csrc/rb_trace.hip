@@ -561,6 +561,7 @@ constexpr int LOCATE_MAX_IT = 96;
 // settle soon is given up and its node left to the rasterisation.
 constexpr int LOCATE_MAX_IT_FOLD = 16;
 constexpr int LTX = RB_WALK_TX, LTY = RB_WALK_TY;  // node tile of one locate workgroup
+constexpr int LOCATE_WAVES = LTX * LTY / 64;
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
@@ -783,7 +784,7 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
 // sequence is cut into groups of LOCATE_GROUP_ROWS tile rows and group g goes to XCD g mod 8,
 // so neighbouring tiles share their ray samples through one L2 while every XCD still gets an
 // even mix of the disk-shaped mask. The launch is padded to a multiple of 8 groups.
-__global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
+__global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
                                                      int tile_i0, int tile_j0, int tiles_x,
@@ -812,22 +813,17 @@ __global__ void __launch_bounds__(256) locate_kernel(SampleBufs sb, int n_rays, 
                             off, to, keys, changed, marks, mtx, mtiles, lost, psi0, dpsi, ids);
     }
     if (to.tmax) {
-        // the workgroup's largest A and 1/A (0 where no record was written)
-        __shared__ float red[2][4];
-        float m0 = A, m1 = A > 0.f ? 1.0f / A : 0.f;
+        // each wave's largest A and 1/A (0 where no record was written); no barrier, so a
+        // wave whose walks end early leaves at once
+        float m0 = A, m1 = A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f;
         for (int o = 32; o > 0; o >>= 1) {
             m0 = fmaxf(m0, __shfl_xor(m0, o));
             m1 = fmaxf(m1, __shfl_xor(m1, o));
         }
         if ((threadIdx.x & 63) == 0) {
-            red[0][threadIdx.x >> 6] = m0;
-            red[1][threadIdx.x >> 6] = m1;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            to.tmax[2 * (size_t)item] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-            to.tmax[2 * (size_t)item + 1] =
-                fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+            const size_t o = 2 * ((size_t)item * LOCATE_WAVES + (threadIdx.x >> 6));
+            to.tmax[o] = m0;
+            to.tmax[o + 1] = m1;
         }
     }
 }
@@ -1267,15 +1263,16 @@ __global__ void ring_positions(double R, double psi0, int N, double2 *pos) {
     }
 }
 
-// Per-transducer maxima of the walk's workgroups (tmax, one pair per (transducer, tile) of a
+// Per-transducer maxima of the walk's waves (tmax, one pair per (transducer, tile, wave) of a
 // chunk) folded into rowmax; one workgroup per transducer of the chunk.
 __global__ void __launch_bounds__(256) tile_max_fold(const float *__restrict__ tmax, int ntiles,
                                                      int e0, unsigned int *__restrict__ rowmax) {
     __shared__ float red[2][4];
     const int el = blockIdx.x;
+    const int per = ntiles * LOCATE_WAVES;
     float m0 = 0.f, m1 = 0.f;
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        const size_t o = 2 * ((size_t)el * ntiles + t);
+    for (int t = threadIdx.x; t < per; t += blockDim.x) {
+        const size_t o = 2 * ((size_t)el * per + t);
         m0 = fmaxf(m0, tmax[o]);
         m1 = fmaxf(m1, tmax[o + 1]);
     }
@@ -1354,7 +1351,7 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
            rb_align((size_t)(g->nx + 3) * (g->ny + 3) * 4 * sizeof(float4)) +
            rb_align((size_t)C * r->n * sizeof(int32_t)) +
-           rb_align((size_t)C * tiles * 2 * sizeof(float));
+           rb_align((size_t)C * tiles * LOCATE_WAVES * 2 * sizeof(float));
 }
 
 size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_params *tp,
@@ -1389,7 +1386,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
     if (ring_out) ringpos = ring_out;
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
-    float *tmax = rb_carve<float>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y * 2);
+    float *tmax =
+        rb_carve<float>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y * LOCATE_WAVES * 2);
     const bool rows = rec && rowmax;
     const TableOut to{*out, rec, rows ? tmax : nullptr, rows ? rowmax : nullptr};
     sb.ring = ringpos;
