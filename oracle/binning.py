@@ -18,7 +18,10 @@ Readings (the paper gives no further detail):
     triangle covers it or when it lies within 2 ds of the source;
   * receivers: the exit angle of each ray, measured from the source angle in [0, 2 pi), is
     linearly interpolated between neighbouring rays that bracket the receiver angle (dT and L
-    interpolated), the smallest travel time wins, and an unbracketed pair is invalid.
+    interpolated), the smallest travel time wins, and an unbracketed pair is invalid;
+  * with an absorption integral B on the rays (Eq. amplitude-abs-discretised), B is carried
+    to the nodes and receivers by the same interpolation as dT (it is smooth and zero at the
+    source).
 """
 from __future__ import annotations
 
@@ -46,6 +49,8 @@ class Tables:
     rx_T: np.ndarray
     rx_A: np.ndarray
     rx_K: np.ndarray
+    B: np.ndarray = None      # int alpha0 ds of the ray at the node (lossy tables), else None
+    rx_B: np.ndarray = None   # the same at the receivers
 
 
 def _ray_block(s: RaySamples, e: int):
@@ -65,6 +70,10 @@ def bin_emitter(s: RaySamples, e: int, grid: Grid, ring: Ring, ds: float, max_st
     with np.errstate(divide="ignore", invalid="ignore"):
         L = np.log(s.A[rows]) + 0.5 * np.log(d)
     TX, TY, KK = s.tx[rows], s.ty[rows], s.K[rows]
+    lossy = s.B is not None
+    fields = (("dT", dT), ("L", L), ("tx", TX), ("ty", TY))
+    if lossy:
+        fields = fields + (("B", s.B[rows]),)
     M = s.M[rows]
     ok = s.valid[rows]
     nr = rows.size
@@ -85,7 +94,7 @@ def bin_emitter(s: RaySamples, e: int, grid: Grid, ring: Ring, ds: float, max_st
     qmap[qidx] = np.arange(qidx.size)
     Pm = qidx.size
     out_valid = np.zeros(Pm, dtype=bool)
-    out = {k: np.zeros(Pm) for k in ("dT", "L", "tx", "ty")}
+    out = {k: np.zeros(Pm) for k, _ in fields}
     out_K = np.zeros(Pm, dtype=np.int64)
     if not tri_j:
         return _finish(out_valid, out, out_K, grid, xe, ye, ds, c0)
@@ -137,7 +146,7 @@ def bin_emitter(s: RaySamples, e: int, grid: Grid, ring: Ring, ds: float, max_st
         t_sel = t_of[sel]
         lam = (la[sel], lb[sel], lc[sel])
         vals = {}
-        for key, fld in (("dT", dT), ("L", L), ("tx", TX), ("ty", TY)):
+        for key, fld in fields:
             vals[key] = sum(l * fld[v[0][t_sel], v[1][t_sel]] for l, v in zip(lam, verts))
         kmax = np.maximum(np.maximum(KK[verts[0][0][t_sel], verts[0][1][t_sel]],
                                      KK[verts[1][0][t_sel], verts[1][1][t_sel]]),
@@ -161,7 +170,7 @@ def bin_emitter(s: RaySamples, e: int, grid: Grid, ring: Ring, ds: float, max_st
         win = order[first]
         q = node[win]
         out_valid[q] = True
-        for k in ("dT", "L", "tx", "ty"):
+        for k, _ in fields:
             out[k][q] = allv[k][win]
         out_K[q] = allv["K"][win]
     return _finish(out_valid, out, out_K, grid, xe, ye, ds, c0)
@@ -177,11 +186,13 @@ def _finish(valid, vals, K, grid, xe, ye, ds, c0):
         tn = np.hypot(vals["tx"], vals["ty"])
         ux = np.where(valid, vals["tx"] / tn, 0.0)
         uy = np.where(valid, vals["ty"] / tn, 0.0)
-    return valid, T, A, ux, uy, np.where(valid, K, 0)
+    B = np.where(valid, vals["B"], 0.0) if "B" in vals else None
+    return valid, T, A, ux, uy, np.where(valid, K, 0), B
 
 
 def receivers_emitter(s: RaySamples, e: int, ring: Ring, c0: float = C0):
-    """Receiver tables of emitter e: (valid, T, A, K) for every receiver r (r = e invalid)."""
+    """Receiver tables of emitter e: (valid, T, A, K, B) for every receiver r (r = e invalid);
+    B is None without an absorption integral on the rays."""
     rows = _ray_block(s, e)
     N = ring.n
     pos = ring.positions()
@@ -193,6 +204,8 @@ def receivers_emitter(s: RaySamples, e: int, ring: Ring, c0: float = C0):
     Tm = np.where(ok, s.T[rows, np.where(ok, M, 0)], np.nan)
     Am = np.where(ok, s.A[rows, np.where(ok, M, 0)], np.nan)
     Km = np.where(ok, s.K[rows, np.where(ok, M, 0)], 0)
+    lossy = s.B is not None
+    Bm = np.where(ok, s.B[rows, np.where(ok, M, 0)], np.nan) if lossy else None
     dm = np.hypot(xm - xe, ym - ye)
     dTm = Tm - dm / c0
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -202,6 +215,7 @@ def receivers_emitter(s: RaySamples, e: int, ring: Ring, c0: float = C0):
     T = np.zeros(N)
     A = np.zeros(N)
     K = np.zeros(N, dtype=np.int64)
+    B = np.zeros(N) if lossy else None
     for r in range(N):
         if r == e:
             continue
@@ -216,14 +230,17 @@ def receivers_emitter(s: RaySamples, e: int, ring: Ring, c0: float = C0):
             dT = (1.0 - lam) * dTm[js] + lam * dTm[js + 1]
             w = int(np.argmin(dT))  # first minimum = lowest ray index on a tie
             L = (1.0 - lam[w]) * Lm[js[w]] + lam[w] * Lm[js[w] + 1]
-            best = (dT[w], L, max(Km[js[w]], Km[js[w] + 1]))
+            Bw = (1.0 - lam[w]) * Bm[js[w]] + lam[w] * Bm[js[w] + 1] if lossy else None
+            best = (dT[w], L, max(Km[js[w]], Km[js[w] + 1]), Bw)
         if best is not None:
             dist = math.hypot(pos[r, 0] - xe, pos[r, 1] - ye)
             valid[r] = True
             T[r] = best[0] + dist / c0
             A[r] = math.exp(best[1]) / math.sqrt(dist)
             K[r] = best[2]
-    return valid, T, A, K
+            if lossy:
+                B[r] = best[3]
+    return valid, T, A, K, B
 
 
 def tables(s: RaySamples, grid: Grid, ring: Ring, ds: float, max_steps: int,
@@ -238,5 +255,7 @@ def tables(s: RaySamples, grid: Grid, ring: Ring, ds: float, max_steps: int,
         rx.append(receivers_emitter(s, int(e), ring, c0))
     st = lambda k: np.stack([r[k] for r in rows])
     sr = lambda k: np.stack([r[k] for r in rx])
+    lossy = s.B is not None
     return Tables(valid=st(0), T=st(1), A=st(2), ux=st(3), uy=st(4), K=st(5),
-                  rx_valid=sr(0), rx_T=sr(1), rx_A=sr(2), rx_K=sr(3))
+                  rx_valid=sr(0), rx_T=sr(1), rx_A=sr(2), rx_K=sr(3),
+                  B=st(6) if lossy else None, rx_B=sr(4) if lossy else None)

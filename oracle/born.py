@@ -18,13 +18,19 @@ Readings:
     (2 k / c)(1 + u_e . u_r) for a lossless medium (the literal form with k (u_e - u_r) is
     available as isochron_sign = -1);
   * the leading minus sign makes dm a descent direction for g_res = g - data (Eq. residual);
-  * Domega is the spacing of the frequency list (omega itself for a single frequency).
+  * Domega is the spacing of the frequency list (omega itself for a single frequency);
+  * absorbing media (Section 2.2, Szabo's model): Upsilon_m = omega c k~ is complex, and
+    |kbar| |d|kbar|/domega| = 2 k (1 + u_e . u_r) dk/domega with the dispersive k and
+    dk/domega = 1/c + y tan(pi y/2) omega^(y-1) alpha0 (Section 3.4), so S is complex and the
+    direction takes the real part of S times the complex double sum.
 """
 from __future__ import annotations
 
 import math
 
 import numpy as np
+
+from . import lossy
 
 
 def forward_bruteforce(G, v):
@@ -52,10 +58,17 @@ def adjoint(G, w, R):
     return np.real(np.conj(w) * np.sum(np.conj(G) * Y, axis=0))
 
 
-def backproject_weight(omega, d_omega, c):
-    """S = (Domega / (2 pi)^3) (2 k / c) / Upsilon_m with k = omega / c, Upsilon_m = omega^2."""
-    k = omega / c
-    return d_omega / (2.0 * math.pi) ** 3 * (2.0 * k / c) / omega ** 2
+def backproject_weight(omega, d_omega, c, alpha0=None, y=None):
+    """S = (Domega / (2 pi)^3) (2 k dk/domega) / Upsilon_m: lossless (alpha0 None) k = omega/c,
+    dk/domega = 1/c, Upsilon_m = omega^2 (real); otherwise the dispersive k, the alpha0 term of
+    dk/domega and the complex Upsilon_m = omega c k~ (complex S)."""
+    if alpha0 is None:
+        k = omega / c
+        return d_omega / (2.0 * math.pi) ** 3 * (2.0 * k / c) / omega ** 2
+    k = lossy.wavenumber(omega, c, alpha0, y)
+    two_k_dk = 2.0 * k / c + 2.0 * k * (y * lossy.tan_py(y) * omega ** (y - 1.0) * alpha0)
+    return (d_omega / (2.0 * math.pi) ** 3 * two_k_dk / omega ** 2
+            / lossy.relative_potential(omega, c, alpha0, y))
 
 
 def backproject(R, H, Hx, Hy, S, isochron_sign=1.0):

@@ -3,7 +3,9 @@
   * Eq. 2D_greens: g = A exp(i [phi + pi/4]), A_geom = A_tab / sqrt(k0);
   * Eq. phase-discretised: phi = omega T - (pi/2) K (lossless: int k ds = omega T);
   * Eq. greens-time-reversed: reciprocal g_dagger = A^-1 exp(-i [phi + pi/4]);
-  * Section 3.4: the angular Jacobian factors |d gamma_e / d e| De (and likewise for r).
+  * Section 3.4: the angular Jacobian factors |d gamma_e / d e| De (and likewise for r);
+  * absorbing media (tables with an absorption integral B): A = A_abs A_geom with
+    A_abs = exp(-omega^y B) (Eq. amplitude-abs-discretised), in g and, inverted, in g_dagger.
 
 Readings:
   * the phase is reduced modulo 2 pi in FP64 before the complex exponential;
@@ -22,6 +24,7 @@ import math
 import numpy as np
 
 from .binning import Tables
+from .lossy import absorption_factor
 from .medium import C0
 
 
@@ -48,22 +51,29 @@ def angular_weights(tb: Tables) -> np.ndarray:
     return np.where(v, a, 0.0)
 
 
-def build_green(tb: Tables, omega: float, c0: float = C0):
-    """G, H, H_x, H_y, each (N, P_m) complex128."""
+def build_green(tb: Tables, omega: float, c0: float = C0, y=None):
+    """G, H, H_x, H_y, each (N, P_m) complex128. y: power-law exponent of lossy tables."""
     k0 = omega / c0
     ph = phase(tb.T, tb.K, omega)
     e = np.exp(1j * ph)
     with np.errstate(divide="ignore", invalid="ignore"):
         G = np.where(tb.valid, tb.A / math.sqrt(k0) * e, 0.0)
         gdag = np.where(tb.valid, math.sqrt(k0) / tb.A * np.conj(e), 0.0)
+        if tb.B is not None:
+            ab = absorption_factor(omega, tb.B, y)
+            G = G * ab
+            gdag = np.where(tb.valid, gdag / ab, 0.0)
     a = angular_weights(tb)
     H = a * gdag
     return G, H, H * tb.ux, H * tb.uy
 
 
-def direct_data(tb: Tables, omega: float, c0: float = C0) -> np.ndarray:
+def direct_data(tb: Tables, omega: float, c0: float = C0, y=None) -> np.ndarray:
     """Ray Green's function at the receivers g(omega, r, e) (Section 6.3.2), shape (N_e, N_r);
-    invalid pairs are zero."""
+    invalid pairs are zero. y: power-law exponent of lossy tables."""
     k0 = omega / c0
     ph = phase(tb.rx_T, tb.rx_K, omega)
-    return np.where(tb.rx_valid, tb.rx_A / math.sqrt(k0) * np.exp(1j * ph), 0.0)
+    g = np.where(tb.rx_valid, tb.rx_A / math.sqrt(k0) * np.exp(1j * ph), 0.0)
+    if tb.rx_B is not None:
+        g = g * absorption_factor(omega, tb.rx_B, y)
+    return g

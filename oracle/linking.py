@@ -23,7 +23,8 @@ Readings (where the paper is silent):
     |f| is the linked ray, valid if |f| <= accept (else the pair is invalid);
   * the rays are traced exactly as the fan's (oracle.trace.trace: Algorithm 1 with the
     paraxial system, Definition 1's last step), so T, A and K at the terminal sample follow
-    Eqs. phase-discretised and amplitude-geom-discretised.
+    Eqs. phase-discretised and amplitude-geom-discretised, and with an absorption map the
+    absorption integral B of Eq. amplitude-abs-discretised as well.
 """
 from __future__ import annotations
 
@@ -51,17 +52,20 @@ class Linked:
     gamma: np.ndarray     # launch angle of the linked ray
     miss: np.ndarray      # |beta - beta_r| of the linked ray (radians)
     rays: np.ndarray      # rays traced by the secant iteration
+    B: np.ndarray = None  # absorption integral at the receiver (absorption map given)
 
 
 def _exit(s, rows, psi_e):
-    """Exit angle from psi_e in [0, 2 pi), T, A, K at the terminal sample of each row."""
+    """Exit angle from psi_e in [0, 2 pi), T, A, K, B (or None) at the terminal sample of
+    each row."""
     M = s.M[rows]
     ok = s.valid[rows]
     m = np.where(ok, M, 0)
     x = s.x[rows, m]
     y = s.y[rows, m]
     beta = np.mod(np.arctan2(y, x) - psi_e, 2.0 * math.pi)
-    return (ok, np.where(ok, beta, np.nan), s.T[rows, m], s.A[rows, m], s.K[rows, m])
+    B = None if s.B is None else s.B[rows, m]
+    return (ok, np.where(ok, beta, np.nan), s.T[rows, m], s.A[rows, m], s.K[rows, m], B)
 
 
 def fan_brackets(s, e: int, ring: Ring, c0: float = C0):
@@ -72,7 +76,7 @@ def fan_brackets(s, e: int, ring: Ring, c0: float = C0):
     rows = rows[np.argsort(s.ray[rows])]
     N = ring.n
     psi_e = ring.angles()[e]
-    ok, beta, Tm, _, _ = _exit(s, rows, psi_e)
+    ok, beta, Tm, _, _, _ = _exit(s, rows, psi_e)
     xe, ye = ring.positions()[e]
     m = np.where(ok, s.M[rows], 0)
     dm = np.hypot(s.x[rows, m] - xe, s.y[rows, m] - ye)
@@ -95,11 +99,12 @@ def fan_brackets(s, e: int, ring: Ring, c0: float = C0):
 
 def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
                  max_steps: int, e: int, c0: float = C0, tol: float = TOL,
-                 accept: float = ACCEPT, max_iter: int = MAX_ITER, fan=None):
-    """Linked receiver tables of emitter e: (valid, T, A, K, gamma, miss, rays), each [N]."""
+                 accept: float = ACCEPT, max_iter: int = MAX_ITER, fan=None, alpha=None):
+    """Linked receiver tables of emitter e: (valid, T, A, K, gamma, miss, rays, B), each
+    [N]; B (absorption integral) is None without an absorption map alpha."""
     N = ring.n
     if fan is None:
-        fan = trace(ns, grid, ring, n_rays, ds, max_steps, emitters=[e], c0=c0)
+        fan = trace(ns, grid, ring, n_rays, ds, max_steps, emitters=[e], c0=c0, alpha=alpha)
     jsel, beta = fan_brackets(fan, e, ring, c0)
     gam_fan = launch_angles(ring, [e], n_rays)[0]
     psi_e = ring.angles()[e]
@@ -130,8 +135,8 @@ def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
         inside = np.isfinite(cand) & (cand > a) & (cand < b)
         cand = np.where(inside, cand, 0.5 * (lo[todo] + hi[todo]))
         s = trace(ns, grid, ring, n_rays, ds, max_steps, emitters=[e], c0=c0,
-                  angles=cand[None, :])
-        ok, bet, T, A, K = _exit(s, np.arange(todo.size), psi_e)
+                  angles=cand[None, :], alpha=alpha)
+        ok, bet, T, A, K, Bx = _exit(s, np.arange(todo.size), psi_e)
         for t, idx in enumerate(todo):
             r = act[idx]
             rays[r] += 1
@@ -142,7 +147,7 @@ def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
             if abs(f) < best_f[idx]:
                 best_f[idx] = abs(f)
                 best_g[idx] = cand[t]
-                best[r] = (T[t], A[t], K[t])
+                best[r] = (T[t], A[t], K[t], 0.0 if Bx is None else Bx[t])
             # keep the sign change inside the bracket
             if (f < 0) == (flo[idx] < 0):
                 lo[idx], flo[idx] = cand[t], f
@@ -154,6 +159,7 @@ def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
     Tout = np.zeros(N)
     Aout = np.zeros(N)
     Kout = np.zeros(N, dtype=np.int64)
+    Bout = None if alpha is None else np.zeros(N)
     gam = np.full(N, np.nan)
     miss = np.full(N, np.nan)
     for idx, r in enumerate(act):
@@ -161,8 +167,10 @@ def link_emitter(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float,
         gam[r] = best_g[idx]
         if best[r] is not None and best_f[idx] <= accept:
             valid[r] = True
-            Tout[r], Aout[r], Kout[r] = best[r]
-    return valid, Tout, Aout, Kout, gam, miss, rays
+            Tout[r], Aout[r], Kout[r] = best[r][:3]
+            if Bout is not None:
+                Bout[r] = best[r][3]
+    return valid, Tout, Aout, Kout, gam, miss, rays, Bout
 
 
 def link_receivers(ns, grid: Grid, ring: Ring, n_rays: int, ds: float, max_steps: int,
@@ -175,4 +183,4 @@ def link_receivers(ns, grid: Grid, ring: Ring, n_rays: int, ds: float, max_steps
            for e in emitters]
     st = lambda k: np.stack([o[k] for o in out])
     return Linked(valid=st(0), T=st(1), A=st(2), K=st(3), gamma=st(4), miss=st(5),
-                  rays=st(6))
+                  rays=st(6), B=None if out[0][7] is None else st(7))

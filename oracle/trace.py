@@ -29,7 +29,10 @@ Readings (where the paper is silent):
   * the travel time T = int n ds / c0 by the trapezoid rule on each (partial) step;
   * the last step: when the full step would reach |x| >= R, the step is redone with
     ds' = the distance along the current unit direction to the ring (exact in water);
-  * a ray that needs more than max_steps steps is invalid.
+  * a ray that needs more than max_steps steps is invalid;
+  * with an absorption map alpha0_s (Eq. amplitude-abs-discretised), B = int alpha0_s ds
+    along the ray by the trapezoid rule at the samples, alpha0_s from the same cubic
+    B-spline as the map (value only).
 """
 from __future__ import annotations
 
@@ -64,6 +67,7 @@ class RaySamples:
     dxy: np.ndarray = None
     kx: np.ndarray = None
     ky: np.ndarray = None
+    B: np.ndarray = None    # int alpha0 ds from the source (absorption map given), else None
 
 
 def launch_angles(ring: Ring, emitters, n_rays: int) -> np.ndarray:
@@ -131,11 +135,12 @@ def heun_step(ns, grid, x, y, kx, ky, dxx, dxy, dkx, dky, h):
 
 def trace(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float, max_steps: int,
           emitters=None, c0: float = C0, angles=None, keep_paraxial: bool = False,
-          stop_at_ring: bool = True) -> RaySamples:
+          stop_at_ring: bool = True, alpha=None) -> RaySamples:
     """Trace the fan of every listed transducer through the refractive-index map ns.
 
     angles: optional launch angles (n_emitters, n_rays_per) overriding the default fan.
     stop_at_ring=False runs exactly max_steps full steps (used by the convergence tests).
+    alpha: optional absorption map (ny, nx) whose line integral B is kept per sample.
     """
     if emitters is None:
         emitters = np.arange(ring.n)
@@ -158,6 +163,7 @@ def trace(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float, max_st
     TX = np.full((nr, S), np.nan)
     TY = np.full((nr, S), np.nan)
     NN = np.full((nr, S), np.nan)
+    BB = None if alpha is None else np.full((nr, S), np.nan)
     keep = {}
     if keep_paraxial:
         for key in ("dxx", "dxy", "dkx", "dky", "kx", "ky"):
@@ -175,6 +181,9 @@ def trace(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float, max_st
     dky = n0 * np.cos(gam)
     X[:, 0], Y[:, 0], T[:, 0], J[:, 0] = x, y, 0.0, 0.0
     TX[:, 0], TY[:, 0], NN[:, 0] = np.cos(gam), np.sin(gam), n0
+    if alpha is not None:
+        BB[:, 0] = 0.0
+        al_cur = bspline(alpha, grid, x, y)[0]
     if keep_paraxial:
         for key, val in (("dxx", dxx), ("dxy", dxy), ("dkx", dkx), ("dky", dky),
                          ("kx", kx), ("ky", ky)):
@@ -218,6 +227,11 @@ def trace(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float, max_st
         X[a, i + 1], Y[a, i + 1] = x[a], y[a]
         # trapezoid rule for T = int n ds / c0 (Eq. phase-discretised / omega)
         T[a, i + 1] = T[a, i] + h * (n_cur[a] + n_new) / (2.0 * c0)
+        if alpha is not None:
+            # trapezoid rule for B = int alpha0 ds (Eq. amplitude-abs-discretised / omega^y)
+            al_new = bspline(alpha, grid, x[a], y[a])[0]
+            BB[a, i + 1] = BB[a, i] + h * (al_cur[a] + al_new) / 2.0
+            al_cur[a] = al_new
         Jn = dxx[a] * (-ty) + dxy[a] * tx
         J[a, i + 1] = Jn
         # caustic count: sign changes of the Jacobian (Eq. phase-discretised)
@@ -245,4 +259,4 @@ def trace(ns: np.ndarray, grid: Grid, ring: Ring, n_rays: int, ds: float, max_st
         A = np.sqrt(NN[:, 1:2] / NN * J[:, 1:2] / np.abs(J)) / np.sqrt(8.0 * math.pi * s1[:, None])
     A[:, 0] = np.nan
     return RaySamples(x=X, y=Y, T=T, J=J, K=Kc, tx=TX, ty=TY, n=NN, A=A, M=M, valid=valid,
-                      emitter=em, ray=rj, **keep)
+                      emitter=em, ray=rj, B=BB, **keep)

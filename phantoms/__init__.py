@@ -167,12 +167,8 @@ def gaussian_inclusion(nx, ny, dx, x0, y0, seed=1, amp=45.0, sigma=8e-3,
     return c
 
 
-def breast_phantom(nx, ny, dx, x0, y0, seed=1, n_lesions=3, mask_radius=None) -> np.ndarray:
-    """Breast-like slice: water 1500 m/s; a fat ellipse at 1470 m/s (semi-axes U[60,80] x
-    U[45,65] mm, random rotation, centre within 5 mm); six glandular Gaussian blobs peaking
-    at 1520-1560 m/s (sigma U[5,12] mm) inside 0.7 of the semi-axes; the map then smoothed by
-    a Gaussian of sigma 2 mm; n_lesions disks of radius U[3,8] mm at 1560-1580 m/s with a
-    0.5 mm tanh edge, not overlapping. Water outside mask_radius if given."""
+def _breast(nx, ny, dx, x0, y0, seed, n_lesions, mask_radius):
+    """Sound speed (m/s) and absorption alpha0 (dB MHz^-y cm^-1) of the breast-like slice."""
     from scipy.ndimage import gaussian_filter
 
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -201,6 +197,9 @@ def breast_phantom(nx, ny, dx, x0, y0, seed=1, n_lesions=3, mask_radius=None) ->
                             * np.exp(-((U - bu) ** 2 + (V - bv) ** 2) / (2 * sig ** 2)))
     c = np.where(inside, tissue, C_WATER)
     c = gaussian_filter(c, sigma=2e-3 / dx, mode="nearest")
+    # absorption: fat 0.45, rising to 0.8 with the glandular blobs; water 0
+    a = np.where(inside, 0.45 + 0.35 * (tissue - 1470.0) / 90.0, 0.0)
+    a = gaussian_filter(a, sigma=2e-3 / dx, mode="nearest")
     placed = []
     tries = 0
     while len(placed) < n_lesions and tries < 10000:
@@ -215,9 +214,49 @@ def breast_phantom(nx, ny, dx, x0, y0, seed=1, n_lesions=3, mask_radius=None) ->
         placed.append((lu, lv, rad))
         s = 0.5 * (1.0 - np.tanh((np.hypot(U - lu, V - lv) - rad) / 0.5e-3))
         c = c * (1.0 - s) + speed * s
+        a = a * (1.0 - s) + 0.95 * s
     if mask_radius is not None:
-        c[X ** 2 + Y ** 2 > mask_radius ** 2] = C_WATER
-    return c
+        out = X ** 2 + Y ** 2 > mask_radius ** 2
+        c[out] = C_WATER
+        a[out] = 0.0
+    return c, a
+
+
+def breast_phantom(nx, ny, dx, x0, y0, seed=1, n_lesions=3, mask_radius=None) -> np.ndarray:
+    """Breast-like slice: water 1500 m/s; a fat ellipse at 1470 m/s (semi-axes U[60,80] x
+    U[45,65] mm, random rotation, centre within 5 mm); six glandular Gaussian blobs peaking
+    at 1520-1560 m/s (sigma U[5,12] mm) inside 0.7 of the semi-axes; the map then smoothed by
+    a Gaussian of sigma 2 mm; n_lesions disks of radius U[3,8] mm at 1560-1580 m/s with a
+    0.5 mm tanh edge, not overlapping. Water outside mask_radius if given."""
+    return _breast(nx, ny, dx, x0, y0, seed, n_lesions, mask_radius)[0]
+
+
+def breast_absorption(nx, ny, dx, x0, y0, seed=1, n_lesions=3, mask_radius=None) -> np.ndarray:
+    """Absorption coefficient alpha0 of the breast_phantom of the same arguments, in
+    dB MHz^-y cm^-1 (the paper's range 0-1, Section 6.1): 0 in water, 0.45 in fat rising to
+    0.8 with the glandular blobs (smoothed like the sound speed), 0.95 in the lesions."""
+    return _breast(nx, ny, dx, x0, y0, seed, n_lesions, mask_radius)[1]
+
+
+def gaussian_absorption(nx, ny, dx, x0, y0, seed=1, amp_db=1.0, sigma=8e-3,
+                        centre_radius=20e-3, mask_radius=None) -> np.ndarray:
+    """alpha0 (dB MHz^-y cm^-1) of amp_db exp(-r^2 / 2 sigma^2) centred on the inclusion that
+    gaussian_inclusion draws from the same seed; 0 outside mask_radius if given."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = centre_radius * math.sqrt(rng.uniform())
+    a = rng.uniform(0.0, 2.0 * math.pi)
+    xc, yc = r * math.cos(a), r * math.sin(a)
+    X, Y = node_coords(nx, ny, dx, x0, y0)
+    out = amp_db * np.exp(-((X - xc) ** 2 + (Y - yc) ** 2) / (2.0 * sigma ** 2))
+    if mask_radius is not None:
+        out[X ** 2 + Y ** 2 > mask_radius ** 2] = 0.0
+    return out
+
+
+def db_to_neper(alpha_db, y: float):
+    """Unit conversion of an absorption coefficient: dB MHz^-y cm^-1 to Np (rad/s)^-y m^-1
+    (amplitude decibels: 1 dB = ln(10)/20 Np)."""
+    return alpha_db * (math.log(10.0) / 20.0) * 100.0 * (2.0e6 * math.pi) ** (-y)
 
 
 def linear_gradient(nx, ny, dx, x0, y0, c_a=C_WATER, gx=500.0, gy=0.0) -> np.ndarray:
@@ -237,6 +276,23 @@ def phantom_for(w: Workload, seed: int | None = None) -> np.ndarray:
     if w.phantom == "water":
         return water(w.nx, w.ny)
     raise ValueError(w.phantom)
+
+
+def absorption_for(w: Workload, seed: int | None = None, y: float = 1.4) -> np.ndarray:
+    """alpha0 map (Np (rad/s)^-y m^-1) matching phantom_for(w, seed): the absorption of the
+    same breast-like slice, or a 1 dB MHz^-y cm^-1 peak on the Gaussian inclusion."""
+    seed = w.phantom_seed if seed is None else seed
+    if w.phantom == "gaussian":
+        a = gaussian_absorption(w.nx, w.ny, w.dx, w.x0, w.y0, seed=seed,
+                                mask_radius=w.mask_radius)
+    elif w.phantom == "breast":
+        a = breast_absorption(w.nx, w.ny, w.dx, w.x0, w.y0, seed=seed,
+                              n_lesions=w.n_lesions, mask_radius=w.mask_radius)
+    elif w.phantom == "water":
+        a = np.zeros((w.ny, w.nx))
+    else:
+        raise ValueError(w.phantom)
+    return db_to_neper(a, y)
 
 
 def complex_noise(shape, seed) -> np.ndarray:

@@ -62,7 +62,10 @@ def test_linear_fields_are_interpolated_exactly():
     s2.A = np.exp(f_L(s.x, s.y)) / np.sqrt(d)
     s2.tx = np.full_like(s.x, 0.6) + 0.0 * s.x
     s2.ty = np.full_like(s.x, 0.8)
-    valid, T, A, ux, uy, K = binning.bin_emitter(s2, e, st.grid, st.ring, st.ds, st.max_steps)
+    f_B = lambda x, y: 0.02 + 0.5 * x - 0.3 * y   # absorption integral (Np (rad/s)^y)
+    s2.B = f_B(s.x, s.y)
+    valid, T, A, ux, uy, K, B = binning.bin_emitter(s2, e, st.grid, st.ring, st.ds,
+                                                    st.max_steps)
     qx, qy = st.grid.mask_coords()
     dq = np.hypot(qx - xe, qy - ye)
     assert valid.sum() > 0.9 * valid.size
@@ -70,6 +73,8 @@ def test_linear_fields_are_interpolated_exactly():
     L = np.log(A[valid] * np.sqrt(dq[valid]))
     assert np.max(np.abs(L - f_L(qx, qy)[valid])) < 1e-12
     assert np.allclose(ux[valid], 0.6, atol=1e-14) and np.allclose(uy[valid], 0.8, atol=1e-14)
+    assert np.max(np.abs(B[valid] - f_B(qx, qy)[valid])) < 1e-15
+    assert np.all(B[~valid] == 0)
 
 
 def test_smallest_travel_time_wins_where_sheets_overlap():
