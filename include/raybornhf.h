@@ -10,7 +10,10 @@
  *   - ray Green's function: Eqs. 2D_greens, phase-discretised, amplitude-geom-discretised;
  *   - Born operator: Eqs. perturb1, derivative, scattering-potential;
  *   - Q=1 gradient: Eq. functional-gradient; Hessian-free direction: Eqs.
- *     sound_speed_update, sound_speed_update2; update m <- m + tau dm (Section 3.4).
+ *     sound_speed_update, sound_speed_update2; update m <- m + tau dm (Section 3.4);
+ *   - absorbing, dispersive media (Szabo's model, Section 2.2): Eqs.
+ *     szabo_dispersion_equation, wave-number, amplitude-abs-discretised, the complex
+ *     scattering potential and Section 3.4's d|kbar|/domega (rb_absorption, *_lossy).
  *
  * Conventions (every entry point):
  *   - Lengths in metres, times in seconds, angular frequencies in rad/s.
@@ -67,6 +70,18 @@ typedef enum { RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3, RB_F16X = 4 } rb_prec;
  * RB_RAY_BORN mode, the first-order Born term of the part of the model removed by the
  * smoothing window (m - m_s); RB_RAY_ONLY omits that term. */
 typedef enum { RB_RAY_BORN = 0, RB_RAY_ONLY = 1 } rb_mode;
+
+/* Absorbing, dispersive medium (Section 2.2, Szabo's model): the complex wavenumber is
+ * k~ = omega/c + alpha0 omega^y [tan(pi y/2) + i] (Eq. szabo_dispersion_equation), with the
+ * power-law absorption alpha = alpha0 omega^y and the real part k = omega/c + alpha0
+ * tan(pi y/2) omega^y = omega / c_p(omega) (Eq. wave-number). alpha0: DEVICE double [ny][nx]
+ * in Np (rad/s)^-y m^-1 (>= 0; 0 in water); y: exponent in (0, 2], at least 1e-3 from 1
+ * (soft tissue: 1 < y <= 1.5). The alpha0 map is a known property of the medium, not an
+ * unknown: the steps update c only. */
+typedef struct {
+    const double *alpha0;
+    double y;
+} rb_absorption;
 
 /* Ring of n point transducers of radius `radius` (Section 2.1); each emits and receives. */
 typedef struct {
@@ -191,6 +206,27 @@ rb_status rb_refractive_index(rb_ctx *ctx, const rb_grid *grid, const double *c,
 rb_status rb_trace_rays(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                         const rb_trace_params *tp, const float *n_s, const rb_tables *out);
 
+/* Maps of one frequency omega in an absorbing medium, float [ny][nx] each:
+ *   n_w = box_w(c0/c) + c0 tan(pi y/2) omega^(y-1) box_w(alpha0), the real wavenumber k of Eq.
+ *         wave-number in units of k0 = omega/c0 (the map the rays of omega follow: with
+ *         dispersion they differ between frequencies);
+ *   a_w = omega^y box_w(alpha0), the absorption alpha (Np/m) the rays integrate.
+ * box_w: the odd box window of rb_refractive_index, applied to both maps (the wavenumber map
+ * is linear in them). With alpha0 = 0, n_w equals rb_refractive_index's n_s bit for bit. */
+rb_status rb_lossy_maps(rb_ctx *ctx, const rb_grid *grid, const double *c,
+                        const rb_absorption *abs, double c0, double omega, int32_t w,
+                        float *n_w, float *a_w);
+
+/* rb_trace_rays through the map n_w of an absorbing medium: the same rays, binning and
+ * receivers, with the amplitude tables A and rx_A carrying the absorption along each ray,
+ * A = A_geom sqrt(k0) A_abs, A_abs = exp(-int a_w ds) (Eq. amplitude-abs-discretised;
+ * trapezoid rule at the ray samples on the cubic B-spline of a_w, value only). The tables then
+ * belong to the frequency of n_w and a_w (rb_lossy_maps); rb_build_green and rb_residual take
+ * them as they are. Receiver linking (rb_set_receiver_linking) applies as in rb_trace_rays. */
+rb_status rb_trace_rays_lossy(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                              const rb_trace_params *tp, const float *n_w, const float *a_w,
+                              const rb_tables *out);
+
 /* Diagnostic of the last rb_trace_rays / rb_frequency_step on this context: the number of
  * (transducer, mask node) pairs that the mesh walk of an unfolded fan could not place in a
  * triangle (reported as invalid table entries). Zero in normal operation. */
@@ -239,6 +275,16 @@ rb_status rb_residual(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
 rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
                          double omega, double d_omega, float *dm, int32_t accumulate);
 
+/* rb_backproject in an absorbing medium (operands from lossy tables): the weight becomes
+ * complex, S[q] = d_omega / (2 pi)^3 2 k dk/domega / Upsilon_m with the dispersive
+ * k = omega/c + alpha0 tan(pi y/2) omega^y, dk/domega = 1/c + y tan(pi y/2) omega^(y-1)
+ * alpha0 (Section 3.4) and Upsilon_m = omega c k~ (Eq. scattering-potential), at the node's
+ * c and alpha0; dm[q] = -Re{ S[q] sum_{e,r} R[e][r] [H_e H_r + H^x_e H^x_r + H^y_e H^y_r](q) }.
+ * alpha0_mask: double [n_mask] (alpha0 at the mask nodes); y as in rb_absorption. */
+rb_status rb_backproject_lossy(rb_ctx *ctx, const rb_green *gr, const float *R,
+                               const double *c_mask, const double *alpha0_mask, double y,
+                               double omega, double d_omega, float *dm, int32_t accumulate);
+
 /* rb_backproject without any allocation, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, hosts that forbid it): the same kernels
  * and result, with the partial sums and the rounded residual in a fixed 64 MiB device array
@@ -270,6 +316,22 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
                             int32_t n_omega, const double *omega, const double *d_omega,
                             const float *data, double tau, rb_mode mode, rb_prec prec,
                             double *residual_norm, rb_report *report);
+
+/* rb_frequency_step in an absorbing, dispersive medium (abs: alpha0 map and exponent y; the
+ * other arguments as in rb_frequency_step). Per frequency the rays are traced again on that
+ * frequency's map (rb_lossy_maps, rb_trace_rays_lossy), so the Green's functions carry its
+ * dispersion and A_abs; the Born term of the rough part uses w = Upsilon_m h^2 with the
+ * complex Upsilon_m = omega c k~ of the model's c and alpha0 at the node (the rough part
+ * m - m_s keeps m_s = (box_w(c0/c)/c0)^2), and the back-projection the complex weight of
+ * rb_backproject_lossy. With alpha0 = 0 the step computes the lossless step's quantities.
+ * rb_trace_lost_nodes / rb_trace_samples and the report's counters describe the last
+ * frequency's trace. */
+rb_status rb_frequency_step_lossy(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                                  const rb_trace_params *tp, double *c,
+                                  const rb_absorption *abs, int32_t smooth_w, int32_t n_omega,
+                                  const double *omega, const double *d_omega, const float *data,
+                                  double tau, rb_mode mode, rb_prec prec,
+                                  double *residual_norm, rb_report *report);
 
 /* Green's functions of a Gauss-Newton step: traced rays (the Hessian-based ray-Born method of
  * Section 6.3.2 b) or water's, computed analytically (App. B; the prototype Born method of

@@ -27,7 +27,8 @@ SYMBOLS = (
     "rb_stage_name", "rb_trace_lost_nodes", "rb_trace_samples", "rb_frequency_sweep",
     "rb_frequency_step_batch", "rb_step_bytes", "rb_set_sample_budget", "rb_autotune",
     "rb_set_tuning", "rb_get_tuning", "rb_set_receiver_linking", "rb_workspace_bytes",
-    "rb_reserve", "rb_backproject_noalloc", "rb_gauss_newton_step",
+    "rb_reserve", "rb_backproject_noalloc", "rb_gauss_newton_step", "rb_lossy_maps",
+    "rb_trace_rays_lossy", "rb_backproject_lossy", "rb_frequency_step_lossy",
 )
 RB_TILE_256x128, RB_TILE_128x128 = 0, 1
 GROUP_MAX = 16  # scans per rb_frequency_step_batch call
@@ -54,6 +55,10 @@ class _Tables(ctypes.Structure):
                 ("T", ctypes.c_void_p), ("A", ctypes.c_void_p), ("ux", ctypes.c_void_p),
                 ("uy", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("rx_T", ctypes.c_void_p),
                 ("rx_A", ctypes.c_void_p), ("rx_flags", ctypes.c_void_p)]
+
+
+class _Absorption(ctypes.Structure):
+    _fields_ = [("alpha0", ctypes.c_void_p), ("y", ctypes.c_double)]
 
 
 class _Green(ctypes.Structure):
@@ -160,6 +165,17 @@ def load(path: str = LIB_PATH):
                                ctypes.c_size_t),
         "rb_reserve": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                         ctypes.POINTER(TraceParams), ctypes.c_int], ctypes.c_int),
+        "rb_lossy_maps": ([P, ctypes.POINTER(Grid), P, ctypes.POINTER(_Absorption), D, D, I32,
+                           P, P], ctypes.c_int),
+        "rb_trace_rays_lossy": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                                 ctypes.POINTER(TraceParams), P, P, ctypes.POINTER(_Tables)],
+                                ctypes.c_int),
+        "rb_backproject_lossy": ([P, ctypes.POINTER(_Green), P, P, P, D, D, D, P, I32],
+                                 ctypes.c_int),
+        "rb_frequency_step_lossy": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
+                                     ctypes.POINTER(TraceParams), P, ctypes.POINTER(_Absorption),
+                                     I32, I32, ctypes.POINTER(D), ctypes.POINTER(D), P, D,
+                                     ctypes.c_int, ctypes.c_int, P, P], ctypes.c_int),
         "rb_gauss_newton_step": ([P, ctypes.POINTER(Grid), ctypes.POINTER(Ring),
                                   ctypes.POINTER(TraceParams), P, I32, I32, ctypes.POINTER(D),
                                   P, D, I32, ctypes.c_int, ctypes.c_int, P, P, P],
@@ -432,6 +448,30 @@ class Context:
                                                  _ptr(out)))
         return out
 
+    def lossy_maps(self, grid: Grid, c: torch.Tensor, alpha0: torch.Tensor, y: float,
+                   c0: float, omega: float, w: int):
+        """rb_lossy_maps: (n_w, a_w), float32 [ny][nx] each, of an absorbing medium at omega
+        (alpha0: float64 [ny][nx] in Np (rad/s)^-y m^-1)."""
+        _dev(c, torch.float64)
+        _dev(alpha0, torch.float64)
+        n_w = torch.empty(grid.ny, grid.nx, dtype=torch.float32, device=self.device)
+        a_w = torch.empty_like(n_w)
+        ab = _Absorption(_ptr(alpha0), float(y))
+        self._check(self.lib.rb_lossy_maps(self._h, ctypes.byref(grid), _ptr(c), ctypes.byref(ab),
+                                           c0, omega, w, _ptr(n_w), _ptr(a_w)))
+        return n_w, a_w
+
+    def trace_rays_lossy(self, grid: Grid, ring: Ring, tp: TraceParams, n_w: torch.Tensor,
+                         a_w: torch.Tensor) -> Tables:
+        _dev(n_w, torch.float32)
+        _dev(a_w, torch.float32)
+        tb = Tables.empty(ring.n, mask_count(grid), self.device)
+        s = tb.struct()
+        self._check(self.lib.rb_trace_rays_lossy(self._h, ctypes.byref(grid), ctypes.byref(ring),
+                                                 ctypes.byref(tp), _ptr(n_w), _ptr(a_w),
+                                                 ctypes.byref(s)))
+        return tb
+
     def trace_rays(self, grid: Grid, ring: Ring, tp: TraceParams, n_s: torch.Tensor) -> Tables:
         _dev(n_s, torch.float32)
         tb = Tables.empty(ring.n, mask_count(grid), self.device)
@@ -493,6 +533,21 @@ class Context:
                                             omega, d_omega, _ptr(dm), int(accumulate)))
         return dm
 
+    def backproject_lossy(self, gr: Green, R: torch.Tensor, c_mask: torch.Tensor,
+                          alpha0_mask: torch.Tensor, y: float, omega: float, d_omega: float,
+                          out: torch.Tensor | None = None,
+                          accumulate: bool = False) -> torch.Tensor:
+        _dev(R, torch.complex64)
+        _dev(c_mask, torch.float64)
+        _dev(alpha0_mask, torch.float64)
+        dm = out if out is not None else torch.empty(gr.n_mask, dtype=torch.float32,
+                                                     device=self.device)
+        g = gr.struct()
+        self._check(self.lib.rb_backproject_lossy(self._h, ctypes.byref(g), _ptr(R),
+                                                  _ptr(c_mask), _ptr(alpha0_mask), float(y),
+                                                  omega, d_omega, _ptr(dm), int(accumulate)))
+        return dm
+
     def backproject_noalloc(self, gr: Green, R: torch.Tensor, c_mask: torch.Tensor,
                             omega: float, d_omega: float, out: torch.Tensor,
                             accumulate: bool = False) -> torch.Tensor:
@@ -527,6 +582,30 @@ class Context:
             self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
             int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode), int(prec),
             _ptr(residual_norm), _ptr(report)))
+        return c
+
+    def frequency_step_lossy(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,
+                             alpha0: torch.Tensor, y: float, smooth_w: int, omegas, d_omegas,
+                             data: torch.Tensor, tau: float, mode: int = RB_RAY_BORN,
+                             residual_norm: torch.Tensor | None = None, prec: int = RB_F32,
+                             report: torch.Tensor | None = None):
+        """rb_frequency_step_lossy: frequency_step in an absorbing, dispersive medium
+        (alpha0: float64 [ny][nx], Np (rad/s)^-y m^-1; y: power-law exponent)."""
+        _dev(c, torch.float64)
+        _dev(alpha0, torch.float64)
+        _dev(data, torch.complex64)
+        if report is not None:
+            _dev(report, torch.uint8)
+            if report.numel() < REPORT_BYTES or report.data_ptr() % 8:
+                raise ValueError("report needs REPORT_BYTES bytes, 8-byte aligned")
+        k = len(omegas)
+        om = (ctypes.c_double * k)(*omegas)
+        dom = (ctypes.c_double * k)(*d_omegas)
+        ab = _Absorption(_ptr(alpha0), float(y))
+        self._check(self.lib.rb_frequency_step_lossy(
+            self._h, ctypes.byref(grid), ctypes.byref(ring), ctypes.byref(tp), _ptr(c),
+            ctypes.byref(ab), int(smooth_w), k, om, dom, _ptr(data), float(tau), int(mode),
+            int(prec), _ptr(residual_norm), _ptr(report)))
         return c
 
     def gauss_newton_step(self, grid: Grid, ring: Ring, tp: TraceParams, c: torch.Tensor,

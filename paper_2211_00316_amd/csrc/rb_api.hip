@@ -320,7 +320,7 @@ static size_t ws_need(const rb_grid *grid, const rb_ring *ring, const rb_trace_p
                       const GeomSizes &gs, size_t sample_budget, int n_cu) {
     const int N = ring->n, nm = (int)gs.nm;
     const size_t P = (size_t)grid->nx * grid->ny;
-    size_t ws = rb_align(P * sizeof(double));  // smoothing
+    size_t ws = 2 * rb_align(P * sizeof(double));  // smoothing (both maps when lossy)
     ws = std::max(ws, rb_trace_ws_bytes(grid, ring, tp, gs.nm, gs.tiles, sample_budget));
     ws = std::max(ws, rb_forward_ws_bytes(N, nm));
     ws = std::max(ws, rb_forward_lp_ws_bytes(N, nm, std::max(8, n_cu)));
@@ -544,11 +544,11 @@ static rb_status check_backproject(rb_ctx *ctx, const rb_green *gr, const float 
     return RB_OK;
 }
 
-// The back-projection's launches with their scratch (partial sums, the residual operand)
-// carved from `a`, which holds at least backproject_ws_bytes.
-static rb_status backproject_with(rb_ctx *ctx, rb_arena *a, const rb_green *gr, const float *R,
-                                  const double *c_mask, double omega, double d_omega, float *dm,
-                                  int32_t accumulate) {
+// The back-projection's contraction with its scratch (partial sums, the residual operand)
+// carved from `a`, which holds at least backproject_ws_bytes: complex partial sums
+// parts[2][mb][n_mask] of sum_{e,r} R[e][r] (H_e H_r + H^x_e H^x_r + H^y_e H^y_r).
+static rb_status backproject_parts(rb_ctx *ctx, rb_arena *a, const rb_green *gr, const float *R,
+                                   float **parts_out, int *mb_out) {
     const bool lp = gr->prec != RB_F32;
     int mb = lp ? rb_rowred_lp_mblocks(gr->n) : rb_rowred_mblocks(gr->n);
     const size_t nn = (size_t)gr->n * gr->n;
@@ -567,8 +567,39 @@ static rb_status backproject_with(rb_ctx *ctx, rb_arena *a, const rb_green *gr, 
         RB_TRY(rb_launch_rowred(ctx, gr->n, gr->n_mask, R, (const float *)gr->H, 3, 0, rsym,
                                 parts, &mb));
     }
+    *parts_out = parts;
+    *mb_out = mb;
+    return RB_OK;
+}
+
+static rb_status backproject_with(rb_ctx *ctx, rb_arena *a, const rb_green *gr, const float *R,
+                                  const double *c_mask, double omega, double d_omega, float *dm,
+                                  int32_t accumulate) {
+    int mb = 0;
+    float *parts = nullptr;
+    RB_TRY(backproject_parts(ctx, a, gr, R, &parts, &mb));
     return rb_launch_backproject_finish(ctx, gr->n_mask, mb, parts, c_mask, omega, d_omega, dm,
                                         accumulate);
+}
+
+static rb_status check_absorption(rb_ctx *ctx, const rb_absorption *abs);
+
+rb_status rb_backproject_lossy(rb_ctx *ctx, const rb_green *gr, const float *R,
+                               const double *c_mask, const double *alpha0_mask, double y,
+                               double omega, double d_omega, float *dm, int32_t accumulate) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_backproject(ctx, gr, R, c_mask, omega, d_omega, dm));
+    const rb_absorption abs{alpha0_mask, y};
+    RB_TRY(check_absorption(ctx, &abs));
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    const bool lp = gr->prec != RB_F32;
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, backproject_ws_bytes(gr->n, gr->n_mask, lp)));
+    int mb = 0;
+    float *parts = nullptr;
+    RB_TRY(backproject_parts(ctx, &ctx->ws, gr, R, &parts, &mb));
+    return rb_launch_backproject_finish_lossy(ctx, gr->n_mask, mb, parts, c_mask, alpha0_mask,
+                                              omega, d_omega, y, nullptr, dm, accumulate);
 }
 
 rb_status rb_backproject(rb_ctx *ctx, const rb_green *gr, const float *R, const double *c_mask,
@@ -626,6 +657,10 @@ struct StepBufs {
     unsigned int *rowmax = nullptr;  // per-row amplitude maxima of the binning (16-bit form)
     double *cq = nullptr, *dm = nullptr, *c_new = nullptr;
     float *parts = nullptr;
+    // absorbing media: row passes of c0/c and alpha0, the maps of the current frequency and
+    // alpha0 at the mask nodes
+    double *tn = nullptr, *ta = nullptr, *aq = nullptr;
+    float *n_w = nullptr, *a_w = nullptr;
 };
 
 static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
@@ -644,7 +679,8 @@ static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
            rb_align(NG * opb) + rb_align(hparts * 3 * NPp * opb) + 3 * rb_align(NN * 8) +
            rb_align(NNp * 4) + rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
            3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
-           rb_align(8) + 2 * rb_align((size_t)2 * N * 4);
+           rb_align(8) + 2 * rb_align((size_t)2 * N * 4) + 2 * rb_align(P * 8) +
+           2 * rb_align(P * 4) + rb_align((size_t)nm * 8);
 }
 
 static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring, rb_prec prec,
@@ -706,30 +742,60 @@ static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     b->dm = rb_carve<double>(a, nm);
     b->c_new = rb_carve<double>(a, nm);
     b->parts = rb_carve<float>(a, (size_t)2 * b->mb * nm);
+    b->tn = rb_carve<double>(a, P);
+    b->ta = rb_carve<double>(a, P);
+    b->n_w = rb_carve<float>(a, P);
+    b->a_w = rb_carve<float>(a, P);
+    b->aq = rb_carve<double>(a, nm);
     return RB_OK;
 }
 
-// a1: tracing map; a2-a3: rays and tables (independent of omega when lossless).
+// a1: tracing map; a2-a3: rays and tables (independent of omega when lossless). In an
+// absorbing medium (abs != NULL) the rays depend on omega: here only the row passes of both
+// maps, the sound-speed part n_s and alpha0 at the nodes; step_trace_lossy per frequency.
 static rb_status step_begin(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
                             const rb_trace_params *tp, double *c, int32_t smooth_w,
-                            double *residual_norm, StepBufs &b) {
-    RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, b.n_s));
-    RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos, b.rowmax));
+                            double *residual_norm, StepBufs &b,
+                            const rb_absorption *abs = nullptr) {
+    if (abs) {
+        RB_TRY(rb_launch_lossy_rows(ctx, grid, c, tp->c0, abs->alpha0, smooth_w, b.tn, b.ta,
+                                    b.n_s));
+        RB_TRY(rb_launch_gather_mask(ctx, abs->alpha0, b.aq));
+    } else {
+        RB_TRY(rb_launch_refractive_index(ctx, grid, c, tp->c0, smooth_w, b.n_s));
+        RB_TRY(rb_launch_trace(ctx, grid, ring, tp, b.n_s, &b.tb, b.rec, b.ringpos, b.rowmax));
+    }
     RB_TRY(rb_launch_gather_mask(ctx, c, b.cq));
     RB_TRY(rb_launch_zero_f64(ctx, b.dm, b.nm));
     if (residual_norm) RB_TRY(rb_launch_zero_f64(ctx, residual_norm, 1));
     return RB_OK;
 }
 
+// a1-a3 of one frequency in an absorbing medium: the maps n_w, a_w of omega (Eq.
+// wave-number in units of k0; alpha = alpha0 omega^y), then rays and tables with A_abs.
+static rb_status step_trace_lossy(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                                  const rb_trace_params *tp, int32_t smooth_w, double om,
+                                  const rb_absorption *abs, StepBufs &b) {
+    const double kd = tp->c0 * tan(0.5 * RB_PI * abs->y) * pow(om, abs->y - 1.0);
+    RB_TRY(rb_launch_lossy_map(ctx, grid, b.tn, b.ta, smooth_w, kd, pow(om, abs->y), b.n_w,
+                               b.a_w));
+    return rb_launch_trace(ctx, grid, ring, tp, b.n_w, &b.tb, b.rec, b.ringpos, b.rowmax, b.a_w);
+}
+
 // a4: Green's functions and back-projection operands. In ray_born mode G is stored as
-// G sqrt(v), v = omega^2 h^2 (m - m_s), so that a5 is the plain symmetric product; ray_only
-// needs no G.
+// G sqrt(v), v = Upsilon_m h^2 (m - m_s) (Upsilon_m = omega^2 lossless, omega c k~ in an
+// absorbing medium), so that a5 is the plain symmetric product; ray_only needs no G.
 static rb_status step_green(rb_ctx *ctx, const rb_grid *grid, const rb_trace_params *tp,
-                            double om, rb_mode mode, StepBufs &b) {
+                            double om, rb_mode mode, StepBufs &b,
+                            const rb_absorption *abs = nullptr) {
     const bool born_term = mode == RB_RAY_BORN;
     if (born_term) {
-        RB_TRY(rb_launch_rough_part(ctx, b.cq, b.n_s, tp->c0, om * om * grid->dx * grid->dx,
-                                    b.wv));
+        if (abs)
+            RB_TRY(rb_launch_rough_part_lossy(ctx, b.cq, b.aq, b.n_s, tp->c0, om, abs->y,
+                                              grid->dx * grid->dx, b.wv));
+        else
+            RB_TRY(rb_launch_rough_part(ctx, b.cq, b.n_s, tp->c0, om * om * grid->dx * grid->dx,
+                                        b.wv));
         // power-of-two scale that brings max |sqrt(v)| to [1, 2) (range of 16-bit types)
         RB_TRY(rb_launch_range_scale(ctx, b.wv, (size_t)b.nm, 1, b.svscale));
     }
@@ -752,8 +818,12 @@ static rb_status step_residual(rb_ctx *ctx, const rb_trace_params *tp, double om
 }
 
 // a8 tail: undo the operand scale and accumulate the direction over the set in FP64.
-static rb_status step_accumulate(rb_ctx *ctx, double om, double d_om, StepBufs &b) {
+static rb_status step_accumulate(rb_ctx *ctx, double om, double d_om, StepBufs &b,
+                                 const rb_absorption *abs = nullptr) {
     if (b.lp) RB_TRY(rb_launch_unscale(ctx, b.parts, (size_t)2 * b.mb * b.nm, b.rscale));
+    if (abs)
+        return rb_launch_backproject_finish_lossy(ctx, b.nm, b.mb, b.parts, b.cq, b.aq, om, d_om,
+                                                  abs->y, b.dm, nullptr, 0);
     return rb_launch_backproject_finish_acc(ctx, b.mb, b.parts, b.cq, om, d_om, b.dm);
 }
 
@@ -778,14 +848,16 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
                               const rb_trace_params *tp, double *c, int32_t smooth_w,
                               int32_t n_omega, const double *omega, const double *d_omega,
                               const float *data, double tau, rb_mode mode, rb_prec prec,
-                              double *residual_norm, int step_index) {
+                              double *residual_norm, int step_index,
+                              const rb_absorption *abs = nullptr) {
     StepBufs b;
     RB_TRY(step_carve(ctx, grid, ring, prec, &b));
-    RB_TRY(step_begin(ctx, grid, ring, tp, c, smooth_w, residual_norm, b));
+    RB_TRY(step_begin(ctx, grid, ring, tp, c, smooth_w, residual_norm, b, abs));
     for (int k = 0; k < n_omega; ++k) {
         const double om = omega[k];
         const bool born = mode == RB_RAY_BORN;
-        RB_TRY(step_green(ctx, grid, tp, om, mode, b));
+        if (abs) RB_TRY(step_trace_lossy(ctx, grid, ring, tp, smooth_w, om, abs, b));
+        RB_TRY(step_green(ctx, grid, tp, om, mode, b, abs));
         // a5: Born term of the rough part in the predicted data
         if (born) {
             if (b.lp)
@@ -804,25 +876,24 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
             RB_TRY(rb_launch_rowred(ctx, b.N, b.nm, b.R, (const float *)b.gr.H, 3, 0, b.rsym,
                                     b.parts, &mbo));
         }
-        RB_TRY(step_accumulate(ctx, om, d_omega[k], b));
+        RB_TRY(step_accumulate(ctx, om, d_omega[k], b, abs));
     }
     return step_end(ctx, c, tau, step_index, b);
 }
 
 
-rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
-                            const rb_trace_params *tp, double *c, int32_t smooth_w,
-                            int32_t n_omega, const double *omega, const double *d_omega,
-                            const float *data, double tau, rb_mode mode, rb_prec prec,
-                            double *residual_norm, rb_report *report) {
-    if (!ctx) return RB_EINVAL;
-    RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
-                           mode, prec));
+// The frequency step with its report handling (abs: absorbing medium or NULL).
+static rb_status frequency_step_with(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                                     const rb_trace_params *tp, double *c, int32_t smooth_w,
+                                     int32_t n_omega, const double *omega,
+                                     const double *d_omega, const float *data, double tau,
+                                     rb_mode mode, rb_prec prec, double *residual_norm,
+                                     rb_report *report, const rb_absorption *abs) {
     RB_HIP(ctx, hipSetDevice(ctx->device));
     if (!report) {
         ctx->deferred = false;
         return step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data,
-                            tau, mode, prec, residual_norm, 0);
+                            tau, mode, prec, residual_norm, 0, abs);
     }
     // asynchronous form: the checks stay on the device (as in a sweep of one step) and the
     // status goes to the caller's report
@@ -832,10 +903,81 @@ rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     if (st == RB_OK) st = rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_FAIL_STEP, 1, -1);
     if (st == RB_OK)
         st = step_enqueue(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
-                          mode, prec, residual_norm, 0);
+                          mode, prec, residual_norm, 0, abs);
     if (st == RB_OK) st = rb_launch_report(ctx, report);
     ctx->deferred = false;
     return st;
+}
+
+rb_status rb_frequency_step(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                            const rb_trace_params *tp, double *c, int32_t smooth_w,
+                            int32_t n_omega, const double *omega, const double *d_omega,
+                            const float *data, double tau, rb_mode mode, rb_prec prec,
+                            double *residual_norm, rb_report *report) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
+                           mode, prec));
+    return frequency_step_with(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data,
+                               tau, mode, prec, residual_norm, report, nullptr);
+}
+
+static rb_status check_absorption(rb_ctx *ctx, const rb_absorption *abs) {
+    if (!abs || !abs->alpha0)
+        return rb_fail(ctx, RB_EINVAL, "absorption needs a device alpha0 map");
+    if (!(abs->y > 0.0 && abs->y <= 2.0) || !(fabs(abs->y - 1.0) >= 1e-3))
+        return rb_fail(ctx, RB_EINVAL, "power-law exponent y = %g outside (0, 2] or within "
+                       "1e-3 of 1", abs->y);
+    return RB_OK;
+}
+
+rb_status rb_lossy_maps(rb_ctx *ctx, const rb_grid *grid, const double *c,
+                        const rb_absorption *abs, double c0, double omega, int32_t w,
+                        float *n_w, float *a_w) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(check_absorption(ctx, abs));
+    if (!c || !n_w || !a_w)
+        return rb_fail(ctx, RB_EINVAL, "c, n_w and a_w must be device pointers");
+    if (w < 1 || (w & 1) == 0) return rb_fail(ctx, RB_EINVAL, "window must be odd and >= 1");
+    if (!finite_pos(c0) || !finite_pos(omega))
+        return rb_fail(ctx, RB_EINVAL, "c0 and omega must be positive");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t P = (size_t)grid->nx * grid->ny;
+    ctx->ws.used = 0;
+    RB_TRY(rb_arena_reserve(ctx, &ctx->ws, 2 * rb_align(P * sizeof(double))));
+    double *tn = rb_carve<double>(&ctx->ws, P);
+    double *ta = rb_carve<double>(&ctx->ws, P);
+    RB_TRY(rb_launch_lossy_rows(ctx, grid, c, c0, abs->alpha0, w, tn, ta, nullptr));
+    const double kd = c0 * tan(0.5 * RB_PI * abs->y) * pow(omega, abs->y - 1.0);
+    return rb_launch_lossy_map(ctx, grid, tn, ta, w, kd, pow(omega, abs->y), n_w, a_w);
+}
+
+rb_status rb_trace_rays_lossy(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                              const rb_trace_params *tp, const float *n_w, const float *a_w,
+                              const rb_tables *out) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(rb_check_grid(ctx, grid));
+    RB_TRY(rb_check_ring(ctx, grid, ring));
+    RB_TRY(rb_check_trace(ctx, tp));
+    if (!n_w || !a_w) return rb_fail(ctx, RB_EINVAL, "n_w and a_w must be device pointers");
+    RB_HIP(ctx, hipSetDevice(ctx->device));
+    RB_TRY(rb_prepare_grid(ctx, grid));
+    RB_TRY(check_tables(ctx, out, ring->n, ctx->n_mask));
+    return rb_launch_trace(ctx, grid, ring, tp, n_w, out, nullptr, nullptr, nullptr, a_w);
+}
+
+rb_status rb_frequency_step_lossy(rb_ctx *ctx, const rb_grid *grid, const rb_ring *ring,
+                                  const rb_trace_params *tp, double *c,
+                                  const rb_absorption *abs, int32_t smooth_w, int32_t n_omega,
+                                  const double *omega, const double *d_omega, const float *data,
+                                  double tau, rb_mode mode, rb_prec prec,
+                                  double *residual_norm, rb_report *report) {
+    if (!ctx) return RB_EINVAL;
+    RB_TRY(check_step_args(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data, tau,
+                           mode, prec));
+    RB_TRY(check_absorption(ctx, abs));
+    return frequency_step_with(ctx, grid, ring, tp, c, smooth_w, n_omega, omega, d_omega, data,
+                               tau, mode, prec, residual_norm, report, abs);
 }
 
 // Gauss-Newton step ----------------------------------------------------------------------

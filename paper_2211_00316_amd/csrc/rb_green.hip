@@ -175,6 +175,70 @@ __global__ void rough_part(const double *__restrict__ cq, const float *__restric
     sv[q] = v >= 0.0 ? make_float2(r, 0.f) : make_float2(0.f, r);
 }
 
+// Absorbing media (Szabo's model, Section 2.2; Eq. scattering-potential): sv = sqrt(v) with
+// v = Upsilon_m h^2 delta complex, Upsilon_m = omega c k~ = omega^2 z, z = 1 + omega^(y-1)
+// c alpha0 (tan(pi y/2) + i) from the model's c and alpha0 at the node. The principal square
+// root in the cancellation-free form; with alpha0 = 0 it is the lossless root.
+__global__ void rough_part_lossy(const double *__restrict__ cq, const double *__restrict__ aq,
+                                 const float *__restrict__ n_s,
+                                 const int32_t *__restrict__ mask_index, int n_mask, double c0,
+                                 double w, double wy1, double tanpy, float2 *__restrict__ sv) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    const double c = cq[q];
+    const double ns = (double)n_s[mask_index[q]];
+    const double delta = 1.0 / (c * c) - ns * ns / (c0 * c0);
+    const double t = wy1 * c * aq[q];
+    const double vr = w * (1.0 + t * tanpy) * delta, vi = w * t * delta;
+    double sr = 0.0, si = 0.0;
+    if (vi == 0.0) {
+        const double r = sqrt(fabs(vr));
+        if (vr >= 0.0) sr = r;
+        else si = r;
+    } else {
+        const double m = sqrt(vr * vr + vi * vi);
+        if (vr >= 0.0) {
+            sr = sqrt(0.5 * (m + vr));
+            si = vi / (2.0 * sr);
+        } else {
+            const double u = sqrt(0.5 * (m - vr));
+            si = copysign(u, vi);
+            sr = fabs(vi) / (2.0 * u);
+        }
+    }
+    sv[q] = make_float2((float)sr, (float)si);
+}
+
+// Hessian-free direction of an absorbing medium (Eq. sound_speed_update2 with Section 3.4's
+// d|kbar|/domega): S = Domega / (2 pi)^3 (2k/c + 2k y tan(pi y/2) omega^(y-1) alpha0)
+// / (omega^2 z), k = omega/c + alpha0 tan(pi y/2) omega^y, z as in rough_part_lossy; S is
+// complex and dm = -Re{S (sr + i si)} over the complex double sum of the contraction.
+template <typename OutT>
+__global__ void backproject_finish_lossy_kernel(int n_mask, int mblocks,
+                                                const float *__restrict__ parts,
+                                                const double *__restrict__ c_mask,
+                                                const double *__restrict__ a_mask, double omega,
+                                                double base, double tanpy, double wy, double wy1,
+                                                double y, OutT *__restrict__ dm, int accumulate) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_mask) return;
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < mblocks; ++b) {
+        sr += (double)parts[(size_t)b * n_mask + q];
+        si += (double)parts[(size_t)(mblocks + b) * n_mask + q];
+    }
+    const double c = c_mask[q], a0 = a_mask[q];
+    const double k = omega / c + a0 * tanpy * wy;
+    const double s = base * (2.0 * k / c + 2.0 * k * (y * tanpy * wy1 * a0));  // base: Dw/(2pi)^3 w^2
+    const double t = wy1 * c * a0;
+    const double zr = 1.0 + t * tanpy, zi = t;
+    const double iz = 1.0 / (zr * zr + zi * zi);
+    const double Sr = s * zr * iz, Si = -s * zi * iz;
+    double v = -(Sr * sr - Si * si);
+    if (accumulate) v += (double)dm[q];
+    dm[q] = (OutT)v;
+}
+
 // m <- m + tau dm (FP64); the candidate c is kept aside until every value is finite.
 __global__ void update_kernel(const double *__restrict__ cq, const double *__restrict__ dm,
                               int n_mask, double tau, double *__restrict__ c_new, int *flag) {
@@ -300,6 +364,38 @@ rb_status rb_launch_backproject_finish_acc(rb_ctx *ctx, int mblocks, const float
     rb_prof_begin(ctx, ST_FINISH);
     hipLaunchKernelGGL(backproject_finish_kernel<double>, dim3(blocks(n)), dim3(256), 0,
                        ctx->stream, n, mblocks, parts, c_mask, omega, d_omega, dm_acc, 1);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_rough_part_lossy(rb_ctx *ctx, const double *cq, const double *aq,
+                                     const float *n_s, double c0, double omega, double y,
+                                     double h2, float *sv) {
+    int n = (int)ctx->n_mask;
+    hipLaunchKernelGGL(rough_part_lossy, dim3(blocks(n)), dim3(256), 0, ctx->stream, cq, aq, n_s,
+                       ctx->d_mask_index, n, c0, omega * omega * h2, pow(omega, y - 1.0),
+                       tan(0.5 * RB_PI * y), (float2 *)sv);
+    RB_CHECK_LAUNCH(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_backproject_finish_lossy(rb_ctx *ctx, int n_mask, int mblocks,
+                                             const float *parts, const double *c_mask,
+                                             const double *a_mask, double omega, double d_omega,
+                                             double y, double *dm_acc, float *dm,
+                                             int accumulate) {
+    const double base = d_omega / (RB_TWO_PI * RB_TWO_PI * RB_TWO_PI) / (omega * omega);
+    const double tanpy = tan(0.5 * RB_PI * y), wy = pow(omega, y), wy1 = pow(omega, y - 1.0);
+    rb_prof_begin(ctx, ST_FINISH);
+    if (dm_acc)
+        hipLaunchKernelGGL(backproject_finish_lossy_kernel<double>, dim3(blocks(n_mask)),
+                           dim3(256), 0, ctx->stream, n_mask, mblocks, parts, c_mask, a_mask,
+                           omega, base, tanpy, wy, wy1, y, dm_acc, 1);
+    else
+        hipLaunchKernelGGL(backproject_finish_lossy_kernel<float>, dim3(blocks(n_mask)),
+                           dim3(256), 0, ctx->stream, n_mask, mblocks, parts, c_mask, a_mask,
+                           omega, base, tanpy, wy, wy1, y, dm, accumulate);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;

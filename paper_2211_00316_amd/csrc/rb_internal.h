@@ -190,10 +190,32 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
 // flag bits of rb_tables stored as the bits of the fourth float. ring_out (nullable, double2
 // [n]) receives the transducer positions. rowmax (nullable, with rec; [n][2]) receives for
 // each transducer the bits of the largest A and of the largest 1/A over its valid records.
+// a_w (nullable, float [ny][nx]): absorption map alpha (Np/m) of an absorbing medium; its
+// line integral along each ray is subtracted from the log-amplitude (A = A_geom A_abs).
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
                           float4 *rec = nullptr, double2 *ring_out = nullptr,
-                          unsigned int *rowmax = nullptr);
+                          unsigned int *rowmax = nullptr, const float *a_w = nullptr);
+// Absorbing media (Szabo's model): row passes of the box window over c0/c (tn) and alpha0
+// (ta), double [ny][nx] each, and n_s = box(c0/c); then per frequency the traced map
+// n_w = box(c0/c) + kd box(alpha0) and the absorption map a_w = ky box(alpha0) (float),
+// kd = c0 tan(pi y/2) omega^(y-1), ky = omega^y.
+rb_status rb_launch_lossy_rows(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
+                               const double *alpha0, int w, double *tn, double *ta,
+                               float *n_s);
+rb_status rb_launch_lossy_map(rb_ctx *ctx, const rb_grid *g, const double *tn, const double *ta,
+                              int w, double kd, double ky, float *n_w, float *a_w);
+// Lossy scattering potential and back-projection weight (rb_green.hip): sv = sqrt(v) with
+// v = Upsilon_m h^2 (m - m_s), Upsilon_m = omega^2 [1 + omega^(y-1) c alpha0 (tan + i)];
+// the finish with the complex weight S (accumulating into dm_acc, or into/over float dm).
+rb_status rb_launch_rough_part_lossy(rb_ctx *ctx, const double *cq, const double *aq,
+                                     const float *n_s, double c0, double omega, double y,
+                                     double h2, float *sv);
+rb_status rb_launch_backproject_finish_lossy(rb_ctx *ctx, int n_mask, int mblocks,
+                                             const float *parts, const double *c_mask,
+                                             const double *a_mask, double omega, double d_omega,
+                                             double y, double *dm_acc, float *dm,
+                                             int accumulate);
 // gs (nullable): complex per-node factor on G; write_g = 0 leaves G unwritten.
 rb_status rb_launch_green(rb_ctx *ctx, const rb_tables *tb, double omega, double c0,
                           const rb_green *out, const float *gs, const float *gscale,

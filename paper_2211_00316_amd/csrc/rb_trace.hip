@@ -8,6 +8,11 @@
 // geometric amplitude of Eq. amplitude-geom-discretised referenced to the first sample by
 // Eq. attenuation_geom_reference. Section 4.5: the map is the uniform cubic B-spline of the
 // grid samples; ray-to-grid by linear interpolation over the triangulated ray samples.
+// Absorbing media (Section 2.2, Szabo's model; Eq. amplitude-abs-discretised): the rays of one
+// frequency follow its dispersive map, and the line integral of the absorption map
+// alpha = alpha0 omega^y (Np/m, the same cubic B-spline, value only) is taken by the
+// trapezoid rule beside the travel time and subtracted from the log-amplitude, so that the
+// interpolated amplitude is A_geom A_abs and nothing downstream changes.
 //
 // GPU design: one lane per ray, the 64 lanes of a wavefront are 64 neighbouring rays of one
 // transducer, so the per-step sample stores are coalesced ([emitter][step][ray] planes).
@@ -112,6 +117,45 @@ __device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, doub
     return Spline{s_v + 1.0f, s_gx * ih, s_gy * ih, s_xx * ih2, s_xy * ih2, s_yy * ih2};
 }
 
+// Absorption map alpha (Np/m) with MPAD replicated nodes on every side, as stored by pad_map
+// with offset 0; p == nullptr for a lossless medium.
+struct AbsMap {
+    const float *p;
+    int nx, ny, nxp;  // nxp = nx + 2 MPAD
+};
+
+// Value of the uniform cubic B-spline of the absorption map at node-index coordinates (u, v):
+// the sixteen control points around the cell weighted by the basis functions (cell index
+// clamped as in spline_eval, which with the padding equals clamping each control point).
+__device__ __forceinline__ float abs_value(const AbsMap &a, double u, double v) {
+    const double fu = floor(u), fv = floor(v);
+    const float tx = (float)(u - fu), ty = (float)(v - fv);
+    const int iu = min(max((int)fu, -2), a.nx), iv = min(max((int)fv, -2), a.ny);
+    float wx[4], wy[4];
+    {
+        const float s = 1.0f - tx, t2 = tx * tx, t3 = t2 * tx;
+        wx[0] = s * s * s * (1.0f / 6.0f);
+        wx[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+        wx[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * tx + 1.0f) * (1.0f / 6.0f);
+        wx[3] = t3 * (1.0f / 6.0f);
+    }
+    {
+        const float s = 1.0f - ty, t2 = ty * ty, t3 = t2 * ty;
+        wy[0] = s * s * s * (1.0f / 6.0f);
+        wy[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+        wy[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * ty + 1.0f) * (1.0f / 6.0f);
+        wy[3] = t3 * (1.0f / 6.0f);
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const f4u row = *reinterpret_cast<const f4u *>(
+            a.p + (size_t)(iv - 1 + b + MPAD) * a.nxp + (iu - 1 + MPAD));
+        acc = fmaf(wy[b], wx[0] * row.x + wx[1] * row.y + wx[2] * row.z + wx[3] * row.w, acc);
+    }
+    return acc;
+}
+
 // Ray state; the position is in node-index units (u, v) = ((x - x0) / dx, (y - y0) / dx).
 // What a ray integrates over its whole length is FP64: position, wave vector and the
 // paraxial dx (FP32 rounding of the direction, repeated every step, moves the far end of
@@ -213,12 +257,12 @@ struct RayEnd {
 // ray j of chunk transducer el go to sb; otherwise only the terminal state goes to *end.
 // Returns the index of the last sample, -1 if the ray did not reach the ring within
 // max_steps.
-template <bool STORE>
-__device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, double R,
-                                          double psi, double2 xy, double cg, double sg,
-                                          int n_rays, int max_steps, double ds, double c0,
-                                          int el, int j, const SampleBufs &sb, int *flag,
-                                          RayEnd *end) {
+template <bool STORE, bool ABS>
+__device__ __forceinline__ int trace_core(const SplineMap &m, const AbsMap &am, const GridP &g,
+                                          double R, double psi, double2 xy, double cg,
+                                          double sg, int n_rays, int max_steps, double ds,
+                                          double c0, int el, int j, const SampleBufs &sb,
+                                          int *flag, RayEnd *end) {
     const int S = max_steps + 1;
     const double ue = (xy.x - g.x0) * g.idx, ve = (xy.y - g.y0) * g.idx;
     const double uc = -g.x0 * g.idx, vc = -g.y0 * g.idx;  // ring centre
@@ -236,6 +280,9 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, do
     r.dkx = (float)(-(double)n_cur * sg);
     r.dky = (float)((double)n_cur * cg);
     double T = 0.0;
+    double Babs = 0.0;  // int alpha ds from the source (absorbing media)
+    float a_cur = 0.0f;
+    if constexpr (ABS) a_cur = abs_value(am, r.u, r.v);
 
     size_t o = (size_t)el * S * n_rays + j;
     if constexpr (STORE) {
@@ -273,6 +320,11 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, do
         sc = spline_eval(m, r.u, r.v, pc);
         float n_new = sc.v;
         T += h * 0.5 * ic0 * ((double)n_cur + (double)n_new);
+        if constexpr (ABS) {
+            const float a_new = abs_value(am, r.u, r.v);
+            Babs += h * 0.5 * ((double)a_cur + (double)a_new);
+            a_cur = a_new;
+        }
         const float kxf = (float)r.kx, kyf = (float)r.ky;
         float ikn = rsqrtf(kxf * kxf + kyf * kyf);
         float tx = kxf * ikn, ty = kyf * ikn;
@@ -286,6 +338,7 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, do
         // L = ln A + ln(d)/2 = lnc1 + ln(d / (n |J|)) / 2
         if (i == 0) lnc1 = 0.5f * __logf(nJ * __builtin_amdgcn_rcpf(8.0f * (float)RB_PI * df));
         float L = lnc1 + 0.5f * __logf(df * __builtin_amdgcn_rcpf(nJ));
+        if constexpr (ABS) L -= (float)Babs;  // ln A_abs (Eq. amplitude-abs-discretised)
         float dT = (float)(T - d * ic0);
         ++i;
         o += n_rays;
@@ -332,7 +385,9 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const GridP &g, do
 
 // Fan ray j of transducer e0 + el (Section 4.4: launch angle gamma = psi + pi + delta,
 // |delta| < pi / 2), samples to sb.
-__device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, double R,
+template <bool ABS>
+__device__ __forceinline__ int trace_ray(const SplineMap &m, const AbsMap &am, const GridP &g,
+                                         double R,
                                          double psi0, int N, int n_rays, int max_steps,
                                          double ds, double c0, int e0, int el, int j,
                                          const SampleBufs &sb, int *flag) {
@@ -343,8 +398,8 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
     sincospi(((double)j + 0.5 - 0.5 * (double)n_rays) / (double)n_rays, &sd, &cd);
     const double cp = xy.x / R, sp = xy.y / R;
     const double cg = -(cp * cd - sp * sd), sg = -(sp * cd + cp * sd);
-    return trace_core<true>(m, g, R, psi, xy, cg, sg, n_rays, max_steps, ds, c0, el, j, sb,
-                            flag, nullptr);
+    return trace_core<true, ABS>(m, am, g, R, psi, xy, cg, sg, n_rays, max_steps, ds, c0, el,
+                                 j, sb, flag, nullptr);
 }
 
 // One lane per ray; a wavefront holds 64 neighbouring rays of one transducer, so the
@@ -353,7 +408,9 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const GridP &g, dou
 // from the fan's middle (rank r: groups mid, mid - 1, mid + 1, ...), over all transducers:
 // the longest run first and the shortest fill the end of the launch. Also counts the
 // samples written (one atomic per wavefront; the workgroup is a whole number of them).
-__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double R, double psi0,
+template <bool ABS>
+__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, AbsMap am, GridP g, double R,
+                                                    double psi0,
                                                     int N, int n_rays, int max_steps, double ds,
                                                     double c0, int e0, int E, SampleBufs sb,
                                                     int *flag, unsigned long long *n_samples) {
@@ -366,7 +423,8 @@ __global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double
         const int grp = (rank & 1) ? mid - 1 - (rank >> 1) : mid + (rank >> 1);
         const int j = grp * 64 + (threadIdx.x & 63);
         if (j < n_rays)
-            M = trace_ray(m, g, R, psi0, N, n_rays, max_steps, ds, c0, e0, el, j, sb, flag);
+            M = trace_ray<ABS>(m, am, g, R, psi0, N, n_rays, max_steps, ds, c0, e0, el, j, sb,
+                               flag);
     }
     int cnt = M >= 0 ? M + 1 : 0;
 #pragma unroll
@@ -374,14 +432,15 @@ __global__ void __launch_bounds__(256) trace_kernel(SplineMap m, GridP g, double
     if ((threadIdx.x & 63) == 0 && cnt > 0) atomicAdd(n_samples, (unsigned long long)cnt);
 }
 
-// Spline map of n - 1 (exact in FP32 for n in [1/2, 2]) with MPAD replicated nodes on every
-// side.
-__global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float *__restrict__ out) {
+// Map minus `off` (the index map stores n - 1, exact in FP32 for n in [1/2, 2]; the absorption
+// map off = 0) with MPAD replicated nodes on every side.
+__global__ void pad_map(const float *__restrict__ ns, int nx, int ny, float off,
+                        float *__restrict__ out) {
     const int nxp = nx + 2 * MPAD;
     int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
     if (i >= nxp) return;
     int si = min(max(i - MPAD, 0), nx - 1), sj = min(max(j - MPAD, 0), ny - 1);
-    out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si] - 1.0f;
+    out[(size_t)j * nxp + i] = ns[(size_t)sj * nx + si] - off;
 }
 
 // Monomial coefficients of the uniform cubic B-spline on cell (iu, iv) = (ci - 2, cj - 2),
@@ -1167,7 +1226,8 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
 // tol or after max_iter rays; the traced ray closest to its receiver gives the receiver
 // tables if |f| <= accept, else the pair is invalid. Pairs without a bracket keep the
 // receiver kernel's invalid entry.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) link_kernel(SplineMap m, GridP g, double R, double psi0,
+template <bool ABS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) link_kernel(SplineMap m, AbsMap am, GridP g, double R, double psi0,
                                                    int N, int n_rays, int max_steps, double ds,
                                                    double c0, int e0, int E, SampleBufs sb,
                                                    const int32_t *__restrict__ rx_j,
@@ -1196,8 +1256,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) l
         double sgm, cgm;
         sincos(cand, &sgm, &cgm);
         RayEnd end;
-        if (trace_core<false>(m, g, R, psi, xy, cgm, sgm, n_rays, max_steps, ds, c0, el, 0, sb,
-                              nullptr, &end) < 0)
+        if (trace_core<false, ABS>(m, am, g, R, psi, xy, cgm, sgm, n_rays, max_steps, ds, c0, el,
+                                   0, sb, nullptr, &end) < 0)
             break;  // the ray did not reach the ring: the pair ends here
         const double f = end.beta - br;
         if (fabs(f) < best_f) {
@@ -1253,6 +1313,38 @@ __global__ void box_cols(const double *__restrict__ tmp, int nx, int ny, int w,
         acc += tmp[(size_t)k * nx + i];
     }
     out[(size_t)j * nx + i] = (float)(acc / w);
+}
+
+// Row pass of the box window over a plain map (the absorption alpha0), FP64 sums.
+__global__ void box_rows_plain(const double *__restrict__ f, int nx, int ny, int w,
+                               double *__restrict__ tmp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    int h = w / 2;
+    double acc = 0.0;
+    for (int s = -h; s <= h; ++s) acc += f[(size_t)j * nx + min(max(i + s, 0), nx - 1)];
+    tmp[(size_t)j * nx + i] = acc / w;
+}
+
+// Column pass of both maps and the maps of one frequency (Section 2.2, Eq. wave-number):
+// n_w = box(c0/c) + kd box(alpha0) with kd = c0 tan(pi y/2) omega^(y-1) (the wavenumber in
+// units of k0), a_w = ky box(alpha0) with ky = omega^y (the absorption in Np/m). With
+// alpha0 = 0 the index is box(c0/c) to the bit.
+__global__ void box_cols_lossy(const double *__restrict__ tn, const double *__restrict__ ta,
+                               int nx, int ny, int w, double kd, double ky,
+                               float *__restrict__ n_w, float *__restrict__ a_w) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= nx) return;
+    int h = w / 2;
+    double an = 0.0, aa = 0.0;
+    for (int s = -h; s <= h; ++s) {
+        const size_t o = (size_t)min(max(j + s, 0), ny - 1) * nx + i;
+        an += tn[o];
+        aa += ta[o];
+    }
+    const double al = aa / w;
+    n_w[(size_t)j * nx + i] = (float)(an / w + kd * al);
+    a_w[(size_t)j * nx + i] = (float)(ky * al);
 }
 
 __global__ void ring_positions(double R, double psi0, int N, double2 *pos) {
@@ -1317,6 +1409,36 @@ rb_status rb_launch_refractive_index(rb_ctx *ctx, const rb_grid *g, const double
     return RB_OK;
 }
 
+// Absorbing media: the row passes of both maps (kept for the maps of every frequency of a
+// step) and the sound-speed part n_s = box(c0/c) (skipped for n_s == nullptr).
+rb_status rb_launch_lossy_rows(rb_ctx *ctx, const rb_grid *g, const double *c, double c0,
+                               const double *alpha0, int w, double *tn, double *ta,
+                               float *n_s) {
+    dim3 blk(256), grd((g->nx + 255) / 256, g->ny);
+    rb_prof_begin(ctx, ST_SMOOTH);
+    hipLaunchKernelGGL(box_rows, grd, blk, 0, ctx->stream, c, c0, g->nx, g->ny, w, tn);
+    RB_CHECK_LAUNCH(ctx);
+    if (n_s) {
+        hipLaunchKernelGGL(box_cols, grd, blk, 0, ctx->stream, tn, g->nx, g->ny, w, n_s);
+        RB_CHECK_LAUNCH(ctx);
+    }
+    hipLaunchKernelGGL(box_rows_plain, grd, blk, 0, ctx->stream, alpha0, g->nx, g->ny, w, ta);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
+rb_status rb_launch_lossy_map(rb_ctx *ctx, const rb_grid *g, const double *tn, const double *ta,
+                              int w, double kd, double ky, float *n_w, float *a_w) {
+    dim3 blk(256), grd((g->nx + 255) / 256, g->ny);
+    rb_prof_begin(ctx, ST_SMOOTH);
+    hipLaunchKernelGGL(box_cols_lossy, grd, blk, 0, ctx->stream, tn, ta, g->nx, g->ny, w, kd, ky,
+                       n_w, a_w);
+    RB_CHECK_LAUNCH(ctx);
+    rb_prof_end(ctx);
+    return RB_OK;
+}
+
 // Emitters per tracer launch so that the ray samples of one chunk fit the budget.
 static int trace_chunk(size_t budget, const rb_ring *r, const rb_trace_params *tp,
                        int64_t n_mask) {
@@ -1348,7 +1470,7 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)C * tiles * sizeof(int2)) +
            rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
            rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
-           rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
+           2 * rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
            rb_align((size_t)(g->nx + 3) * (g->ny + 3) * 4 * sizeof(float4)) +
            rb_align((size_t)C * r->n * sizeof(int32_t)) +
            rb_align((size_t)C * tiles * LOCATE_WAVES * 2 * sizeof(float));
@@ -1361,7 +1483,8 @@ size_t rb_trace_ws_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_para
 
 rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                           const rb_trace_params *tp, const float *n_s, const rb_tables *out,
-                          float4 *rec, double2 *ring_out, unsigned int *rowmax) {
+                          float4 *rec, double2 *ring_out, unsigned int *rowmax,
+                          const float *a_w) {
     const int N = r->n, nr = tp->n_rays, S = tp->max_steps + 1;
     const int n_mask = (int)ctx->n_mask;
     const int C = trace_chunk(ctx->sample_budget, r, tp, n_mask);
@@ -1398,6 +1521,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     uint8_t *marks = rb_carve<uint8_t>(&ctx->ws, (size_t)C * mtiles + 4);  // whole words zeroed
     const int nxp = g->nx + 2 * MPAD, nyp = g->ny + 2 * MPAD;
     float *padded = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
+    float *apad = rb_carve<float>(&ctx->ws, (size_t)nxp * nyp);
+    const AbsMap amap{a_w ? apad : nullptr, g->nx, g->ny, nxp};
     int32_t *rx_j = rb_carve<int32_t>(&ctx->ws, (size_t)C * N);
     float4 *coef = rb_carve<float4>(&ctx->ws, (size_t)(g->nx + 3) * (g->ny + 3) * 4);
     SplineMap smap{coef, g->nx, g->ny, g->nx + 3, (float)(1.0 / g->dx)};
@@ -1413,8 +1538,13 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     RB_CHECK_LAUNCH(ctx);
     if (rows) RB_TRY(rb_launch_fill_i32(ctx, reinterpret_cast<int32_t *>(rowmax), 2 * N, 0));
     hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, n_s,
-                       g->nx, g->ny, padded);
+                       g->nx, g->ny, 1.0f, padded);
     RB_CHECK_LAUNCH(ctx);
+    if (a_w) {
+        hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, a_w,
+                           g->nx, g->ny, 0.0f, apad);
+        RB_CHECK_LAUNCH(ctx);
+    }
     hipLaunchKernelGGL(spline_coef, dim3((g->nx + 3 + 255) / 256, g->ny + 3), dim3(256), 0,
                        ctx->stream, padded, g->nx, g->ny, coef);
     RB_CHECK_LAUNCH(ctx);
@@ -1429,9 +1559,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         RB_CHECK_LAUNCH(ctx);
         rb_prof_begin(ctx, ST_TRACE);
         const int waves = E * ((nr + 63) / 64);
-        hipLaunchKernelGGL(trace_kernel, dim3((waves + 3) / 4), dim3(256), 0, ctx->stream,
-                           smap, gp, r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0,
-                           e0, E, sb, ctx->d_flag, nsamp);
+        hipLaunchKernelGGL(a_w ? trace_kernel<true> : trace_kernel<false>,
+                           dim3((waves + 3) / 4), dim3(256), 0, ctx->stream, smap, amap, gp,
+                           r->radius, r->psi0, N, nr, tp->max_steps, tp->ds, tp->c0, e0, E, sb,
+                           ctx->d_flag, nsamp);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // folded fans: tiles near inverted triangles
@@ -1494,8 +1625,9 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         RB_CHECK_LAUNCH(ctx);
         if (ctx->link_iter > 0) {
             const long lanes = (long)E * N;
-            hipLaunchKernelGGL(link_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0,
-                               ctx->stream, smap, gp, r->radius, r->psi0, N, nr, tp->max_steps,
+            hipLaunchKernelGGL(a_w ? link_kernel<true> : link_kernel<false>,
+                               dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0,
+                               ctx->stream, smap, amap, gp, r->radius, r->psi0, N, nr, tp->max_steps,
                                tp->ds, tp->c0, e0, E, sb, rx_j, ctx->link_iter, ctx->link_tol,
                                RB_LINK_ACCEPT, *out);
             RB_CHECK_LAUNCH(ctx);

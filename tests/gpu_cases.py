@@ -20,23 +20,26 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
+_PARAMS = {
+    # N, R, dx, n_rays, seed, amplitude (m/s), sigma of the inclusion
+    "small": (32, 0.02, 0.4e-3, 180, 11, 45.0, 4e-3),
+    "ragged": (37, 0.021, 0.37e-3, 101, 12, -30.0, 3e-3),
+    # a strong slow lens: rays through it cross (caustics), the fans fold
+    "folded": (32, 0.02, 0.4e-3, 180, 14, -300.0, 3e-3),
+}
+
+
 @functools.lru_cache(maxsize=None)
 def case(name):
     """(StepSetup, c map) of a named parity case."""
-    if name == "small":
-        N, R, dx, nr, seed, amp, sig = 32, 0.02, 0.4e-3, 180, 11, 45.0, 4e-3
-    elif name == "ragged":
-        N, R, dx, nr, seed, amp, sig = 37, 0.021, 0.37e-3, 101, 12, -30.0, 3e-3
-    elif name == "folded":
-        # a strong slow lens: rays through it cross (caustics), the fans fold
-        N, R, dx, nr, seed, amp, sig = 32, 0.02, 0.4e-3, 180, 14, -300.0, 3e-3
-    elif name == "ring64":
+    if name == "ring64":
         w = ph.SMALL
         grid = Grid(w.nx, w.ny, w.dx, w.x0, w.y0, w.mask_radius)
         st = StepSetup(grid, Ring(w.n_trans, w.radius), w.n_rays, w.ds, w.max_steps())
         return st, ph.phantom_for(w)
-    else:
+    if name not in _PARAMS:
         raise KeyError(name)
+    N, R, dx, nr, seed, amp, sig = _PARAMS[name]
     nx = int(math.ceil(2 * (R + 2e-3) / dx)) + 1
     x0 = -(nx - 1) * dx / 2
     grid = Grid(nx, nx, dx, x0, x0, 0.9 * R)
@@ -44,6 +47,20 @@ def case(name):
     c = ph.gaussian_inclusion(nx, nx, dx, x0, x0, seed=seed, amp=amp, sigma=sig,
                               centre_radius=0.3 * R, mask_radius=0.9 * R)
     return st, c
+
+
+@functools.lru_cache(maxsize=None)
+def absorption_case(name, y=1.4):
+    """alpha0 (Np (rad/s)^-y m^-1) of a named parity case: a 1 dB MHz^-y cm^-1 peak on the
+    case's inclusion (ring64: the absorption of its workload's phantom)."""
+    if name == "ring64":
+        return ph.absorption_for(ph.SMALL, y=y)
+    N, R, dx, nr, seed, amp, sig = _PARAMS[name]
+    st, _ = case(name)
+    g = st.grid
+    a = ph.gaussian_absorption(g.nx, g.ny, g.dx, g.x0, g.y0, seed=seed, amp_db=1.0, sigma=sig,
+                               centre_radius=0.3 * R, mask_radius=0.9 * R)
+    return ph.db_to_neper(a, y)
 
 
 def oracle_tables_of(st, ns, emitters=None):
