@@ -56,9 +56,11 @@ STAGE_KERNELS = {
 }
 
 
-def synthesize_data(ctx, w, grid, ring, tp, c_true, freq_idx):
+def synthesize_data(ctx, w, grid, ring, tp, c_true, freq_idx, alpha0=None, y=1.4):
     """Measured data of the listed frequencies, made on the GPU by the library itself:
-    ray-Born prediction of the phantom (window of that frequency) plus 1 % noise."""
+    ray-Born prediction of the phantom (window of that frequency) plus 1 % noise. alpha0
+    (float64 [ny][nx], Np (rad/s)^-y m^-1): the absorbing, dispersive phantom (rays of each
+    frequency on its map, A_abs, complex scattering potential)."""
     import numpy as np
     import torch
 
@@ -70,15 +72,25 @@ def synthesize_data(ctx, w, grid, ring, tp, c_true, freq_idx):
     out = torch.empty(len(freq_idx), N, N, dtype=torch.complex64, device="cuda:0")
     zero = torch.zeros(N, N, dtype=torch.complex64, device="cuda:0")
     mask = _mask_index(w)
+    a_t = None if alpha0 is None else torch.as_tensor(alpha0, device="cuda:0")
     for s, k in enumerate(freq_idx):
         om = 2 * math.pi * w.freqs[k]
         ns = ctx.refractive_index(grid, c_t, 1500.0, w.smooth_window(k))
-        tb = ctx.trace_rays(grid, ring, tp, ns)
+        if a_t is None:
+            tb = ctx.trace_rays(grid, ring, tp, ns)
+        else:
+            n_w, a_w = ctx.lossy_maps(grid, c_t, a_t, y, 1500.0, om, w.smooth_window(k))
+            tb = ctx.trace_rays_lossy(grid, ring, tp, n_w, a_w)
+            del n_w, a_w
         gr = ctx.build_green(tb, om, 1500.0)
         cm = c_t.reshape(-1)[mask]
         delta = (1.0 / cm ** 2 - (ns.reshape(-1)[mask].double() / 1500.0) ** 2).float()
         wv = torch.full((mask.numel(),), om * om * w.dx * w.dx, dtype=torch.complex64,
                         device="cuda:0")
+        if a_t is not None:
+            # scattering potential omega c k~ = omega^2 [1 + omega^(y-1) c alpha0 (tan + i)]
+            t = om ** (y - 1.0) * cm * a_t.reshape(-1)[mask]
+            wv = wv * (1.0 + t * math.tan(0.5 * math.pi * y) + 1j * t).to(torch.complex64)
         d = ctx.born_forward(gr, wv, delta)
         clean = ctx.residual(tb, om, 1500.0, zero, d)     # g_ray + Born term - 0
         keep = (clean != 0)
@@ -205,8 +217,10 @@ def start_model(w, start, c_true):
     return torch.full((w.ny, w.nx), 1500.0, dtype=torch.float64, device="cuda:0")
 
 
-def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start):
-    """Time `steps` frequency steps of one form from c_start (after `warmup`)."""
+def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start, alpha0=None,
+             y=1.4):
+    """Time `steps` frequency steps of one form from c_start (after `warmup`); alpha0 (device
+    float64 map): the lossy, dispersive step (rb_frequency_step_lossy)."""
     import torch
 
     from paper_2211_00316_amd import _lib
@@ -217,6 +231,10 @@ def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start):
 
     def one_step(k):
         om = 2 * math.pi * w.freqs[k]
+        if alpha0 is not None:
+            ctx.frequency_step_lossy(grid, ring, tp, c, alpha0, y, w.smooth_window(k), [om],
+                                     [d_om or om], data[k], w.tau, residual_norm=rn, prec=prec)
+            return
         ctx.frequency_step(grid, ring, tp, c, w.smooth_window(k), [om], [d_om or om],
                            data[k], w.tau, residual_norm=rn, prec=prec)
 
@@ -488,6 +506,8 @@ def main():
     ap.add_argument("--no-gn", action="store_true",
                     help="skip the Gauss-Newton (Hessian-based) and prototype Born steps")
     ap.add_argument("--gn-inner", type=int, default=12, help="CG iterations of a Gauss-Newton step")
+    ap.add_argument("--no-lossy", action="store_true",
+                    help="skip the absorbing, dispersive (Szabo) form of the same steps")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests of the bounded serving leg of the default run (0 skips it)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 form")
@@ -656,6 +676,9 @@ def main():
             "stages_ms_per_step": {k: round(v[0] / n_late, 3) for k, v in stl.items()}}
     if not args.no_gn:
         line.update(gauss_newton_legs(ctx, w, grid, ring, tp, data, prec_code, args, c_start))
+    if not args.no_lossy:
+        line["lossy_form"] = lossy_leg(ctx, w, grid, ring, tp, c_true, prec_code, args, c_start,
+                                       ms_eager)
     del data
     ctx.close()
     torch.cuda.synchronize()
@@ -672,6 +695,55 @@ def main():
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
+
+
+def lossy_leg(ctx, w, grid, ring, tp, c_true, prec, args, c_start, ms_lossless):
+    """The same steps in the absorbing, dispersive medium (Szabo's model, y = 1.4, the
+    phantom's alpha0 map of 0-1 dB MHz^-y cm^-1): data synthesised in that medium, one
+    rb_frequency_step_lossy per frequency (rays traced on that frequency's map), and one step
+    of a set of two frequencies (two traces) beside the lossless step of the same set."""
+    import torch
+
+    import phantoms as ph
+
+    y = 1.4
+    alpha0 = ph.absorption_for(w, y=y)
+    n_total = args.warmup + args.steps
+    print("[bench] lossy data", file=sys.stderr, flush=True)
+    data = synthesize_data(ctx, w, grid, ring, tp, c_true, list(range(n_total)), alpha0, y)
+    a_t = torch.as_tensor(alpha0, device="cuda:0")
+    ms, st, _ = run_form(ctx, w, grid, ring, tp, data, prec, args.steps, args.warmup,
+                         "lossy", c_start, alpha0=a_t, y=y)
+    k0 = args.warmup
+    oms = [2 * math.pi * w.freqs[k0], 2 * math.pi * w.freqs[k0 + 1]]
+    d_om = oms[1] - oms[0]
+    d2 = data[k0:k0 + 2].contiguous()
+    win = w.smooth_window(k0)
+
+    def timed(fn, reps=2):
+        c = c_start.clone()
+        fn(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.copy_(c_start)
+            fn(c)
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t0) / reps
+
+    ms2 = timed(lambda c: ctx.frequency_step_lossy(grid, ring, tp, c, a_t, y, win, oms,
+                                                   [d_om, d_om], d2, w.tau, prec=prec))
+    ms2l = timed(lambda c: ctx.frequency_step(grid, ring, tp, c, win, oms, [d_om, d_om], d2,
+                                              w.tau, prec=prec))
+    print(f"[bench] lossy step {ms:.1f} ms; set of two: {ms2:.1f} ms (lossless {ms2l:.1f})",
+          file=sys.stderr, flush=True)
+    del data
+    return {"ms_per_step": round(ms, 2), "value": round(1000.0 / ms, 4),
+            "medium": "Szabo power law y = 1.4, alpha0 0-1 dB MHz^-y cm^-1 (phantom's map)",
+            "cost_vs_lossless": round(ms / ms_lossless, 3),
+            "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in st.items()},
+            "two_frequency_set": {"lossy_ms": round(ms2, 2), "lossless_ms": round(ms2l, 2),
+                                  "traces": "one per frequency (lossy), one per set (lossless)"}}
 
 
 def gauss_newton_legs(ctx, w, grid, ring, tp, data, prec, args, c_start):
