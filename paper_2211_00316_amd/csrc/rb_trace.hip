@@ -576,16 +576,19 @@ __device__ __forceinline__ float ray_atan2(float y, float x) {
     return y < 0.f ? -a : a;
 }
 
-__device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
-                                             const float lam[3], int K, double d, double c0,
-                                             const TableOut &to, size_t out, float &A) {
-    const float4 f0 = sb.fld[vb[0]], f1 = sb.fld[vb[1]], f2 = sb.fld[vb[2]];
+// REC: compact records (to.rec); otherwise the tables of the C ABI, whose T needs the FP64
+// distance d (df: the same distance in FP32, for the amplitude).
+template <bool REC>
+__device__ __forceinline__ float write_entry_f(const float4 f0, const float4 f1, const float4 f2,
+                                               const float lam[3], int K, float df, double d,
+                                               double c0, const TableOut &to, size_t out,
+                                               float &A) {
     const float dT = tri_dT(lam[0], lam[1], lam[2], f0.x, f1.x, f2.x);
     const float L = tri_dT(lam[0], lam[1], lam[2], f0.y, f1.y, f2.y);
     const float tx = tri_dT(lam[0], lam[1], lam[2], f0.z, f1.z, f2.z);
     const float ty = tri_dT(lam[0], lam[1], lam[2], f0.w, f1.w, f2.w);
-    A = __expf(L) * rsqrtf((float)d);
-    if (to.rec) {
+    A = __expf(L) * rsqrtf(df);
+    if constexpr (REC) {
         to.rec[out] = make_float4(dT, A, ray_atan2(ty, tx), __int_as_float(0x80 | (K & 3)));
         return dT;
     }
@@ -599,8 +602,18 @@ __device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t 
     return dT;
 }
 
+template <bool REC>
+__device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
+                                             const float lam[3], int K, float df, double d,
+                                             double c0, const TableOut &to, size_t out,
+                                             float &A) {
+    return write_entry_f<REC>(sb.fld[vb[0]], sb.fld[vb[1]], sb.fld[vb[2]], lam, K, df, d, c0, to,
+                              out, A);
+}
+
+template <bool REC>
 __device__ __forceinline__ void write_invalid(const TableOut &to, size_t out) {
-    if (to.rec) {
+    if constexpr (REC) {
         to.rec[out] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
@@ -623,6 +636,29 @@ constexpr int LTX = RB_WALK_TX, LTY = RB_WALK_TY;  // node tile of one locate wo
 constexpr int LOCATE_WAVES = LTX * LTY / 64;
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
+// The two triangles of quad (j, i) with corners p00 (ray j, step i), p10 (ray j + 1, step i),
+// p01 (ray j, step i + 1), p11: half 0 = (p00, p10, p11), half 1 = (p00, p11, p01). Returns
+// the half that holds (pu, pv) with its barycentric coordinates, or -1.
+__device__ __forceinline__ int quad_test(float2 p00, float2 p10, float2 p01, float2 p11,
+                                         float pu, float pv, float lam[3]) {
+    float la, lb, lc;
+    if (barycentric(p00.x, p00.y, p10.x, p10.y, p11.x, p11.y, pu, pv, la, lb, lc) &&
+        la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
+        lam[0] = la;
+        lam[1] = lb;
+        lam[2] = lc;
+        return 0;
+    }
+    if (barycentric(p00.x, p00.y, p11.x, p11.y, p01.x, p01.y, pu, pv, la, lb, lc) &&
+        la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
+        lam[0] = la;
+        lam[1] = lb;
+        lam[2] = lc;
+        return 1;
+    }
+    return -1;
+}
+
 __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
                                           size_t ebase, int n_rays, float pu, float pv, int &j,
                                           int &i, size_t vb[3], float lam[3], int &half,
@@ -639,27 +675,12 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
         const f4u q1 = *reinterpret_cast<const f4u *>(sb.pos + b01);
         const float2 p00 = make_float2(q0.x, q0.y), p10 = make_float2(q0.z, q0.w);
         const float2 p01 = make_float2(q1.x, q1.y), p11 = make_float2(q1.z, q1.w);
-        float la, lb, lc;
-        if (barycentric(p00.x, p00.y, p10.x, p10.y, p11.x, p11.y, pu, pv, la, lb, lc) &&
-            la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
+        const int h = quad_test(p00, p10, p01, p11, pu, pv, lam);
+        if (h >= 0) {
             vb[0] = b00;
-            vb[1] = b00 + 1;
-            vb[2] = b01 + 1;
-            lam[0] = la;
-            lam[1] = lb;
-            lam[2] = lc;
-            half = 0;
-            return true;
-        }
-        if (barycentric(p00.x, p00.y, p11.x, p11.y, p01.x, p01.y, pu, pv, la, lb, lc) &&
-            la >= -RB_BARY_EPS && lb >= -RB_BARY_EPS && lc >= -RB_BARY_EPS) {
-            vb[0] = b00;
-            vb[1] = b01 + 1;
-            vb[2] = b01;
-            lam[0] = la;
-            lam[1] = lb;
-            lam[2] = lc;
-            half = 1;
+            vb[1] = h == 0 ? b00 + 1 : b01 + 1;
+            vb[2] = h == 0 ? b01 + 1 : b01;
+            half = h;
             return true;
         }
         // step across the quad edge the point lies farthest outside of
@@ -712,9 +733,9 @@ __device__ __forceinline__ float guess_atan2(float y, float x) {
 
 // Fan ray and step of the straight ray from the transducer (angle psi on the ring, psi_pi =
 // psi + pi in FP32) to the node at offset (ddx, ddy), distance d; ids = 1 / ds. A guess only.
-__device__ __forceinline__ void straight_guess(double ddx, double ddy, double d, float psi_pi,
-                                               double ids, int n_rays, int S, int &j, int &i) {
-    float rel = guess_atan2((float)ddy, (float)ddx) - psi_pi;
+__device__ __forceinline__ void straight_guess(float ddx, float ddy, float d, float psi_pi,
+                                               float ids, int n_rays, int S, int &j, int &i) {
+    float rel = guess_atan2(ddy, ddx) - psi_pi;
     rel -= (float)RB_TWO_PI * floorf((rel + (float)RB_PI) * (float)(1.0 / RB_TWO_PI));
     j = (int)floorf((rel + 0.5f * (float)RB_PI) * (float)n_rays * (float)(1.0 / RB_PI) - 0.5f);
     j = min(max(j, 0), n_rays - 2);
@@ -744,7 +765,7 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
         double ddx = g.x0 + cu * g.dx - xy.x, ddy = g.y0 + cv * g.dx - xy.y;
         double d = sqrt(ddx * ddx + ddy * ddy);
         int j, i, jw, iw;
-        straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, jw, iw);
+        straight_guess((float)ddx, (float)ddy, (float)d, psi_pi, (float)ids, n_rays, S, jw, iw);
         j = jw;
         i = iw;
         size_t vb[3];
@@ -772,9 +793,10 @@ __device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int el, i
     return K;
 }
 
-// One (transducer, mask node) of the walk: writes its table entry (and, in a folded fan, its
-// seed key); returns the amplitude written (0 for an invalid entry or a node left to the
-// rasterisation).
+// One (transducer, grid node) of the walk: for a mask node (q >= 0) writes its table entry
+// (and, in a folded fan, its seed key); returns the amplitude written (0 for an invalid entry,
+// a node outside the mask or a node left to the rasterisation).
+template <bool REC>
 __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, int S, int el,
                                              int e0, const GridP &g, double ds, double c0,
                                              int n_mask, int ii, int jj, int q, bool fold, int t,
@@ -785,45 +807,60 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
                                              uint8_t *__restrict__ marks, int mtx, int mtiles,
                                              int *lost, double psi0, float dpsi, double ids) {
     const int e = e0 + el;
-    const size_t out = (size_t)e * n_mask + q;
-    const size_t kq = (size_t)el * n_mask + q;
     const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;  // the walk's guess only
     const double2 xy = sb.ring[e];
-    double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
-    double ddx = px - xy.x, ddy = py - xy.y;
-    double d = sqrt_newton(ddx * ddx + ddy * ddy);
+    // Distance from the transducer. Records: FP32 (it decides validity, the walk's start and
+    // A = exp(L) / sqrt(d); the reader rebuilds T from its own FP64 distance). ABI tables:
+    // FP64, for T = dT + d / c0.
+    float ddx, ddy, df;
+    double d = 0.0;
+    if constexpr (REC) {
+        ddx = fmaf((float)ii, (float)g.dx, (float)(g.x0 - xy.x));
+        ddy = fmaf((float)jj, (float)g.dx, (float)(g.y0 - xy.y));
+        df = __builtin_amdgcn_sqrtf(fmaf(ddx, ddx, ddy * ddy));
+    } else {
+        const double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
+        const double dx64 = px - xy.x, dy64 = py - xy.y;
+        d = sqrt_newton(dx64 * dx64 + dy64 * dy64);
+        ddx = (float)dx64;
+        ddy = (float)dy64;
+        df = (float)d;
+    }
+    int j, i;
+    straight_guess(ddx, ddy, df, psi_pi, (float)ids, n_rays, S, j, i);
+    const int2 o = off[(size_t)el * ntiles + t];
+    j = min(max(j + o.x, 0), n_rays - 2);
+    i = min(max(i + o.y, 1), S - 2);
+    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
+    const size_t ebase = (size_t)el * S * n_rays;
+    if (q < 0) return 0.f;  // outside the mask
+    const size_t out = (size_t)e * n_mask + q;
+    const size_t kq = (size_t)el * n_mask + q;
     const size_t mq = (size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT);
-    // a node near a fold (marked tile) is left to the rasterisation, which offers it every
-    // triangle that touches its tile
-    if (d < 2.0 * ds || (fold && marks[mq])) {
-        write_invalid(to, out);
+    if (df < (float)(2.0 * ds) || (fold && marks[mq])) {
+        write_invalid<REC>(to, out);
         if (fold) {
             keys[kq] = ~0ull;
             changed[kq] = 0;
         }
         return 0.f;
     }
-    int j, i;
-    straight_guess(ddx, ddy, d, psi_pi, ids, n_rays, S, j, i);
-    const int2 o = off[(size_t)el * ntiles + t];
-    j = min(max(j + o.x, 0), n_rays - 2);
-    i = min(max(i + o.y, 1), S - 2);
     size_t vb[3];
     float lam[3];
     int half;
-    if (mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays, n_rays, (float)ii,
-                  (float)jj, j, i, vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
+    if (mesh_walk(sb, Mrow, ebase, n_rays, (float)ii, (float)jj, j, i, vb, lam, half,
+                  fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
         // no ray of an unfolded fan has K > 0
         const int K = fold ? tri_K(sb, n_rays, el, j, i, half, vb) : 0;
         float A;
-        const float dT = write_entry(sb, vb, lam, K, d, c0, to, out, A);
+        const float dT = write_entry<REC>(sb, vb, lam, K, df, d, c0, to, out, A);
         if (fold) {
             keys[kq] = tri_key(dT, (uint32_t)(((size_t)j * S + i) * 2 + half));
             changed[kq] = 0;
         }
         return A;
     }
-    write_invalid(to, out);
+    write_invalid<REC>(to, out);
     if (fold) {  // left to the rasterisation
         keys[kq] = ~0ull;
         changed[kq] = 0;
@@ -832,6 +869,18 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
         atomicAdd(lost, 1);
     }
     return 0.f;
+}
+
+// Largest value over the 64 lanes of a wave (non-negative inputs), returned in every lane:
+// row reductions by DPP lane swaps, then the row results broadcast across rows (GFX9 DPP).
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
@@ -843,6 +892,7 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
 // sequence is cut into groups of LOCATE_GROUP_ROWS tile rows and group g goes to XCD g mod 8,
 // so neighbouring tiles share their ray samples through one L2 while every XCD still gets an
 // even mix of the disk-shaped mask. The launch is padded to a multiple of 8 groups.
+template <bool REC>
 __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
@@ -853,7 +903,8 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
                                                      uint8_t *__restrict__ changed,
                                                      uint8_t *__restrict__ marks, int mtx,
                                                      int mtiles, int *lost, float dpsi,
-                                                     double ids) {
+                                                     double ids, float cxn, float cyn,
+                                                     float r2n) {
     const int ntiles = tiles_x * tiles_y;
     const int G = LOCATE_GROUP_ROWS * tiles_x;
     const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
@@ -865,20 +916,19 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
     const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
     float A = 0.f;
-    if (ii < g.nx && jj < g.ny) {
+    // nodes clearly outside the mask disc (node units; the margin leaves the decision on the
+    // circle to qmap) issue nothing
+    const float ru = (float)ii - cxn, rv = (float)jj - cyn;
+    if (ii < g.nx && jj < g.ny && ru * ru + rv * rv <= r2n) {
         const int q = qmap[(size_t)jj * g.nx + ii];
-        if (q >= 0)
-            A = locate_node(sb, n_rays, S, el, e0, g, ds, c0, n_mask, ii, jj, q, fold, t, ntiles,
-                            off, to, keys, changed, marks, mtx, mtiles, lost, psi0, dpsi, ids);
+        A = locate_node<REC>(sb, n_rays, S, el, e0, g, ds, c0, n_mask, ii, jj, q, fold, t,
+                             ntiles, off, to, keys, changed, marks, mtx, mtiles, lost, psi0,
+                             dpsi, ids);
     }
-    if (to.tmax) {
+    if (REC && to.tmax) {
         // each wave's largest A and 1/A (0 where no record was written); no barrier, so a
         // wave whose walks end early leaves at once
-        float m0 = A, m1 = A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f;
-        for (int o = 32; o > 0; o >>= 1) {
-            m0 = fmaxf(m0, __shfl_xor(m0, o));
-            m1 = fmaxf(m1, __shfl_xor(m1, o));
-        }
+        const float m0 = wave_max(A), m1 = wave_max(A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f);
         if ((threadIdx.x & 63) == 0) {
             const size_t o = 2 * ((size_t)item * LOCATE_WAVES + (threadIdx.x >> 6));
             to.tmax[o] = m0;
@@ -1040,7 +1090,8 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double d = sqrt_newton((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
-        write_invalid(to, out);
+        if (to.rec) write_invalid<true>(to, out);
+        else write_invalid<false>(to, out);
         return;
     }
     uint32_t tri = (uint32_t)(key & 0xffffffffu);
@@ -1065,7 +1116,8 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     float lam[3] = {la, lb, lc};
     const int K = tri_K(sb, n_rays, el, j, i, half, vb);
     float A;
-    write_entry(sb, vb, lam, K, d, c0, to, out, A);
+    if (to.rec) write_entry<true>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
+    else write_entry<false>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
     if (to.rowmax && A > 0.f) {
         atomicMax(to.rowmax + 2 * e, __float_as_uint(A));
         atomicMax(to.rowmax + 2 * e + 1, __float_as_uint(1.0f / A));
@@ -1585,12 +1637,15 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         const long G = (long)LOCATE_GROUP_ROWS * ctx->tiles_x;
         const long groups = ((long)E * ntiles + G - 1) / G;
         const long nblk = (groups + 7) / 8 * 8 * G;
-        hipLaunchKernelGGL(locate_kernel, dim3((unsigned)nblk), dim3(LTX * LTY), 0, ctx->stream,
+        hipLaunchKernelGGL(rec ? locate_kernel<true> : locate_kernel<false>, dim3((unsigned)nblk),
+                           dim3(LTX * LTY), 0, ctx->stream,
                            sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
                            toff, to, keys, changed, marks, mtx, mtiles, lost,
-                           (float)(RB_TWO_PI / N), 1.0 / tp->ds);
+                           (float)(RB_TWO_PI / N), 1.0 / tp->ds, (float)(-g->x0 / g->dx),
+                           (float)(-g->y0 / g->dx),
+                           (float)((g->mask_radius / g->dx + 2.0) * (g->mask_radius / g->dx + 2.0)));
         RB_CHECK_LAUNCH(ctx);
         if (rows) {
             hipLaunchKernelGGL(tile_max_fold, dim3(E), dim3(256), 0, ctx->stream, tmax, ntiles,
