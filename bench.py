@@ -218,9 +218,10 @@ def start_model(w, start, c_true):
 
 
 def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start, alpha0=None,
-             y=1.4):
-    """Time `steps` frequency steps of one form from c_start (after `warmup`); alpha0 (device
-    float64 map): the lossy, dispersive step (rb_frequency_step_lossy)."""
+             y=1.4, first=0):
+    """Time `steps` frequency steps of one form from c_start (after `warmup`), at the
+    frequencies first + warmup ... (data[k - first] is frequency k's); alpha0 (device float64
+    map): the lossy, dispersive step (rb_frequency_step_lossy)."""
     import torch
 
     from paper_2211_00316_amd import _lib
@@ -233,18 +234,19 @@ def run_form(ctx, w, grid, ring, tp, data, prec, steps, warmup, tag, c_start, al
         om = 2 * math.pi * w.freqs[k]
         if alpha0 is not None:
             ctx.frequency_step_lossy(grid, ring, tp, c, alpha0, y, w.smooth_window(k), [om],
-                                     [d_om or om], data[k], w.tau, residual_norm=rn, prec=prec)
+                                     [d_om or om], data[k - first], w.tau, residual_norm=rn,
+                                     prec=prec)
             return
         ctx.frequency_step(grid, ring, tp, c, w.smooth_window(k), [om], [d_om or om],
-                           data[k], w.tau, residual_norm=rn, prec=prec)
+                           data[k - first], w.tau, residual_norm=rn, prec=prec)
 
-    for k in range(warmup):
+    for k in range(first, first + warmup):
         one_step(k)
         print(f"[bench] {tag} warmup step {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
-    for k in range(warmup, warmup + steps):
+    for k in range(first + warmup, first + warmup + steps):
         one_step(k)
         print(f"[bench] {tag} step {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -501,8 +503,8 @@ def main():
                     help="plain 16-bit form timed beside the headline (faster, outside the "
                          "image tolerance)")
     ap.add_argument("--late-steps", type=int, default=3,
-                    help="steps timed from the true phantom (a late stage of the continuation: "
-                         "bent rays, folded fans); 0 skips them")
+                    help="steps timed from the true phantom at the last frequencies (a late stage of the "
+                         "continuation: bent rays, folded fans); 0 skips them")
     ap.add_argument("--no-gn", action="store_true",
                     help="skip the Gauss-Newton (Hessian-based) and prototype Born steps")
     ap.add_argument("--gn-inner", type=int, default=12, help="CG iterations of a Gauss-Newton step")
@@ -666,12 +668,21 @@ def main():
         line[f"{args.fast_form}_form"] = ff
         del cf
     if args.late_steps > 0:
+        # the last frequencies of the continuation (their narrowest smoothing windows), from
+        # the true phantom: bent rays and folded fans
         c_late = start_model(w, "truth", c_true)
-        n_late = min(args.late_steps, len(w.freqs) - args.warmup)
-        msl, stl, _ = run_form(ctx, w, grid, ring, tp, data, prec_code, n_late,
-                               min(args.warmup, n_total - n_late), args.prec + "-late", c_late)
+        n_late = min(args.late_steps, len(w.freqs) - 1)
+        wl = min(1, len(w.freqs) - n_late)
+        first = len(w.freqs) - n_late - wl
+        late_data = synthesize_data(ctx, w, grid, ring, tp, c_true,
+                                    list(range(first, len(w.freqs))))
+        msl, stl, _ = run_form(ctx, w, grid, ring, tp, late_data, prec_code, n_late, wl,
+                               args.prec + "-late", c_late, first=first)
+        del late_data
         line["late_stage_form"] = {
             "ms_per_step": round(msl, 2), "value": round(1000.0 / msl, 4), "steps": n_late,
+            "frequencies_hz": [round(w.freqs[k]) for k in range(first + wl, len(w.freqs))],
+            "smoothing_windows": [w.smooth_window(k) for k in range(first + wl, len(w.freqs))],
             "start_model": "true phantom (bent rays, folded fans)",
             "stages_ms_per_step": {k: round(v[0] / n_late, 3) for k, v in stl.items()}}
     if not args.no_gn:

@@ -961,8 +961,34 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv,
     float vmin = fminf(fminf(tv[0], tv[1]), tv[2]), vmax = fmaxf(fmaxf(tv[0], tv[1]), tv[2]);
     int i0 = max((int)ceilf(umin - 1e-4f), 0), i1 = min((int)floorf(umax + 1e-4f), nx - 1);
     int j0 = max((int)ceilf(vmin - 1e-4f), 0), j1 = min((int)floorf(vmax + 1e-4f), ny - 1);
+    // Scanline bounds: on row jj only the nodes within m of the triangle's extent over the
+    // strip |v - jj| <= m are tested (the edges clipped to the strip bound it). m covers the
+    // coverage tolerance and the rounding of the barycentric test, so the nodes skipped are
+    // nodes the test rejects; long thin triangles of a folding fan cost their rows and the
+    // nodes they cover instead of their bounding box.
+    const float m = 0.05f + 1e-4f * ((umax - umin) + (vmax - vmin));
     for (int jj = j0; jj <= j1; ++jj) {
-        for (int ii = i0; ii <= i1; ++ii) {
+        const float y = (float)jj;
+        float lo = 3.0e38f, hi = -3.0e38f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = k == 2 ? 0 : k + 1;
+            const float ua = tu[k], va = tv[k], ub = tu[k1], vb_ = tv[k1];
+            if (fmaxf(va, vb_) < y - m || fminf(va, vb_) > y + m) continue;
+            float t0 = 0.f, t1 = 1.f;
+            if (va != vb_) {
+                const float ia = 1.0f / (vb_ - va);
+                const float s0 = (y - m - va) * ia, s1 = (y + m - va) * ia;
+                t0 = fmaxf(fminf(s0, s1), 0.f);
+                t1 = fminf(fmaxf(s0, s1), 1.f);
+            }
+            const float x0 = fmaf(t0, ub - ua, ua), x1 = fmaf(t1, ub - ua, ua);
+            lo = fminf(lo, fminf(x0, x1));
+            hi = fmaxf(hi, fmaxf(x0, x1));
+        }
+        if (!(lo <= hi)) continue;
+        const int ia = max(i0, (int)ceilf(lo - m)), ib = min(i1, (int)floorf(hi + m));
+        for (int ii = ia; ii <= ib; ++ii) {
             int q = qmap[(size_t)jj * nx + ii];
             if (q < 0) continue;
             float la, lb, lc;
@@ -1071,15 +1097,15 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
 }
 
 // General path: per (folded transducer, mask node) whose walk result the rasterisation
-// replaced, interpolate the winning triangle.
-__device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, int S, int el,
+// replaced, interpolate the winning triangle. Returns the amplitude written (0 if none).
+__device__ __forceinline__ float resolve_node(const SampleBufs &sb, int n_rays, int S, int el,
                                              int q, int e0, const GridP &g, double ds, double c0,
                                              int n_mask, const int32_t *__restrict__ mask_index,
                                              const unsigned long long *__restrict__ keys,
                                              const uint8_t *__restrict__ changed,
                                              const TableOut &to) {
     const size_t tid = (size_t)el * n_mask + q;
-    if (!changed[tid]) return;
+    if (!changed[tid]) return 0.f;
     int e = e0 + el;
     size_t out = (size_t)e * n_mask + q;
     unsigned long long key = keys[tid];
@@ -1092,7 +1118,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     if (key == ~0ull || d < 2.0 * ds) {
         if (to.rec) write_invalid<true>(to, out);
         else write_invalid<false>(to, out);
-        return;
+        return 0.f;
     }
     uint32_t tri = (uint32_t)(key & 0xffffffffu);
     int half = tri & 1;
@@ -1118,10 +1144,7 @@ __device__ __forceinline__ void resolve_node(const SampleBufs &sb, int n_rays, i
     float A;
     if (to.rec) write_entry<true>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
     else write_entry<false>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
-    if (to.rowmax && A > 0.f) {
-        atomicMax(to.rowmax + 2 * e, __float_as_uint(A));
-        atomicMax(to.rowmax + 2 * e + 1, __float_as_uint(1.0f / A));
-    }
+    return A;
 }
 
 __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays, int S, int e0,
@@ -1131,12 +1154,26 @@ __global__ void __launch_bounds__(256) resolve_kernel(SampleBufs sb, int n_rays,
                                                       const unsigned long long *__restrict__ keys,
                                                       const uint8_t *__restrict__ changed,
                                                       TableOut to) {
-    const size_t total = (size_t)flist[0] * n_mask;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        const int f = (int)(t / n_mask);
-        resolve_node(sb, n_rays, S, flist[1 + f], (int)(t - (size_t)f * n_mask), e0, g, ds, c0,
-                     n_mask, mask_index, keys, changed, to);
+    // A workgroup takes 256 consecutive nodes of one folded transducer, so the largest A and
+    // 1/A it writes reach the per-row maxima as one atomic pair per wave (the walk's are
+    // folded in by tile_max_fold; max is order-independent).
+    const int per = (n_mask + 255) / 256;
+    const size_t total = (size_t)flist[0] * per;
+    for (size_t b = blockIdx.x; b < total; b += gridDim.x) {  // uniform over the workgroup
+        const int f = (int)(b / per);
+        const int el = flist[1 + f];
+        const int q = (int)(b - (size_t)f * per) * 256 + (int)threadIdx.x;
+        float A = 0.f;
+        if (q < n_mask)
+            A = resolve_node(sb, n_rays, S, el, q, e0, g, ds, c0, n_mask, mask_index, keys,
+                             changed, to);
+        if (to.rowmax) {
+            const float m0 = wave_max(A), m1 = wave_max(A > 0.f ? 1.0f / A : 0.f);
+            if ((threadIdx.x & 63) == 0 && m0 > 0.f) {
+                atomicMax(to.rowmax + 2 * (e0 + el), __float_as_uint(m0));
+                atomicMax(to.rowmax + 2 * (e0 + el) + 1, __float_as_uint(m1));
+            }
+        }
     }
 }
 
