@@ -576,18 +576,35 @@ __device__ __forceinline__ float ray_atan2(float y, float x) {
     return y < 0.f ? -a : a;
 }
 
+// Table rows of transducer e (uniform over a workgroup): entry q of the row is out + q.
+__device__ __forceinline__ TableOut table_row(const TableOut &to, size_t off) {
+    TableOut r = to;
+    if (to.rec) {
+        r.rec = to.rec + off;
+    } else {
+        r.tb.T = to.tb.T + off;
+        r.tb.A = to.tb.A + off;
+        r.tb.ux = to.tb.ux + off;
+        r.tb.uy = to.tb.uy + off;
+        r.tb.flags = to.tb.flags + off;
+    }
+    return r;
+}
+
 // REC: compact records (to.rec); otherwise the tables of the C ABI, whose T needs the FP64
-// distance d (df: the same distance in FP32, for the amplitude).
+// distance d (df: the same distance in FP32, for the amplitude; a positive normal number).
+// `to` holds the rows of the entry's transducer (table_row), out is the node's mask index.
 template <bool REC>
 __device__ __forceinline__ float write_entry_f(const float4 f0, const float4 f1, const float4 f2,
                                                const float lam[3], int K, float df, double d,
-                                               double c0, const TableOut &to, size_t out,
+                                               double c0, const TableOut &to, uint32_t out,
                                                float &A) {
     const float dT = tri_dT(lam[0], lam[1], lam[2], f0.x, f1.x, f2.x);
     const float L = tri_dT(lam[0], lam[1], lam[2], f0.y, f1.y, f2.y);
     const float tx = tri_dT(lam[0], lam[1], lam[2], f0.z, f1.z, f2.z);
     const float ty = tri_dT(lam[0], lam[1], lam[2], f0.w, f1.w, f2.w);
-    A = __expf(L) * rsqrtf(df);
+    // exp(L) = 2^(L log2 e); L is far from the range where exp2 loses precision
+    A = __builtin_amdgcn_exp2f(L * 1.44269504f) * __builtin_amdgcn_rsqf(df);
     if constexpr (REC) {
         to.rec[out] = make_float4(dT, A, ray_atan2(ty, tx), __int_as_float(0x80 | (K & 3)));
         return dT;
@@ -603,16 +620,7 @@ __device__ __forceinline__ float write_entry_f(const float4 f0, const float4 f1,
 }
 
 template <bool REC>
-__device__ __forceinline__ float write_entry(const SampleBufs &sb, const size_t vb[3],
-                                             const float lam[3], int K, float df, double d,
-                                             double c0, const TableOut &to, size_t out,
-                                             float &A) {
-    return write_entry_f<REC>(sb.fld[vb[0]], sb.fld[vb[1]], sb.fld[vb[2]], lam, K, df, d, c0, to,
-                              out, A);
-}
-
-template <bool REC>
-__device__ __forceinline__ void write_invalid(const TableOut &to, size_t out) {
+__device__ __forceinline__ void write_invalid(const TableOut &to, uint32_t out) {
     if constexpr (REC) {
         to.rec[out] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
@@ -659,10 +667,12 @@ __device__ __forceinline__ int quad_test(float2 p00, float2 p10, float2 p01, flo
     return -1;
 }
 
-__device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *__restrict__ Mrow,
-                                          size_t ebase, int n_rays, float pu, float pv, int &j,
-                                          int &i, size_t vb[3], float lam[3], int &half,
-                                          int max_it = LOCATE_MAX_IT) {
+// posE, Mrow: the transducer's samples and last-sample indices (uniform over a workgroup in
+// the walk); vb: the found triangle's vertices as sample offsets from posE.
+__device__ __forceinline__ bool mesh_walk(const float2 *__restrict__ posE,
+                                          const int32_t *__restrict__ Mrow, int n_rays, float pu,
+                                          float pv, int &j, int &i, uint32_t vb[3], float lam[3],
+                                          int &half, int max_it = LOCATE_MAX_IT) {
     for (int it = 0; it < max_it; ++it) {
         // rays j and j+1 are adjacent in memory: one load per pair (j <= n_rays - 2)
         const i2u Mv = *reinterpret_cast<const i2u *>(Mrow + j);
@@ -670,9 +680,9 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
         int top = min(Mj, Mj1) - 1;  // last quad index along the rays
         if (Mj < 0 || Mj1 < 0 || top < 1) return false;
         if (i > top) i = top;
-        size_t b00 = ebase + (size_t)i * n_rays + j, b01 = b00 + n_rays;
-        const f4u q0 = *reinterpret_cast<const f4u *>(sb.pos + b00);
-        const f4u q1 = *reinterpret_cast<const f4u *>(sb.pos + b01);
+        const uint32_t b00 = (uint32_t)(i * n_rays + j), b01 = b00 + (uint32_t)n_rays;
+        const f4u q0 = *reinterpret_cast<const f4u *>(posE + b00);
+        const f4u q1 = *reinterpret_cast<const f4u *>(posE + b01);
         const float2 p00 = make_float2(q0.x, q0.y), p10 = make_float2(q0.z, q0.w);
         const float2 p01 = make_float2(q1.x, q1.y), p11 = make_float2(q1.z, q1.w);
         const int h = quad_test(p00, p10, p01, p11, pu, pv, lam);
@@ -689,7 +699,7 @@ __device__ __forceinline__ bool mesh_walk(const SampleBufs &sb, const int32_t *_
         auto side = [&](float2 a, float2 b) {
             float ex = b.x - a.x, ey = b.y - a.y;
             float cr = ex * (pv - a.y) - ey * (pu - a.x);
-            return sg * cr * rsqrtf(ex * ex + ey * ey + 1e-30f);
+            return sg * cr * __builtin_amdgcn_rsqf(ex * ex + ey * ey + 1e-30f);
         };
         float s_i0 = side(p00, p10);   // edge at step i
         float s_j1 = side(p10, p11);   // edge along ray j+1
@@ -768,10 +778,10 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
         straight_guess((float)ddx, (float)ddy, (float)d, psi_pi, (float)ids, n_rays, S, jw, iw);
         j = jw;
         i = iw;
-        size_t vb[3];
+        uint32_t vb[3];
         float lam[3];
         int half;
-        if (d >= 2.0 * ds && mesh_walk(sb, sb.M + (size_t)el * n_rays, (size_t)el * S * n_rays,
+        if (d >= 2.0 * ds && mesh_walk(sb.pos + (size_t)el * S * n_rays, sb.M + (size_t)el * n_rays,
                                        n_rays, (float)cu, (float)cv, j, i, vb, lam, half))
             o = make_int2(j - jw, i - iw);
     }
@@ -781,44 +791,43 @@ __global__ void __launch_bounds__(256) tile_offset_kernel(SampleBufs sb, int n_r
 // Caustic count of a triangle (vertices (ray, sample): (j, i), (j + 1, i), (j + 1, i + 1) for
 // half 0; (j, i), (j + 1, i + 1), (j, i + 1) for half 1): the largest of its vertices', K being
 // stored from the first sample of a ray where it is positive.
-__device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int el, int j, int i,
-                                     int half, const size_t vb[3]) {
+__device__ __forceinline__ int tri_K(const SampleBufs &sb, int n_rays, int S, int el, int j,
+                                     int i, int half, const uint32_t vb[3]) {
+    const uint8_t *KE = sb.K + (size_t)el * S * n_rays;
     const int kf0 = sb.kfirst[(size_t)el * n_rays + j], kf1 = sb.kfirst[(size_t)el * n_rays + j + 1];
     const int vi[3] = {i, half ? i + 1 : i, i + 1};
     const int kf[3] = {kf0, kf1, half ? kf0 : kf1};
     int K = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        if (vi[k] >= kf[k]) K = max(K, (int)sb.K[vb[k]]);
+        if (vi[k] >= kf[k]) K = max(K, (int)KE[vb[k]]);
     return K;
 }
 
 // One (transducer, grid node) of the walk: for a mask node (q >= 0) writes its table entry
 // (and, in a folded fan, its seed key); returns the amplitude written (0 for an invalid entry,
 // a node outside the mask or a node left to the rasterisation).
-template <bool REC>
+template <bool REC, bool fold>
 __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, int S, int el,
-                                             int e0, const GridP &g, double ds, double c0,
-                                             int n_mask, int ii, int jj, int q, bool fold, int t,
-                                             int ntiles, const int2 *__restrict__ off,
-                                             const TableOut &to,
+                                             int e0, const GridP &g, float two_ds, double c0,
+                                             int n_mask, int ii, int jj, int q, int2 o,
+                                             const float4 wc, const TableOut &toE,
                                              unsigned long long *__restrict__ keys,
                                              uint8_t *__restrict__ changed,
                                              uint8_t *__restrict__ marks, int mtx, int mtiles,
-                                             int *lost, double psi0, float dpsi, double ids) {
+                                             int *lost, float ids) {
     const int e = e0 + el;
-    const float psi_pi = (float)(psi0 + RB_PI) + (float)e * dpsi;  // the walk's guess only
-    const double2 xy = sb.ring[e];
     // Distance from the transducer. Records: FP32 (it decides validity, the walk's start and
     // A = exp(L) / sqrt(d); the reader rebuilds T from its own FP64 distance). ABI tables:
     // FP64, for T = dT + d / c0.
     float ddx, ddy, df;
     double d = 0.0;
     if constexpr (REC) {
-        ddx = fmaf((float)ii, (float)g.dx, (float)(g.x0 - xy.x));
-        ddy = fmaf((float)jj, (float)g.dx, (float)(g.y0 - xy.y));
+        ddx = fmaf((float)ii, (float)g.dx, wc.x);
+        ddy = fmaf((float)jj, (float)g.dx, wc.y);
         df = __builtin_amdgcn_sqrtf(fmaf(ddx, ddx, ddy * ddy));
     } else {
+        const double2 xy = sb.ring[e];
         const double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
         const double dx64 = px - xy.x, dy64 = py - xy.y;
         d = sqrt_newton(dx64 * dx64 + dy64 * dy64);
@@ -827,40 +836,40 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
         df = (float)d;
     }
     int j, i;
-    straight_guess(ddx, ddy, df, psi_pi, (float)ids, n_rays, S, j, i);
-    const int2 o = off[(size_t)el * ntiles + t];
+    straight_guess(ddx, ddy, df, wc.z, ids, n_rays, S, j, i);
     j = min(max(j + o.x, 0), n_rays - 2);
     i = min(max(i + o.y, 1), S - 2);
-    const int32_t *Mrow = sb.M + (size_t)el * n_rays;
-    const size_t ebase = (size_t)el * S * n_rays;
     if (q < 0) return 0.f;  // outside the mask
-    const size_t out = (size_t)e * n_mask + q;
+    const uint32_t out = (uint32_t)q;
     const size_t kq = (size_t)el * n_mask + q;
     const size_t mq = (size_t)el * mtiles + (jj >> MT_SHIFT) * mtx + (ii >> MT_SHIFT);
-    if (df < (float)(2.0 * ds) || (fold && marks[mq])) {
-        write_invalid<REC>(to, out);
+    if (df < two_ds || (fold && marks[mq])) {
+        write_invalid<REC>(toE, out);
         if (fold) {
             keys[kq] = ~0ull;
             changed[kq] = 0;
         }
         return 0.f;
     }
-    size_t vb[3];
+    const size_t ebase = (size_t)el * S * n_rays;  // the transducer's samples
+    uint32_t vb[3];
     float lam[3];
     int half;
-    if (mesh_walk(sb, Mrow, ebase, n_rays, (float)ii, (float)jj, j, i, vb, lam, half,
-                  fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
+    if (mesh_walk(sb.pos + ebase, sb.M + (size_t)el * n_rays, n_rays, (float)ii, (float)jj, j, i,
+                  vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
         // no ray of an unfolded fan has K > 0
-        const int K = fold ? tri_K(sb, n_rays, el, j, i, half, vb) : 0;
+        const int K = fold ? tri_K(sb, n_rays, S, el, j, i, half, vb) : 0;
+        const float4 *fldE = sb.fld + ebase;
         float A;
-        const float dT = write_entry<REC>(sb, vb, lam, K, df, d, c0, to, out, A);
+        const float dT = write_entry_f<REC>(fldE[vb[0]], fldE[vb[1]], fldE[vb[2]], lam, K, df, d,
+                                            c0, toE, out, A);
         if (fold) {
             keys[kq] = tri_key(dT, (uint32_t)(((size_t)j * S + i) * 2 + half));
             changed[kq] = 0;
         }
         return A;
     }
-    write_invalid<REC>(to, out);
+    write_invalid<REC>(toE, out);
     if (fold) {  // left to the rasterisation
         keys[kq] = ~0ull;
         changed[kq] = 0;
@@ -902,9 +911,9 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
                                                      unsigned long long *__restrict__ keys,
                                                      uint8_t *__restrict__ changed,
                                                      uint8_t *__restrict__ marks, int mtx,
-                                                     int mtiles, int *lost, float dpsi,
-                                                     double ids, float cxn, float cyn,
-                                                     float r2n) {
+                                                     int mtiles, int *lost, float idsf,
+                                                     float two_ds, float cxn, float cyn,
+                                                     float r2n, const float4 *__restrict__ wcon) {
     const int ntiles = tiles_x * tiles_y;
     const int G = LOCATE_GROUP_ROWS * tiles_x;
     const int L = blockIdx.x, xcd = L & 7, k = L >> 3;
@@ -921,9 +930,15 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
     const float ru = (float)ii - cxn, rv = (float)jj - cyn;
     if (ii < g.nx && jj < g.ny && ru * ru + rv * rv <= r2n) {
         const int q = qmap[(size_t)jj * g.nx + ii];
-        A = locate_node<REC>(sb, n_rays, S, el, e0, g, ds, c0, n_mask, ii, jj, q, fold, t,
-                             ntiles, off, to, keys, changed, marks, mtx, mtiles, lost, psi0,
-                             dpsi, ids);
+        const TableOut toE = table_row(to, (size_t)(e0 + el) * n_mask);
+        if (fold)
+            A = locate_node<REC, true>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj, q,
+                                       off[item], wcon[e0 + el], toE, keys, changed, marks, mtx,
+                                       mtiles, lost, idsf);
+        else
+            A = locate_node<REC, false>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj, q,
+                                        off[item], wcon[e0 + el], toE, keys, changed, marks, mtx,
+                                        mtiles, lost, idsf);
     }
     if (REC && to.tmax) {
         // each wave's largest A and 1/A (0 where no record was written); no barrier, so a
@@ -1107,7 +1122,8 @@ __device__ __forceinline__ float resolve_node(const SampleBufs &sb, int n_rays, 
     const size_t tid = (size_t)el * n_mask + q;
     if (!changed[tid]) return 0.f;
     int e = e0 + el;
-    size_t out = (size_t)e * n_mask + q;
+    const TableOut toE = table_row(to, (size_t)e * n_mask);
+    const uint32_t out = (uint32_t)q;
     unsigned long long key = keys[tid];
     int p = mask_index[q];
     int ii = p % g.nx, jj = p / g.nx;
@@ -1116,34 +1132,39 @@ __device__ __forceinline__ float resolve_node(const SampleBufs &sb, int n_rays, 
     double px = g.x0 + ii * g.dx, py = g.y0 + jj * g.dx;
     double d = sqrt_newton((px - xe) * (px - xe) + (py - ye) * (py - ye));
     if (key == ~0ull || d < 2.0 * ds) {
-        if (to.rec) write_invalid<true>(to, out);
-        else write_invalid<false>(to, out);
+        if (to.rec) write_invalid<true>(toE, out);
+        else write_invalid<false>(toE, out);
         return 0.f;
     }
     uint32_t tri = (uint32_t)(key & 0xffffffffu);
     int half = tri & 1;
     uint32_t rest = tri >> 1;
     int j = (int)(rest / S), i = (int)(rest % S);
-    size_t b00 = ((size_t)el * S + i) * n_rays + j;
-    size_t b01 = b00 + n_rays;
-    size_t vb[3];
+    const size_t ebase = (size_t)el * S * n_rays;  // the transducer's samples
+    const uint32_t b00 = (uint32_t)(i * n_rays + j), b01 = b00 + (uint32_t)n_rays;
+    uint32_t vb[3];
     vb[0] = b00;
     vb[1] = half ? b01 + 1 : b00 + 1;
     vb[2] = half ? b01 : b01 + 1;
     float tu[3], tv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float2 pk = sb.pos[vb[k]];
+        float2 pk = sb.pos[ebase + vb[k]];
         tu[k] = pk.x;
         tv[k] = pk.y;
     }
     float la, lb, lc;
     barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la, lb, lc);
     float lam[3] = {la, lb, lc};
-    const int K = tri_K(sb, n_rays, el, j, i, half, vb);
+    const int K = tri_K(sb, n_rays, S, el, j, i, half, vb);
+    const float4 *fldE = sb.fld + ebase;
     float A;
-    if (to.rec) write_entry<true>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
-    else write_entry<false>(sb, vb, lam, K, (float)d, d, c0, to, out, A);
+    if (to.rec)
+        write_entry_f<true>(fldE[vb[0]], fldE[vb[1]], fldE[vb[2]], lam, K, (float)d, d, c0, toE,
+                            out, A);
+    else
+        write_entry_f<false>(fldE[vb[0]], fldE[vb[1]], fldE[vb[2]], lam, K, (float)d, d, c0, toE,
+                             out, A);
     return A;
 }
 
@@ -1436,11 +1457,17 @@ __global__ void box_cols_lossy(const double *__restrict__ tn, const double *__re
     a_w[(size_t)j * nx + i] = (float)(ky * al);
 }
 
-__global__ void ring_positions(double R, double psi0, int N, double2 *pos) {
+// Transducer positions, and the walk's per-transducer constants in FP32: the grid origin
+// relative to the transducer (x0 - x_e, y0 - y_e) and psi_e + pi (its straight-ray guess).
+__global__ void ring_positions(double R, double psi0, int N, double2 *pos, GridP g, float dpsi,
+                               float4 *wcon) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < N) {
         double psi = psi0 + RB_TWO_PI * (double)e / (double)N;
-        pos[e] = make_double2(R * cos(psi), R * sin(psi));
+        const double2 xy = make_double2(R * cos(psi), R * sin(psi));
+        pos[e] = xy;
+        wcon[e] = make_float4((float)(g.x0 - xy.x), (float)(g.y0 - xy.y),
+                              (float)(psi0 + RB_PI) + (float)e * dpsi, 0.f);
     }
 }
 
@@ -1556,7 +1583,8 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align((size_t)C * nr * sizeof(double)) +
            2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
            rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
-           rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)C * tiles * sizeof(int2)) +
+           rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)r->n * sizeof(float4)) +
+           rb_align((size_t)C * tiles * sizeof(int2)) +
            rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
            rb_align((size_t)C * n_mask) + rb_align(mtiles_of(g) * (size_t)C + 4) +
            2 * rb_align((size_t)(g->nx + 2 * MPAD) * (g->ny + 2 * MPAD) * sizeof(float)) +
@@ -1596,6 +1624,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
     int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
+    float4 *wcon = rb_carve<float4>(&ctx->ws, (size_t)N);
     if (ring_out) ringpos = ring_out;
     int2 *toff = rb_carve<int2>(&ctx->ws, (size_t)C * ctx->tiles_x * ctx->tiles_y);
     float *tmax =
@@ -1623,7 +1652,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     if (!ctx->deferred) RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag, RB_W_COUNT, 0));
     else RB_TRY(rb_launch_fill_i32(ctx, ctx->d_flag + RB_W_LOST, RB_W_COUNT - RB_W_LOST, 0));
     hipLaunchKernelGGL(ring_positions, dim3((N + 255) / 256), dim3(256), 0, ctx->stream,
-                       r->radius, r->psi0, N, ringpos);
+                       r->radius, r->psi0, N, ringpos, gp, (float)(RB_TWO_PI / N), wcon);
     RB_CHECK_LAUNCH(ctx);
     if (rows) RB_TRY(rb_launch_fill_i32(ctx, reinterpret_cast<int32_t *>(rowmax), 2 * N, 0));
     hipLaunchKernelGGL(pad_map, dim3((nxp + 255) / 256, nyp), dim3(256), 0, ctx->stream, n_s,
@@ -1680,9 +1709,10 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
                            toff, to, keys, changed, marks, mtx, mtiles, lost,
-                           (float)(RB_TWO_PI / N), 1.0 / tp->ds, (float)(-g->x0 / g->dx),
+                           (float)(1.0 / tp->ds), (float)(2.0 * tp->ds), (float)(-g->x0 / g->dx),
                            (float)(-g->y0 / g->dx),
-                           (float)((g->mask_radius / g->dx + 2.0) * (g->mask_radius / g->dx + 2.0)));
+                           (float)((g->mask_radius / g->dx + 2.0) * (g->mask_radius / g->dx + 2.0)),
+                           wcon);
         RB_CHECK_LAUNCH(ctx);
         if (rows) {
             hipLaunchKernelGGL(tile_max_fold, dim3(E), dim3(256), 0, ctx->stream, tmax, ntiles,
