@@ -85,8 +85,8 @@ static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 rb_status rb_check_grid(rb_ctx *ctx, const rb_grid *g) {
     if (!g) return rb_fail(ctx, RB_EINVAL, "grid is NULL");
     if (g->nx < 4 || g->ny < 4) return rb_fail(ctx, RB_EINVAL, "grid must be at least 4x4");
-    if ((int64_t)g->nx * g->ny > (int64_t)1 << 30)
-        return rb_fail(ctx, RB_EINVAL, "grid too large");
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 30 || g->nx > 65535)
+        return rb_fail(ctx, RB_EINVAL, "grid too large (at most 2^30 nodes, 65535 per row)");
     if (!finite_pos(g->dx) || !std::isfinite(g->x0) || !std::isfinite(g->y0) ||
         !finite_pos(g->mask_radius))
         return rb_fail(ctx, RB_EINVAL, "grid spacing, origin and mask radius must be finite");
@@ -149,14 +149,32 @@ rb_status rb_prepare_grid(rb_ctx *ctx, const rb_grid *g) {
     RB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->d_mask_index) RB_HIP(ctx, hipFree(ctx->d_mask_index));
     if (ctx->d_qmap) RB_HIP(ctx, hipFree(ctx->d_qmap));
+    if (ctx->d_qrow) RB_HIP(ctx, hipFree(ctx->d_qrow));
     ctx->d_mask_index = nullptr;
     ctx->d_qmap = nullptr;
+    ctx->d_qrow = nullptr;
     ctx->have_grid = false;
     RB_HIP(ctx, hipMalloc(&ctx->d_mask_index, n * sizeof(int32_t)));
     RB_HIP(ctx, hipMalloc(&ctx->d_qmap, map.size() * sizeof(int32_t)));
     RB_HIP(ctx, hipMemcpy(ctx->d_mask_index, idx.data(), n * sizeof(int32_t),
                           hipMemcpyHostToDevice));
     RB_HIP(ctx, hipMemcpy(ctx->d_qmap, map.data(), map.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    // the mask is a disc: each row's nodes are one run of consecutive indices
+    std::vector<int2> qrow((size_t)g->ny, make_int2(1, 0));  // empty: first > last
+    for (int j = 0; j < g->ny; ++j) {
+        int lo = -1, hi = -1;
+        for (int i = 0; i < g->nx; ++i)
+            if (map[(size_t)j * g->nx + i] >= 0) {
+                if (lo < 0) lo = i;
+                hi = i;
+            }
+        if (lo >= 0)
+            qrow[j] = make_int2((int)((uint32_t)lo | ((uint32_t)hi << 16)),
+                                map[(size_t)j * g->nx + lo] - lo);
+    }
+    RB_HIP(ctx, hipMalloc(&ctx->d_qrow, qrow.size() * sizeof(int2)));
+    RB_HIP(ctx, hipMemcpy(ctx->d_qrow, qrow.data(), qrow.size() * sizeof(int2),
                           hipMemcpyHostToDevice));
     int imin = g->nx, imax = -1, jmin = g->ny, jmax = -1;
     for (int32_t p : idx) {
@@ -378,6 +396,7 @@ void rb_destroy(rb_ctx *ctx) {
     if (ctx->gn.base) (void)hipFree(ctx->gn.base);
     if (ctx->d_mask_index) (void)hipFree(ctx->d_mask_index);
     if (ctx->d_qmap) (void)hipFree(ctx->d_qmap);
+    if (ctx->d_qrow) (void)hipFree(ctx->d_qrow);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
     if (ctx->d_red) (void)hipFree(ctx->d_red);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);

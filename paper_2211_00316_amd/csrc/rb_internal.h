@@ -58,6 +58,7 @@ struct rb_ctx {
     int64_t n_mask = 0;
     int32_t *d_mask_index = nullptr;  // [n_mask] flat node index of each mask node
     int32_t *d_qmap = nullptr;        // [nx*ny] mask index of each node, -1 outside
+    int2 *d_qrow = nullptr;           // [ny] mask row: (first | last << 16, index - i)
     int tile_i0 = 0, tile_j0 = 0;     // walk tiles (RB_WALK_TX x RB_WALK_TY nodes) over the mask bbox
     int tiles_x = 0, tiles_y = 0;
 

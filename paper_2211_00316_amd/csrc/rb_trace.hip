@@ -956,9 +956,11 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
 // Offer triangle tid to every mask node it covers. Keys only decrease, so a stale read of a
 // node's key costs at most a needless atomic; a node whose key this triangle lowers is
 // marked changed (its record is then rebuilt by the resolve pass).
+// qrow: per grid row, the mask's run of nodes (first | last << 16) and the mask index of node
+// i of the row minus i (the mask is a disc: one run per row).
 __device__ __forceinline__ void raster_tri(const float *tu, const float *tv,
                                            const float4 *__restrict__ fld, const size_t *vb,
-                                           int nx, int ny, const int32_t *__restrict__ qmap,
+                                           int nx, int ny, const int2 *qrow,
                                            unsigned long long *__restrict__ keys,
                                            uint8_t *__restrict__ changed,
                                            const uint8_t *__restrict__ marks, int mtx,
@@ -1002,10 +1004,11 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv,
             hi = fmaxf(hi, fmaxf(x0, x1));
         }
         if (!(lo <= hi)) continue;
-        const int ia = max(i0, (int)ceilf(lo - m)), ib = min(i1, (int)floorf(hi + m));
+        const int2 qr = qrow[jj];
+        const int ia = max(max(i0, (int)ceilf(lo - m)), (int)((uint32_t)qr.x & 0xffffu));
+        const int ib = min(min(i1, (int)floorf(hi + m)), (int)((uint32_t)qr.x >> 16));
         for (int ii = ia; ii <= ib; ++ii) {
-            int q = qmap[(size_t)jj * nx + ii];
-            if (q < 0) continue;
+            const int q = qr.y + ii;
             float la, lb, lc;
             if (!barycentric(tu[0], tv[0], tu[1], tv[1], tu[2], tv[2], (float)ii, (float)jj, la,
                              lb, lc))
@@ -1044,7 +1047,7 @@ constexpr int RCH = 8;
 template <bool MARK>
 __device__ __forceinline__ void raster_run(const SampleBufs &sb, int n_rays, int S, int el,
                                            int c, int j, int nx, int ny, int n_mask,
-                                           const int32_t *__restrict__ qmap,
+                                           const int2 *qrow,
                                            unsigned long long *__restrict__ keys,
                                            uint8_t *__restrict__ changed,
                                            uint8_t *__restrict__ marks, int mtx, int mtiles) {
@@ -1082,23 +1085,32 @@ __device__ __forceinline__ void raster_run(const SampleBufs &sb, int n_rays, int
                 }
             }
         } else {
-            raster_tri(tu0, tv0, sb.fld, vb0, nx, ny, qmap, ek, ec, em, mtx, id0);
-            raster_tri(tu1, tv1, sb.fld, vb1, nx, ny, qmap, ek, ec, em, mtx, id0 + 1);
+            raster_tri(tu0, tv0, sb.fld, vb0, nx, ny, qrow, ek, ec, em, mtx, id0);
+            raster_tri(tu1, tv1, sb.fld, vb1, nx, ny, qrow, ek, ec, em, mtx, id0 + 1);
         }
         u0 = u3; v0 = v3;  // (j, i+1)
         u1 = u2; v1 = v2;  // (j+1, i+1)
     }
 }
 
+constexpr int RASTER_ROWS = 4096;  // grid rows of the LDS copy of the mask's row table
+
 template <bool MARK>
 __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int nx,
                                                      int ny, int n_mask,
-                                                     const int32_t *__restrict__ qmap,
+                                                     const int2 *__restrict__ qrow_g,
                                                      const int32_t *__restrict__ flist,
                                                      unsigned long long *__restrict__ keys,
                                                      uint8_t *__restrict__ changed,
                                                      uint8_t *__restrict__ marks, int mtx,
                                                      int mtiles) {
+    __shared__ int2 s_qrow[MARK ? 1 : RASTER_ROWS];
+    const int2 *qrow = qrow_g;
+    if (!MARK && ny <= RASTER_ROWS) {
+        for (int r = threadIdx.x; r < ny; r += blockDim.x) s_qrow[r] = qrow_g[r];
+        __syncthreads();
+        qrow = s_qrow;
+    }
     const size_t nq = (size_t)n_rays - 1, nc = (size_t)(S + RCH - 1) / RCH, per = nc * nq;
     const size_t total = (size_t)flist[0] * per;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -1106,7 +1118,7 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
         const int f = (int)(t / per);
         const size_t rest = t - (size_t)f * per;
         const int c = (int)(rest / nq), j = (int)(rest - (size_t)c * nq);
-        raster_run<MARK>(sb, n_rays, S, flist[1 + f], c, j, nx, ny, n_mask, qmap, keys, changed,
+        raster_run<MARK>(sb, n_rays, S, flist[1 + f], c, j, nx, ny, n_mask, qrow, keys, changed,
                          marks, mtx, mtiles);
     }
 }
@@ -1688,7 +1700,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(raster_kernel<true>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
-                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
+                           nr, S, g->nx, g->ny, n_mask, ctx->d_qrow, flist, keys, changed, marks,
                            mtx, mtiles);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
@@ -1724,7 +1736,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         // the nodes it changed
         rb_prof_begin(ctx, ST_RASTER);
         hipLaunchKernelGGL(raster_kernel<false>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
-                           nr, S, g->nx, g->ny, n_mask, ctx->d_qmap, flist, keys, changed, marks,
+                           nr, S, g->nx, g->ny, n_mask, ctx->d_qrow, flist, keys, changed, marks,
                            mtx, mtiles);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(resolve_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
