@@ -287,27 +287,29 @@ __device__ __forceinline__ float wrap_pi(float x) {
     return x - (float)RB_TWO_PI * rintf(x * (float)(1.0 / RB_TWO_PI));
 }
 
-// Stores go through LDS: the workgroup's 64 x 64 tile of G leaves as 16-byte pieces of
-// rows (over nodes), and each node's 64 transducers of H as one 128-byte row piece written by
-// eight consecutive threads (H in two halves of three planes; one 28 KB buffer for all).
-constexpr int GH_LD = GE + 8;  // H staging pitch (elements): 16-byte lane writes miss no bank
+// Stores go through LDS: the workgroup's tile of G (4 GWt transducers x 64 nodes) leaves
+// as 16-byte pieces of rows (over nodes), and each node's 4 GWt transducers of H as one row
+// piece written by consecutive threads, 16 bytes each (H in two halves of three planes; one
+// buffer for all, its pitch 8 elements longer than a row so 16-byte lane writes miss no bank).
 
-template <typename T, bool SPLIT>
-__global__ void __launch_bounds__(256) green_lp_rec_kernel(
+template <typename T, bool SPLIT, int GWt, int NW>
+__global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
     const float4 *__restrict__ rec, const int32_t *__restrict__ mask_index,
     const double2 *__restrict__ ring, double x0, double y0, double dx, int nx, int N, int n_mask,
     double omega, double c0, const float2 *__restrict__ gs, const float *__restrict__ gscale,
     int write_g, T *__restrict__ Gp, T *__restrict__ Ht, const unsigned int *__restrict__ rowmax,
     float gmax, float *__restrict__ scales, T *__restrict__ Htlo) {
-    __shared__ __attribute__((aligned(16))) T stage[3 * GQ * GH_LD];
+    constexpr int GEt = NW * GWt, GHL = GEt + 8;  // transducers per workgroup, staging pitch
+    constexpr int NT = 64 * NW;                   // threads
+    __shared__ __attribute__((aligned(16))) T stage[3 * GQ * GHL];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int q0 = blockIdx.x * GQ, E0 = blockIdx.y * GE;
+    const int q0 = blockIdx.x * GQ, E0 = blockIdx.y * GEt;
     const int q = q0 + lane;
-    const int e0 = E0 + w * GW;
+    const int e0 = E0 + w * GWt;
     const int Np = rb_lp_pad(N), Mp = rb_lp_pad(n_mask);
     const size_t gplane = (size_t)N * Mp;
     const bool node = q < n_mask;
-    float th[GW + 2], dTr[GW], Ar[GW];
+    float th[GWt + 2], dTr[GWt], Ar[GWt];
     uint32_t valid = 0, Kb = 0;
     double px = 0.0, py = 0.0;
     float2 f2 = make_float2(1.f, 0.f);
@@ -315,9 +317,9 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
         const int p = mask_index[q];
         px = x0 + (p % nx) * dx;
         py = y0 + (p / nx) * dx;
-        // records of rows e0 - 1 .. e0 + GW (indices mod N)
+        // records of rows e0 - 1 .. e0 + GWt (indices mod N)
 #pragma unroll
-        for (int r = 0; r < GW + 2; ++r) {
+        for (int r = 0; r < GWt + 2; ++r) {
             int e = e0 - 1 + r;
             e = e < 0 ? e + N : (e >= N ? e - N : e);
             if (e >= N) e = 0;  // rows past the padding end: never used
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
             const uint32_t f = __float_as_uint(v.w);
             valid |= (f & 0x80) ? (1u << r) : 0u;
             th[r] = v.z;
-            if (r >= 1 && r <= GW) {
+            if (r >= 1 && r <= GWt) {
                 dTr[r - 1] = v.x;
                 Ar[r - 1] = v.y;
                 Kb |= (f & 3) << (2 * (r - 1));
@@ -340,11 +342,11 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     }
     const double k0 = omega / c0, ic0 = 1.0 / c0;
     const float sk = (float)sqrt(k0), isk = 1.0f / sk;
-    T *sg = stage;  // G tile [2][GE][GQ]
-    uint32_t hp[6][GW / 2];  // (c, part) rows, two transducers per dword
-    uint32_t hl[6][GW / 2];  // their low parts (split form)
+    T *sg = stage;  // G tile [2][GEt][GQ]
+    uint32_t hp[6][GWt / 2];  // (c, part) rows, two transducers per dword
+    uint32_t hl[6][GWt / 2];  // their low parts (split form)
 #pragma unroll
-    for (int r = 0; r < GW; ++r) {
+    for (int r = 0; r < GWt; ++r) {
         const int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
         float rsg = 1.f, rsh = 1.f;
@@ -372,8 +374,8 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
             hi *= rsh;
         }
         const float tr = gr * f2.x - gi * f2.y, ti = gr * f2.y + gi * f2.x;
-        sg[(w * GW + r) * GQ + lane] = to_lp<T>(tr);
-        sg[(GE + w * GW + r) * GQ + lane] = to_lp<T>(ti);
+        sg[(w * GWt + r) * GQ + lane] = to_lp<T>(tr);
+        sg[(GEt + w * GWt + r) * GQ + lane] = to_lp<T>(ti);
         float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
 #pragma unroll
         for (int cp = 0; cp < 6; ++cp) {
@@ -387,40 +389,43 @@ __global__ void __launch_bounds__(256) green_lp_rec_kernel(
     }
     __syncthreads();
     if (write_g) {
-        // 2 planes x GE rows x 8 pieces of 8 nodes: four per thread
+        // 2 planes x GEt rows x 8 pieces of 8 nodes
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int id = tid + 256 * k;
-            const int part = id >> 9, row = (id >> 3) & (GE - 1), ch = id & 7;
+        for (int k = 0; k < 2 * GEt * 8 / NT; ++k) {
+            const int id = tid + NT * k;
+            const int part = id / (GEt * 8), row = (id >> 3) % GEt, ch = id & 7;
             const int e = E0 + row, qq = q0 + ch * 8;
             if (e < N && qq < Mp)
                 *reinterpret_cast<uint4 *>(Gp + part * gplane + (size_t)e * Mp + qq) =
-                    *reinterpret_cast<const uint4 *>(&sg[(part * GE + row) * GQ + ch * 8]);
+                    *reinterpret_cast<const uint4 *>(&sg[(part * GEt + row) * GQ + ch * 8]);
         }
     }
     const size_t hplane = (size_t)n_mask * Np;
-    auto store = [&](const uint32_t (&src)[6][GW / 2], T *base) {
+    auto store = [&](const uint32_t (&src)[6][GWt / 2], T *base) {
+        constexpr int PC = GEt / 8;  // pieces of 8 transducers per node row
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             __syncthreads();  // the staging buffer is free again
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int cp = 3 * half + k;
-                uint4 *dst = reinterpret_cast<uint4 *>(&stage[(k * GQ + lane) * GH_LD + w * GW]);
-                dst[0] = make_uint4(src[cp][0], src[cp][1], src[cp][2], src[cp][3]);
-                dst[1] = make_uint4(src[cp][4], src[cp][5], src[cp][6], src[cp][7]);
+                uint4 *dst = reinterpret_cast<uint4 *>(&stage[(k * GQ + lane) * GHL + w * GWt]);
+#pragma unroll
+                for (int u = 0; u < GWt / 8; ++u)
+                    dst[u] = make_uint4(src[cp][4 * u], src[cp][4 * u + 1], src[cp][4 * u + 2],
+                                        src[cp][4 * u + 3]);
             }
             __syncthreads();
-            // 3 planes x GQ node rows x 8 pieces of 8 transducers: six per thread
+            // 3 planes x GQ node rows x PC pieces of 8 transducers
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const int id = tid + 256 * k;
-                const int pl = id >> 9, qr = (id >> 3) & (GQ - 1), ch = id & 7;
+            for (int k = 0; k < 3 * GQ * PC / NT; ++k) {
+                const int id = tid + NT * k;
+                const int pl = id / (GQ * PC), qr = (id / PC) % GQ, ch = id % PC;
                 const int qq = q0 + qr, e = E0 + ch * 8;
                 if (qq < n_mask && e < Np)
                     *reinterpret_cast<uint4 *>(base + (size_t)(3 * half + pl) * hplane +
                                                (size_t)qq * Np + e) =
-                        *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GH_LD + ch * 8]);
+                        *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GHL + ch * 8]);
             }
         }
     };
@@ -1353,23 +1358,27 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
                                  const float *gscale, int write_g, const unsigned int *rowmax) {
     const int nm = (int)ctx->n_mask;
     const rb_grid &g = ctx->grid;
+    // the split form holds twice the packed rows per lane: 8 transducers per wave (8 waves
+    // per workgroup, so a workgroup still writes 128-byte row pieces of H) keep it at 4 waves
+    // per SIMD
+    constexpr int GWS = 8;
     dim3 grd((nm + GQ - 1) / GQ, (n + GE - 1) / GE);
     const float gmax = gs ? GS_MAX : 1.f;
     const size_t hlo = 6 * (size_t)nm * rb_lp_pad(n);  // low parts follow H
     rb_prof_begin(ctx, ST_GREEN);
     if (out->prec == RB_BF16)
-        hipLaunchKernelGGL((green_lp_rec_kernel<__bf16, false>), grd, dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL((green_lp_rec_kernel<__bf16, false, GW, 4>), grd, dim3(256), 0, ctx->stream,
                            rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
                            c0, (const float2 *)gs, gscale, write_g, (__bf16 *)out->G,
                            (__bf16 *)out->H, rowmax, gmax, out->scales, nullptr);
     else if (rb_prec_split(out->prec))
-        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, true>), grd, dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, true, GWS, 8>), grd, dim3(512), 0, ctx->stream,
                            rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
                            c0, (const float2 *)gs, gscale, write_g, (_Float16 *)out->G,
                            (_Float16 *)out->H, rowmax, gmax, out->scales,
                            (_Float16 *)out->H + hlo);
     else
-        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, false>), grd, dim3(256), 0,
+        hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, false, GW, 4>), grd, dim3(256), 0,
                            ctx->stream, rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n,
                            nm, omega, c0, (const float2 *)gs, gscale, write_g,
                            (_Float16 *)out->G, (_Float16 *)out->H, rowmax, gmax, out->scales,
