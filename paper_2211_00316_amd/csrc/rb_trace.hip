@@ -53,10 +53,13 @@ constexpr int MPAD = 3;
 // stored per cell as the bicubic in the cell's local coordinates (tx, ty) in [0, 1):
 // coef[cell][j] = (a_j0, a_j1, a_j2, a_j3) with value sum_{j,i} a_ji tx^i ty^j. Cells
 // (iu, iv), iu in [-2, nx], iv in [-2, ny], have index (iv + 2) (nx + 3) + iu + 2.
+constexpr int PATCH_STRIDE = 256;  // threads of a tracing workgroup
+
 struct SplineMap {
     const float4 *coef;  // [(ny + 3) (nx + 3)][4]
     int nx, ny, ncx;     // ncx = nx + 3 cells per row
     float ih;            // 1 / dx
+    float4 *patch;       // this lane's cell cache in LDS: 4 float4 at stride PATCH_STRIDE
 };
 
 struct Spline {
@@ -67,11 +70,11 @@ struct Spline {
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef int i2u __attribute__((ext_vector_type(2), aligned(4)));
 
-// The 16 coefficients of the cell a lane evaluated last. A step is shorter than a cell, so
-// consecutive evaluations (predictor, corrector, next predictor) mostly fall in the same
-// cell and reuse them instead of loading again.
+// The cell a lane evaluated last; its 16 coefficients stay in the lane's LDS slot
+// (m.patch). A step is shorter than a cell, so consecutive evaluations (predictor,
+// corrector, next predictor) mostly fall in the same cell and read them from LDS instead of
+// loading them again; kept in LDS rather than in registers, they cost no register copies.
 struct Patch {
-    float f[16];
     int cell = -1;  // (iv + 2) (nx + 3) + iu + 2 of the stored cell, -1 for none
 };
 
@@ -85,22 +88,25 @@ __device__ __forceinline__ Spline spline_eval(const SplineMap &m, double u, doub
     if (cell != pc.cell) {
         const float4 *p = m.coef + (size_t)cell * 4;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const float4 q = p[b];
-            pc.f[4 * b] = q.x;
-            pc.f[4 * b + 1] = q.y;
-            pc.f[4 * b + 2] = q.z;
-            pc.f[4 * b + 3] = q.w;
-        }
+        for (int b = 0; b < 4; ++b) m.patch[b * PATCH_STRIDE] = p[b];
         pc.cell = cell;
+    }
+    float f[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float4 q = m.patch[b * PATCH_STRIDE];
+        f[4 * b] = q.x;
+        f[4 * b + 1] = q.y;
+        f[4 * b + 2] = q.z;
+        f[4 * b + 3] = q.w;
     }
     // Row polynomials Q_j(tx) = sum_i a_ji tx^i and their first two tx-derivatives (Horner),
     // then the same in ty: value, gradient and Hessian of the bicubic.
     float q0[4], q1[4], q2[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float a0 = pc.f[4 * j], a1 = pc.f[4 * j + 1], a2 = pc.f[4 * j + 2];
-        const float a3 = pc.f[4 * j + 3];
+        const float a0 = f[4 * j], a1 = f[4 * j + 1], a2 = f[4 * j + 2];
+        const float a3 = f[4 * j + 3];
         const float b3 = 3.0f * a3, b2 = a2 + a2;
         q0[j] = fmaf(fmaf(fmaf(a3, tx, a2), tx, a1), tx, a0);
         q1[j] = fmaf(fmaf(b3, tx, b2), tx, a1);
@@ -409,11 +415,14 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const AbsMap &am, c
 // the longest run first and the shortest fill the end of the launch. Also counts the
 // samples written (one atomic per wavefront; the workgroup is a whole number of them).
 template <bool ABS>
-__global__ void __launch_bounds__(256) trace_kernel(SplineMap m, AbsMap am, GridP g, double R,
-                                                    double psi0,
-                                                    int N, int n_rays, int max_steps, double ds,
-                                                    double c0, int e0, int E, SampleBufs sb,
-                                                    int *flag, unsigned long long *n_samples) {
+__global__ void __launch_bounds__(PATCH_STRIDE) trace_kernel(SplineMap m, AbsMap am, GridP g,
+                                                             double R, double psi0, int N,
+                                                             int n_rays, int max_steps,
+                                                             double ds, double c0, int e0, int E,
+                                                             SampleBufs sb, int *flag,
+                                                             unsigned long long *n_samples) {
+    __shared__ float4 s_patch[4 * PATCH_STRIDE];
+    m.patch = s_patch + threadIdx.x;
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int n_groups = (n_rays + 63) / 64;
     const int el = wave % E, rank = wave / E;
@@ -1349,12 +1358,14 @@ __global__ void __launch_bounds__(256) receiver_kernel(SampleBufs sb, int n_rays
 // tables if |f| <= accept, else the pair is invalid. Pairs without a bracket keep the
 // receiver kernel's invalid entry.
 template <bool ABS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) link_kernel(SplineMap m, AbsMap am, GridP g, double R, double psi0,
+__global__ void __launch_bounds__(PATCH_STRIDE) __attribute__((amdgpu_waves_per_eu(2))) link_kernel(SplineMap m, AbsMap am, GridP g, double R, double psi0,
                                                    int N, int n_rays, int max_steps, double ds,
                                                    double c0, int e0, int E, SampleBufs sb,
                                                    const int32_t *__restrict__ rx_j,
                                                    int max_iter, double tol, double accept,
                                                    rb_tables tb) {
+    __shared__ float4 s_patch[4 * PATCH_STRIDE];
+    m.patch = s_patch + threadIdx.x;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= E * N) return;
     const int el = t / N, r = t - el * N, e = e0 + el;
