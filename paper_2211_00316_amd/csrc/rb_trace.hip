@@ -414,8 +414,10 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const AbsMap &am, c
 // from the fan's middle (rank r: groups mid, mid - 1, mid + 1, ...), over all transducers:
 // the longest run first and the shortest fill the end of the launch. Also counts the
 // samples written (one atomic per wavefront; the workgroup is a whole number of them).
+// Four waves per SIMD (128 registers, a few spilled) hide more of the coefficient loads'
+// latency than three without spills.
 template <bool ABS>
-__global__ void __launch_bounds__(PATCH_STRIDE) trace_kernel(SplineMap m, AbsMap am, GridP g,
+__global__ void __launch_bounds__(PATCH_STRIDE) __attribute__((amdgpu_waves_per_eu(4))) trace_kernel(SplineMap m, AbsMap am, GridP g,
                                                              double R, double psi0, int N,
                                                              int n_rays, int max_steps,
                                                              double ds, double c0, int e0, int E,
