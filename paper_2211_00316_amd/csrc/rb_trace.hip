@@ -893,14 +893,17 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
 
 // Largest value over the 64 lanes of a wave (non-negative inputs), returned in every lane:
 // row reductions by DPP lane swaps, then the row results broadcast across rows (GFX9 DPP).
-__device__ __forceinline__ float wave_max(float v) {
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)));
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)));
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false)));
-    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false)));
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+// Non-negative floats order as their bit patterns, so the maxima are unsigned-integer ones:
+// one v_max_u32 with a DPP operand per stage (a float max would also quiet NaNs first).
+__device__ __forceinline__ float wave_max(float x) {
+    uint32_t v = __float_as_uint(x);
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
 }
 
 // One lane per (transducer, mask node); a workgroup covers a 16 x 16 tile of grid nodes of
