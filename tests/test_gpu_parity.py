@@ -95,7 +95,10 @@ def test_trace_rays_tables_folded_fans(ctx):
     _say(f"  nodes on a different arrival sheet: {other} of {np.count_nonzero(both)}")
     assert other <= 1e-3 * np.count_nonzero(both)
     assert rel_l2(T[same], tb_o.T[same]) <= 1e-5
-    assert rel_l2(to_np(tb.A)[same], tb_o.A[same]) <= 1e-3
+    # measured 4e-7 (FP32 fields; the caustic's largest amplitudes 2e-6)
+    err_a = rel_l2(to_np(tb.A)[same], tb_o.A[same])
+    _say(f"  amplitude rel. L2 on the same sheet: {err_a:.2e}")
+    assert err_a <= 1e-5
 
 
 def test_trace_rays_is_deterministic(ctx):
