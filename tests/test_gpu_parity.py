@@ -300,6 +300,12 @@ def test_invalid_arguments_are_rejected(ctx):
     with pytest.raises(_lib.RayBornError) as e:
         ctx.trace_rays(grid, ring, short, ns)
     assert e.value.status == _lib.RB_ENONFINITE
+    # rows longer than 65535 nodes do not fit the 16-bit mask-run bounds of the binning
+    wide = _lib.Grid(70000, 4, grid.dx, grid.x0, grid.y0, grid.mask_radius)
+    ns_wide = torch.ones(4, 70000, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(_lib.RayBornError) as e:
+        ctx.trace_rays(wide, ring, tp, ns_wide)
+    assert e.value.status == _lib.RB_EINVAL
 
 
 def test_nonfinite_update_leaves_model_unchanged(ctx):
