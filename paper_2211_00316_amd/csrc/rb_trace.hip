@@ -652,7 +652,9 @@ constexpr int LOCATE_MAX_IT = 96;
 // settle soon is given up and its node left to the rasterisation.
 constexpr int LOCATE_MAX_IT_FOLD = 16;
 constexpr int LTX = RB_WALK_TX, LTY = RB_WALK_TY;  // node tile of one locate workgroup
-constexpr int LOCATE_WAVES = LTX * LTY / 64;
+constexpr int LOCATE_NPL = 2;  // nodes per lane of the walk (rows jj and jj + LTY / 2)
+constexpr int LOCATE_THREADS = LTX * LTY / LOCATE_NPL;
+constexpr int LOCATE_WAVES = LOCATE_THREADS / 64;
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
 
 // The two triangles of quad (j, i) with corners p00 (ray j, step i), p10 (ray j + 1, step i),
@@ -916,7 +918,7 @@ __device__ __forceinline__ float wave_max(float x) {
 // so neighbouring tiles share their ray samples through one L2 while every XCD still gets an
 // even mix of the disk-shaped mask. The launch is padded to a multiple of 8 groups.
 template <bool REC>
-__global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
+__global__ void __launch_bounds__(LOCATE_THREADS, 8) locate_kernel(SampleBufs sb, int n_rays, int S, int E,
                                                      int e0, GridP g, double R, double psi0,
                                                      int N, double ds, double c0, int n_mask,
                                                      int tile_i0, int tile_j0, int tiles_x,
@@ -937,27 +939,36 @@ __global__ void __launch_bounds__(256, 8) locate_kernel(SampleBufs sb, int n_ray
     const bool fold = sb.folded[el] != 0;  // uniform over the block
     const int ti = t % tiles_x, tj = t / tiles_x;
     const int ii = tile_i0 + ti * LTX + (threadIdx.x % LTX);
-    const int jj = tile_j0 + tj * LTY + (threadIdx.x / LTX);
-    float A = 0.f;
-    // nodes clearly outside the mask disc (node units; the margin leaves the decision on the
-    // circle to qmap) issue nothing
-    const float ru = (float)ii - cxn, rv = (float)jj - cyn;
-    if (ii < g.nx && jj < g.ny && ru * ru + rv * rv <= r2n) {
-        const int q = qmap[(size_t)jj * g.nx + ii];
-        const TableOut toE = table_row(to, (size_t)(e0 + el) * n_mask);
-        if (fold)
-            A = locate_node<REC, true>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj, q,
-                                       off[item], wcon[e0 + el], toE, keys, changed, marks, mtx,
-                                       mtiles, lost, idsf);
-        else
-            A = locate_node<REC, false>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj, q,
-                                        off[item], wcon[e0 + el], toE, keys, changed, marks, mtx,
-                                        mtiles, lost, idsf);
+    const TableOut toE = table_row(to, (size_t)(e0 + el) * n_mask);
+    const int2 o = off[item];
+    const float4 wc = wcon[e0 + el];
+    // largest A and 1/A of the lane's records (bits of non-negative floats)
+    uint32_t amax = 0u, iamax = 0u;
+#pragma unroll
+    for (int h = 0; h < LOCATE_NPL; ++h) {
+        const int jj = tile_j0 + tj * LTY + h * (LOCATE_THREADS / LTX) + (threadIdx.x / LTX);
+        float A = 0.f;
+        // nodes clearly outside the mask disc (node units; the margin leaves the decision on
+        // the circle to qmap) issue nothing
+        const float ru = (float)ii - cxn, rv = (float)jj - cyn;
+        if (ii < g.nx && jj < g.ny && ru * ru + rv * rv <= r2n) {
+            const int q = qmap[(size_t)jj * g.nx + ii];
+            if (fold)
+                A = locate_node<REC, true>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj,
+                                           q, o, wc, toE, keys, changed, marks, mtx, mtiles,
+                                           lost, idsf);
+            else
+                A = locate_node<REC, false>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj,
+                                            q, o, wc, toE, keys, changed, marks, mtx, mtiles,
+                                            lost, idsf);
+        }
+        amax = max(amax, __float_as_uint(A));
+        iamax = max(iamax, __float_as_uint(A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f));
     }
     if (REC && to.tmax) {
         // each wave's largest A and 1/A (0 where no record was written); no barrier, so a
         // wave whose walks end early leaves at once
-        const float m0 = wave_max(A), m1 = wave_max(A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f);
+        const float m0 = wave_max(__uint_as_float(amax)), m1 = wave_max(__uint_as_float(iamax));
         if ((threadIdx.x & 63) == 0) {
             const size_t o = 2 * ((size_t)item * LOCATE_WAVES + (threadIdx.x >> 6));
             to.tmax[o] = m0;
@@ -1732,7 +1743,7 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         const long groups = ((long)E * ntiles + G - 1) / G;
         const long nblk = (groups + 7) / 8 * 8 * G;
         hipLaunchKernelGGL(rec ? locate_kernel<true> : locate_kernel<false>, dim3((unsigned)nblk),
-                           dim3(LTX * LTY), 0, ctx->stream,
+                           dim3(LOCATE_THREADS), 0, ctx->stream,
                            sb, nr,
                            S, E, e0, gp, r->radius, r->psi0, N, tp->ds, tp->c0, n_mask,
                            ctx->tile_i0, ctx->tile_j0, ctx->tiles_x, ctx->tiles_y, ctx->d_qmap,
