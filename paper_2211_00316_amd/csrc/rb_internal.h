@@ -168,6 +168,8 @@ inline bool rb_prec_split(int p) { return p == RB_F16X; }
 // Transducer dimension of the 16-bit operand rows (H, residual): a whole number of 32-deep
 // contraction steps, zeros past n.
 __host__ __device__ inline int rb_lp_pad(int n) { return (n + 31) & ~31; }
+// Row length of the 8-bit operand planes of the split back-projection (K steps of 64 bytes).
+__host__ __device__ inline int rb_lp8_pad(int n) { return (n + 63) & ~63; }
 template <typename T> T *rb_carve(rb_arena *a, size_t count) {
     T *p = reinterpret_cast<T *>(a->base + a->used);
     a->used += rb_align(count * sizeof(T));
@@ -254,7 +256,11 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
                              const rb_green *out, const float *gs, const float *gscale,
                              int write_g, unsigned int *rowmax);
 // The same from the compact records of rb_launch_trace (ring: transducer positions; rowmax:
-// the binning's per-row amplitude maxima).
+// the binning's per-row amplitude maxima). With the split form (RB_F16X) the three operand
+// components are the rotated ones of the frequency step's back-projection, H, b = H (u_x -
+// i u_y) and a = H (u_x + i u_y) (a^T Rs b = (H u_x)^T Rs (H u_x) + (H u_y)^T Rs (H u_y)), with
+// the FP16 low parts of H and a in the first and third low-part slots and the low part of b,
+// times 2^6, as FP8 (E4M3) planes [2][n_mask][rb_lp8_pad(n)] in the second.
 rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
                                  double omega, double c0, const rb_green *out, const float *gs,
                                  const float *gscale, int write_g, const unsigned int *rowmax);
@@ -262,15 +268,19 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
 // symmetric part of R (the bilinear forms h^T R h see nothing else; rb_lowp.hip), divided by
 // rows[e] rows[r] (the per-row scales of the other operand; nullable) and scaled by a power
 // of two kept in scale[0..1] (device, 2 floats).
+// R8 (nullable, split form of the frequency step): also the symmetric part Rs in FP8 (E4M3)
+// planes [2][n][rb_lp8_pad(n)] (zero past n), at the 16-bit operand's scale times 2^-6.
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale, const float *rows);
+                              float *scale, const float *rows, void *R8 = nullptr);
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);
 // 16-bit G [2][n][m_pad] -> conj(G) node-major [2][n_mask][n_pad] (operand of the adjoint).
 rb_status rb_launch_transpose_conj(rb_ctx *ctx, const rb_green *gr, void *Gt);
 // Hlo (nullable): low parts of a split operand (RB_F16X), added with weight 2 in the epilogue.
+// R8 (nullable, with the split form's operands of the frequency step: H, b, a and their low
+// parts, rb_launch_green_lp_rec): the rotated split form, two contractions (n_comp is then 2).
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks,
-                              const void *Hlo = nullptr);
+                              const void *Hlo = nullptr, const void *R8 = nullptr);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale);
 
@@ -282,6 +292,7 @@ struct rb_rowred_prob {
     float *parts;     // [2][mblocks][n_mask] partial sums
     int n, n_mask;
     const void *Hlo;  // low parts of H (split form) or NULL
+    const void *R8;   // FP8 planes of Rs (rotated split form) or NULL
 };
 rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_prob *probs,
                                     int count, int n_comp);

@@ -345,6 +345,10 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
     T *sg = stage;  // G tile [2][GEt][GQ]
     uint32_t hp[6][GWt / 2];  // (c, part) rows, two transducers per dword
     uint32_t hl[6][GWt / 2];  // their low parts (split form)
+    uint32_t b8[2][GWt / 4];  // split form: low part of b (re, im) as FP8, four per dword
+    float b8p[2] = {0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < GWt / 4; ++u) b8[0][u] = b8[1][u] = 0u;
 #pragma unroll
     for (int r = 0; r < GWt; ++r) {
         const int e = e0 + r;
@@ -376,14 +380,44 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         const float tr = gr * f2.x - gi * f2.y, ti = gr * f2.y + gi * f2.x;
         sg[(w * GWt + r) * GQ + lane] = to_lp<T>(tr);
         sg[(GEt + w * GWt + r) * GQ + lane] = to_lp<T>(ti);
-        float v[6] = {hr, hi, hr * vx, hi * vx, hr * vy, hi * vy};
+        // components H, H u_x, H u_y; in the split form the rotated ones H, b = H (u_x - i u_y),
+        // a = H (u_x + i u_y), whose bilinear form a^T Rs b is the sum of the other two
+        // quadratic forms (Rs symmetric), so the back-projection needs two contractions
+        float v[6];
+        v[0] = hr;
+        v[1] = hi;
+        if constexpr (SPLIT) {
+            v[2] = hr * vx + hi * vy;
+            v[3] = hi * vx - hr * vy;
+            v[4] = hr * vx - hi * vy;
+            v[5] = hi * vx + hr * vy;
+        } else {
+            v[2] = hr * vx;
+            v[3] = hi * vx;
+            v[4] = hr * vy;
+            v[5] = hi * vy;
+        }
 #pragma unroll
         for (int cp = 0; cp < 6; ++cp) {
             if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
             if constexpr (SPLIT) {
-                if (r & 1) hl[cp][r >> 1] |= lp_lo_bits<T>(v[cp]) << 16;
-                else hl[cp][r >> 1] = lp_lo_bits<T>(v[cp]);
+                if (cp == 2 || cp == 3) {
+                    // low part of b: |lo| <= 4 (half an FP16 ulp below 2^14), times 2^6 in FP8
+                    const float lo = 64.f * (v[cp] - from_lp<T>(to_lp<T>(v[cp])));
+                    if (!(r & 1))
+                        b8p[cp - 2] = lo;
+                    else if ((r >> 1) & 1)  // bytes 2, 3 of the dword
+                        b8[cp - 2][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                            b8p[cp - 2], lo, (int)b8[cp - 2][r >> 2], true);
+                    else  // bytes 0, 1
+                        b8[cp - 2][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                            b8p[cp - 2], lo, (int)b8[cp - 2][r >> 2], false);
+                } else if (r & 1) {
+                    hl[cp][r >> 1] |= lp_lo_bits<T>(v[cp]) << 16;
+                } else {
+                    hl[cp][r >> 1] = lp_lo_bits<T>(v[cp]);
+                }
             }
         }
     }
@@ -401,7 +435,8 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         }
     }
     const size_t hplane = (size_t)n_mask * Np;
-    auto store = [&](const uint32_t (&src)[6][GWt / 2], T *base) {
+    // skip_b: the split form's low parts, whose second component (b) leaves as FP8 below
+    auto store = [&](const uint32_t (&src)[6][GWt / 2], T *base, bool skip_b) {
         constexpr int PC = GEt / 8;  // pieces of 8 transducers per node row
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -422,15 +457,37 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
                 const int id = tid + NT * k;
                 const int pl = id / (GQ * PC), qr = (id / PC) % GQ, ch = id % PC;
                 const int qq = q0 + qr, e = E0 + ch * 8;
-                if (qq < n_mask && e < Np)
-                    *reinterpret_cast<uint4 *>(base + (size_t)(3 * half + pl) * hplane +
+                const int plane = 3 * half + pl;
+                if (qq < n_mask && e < Np && !(skip_b && (plane == 2 || plane == 3)))
+                    *reinterpret_cast<uint4 *>(base + (size_t)plane * hplane +
                                                (size_t)qq * Np + e) =
                         *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GHL + ch * 8]);
             }
         }
     };
-    store(hp, Ht);
-    if constexpr (SPLIT) store(hl, Htlo);
+    if constexpr (SPLIT) {
+        // FP8 low part of b: planes [2][n_mask][Np8] bytes in the second low-part slot,
+        // staged [part][node][GEt bytes] and written as 16-byte row pieces
+        static_assert(2 * GQ * GEt <= (int)sizeof(stage) && 2 * GQ * GEt / 16 == NT && GWt == 8,
+                      "FP8 staging: one piece per thread");
+        const int Np8 = rb_lp8_pad(N);
+        uint8_t *s8 = reinterpret_cast<uint8_t *>(stage);
+        __syncthreads();  // the staging buffer is free again
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt)
+            *reinterpret_cast<uint2 *>(&s8[(pt * GQ + lane) * GEt + w * GWt]) =
+                make_uint2(b8[pt][0], b8[pt][1]);
+        __syncthreads();
+        const int pt = tid / (GQ * GEt / 16), qr = (tid / (GEt / 16)) % GQ, ch = tid % (GEt / 16);
+        const int qq = q0 + qr;
+        uint8_t *base8 = reinterpret_cast<uint8_t *>(Htlo + 2 * hplane);
+        if (qq < n_mask)
+            *reinterpret_cast<uint4 *>(base8 + (size_t)pt * n_mask * Np8 + (size_t)qq * Np8 + E0 +
+                                       16 * ch) =
+                *reinterpret_cast<const uint4 *>(&s8[(pt * GQ + qr) * GEt + 16 * ch]);
+    }
+    store(hp, Ht, false);
+    if constexpr (SPLIT) store(hl, Htlo, true);
 }
 
 // conj(G) in the back-projection's operand layout, for the 16-bit adjoint: G planar
@@ -554,6 +611,40 @@ __global__ void to_planar_kernel(const float2 *__restrict__ src, int n, int np, 
     }
     dst[i] = to_lp<T>(v.x * s);
     dst[nn + i] = to_lp<T>(v.y * s);
+}
+
+// The symmetric part Rs of R (divided by rows[e] rows[r] when given) at the 16-bit operand's
+// scale times 2^-6, as FP8 (E4M3) planes [2][n][np8] (zero past n): the operand of the split
+// back-projection's correction term. |Rs scale| < 2^13, so the values stay below 2^7 (the
+// format's largest finite value is 448). One thread per four columns of a row.
+__global__ void to_fp8_kernel(const float2 *__restrict__ src, int n, int np8,
+                              const float *__restrict__ scale, const float *__restrict__ rows,
+                              uint32_t *__restrict__ dst) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w4 = np8 / 4;
+    const size_t nw = (size_t)n * w4;
+    if (i >= nw) return;
+    const int row = (int)(i / w4), col0 = (int)(i - (size_t)row * w4) * 4;
+    const float s = scale[0] * (1.f / 64.f);
+    float re[4], im[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int col = col0 + k;
+        re[k] = im[k] = 0.f;
+        if (col < n) {
+            const float2 a = src[(size_t)row * n + col], b = src[(size_t)col * n + row];
+            float f = 0.5f * s;
+            if (rows) f /= rows[row] * rows[col];
+            re[k] = f * (a.x + b.x);
+            im[k] = f * (a.y + b.y);
+        }
+    }
+    int pr = __builtin_amdgcn_cvt_pk_fp8_f32(re[0], re[1], 0, false);
+    pr = __builtin_amdgcn_cvt_pk_fp8_f32(re[2], re[3], pr, true);
+    int pi = __builtin_amdgcn_cvt_pk_fp8_f32(im[0], im[1], 0, false);
+    pi = __builtin_amdgcn_cvt_pk_fp8_f32(im[2], im[3], pi, true);
+    dst[i] = (uint32_t)pr;
+    dst[nw + i] = (uint32_t)pi;
 }
 
 __global__ void square_scale_kernel(const float *__restrict__ g, float *scale) {
@@ -838,6 +929,101 @@ __device__ __forceinline__ void lr_mainloop(T *s0, T *s1, T *s2, const LrLoad &L
     }
 }
 
+// FP8 (E4M3) K loop of the rotated split form's correction term: acc += A B^T with 8-bit
+// operands, K steps of 64 values (64-byte rows, the same bytes per stage as a 16-bit step of
+// 32), loaded by the same loader into the same swizzled stages (the planes seen as 16-bit
+// values). A lane's 32 bytes of a 32 x 32 x 64 MFMA operand are the two 16-byte chunks its
+// half of the wave reads in the two sub-steps of a 16-bit step (chunks h and 2 + h): the same
+// K values on both operands, so every K value meets its partner once.
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+// A fragments of a wave's 32-row tiles (re, im); the B fragments of its two 32-column tiles are
+// read one tile at a time inside the MFMA sequence (fewer live registers).
+struct Lr8Frag {
+    intx8 ar[LR_MT], ai[LR_MT];
+};
+
+__device__ __forceinline__ intx8 lr_rd8(const void *p, int c0, int c1) {
+    const char *b = static_cast<const char *>(p);
+    const uint4 x = *reinterpret_cast<const uint4 *>(b + 2 * c0);
+    const uint4 y = *reinterpret_cast<const uint4 *>(b + 2 * c1);
+    intx8 r;
+    r[0] = (int)x.x; r[1] = (int)x.y; r[2] = (int)x.z; r[3] = (int)x.w;
+    r[4] = (int)y.x; r[5] = (int)y.y; r[6] = (int)y.z; r[7] = (int)y.w;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void lr_read8(Lr8Frag &f, const T *st, int wm, int lane) {
+    const int h = lane >> 5, sw = (lane >> 2) & 3;
+    const int c0 = (h ^ sw) * 8, c1 = ((2 + h) ^ sw) * 8;
+#pragma unroll
+    for (int mt = 0; mt < LR_MT; ++mt) {
+        const int o = (wm * (32 * LR_MT) + mt * 32 + (lane & 31)) * LR_BK;
+        f.ar[mt] = lr_rd8(st + o, c0, c1);
+        f.ai[mt] = lr_rd8(st + o + LR_AP, c0, c1);
+    }
+}
+
+__device__ __forceinline__ floatx16 mfma_fp8(intx8 a, intx8 b, floatx16 c) {
+    // E4M3 operands (format 0 on both sides), no block scales
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void lr_mfma8(const Lr8Frag &f, const T *st, int wn, int lane,
+                                         floatx16 (&acc_re)[LR_MT][2],
+                                         floatx16 (&acc_im)[LR_MT][2]) {
+    const int h = lane >> 5, sw = (lane >> 2) & 3;
+    const int c0 = (h ^ sw) * 8, c1 = ((2 + h) ^ sw) * 8;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int o = 2 * LR_AP + (wn * 64 + nt * 32 + (lane & 31)) * LR_BK;
+        const intx8 br = lr_rd8(st + o, c0, c1), bi = lr_rd8(st + o + LR_BP, c0, c1);
+        intx8 bn;  // -b_im: the sign bit of every byte flipped
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bn[k] = bi[k] ^ (int)0x80808080u;
+#pragma unroll
+        for (int mt = 0; mt < LR_MT; ++mt) {
+            acc_re[mt][nt] = mfma_fp8(f.ar[mt], br, acc_re[mt][nt]);
+            acc_im[mt][nt] = mfma_fp8(f.ar[mt], bi, acc_im[mt][nt]);
+            acc_re[mt][nt] = mfma_fp8(f.ai[mt], bn, acc_re[mt][nt]);
+            acc_im[mt][nt] = mfma_fp8(f.ai[mt], br, acc_im[mt][nt]);
+        }
+    }
+}
+
+// Steps kt0 .. kt1 - 1 (step kt0 + i in stage i mod 3): after the barrier of step k its
+// fragments are read and step k + 2 is fetched into the stage of step k - 1, which every
+// wave finished reading before that barrier. The stages must be free when it starts (a
+// barrier after their last reads); no load is outstanding when it returns.
+template <typename T>
+__device__ __forceinline__ void lr_mainloop8(T *s0, T *s1, T *s2, const LrLoad &L, int kt0,
+                                             int kt1, floatx16 (&acc_re)[LR_MT][2],
+                                             floatx16 (&acc_im)[LR_MT][2]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    auto step = [&](T *cur, T *nn, int kt) {
+        if (kt + 1 < kt1) lr_sync<LR_AU + LR_BU>();
+        else lr_sync<0>();
+        Lr8Frag f;
+        lr_read8<T>(f, cur, wm, lane);
+        if (kt + 2 < kt1) lr_fetch<T>(L, nn, kt + 2);
+        lr_mfma8<T>(f, cur, wn, lane, acc_re, acc_im);
+    };
+    if (kt0 >= kt1) return;
+    lr_fetch<T>(L, s0, kt0);
+    if (kt0 + 1 < kt1) lr_fetch<T>(L, s1, kt0 + 1);
+    int kt = kt0;
+    for (; kt + 3 <= kt1; kt += 3) {
+        step(s0, s2, kt);
+        step(s1, s0, kt + 1);
+        step(s2, s1, kt + 2);
+    }
+    if (kt < kt1) step(s0, s2, kt);
+    if (kt + 1 < kt1) step(s1, s0, kt + 1);
+}
+
 // The back-projection contractions of one launch: `count` independent problems (one per scan
 // of a batch; count = 1 for a single call). Problem p owns items item0[p] .. item0[p+1]-1 of
 // the launch's item list; XCD x walks items xcd0[x] .. xcd0[x+1]-1.
@@ -847,6 +1033,12 @@ __device__ __forceinline__ void lr_mainloop(T *s0, T *s1, T *s2, const LrLoad &L
 struct RowGroup {
     int count;
     int full;
+    // rot (with full and Hlo): the rotated split form of the frequency step. Component 0 is
+    // h = H as in the split form; component 1 contracts b (FP16 high part, then the FP8 low
+    // part against the FP8 Rs in R8[p], into the same accumulators, so Y = Rs b to first
+    // order) and its epilogue takes a_hi + a_lo (components 2 of Ht and Hlo) with weight 1.
+    int rot;
+    const void *R8[RB_GROUP_MAX];
     int item0[RB_GROUP_MAX + 1];
     int xcd0[9];
     int n[RB_GROUP_MAX], n_cols[RB_GROUP_MAX];
@@ -948,6 +1140,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
 
             for (int c = 0; c < n_comp; ++c) {
                 const T *Hc = Ht + (size_t)(2 * c) * hplane;
+                const bool corr = grp.rot && c == 1;  // b: FP8 correction, epilogue with a
+                const int ce = corr ? 2 : c;          // component of the epilogue operand
                 const LrLoad ld = lr_load<T>(Rp, rplane, row0, Hc, hplane, col0, np);
                 floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
@@ -960,20 +1154,34 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                             acc_im[mt][nt][i] = 0.f;
                         }
                 lr_mainloop<T, true>(s0, s1, s2, ld, KT0, KT, acc_re, acc_im);
+                if (corr) {
+                    // + Rs b_lo on FP8 operands (R8 = Rs / 2^6, b_lo stored times 2^6), in
+                    // 64-byte rows of rb_lp8_pad(n) bytes, seen as 16-bit values by the loader
+                    const int np8 = rb_lp8_pad(n);
+                    const T *R8 = static_cast<const T *>(grp.R8[p]);
+                    const T *B8 = Hlo + (size_t)2 * hplane;
+                    const LrLoad l8 = lr_load<T>(R8, (size_t)n * np8 / 2, row0, B8,
+                                                 (size_t)n_cols * np8 / 2, col0, np8 / 2);
+                    __syncthreads();  // every wave is done with the 16-bit loop's stages
+                    lr_mainloop8<T>(s0, s1, s2, l8, 0, np8 / 64, acc_re, acc_im);
+                }
                 // epilogue: E_c[e][q] = Ht_c[q][e] for the tile's 256 rows e and 128 nodes q,
                 // staged through the three LDS stages (coalesced loads of row pieces of Ht_c);
                 // a split operand adds its low part with weight 2 (h_hi + 2 h_lo against
-                // Y = Rs h_hi: the first-order rounding of h on both sides)
+                // Y = Rs h_hi: the first-order rounding of h on both sides), the rotated
+                // form's second component a_hi + a_lo against Y = Rs b with weight 1
+                const T *He = Ht + (size_t)(2 * ce) * hplane;
                 __syncthreads();  // every wave is done with the K loop's stages
-                lr_fetch_e<T>(Hc, hplane, np, row0, col0, s0, s1, s2);
+                lr_fetch_e<T>(He, hplane, np, row0, col0, s0, s1, s2);
                 lr_sync<0>();
                 lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 1.f, cs_re, cs_im);
                 __syncthreads();  // LDS buffers are refilled next
                 if (Hlo) {
-                    lr_fetch_e<T>(Hlo + (size_t)(2 * c) * hplane, hplane, np, row0, col0, s0, s1,
-                                  s2);
+                    lr_fetch_e<T>(Hlo + (size_t)(2 * ce) * hplane, hplane, np, row0, col0, s0,
+                                  s1, s2);
                     lr_sync<0>();
-                    lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 2.f, cs_re, cs_im);
+                    lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, corr ? 1.f : 2.f, cs_re,
+                                   cs_im);
                     __syncthreads();
                 }
             }
@@ -1389,7 +1597,7 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
 }
 
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale, const float *rows) {
+                              float *scale, const float *rows, void *R8) {
     size_t nn = (size_t)n * n;
     const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
@@ -1406,6 +1614,13 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
         hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
                            (const float2 *)R, n, np, bm, scale, rows, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
+    if (R8) {
+        const size_t nw = (size_t)n * (rb_lp8_pad(n) / 4);
+        hipLaunchKernelGGL(to_fp8_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0,
+                           ctx->stream, (const float2 *)R, n, rb_lp8_pad(n), scale, rows,
+                           (uint32_t *)R8);
+        RB_CHECK_LAUNCH(ctx);
+    }
     rb_prof_end(ctx);
     return RB_OK;
 }
@@ -1439,6 +1654,8 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
     RowGroup g{};
     g.count = count;
     g.full = rb_prec_split(prec) ? 1 : 0;
+    g.rot = g.full && pr[0].R8 ? 1 : 0;
+    if (g.rot) n_comp = 2;
     int64_t items = 0, cost = 0;
     int64_t pcost[RB_GROUP_MAX];  // cost of one item of each problem (K blocks it walks)
     for (int i = 0; i < count; ++i) {
@@ -1459,6 +1676,9 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
         g.Rp[i] = pr[i].Rp;
         g.Ht[i] = pr[i].Ht;
         g.Hlo[i] = pr[i].Hlo;
+        g.R8[i] = pr[i].R8;
+        if ((pr[i].R8 != nullptr) != (g.rot != 0) || (g.rot && !pr[i].Hlo))
+            return rb_fail(ctx, RB_EINVAL, "grouped back-projection: mixed operand forms");
         g.parts[i] = pr[i].parts;
         const int64_t it = (int64_t)nblocks * ((mblocks + 1) / 2);
         pcost[i] = g.full ? 2 * mblocks : mblocks + 1;
@@ -1507,8 +1727,8 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
 
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks_out,
-                              const void *Hlo) {
-    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask, Hlo};
+                              const void *Hlo, const void *R8) {
+    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask, Hlo, R8};
     RB_TRY(rb_launch_rowred_lp_group(ctx, prec, &pr, 1, n_comp));
     if (mblocks_out) *mblocks_out = rb_rowred_lp_mblocks(n);
     return RB_OK;
