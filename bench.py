@@ -38,8 +38,9 @@ TRACE_FLOP_PER_SAMPLE = 550     # two spline value+gradient+Hessian evaluations,
 TABLE_BYTES = {"f32": 21,       # one table entry: T 8, A 4, (u_x, u_y) 8, flags 1
                "bf16": 16, "f16": 16, "f16x": 16}   # compact record: dT, A, theta, flags
 SAMPLE_BYTES = 24               # one ray sample: position 8, (dT, L, t_x, t_y) 16 (K only in folds)
-# operand bytes written per (e, p): G (complex) + H, H_x, H_y (+ their low parts when split)
-OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16, "f16x": 28}
+# operand bytes written per (e, p): G (complex) + H, H_x, H_y; split form: G + H, b, a (FP16)
+# + their low parts (FP8)
+OPERAND_BYTES = {"f32": 32, "bf16": 16, "f16": 16, "f16x": 22}
 
 CSRC = os.path.join(ROOT, "paper_2211_00316_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
@@ -182,7 +183,8 @@ def _pad(x, m):
 
 def contraction_flops(stage, N, Pm, prec):
     """(issued, own, dense) flop of one launch of a contraction. issued: what the kernel's
-    tiles compute (the MFMA instructions it issues); own: the symmetric products' unique
+    tiles compute (the MFMA instructions it issues; in the split form the FP8 product counts
+    half, its MFMA rate being twice the FP16 one); own: the symmetric products' unique
     entries, 8 flop per complex multiply-add over N (N + 1) / 2 pairs; dense: the plain
     complex GEMM count (8 N^2 P_m for the forward, three of them for the back-projection)."""
     own_pairs = N * (N + 1) // 2
@@ -199,12 +201,14 @@ def contraction_flops(stage, N, Pm, prec):
     # the whole symmetric R in the split form), node tiles of 128 (64 in FP32)
     Np = _pad(N, 32)
     mb = _pad(N, 256) // 256
-    if prec == "f16x":
-        rows_k = mb * 256 * Np
-    else:
-        rows_k = sum(256 * (Np - 256 * i) for i in range(mb))
     cols = _pad(Pm, 64 if prec == "f32" else 128)
-    return 24.0 * rows_k * cols, 24.0 * own_pairs * Pm, 24.0 * N * N * Pm
+    if prec == "f16x":
+        # two FP16 products over all of Rs (H; b) and one FP8 product (b's low part, K rows
+        # padded to 64)
+        issued = 16.0 * mb * 256 * Np * cols + 0.5 * 8.0 * mb * 256 * _pad(N, 64) * cols
+    else:
+        issued = 24.0 * sum(256 * (Np - 256 * i) for i in range(mb)) * cols
+    return issued, 24.0 * own_pairs * Pm, 24.0 * N * N * Pm
 
 
 def start_model(w, start, c_true):
@@ -327,7 +331,8 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
                              contraction_flops("backproject_gemm", N, Pm, prec)[0] / 1e12,
                              "TFLOP/s", peak, peak_name,
                              "flop the kernel issues (3 complex products, row slabs of 256 "
-                             "over the block upper triangle of R, or all of R when split)"),
+                             "over the block upper triangle of R; split: 2 FP16 products over "
+                             "all of Rs + 1 FP8 product counted at half)"),
     }
     out = {}
     for stage, (bound, units, unit, pk, pk_name, what) in work.items():

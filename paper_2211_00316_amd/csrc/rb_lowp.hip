@@ -344,11 +344,14 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
     const float sk = (float)sqrt(k0), isk = 1.0f / sk;
     T *sg = stage;  // G tile [2][GEt][GQ]
     uint32_t hp[6][GWt / 2];  // (c, part) rows, two transducers per dword
-    uint32_t hl[6][GWt / 2];  // their low parts (split form)
-    uint32_t b8[2][GWt / 4];  // split form: low part of b (re, im) as FP8, four per dword
-    float b8p[2] = {0.f, 0.f};
+    uint32_t b8[6][GWt / 4];  // split form: their low parts times 2^6 as FP8, four per dword
+    float b8p[6];
 #pragma unroll
-    for (int u = 0; u < GWt / 4; ++u) b8[0][u] = b8[1][u] = 0u;
+    for (int cp = 0; cp < 6; ++cp) {
+        b8p[cp] = 0.f;
+#pragma unroll
+        for (int u = 0; u < GWt / 4; ++u) b8[cp][u] = 0u;
+    }
 #pragma unroll
     for (int r = 0; r < GWt; ++r) {
         const int e = e0 + r;
@@ -402,22 +405,17 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
             if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
             if constexpr (SPLIT) {
-                if (cp == 2 || cp == 3) {
-                    // low part of b: |lo| <= 4 (half an FP16 ulp below 2^14), times 2^6 in FP8
-                    const float lo = 64.f * (v[cp] - from_lp<T>(to_lp<T>(v[cp])));
-                    if (!(r & 1))
-                        b8p[cp - 2] = lo;
-                    else if ((r >> 1) & 1)  // bytes 2, 3 of the dword
-                        b8[cp - 2][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
-                            b8p[cp - 2], lo, (int)b8[cp - 2][r >> 2], true);
-                    else  // bytes 0, 1
-                        b8[cp - 2][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
-                            b8p[cp - 2], lo, (int)b8[cp - 2][r >> 2], false);
-                } else if (r & 1) {
-                    hl[cp][r >> 1] |= lp_lo_bits<T>(v[cp]) << 16;
-                } else {
-                    hl[cp][r >> 1] = lp_lo_bits<T>(v[cp]);
-                }
+                // low part: |lo| <= 4 (half an FP16 ulp below 2^14), times 2^6 in FP8 (E4M3);
+                // a correction of relative size 2^-11 needs no more than its 3 bits
+                const float lo = 64.f * (v[cp] - from_lp<T>(to_lp<T>(v[cp])));
+                if (!(r & 1))
+                    b8p[cp] = lo;
+                else if ((r >> 1) & 1)  // bytes 2, 3 of the dword
+                    b8[cp][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                        b8p[cp], lo, (int)b8[cp][r >> 2], true);
+                else  // bytes 0, 1
+                    b8[cp][r >> 2] = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                        b8p[cp], lo, (int)b8[cp][r >> 2], false);
             }
         }
     }
@@ -435,8 +433,7 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         }
     }
     const size_t hplane = (size_t)n_mask * Np;
-    // skip_b: the split form's low parts, whose second component (b) leaves as FP8 below
-    auto store = [&](const uint32_t (&src)[6][GWt / 2], T *base, bool skip_b) {
+    auto store = [&](const uint32_t (&src)[6][GWt / 2], T *base) {
         constexpr int PC = GEt / 8;  // pieces of 8 transducers per node row
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
@@ -458,7 +455,7 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
                 const int pl = id / (GQ * PC), qr = (id / PC) % GQ, ch = id % PC;
                 const int qq = q0 + qr, e = E0 + ch * 8;
                 const int plane = 3 * half + pl;
-                if (qq < n_mask && e < Np && !(skip_b && (plane == 2 || plane == 3)))
+                if (qq < n_mask && e < Np)
                     *reinterpret_cast<uint4 *>(base + (size_t)plane * hplane +
                                                (size_t)qq * Np + e) =
                         *reinterpret_cast<const uint4 *>(&stage[(pl * GQ + qr) * GHL + ch * 8]);
@@ -466,28 +463,34 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         }
     };
     if constexpr (SPLIT) {
-        // FP8 low part of b: planes [2][n_mask][Np8] bytes in the second low-part slot,
-        // staged [part][node][GEt bytes] and written as 16-byte row pieces
-        static_assert(2 * GQ * GEt <= (int)sizeof(stage) && 2 * GQ * GEt / 16 == NT && GWt == 8,
-                      "FP8 staging: one piece per thread");
+        // FP8 low parts: component c's planes [2][n_mask][Np8] bytes at the start of its
+        // low-part slot, staged [plane][node][GEt bytes] and written as 16-byte row pieces
+        constexpr int PP = GEt / 16;  // pieces per node row of one plane
+        static_assert(6 * GQ * GEt <= (int)sizeof(stage) && (6 * GQ * PP) % NT == 0 && GWt == 8,
+                      "FP8 staging");
         const int Np8 = rb_lp8_pad(N);
         uint8_t *s8 = reinterpret_cast<uint8_t *>(stage);
         __syncthreads();  // the staging buffer is free again
 #pragma unroll
-        for (int pt = 0; pt < 2; ++pt)
-            *reinterpret_cast<uint2 *>(&s8[(pt * GQ + lane) * GEt + w * GWt]) =
-                make_uint2(b8[pt][0], b8[pt][1]);
+        for (int cp = 0; cp < 6; ++cp)
+            *reinterpret_cast<uint2 *>(&s8[(cp * GQ + lane) * GEt + w * GWt]) =
+                make_uint2(b8[cp][0], b8[cp][1]);
         __syncthreads();
-        const int pt = tid / (GQ * GEt / 16), qr = (tid / (GEt / 16)) % GQ, ch = tid % (GEt / 16);
-        const int qq = q0 + qr;
-        uint8_t *base8 = reinterpret_cast<uint8_t *>(Htlo + 2 * hplane);
-        if (qq < n_mask)
-            *reinterpret_cast<uint4 *>(base8 + (size_t)pt * n_mask * Np8 + (size_t)qq * Np8 + E0 +
-                                       16 * ch) =
-                *reinterpret_cast<const uint4 *>(&s8[(pt * GQ + qr) * GEt + 16 * ch]);
+        uint8_t *base8 = reinterpret_cast<uint8_t *>(Htlo);
+#pragma unroll
+        for (int k = 0; k < 6 * GQ * PP / NT; ++k) {
+            const int id = tid + NT * k;
+            const int cp = id / (GQ * PP), qr = (id / PP) % GQ, ch = id % PP;
+            const int qq = q0 + qr;
+            // slot of component cp / 2 (4 hplane bytes), part cp % 2
+            const size_t o = (size_t)(cp >> 1) * 4 * hplane + (size_t)(cp & 1) * n_mask * Np8 +
+                             (size_t)qq * Np8 + E0 + 16 * ch;
+            if (qq < n_mask)
+                *reinterpret_cast<uint4 *>(base8 + o) =
+                    *reinterpret_cast<const uint4 *>(&s8[(cp * GQ + qr) * GEt + 16 * ch]);
+        }
     }
-    store(hp, Ht, false);
-    if constexpr (SPLIT) store(hl, Htlo, true);
+    store(hp, Ht);
 }
 
 // conj(G) in the back-projection's operand layout, for the 16-bit adjoint: G planar
@@ -833,6 +836,86 @@ __device__ __forceinline__ void lr_fetch_e(const T *Hc, size_t hplane, int np, i
     }
 }
 
+// The same for an FP8 operand (the low parts of the rotated split form, planes [2][n_mask]
+// [np8] bytes): rows e in chunks of LR_ECH8 (stage s0) and LR_BM - LR_ECH8 (s1), laid out
+// [part][q][e] with the 16-byte piece k of a row in slot k ^ ((q >> 2) & 3).
+constexpr int LR_ECH8 = 192;
+static_assert(2 * LR_BN * LR_ECH8 == 2 * LR_STAGE && LR_ECH8 % 32 == 0 && LR_ECH8 % 16 == 0,
+              "FP8 epilogue chunks");
+template <typename T>
+__device__ __forceinline__ void lr_fetch_e8(const uint8_t *Hc, size_t plane8, int np8, int row0,
+                                            int col0, T *s0, T *s1) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(Hc, 2 * plane8);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+        T *st = ch == 0 ? s0 : s1;
+        constexpr int waves = LR_THREADS / 64;
+        const int len = ch == 1 ? LR_BM - LR_ECH8 : LR_ECH8;
+        const int pr = len / 16;                     // pieces per row
+        const int nu = 2 * LR_BN * pr / 64 / waves;  // loads per lane
+#pragma unroll
+        for (int u = 0; u < nu; ++u) {
+            const int b = w + waves * u;
+            const int P = b * 64 + l;
+            const int row = P / pr, slot = P - row * pr;
+            const int part = row / LR_BN, q = row - part * LR_BN;
+            const int piece = slot ^ ((q >> 2) & 3);
+            const uint32_t off = (uint32_t)(part * plane8 + (size_t)(col0 + q) * np8 + row0 +
+                                            ch * LR_ECH8 + piece * 16);
+            load_lds16(r, st + b * 512, off, 0u);
+        }
+    }
+}
+
+// Epilogue of an FP8 operand staged by lr_fetch_e8: four consecutive rows e per register
+// group are one 4-byte LDS read per part; the values carry 2^6, folded into f.
+template <typename T>
+__device__ __forceinline__ void lr_epilogue8(const T *s0, const T *s1, int row0, int np,
+                                             const floatx16 (&acc_re)[LR_MT][2],
+                                             const floatx16 (&acc_im)[LR_MT][2], float f,
+                                             float (&cs_re)[2], float (&cs_im)[2]) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int q = wn * 64 + nt * 32 + (lane & 31);
+        const int hq = (q >> 2) & 3;
+#pragma unroll
+        for (int mt = 0; mt < LR_MT; ++mt) {
+            const int eb = wm * (32 * LR_MT) + mt * 32;  // wave-uniform
+            const int ch = eb / LR_ECH8;
+            const uint8_t *st = reinterpret_cast<const uint8_t *>(ch == 0 ? s0 : s1);
+            const int pr = ch == 1 ? (LR_BM - LR_ECH8) / 16 : LR_ECH8 / 16;
+            const float rm = row0 + eb < np ? f : 0.f;
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int el = eb - ch * LR_ECH8 + g * 8 + (lane >> 5) * 4;
+                const int o = (q * pr + ((el >> 4) ^ hq)) * 16 + (el & 15);
+                const int wr = *reinterpret_cast<const int *>(st + o);
+                const int wi = *reinterpret_cast<const int *>(st + o + LR_BN * pr * 16);
+                const f2v r01 = __builtin_amdgcn_cvt_pk_f32_fp8(wr, false);
+                const f2v r23 = __builtin_amdgcn_cvt_pk_f32_fp8(wr, true);
+                const f2v i01 = __builtin_amdgcn_cvt_pk_f32_fp8(wi, false);
+                const f2v i23 = __builtin_amdgcn_cvt_pk_f32_fp8(wi, true);
+                const float er[4] = {r01[0], r01[1], r23[0], r23[1]};
+                const float ei[4] = {i01[0], i01[1], i23[0], i23[1]};
+#pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    const float yr = acc_re[mt][nt][g * 4 + z];
+                    const float yi = acc_im[mt][nt][g * 4 + z];
+                    sr += er[z] * yr - ei[z] * yi;
+                    si += er[z] * yi + ei[z] * yr;
+                }
+            }
+            cs_re[nt] += rm * sr;
+            cs_im[nt] += rm * si;
+        }
+    }
+}
+
 // Issue order of one sub-step: its 16 MFMAs carry the 8 LDS reads of the next sub-step and,
 // in the first sub-step, the 6 loads of step k+2.
 __device__ __forceinline__ void lr_sched_first() {
@@ -1159,7 +1242,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                     // 64-byte rows of rb_lp8_pad(n) bytes, seen as 16-bit values by the loader
                     const int np8 = rb_lp8_pad(n);
                     const T *R8 = static_cast<const T *>(grp.R8[p]);
-                    const T *B8 = Hlo + (size_t)2 * hplane;
+                    const T *B8 = Hlo + (size_t)2 * hplane;  // the second low-part slot
                     const LrLoad l8 = lr_load<T>(R8, (size_t)n * np8 / 2, row0, B8,
                                                  (size_t)n_cols * np8 / 2, col0, np8 / 2);
                     __syncthreads();  // every wave is done with the 16-bit loop's stages
@@ -1176,12 +1259,21 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                 lr_sync<0>();
                 lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 1.f, cs_re, cs_im);
                 __syncthreads();  // LDS buffers are refilled next
-                if (Hlo) {
+                if (Hlo && grp.rot) {
+                    // FP8 low part (times 2^6) at the start of the component's low-part slot
+                    const int np8 = rb_lp8_pad(n);
+                    const uint8_t *lo8 = reinterpret_cast<const uint8_t *>(Hlo) +
+                                         (size_t)ce * 4 * hplane;
+                    lr_fetch_e8<T>(lo8, (size_t)n_cols * np8, np8, row0, col0, s0, s1);
+                    lr_sync<0>();
+                    lr_epilogue8<T>(s0, s1, row0, np, acc_re, acc_im,
+                                    (corr ? 1.f : 2.f) * (1.f / 64.f), cs_re, cs_im);
+                    __syncthreads();
+                } else if (Hlo) {
                     lr_fetch_e<T>(Hlo + (size_t)(2 * ce) * hplane, hplane, np, row0, col0, s0,
                                   s1, s2);
                     lr_sync<0>();
-                    lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, corr ? 1.f : 2.f, cs_re,
-                                   cs_im);
+                    lr_epilogue<T>(s0, s1, s2, row0, np, acc_re, acc_im, 2.f, cs_re, cs_im);
                     __syncthreads();
                 }
             }
