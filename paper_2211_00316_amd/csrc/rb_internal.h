@@ -258,9 +258,9 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
 // The same from the compact records of rb_launch_trace (ring: transducer positions; rowmax:
 // the binning's per-row amplitude maxima). With the split form (RB_F16X) the three operand
 // components are the rotated ones of the frequency step's back-projection, H, b = H (u_x -
-// i u_y) and a = H (u_x + i u_y) (a^T Rs b = (H u_x)^T Rs (H u_x) + (H u_y)^T Rs (H u_y)), with
-// the FP16 low parts of H and a in the first and third low-part slots and the low part of b,
-// times 2^6, as FP8 (E4M3) planes [2][n_mask][rb_lp8_pad(n)] in the second.
+// i u_y) and a = H (u_x + i u_y) (a^T Rs b = (H u_x)^T Rs (H u_x) + (H u_y)^T Rs (H u_y)); the
+// low parts of H, b and a, times 2^6, as FP8 (E4M3) at the start of the three low-part slots,
+// each [2][rb_lp8_pad(n) / 64][n_mask][64] (blocks of 64 transducers, node-major inside).
 rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
                                  double omega, double c0, const rb_green *out, const float *gs,
                                  const float *gscale, int write_g, const unsigned int *rowmax);

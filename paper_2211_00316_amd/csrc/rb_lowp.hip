@@ -463,11 +463,13 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         }
     };
     if constexpr (SPLIT) {
-        // FP8 low parts: component c's planes [2][n_mask][Np8] bytes at the start of its
-        // low-part slot, staged [plane][node][GEt bytes] and written as 16-byte row pieces
+        // FP8 low parts: component c's planes [2][Np8 / 64][n_mask][64 bytes] at the start
+        // of its low-part slot (a block of 64 transducers per workgroup: its 64 nodes are
+        // 4 KiB in a row), staged [plane][node][GEt bytes]
         constexpr int PP = GEt / 16;  // pieces per node row of one plane
-        static_assert(6 * GQ * GEt <= (int)sizeof(stage) && (6 * GQ * PP) % NT == 0 && GWt == 8,
-                      "FP8 staging");
+        static_assert(6 * GQ * GEt <= (int)sizeof(stage) && (6 * GQ * PP) % NT == 0 &&
+                          GWt == 8 && GEt == 64,
+                      "FP8 staging: one block of 64 transducers per workgroup");
         const int Np8 = rb_lp8_pad(N);
         uint8_t *s8 = reinterpret_cast<uint8_t *>(stage);
         __syncthreads();  // the staging buffer is free again
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
             const int qq = q0 + qr;
             // slot of component cp / 2 (4 hplane bytes), part cp % 2
             const size_t o = (size_t)(cp >> 1) * 4 * hplane + (size_t)(cp & 1) * n_mask * Np8 +
-                             (size_t)qq * Np8 + E0 + 16 * ch;
+                             (size_t)(E0 >> 6) * n_mask * 64 + (size_t)qq * 64 + 16 * ch;
             if (qq < n_mask)
                 *reinterpret_cast<uint4 *>(base8 + o) =
                     *reinterpret_cast<const uint4 *>(&s8[(cp * GQ + qr) * GEt + 16 * ch]);
@@ -836,15 +838,16 @@ __device__ __forceinline__ void lr_fetch_e(const T *Hc, size_t hplane, int np, i
     }
 }
 
-// The same for an FP8 operand (the low parts of the rotated split form, planes [2][n_mask]
-// [np8] bytes): rows e in chunks of LR_ECH8 (stage s0) and LR_BM - LR_ECH8 (s1), laid out
-// [part][q][e] with the 16-byte piece k of a row in slot k ^ ((q >> 2) & 3).
+// The same for an FP8 operand (the low parts of the rotated split form, [part][block of 64
+// transducers][n_cols nodes][64 bytes]): rows e in chunks of LR_ECH8 (stage s0) and
+// LR_BM - LR_ECH8 (s1), laid out [part][q][e] with the 16-byte piece k of a row in slot
+// k ^ ((q >> 2) & 3).
 constexpr int LR_ECH8 = 192;
 static_assert(2 * LR_BN * LR_ECH8 == 2 * LR_STAGE && LR_ECH8 % 32 == 0 && LR_ECH8 % 16 == 0,
               "FP8 epilogue chunks");
 template <typename T>
-__device__ __forceinline__ void lr_fetch_e8(const uint8_t *Hc, size_t plane8, int np8, int row0,
-                                            int col0, T *s0, T *s1) {
+__device__ __forceinline__ void lr_fetch_e8(const uint8_t *Hc, size_t plane8, int n_cols,
+                                            int row0, int col0, T *s0, T *s1) {
     const __amdgpu_buffer_rsrc_t r = plane_rsrc(Hc, 2 * plane8);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
 #pragma unroll
@@ -861,8 +864,9 @@ __device__ __forceinline__ void lr_fetch_e8(const uint8_t *Hc, size_t plane8, in
             const int row = P / pr, slot = P - row * pr;
             const int part = row / LR_BN, q = row - part * LR_BN;
             const int piece = slot ^ ((q >> 2) & 3);
-            const uint32_t off = (uint32_t)(part * plane8 + (size_t)(col0 + q) * np8 + row0 +
-                                            ch * LR_ECH8 + piece * 16);
+            const int e = row0 + ch * LR_ECH8 + piece * 16;  // 16-aligned, inside one block
+            const uint32_t off = (uint32_t)(part * plane8 + (size_t)(e >> 6) * n_cols * 64 +
+                                            (size_t)(col0 + q) * 64 + (e & 63));
             load_lds16(r, st + b * 512, off, 0u);
         }
     }
@@ -1076,13 +1080,45 @@ __device__ __forceinline__ void lr_mfma8(const Lr8Frag &f, const T *st, int wn, 
     }
 }
 
+// Loader of the FP8 pass: A = Rs in FP8 rows of a_ld bytes (a K step is the next 64 bytes of
+// each row); B = the low part of b in blocks of 64 transducers, [part][block][node][64 bytes]
+// (a K step is the next block, b_step bytes further). Same lane layout as lr_load.
+__device__ __forceinline__ LrLoad lr_load8(const void *A, size_t a_plane, int a_row0, int a_ld,
+                                           const void *B, size_t b_plane, int b_row0) {
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int kc = (l & 3) ^ ((l >> 4) & 3);
+    LrLoad L;
+    L.ra = plane_rsrc(A, 2 * a_plane);
+    L.rb = plane_rsrc(B, 2 * b_plane);
+    L.a_off = (uint32_t)((size_t)(a_row0 + 16 * w + (l >> 2)) * a_ld + kc * 16);
+    L.b_off = (uint32_t)((size_t)(b_row0 + 16 * w + (l >> 2)) * 64 + kc * 16);
+    L.a_half = (uint32_t)((size_t)128 * a_ld);
+    L.a_plane = (uint32_t)a_plane;
+    L.b_plane = (uint32_t)b_plane;
+    return L;
+}
+
+template <typename T>
+__device__ __forceinline__ void lr_fetch8(const LrLoad &L, T *st, int kp, uint32_t b_step) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t ka = (uint32_t)kp * 64u, kb = (uint32_t)kp * b_step;
+#pragma unroll
+    for (int u = 0; u < LR_AU; ++u)
+        load_lds16(L.ra, st + (w + 8 * u) * 512,
+                   L.a_off + (u & 1) * L.a_half + (u >> 1) * L.a_plane, ka);
+#pragma unroll
+    for (int u = 0; u < LR_BU; ++u)
+        load_lds16(L.rb, st + 2 * LR_AP + (w + 8 * u) * 512, L.b_off + u * L.b_plane, kb);
+}
+
 // Steps kt0 .. kt1 - 1 (step kt0 + i in stage i mod 3): after the barrier of step k its
 // fragments are read and step k + 2 is fetched into the stage of step k - 1, which every
 // wave finished reading before that barrier. The stages must be free when it starts (a
 // barrier after their last reads); no load is outstanding when it returns.
 template <typename T>
-__device__ __forceinline__ void lr_mainloop8(T *s0, T *s1, T *s2, const LrLoad &L, int kt0,
-                                             int kt1, floatx16 (&acc_re)[LR_MT][2],
+__device__ __forceinline__ void lr_mainloop8(T *s0, T *s1, T *s2, const LrLoad &L,
+                                             uint32_t b_step, int kt0, int kt1,
+                                             floatx16 (&acc_re)[LR_MT][2],
                                              floatx16 (&acc_im)[LR_MT][2]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -1091,12 +1127,12 @@ __device__ __forceinline__ void lr_mainloop8(T *s0, T *s1, T *s2, const LrLoad &
         else lr_sync<0>();
         Lr8Frag f;
         lr_read8<T>(f, cur, wm, lane);
-        if (kt + 2 < kt1) lr_fetch<T>(L, nn, kt + 2);
+        if (kt + 2 < kt1) lr_fetch8<T>(L, nn, kt + 2, b_step);
         lr_mfma8<T>(f, cur, wn, lane, acc_re, acc_im);
     };
     if (kt0 >= kt1) return;
-    lr_fetch<T>(L, s0, kt0);
-    if (kt0 + 1 < kt1) lr_fetch<T>(L, s1, kt0 + 1);
+    lr_fetch8<T>(L, s0, kt0, b_step);
+    if (kt0 + 1 < kt1) lr_fetch8<T>(L, s1, kt0 + 1, b_step);
     int kt = kt0;
     for (; kt + 3 <= kt1; kt += 3) {
         step(s0, s2, kt);
@@ -1241,12 +1277,12 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                     // + Rs b_lo on FP8 operands (R8 = Rs / 2^6, b_lo stored times 2^6), in
                     // 64-byte rows of rb_lp8_pad(n) bytes, seen as 16-bit values by the loader
                     const int np8 = rb_lp8_pad(n);
-                    const T *R8 = static_cast<const T *>(grp.R8[p]);
                     const T *B8 = Hlo + (size_t)2 * hplane;  // the second low-part slot
-                    const LrLoad l8 = lr_load<T>(R8, (size_t)n * np8 / 2, row0, B8,
-                                                 (size_t)n_cols * np8 / 2, col0, np8 / 2);
+                    const LrLoad l8 = lr_load8(grp.R8[p], (size_t)n * np8, row0, np8, B8,
+                                               (size_t)n_cols * np8, col0);
                     __syncthreads();  // every wave is done with the 16-bit loop's stages
-                    lr_mainloop8<T>(s0, s1, s2, l8, 0, np8 / 64, acc_re, acc_im);
+                    lr_mainloop8<T>(s0, s1, s2, l8, (uint32_t)n_cols * 64u, 0, np8 / 64, acc_re,
+                                    acc_im);
                 }
                 // epilogue: E_c[e][q] = Ht_c[q][e] for the tile's 256 rows e and 128 nodes q,
                 // staged through the three LDS stages (coalesced loads of row pieces of Ht_c);
@@ -1264,7 +1300,7 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                     const int np8 = rb_lp8_pad(n);
                     const uint8_t *lo8 = reinterpret_cast<const uint8_t *>(Hlo) +
                                          (size_t)ce * 4 * hplane;
-                    lr_fetch_e8<T>(lo8, (size_t)n_cols * np8, np8, row0, col0, s0, s1);
+                    lr_fetch_e8<T>(lo8, (size_t)n_cols * np8, n_cols, row0, col0, s0, s1);
                     lr_sync<0>();
                     lr_epilogue8<T>(s0, s1, row0, np, acc_re, acc_im,
                                     (corr ? 1.f : 2.f) * (1.f / 64.f), cs_re, cs_im);
