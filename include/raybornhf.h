@@ -63,7 +63,13 @@ typedef enum {
  * operand H stored as two FP16 parts, h = h_hi + h_lo (h_lo: the rounding error of h_hi),
  * and the back-projection's epilogue weighting the low part twice against R h_hi (R's whole
  * symmetric part): the bilinear form h^T R h is then free of the first-order rounding of h,
- * which dominates the error of the plain 16-bit forms. */
+ * which dominates the error of the plain 16-bit forms. Inside rb_frequency_step (and the
+ * sweep, the batch and the lossy step) the same form runs on the step's own operands: H and,
+ * for the two angular components (Eq. sound_speed_update2's weight 1 + u_e . u_r), one
+ * bilinear form a^T Rs b with a = H (u_x + i u_y), b = H (u_x - i u_y), which equals the sum
+ * of their quadratic forms; the low parts are FP8 (E4M3) there, and b's enters the
+ * contraction on FP8 matrix instructions. The operands passed through this header keep the
+ * layout below. */
 typedef enum { RB_F32 = 1, RB_BF16 = 2, RB_F16 = 3, RB_F16X = 4 } rb_prec;
 
 /* Predicted data of the frequency step: ray Green's function at the receivers plus, in
