@@ -26,6 +26,9 @@ _PARAMS = {
     "ragged": (37, 0.021, 0.37e-3, 101, 12, -30.0, 3e-3),
     # a strong slow lens: rays through it cross (caustics), the fans fold
     "folded": (32, 0.02, 0.4e-3, 180, 14, -300.0, 3e-3),
+    # several row slabs of the 16-bit back-projection (256 transducers each), transducer
+    # blocks of 64 with a partial last one (300 = 4 x 64 + 44), a partial last node tile
+    "wide": (300, 0.021, 0.37e-3, 101, 13, 35.0, 3e-3),
 }
 
 

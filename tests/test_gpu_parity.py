@@ -1,6 +1,7 @@
 """GPU-vs-oracle parity of every C-ABI entry point (HIP path on cuda:0, FP64 oracle on the
 host, same seeded inputs). Tolerances (relative L2 over valid entries) follow the FP32 form:
 travel time <= 1e-5, Green's functions, data and gradients <= 1e-4."""
+import functools
 import math
 import sys
 
@@ -481,4 +482,41 @@ def test_frequency_step_lowp_image(ctx, name, window, pname):
     re = float(np.linalg.norm(c_new - c_ref.ravel()[q]) /
                np.linalg.norm((c_ref - c0).ravel()[q]))   # the gate: relative to the change
     _say(f"  image RE {re:.2e} (||c||-normalised {img:.2e})")
+    assert re <= (IMAGE_GATE if pname == "fp16x" else 40 * u)
+
+
+@functools.lru_cache(maxsize=None)
+def _wide_reference(window):
+    """Oracle step of the "wide" case from water (data, start and result)."""
+    import phantoms as ph
+
+    st, c_true = case("wide")
+    N = st.ring.n
+    om = [2 * math.pi * 250e3]
+    data = ostep.synthesize(c_true, st, om, ph.complex_noise((1, N, N), 2), background="water")
+    c0 = np.full_like(c_true, C0)
+    return om, data, c0, ostep.frequency_step(c0, st, om, om, data, 0.12, window=window)
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16x"])
+def test_frequency_step_lowp_image_wide(ctx, pname):
+    """The step's 16-bit operands over several row slabs and a partial last block of 64
+    transducers (the split form's FP8 low parts are stored in such blocks), against the
+    oracle with the image gate of the reduced-precision form."""
+    import torch
+
+    prec, u = LOWP[pname]
+    st, _ = case("wide")
+    om, data, c0, c_ref = _wide_reference(5)
+    grid, ring, tp = abi_structs(st)
+    _say(f"frequency_step {pname} wide (N = {st.ring.n}) w=5")
+    c_g = torch.as_tensor(c0.copy(), device="cuda:0")
+    ctx.frequency_step(grid, ring, tp, c_g, 5, om, om,
+                       torch.as_tensor(data.astype(np.complex64), device="cuda:0"), 0.12,
+                       prec=prec)
+    q = st.grid.mask_index()
+    c_new = to_np(c_g).ravel()[q]
+    re = float(np.linalg.norm(c_new - c_ref.ravel()[q]) /
+               np.linalg.norm((c_ref - c0).ravel()[q]))
+    _say(f"  image RE {re:.2e}")
     assert re <= (IMAGE_GATE if pname == "fp16x" else 40 * u)
