@@ -202,12 +202,16 @@ def contraction_flops(stage, N, Pm, prec):
     Np = _pad(N, 32)
     mb = _pad(N, 256) // 256
     cols = _pad(Pm, 64 if prec == "f32" else 128)
+    tri = sum(256 * (Np - 256 * i) for i in range(mb))   # K values of the block triangle
     if prec == "f16x":
         # two FP16 products over all of Rs (H; b) and one FP8 product (b's low part, K rows
         # padded to 64)
         issued = 16.0 * mb * 256 * Np * cols + 0.5 * 8.0 * mb * 256 * _pad(N, 64) * cols
+    elif prec == "f32":
+        issued = 24.0 * tri * cols   # H, H u_x, H u_y over the block triangle
     else:
-        issued = 24.0 * sum(256 * (Np - 256 * i) for i in range(mb)) * cols
+        # H over the block triangle, the bilinear form a^T Rs b over all of Rs
+        issued = 8.0 * tri * cols + 8.0 * mb * 256 * Np * cols
     return issued, 24.0 * own_pairs * Pm, 24.0 * N * N * Pm
 
 
@@ -330,9 +334,10 @@ def kernel_rooflines(stages, steps, N, Pm, samples, prec, workload):
         "backproject_gemm": ("mfma",
                              contraction_flops("backproject_gemm", N, Pm, prec)[0] / 1e12,
                              "TFLOP/s", peak, peak_name,
-                             "flop the kernel issues (3 complex products, row slabs of 256 "
-                             "over the block upper triangle of R; split: 2 FP16 products over "
-                             "all of Rs + 1 FP8 product counted at half)"),
+                             "flop the kernel issues (row slabs of 256; FP32: 3 complex "
+                             "products over the block upper triangle of R; 16-bit: H over it "
+                             "and the bilinear form a^T Rs b over all of Rs; split: 2 FP16 "
+                             "products over all of Rs + 1 FP8 product counted at half)"),
     }
     out = {}
     for stage, (bound, units, unit, pk, pk_name, what) in work.items():

@@ -673,6 +673,7 @@ struct StepBufs {
     float *d_born = nullptr, *R = nullptr, *rsym = nullptr;
     uint16_t *Rp = nullptr;
     uint8_t *Rp8 = nullptr;  // split form: FP8 planes of Rs (the correction term's operand)
+    uint16_t *Rf = nullptr;  // 16-bit forms: the whole Rs (Rp itself in the split form)
     float *rscale = nullptr, *wv = nullptr, *svscale = nullptr;
     unsigned int *rowmax = nullptr;  // per-row amplitude maxima of the binning (16-bit form)
     double *cq = nullptr, *dm = nullptr, *c_new = nullptr;
@@ -699,6 +700,7 @@ static size_t step_arena_bytes(int N, int nm, size_t P, rb_prec prec) {
            rb_align(NG * opb) + rb_align(hparts * 3 * NPp * opb) + 3 * rb_align(NN * 8) +
            rb_align(NNp * 4) +
            (rb_prec_split(prec) ? rb_align((size_t)2 * N * rb_lp8_pad(N)) : 0) +
+           (lp && !rb_prec_split(prec) ? rb_align(NNp * 4) : 0) +
            rb_align((size_t)nm * 8) + rb_align((size_t)nm * 4) +
            3 * rb_align((size_t)nm * 8) + rb_align((size_t)2 * mb * nm * 4) + rb_align(8) +
            rb_align(8) + 2 * rb_align((size_t)2 * N * 4) + 2 * rb_align(P * 8) +
@@ -758,6 +760,7 @@ static rb_status step_carve(rb_ctx *ctx, const rb_grid *grid, const rb_ring *rin
     b->rsym = rb_carve<float>(a, 2 * NN);
     b->Rp = rb_carve<uint16_t>(a, 2 * NNp);
     if (rb_prec_split(prec)) b->Rp8 = rb_carve<uint8_t>(a, (size_t)2 * N * rb_lp8_pad(N));
+    if (lp) b->Rf = rb_prec_split(prec) ? b->Rp : rb_carve<uint16_t>(a, 2 * NNp);
     b->rscale = rb_carve<float>(a, 2);
     b->wv = rb_carve<float>(a, 2 * (size_t)nm);
     b->svscale = rb_carve<float>(a, 2);
@@ -838,7 +841,7 @@ static rb_status step_residual(rb_ctx *ctx, const rb_trace_params *tp, double om
                               residual_norm));
     if (b.lp)
         RB_TRY(rb_launch_to_planar(ctx, prec, b.R, b.N, b.Rp, b.rscale, b.gr.scales + b.N,
-                                   b.Rp8));
+                                   b.Rp8, b.Rf));
     return RB_OK;
 }
 
@@ -895,7 +898,7 @@ static rb_status step_enqueue(rb_ctx *ctx, const rb_grid *grid, const rb_ring *r
         // a8: Hessian-free back-projection
         if (b.lp) {
             RB_TRY(rb_launch_rowred_lp(ctx, prec, b.N, b.nm, b.Rp, b.gr.H, 3, b.parts, nullptr,
-                                       h_low(&b.gr), b.Rp8));
+                                       h_low(&b.gr), b.Rp8, b.Rf));
         } else {
             int mbo = b.mb;
             RB_TRY(rb_launch_rowred(ctx, b.N, b.nm, b.R, (const float *)b.gr.H, 3, 0, b.rsym,
@@ -1464,7 +1467,8 @@ static rb_status batch_enqueue(const rb_scan_step *st, int count, rb_prec prec,
                 rb_rowred_prob pr[RB_GROUP_MAX];
                 for (int a = 0; a < na; ++a) {
                     StepBufs &b = bufs[act[a]];
-                    pr[a] = rb_rowred_prob{b.Rp, b.gr.H, b.parts, b.N, b.nm, h_low(&b.gr), b.Rp8};
+                    pr[a] = rb_rowred_prob{b.Rp,  b.gr.H,        b.parts, b.N,
+                                           b.nm,  h_low(&b.gr),  b.Rp8,   b.Rf};
                 }
                 res = rb_launch_rowred_lp_group(lead, prec, pr, na, 3);
             } else {

@@ -256,10 +256,10 @@ rb_status rb_launch_green_lp(rb_ctx *ctx, const rb_tables *tb, double omega, dou
                              const rb_green *out, const float *gs, const float *gscale,
                              int write_g, unsigned int *rowmax);
 // The same from the compact records of rb_launch_trace (ring: transducer positions; rowmax:
-// the binning's per-row amplitude maxima). With the split form (RB_F16X) the three operand
-// components are the rotated ones of the frequency step's back-projection, H, b = H (u_x -
-// i u_y) and a = H (u_x + i u_y) (a^T Rs b = (H u_x)^T Rs (H u_x) + (H u_y)^T Rs (H u_y)); the
-// low parts of H, b and a, times 2^6, as FP8 (E4M3) at the start of the three low-part slots,
+// the binning's per-row amplitude maxima), for the frequency step's back-projection: the
+// three operand components are the rotated ones, H, b = H (u_x - i u_y) and a = H (u_x +
+// i u_y) (a^T Rs b = (H u_x)^T Rs (H u_x) + (H u_y)^T Rs (H u_y)). In the split form the low
+// parts of H, b and a, times 2^6, are FP8 (E4M3) at the start of the three low-part slots,
 // each [2][rb_lp8_pad(n) / 64][n_mask][64] (blocks of 64 transducers, node-major inside).
 rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *ring, int n,
                                  double omega, double c0, const rb_green *out, const float *gs,
@@ -270,17 +270,23 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
 // of two kept in scale[0..1] (device, 2 floats).
 // R8 (nullable, split form of the frequency step): also the symmetric part Rs in FP8 (E4M3)
 // planes [2][n][rb_lp8_pad(n)] (zero past n), at the 16-bit operand's scale times 2^-6.
+// Rfull (nullable, plain 16-bit forms of the frequency step): also the whole Rs as 16-bit
+// planes like Rp (the operand of the rotated bilinear form).
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale, const float *rows, void *R8 = nullptr);
+                              float *scale, const float *rows, void *R8 = nullptr,
+                              void *Rfull = nullptr);
 rb_status rb_launch_unscale(rb_ctx *ctx, float *parts, size_t count, const float *scale);
 // 16-bit G [2][n][m_pad] -> conj(G) node-major [2][n_mask][n_pad] (operand of the adjoint).
 rb_status rb_launch_transpose_conj(rb_ctx *ctx, const rb_green *gr, void *Gt);
 // Hlo (nullable): low parts of a split operand (RB_F16X), added with weight 2 in the epilogue.
-// R8 (nullable, with the split form's operands of the frequency step: H, b, a and their low
-// parts, rb_launch_green_lp_rec): the rotated split form, two contractions (n_comp is then 2).
+// Rf (nullable, with the frequency step's operands H, b, a of rb_launch_green_lp_rec): the
+// rotated form, two contractions (n_comp is then 2): h^T R h over Rp, then a^T Rs b with Rs
+// = Rf (the whole symmetric part; Rp itself in the split form, whose low parts Hlo and FP8
+// Rs R8 it also takes).
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks,
-                              const void *Hlo = nullptr, const void *R8 = nullptr);
+                              const void *Hlo = nullptr, const void *R8 = nullptr,
+                              const void *Rf = nullptr);
 rb_status rb_launch_forward_lp(rb_ctx *ctx, const rb_green *gr, const float *w,
                                const float *delta, float *d, const float *gscale);
 
@@ -293,6 +299,7 @@ struct rb_rowred_prob {
     int n, n_mask;
     const void *Hlo;  // low parts of H (split form) or NULL
     const void *R8;   // FP8 planes of Rs (rotated split form) or NULL
+    const void *Rf;   // 16-bit planes of the whole Rs (rotated forms) or NULL
 };
 rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_prob *probs,
                                     int count, int n_comp);

@@ -383,23 +383,11 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         const float tr = gr * f2.x - gi * f2.y, ti = gr * f2.y + gi * f2.x;
         sg[(w * GWt + r) * GQ + lane] = to_lp<T>(tr);
         sg[(GEt + w * GWt + r) * GQ + lane] = to_lp<T>(ti);
-        // components H, H u_x, H u_y; in the split form the rotated ones H, b = H (u_x - i u_y),
-        // a = H (u_x + i u_y), whose bilinear form a^T Rs b is the sum of the other two
-        // quadratic forms (Rs symmetric), so the back-projection needs two contractions
-        float v[6];
-        v[0] = hr;
-        v[1] = hi;
-        if constexpr (SPLIT) {
-            v[2] = hr * vx + hi * vy;
-            v[3] = hi * vx - hr * vy;
-            v[4] = hr * vx - hi * vy;
-            v[5] = hi * vx + hr * vy;
-        } else {
-            v[2] = hr * vx;
-            v[3] = hi * vx;
-            v[4] = hr * vy;
-            v[5] = hi * vy;
-        }
+        // the rotated components H, b = H (u_x - i u_y), a = H (u_x + i u_y): the bilinear
+        // form a^T Rs b is the sum of the quadratic forms of H u_x and H u_y (Rs symmetric),
+        // so the back-projection needs two contractions
+        const float v[6] = {hr, hi, hr * vx + hi * vy, hi * vx - hr * vy, hr * vx - hi * vy,
+                            hi * vx + hr * vy};
 #pragma unroll
         for (int cp = 0; cp < 6; ++cp) {
             if (r & 1) hp[cp][r >> 1] |= lp_bits<T>(v[cp]) << 16;
@@ -1152,12 +1140,14 @@ __device__ __forceinline__ void lr_mainloop8(T *s0, T *s1, T *s2, const LrLoad &
 struct RowGroup {
     int count;
     int full;
-    // rot (with full and Hlo): the rotated split form of the frequency step. Component 0 is
-    // h = H as in the split form; component 1 contracts b (FP16 high part, then the FP8 low
-    // part against the FP8 Rs in R8[p], into the same accumulators, so Y = Rs b to first
-    // order) and its epilogue takes a_hi + a_lo (components 2 of Ht and Hlo) with weight 1.
+    // rot: the rotated operands of the frequency step (H, b, a). Component 0 is h = H as
+    // before (over the block triangle Rp, or all of Rs in the split form); component 1
+    // contracts b over the whole Rs in Rf[p] (in the split form then b's FP8 low part
+    // against the FP8 Rs in R8[p], into the same accumulators, so Y = Rs b to first order),
+    // and its epilogue takes a (component 2; split: a_hi + a_lo, weight 1).
     int rot;
     const void *R8[RB_GROUP_MAX];
+    const void *Rf[RB_GROUP_MAX];
     int item0[RB_GROUP_MAX + 1];
     int xcd0[9];
     int n[RB_GROUP_MAX], n_cols[RB_GROUP_MAX];
@@ -1259,9 +1249,10 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
 
             for (int c = 0; c < n_comp; ++c) {
                 const T *Hc = Ht + (size_t)(2 * c) * hplane;
-                const bool corr = grp.rot && c == 1;  // b: FP8 correction, epilogue with a
+                const bool corr = grp.rot && c == 1;  // b over all of Rs, epilogue with a
                 const int ce = corr ? 2 : c;          // component of the epilogue operand
-                const LrLoad ld = lr_load<T>(Rp, rplane, row0, Hc, hplane, col0, np);
+                const T *Ra = corr ? static_cast<const T *>(grp.Rf[p]) : Rp;
+                const LrLoad ld = lr_load<T>(Ra, rplane, row0, Hc, hplane, col0, np);
                 floatx16 acc_re[LR_MT][2], acc_im[LR_MT][2];
 #pragma unroll
                 for (int mt = 0; mt < LR_MT; ++mt)
@@ -1272,8 +1263,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                             acc_re[mt][nt][i] = 0.f;
                             acc_im[mt][nt][i] = 0.f;
                         }
-                lr_mainloop<T, true>(s0, s1, s2, ld, KT0, KT, acc_re, acc_im);
-                if (corr) {
+                lr_mainloop<T, true>(s0, s1, s2, ld, corr ? 0 : KT0, KT, acc_re, acc_im);
+                if (corr && grp.R8[p]) {
                     // + Rs b_lo on FP8 operands (R8 = Rs / 2^6, b_lo stored times 2^6), in
                     // 64-byte rows of rb_lp8_pad(n) bytes, seen as 16-bit values by the loader
                     const int np8 = rb_lp8_pad(n);
@@ -1725,7 +1716,7 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
 }
 
 rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, void *Rp,
-                              float *scale, const float *rows, void *R8) {
+                              float *scale, const float *rows, void *R8, void *Rfull) {
     size_t nn = (size_t)n * n;
     const int np = rb_lp_pad(n);
     rb_prof_begin(ctx, ST_RESIDUAL);
@@ -1742,6 +1733,15 @@ rb_status rb_launch_to_planar(rb_ctx *ctx, rb_prec prec, const float *R, int n, 
         hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
                            (const float2 *)R, n, np, bm, scale, rows, (_Float16 *)Rp);
     RB_CHECK_LAUNCH(ctx);
+    if (Rfull && Rfull != Rp) {  // one block: the whole symmetric part
+        if (prec == RB_BF16)
+            hipLaunchKernelGGL(to_planar_kernel<__bf16>, grd, dim3(256), 0, ctx->stream,
+                               (const float2 *)R, n, np, np, scale, rows, (__bf16 *)Rfull);
+        else
+            hipLaunchKernelGGL(to_planar_kernel<_Float16>, grd, dim3(256), 0, ctx->stream,
+                               (const float2 *)R, n, np, np, scale, rows, (_Float16 *)Rfull);
+        RB_CHECK_LAUNCH(ctx);
+    }
     if (R8) {
         const size_t nw = (size_t)n * (rb_lp8_pad(n) / 4);
         hipLaunchKernelGGL(to_fp8_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0,
@@ -1782,7 +1782,7 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
     RowGroup g{};
     g.count = count;
     g.full = rb_prec_split(prec) ? 1 : 0;
-    g.rot = g.full && pr[0].R8 ? 1 : 0;
+    g.rot = pr[0].Rf ? 1 : 0;
     if (g.rot) n_comp = 2;
     int64_t items = 0, cost = 0;
     int64_t pcost[RB_GROUP_MAX];  // cost of one item of each problem (K blocks it walks)
@@ -1805,11 +1805,16 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
         g.Ht[i] = pr[i].Ht;
         g.Hlo[i] = pr[i].Hlo;
         g.R8[i] = pr[i].R8;
-        if ((pr[i].R8 != nullptr) != (g.rot != 0) || (g.rot && !pr[i].Hlo))
+        g.Rf[i] = pr[i].Rf;
+        // rotated forms: Rf everywhere; split: its low parts and FP8 Rs everywhere too
+        if ((pr[i].Rf != nullptr) != (g.rot != 0) ||
+            (g.rot && g.full && (!pr[i].Hlo || !pr[i].R8)) || (!g.full && pr[i].R8))
             return rb_fail(ctx, RB_EINVAL, "grouped back-projection: mixed operand forms");
         g.parts[i] = pr[i].parts;
         const int64_t it = (int64_t)nblocks * ((mblocks + 1) / 2);
-        pcost[i] = g.full ? 2 * mblocks : mblocks + 1;
+        // K blocks of 256 an item walks (per component; rotated: in all, the FP8 pass as half)
+        pcost[i] = !g.rot ? (g.full ? 2 * mblocks : mblocks + 1)
+                          : (g.full ? 5 * mblocks : 3 * mblocks + 1);
         items += it;
         cost += it * pcost[i];
     }
@@ -1855,8 +1860,8 @@ rb_status rb_launch_rowred_lp_group(rb_ctx *ctx, rb_prec prec, const rb_rowred_p
 
 rb_status rb_launch_rowred_lp(rb_ctx *ctx, rb_prec prec, int n, int n_mask, const void *Rp,
                               const void *Ht, int n_comp, float *parts, int *mblocks_out,
-                              const void *Hlo, const void *R8) {
-    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask, Hlo, R8};
+                              const void *Hlo, const void *R8, const void *Rf) {
+    const rb_rowred_prob pr{Rp, Ht, parts, n, n_mask, Hlo, R8, Rf};
     RB_TRY(rb_launch_rowred_lp_group(ctx, prec, &pr, 1, n_comp));
     if (mblocks_out) *mblocks_out = rb_rowred_lp_mblocks(n);
     return RB_OK;
