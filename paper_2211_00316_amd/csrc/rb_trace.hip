@@ -1084,6 +1084,26 @@ __device__ __forceinline__ void raster_run(const SampleBufs &sb, int n_rays, int
     unsigned long long *ek = keys + (size_t)el * n_mask;
     uint8_t *ec = changed + (size_t)el * n_mask;
     uint8_t *em = marks + (size_t)el * mtiles;
+    if (!MARK) {
+        // The run's bounding box holds every triangle's: if its tiles hold no mark, no
+        // triangle of the run touches a marked tile and each would return at its own test.
+        float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+        size_t bb = ((size_t)el * S + i0) * n_rays + j;
+        for (int i = i0; i <= i1; ++i, bb += n_rays) {
+            const f4u q = *reinterpret_cast<const f4u *>(sb.pos + bb);
+            umin = fminf(umin, fminf(q.x, q.z));
+            umax = fmaxf(umax, fmaxf(q.x, q.z));
+            vmin = fminf(vmin, fminf(q.y, q.w));
+            vmax = fmaxf(vmax, fmaxf(q.y, q.w));
+        }
+        const float bu[3] = {umin, umax, umax}, bv[3] = {vmin, vmax, vmax};
+        int ti0, ti1, tj0, tj1;
+        bbox_tiles(bu, bv, nx, ny, ti0, ti1, tj0, tj1);
+        bool any = false;
+        for (int tj = tj0; tj <= tj1 && !any; ++tj)
+            for (int ti = ti0; ti <= ti1; ++ti) any |= em[tj * mtx + ti] != 0;
+        if (!any) return;
+    }
     size_t b = ((size_t)el * S + i0) * n_rays + j;
     f4u q = *reinterpret_cast<const f4u *>(sb.pos + b);
     float u0 = q.x, v0 = q.y, u1 = q.z, v1 = q.w;
