@@ -394,8 +394,11 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
             else hp[cp][r >> 1] = lp_bits<T>(v[cp]);
             if constexpr (SPLIT) {
                 // low part: |lo| <= 4 (half an FP16 ulp below 2^14), times 2^6 in FP8 (E4M3);
-                // a correction of relative size 2^-11 needs no more than its 3 bits
-                const float lo = 64.f * (v[cp] - from_lp<T>(to_lp<T>(v[cp])));
+                // a correction of relative size 2^-11 needs no more than its 3 bits. Clamped
+                // to the format's largest value (448; beyond it the conversion gives NaN), which
+                // only a value rounded up to 2^14 itself could reach.
+                const float lo = fminf(fmaxf(64.f * (v[cp] - from_lp<T>(to_lp<T>(v[cp]))), -448.f),
+                                       448.f);
                 if (!(r & 1))
                     b8p[cp] = lo;
                 else if ((r >> 1) & 1)  // bytes 2, 3 of the dword
