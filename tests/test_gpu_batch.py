@@ -72,12 +72,12 @@ def _alone(name, prec):
     return s.c
 
 
-@pytest.mark.parametrize("pname", ["f32", "bf16"])
+@pytest.mark.parametrize("pname", ["f32", "bf16", "fp16x"])
 def test_batch_matches_oracle_and_single_steps(pname):
     import torch
     from paper_2211_00316_amd import _lib
 
-    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16}[pname]
+    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16, "fp16x": _lib.RB_F16X}[pname]
     names = ["small", "ragged", "folded", "ring64"]
     ctxs = _contexts(len(names))
     steps = [_step_args(cx, n) for cx, n in zip(ctxs, names)]
@@ -98,9 +98,12 @@ def test_batch_matches_oracle_and_single_steps(pname):
                 _say(f"  {name}: update rel L2 vs oracle {err:.2e}")
                 assert err <= 1e-4
             else:
-                err = rel_l2(c, c_ref.ravel()[q])
-                _say(f"  {name}: image rel L2 vs oracle {err:.2e}")
-                assert err <= 2e-3
+                # image error relative to the step's change (split form: the 2e-3 tolerance
+                # of the reduced-precision form; BF16: 40 units of its rounding)
+                err = rel_l2(c - C0, (c_ref.ravel() - C0)[q])
+                _say(f"  {name}: image RE vs oracle {err:.2e} "
+                     f"(||c||-normalised {rel_l2(c, c_ref.ravel()[q]):.2e})")
+                assert err <= (2e-3 if pname == "fp16x" else 40 * 2.0 ** -9)
     for cx in ctxs:
         cx.close()
 

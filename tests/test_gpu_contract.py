@@ -30,12 +30,12 @@ def _step_inputs(name="ring64", freqs=(250e3,)):
     return st, c_true, om, data
 
 
-@pytest.mark.parametrize("pname", ["f32", "bf16"])
+@pytest.mark.parametrize("pname", ["f32", "bf16", "fp16x"])
 def test_reserved_context_steps_without_allocating(pname):
     import torch
     from paper_2211_00316_amd import _lib
 
-    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16}[pname]
+    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16, "fp16x": _lib.RB_F16X}[pname]
     st, c_true, om, data = _step_inputs()
     grid, ring, tp = abi_structs(st)
     ctx = _lib.Context("cuda:0")
@@ -78,7 +78,7 @@ def test_reserved_context_steps_without_allocating(pname):
     ctx.close()
 
 
-@pytest.mark.parametrize("pname", ["f32", "bf16"])
+@pytest.mark.parametrize("pname", ["f32", "bf16", "fp16x"])
 def test_single_step_captured_by_the_caller(pname):
     # One rb_frequency_step with a device report, captured into the caller's HIP graph on the
     # context's stream and replayed several times with eager work and synchronisations in
@@ -86,7 +86,7 @@ def test_single_step_captured_by_the_caller(pname):
     import torch
     from paper_2211_00316_amd import _lib
 
-    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16}[pname]
+    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16, "fp16x": _lib.RB_F16X}[pname]
     st, c_true, om, data = _step_inputs("ragged", (200e3, 260e3))
     dom = [om[1] - om[0]] * 2
     grid, ring, tp = abi_structs(st)

@@ -74,12 +74,12 @@ def test_sweep_matches_oracle_steps(ctx):
     assert rel_l2(dc, dc_ref) <= 2e-4
 
 
-@pytest.mark.parametrize("pname", ["f32", "bf16"])
+@pytest.mark.parametrize("pname", ["f32", "bf16", "fp16x"])
 def test_sweep_and_graph_replays_equal_single_steps(ctx, pname):
     import torch
     from paper_2211_00316_amd import _lib
 
-    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16}[pname]
+    prec = {"f32": _lib.RB_F32, "bf16": _lib.RB_BF16, "fp16x": _lib.RB_F16X}[pname]
     st, _ = case("small")
     grid, ring, tp = abi_structs(st)
     data = torch.as_tensor(_data("small").astype(np.complex64), device="cuda:0")
