@@ -110,9 +110,11 @@ def test_autotune_keeps_the_fastest_and_the_step_still_matches(ctx, pname):
         _say(f"  tuned step: update rel L2 {err:.2e}")
         assert err <= 1e-4
     else:
-        err = rel_l2(c_new, c_ref.ravel()[q])
-        _say(f"  tuned step: image rel L2 {err:.2e}")
-        assert err <= 2e-3
+        # image error relative to the step's change: 40 units of BF16 rounding
+        err = rel_l2(c_new - C0, (c_ref - c0).ravel()[q])
+        _say(f"  tuned step: image RE {err:.2e} "
+             f"(||c||-normalised {rel_l2(c_new, c_ref.ravel()[q]):.2e})")
+        assert err <= 40 * 2.0 ** -9
     ctx.set_tuning(None)
 
 
