@@ -1268,8 +1268,8 @@ __global__ void __launch_bounds__(LR_THREADS) rowred_lp_kernel(const RowGroup gr
                         }
                 lr_mainloop<T, true>(s0, s1, s2, ld, corr ? 0 : KT0, KT, acc_re, acc_im);
                 if (corr && grp.R8[p]) {
-                    // + Rs b_lo on FP8 operands (R8 = Rs / 2^6, b_lo stored times 2^6), in
-                    // 64-byte rows of rb_lp8_pad(n) bytes, seen as 16-bit values by the loader
+                    // + Rs b_lo on FP8 operands (R8 = Rs / 2^6 in rows of rb_lp8_pad(n)
+                    // bytes; b_lo times 2^6 in blocks of 64 transducers), K steps of 64
                     const int np8 = rb_lp8_pad(n);
                     const T *B8 = Hlo + (size_t)2 * hplane;  // the second low-part slot
                     const LrLoad l8 = lr_load8(grp.R8[p], (size_t)n * np8, row0, np8, B8,
