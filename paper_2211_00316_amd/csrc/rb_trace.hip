@@ -652,7 +652,7 @@ constexpr int LOCATE_MAX_IT = 96;
 // settle soon is given up and its node left to the rasterisation.
 constexpr int LOCATE_MAX_IT_FOLD = 16;
 constexpr int LTX = RB_WALK_TX, LTY = RB_WALK_TY;  // node tile of one locate workgroup
-constexpr int LOCATE_NPL = 2;  // nodes per lane of the walk (rows jj and jj + LTY / 2)
+constexpr int LOCATE_NPL = 2;  // nodes per lane (rows jj and jj + LTY / 2; folded: jj + 1)
 constexpr int LOCATE_THREADS = LTX * LTY / LOCATE_NPL;
 constexpr int LOCATE_WAVES = LOCATE_THREADS / 64;
 constexpr int LOCATE_GROUP_ROWS = 2;  // tile rows per XCD group
@@ -828,7 +828,7 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
                                              unsigned long long *__restrict__ keys,
                                              uint8_t *__restrict__ changed,
                                              uint8_t *__restrict__ marks, int mtx, int mtiles,
-                                             int *lost, float ids) {
+                                             int *lost, float ids, int &js, int &is) {
     const int e = e0 + el;
     // Distance from the transducer. Records: FP32 (it decides validity, the walk's start and
     // A = exp(L) / sqrt(d); the reader rebuilds T from its own FP64 distance). ABI tables:
@@ -848,10 +848,17 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
         ddy = (float)dy64;
         df = (float)d;
     }
-    int j, i;
-    straight_guess(ddx, ddy, df, wc.z, ids, n_rays, S, j, i);
-    j = min(max(j + o.x, 0), n_rays - 2);
-    i = min(max(i + o.y, 1), S - 2);
+    // start: in a folded fan the quad where the lane's previous walk (the node one row below)
+    // ended, else the straight-ray guess plus the tile's offset. (In an unfolded fan the two
+    // walks of a lane stay independent, so that their loads overlap: chaining them there
+    // made the walk slower.)
+    int j = fold ? js : -1, i = is;
+    if (j < 0) {
+        straight_guess(ddx, ddy, df, wc.z, ids, n_rays, S, j, i);
+        j = min(max(j + o.x, 0), n_rays - 2);
+        i = min(max(i + o.y, 1), S - 2);
+    }
+    js = -1;
     if (q < 0) return 0.f;  // outside the mask
     const uint32_t out = (uint32_t)q;
     const size_t kq = (size_t)el * n_mask + q;
@@ -870,6 +877,8 @@ __device__ __forceinline__ float locate_node(const SampleBufs &sb, int n_rays, i
     int half;
     if (mesh_walk(sb.pos + ebase, sb.M + (size_t)el * n_rays, n_rays, (float)ii, (float)jj, j, i,
                   vb, lam, half, fold ? LOCATE_MAX_IT_FOLD : LOCATE_MAX_IT)) {
+        js = j;
+        is = i;
         // no ray of an unfolded fan has K > 0
         const int K = fold ? tri_K(sb, n_rays, S, el, j, i, half, vb) : 0;
         const float4 *fldE = sb.fld + ebase;
@@ -944,9 +953,12 @@ __global__ void __launch_bounds__(LOCATE_THREADS, 8) locate_kernel(SampleBufs sb
     const float4 wc = wcon[e0 + el];
     // largest A and 1/A of the lane's records (bits of non-negative floats)
     uint32_t amax = 0u, iamax = 0u;
+    int js = -1, is = 0;  // quad of the lane's last successful walk (folded fans)
 #pragma unroll
     for (int h = 0; h < LOCATE_NPL; ++h) {
-        const int jj = tile_j0 + tj * LTY + h * (LOCATE_THREADS / LTX) + (threadIdx.x / LTX);
+        const int jj = tile_j0 + tj * LTY +
+                       (fold ? LOCATE_NPL * (threadIdx.x / LTX) + h
+                             : h * (LOCATE_THREADS / LTX) + (threadIdx.x / LTX));
         float A = 0.f;
         // nodes clearly outside the mask disc (node units; the margin leaves the decision on
         // the circle to qmap) issue nothing
@@ -956,11 +968,11 @@ __global__ void __launch_bounds__(LOCATE_THREADS, 8) locate_kernel(SampleBufs sb
             if (fold)
                 A = locate_node<REC, true>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj,
                                            q, o, wc, toE, keys, changed, marks, mtx, mtiles,
-                                           lost, idsf);
+                                           lost, idsf, js, is);
             else
                 A = locate_node<REC, false>(sb, n_rays, S, el, e0, g, two_ds, c0, n_mask, ii, jj,
                                             q, o, wc, toE, keys, changed, marks, mtx, mtiles,
-                                            lost, idsf);
+                                            lost, idsf, js, is);
         }
         amax = max(amax, __float_as_uint(A));
         iamax = max(iamax, __float_as_uint(A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f));
