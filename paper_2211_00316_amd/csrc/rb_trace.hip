@@ -174,9 +174,11 @@ struct Ray {
 };
 
 // 1 / sqrt(a) from the FP32 estimate and one Newton step (relative error about the square
-// of the FP32 one).
+// of the FP32 one). The estimate is the hardware reciprocal square root alone: its arguments
+// here are squared wave-vector norms near n^2, never denormal, so the library's rescaling
+// for tiny arguments would only add instructions.
 __device__ __forceinline__ double rsqrt_newton(double a) {
-    const double y = (double)rsqrtf((float)a);
+    const double y = (double)__builtin_amdgcn_rsqf((float)a);
     return y * fma(-0.5 * a * y, y, 1.5);
 }
 
@@ -205,12 +207,12 @@ __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, c
     float kpx = kx + hf * s1.gx, kpy = ky + hf * s1.gy;     // auxiliary ray direction
     Spline s2 = spline_eval(m, r.u + hu * (double)qxx, r.v + hu * (double)qxy, pc);
     float n2 = s2.v;
-    float ikpn = rsqrtf(kpx * kpx + kpy * kpy);
+    float ikpn = __builtin_amdgcn_rsqf(kpx * kpx + kpy * kpy);
     float qxx2 = kpx * ikpn, qxy2 = kpy * ikpn;
     kpx = n2 * qxx2;
     kpy = n2 * qxy2;
     float sx = qxx + qxx2, sy = qxy + qxy2;
-    float isn = rsqrtf(sx * sx + sy * sy);
+    float isn = __builtin_amdgcn_rsqf(sx * sx + sy * sy);
     Ray o;
     o.u = r.u + hu * (double)(sx * isn);                    // position along mean direction
     o.v = r.v + hu * (double)(sy * isn);
@@ -230,9 +232,10 @@ __device__ __forceinline__ Ray heun_step(const SplineMap &m, const Spline &s1, c
 }
 
 // Square root of a positive double from the FP32 estimate and one Newton step (relative
-// error about the square of the FP32 one).
+// error about the square of the FP32 one). The estimate is the hardware square root (about
+// one ulp, not correctly rounded): the Newton step in FP64 removes its error either way.
 __device__ __forceinline__ double sqrt_newton(double a) {
-    float s0 = sqrtf((float)a);
+    float s0 = __builtin_amdgcn_sqrtf((float)a);
     double s = (double)s0;
     return fma(a - s * s, (double)(0.5f * __builtin_amdgcn_rcpf(s0)), s);
 }
@@ -332,7 +335,7 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const AbsMap &am, 
             a_cur = a_new;
         }
         const float kxf = (float)r.kx, kyf = (float)r.ky;
-        float ikn = rsqrtf(kxf * kxf + kyf * kyf);
+        float ikn = __builtin_amdgcn_rsqf(kxf * kxf + kyf * kyf);
         float tx = kxf * ikn, ty = kyf * ikn;
         float J = (float)r.dxx * (-ty) + (float)r.dxy * tx;
         if (i >= 1 && J * J_prev < 0.0f) ++K;
@@ -341,9 +344,14 @@ __device__ __forceinline__ int trace_core(const SplineMap &m, const AbsMap &am, 
         float df = (float)d;
         float nJ = n_new * fabsf(J);
         // Eq. attenuation_geom_reference with the first sample as reference, as a logarithm:
-        // L = ln A + ln(d)/2 = lnc1 + ln(d / (n |J|)) / 2
-        if (i == 0) lnc1 = 0.5f * __logf(nJ * __builtin_amdgcn_rcpf(8.0f * (float)RB_PI * df));
-        float L = lnc1 + 0.5f * __logf(df * __builtin_amdgcn_rcpf(nJ));
+        // L = ln A + ln(d)/2 = lnc1 + ln(d / (n |J|)) / 2 with
+        // lnc1 = ln(n_1 |J_1| / (8 pi d_1)) / 2 = -ln(d_1 / (n_1 |J_1|)) / 2 - ln(8 pi) / 2,
+        // so one logarithm per sample (hardware log2; its argument is of order d / |J|, far
+        // from the denormal range).
+        const float lh = (0.5f * 0.693147181f) *
+                         __builtin_amdgcn_logf(df * __builtin_amdgcn_rcpf(nJ));
+        if (i == 0) lnc1 = -lh - 0.5f * 3.22417143f;  // ln(8 pi) = 3.2241714...
+        float L = lnc1 + lh;
         if constexpr (ABS) L -= (float)Babs;  // ln A_abs (Eq. amplitude-abs-discretised)
         float dT = (float)(T - d * ic0);
         ++i;
