@@ -424,6 +424,12 @@ __device__ __forceinline__ int trace_ray(const SplineMap &m, const AbsMap &am, c
 // samples written (one atomic per wavefront; the workgroup is a whole number of them).
 // Four waves per SIMD (128 registers, a few spilled) hide more of the coefficient loads'
 // latency than three without spills.
+// Workgroups (four transducers of one rank) are dealt to the 8 XCDs round-robin by launch
+// index. When E is a multiple of 32 the transducer groups of a rank are renamed so that each
+// XCD traces one contiguous arc of E / 8 transducers: same-rank rays of neighbouring
+// transducers cross nearly the same cells at about the same time, so that XCD's L2 fetches
+// their spline coefficients once instead of once per group of four. (Which wave traces which
+// ray changes nothing in the results.)
 template <bool ABS>
 __global__ void __launch_bounds__(PATCH_STRIDE) __attribute__((amdgpu_waves_per_eu(4))) trace_kernel(SplineMap m, AbsMap am, GridP g,
                                                              double R, double psi0, int N,
@@ -435,7 +441,12 @@ __global__ void __launch_bounds__(PATCH_STRIDE) __attribute__((amdgpu_waves_per_
     m.patch = s_patch + threadIdx.x;
     const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int n_groups = (n_rays + 63) / 64;
-    const int el = wave % E, rank = wave / E;
+    const int rank = wave / E;
+    int el = wave % E;
+    if ((E & 31) == 0) {  // group g of four -> (g mod 8) (E / 32) + g / 8
+        const int g = el >> 2;
+        el = (((g & 7) * (E >> 5) + (g >> 3)) << 2) | (el & 3);
+    }
     int M = -1;
     if (rank < n_groups) {
         const int mid = n_groups / 2;
