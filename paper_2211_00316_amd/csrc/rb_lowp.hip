@@ -142,6 +142,22 @@ __device__ __forceinline__ void row_scales(const unsigned int *__restrict__ rowm
     sh = pow2_scale((float)RB_PI * sk * iamax);
 }
 
+// The scales of every row for one frequency, scales[e] (G) and scales[N + e] (H), before the
+// assembly from compact records, which then reads them instead of recomputing them in every
+// lane.
+__global__ void __launch_bounds__(256) row_scale_kernel(const unsigned int *__restrict__ rowmax,
+                                                        int N, double omega, double c0,
+                                                        float gmax, float *__restrict__ scales) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N) return;
+    const double k0 = omega / c0;
+    const float sk = (float)sqrt(k0), isk = 1.0f / sk;
+    float sg, sh;
+    row_scales(rowmax, e, sk, isk, gmax, sg, sh);
+    scales[e] = sg;
+    scales[N + e] = sh;
+}
+
 // Largest A and 1/A over the valid entries of each row of the ABI tables (one workgroup per
 // transducer), as the bits rowmax[2e], rowmax[2e+1].
 __global__ void __launch_bounds__(256) row_amax_kernel(rb_tables tb, int n_mask,
@@ -287,6 +303,15 @@ __device__ __forceinline__ float wrap_pi(float x) {
     return x - (float)RB_TWO_PI * rintf(x * (float)(1.0 / RB_TWO_PI));
 }
 
+// Distance from the squared distance a > 0 (normal): the hardware FP32 square root and one
+// Newton step in FP64, relative error about 1e-14 (the phase needs about 1e-9 of T), in a
+// third of the instructions of the correctly rounded FP64 square root.
+__device__ __forceinline__ double dist_newton(double a) {
+    const float s0 = __builtin_amdgcn_sqrtf((float)a);
+    const double s = (double)s0;
+    return fma(fma(-s, s, a), (double)(0.5f * __builtin_amdgcn_rcpf(s0)), s);
+}
+
 // Stores go through LDS: the workgroup's tile of G (4 GWt transducers x 64 nodes) leaves
 // as 16-byte pieces of rows (over nodes), and each node's 4 GWt transducers of H as one row
 // piece written by consecutive threads, 16 bytes each (H in two halves of three planes; one
@@ -297,12 +322,13 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
     const float4 *__restrict__ rec, const int32_t *__restrict__ mask_index,
     const double2 *__restrict__ ring, double x0, double y0, double dx, int nx, int N, int n_mask,
     double omega, double c0, const float2 *__restrict__ gs, const float *__restrict__ gscale,
-    int write_g, T *__restrict__ Gp, T *__restrict__ Ht, const unsigned int *__restrict__ rowmax,
-    float gmax, float *__restrict__ scales, T *__restrict__ Htlo) {
+    int write_g, T *__restrict__ Gp, T *__restrict__ Ht, const float *__restrict__ scales,
+    T *__restrict__ Htlo) {
     constexpr int GEt = NW * GWt, GHL = GEt + 8;  // transducers per workgroup, staging pitch
     constexpr int NT = 64 * NW;                   // threads
     __shared__ __attribute__((aligned(16))) T stage[3 * GQ * GHL];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // w is the wave's index (uniform), so the rows' scales are scalar loads
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q0 = blockIdx.x * GQ, E0 = blockIdx.y * GEt;
     const int q = q0 + lane;
     const int e0 = E0 + w * GWt;
@@ -357,12 +383,9 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
         const int e = e0 + r;
         float gr = 0.f, gi = 0.f, hr = 0.f, hi = 0.f, vx = 0.f, vy = 0.f;
         float rsg = 1.f, rsh = 1.f;
-        if (e < N) {
-            row_scales(rowmax, e, sk, isk, gmax, rsg, rsh);
-            if (blockIdx.x == 0 && lane == 0) {
-                scales[e] = rsg;
-                scales[N + e] = rsh;
-            }
+        if (e < N) {  // row_scale_kernel's
+            rsg = scales[e];
+            rsh = scales[N + e];
         }
         if (node && e < N && (valid >> (r + 1) & 1u)) {
             __sincosf(th[r + 1], &vy, &vx);
@@ -373,7 +396,7 @@ __global__ void __launch_bounds__(64 * NW) green_lp_rec_kernel(
             else if (vm) a = fabsf(wrap_pi(th[r + 1] - th[r]));
             const double2 xe = ring[e];
             const double ddx = px - xe.x, ddy = py - xe.y;
-            const double Tt = (double)dTr[r] + sqrt(ddx * ddx + ddy * ddy) * ic0;
+            const double Tt = (double)dTr[r] + dist_newton(ddx * ddx + ddy * ddy) * ic0;
             green_entry(omega, Tt, Kb >> (2 * r), Ar[r], a, sk, isk, gr, gi, hr, hi);
             gr *= rsg;
             gi *= rsg;
@@ -1696,23 +1719,24 @@ rb_status rb_launch_green_lp_rec(rb_ctx *ctx, const float4 *rec, const double2 *
     const float gmax = gs ? GS_MAX : 1.f;
     const size_t hlo = 6 * (size_t)nm * rb_lp_pad(n);  // low parts follow H
     rb_prof_begin(ctx, ST_GREEN);
+    hipLaunchKernelGGL(row_scale_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, rowmax,
+                       n, omega, c0, gmax, out->scales);
+    RB_CHECK_LAUNCH(ctx);
     if (out->prec == RB_BF16)
         hipLaunchKernelGGL((green_lp_rec_kernel<__bf16, false, GW, 4>), grd, dim3(256), 0, ctx->stream,
                            rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
                            c0, (const float2 *)gs, gscale, write_g, (__bf16 *)out->G,
-                           (__bf16 *)out->H, rowmax, gmax, out->scales, nullptr);
+                           (__bf16 *)out->H, out->scales, nullptr);
     else if (rb_prec_split(out->prec))
         hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, true, GWS, 8>), grd, dim3(512), 0, ctx->stream,
                            rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n, nm, omega,
                            c0, (const float2 *)gs, gscale, write_g, (_Float16 *)out->G,
-                           (_Float16 *)out->H, rowmax, gmax, out->scales,
-                           (_Float16 *)out->H + hlo);
+                           (_Float16 *)out->H, out->scales, (_Float16 *)out->H + hlo);
     else
         hipLaunchKernelGGL((green_lp_rec_kernel<_Float16, false, GW, 4>), grd, dim3(256), 0,
                            ctx->stream, rec, ctx->d_mask_index, ring, g.x0, g.y0, g.dx, g.nx, n,
                            nm, omega, c0, (const float2 *)gs, gscale, write_g,
-                           (_Float16 *)out->G, (_Float16 *)out->H, rowmax, gmax, out->scales,
-                           nullptr);
+                           (_Float16 *)out->G, (_Float16 *)out->H, out->scales, nullptr);
     RB_CHECK_LAUNCH(ctx);
     rb_prof_end(ctx);
     return RB_OK;
