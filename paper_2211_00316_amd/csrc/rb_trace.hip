@@ -1082,12 +1082,14 @@ __device__ __forceinline__ void raster_tri(const float *tu, const float *tv,
 // The general path runs over the folded transducers of a chunk only: flist[0] = their count,
 // flist[1 ..] = their chunk indices in increasing order. Its kernels are grid-stride loops
 // over that list, so a chunk without folded fans costs one short launch each.
-__global__ void folded_list(const int32_t *__restrict__ folded, int E, int32_t *flist) {
+__global__ void folded_list(const int32_t *__restrict__ folded, int E, int32_t *flist,
+                            unsigned long long *next) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         int c = 0;
         for (int el = 0; el < E; ++el)
             if (folded[el]) flist[1 + c++] = el;
         flist[0] = c;
+        *next = 0ull;  // the smallest-key pass's work counter
     }
 }
 
@@ -1171,6 +1173,14 @@ __device__ __forceinline__ void raster_run(const SampleBufs &sb, int n_rays, int
 
 constexpr int RASTER_ROWS = 4096;  // grid rows of the LDS copy of the mask's row table
 
+// Dynamic LDS of the smallest-key pass: the mask's row table when the grid has at most
+// RASTER_ROWS rows (the kernel then reads it from LDS), else none (read from memory).
+inline size_t raster_lds_bytes(int ny) {
+    return ny <= RASTER_ROWS ? (size_t)ny * sizeof(int2) : 0;
+}
+
+constexpr int RCHUNK = 1024;  // items a wave of the smallest-key pass takes at a time
+
 template <bool MARK>
 __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, int S, int nx,
                                                      int ny, int n_mask,
@@ -1179,8 +1189,8 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
                                                      unsigned long long *__restrict__ keys,
                                                      uint8_t *__restrict__ changed,
                                                      uint8_t *__restrict__ marks, int mtx,
-                                                     int mtiles) {
-    __shared__ int2 s_qrow[MARK ? 1 : RASTER_ROWS];
+                                                     int mtiles, unsigned long long *next) {
+    extern __shared__ int2 s_qrow[];  // raster_lds_bytes(ny) in the smallest-key pass
     const int2 *qrow = qrow_g;
     if (!MARK && ny <= RASTER_ROWS) {
         for (int r = threadIdx.x; r < ny; r += blockDim.x) s_qrow[r] = qrow_g[r];
@@ -1189,13 +1199,34 @@ __global__ void __launch_bounds__(256) raster_kernel(SampleBufs sb, int n_rays, 
     }
     const size_t nq = (size_t)n_rays - 1, nc = (size_t)(S + RCH - 1) / RCH, per = nc * nq;
     const size_t total = (size_t)flist[0] * per;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
+    auto item = [&](size_t t) {
         const int f = (int)(t / per);
         const size_t rest = t - (size_t)f * per;
         const int c = (int)(rest / nq), j = (int)(rest - (size_t)c * nq);
         raster_run<MARK>(sb, n_rays, S, flist[1 + f], c, j, nx, ny, n_mask, qrow, keys, changed,
                          marks, mtx, mtiles);
+    };
+    if (MARK) {
+        for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+             t += (size_t)gridDim.x * blockDim.x)
+            item(t);
+        return;
+    }
+    // Runs differ widely in cost (those near marked tiles rasterise, the others return after
+    // their bounding-box test), so each wave takes RCHUNK consecutive items at a time from a
+    // counter (zeroed by folded_list) instead of a fixed share; every wave leaves once the
+    // counter has passed the last item.
+    if (total == 0) return;  // no folded fan: not even one atomic per wave
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(next, (unsigned long long)RCHUNK);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        const size_t b0 = ((size_t)hi << 32) | lo;
+        if (b0 >= total) break;
+        const size_t b1 = min(b0 + (size_t)RCHUNK, total);
+        for (size_t t = b0 + lane; t < b1; t += 64) item(t);
     }
 }
 
@@ -1672,7 +1703,7 @@ static size_t trace_bytes(const rb_grid *g, const rb_ring *r, const rb_trace_par
            rb_align(plane) + 2 * rb_align((size_t)C * nr * sizeof(int32_t)) +
            rb_align((size_t)C * nr * sizeof(double)) +
            2 * rb_align((size_t)C * nr * sizeof(float)) + rb_align((size_t)C * nr) +
-           rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 1) * sizeof(int32_t)) +
+           rb_align((size_t)C * sizeof(int32_t)) + rb_align(((size_t)C + 4) * sizeof(int32_t)) +
            rb_align((size_t)r->n * sizeof(double2)) + rb_align((size_t)r->n * sizeof(float4)) +
            rb_align((size_t)C * tiles * sizeof(int2)) +
            rb_align((size_t)C * n_mask * sizeof(unsigned long long)) +
@@ -1712,7 +1743,8 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
     sb.ex_L = rb_carve<float>(&ctx->ws, (size_t)C * nr);
     sb.ex_K = rb_carve<uint8_t>(&ctx->ws, (size_t)C * nr);
     sb.folded = rb_carve<int32_t>(&ctx->ws, (size_t)C);
-    int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 1);
+    int32_t *flist = rb_carve<int32_t>(&ctx->ws, (size_t)C + 4);  // + the 8-byte counter
+    unsigned long long *rnext = reinterpret_cast<unsigned long long *>(flist + ((C + 2) & ~1));
     double2 *ringpos = rb_carve<double2>(&ctx->ws, (size_t)N);
     float4 *wcon = rb_carve<float4>(&ctx->ws, (size_t)N);
     if (ring_out) ringpos = ring_out;
@@ -1775,11 +1807,12 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         rb_prof_end(ctx);
         // folded fans: tiles near inverted triangles
         rb_prof_begin(ctx, ST_RASTER);
-        hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist);
+        hipLaunchKernelGGL(folded_list, dim3(1), dim3(64), 0, ctx->stream, sb.folded, E, flist,
+                           rnext);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(raster_kernel<true>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
                            nr, S, g->nx, g->ny, n_mask, ctx->d_qrow, flist, keys, changed, marks,
-                           mtx, mtiles);
+                           mtx, mtiles, rnext);
         RB_CHECK_LAUNCH(ctx);
         rb_prof_end(ctx);
         // every fan: walk per (transducer, node); for folded fans also the seed keys
@@ -1813,9 +1846,20 @@ rb_status rb_launch_trace(rb_ctx *ctx, const rb_grid *g, const rb_ring *r,
         // folded fans: smallest-key rasterisation against the walk's keys, and resolve of
         // the nodes it changed
         rb_prof_begin(ctx, ST_RASTER);
-        hipLaunchKernelGGL(raster_kernel<false>, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb,
-                           nr, S, g->nx, g->ny, n_mask, ctx->d_qrow, flist, keys, changed, marks,
-                           mtx, mtiles);
+        // as many workgroups as are resident at once (with 2048, registers and LDS let 5 or 6
+        // per CU run and the rest waited for a second round); their waves take the items from
+        // the counter folded_list zeroed
+        const size_t rlds = raster_lds_bytes(g->ny);
+        int rpc = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rpc, raster_kernel<false>, 256, rlds) !=
+                hipSuccess ||
+            rpc < 1) {
+            (void)hipGetLastError();  // a failed query is no launch error
+            rpc = 4;
+        }
+        hipLaunchKernelGGL(raster_kernel<false>, dim3(rpc * ctx->n_cu), dim3(256), rlds,
+                           ctx->stream, sb, nr, S, g->nx, g->ny, n_mask, ctx->d_qrow, flist, keys,
+                           changed, marks, mtx, mtiles, rnext);
         RB_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(resolve_kernel, dim3(FOLD_GRID), dim3(256), 0, ctx->stream, sb, nr, S,
                            e0, gp, tp->ds, tp->c0, n_mask, ctx->d_mask_index, flist, keys,
