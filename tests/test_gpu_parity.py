@@ -102,6 +102,34 @@ def test_trace_rays_tables_folded_fans(ctx):
     assert err_a <= 1e-5
 
 
+def test_trace_rays_folded_fans_in_chunks_equal_one_launch():
+    # A sample budget that splits the transducers into about five tracer chunks (the last one
+    # ragged): every chunk's folded fans go through the rasterisation again, whose waves take
+    # their runs from a counter reset per chunk, so the tables equal those of one launch
+    # bitwise.
+    import math
+    import torch
+    from paper_2211_00316_amd import _lib
+
+    st, c = case("folded")
+    grid, ring, tp = abi_structs(st)
+    ns_g = torch.as_tensor(oracle_tables("folded")[1].astype(np.float32), device="cuda:0")
+    n_mask = st.grid.mask_index().size
+    per = (tp.max_steps + 1) * tp.n_rays * 25 + n_mask * 8 + tp.n_rays * 32
+    out = []
+    for budget in (1 << 30, per * math.ceil(st.ring.n / 5)):
+        cx = _lib.Context("cuda:0")
+        cx.set_sample_budget(budget)
+        _say(f"trace_rays folded, sample budget {budget}")
+        out.append(cx.trace_rays(grid, ring, tp, ns_g))
+        torch.cuda.synchronize()
+        cx.close()
+    a, b = out
+    for x, y in zip((a.T, a.A, a.ux, a.uy, a.flags, a.rx_T, a.rx_A, a.rx_flags),
+                    (b.T, b.A, b.ux, b.uy, b.flags, b.rx_T, b.rx_A, b.rx_flags)):
+        assert torch.equal(x, y)
+
+
 def test_trace_rays_is_deterministic(ctx):
     import torch
 
